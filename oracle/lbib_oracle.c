@@ -1,0 +1,552 @@
+/* FP64 CPU oracle of one coupled LBM + IB time step of LBIBCell (arXiv:1503.06726).
+ *
+ * TEST INFRASTRUCTURE ONLY: the plain, slow reference the HIP library is checked
+ * against.  Only the tests, the smoke check and the benchmark's CPU-baseline leg
+ * load it.  It shares no code with the HIP library.
+ *
+ * Build: gcc -O2 -std=c99 -fPIC -shared -ffp-contract=off [-fopenmp]
+ * (contraction off, so every product and sum rounds as written; OpenMP, when
+ * enabled, only splits the lattice loops by rows, each element is still computed
+ * by exactly the statements below).
+ *
+ * Readings of the paper taken here (where it is silent, garbled or ambiguous):
+ *  - D2Q9 numbering: rest, +x, +y, -x, -y, then the diagonals (1,1), (-1,1),
+ *    (-1,-1), (1,-1).  The printed diagonal formula has a misplaced parenthesis;
+ *    the lattice is the standard one.
+ *  - Equilibrium: the printed second-order term lacks c_s^2 and the identity; the
+ *    standard form w rho [1 + v.u/cs2 + ((v.u)^2 - cs2 u.u)/(2 cs2^2)] is used.
+ *  - Forcing: the literal first-order term dt w rho (v.f)/cs2 of Eq. (bgkequation),
+ *    no (1 - 1/(2 tau)) prefactor, velocity u = sum f v / rho without a half-force
+ *    shift; f is an acceleration field (spread force plus uniform body acceleration).
+ *  - Time level of the interpolated velocity: u^n, the moments of f^n taken before
+ *    collision (explicit Euler, the u(x,t) -> U(l,t) labels of Fig. "Algorithm
+ *    Overview").  interp_new_u = 1 switches to u^{n+1} for comparison.
+ *  - The species see the same u^n; the reaction term is added after collision as
+ *    w_i R(phi^n, m^n) (explicit Euler, pre-collision phi), without a tau correction.
+ *  - D2Q5 sound speed cs2 = 1/3 (consistent with w0 = 1/3, w1-4 = 1/6), so
+ *    tau_D = D/cs2 + 1/2.
+ *  - 2-D kernel: delta(r) = delta1D(r_x) delta1D(r_y) (the printed product repeats r).
+ *    Stencil: i0 = floor(X) - 1, four points per axis, h = 1.  Nodal forces are
+ *    spread without an arc-length weight.  Near walls, points outside the lattice
+ *    are dropped.
+ *  - Walls (not in the paper's hot path): halfway bounce-back, walls at y = -1/2 and
+ *    y = ny - 1/2, for f and for every species (zero flux).  x is always periodic.
+ *  - Domain IDs: crossing-number test at integer lattice coordinates, half-open in y
+ *    ((a.y > y) != (b.y > y)), strict in x (x < x_crossing); positions are unwrapped,
+ *    a cell is tested with its periodic images; overlapping cells: the smallest ID wins.
+ *  - Source/decay law: R = sigma [m != 0] - lambda phi.  Schnakenberg:
+ *    R_0 = gamma (a - phi0 + phi0^2 phi1), R_1 = gamma (b - phi0^2 phi1).
+ */
+#include "lbib_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- lattice constants (Suppl. "Lattice Boltzmann Method", D2Q9 and D2Q5 footnotes) ---- */
+static const int VX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int VY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+static const double W9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                             1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+static const double W5[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+static const double CS2 = 1.0 / 3.0;
+
+struct orc_ctx {
+    orc_params p;
+    int64_t nn;                   /* nx * ny */
+    double *f, *fnew;             /* [9][ny][nx], state f^n (pre-collision) */
+    double *g, *gnew;             /* [S][5][ny][nx] */
+    double *rho, *ux, *uy;        /* moments of f^n of the current step */
+    double *ex, *ey;              /* spread force + body acceleration of the current step */
+    int32_t *mask;                /* domain IDs of X^n */
+    int32_t n_cells;
+    int64_t n_nodes;
+    int32_t *off;
+    double *X, *F, *l0, *A0, *area;
+};
+
+static int64_t wrapi(int64_t i, int64_t n) { int64_t r = i % n; return r < 0 ? r + n : r; }
+
+/* ------------------------------------------------------------------------------------
+ * Eq. (1Dkernel): delta1D(r) = (1 + cos(pi |r| / 2)) / 4 for |r| <= 2, else 0.
+ * The alternative is Peskin's standard 4-point kernel (the one named in his 2002
+ * review), offered because the cosine kernel has a nonzero first moment.
+ * ---------------------------------------------------------------------------------- */
+double orc_delta1d(int32_t kernel, double r)
+{
+    double a = fabs(r);
+    if (kernel == ORC_DELTA_PESKIN) {
+        if (a <= 1.0) return (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * a * a)) / 8.0;
+        if (a <= 2.0) return (5.0 - 2.0 * a - sqrt(-7.0 + 12.0 * a - 4.0 * a * a)) / 8.0;
+        return 0.0;
+    }
+    if (a <= 2.0) return 0.25 * (1.0 + cos(M_PI * a / 2.0));
+    return 0.0;
+}
+
+/* Eq. (standardequilibrium), with the garbled second-order term read as
+ * ((v_i.u)^2 - cs2 u.u) / (2 cs2^2). */
+void orc_equilibrium9(double rho, double ux, double uy, double out[9])
+{
+    double uu = ux * ux + uy * uy;
+    for (int i = 0; i < 9; ++i) {
+        double vu = VX[i] * ux + VY[i] * uy;
+        out[i] = W9[i] * rho * (1.0 + vu / CS2 + (vu * vu - CS2 * uu) / (2.0 * CS2 * CS2));
+    }
+}
+
+/* D2Q5 equilibrium with the fluid's velocity: g_i^eq = phi w_i (1 + v_i.u / cs2). */
+void orc_equilibrium5(double phi, double ux, double uy, double out[5])
+{
+    for (int i = 0; i < 5; ++i) {
+        double vu = VX[i] * ux + VY[i] * uy;
+        out[i] = phi * W5[i] * (1.0 + vu / CS2);
+    }
+}
+
+/* Reaction terms (the paper's CDESolver hook; Schnakenberg from "Turing Patterning").
+ * phi: the S local concentrations; m: the local domain ID. */
+double orc_reaction(const orc_params* p, int32_t s, const double* phi, int32_t m)
+{
+    const double* c = p->rc[s];
+    switch (p->reaction[s]) {
+    case ORC_REACT_SOURCE_DECAY:
+        return (m != 0 ? c[0] : 0.0) - c[1] * phi[s];
+    case ORC_REACT_SCHNAKENBERG: {
+        double R = phi[0], L = phi[1];
+        if (s == 0) return c[2] * (c[0] - R + R * R * L);
+        return c[2] * (c[1] - R * R * L);
+    }
+    default:
+        return 0.0;
+    }
+}
+
+/* ------------------------------------------------------------------------------------
+ * Membrane forces, per node, in the paper's per-node form:
+ *  tension   F_i = phi_m ( (x_{i-1}-x_i)/|x_{i-1}-x_i| + (x_{i+1}-x_i)/|x_{i+1}-x_i| )
+ *            (Eq. membraneforce);
+ *  springs   F_i = k (|x_{i+1}-x_i| - l0_i) unit(x_{i+1}-x_i)
+ *                + k (|x_{i-1}-x_i| - l0_{i-1}) unit(x_{i-1}-x_i)
+ *            (Hookean membrane springs; l0_i is the rest length of edge (i, i+1));
+ *  area      F_i = kappa_A (A0 - A) dA/dX_i, A = 1/2 sum (x_k y_{k+1} - x_{k+1} y_k)
+ *            (gradient of kappa_A (A - A0)^2 / 2; not in the paper, used by the tiny
+ *            workload's area pressure).
+ * ---------------------------------------------------------------------------------- */
+void orc_forces(const orc_params* p, int32_t n_cells, const int32_t* off, const double* X,
+                const double* l0, const double* A0, double* F, double* area)
+{
+    for (int32_t c = 0; c < n_cells; ++c) {
+        int64_t a = off[c], b = off[c + 1], n = b - a;
+        double A = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            int64_t i = a + k, j = a + (k + 1) % n;
+            A += X[2 * i] * X[2 * j + 1] - X[2 * j] * X[2 * i + 1];
+        }
+        A *= 0.5;
+        if (area) area[c] = A;
+        for (int64_t k = 0; k < n; ++k) {
+            int64_t i = a + k, ip = a + (k + 1) % n, im = a + (k + n - 1) % n;
+            double dpx = X[2 * ip] - X[2 * i], dpy = X[2 * ip + 1] - X[2 * i + 1];
+            double dmx = X[2 * im] - X[2 * i], dmy = X[2 * im + 1] - X[2 * i + 1];
+            double Lp = sqrt(dpx * dpx + dpy * dpy), Lm = sqrt(dmx * dmx + dmy * dmy);
+            double fx = 0.0, fy = 0.0;
+            /* tension */
+            fx += p->phi_m * (dmx / Lm + dpx / Lp);
+            fy += p->phi_m * (dmy / Lm + dpy / Lp);
+            /* springs */
+            fx += p->k_spring * (Lp - l0[i]) * dpx / Lp + p->k_spring * (Lm - l0[im]) * dmx / Lm;
+            fy += p->k_spring * (Lp - l0[i]) * dpy / Lp + p->k_spring * (Lm - l0[im]) * dmy / Lm;
+            /* area pressure */
+            double s = p->kappa_area * (A0[c] - A);
+            fx += s * 0.5 * (X[2 * ip + 1] - X[2 * im + 1]);
+            fy += s * 0.5 * (X[2 * im] - X[2 * ip]);
+            F[2 * i] = fx;
+            F[2 * i + 1] = fy;
+        }
+    }
+}
+
+/* Eq. (forcedistribution) discretised: f(x) += F_l delta(x - X_l) over the 4x4
+ * stencil i0 = floor(X) - 1 .. i0 + 3, nodes in index order.  ex/ey accumulate. */
+void orc_spread(const orc_params* p, int64_t n, const double* X, const double* F,
+                double* ex, double* ey)
+{
+    for (int64_t l = 0; l < n; ++l) {
+        double x = X[2 * l], y = X[2 * l + 1];
+        int64_t i0 = (int64_t)floor(x) - 1, j0 = (int64_t)floor(y) - 1;
+        for (int bb = 0; bb < 4; ++bb) {
+            int64_t j = j0 + bb;
+            if (p->bc_y == ORC_WALLS) { if (j < 0 || j >= p->ny) continue; }
+            else j = wrapi(j, p->ny);
+            double wy = orc_delta1d(p->delta_kernel, y - (double)(j0 + bb));
+            for (int aa = 0; aa < 4; ++aa) {
+                int64_t i = wrapi(i0 + aa, p->nx);
+                double w = orc_delta1d(p->delta_kernel, x - (double)(i0 + aa)) * wy;
+                ex[j * p->nx + i] += w * F[2 * l];
+                ey[j * p->nx + i] += w * F[2 * l + 1];
+            }
+        }
+    }
+}
+
+/* Eq. (conversion2) discretised: U_l = sum_x u(x) delta(x - X_l), same stencil. */
+void orc_interp(const orc_params* p, int64_t n, const double* X, const double* ux,
+                const double* uy, double* U)
+{
+    for (int64_t l = 0; l < n; ++l) {
+        double x = X[2 * l], y = X[2 * l + 1];
+        int64_t i0 = (int64_t)floor(x) - 1, j0 = (int64_t)floor(y) - 1;
+        double sx = 0.0, sy = 0.0;
+        for (int bb = 0; bb < 4; ++bb) {
+            int64_t j = j0 + bb;
+            if (p->bc_y == ORC_WALLS) { if (j < 0 || j >= p->ny) continue; }
+            else j = wrapi(j, p->ny);
+            double wy = orc_delta1d(p->delta_kernel, y - (double)(j0 + bb));
+            for (int aa = 0; aa < 4; ++aa) {
+                int64_t i = wrapi(i0 + aa, p->nx);
+                double w = orc_delta1d(p->delta_kernel, x - (double)(i0 + aa)) * wy;
+                sx += w * ux[j * p->nx + i];
+                sy += w * uy[j * p->nx + i];
+            }
+        }
+        U[2 * l] = sx;
+        U[2 * l + 1] = sy;
+    }
+}
+
+/* Domain IDs on the lattice (Section "Cell Representation": the domain on the left
+ * of each CCW connection carries the cell's ID, zero is the extracellular space).
+ * For each cell in ascending ID, each lattice node (integer coordinates) of its
+ * bounding box, in unwrapped coordinates (which covers the periodic images), is
+ * inside when the number of edges crossed by the ray to +x is odd; a node keeps the
+ * first (smallest) ID that claims it.  Returns the number of nodes claimed twice. */
+int64_t orc_raster(const orc_params* p, int32_t n_cells, const int32_t* off, const double* X,
+                   int32_t* mask)
+{
+    int64_t overlaps = 0;
+    int64_t nx = p->nx, ny = p->ny;
+    memset(mask, 0, sizeof(int32_t) * (size_t)(nx * ny));
+    double* xc = NULL;
+    size_t cap = 0;
+    for (int32_t c = 0; c < n_cells; ++c) {
+        int64_t a = off[c], b = off[c + 1], n = b - a;
+        double xmin = X[2 * a], xmax = xmin, ymin = X[2 * a + 1], ymax = ymin;
+        for (int64_t k = a; k < b; ++k) {
+            if (X[2 * k] < xmin) xmin = X[2 * k];
+            if (X[2 * k] > xmax) xmax = X[2 * k];
+            if (X[2 * k + 1] < ymin) ymin = X[2 * k + 1];
+            if (X[2 * k + 1] > ymax) ymax = X[2 * k + 1];
+        }
+        if ((size_t)n > cap) { cap = (size_t)n; xc = (double*)realloc(xc, cap * sizeof(double)); }
+        for (int64_t py = (int64_t)ceil(ymin); py <= (int64_t)floor(ymax); ++py) {
+            /* crossings of this row: (a.y > py) != (b.y > py) */
+            int64_t nc = 0;
+            for (int64_t k = 0; k < n; ++k) {
+                const double* A = &X[2 * (a + k)];
+                const double* B = &X[2 * (a + (k + 1) % n)];
+                if ((A[1] > (double)py) != (B[1] > (double)py))
+                    xc[nc++] = A[0] + ((double)py - A[1]) * (B[0] - A[0]) / (B[1] - A[1]);
+            }
+            if (nc == 0) continue;
+            int64_t jj;
+            if (p->bc_y == ORC_WALLS) { if (py < 0 || py >= ny) continue; jj = py; }
+            else jj = wrapi(py, ny);
+            for (int64_t px = (int64_t)ceil(xmin); px <= (int64_t)floor(xmax); ++px) {
+                int64_t cnt = 0;
+                for (int64_t q = 0; q < nc; ++q)
+                    if ((double)px < xc[q]) ++cnt;
+                if (cnt & 1) {
+                    int32_t* m = &mask[jj * nx + wrapi(px, nx)];
+                    if (*m == 0) *m = c + 1;
+                    else ++overlaps;
+                }
+            }
+        }
+    }
+    free(xc);
+    return overlaps;
+}
+
+/* ------------------------------------------------------------------------------------
+ * simulation context
+ * ---------------------------------------------------------------------------------- */
+orc_ctx* orc_create(const orc_params* p)
+{
+    orc_ctx* c = (orc_ctx*)calloc(1, sizeof(orc_ctx));
+    c->p = *p;
+    c->nn = (int64_t)p->nx * p->ny;
+    size_t nn = (size_t)c->nn;
+    int S = p->n_species;
+    c->f = (double*)malloc(sizeof(double) * 9 * nn);
+    c->fnew = (double*)malloc(sizeof(double) * 9 * nn);
+    c->g = (double*)malloc(sizeof(double) * (size_t)(5 * (S > 0 ? S : 1)) * nn);
+    c->gnew = (double*)malloc(sizeof(double) * (size_t)(5 * (S > 0 ? S : 1)) * nn);
+    c->rho = (double*)malloc(sizeof(double) * nn);
+    c->ux = (double*)malloc(sizeof(double) * nn);
+    c->uy = (double*)malloc(sizeof(double) * nn);
+    c->ex = (double*)calloc(nn, sizeof(double));
+    c->ey = (double*)calloc(nn, sizeof(double));
+    c->mask = (int32_t*)calloc(nn, sizeof(int32_t));
+    orc_set_fields(c, NULL, NULL, NULL);
+    return c;
+}
+
+void orc_destroy(orc_ctx* c)
+{
+    if (!c) return;
+    free(c->f); free(c->fnew); free(c->g); free(c->gnew);
+    free(c->rho); free(c->ux); free(c->uy); free(c->ex); free(c->ey); free(c->mask);
+    free(c->off); free(c->X); free(c->F); free(c->l0); free(c->A0); free(c->area);
+    free(c);
+}
+
+int32_t orc_set_cells(orc_ctx* c, int32_t n_cells, const int32_t* off, const double* X,
+                      const double* rest_len, const double* rest_area)
+{
+    free(c->off); free(c->X); free(c->F); free(c->l0); free(c->A0); free(c->area);
+    c->n_cells = n_cells;
+    c->n_nodes = off[n_cells];
+    size_t N = (size_t)c->n_nodes;
+    c->off = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_cells + 1));
+    memcpy(c->off, off, sizeof(int32_t) * (size_t)(n_cells + 1));
+    c->X = (double*)malloc(sizeof(double) * 2 * (N ? N : 1));
+    c->F = (double*)calloc(2 * (N ? N : 1), sizeof(double));
+    c->l0 = (double*)malloc(sizeof(double) * (N ? N : 1));
+    c->A0 = (double*)malloc(sizeof(double) * (size_t)(n_cells ? n_cells : 1));
+    c->area = (double*)malloc(sizeof(double) * (size_t)(n_cells ? n_cells : 1));
+    memcpy(c->X, X, sizeof(double) * 2 * N);
+    for (int32_t q = 0; q < n_cells; ++q) {
+        int64_t a = off[q], b = off[q + 1], n = b - a;
+        double A = 0.0;
+        for (int64_t k = 0; k < n; ++k) {
+            int64_t i = a + k, j = a + (k + 1) % n;
+            double dx = X[2 * j] - X[2 * i], dy = X[2 * j + 1] - X[2 * i + 1];
+            c->l0[i] = rest_len ? rest_len[i] : sqrt(dx * dx + dy * dy);
+            A += X[2 * i] * X[2 * j + 1] - X[2 * j] * X[2 * i + 1];
+        }
+        c->A0[q] = rest_area ? rest_area[q] : 0.5 * A;
+    }
+    return 0;
+}
+
+/* Equilibrium initial state: f = f^eq(rho, u), g_s = g^eq(phi_s, u).  NULL fields take
+ * rho0, zero velocity and zero concentration. */
+void orc_set_fields(orc_ctx* c, const double* rho, const double* u, const double* phi)
+{
+    int64_t nn = c->nn;
+    double e9[9], e5[5];
+    for (int64_t x = 0; x < nn; ++x) {
+        double r = rho ? rho[x] : c->p.rho0;
+        double vx = u ? u[x] : 0.0, vy = u ? u[nn + x] : 0.0;
+        orc_equilibrium9(r, vx, vy, e9);
+        for (int i = 0; i < 9; ++i) c->f[i * nn + x] = e9[i];
+        for (int s = 0; s < c->p.n_species; ++s) {
+            orc_equilibrium5(phi ? phi[s * nn + x] : 0.0, vx, vy, e5);
+            for (int i = 0; i < 5; ++i) c->g[(s * 5 + i) * nn + x] = e5[i];
+        }
+    }
+}
+
+static int needs_mask(const orc_params* p)
+{
+    for (int s = 0; s < p->n_species; ++s)
+        if (p->reaction[s] == ORC_REACT_SOURCE_DECAY) return 1;
+    return 0;
+}
+
+static void moments(orc_ctx* c)
+{
+    int64_t nn = c->nn;
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < nn; ++x) {
+        double r = 0.0, jx = 0.0, jy = 0.0;
+        for (int i = 0; i < 9; ++i) {
+            double fi = c->f[i * nn + x];
+            r += fi;
+            jx += fi * VX[i];
+            jy += fi * VY[i];
+        }
+        c->rho[x] = r;
+        c->ux[x] = jx / r;
+        c->uy[x] = jy / r;
+    }
+}
+
+/* One coupled step, in the order of Fig. "Algorithm Overview":
+ *  1 membrane forces F(X^n); 2 spread F -> f(x) (+ body acceleration);
+ *  3 domain IDs m^n of X^n (only when a reaction reads them);
+ *  4 collision of fluid (Eq. bgkequation) and species (D2Q5 equation) with u^n;
+ *  5 streaming (free flight), halfway bounce-back at walls;
+ *  6 interpolation of u^n to the nodes (Eq. conversion2) and explicit move. */
+static void step_once(orc_ctx* c)
+{
+    const orc_params* p = &c->p;
+    int64_t nx = p->nx, ny = p->ny, nn = c->nn;
+    int S = p->n_species;
+
+    /* 1-2: forces and spreading */
+    memset(c->ex, 0, sizeof(double) * (size_t)nn);
+    memset(c->ey, 0, sizeof(double) * (size_t)nn);
+    if (c->n_cells > 0) {
+        orc_forces(p, c->n_cells, c->off, c->X, c->l0, c->A0, c->F, c->area);
+        orc_spread(p, c->n_nodes, c->X, c->F, c->ex, c->ey);
+    }
+    for (int64_t x = 0; x < nn; ++x) { c->ex[x] += p->body[0]; c->ey[x] += p->body[1]; }
+
+    /* 3: domain IDs */
+    if (needs_mask(p)) orc_raster(p, c->n_cells, c->off, c->X, c->mask);
+    else memset(c->mask, 0, sizeof(int32_t) * (size_t)nn);
+
+    /* 4: moments and collision (post-collision values into f / g in place) */
+    moments(c);
+    double tauD[2];
+    for (int s = 0; s < S; ++s) tauD[s] = p->D[s] / CS2 + 0.5;
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < nn; ++x) {
+        double feq[9], geq[5], phi[2] = {0.0, 0.0}, R[2];
+        double r = c->rho[x], vx = c->ux[x], vy = c->uy[x];
+        orc_equilibrium9(r, vx, vy, feq);
+        for (int i = 0; i < 9; ++i) {
+            double fi = c->f[i * nn + x];
+            double force = r * W9[i] * (VX[i] * c->ex[x] + VY[i] * c->ey[x]) / CS2;
+            c->f[i * nn + x] = fi - (fi - feq[i]) / p->tau + force;
+        }
+        for (int s = 0; s < S; ++s) {
+            double sum = 0.0;
+            for (int i = 0; i < 5; ++i) sum += c->g[(s * 5 + i) * nn + x];
+            phi[s] = sum;
+        }
+        for (int s = 0; s < S; ++s) R[s] = orc_reaction(p, s, phi, c->mask[x]);
+        for (int s = 0; s < S; ++s) {
+            orc_equilibrium5(phi[s], vx, vy, geq);
+            for (int i = 0; i < 5; ++i) {
+                double gi = c->g[(s * 5 + i) * nn + x];
+                c->g[(s * 5 + i) * nn + x] = gi - (gi - geq[i]) / tauD[s] + W5[i] * R[s];
+            }
+        }
+    }
+
+    /* 5: streaming f(x + v_i, t + 1) = f*(x, t); a population leaving through a wall
+     * returns to its node in the opposite direction (halfway bounce-back). */
+#pragma omp parallel for schedule(static)
+    for (int64_t y = 0; y < ny; ++y) {
+        for (int64_t x = 0; x < nx; ++x) {
+            int64_t src = y * nx + x;
+            for (int i = 0; i < 9; ++i) {
+                int64_t xd = wrapi(x + VX[i], nx), yd = y + VY[i];
+                double v = c->f[i * nn + src];
+                if (p->bc_y == ORC_WALLS && (yd < 0 || yd >= ny)) {
+                    if (yd >= ny && p->wall_u_top != 0.0)
+                        v -= 2.0 * W9[i] * c->rho[src] * (VX[i] * p->wall_u_top) / CS2;
+                    c->fnew[OPP[i] * nn + src] = v;
+                } else {
+                    c->fnew[i * nn + wrapi(yd, ny) * nx + xd] = v;
+                }
+            }
+            for (int s = 0; s < S; ++s) {
+                for (int i = 0; i < 5; ++i) {
+                    int64_t xd = wrapi(x + VX[i], nx), yd = y + VY[i];
+                    double v = c->g[(s * 5 + i) * nn + src];
+                    if (p->bc_y == ORC_WALLS && (yd < 0 || yd >= ny))
+                        c->gnew[(s * 5 + OPP[i]) * nn + src] = v;
+                    else
+                        c->gnew[(s * 5 + i) * nn + wrapi(yd, ny) * nx + xd] = v;
+                }
+            }
+        }
+    }
+    double* t = c->f; c->f = c->fnew; c->fnew = t;
+    t = c->g; c->g = c->gnew; c->gnew = t;
+
+    /* 6: interpolate and move (positions stay unwrapped) */
+    if (c->n_nodes > 0) {
+        double* U = (double*)malloc(sizeof(double) * 2 * (size_t)c->n_nodes);
+        if (p->interp_new_u) {
+            /* alternative reading: the velocity after advancing the fluid */
+            double *r2 = c->rho, *x2 = c->ux, *y2 = c->uy;
+            double* tmp = (double*)malloc(sizeof(double) * 3 * (size_t)nn);
+            c->rho = tmp; c->ux = tmp + nn; c->uy = tmp + 2 * nn;
+            moments(c);
+            orc_interp(p, c->n_nodes, c->X, c->ux, c->uy, U);
+            c->rho = r2; c->ux = x2; c->uy = y2;
+            free(tmp);
+        } else {
+            orc_interp(p, c->n_nodes, c->X, c->ux, c->uy, U);
+        }
+        for (int64_t l = 0; l < 2 * c->n_nodes; ++l) c->X[l] += U[l];
+        free(U);
+    }
+}
+
+void orc_step(orc_ctx* c, int32_t n)
+{
+    for (int32_t k = 0; k < n; ++k) step_once(c);
+}
+
+void orc_get_fields(orc_ctx* c, double* rho, double* u, double* phi, double* X, int32_t* mask)
+{
+    int64_t nn = c->nn;
+    for (int64_t x = 0; x < nn; ++x) {
+        double r = 0.0, jx = 0.0, jy = 0.0;
+        for (int i = 0; i < 9; ++i) {
+            double fi = c->f[i * nn + x];
+            r += fi; jx += fi * VX[i]; jy += fi * VY[i];
+        }
+        if (rho) rho[x] = r;
+        if (u) { u[x] = jx / r; u[nn + x] = jy / r; }
+        if (phi) {
+            for (int s = 0; s < c->p.n_species; ++s) {
+                double sum = 0.0;
+                for (int i = 0; i < 5; ++i) sum += c->g[(s * 5 + i) * nn + x];
+                phi[s * nn + x] = sum;
+            }
+        }
+    }
+    if (X && c->n_nodes) memcpy(X, c->X, sizeof(double) * 2 * (size_t)c->n_nodes);
+    if (mask) orc_raster(&c->p, c->n_cells, c->off, c->X, mask);
+}
+
+void orc_get_populations(const orc_ctx* c, double* f, double* g)
+{
+    if (f) memcpy(f, c->f, sizeof(double) * 9 * (size_t)c->nn);
+    if (g && c->p.n_species) memcpy(g, c->g, sizeof(double) * 5 * (size_t)c->p.n_species * (size_t)c->nn);
+}
+
+void orc_set_populations(orc_ctx* c, const double* f, const double* g)
+{
+    if (f) memcpy(c->f, f, sizeof(double) * 9 * (size_t)c->nn);
+    if (g && c->p.n_species) memcpy(c->g, g, sizeof(double) * 5 * (size_t)c->p.n_species * (size_t)c->nn);
+}
+
+void orc_get_last_spread(const orc_ctx* c, double* ex, double* ey)
+{
+    memcpy(ex, c->ex, sizeof(double) * (size_t)c->nn);
+    memcpy(ey, c->ey, sizeof(double) * (size_t)c->nn);
+}
+
+void orc_get_forces(orc_ctx* c, double* F, double* area)
+{
+    if (c->n_cells == 0) return;
+    orc_forces(&c->p, c->n_cells, c->off, c->X, c->l0, c->A0, F, area);
+}
+
+void orc_invariants(const orc_ctx* c, double* out)
+{
+    /* long double accumulators: the sums are used to check conservation to round-off */
+    int64_t nn = c->nn;
+    long double m = 0.0L, px = 0.0L, py = 0.0L;
+    for (int64_t x = 0; x < nn; ++x)
+        for (int i = 0; i < 9; ++i) {
+            double fi = c->f[i * nn + x];
+            m += fi; px += fi * VX[i]; py += fi * VY[i];
+        }
+    out[0] = (double)m; out[1] = (double)px; out[2] = (double)py;
+    for (int s = 0; s < c->p.n_species; ++s) {
+        long double t = 0.0L;
+        for (int64_t x = 0; x < nn; ++x)
+            for (int i = 0; i < 5; ++i) t += c->g[(s * 5 + i) * nn + x];
+        out[3 + s] = (double)t;
+    }
+}
