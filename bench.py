@@ -1,0 +1,136 @@
+"""Throughput of the coupled LBM + IB step on one MI355X.
+
+A step is one pass of the whole hot path (lattice pass with force spreading, membrane
+interpolation / advection / forces, node binning, domain-ID rasterisation) over the
+2048 x 2048 lattice with 2000 Voronoi cells.  Prints one JSON line (rank 0).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|tissue|tiny]
+                  [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "coupled LBM+IB MLUPS at 2048²/2000 cells (% HBM peak); ADE iters-to-steady"
+HBM_PEAK_GBS = 8000.0
+# HBM traffic per launch of the lattice kernel measured with rocprofv3 --pmc (FETCH_SIZE,
+# WRITE_SIZE, scaled by a copy kernel of known size); None until taken for the current kernel
+LATTICE_TRAFFIC_BYTES = None
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def lattice_bytes_per_update(S: int, mask: bool) -> int:
+    """Algorithmic bytes per lattice node of one lattice pass: every FP32 population read
+    once and written once, plus the 16-bit domain ID read."""
+    return 4 * 2 * (9 + 5 * S) + (2 if mask else 0)
+
+
+def step_bytes_per_update(S: int, mask: bool, n_nodes: int, nn: int) -> float:
+    """Algorithmic bytes per lattice node of a whole step: the lattice pass plus the node
+    positions read and written (16 B per node, FP64 x and y)."""
+    return lattice_bytes_per_update(S, mask) + 16.0 * n_nodes / nn
+
+
+def cpu_baseline(w, budget_s: float = 12.0, max_steps: int = 30):
+    from oracle import oracle as O
+    log("cpu baseline: oracle on the same workload")
+    o = O.from_workload(w)
+    t0 = time.perf_counter()
+    n = 0
+    while n < max_steps:
+        o.step(1)
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    mlups = w.nx * w.ny * n / dt / 1e6
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
+            "sample": f"{n} steps of the same {w.nx}x{w.ny} workload ({w.n_cells} cells) in FP64, "
+                      f"{dt:.1f} s, OpenMP lattice loops"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="large", choices=["large", "tissue", "tiny"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the lattice would shard into "
+              "y-slabs across GPUs, which this build does not implement.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1503_06726_amd import lbib, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = W.WORKLOADS[args.workload]()
+    S = w.n_species
+    mask = w.mask_needed()
+    log(f"workload: {w.name}, {w.n_nodes} nodes")
+    stream = torch.cuda.current_stream().cuda_stream
+    sim = lbib.from_workload(w, stream=stream)
+    log(f"device memory: {sim.device_bytes() / 2**20:.1f} MiB")
+    sim.step(args.warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} steps done")
+
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    timings = {lbib.KERNEL_NAMES[k]: sim.get_timing(k) for k in range(5)}
+    sim.set_timing(False)
+    log(f"timed {args.steps} steps: {dt:.3f} s")
+    for k, (ms, n) in timings.items():
+        if n:
+            log(f"  {k:12s} {ms / n * 1e3:9.2f} us/launch  ({n} launches)")
+
+    # sanity: the state is finite after the timed run
+    red = sim.reduce()
+    sim.close()
+
+    nn = w.nx * w.ny
+    mlups = nn * args.steps / dt / 1e6
+    lat_ms, lat_n = timings["lattice"]
+    lat_s = lat_ms / lat_n / 1e3
+    b_lat = lattice_bytes_per_update(S, mask)
+    achieved = b_lat * nn / lat_s / 1e9
+    b_step = step_bytes_per_update(S, mask, w.n_nodes, nn)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": LATTICE_TRAFFIC_BYTES,
+            "kernel": "k_lattice", "bytes_per_update": b_lat, "us_per_launch": round(lat_s * 1e6, 2),
+            "step_bytes_per_update": round(b_step, 2),
+            "step_frac": round(b_step * mlups * 1e6 / 1e9 / HBM_PEAK_GBS, 4)}
+    out = {"metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (seeded Voronoi tissue, SeedSequence(1503))",
+           "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "n_cells": w.n_cells, "n_nodes": w.n_nodes,
+                      "species": S, "tau": w.tau, "storage": "fp32 deviations, fp64 node positions"},
+           "roofline": roof,
+           "kernels_us": {k: round(ms / n * 1e3, 2) for k, (ms, n) in timings.items() if n},
+           "mass": red[0]}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

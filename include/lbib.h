@@ -1,0 +1,183 @@
+/* lbib -- MI355X (gfx950) library for the coupled lattice-Boltzmann / immersed-boundary
+ * time step of the LBIBCell method (Tanaka, Sichau & Iber, arXiv:1503.06726).
+ *
+ * One step advances, on one GPU:
+ *   - the D2Q9 BGK fluid with the immersed-boundary body force
+ *       (Suppl. "Lattice Boltzmann Method", Eq. bgkequation, Eq. standardequilibrium);
+ *   - one D2Q5 advection-diffusion(-reaction) lattice per morphogen species, fed with the
+ *     fluid's velocity (Suppl. "Lattice Boltzmann Method", D2Q5 equations; reaction laws of
+ *     the "Turing Patterning" section and a source/decay law);
+ *   - the polygonal cell membranes: forces (Eq. membraneforce, Hookean springs, area
+ *     pressure), spreading to the lattice (Eq. forcedistribution) and interpolation back with
+ *     the 4x4 cosine kernel (Eq. 1Dkernel), explicit node advection (Eq. conversion2);
+ *   - the domain-ID map (Section "Cell Representation": the ID of the cell on the left of each
+ *     counter-clockwise connection, zero outside all cells).
+ *
+ * Units: lattice units, dx = dt = 1, c_s^2 = 1/3.  x is periodic; y is periodic or bounded by
+ * no-slip halfway bounce-back walls at y = -1/2 and y = ny - 1/2.
+ *
+ * Layouts (all caller buffers are C-contiguous, row-major):
+ *   scalar field    [ny][nx], index y*nx + x
+ *   vector field    [2][ny][nx] (x component plane, then y component plane)
+ *   species fields  [n_species][ny][nx]
+ *   node positions  [N][2] (x, y) doubles, unwrapped in x (and in y when periodic)
+ *   cells           CSR: offsets[n_cells+1], offsets[0] = 0; nodes offsets[c] .. offsets[c+1]-1
+ *                   form cell c+1's polygon in counter-clockwise order; edge k joins node k to
+ *                   its cyclic successor in the same cell.
+ *
+ * Ownership: every input is copied before the call returns; outputs go to caller buffers.
+ * The context owns its device memory (hipMalloc) and launches on the stream given at creation.
+ *
+ * Errors: every call returns an lbib_status; nothing prints or aborts.  A call that fails
+ * validation leaves the context unchanged.  lbib_last_error() gives a message.
+ *
+ * Threading: a context is not thread-safe.  lbib_step() is asynchronous on the context's
+ * stream; calls that return data synchronise that stream.
+ */
+#ifndef LBIB_H
+#define LBIB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBIB_VERSION 1
+
+typedef enum {
+    LBIB_OK = 0,
+    LBIB_EINVAL = -1,    /* an argument failed validation */
+    LBIB_ENOMEM = -2,    /* device or host allocation failed */
+    LBIB_EDEVICE = -3,   /* no usable GPU, or a HIP call failed */
+    LBIB_ESTATE = -4,    /* call made in the wrong state (e.g. NULL context) */
+    LBIB_ENUMERIC = -5   /* non-finite state detected (monitor or node positions) */
+} lbib_status;
+
+enum { LBIB_PERIODIC = 0, LBIB_WALLS = 1 };
+enum { LBIB_DELTA_COS4 = 0,      /* the paper's kernel (1 + cos(pi r / 2)) / 4, |r| <= 2 */
+       LBIB_DELTA_PESKIN4 = 1 }; /* Peskin's standard 4-point kernel (zero first moment) */
+enum { LBIB_REACT_NONE = 0,
+       LBIB_REACT_SOURCE_DECAY = 1,   /* R = c[0] * [inside any cell] - c[1] * phi            */
+       LBIB_REACT_SCHNAKENBERG = 2 }; /* species 0: R = c[2] (c[0] - u + u^2 v),
+                                         species 1: R = c[2] (c[1] - u^2 v), u = phi_0, v = phi_1;
+                                         both species must name it, with equal c[0..2] */
+enum { LBIB_STORAGE_FP32 = 0 };       /* populations stored as FP32 deviations from rest */
+
+typedef struct {
+    double D;          /* diffusivity, > 0; relaxation time tau_D = 3 D + 1/2 */
+    double phi_ref;    /* storage reference concentration (deviation storage); any finite value */
+    int32_t reaction;  /* LBIB_REACT_* */
+    int32_t reserved;  /* must be 0 */
+    double c[4];       /* reaction constants (per step), see LBIB_REACT_* */
+} lbib_species;
+
+typedef struct {
+    int32_t nx, ny;          /* lattice size, 4 .. 32767 each */
+    int32_t bc_y;            /* LBIB_PERIODIC or LBIB_WALLS */
+    int32_t delta_kernel;    /* LBIB_DELTA_* */
+    double tau;              /* fluid relaxation time, > 1/2; nu = (tau - 1/2) / 3 */
+    double rho0;             /* reference density (initial density and storage reference), > 0 */
+    double body_accel[2];    /* uniform acceleration added to the spread force field */
+    double k_spring;         /* Hookean membrane spring constant (0 disables) */
+    double phi_m;            /* constant membrane tension (0 disables) */
+    double kappa_area;       /* area-pressure stiffness: energy kappa_A (A - A0)^2 / 2 (0 disables) */
+    int32_t n_species;       /* 0, 1 or 2 */
+    int32_t storage;         /* LBIB_STORAGE_FP32 */
+    lbib_species species[2];
+} lbib_params;
+
+typedef struct lbib_ctx lbib_ctx;
+
+/* Validate parameters without touching a GPU.  msg (optional) receives a reason.
+ * Returns LBIB_OK or LBIB_EINVAL. */
+lbib_status lbib_validate_params(const lbib_params* p, char* msg, size_t msg_len);
+
+/* Validate a cell set (same rules as lbib_set_cells) without touching a GPU. */
+lbib_status lbib_validate_cells(const lbib_params* p, int32_t n_cells, const int32_t* offsets,
+                                const double* xy, const double* rest_len, const double* rest_area,
+                                char* msg, size_t msg_len);
+
+/* Create a context on the current HIP device.  hip_stream is a hipStream_t to launch on
+ * (NULL: the library creates its own).  The lattice starts at rest: rho = rho0, u = 0,
+ * every concentration 0, no cells.  On failure *out is NULL and the status says why
+ * (LBIB_EINVAL, LBIB_EDEVICE when no GPU is usable, LBIB_ENOMEM). */
+lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out);
+
+/* Set the membranes (Section "Cell Representation": closed CCW polygons, the cell's ID is
+ * c+1 for the c-th polygon, 0 is the extracellular space).
+ *   offsets   [n_cells+1] host int32, CSR as above; 0 <= n_cells <= 65535;
+ *             3 .. 4096 nodes per cell
+ *   xy        [N][2] host doubles, N = offsets[n_cells]; finite, |coordinate| < 2^20
+ *   rest_len  [N] host doubles (edge k's rest length) or NULL for the initial edge lengths
+ *   rest_area [n_cells] host doubles or NULL for the initial areas
+ * Rejected (LBIB_EINVAL): clockwise or degenerate polygons (signed area <= 0), non-finite
+ * values, bad offsets, a polygon spanning nx (or ny when periodic) or more, and with walls
+ * any node closer than 2 lattice units to a wall (y < 1.5 or y > ny - 2.5).
+ * Computes the forces of the new positions and the domain-ID map. */
+lbib_status lbib_set_cells(lbib_ctx* ctx, int32_t n_cells, const int32_t* offsets, const double* xy,
+                           const double* rest_len, const double* rest_area);
+
+/* Reset the lattice to equilibrium populations f^eq(rho, u), g^eq(phi_s, u)
+ * (Eq. standardequilibrium and the D2Q5 equilibrium).  Host doubles:
+ *   rho [ny][nx] or NULL (rho0), u [2][ny][nx] or NULL (0), phi [S][ny][nx] or NULL (0). */
+lbib_status lbib_set_fields(lbib_ctx* ctx, const double* rho, const double* u, const double* phi);
+
+/* Enqueue n >= 0 coupled steps on the context's stream (asynchronous).  Each step, from
+ * state (f^n, g^n, X^n): spread the membrane forces F(X^n) plus the body acceleration, collide
+ * the fluid and every species with u^n = sum f^n v / rho^n and the domain IDs of X^n, stream,
+ * then move every node by the interpolated u^n (Fig. "Algorithm Overview"). */
+lbib_status lbib_step(lbib_ctx* ctx, int32_t n);
+
+/* Copy the current state to host buffers (NULL skips an output); synchronises the stream.
+ *   rho [ny][nx], u [2][ny][nx], phi [S][ny][nx] doubles (moments of the current populations),
+ *   xy [N][2] doubles (current node positions), cell_id_map [ny][nx] int32 (domain IDs).
+ * Returns LBIB_ENUMERIC (after copying) if a node position became non-finite. */
+lbib_status lbib_get_fields(lbib_ctx* ctx, double* rho, double* u, double* phi, double* xy,
+                            int32_t* cell_id_map);
+
+/* Membrane forces F(X) of the current positions ([N][2] doubles, NULL skips) and the
+ * cell areas ([n_cells] doubles, NULL skips); synchronises. */
+lbib_status lbib_get_forces(lbib_ctx* ctx, double* F, double* area);
+
+/* The force field the next step will use: the current forces spread to the lattice plus the
+ * body acceleration, as [2][ny][nx] doubles (Eq. forcedistribution); synchronises. */
+lbib_status lbib_get_spread(lbib_ctx* ctx, double* e);
+
+/* Global sums over the lattice in FP64, deterministic:
+ *   out[0] = sum rho, out[1] = sum rho ux, out[2] = sum rho uy, out[3+s] = sum phi_s.
+ * out has 3 + n_species doubles.  Returns LBIB_ENUMERIC if any sum is not finite. */
+lbib_status lbib_reduce(lbib_ctx* ctx, double* out);
+
+/* Wait for all queued work on the context's stream. */
+lbib_status lbib_sync(lbib_ctx* ctx);
+
+/* Per-kernel timing with HIP events on the context's stream (0 disables, default).
+ * Kernel ids: LBIB_K_LATTICE, LBIB_K_MEMBRANE, LBIB_K_BIN_SCAN, LBIB_K_BIN_SCATTER,
+ * LBIB_K_RASTER.  lbib_get_timing synchronises and returns the summed milliseconds and
+ * the number of timed launches since timing was last enabled. */
+enum { LBIB_K_LATTICE = 0, LBIB_K_MEMBRANE = 1, LBIB_K_BIN_SCAN = 2, LBIB_K_BIN_SCATTER = 3,
+       LBIB_K_RASTER = 4, LBIB_K_COUNT = 5 };
+lbib_status lbib_set_timing(lbib_ctx* ctx, int32_t enable);
+lbib_status lbib_get_timing(lbib_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches);
+
+/* Bytes of device memory the context holds. */
+lbib_status lbib_device_bytes(const lbib_ctx* ctx, size_t* bytes);
+
+/* Last error message of the context (never NULL; "" when none). */
+const char* lbib_last_error(const lbib_ctx* ctx);
+
+/* Name of a status code. */
+const char* lbib_status_string(lbib_status s);
+
+/* Library version (LBIB_VERSION). */
+int32_t lbib_version(void);
+
+/* Free the context and its device memory (waits for its stream).  NULL is ignored. */
+void lbib_destroy(lbib_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBIB_H */

@@ -42,6 +42,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ---- lattice constants (Suppl. "Lattice Boltzmann Method", D2Q9 and D2Q5 footnotes) ---- */
 static const int VX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -530,6 +533,15 @@ void orc_get_forces(orc_ctx* c, double* F, double* area)
 {
     if (c->n_cells == 0) return;
     orc_forces(&c->p, c->n_cells, c->off, c->X, c->l0, c->A0, F, area);
+}
+
+int32_t orc_threads(void)
+{
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 void orc_invariants(const orc_ctx* c, double* out)

@@ -85,6 +85,7 @@ void     orc_set_populations(orc_ctx* c, const double* f, const double* g);
 void     orc_get_last_spread(const orc_ctx* c, double* ex, double* ey);
 void     orc_get_forces(orc_ctx* c, double* F, double* area);
 void     orc_invariants(const orc_ctx* c, double* out);   /* sum rho, sum rho*ux, sum rho*uy, sum phi_s */
+int32_t  orc_threads(void);                               /* OpenMP threads the lattice loops use */
 
 #ifdef __cplusplus
 }

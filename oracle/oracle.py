@@ -82,6 +82,8 @@ def lib():
     L.orc_get_last_spread.argtypes = [C.c_void_p, dp, dp]
     L.orc_get_forces.argtypes = [C.c_void_p, dp, dp]
     L.orc_invariants.argtypes = [C.c_void_p, dp]
+    L.orc_threads.restype = C.c_int32
+    L.orc_threads.argtypes = []
     _lib = L
     return L
 
@@ -111,6 +113,11 @@ def make_params(d: dict, interp_new_u: bool = False, wall_u_top: float = 0.0) ->
             p.rc[s][k] = float(v)
     p.wall_u_top = float(wall_u_top)
     return p
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's lattice loops run on (1 without OpenMP)."""
+    return int(lib().orc_threads())
 
 
 def delta1d(kernel: int, r: float) -> float:

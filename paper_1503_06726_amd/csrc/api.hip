@@ -1,0 +1,663 @@
+// C ABI of the lbib library: context management, validation, the step loop and data
+// movement.  All device work is issued on the context's stream.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lbib_internal.h"
+
+using namespace lbib;
+
+namespace {
+
+#define LBIB_HIP(ctx, call)                                                                   \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) {                                                               \
+            (ctx)->err = std::string(#call) + " failed: " + hipGetErrorString(e_);            \
+            return e_ == hipErrorOutOfMemory ? LBIB_ENOMEM : LBIB_EDEVICE;                    \
+        }                                                                                     \
+    } while (0)
+
+template <typename T>
+lbib_status dev_alloc(lbib_ctx* c, T** p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        c->err = std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) + " bytes failed: " +
+                 hipGetErrorString(e);
+        return e == hipErrorOutOfMemory ? LBIB_ENOMEM : LBIB_EDEVICE;
+    }
+    c->device_bytes += count * sizeof(T);
+    return LBIB_OK;
+}
+
+template <typename T>
+void dev_free(lbib_ctx* c, T*& p, size_t count)
+{
+    if (p) {
+        (void)hipFree((void*)p);
+        c->device_bytes -= (count ? count : 1) * sizeof(T);
+    }
+    p = nullptr;
+}
+
+#define LBIB_TRY(expr)                  \
+    do {                                \
+        lbib_status s_ = (expr);        \
+        if (s_ != LBIB_OK) return s_;   \
+    } while (0)
+
+// -------------------------------------------------------------------------------------
+// timing
+// -------------------------------------------------------------------------------------
+hipEvent_t take_event(lbib_ctx* c)
+{
+    if (!c->free_events.empty()) {
+        hipEvent_t e = c->free_events.back();
+        c->free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+lbib_status harvest(lbib_ctx* c)
+{
+    if (c->pending.empty()) return LBIB_OK;
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    for (auto& t : c->pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
+            c->t_ms[t.kernel] += ms;
+            c->t_count[t.kernel] += 1;
+        }
+        c->free_events.push_back(t.start);
+        c->free_events.push_back(t.stop);
+    }
+    c->pending.clear();
+    return LBIB_OK;
+}
+
+struct Timed {
+    lbib_ctx* c;
+    int kernel;
+    hipEvent_t start = nullptr, stop = nullptr;
+    Timed(lbib_ctx* ctx, int k) : c(ctx), kernel(k)
+    {
+        if (!c->timing) return;
+        start = take_event(c);
+        stop = take_event(c);
+        if (start) (void)hipEventRecord(start, c->stream);
+    }
+    ~Timed()
+    {
+        if (!c->timing || !start || !stop) return;
+        (void)hipEventRecord(stop, c->stream);
+        c->pending.push_back({kernel, start, stop});
+    }
+};
+
+// -------------------------------------------------------------------------------------
+// kernel argument builders
+// -------------------------------------------------------------------------------------
+LatticeArgs lattice_args(lbib_ctx* c)
+{
+    LatticeArgs a;
+    std::memset(&a, 0, sizeof a);
+    const lbib_params& p = c->p;
+    a.fsrc = c->f[c->cur];
+    a.fdst = c->f[1 - c->cur];
+    a.gsrc = c->g[c->cur];
+    a.gdst = c->g[1 - c->cur];
+    a.nn = c->nn;
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.walls = p.bc_y == LBIB_WALLS;
+    a.ntx = c->ntx;
+    a.nty = c->nty;
+    a.omega = (float)(1.0 / p.tau);
+    a.rho0 = (float)p.rho0;
+    for (int s = 0; s < 2; ++s) {
+        const lbib_species& sp = p.species[s];
+        const double tau_s = 3.0 * sp.D + 0.5;    // D = cs2 (tau_D - 1/2), cs2 = 1/3
+        a.omega_s[s] = s < c->S ? (float)(1.0 / tau_s) : 0.0f;
+        a.phi_ref[s] = (float)sp.phi_ref;
+        a.react[s] = s < c->S ? sp.reaction : 0;
+        for (int k = 0; k < 4; ++k) a.rc[s][k] = (float)sp.c[k];
+    }
+    a.bodyx = (float)p.body_accel[0];
+    a.bodyy = (float)p.body_accel[1];
+    a.kernel = p.delta_kernel;
+    a.bin_off = c->d_bin_off;
+    a.rec = c->d_rec;
+    a.rec_ij = c->d_rec_ij;
+    a.bin_count = c->d_bin_count;
+    a.uband = c->uband;
+    a.mask = c->mask;
+    a.e_out = nullptr;
+    return a;
+}
+
+MembraneArgs membrane_args(lbib_ctx* c, int advect)
+{
+    MembraneArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.off = c->d_off;
+    a.X = c->d_X;
+    a.F = c->d_F;
+    a.l0 = c->d_l0;
+    a.A0 = c->d_A0;
+    a.area = c->d_area;
+    a.uband = c->uband;
+    a.nn = c->nn;
+    a.nx = c->p.nx;
+    a.ny = c->p.ny;
+    a.walls = c->p.bc_y == LBIB_WALLS;
+    a.kernel = c->p.delta_kernel;
+    a.ntx = c->ntx;
+    a.nty = c->nty;
+    a.k_spring = c->p.k_spring;
+    a.phi_m = c->p.phi_m;
+    a.kappa = c->p.kappa_area;
+    a.key = c->d_key;
+    a.rank = c->d_rank;
+    a.bin_count = c->d_bin_count;
+    a.err = c->d_err;
+    a.advect = advect;
+    return a;
+}
+
+ScatterArgs scatter_args(lbib_ctx* c)
+{
+    ScatterArgs a;
+    a.X = c->d_X;
+    a.F = c->d_F;
+    a.key = c->d_key;
+    a.rank = c->d_rank;
+    a.bin_off = c->d_bin_off;
+    a.rec = c->d_rec;
+    a.rec_ij = c->d_rec_ij;
+    a.n = c->n_nodes;
+    a.nx = c->p.nx;
+    a.ny = c->p.ny;
+    a.walls = c->p.bc_y == LBIB_WALLS;
+    return a;
+}
+
+RasterArgs raster_args(lbib_ctx* c)
+{
+    RasterArgs a;
+    a.off = c->d_off;
+    a.X = c->d_X;
+    a.mask = c->mask;
+    a.nx = c->p.nx;
+    a.ny = c->p.ny;
+    a.walls = c->p.bc_y == LBIB_WALLS;
+    return a;
+}
+
+#define LBIB_LAUNCH(ctx, call)                                                               \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            (ctx)->err = std::string(#call) + ": " + hipGetErrorString(e_);                  \
+            return LBIB_EDEVICE;                                                             \
+        }                                                                                    \
+    } while (0)
+
+// forces of the current positions, binning, and (when a reaction reads it) the domain map
+lbib_status membrane_refresh(lbib_ctx* c, int advect)
+{
+    {
+        Timed tm(c, LBIB_K_MEMBRANE);
+        LBIB_LAUNCH(c, launch_membrane(c, membrane_args(c, advect)));
+    }
+    {
+        Timed tm(c, LBIB_K_BIN_SCAN);
+        LBIB_LAUNCH(c, launch_scan(c));
+    }
+    {
+        Timed tm(c, LBIB_K_BIN_SCATTER);
+        LBIB_LAUNCH(c, launch_scatter(c, scatter_args(c)));
+    }
+    if (c->mask_needed) {
+        Timed tm(c, LBIB_K_RASTER);
+        LBIB_LAUNCH(c, launch_raster(c, raster_args(c)));
+    }
+    return LBIB_OK;
+}
+
+lbib_status ensure_stage(lbib_ctx* c, size_t doubles)
+{
+    if (c->stage_bytes >= doubles * sizeof(double)) return LBIB_OK;
+    if (c->d_stage) {
+        LBIB_HIP(c, hipStreamSynchronize(c->stream));
+        dev_free(c, c->d_stage, c->stage_bytes / sizeof(double));
+        c->stage_bytes = 0;
+    }
+    LBIB_TRY(dev_alloc(c, &c->d_stage, doubles));
+    c->stage_bytes = doubles * sizeof(double);
+    return LBIB_OK;
+}
+
+lbib_status check_err_flag(lbib_ctx* c)
+{
+    int h = 0;
+    LBIB_HIP(c, hipMemcpyAsync(&h, c->d_err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    if (h) {
+        c->err = "a membrane node position or force became non-finite";
+        return LBIB_ENUMERIC;
+    }
+    return LBIB_OK;
+}
+
+void free_nodes(lbib_ctx* c)
+{
+    const size_t N = (size_t)c->n_nodes, C = (size_t)c->n_cells;
+    dev_free(c, c->d_off, C + 1);
+    dev_free(c, c->d_X, N);
+    dev_free(c, c->d_F, N);
+    dev_free(c, c->d_l0, N);
+    dev_free(c, c->d_A0, C);
+    dev_free(c, c->d_area, C);
+    dev_free(c, c->d_key, N);
+    dev_free(c, c->d_rank, N);
+    dev_free(c, c->d_rec, N);
+    dev_free(c, c->d_rec_ij, N);
+    c->n_nodes = 0;
+    c->n_cells = 0;
+    c->max_cell_nodes = 0;
+    c->mask_needed = false;
+}
+
+void free_all(lbib_ctx* c)
+{
+    free_nodes(c);
+    const size_t nn = (size_t)c->nn;
+    for (int b = 0; b < 2; ++b) {
+        dev_free(c, c->f[b], 9 * nn);
+        dev_free(c, c->g[b], 5 * (size_t)c->S * nn);
+    }
+    dev_free(c, c->uband, 2 * nn);
+    dev_free(c, c->mask, nn);
+    dev_free(c, c->d_bin_count, (size_t)c->nbins);
+    dev_free(c, c->d_bin_off, (size_t)c->nbins + 1);
+    dev_free(c, c->d_err, 1);
+    dev_free(c, c->d_partial, c->partial_count * 5);
+    if (c->d_stage) dev_free(c, c->d_stage, c->stage_bytes / sizeof(double));
+    c->stage_bytes = 0;
+    for (auto& t : c->pending) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    c->pending.clear();
+    for (auto e : c->free_events) (void)hipEventDestroy(e);
+    c->free_events.clear();
+}
+
+bool any_source_decay(const lbib_params& p)
+{
+    for (int s = 0; s < p.n_species; ++s)
+        if (p.species[s].reaction == LBIB_REACT_SOURCE_DECAY) return true;
+    return false;
+}
+
+lbib_status init_fields(lbib_ctx* c, const double* rho, const double* u, const double* phi)
+{
+    const size_t nn = (size_t)c->nn;
+    const size_t need = nn * (size_t)((rho ? 1 : 0) + (u ? 2 : 0) + (phi ? c->S : 0));
+    double *d_rho = nullptr, *d_u = nullptr, *d_phi = nullptr;
+    if (need) {
+        LBIB_TRY(ensure_stage(c, need));
+        double* q = c->d_stage;
+        if (rho) {
+            d_rho = q;
+            LBIB_HIP(c, hipMemcpyAsync(d_rho, rho, nn * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            q += nn;
+        }
+        if (u) {
+            d_u = q;
+            LBIB_HIP(c, hipMemcpyAsync(d_u, u, 2 * nn * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            q += 2 * nn;
+        }
+        if (phi && c->S) {
+            d_phi = q;
+            LBIB_HIP(c, hipMemcpyAsync(d_phi, phi, (size_t)c->S * nn * sizeof(double), hipMemcpyHostToDevice,
+                                       c->stream));
+        }
+    }
+    LBIB_LAUNCH(c, launch_init(c, d_rho, d_u, d_phi, d_rho != nullptr, d_u != nullptr, d_phi != nullptr));
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    return LBIB_OK;
+}
+
+}  // namespace
+
+// =======================================================================================
+// C ABI
+// =======================================================================================
+extern "C" {
+
+int32_t lbib_version(void) { return LBIB_VERSION; }
+
+const char* lbib_status_string(lbib_status s)
+{
+    switch (s) {
+    case LBIB_OK: return "LBIB_OK";
+    case LBIB_EINVAL: return "LBIB_EINVAL";
+    case LBIB_ENOMEM: return "LBIB_ENOMEM";
+    case LBIB_EDEVICE: return "LBIB_EDEVICE";
+    case LBIB_ESTATE: return "LBIB_ESTATE";
+    case LBIB_ENUMERIC: return "LBIB_ENUMERIC";
+    }
+    return "LBIB_UNKNOWN";
+}
+
+const char* lbib_last_error(const lbib_ctx* ctx)
+{
+    if (!ctx) return "";
+    return ctx->err.c_str();
+}
+
+lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out)
+{
+    if (!out) return LBIB_EINVAL;
+    *out = nullptr;
+    std::string msg;
+    if (check_params(p, msg) != LBIB_OK) return LBIB_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return LBIB_EDEVICE;
+
+    lbib_ctx* c = new (std::nothrow) lbib_ctx();
+    if (!c) return LBIB_ENOMEM;
+    c->p = *p;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return LBIB_EDEVICE;
+    }
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return LBIB_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    c->nn = (int64_t)p->nx * p->ny;
+    c->S = p->n_species;
+    c->ntx = (p->nx + TILE_X - 1) / TILE_X;
+    c->nty = (p->ny + TILE_Y - 1) / TILE_Y;
+    c->nbins = c->ntx * c->nty;
+    c->partial_count = 4096;
+    const size_t nn = (size_t)c->nn;
+    lbib_status s = LBIB_OK;
+    for (int b = 0; b < 2 && s == LBIB_OK; ++b) {
+        s = dev_alloc(c, &c->f[b], 9 * nn);
+        if (s == LBIB_OK && c->S) s = dev_alloc(c, &c->g[b], 5 * (size_t)c->S * nn);
+    }
+    if (s == LBIB_OK) s = dev_alloc(c, &c->uband, 2 * nn);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->mask, nn);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_bin_count, (size_t)c->nbins);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_bin_off, (size_t)c->nbins + 1);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_err, 1);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_partial, c->partial_count * 5);
+    if (s == LBIB_OK && (launch_fill_f32(c, c->uband, 2 * c->nn) != hipSuccess ||
+                         launch_fill_u16(c, c->mask, c->nn) != hipSuccess ||
+                         launch_fill_i32(c, c->d_bin_count, c->nbins, 0) != hipSuccess ||
+                         launch_fill_i32(c, c->d_bin_off, c->nbins + 1, 0) != hipSuccess ||
+                         launch_fill_i32(c, c->d_err, 1, 0) != hipSuccess))
+        s = LBIB_EDEVICE;
+    if (s == LBIB_OK) s = init_fields(c, nullptr, nullptr, nullptr);
+    if (s != LBIB_OK) {
+        (void)hipStreamSynchronize(c->stream);
+        free_all(c);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return s;
+    }
+    *out = c;
+    return LBIB_OK;
+}
+
+void lbib_destroy(lbib_ctx* c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, const double* xy,
+                           const double* rest_len, const double* rest_area)
+{
+    if (!c) return LBIB_ESTATE;
+    std::string msg;
+    if (check_cells(&c->p, n_cells, off, xy, rest_len, rest_area, msg) != LBIB_OK) {
+        c->err = msg;
+        return LBIB_EINVAL;
+    }
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    free_nodes(c);
+    if (n_cells == 0) return LBIB_OK;
+    const size_t N = (size_t)off[n_cells], C = (size_t)n_cells;
+
+    // rest lengths / areas default to the initial ones
+    std::vector<double> l0(N), A0(C);
+    int max_n = 0;
+    for (size_t q = 0; q < C; ++q) {
+        const size_t a = (size_t)off[q], n = (size_t)off[q + 1] - a;
+        if ((int)n > max_n) max_n = (int)n;
+        double A = 0.0;
+        for (size_t k = 0; k < n; ++k) {
+            const size_t i = a + k, j = a + (k + 1) % n;
+            const double dx = xy[2 * j] - xy[2 * i], dy = xy[2 * j + 1] - xy[2 * i + 1];
+            l0[i] = rest_len ? rest_len[i] : std::sqrt(dx * dx + dy * dy);
+            A += (xy[2 * i] - xy[2 * a]) * (xy[2 * j + 1] - xy[2 * a + 1]) -
+                 (xy[2 * j] - xy[2 * a]) * (xy[2 * i + 1] - xy[2 * a + 1]);
+        }
+        A0[q] = rest_area ? rest_area[q] : 0.5 * A;
+    }
+    lbib_status s = LBIB_OK;
+    s = dev_alloc(c, &c->d_off, C + 1);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_X, N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_F, N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_l0, N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_A0, C);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_area, C);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_key, N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_rank, N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_rec, N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_rec_ij, N);
+    c->n_cells = n_cells;
+    c->n_nodes = (int64_t)N;
+    if (s != LBIB_OK) {
+        free_nodes(c);
+        return s;
+    }
+    c->max_cell_nodes = max_n;
+    c->mask_needed = any_source_decay(c->p);
+    LBIB_HIP(c, hipMemcpyAsync(c->d_off, off, (C + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    LBIB_HIP(c, hipMemcpyAsync(c->d_X, xy, N * sizeof(double2), hipMemcpyHostToDevice, c->stream));
+    LBIB_HIP(c, hipMemcpyAsync(c->d_l0, l0.data(), N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    LBIB_HIP(c, hipMemcpyAsync(c->d_A0, A0.data(), C * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    LBIB_LAUNCH(c, launch_fill_i32(c, c->d_bin_count, c->nbins, 0));
+    LBIB_LAUNCH(c, launch_fill_i32(c, c->d_err, 1, 0));
+    if (c->mask_needed) LBIB_LAUNCH(c, launch_fill_u16(c, c->mask, c->nn));
+    LBIB_TRY(membrane_refresh(c, 0));
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    return check_err_flag(c);
+}
+
+lbib_status lbib_set_fields(lbib_ctx* c, const double* rho, const double* u, const double* phi)
+{
+    if (!c) return LBIB_ESTATE;
+    const int64_t nn = c->nn;
+    for (int64_t i = 0; rho && i < nn; ++i)
+        if (!std::isfinite(rho[i]) || !(rho[i] > 0.0)) {
+            c->err = "rho must be finite and positive";
+            return LBIB_EINVAL;
+        }
+    for (int64_t i = 0; u && i < 2 * nn; ++i)
+        if (!std::isfinite(u[i])) {
+            c->err = "u must be finite";
+            return LBIB_EINVAL;
+        }
+    for (int64_t i = 0; phi && i < (int64_t)c->S * nn; ++i)
+        if (!std::isfinite(phi[i])) {
+            c->err = "phi must be finite";
+            return LBIB_EINVAL;
+        }
+    return init_fields(c, rho, u, phi);
+}
+
+lbib_status lbib_step(lbib_ctx* c, int32_t n)
+{
+    if (!c) return LBIB_ESTATE;
+    if (n < 0) {
+        c->err = "negative step count";
+        return LBIB_EINVAL;
+    }
+    const bool nodes = c->n_cells > 0;
+    for (int32_t k = 0; k < n; ++k) {
+        {
+            Timed tm(c, LBIB_K_LATTICE);
+            LBIB_LAUNCH(c, launch_lattice(c, lattice_args(c), nodes, c->mask_needed));
+        }
+        c->cur = 1 - c->cur;
+        if (nodes) LBIB_TRY(membrane_refresh(c, 1));
+        if (c->timing && c->pending.size() > 4096) LBIB_TRY(harvest(c));
+    }
+    return LBIB_OK;
+}
+
+lbib_status lbib_get_fields(lbib_ctx* c, double* rho, double* u, double* phi, double* xy, int32_t* cell_id_map)
+{
+    if (!c) return LBIB_ESTATE;
+    const size_t nn = (size_t)c->nn;
+    if (rho || u || (phi && c->S)) {
+        LBIB_TRY(ensure_stage(c, nn * (size_t)(3 + c->S)));
+        LBIB_LAUNCH(c, launch_moments(c, c->d_stage));
+        if (rho)
+            LBIB_HIP(c, hipMemcpyAsync(rho, c->d_stage, nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        if (u)
+            LBIB_HIP(c, hipMemcpyAsync(u, c->d_stage + nn, 2 * nn * sizeof(double), hipMemcpyDeviceToHost,
+                                       c->stream));
+        if (phi && c->S)
+            LBIB_HIP(c, hipMemcpyAsync(phi, c->d_stage + 3 * nn, (size_t)c->S * nn * sizeof(double),
+                                       hipMemcpyDeviceToHost, c->stream));
+    }
+    if (xy && c->n_nodes)
+        LBIB_HIP(c, hipMemcpyAsync(xy, c->d_X, (size_t)c->n_nodes * sizeof(double2), hipMemcpyDeviceToHost,
+                                   c->stream));
+    if (cell_id_map) {
+        if (!c->mask_needed) {
+            // the map is only maintained when a reaction reads it: build it now
+            LBIB_LAUNCH(c, launch_fill_u16(c, c->mask, c->nn));
+            if (c->n_cells) LBIB_LAUNCH(c, launch_raster(c, raster_args(c)));
+        }
+        std::vector<uint16_t> h(nn);
+        LBIB_HIP(c, hipMemcpyAsync(h.data(), c->mask, nn * sizeof(uint16_t), hipMemcpyDeviceToHost, c->stream));
+        LBIB_HIP(c, hipStreamSynchronize(c->stream));
+        for (size_t i = 0; i < nn; ++i) cell_id_map[i] = h[i];
+    }
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    return check_err_flag(c);
+}
+
+lbib_status lbib_get_forces(lbib_ctx* c, double* F, double* area)
+{
+    if (!c) return LBIB_ESTATE;
+    if (!c->n_cells) return LBIB_OK;
+    const size_t N = (size_t)c->n_nodes;
+    if (F) {
+        std::vector<float> h(2 * N);
+        LBIB_HIP(c, hipMemcpyAsync(h.data(), c->d_F, N * sizeof(float2), hipMemcpyDeviceToHost, c->stream));
+        LBIB_HIP(c, hipStreamSynchronize(c->stream));
+        for (size_t i = 0; i < 2 * N; ++i) F[i] = h[i];
+    }
+    if (area)
+        LBIB_HIP(c, hipMemcpyAsync(area, c->d_area, (size_t)c->n_cells * sizeof(double), hipMemcpyDeviceToHost,
+                                   c->stream));
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    return LBIB_OK;
+}
+
+lbib_status lbib_get_spread(lbib_ctx* c, double* e)
+{
+    if (!c) return LBIB_ESTATE;
+    if (!e) return LBIB_EINVAL;
+    const size_t nn = (size_t)c->nn;
+    LBIB_TRY(ensure_stage(c, 2 * nn));
+    LatticeArgs a = lattice_args(c);
+    a.e_out = c->d_stage;
+    if (!c->n_cells) a.bin_off = nullptr;
+    LBIB_LAUNCH(c, launch_spread_inspect(c, a));
+    LBIB_HIP(c, hipMemcpyAsync(e, c->d_stage, 2 * nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    return LBIB_OK;
+}
+
+lbib_status lbib_reduce(lbib_ctx* c, double* out)
+{
+    if (!c) return LBIB_ESTATE;
+    if (!out) return LBIB_EINVAL;
+    const int nv = 3 + c->S;
+    LBIB_TRY(ensure_stage(c, 8));
+    LBIB_LAUNCH(c, launch_reduce(c, c->d_stage));
+    LBIB_HIP(c, hipMemcpyAsync(out, c->d_stage, (size_t)nv * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    for (int v = 0; v < nv; ++v)
+        if (!std::isfinite(out[v])) {
+            c->err = "non-finite lattice sum";
+            return LBIB_ENUMERIC;
+        }
+    return LBIB_OK;
+}
+
+lbib_status lbib_sync(lbib_ctx* c)
+{
+    if (!c) return LBIB_ESTATE;
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    return LBIB_OK;
+}
+
+lbib_status lbib_set_timing(lbib_ctx* c, int32_t enable)
+{
+    if (!c) return LBIB_ESTATE;
+    LBIB_TRY(harvest(c));
+    c->timing = enable != 0;
+    for (int k = 0; k < LBIB_K_COUNT; ++k) {
+        c->t_ms[k] = 0.0;
+        c->t_count[k] = 0;
+    }
+    return LBIB_OK;
+}
+
+lbib_status lbib_get_timing(lbib_ctx* c, int32_t kernel, double* total_ms, int64_t* launches)
+{
+    if (!c) return LBIB_ESTATE;
+    if (kernel < 0 || kernel >= LBIB_K_COUNT) return LBIB_EINVAL;
+    LBIB_TRY(harvest(c));
+    if (total_ms) *total_ms = c->t_ms[kernel];
+    if (launches) *launches = c->t_count[kernel];
+    return LBIB_OK;
+}
+
+lbib_status lbib_device_bytes(const lbib_ctx* c, size_t* bytes)
+{
+    if (!c || !bytes) return LBIB_ESTATE;
+    *bytes = c->device_bytes;
+    return LBIB_OK;
+}
+
+}  // extern "C"

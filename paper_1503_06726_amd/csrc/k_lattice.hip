@@ -1,0 +1,537 @@
+// Lattice kernels of the coupled step (gfx950).
+//
+// k_lattice: one fused pass per time step over the whole lattice, one 64x4 tile per
+// workgroup.  Per tile:
+//   1. spread the membrane forces of the nodes whose 4x4 stencil reaches the tile
+//      (Eq. forcedistribution with the kernel of Eq. 1Dkernel), summed in LDS in 64-bit
+//      fixed point so the result does not depend on node order;
+//   2. per lattice node: pull the D2Q9 populations (streaming of Eq. bgkequation, halfway
+//      bounce-back at walls), take rho and u = sum f v / rho, collide with the BGK operator
+//      and the body-force term w_i rho (v_i . e) / cs2, store;
+//   3. per species: pull the D2Q5 populations, take phi, add the reaction, collide towards
+//      phi w_i (1 + v_i . u / cs2) with the fluid's u, store;
+//   4. write u where a node stencil reaches (read by the membrane kernel's interpolation),
+//      read the domain ID and clear it for the next rasterisation.
+// The pass reads every population once and writes it once: it is HBM-bandwidth bound.
+#include "lbib_internal.h"
+
+namespace lbib {
+
+// D2Q9 weights (Suppl. "Lattice Boltzmann Method": 4/9, 1/9 x4, 1/36 x4)
+#define W0 (4.0f / 9.0f)
+#define W1 (1.0f / 9.0f)
+#define W5 (1.0f / 36.0f)
+// D2Q5 weights: 1/3, 1/6 x4
+#define Q0 (1.0f / 3.0f)
+#define Q1 (1.0f / 6.0f)
+
+struct Nbr {
+    int64_t rc, rm, rp;   // row offsets of y, y-1, y+1 (clamped at walls)
+    int xm, xp;
+    bool bot, top;        // y-1 (y+1) lies beyond a wall
+};
+
+__device__ inline Nbr neighbours(int x, int y, int nx, int ny, int walls)
+{
+    Nbr n;
+    n.xm = (x == 0) ? nx - 1 : x - 1;
+    n.xp = (x == nx - 1) ? 0 : x + 1;
+    int ym, yp;
+    if (walls) {
+        n.bot = (y == 0);
+        n.top = (y == ny - 1);
+        ym = n.bot ? y : y - 1;
+        yp = n.top ? y : y + 1;
+    } else {
+        n.bot = n.top = false;
+        ym = (y == 0) ? ny - 1 : y - 1;
+        yp = (y == ny - 1) ? 0 : y + 1;
+    }
+    n.rc = (int64_t)y * nx;
+    n.rm = (int64_t)ym * nx;
+    n.rp = (int64_t)yp * nx;
+    return n;
+}
+
+// f_i(x) = s_i(x - v_i); across a wall the population returns reversed: s_opp(i)(x).
+// Velocities: 0 rest, 1 (1,0), 2 (0,1), 3 (-1,0), 4 (0,-1), 5 (1,1), 6 (-1,1), 7 (-1,-1), 8 (1,-1).
+__device__ inline void pull9(const float* __restrict__ s, int64_t nn, int x, const Nbr& n, float f[9])
+{
+    const float* p2 = n.bot ? s + 4 * nn + n.rc + x : s + 2 * nn + n.rm + x;
+    const float* p4 = n.top ? s + 2 * nn + n.rc + x : s + 4 * nn + n.rp + x;
+    const float* p5 = n.bot ? s + 7 * nn + n.rc + x : s + 5 * nn + n.rm + n.xm;
+    const float* p6 = n.bot ? s + 8 * nn + n.rc + x : s + 6 * nn + n.rm + n.xp;
+    const float* p7 = n.top ? s + 5 * nn + n.rc + x : s + 7 * nn + n.rp + n.xp;
+    const float* p8 = n.top ? s + 6 * nn + n.rc + x : s + 8 * nn + n.rp + n.xm;
+    f[0] = s[n.rc + x];
+    f[1] = s[nn + n.rc + n.xm];
+    f[2] = *p2;
+    f[3] = s[3 * nn + n.rc + n.xp];
+    f[4] = *p4;
+    f[5] = *p5;
+    f[6] = *p6;
+    f[7] = *p7;
+    f[8] = *p8;
+}
+
+__device__ inline void pull5(const float* __restrict__ s, int64_t nn, int x, const Nbr& n, float g[5])
+{
+    const float* p2 = n.bot ? s + 4 * nn + n.rc + x : s + 2 * nn + n.rm + x;
+    const float* p4 = n.top ? s + 2 * nn + n.rc + x : s + 4 * nn + n.rp + x;
+    g[0] = s[n.rc + x];
+    g[1] = s[nn + n.rc + n.xm];
+    g[2] = *p2;
+    g[3] = s[3 * nn + n.rc + n.xp];
+    g[4] = *p4;
+}
+
+__device__ inline unsigned long long to_fixed(float v)
+{
+    v = fminf(fmaxf(v, -FIX_CLAMP), FIX_CLAMP);
+    return (unsigned long long)__float2ll_rn(v * FIX_SCALE);
+}
+
+// Spread the binned node forces into this tile's LDS accumulators.
+__device__ inline void spread_tile(const LatticeArgs& a, int tcol, int trow, int x0, int y0,
+                                   unsigned long long* accx, unsigned long long* accy, int* tch)
+{
+    const int t = threadIdx.x;
+    // bin columns whose origins reach the tile: origins in [x0-3, x0+TILE_X-1] (wrapped)
+    int cols[4], ncol = 0;
+    {
+        int xs = x0 - 3;
+        if (xs < 0) xs += a.nx;
+        int cc = xs / TILE_X;
+        for (;;) {
+            cols[ncol++] = cc;
+            if (cc == tcol || ncol == 4) break;
+            cc = (cc + 1 == a.ntx) ? 0 : cc + 1;
+        }
+    }
+    int rows[4], nrow = 0;
+    {
+        int ys = y0 - 3;
+        if (a.walls) {
+            if (ys < 0) ys = 0;
+        } else if (ys < 0) {
+            ys += a.ny;
+        }
+        int rr = ys / TILE_Y;
+        for (;;) {
+            rows[nrow++] = rr;
+            if (rr == trow || nrow == 4) break;
+            rr = (rr + 1 == a.nty) ? 0 : rr + 1;
+        }
+    }
+    for (int ir = 0; ir < nrow; ++ir) {
+        for (int ic = 0; ic < ncol; ++ic) {
+            const int b = rows[ir] * a.ntx + cols[ic];
+            const int beg = a.bin_off[b], end = a.bin_off[b + 1];
+            for (int k = beg + t; k < end; k += TILE_N) {
+                const float4 r = a.rec[k];
+                const int ij = a.rec_ij[k];
+                const int i0 = ij & 0xFFFF;
+                const int j0 = ij >> 16;              // sign-extended 16-bit row
+                float wx[4], wy[4];
+                delta_weights(a.kernel, r.x, wx);
+                delta_weights(a.kernel, r.y, wy);
+#pragma unroll
+                for (int bb = 0; bb < 4; ++bb) {
+                    int j = j0 + bb;
+                    if (a.walls) {
+                        if (j < 0 || j >= a.ny) continue;
+                    } else if (j >= a.ny) {
+                        j -= a.ny;
+                    }
+                    const int ly = j - y0;
+                    if ((unsigned)ly >= (unsigned)TILE_Y) continue;
+#pragma unroll
+                    for (int aa = 0; aa < 4; ++aa) {
+                        int i = i0 + aa;
+                        if (i >= a.nx) i -= a.nx;
+                        const int lx = i - x0;
+                        if ((unsigned)lx >= (unsigned)TILE_X) continue;
+                        const float w = wx[aa] * wy[bb];
+                        const int o = ly * TILE_X + lx;
+                        atomicAdd(&accx[o], to_fixed(w * r.z));
+                        atomicAdd(&accy[o], to_fixed(w * r.w));
+                        tch[o] = 1;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int S, bool NODES, bool MASK>
+__global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
+{
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int tcol = tile % a.ntx, trow = tile / a.ntx;
+    const int x0 = tcol * TILE_X, y0 = trow * TILE_Y;
+    const int t = threadIdx.x;
+    const int x = x0 + (t % TILE_X), y = y0 + (t / TILE_X);
+
+    float ex = a.bodyx, ey = a.bodyy;
+    bool touched = false;
+    if constexpr (NODES) {
+        __shared__ unsigned long long accx[TILE_N], accy[TILE_N];
+        __shared__ int tch[TILE_N];
+        accx[t] = 0ull;
+        accy[t] = 0ull;
+        tch[t] = 0;
+        if (t == 0) a.bin_count[tile] = 0;     // counts of the next binning
+        __syncthreads();
+        spread_tile(a, tcol, trow, x0, y0, accx, accy, tch);
+        __syncthreads();
+        ex += __ll2float_rn((long long)accx[t]) * FIX_INV;
+        ey += __ll2float_rn((long long)accy[t]) * FIX_INV;
+        touched = tch[t] != 0;
+    }
+    if (x >= a.nx || y >= a.ny) return;
+
+    const Nbr n = neighbours(x, y, a.nx, a.ny, a.walls);
+    const int64_t nn = a.nn;
+    const int64_t o = n.rc + x;
+
+    float f[9];
+    pull9(a.fsrc, nn, x, n, f);
+    const float drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    const float rho = a.rho0 + drho;
+    const float jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const float jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    const float inv = 1.0f / rho;
+    const float ux = jx * inv, uy = jy * inv;
+    const float usq = 1.5f * (ux * ux + uy * uy);
+    const float om = a.omega, om1 = 1.0f - a.omega;
+    // force term 3 w_i rho (v_i . e)
+    const float fx = 3.0f * rho * ex, fy = 3.0f * rho * ey;
+    {
+        // equilibrium deviation w_i (drho + rho (3 vu + 4.5 vu^2 - 1.5 u^2))
+        float* __restrict__ d = a.fdst + o;
+        d[0] = om1 * f[0] + om * W0 * (drho - rho * usq);
+        float vu, eq;
+        vu = ux;       eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[nn]     = om1 * f[1] + om * eq + W1 * fx;
+        vu = uy;       eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[2 * nn] = om1 * f[2] + om * eq + W1 * fy;
+        vu = -ux;      eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[3 * nn] = om1 * f[3] + om * eq - W1 * fx;
+        vu = -uy;      eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[4 * nn] = om1 * f[4] + om * eq - W1 * fy;
+        vu = ux + uy;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[5 * nn] = om1 * f[5] + om * eq + W5 * (fx + fy);
+        vu = uy - ux;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[6 * nn] = om1 * f[6] + om * eq + W5 * (fy - fx);
+        vu = -ux - uy; eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[7 * nn] = om1 * f[7] + om * eq - W5 * (fx + fy);
+        vu = ux - uy;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[8 * nn] = om1 * f[8] + om * eq + W5 * (fx - fy);
+    }
+
+    if constexpr (S > 0) {
+        int m = 0;
+        if constexpr (MASK) {
+            m = a.mask[o];
+            a.mask[o] = 0;
+        }
+        float g[S][5], dphi[S], phi[S], R[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            pull5(a.gsrc + (int64_t)5 * s * nn, nn, x, n, g[s]);
+            dphi[s] = ((g[s][0] + g[s][1]) + (g[s][2] + g[s][3])) + g[s][4];
+            phi[s] = a.phi_ref[s] + dphi[s];
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const float* c = a.rc[s];
+            if (a.react[s] == 1) {
+                R[s] = (m != 0 ? c[0] : 0.0f) - c[1] * phi[s];
+            } else if (a.react[s] == 2 && S == 2) {
+                const float u2v = phi[0] * phi[0] * phi[S - 1];
+                R[s] = (s == 0) ? c[2] * (c[0] - phi[0] + u2v) : c[2] * (c[1] - u2v);
+            } else {
+                R[s] = 0.0f;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const float os = a.omega_s[s], os1 = 1.0f - a.omega_s[s];
+            const float p3 = 3.0f * phi[s];
+            float* __restrict__ d = a.gdst + (int64_t)5 * s * nn + o;
+            // equilibrium deviation w_i (dphi + 3 phi v_i . u) and reaction w_i R
+            d[0]      = os1 * g[s][0] + os * Q0 * dphi[s] + Q0 * R[s];
+            d[nn]     = os1 * g[s][1] + os * Q1 * (dphi[s] + p3 * ux) + Q1 * R[s];
+            d[2 * nn] = os1 * g[s][2] + os * Q1 * (dphi[s] + p3 * uy) + Q1 * R[s];
+            d[3 * nn] = os1 * g[s][3] + os * Q1 * (dphi[s] - p3 * ux) + Q1 * R[s];
+            d[4 * nn] = os1 * g[s][4] + os * Q1 * (dphi[s] - p3 * uy) + Q1 * R[s];
+        }
+    } else if constexpr (MASK) {
+        a.mask[o] = 0;
+    }
+
+    if constexpr (NODES) {
+        if (touched) {
+            a.uband[o] = ux;
+            a.uband[nn + o] = uy;
+        }
+    }
+}
+
+// The spread force field alone (inspection): same tiling and summation as k_lattice.
+__global__ __launch_bounds__(TILE_N) void k_spread_inspect(LatticeArgs a)
+{
+    const int tile = blockIdx.x;
+    const int tcol = tile % a.ntx, trow = tile / a.ntx;
+    const int x0 = tcol * TILE_X, y0 = trow * TILE_Y;
+    const int t = threadIdx.x;
+    const int x = x0 + (t % TILE_X), y = y0 + (t / TILE_X);
+    __shared__ unsigned long long accx[TILE_N], accy[TILE_N];
+    __shared__ int tch[TILE_N];
+    accx[t] = 0ull;
+    accy[t] = 0ull;
+    tch[t] = 0;
+    __syncthreads();
+    if (a.bin_off) spread_tile(a, tcol, trow, x0, y0, accx, accy, tch);
+    __syncthreads();
+    if (x >= a.nx || y >= a.ny) return;
+    const int64_t o = (int64_t)y * a.nx + x;
+    a.e_out[o] = (double)(__ll2float_rn((long long)accx[t]) * FIX_INV + a.bodyx);
+    a.e_out[a.nn + o] = (double)(__ll2float_rn((long long)accy[t]) * FIX_INV + a.bodyy);
+}
+
+// Equilibrium initial state, written in the stored (pre-streaming) layout so that the next
+// pull yields f_i(x) = f_i^eq(rho(x), u(x)): s_i(x - v_i) = f_i^eq(x), or across a wall
+// s_opp(i)(x) = f_i^eq(x).
+struct InitArgs {
+    float* f;
+    float* g;
+    const double* rho;
+    const double* u;
+    const double* phi;
+    int64_t nn;
+    int nx, ny, walls, S;
+    double rho0;
+    double phi_ref[2];
+};
+
+__global__ void k_init(InitArgs a)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.nn) return;
+    const int x = (int)(idx % a.nx), y = (int)(idx / a.nx);
+    const int vx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int vy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    const int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    const double w9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    const double w5[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+    const double rho = a.rho ? a.rho[idx] : a.rho0;
+    const double ux = a.u ? a.u[idx] : 0.0, uy = a.u ? a.u[a.nn + idx] : 0.0;
+    const double drho = rho - a.rho0;
+    const double usq = 1.5 * (ux * ux + uy * uy);
+    for (int i = 0; i < 9; ++i) {
+        const double vu = vx[i] * ux + vy[i] * uy;
+        const float val = (float)(w9[i] * (drho + rho * (3.0 * vu + 4.5 * vu * vu - usq)));
+        const int sy = y - vy[i];
+        if (a.walls && (sy < 0 || sy >= a.ny)) {
+            a.f[(int64_t)opp[i] * a.nn + idx] = val;
+        } else {
+            const int sx = (x - vx[i] + a.nx) % a.nx;
+            const int syy = (sy + a.ny) % a.ny;
+            a.f[(int64_t)i * a.nn + (int64_t)syy * a.nx + sx] = val;
+        }
+    }
+    for (int s = 0; s < a.S; ++s) {
+        const double phi = a.phi ? a.phi[(int64_t)s * a.nn + idx] : 0.0;
+        const double dphi = phi - a.phi_ref[s];
+        float* gs = a.g + (int64_t)5 * s * a.nn;
+        for (int i = 0; i < 5; ++i) {
+            const double vu = vx[i] * ux + vy[i] * uy;
+            const float val = (float)(w5[i] * (dphi + 3.0 * phi * vu));
+            const int sy = y - vy[i];
+            if (a.walls && (sy < 0 || sy >= a.ny)) {
+                gs[(int64_t)opp[i] * a.nn + idx] = val;
+            } else {
+                const int sx = (x - vx[i] + a.nx) % a.nx;
+                const int syy = (sy + a.ny) % a.ny;
+                gs[(int64_t)i * a.nn + (int64_t)syy * a.nx + sx] = val;
+            }
+        }
+    }
+}
+
+// Moments of the current state in FP64: planes rho, ux, uy, phi_0 .. phi_{S-1}.
+struct MomentArgs {
+    const float* f;
+    const float* g;
+    double* out;
+    int64_t nn;
+    int nx, ny, walls, S;
+    double rho0;
+    double phi_ref[2];
+};
+
+__device__ inline void node_moments(const MomentArgs& a, int x, int y, double& drho, double& jx,
+                                    double& jy, double dphi[2])
+{
+    const Nbr n = neighbours(x, y, a.nx, a.ny, a.walls);
+    float f[9];
+    pull9(a.f, a.nn, x, n, f);
+    drho = 0.0;
+    for (int i = 0; i < 9; ++i) drho += (double)f[i];
+    jx = ((double)f[1] - f[3]) + ((double)f[5] - f[6]) + ((double)f[8] - f[7]);
+    jy = ((double)f[2] - f[4]) + ((double)f[5] + f[6]) - ((double)f[7] + f[8]);
+    for (int s = 0; s < a.S; ++s) {
+        float g[5];
+        pull5(a.g + (int64_t)5 * s * a.nn, a.nn, x, n, g);
+        double t = 0.0;
+        for (int i = 0; i < 5; ++i) t += (double)g[i];
+        dphi[s] = t;
+    }
+}
+
+__global__ void k_moments(MomentArgs a)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.nn) return;
+    const int x = (int)(idx % a.nx), y = (int)(idx / a.nx);
+    double drho, jx, jy, dphi[2] = {0.0, 0.0};
+    node_moments(a, x, y, drho, jx, jy, dphi);
+    const double rho = a.rho0 + drho;
+    a.out[idx] = rho;
+    a.out[a.nn + idx] = jx / rho;
+    a.out[2 * a.nn + idx] = jy / rho;
+    for (int s = 0; s < a.S; ++s) a.out[(3 + s) * a.nn + idx] = a.phi_ref[s] + dphi[s];
+}
+
+// Deterministic FP64 sums: fixed node-to-thread assignment, fixed LDS tree, then one block
+// adds the per-block partials in order.
+constexpr int RED_THREADS = 256;
+constexpr int RED_MAXV = 5;
+
+__global__ __launch_bounds__(RED_THREADS) void k_reduce_partial(MomentArgs a, double* partial)
+{
+    __shared__ double sh[RED_MAXV][RED_THREADS];
+    const int nv = 3 + a.S;
+    double acc[RED_MAXV] = {0, 0, 0, 0, 0};
+    const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
+    for (int64_t idx = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; idx < a.nn; idx += stride) {
+        const int x = (int)(idx % a.nx), y = (int)(idx / a.nx);
+        double drho, jx, jy, dphi[2] = {0.0, 0.0};
+        node_moments(a, x, y, drho, jx, jy, dphi);
+        acc[0] += drho;
+        acc[1] += jx;
+        acc[2] += jy;
+        for (int s = 0; s < a.S; ++s) acc[3 + s] += dphi[s];
+    }
+    for (int v = 0; v < nv; ++v) sh[v][threadIdx.x] = acc[v];
+    __syncthreads();
+    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int v = 0; v < nv; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int v = 0; v < nv; ++v) partial[(int64_t)blockIdx.x * RED_MAXV + v] = sh[v][0];
+}
+
+__global__ void k_reduce_final(const double* partial, int nblocks, int nv, double rho_total,
+                               double phi_tot0, double phi_tot1, double* out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double acc[RED_MAXV] = {0, 0, 0, 0, 0};
+    for (int b = 0; b < nblocks; ++b)
+        for (int v = 0; v < nv; ++v) acc[v] += partial[(int64_t)b * RED_MAXV + v];
+    out[0] = rho_total + acc[0];
+    out[1] = acc[1];
+    out[2] = acc[2];
+    if (nv > 3) out[3] = phi_tot0 + acc[3];
+    if (nv > 4) out[4] = phi_tot1 + acc[4];
+}
+
+// ---------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------
+template <int S>
+static hipError_t launch_lattice_s(lbib_ctx* c, const LatticeArgs& a, bool nodes, bool mask)
+{
+    dim3 grid((unsigned)c->nbins), block(TILE_N);
+    if (nodes && mask) hipLaunchKernelGGL((k_lattice<S, true, true>), grid, block, 0, c->stream, a);
+    else if (nodes) hipLaunchKernelGGL((k_lattice<S, true, false>), grid, block, 0, c->stream, a);
+    else if (mask) hipLaunchKernelGGL((k_lattice<S, false, true>), grid, block, 0, c->stream, a);
+    else hipLaunchKernelGGL((k_lattice<S, false, false>), grid, block, 0, c->stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lattice(lbib_ctx* c, const LatticeArgs& a, bool nodes, bool mask)
+{
+    switch (c->S) {
+    case 0: return launch_lattice_s<0>(c, a, nodes, mask);
+    case 1: return launch_lattice_s<1>(c, a, nodes, mask);
+    default: return launch_lattice_s<2>(c, a, nodes, mask);
+    }
+}
+
+hipError_t launch_spread_inspect(lbib_ctx* c, const LatticeArgs& a)
+{
+    hipLaunchKernelGGL(k_spread_inspect, dim3((unsigned)c->nbins), dim3(TILE_N), 0, c->stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(lbib_ctx* c, const double* rho, const double* u, const double* phi, int has_rho,
+                       int has_u, int has_phi)
+{
+    InitArgs a;
+    a.f = c->f[c->cur];
+    a.g = c->g[c->cur];
+    a.rho = has_rho ? rho : nullptr;
+    a.u = has_u ? u : nullptr;
+    a.phi = has_phi ? phi : nullptr;
+    a.nn = c->nn;
+    a.nx = c->p.nx;
+    a.ny = c->p.ny;
+    a.walls = c->p.bc_y == LBIB_WALLS;
+    a.S = c->S;
+    a.rho0 = c->p.rho0;
+    a.phi_ref[0] = c->p.species[0].phi_ref;
+    a.phi_ref[1] = c->p.species[1].phi_ref;
+    const unsigned nb = (unsigned)((c->nn + 255) / 256);
+    hipLaunchKernelGGL(k_init, dim3(nb), dim3(256), 0, c->stream, a);
+    return hipGetLastError();
+}
+
+static MomentArgs moment_args(lbib_ctx* c, double* out)
+{
+    MomentArgs a;
+    a.f = c->f[c->cur];
+    a.g = c->g[c->cur];
+    a.out = out;
+    a.nn = c->nn;
+    a.nx = c->p.nx;
+    a.ny = c->p.ny;
+    a.walls = c->p.bc_y == LBIB_WALLS;
+    a.S = c->S;
+    a.rho0 = c->p.rho0;
+    a.phi_ref[0] = c->p.species[0].phi_ref;
+    a.phi_ref[1] = c->p.species[1].phi_ref;
+    return a;
+}
+
+hipError_t launch_moments(lbib_ctx* c, double* out)
+{
+    MomentArgs a = moment_args(c, out);
+    const unsigned nb = (unsigned)((c->nn + 255) / 256);
+    hipLaunchKernelGGL(k_moments, dim3(nb), dim3(256), 0, c->stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(lbib_ctx* c, double* out_dev)
+{
+    MomentArgs a = moment_args(c, nullptr);
+    int nblocks = (int)((c->nn + RED_THREADS * 16 - 1) / (RED_THREADS * 16));
+    if (nblocks > (int)c->partial_count) nblocks = (int)c->partial_count;
+    if (nblocks < 1) nblocks = 1;
+    hipLaunchKernelGGL(k_reduce_partial, dim3(nblocks), dim3(RED_THREADS), 0, c->stream, a, c->d_partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const double rho_total = c->p.rho0 * (double)c->nn;
+    const double p0 = c->p.species[0].phi_ref * (double)c->nn;
+    const double p1 = c->p.species[1].phi_ref * (double)c->nn;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, c->stream, (const double*)c->d_partial, nblocks,
+                       3 + c->S, rho_total, p0, p1, out_dev);
+    return hipGetLastError();
+}
+
+}  // namespace lbib

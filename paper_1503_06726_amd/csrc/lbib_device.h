@@ -1,0 +1,148 @@
+// Device-side definitions shared by the lbib HIP kernels (gfx950).
+//
+// Storage: every population is kept as an FP32 deviation from its rest value,
+// df_i = f_i - w_i rho0 and dg_i = g_i - w_i phi_ref, in structure-of-arrays planes
+// [q][ny][nx] (x fastest).  The arrays hold post-collision, pre-streaming values; a
+// lattice pass pulls f_i(x) = f*_i(x - v_i) (or, across a wall, f*_opp(i)(x)), collides,
+// and stores f*_i(x) in place of x in the other buffer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbib {
+
+// lattice tile of one workgroup: 64 x 4 nodes, one 64-wide wavefront per row
+constexpr int TILE_X = 64;
+constexpr int TILE_Y = 4;
+constexpr int TILE_N = TILE_X * TILE_Y;
+
+constexpr int MEMBRANE_THREADS = 256;
+constexpr int MAX_CELL_NODES = 4096;            // LDS holds one cell's positions as double2
+constexpr int RASTER_THREADS = 256;
+constexpr int RASTER_LDS_WORDS = 8192;          // 32 KB bitmap per raster pass
+constexpr int SCAN_THREADS = 1024;
+
+// Spread forces are summed in 64-bit fixed point (integer addition is associative, so the
+// sum does not depend on the order the nodes arrive in): value = integer * 2^-48.
+constexpr float FIX_SCALE = 281474976710656.0f;          // 2^48
+constexpr float FIX_INV = 1.0f / 281474976710656.0f;     // 2^-48 (exact)
+constexpr float FIX_CLAMP = 16384.0f;                    // |contribution| bound, keeps sums in range
+
+struct LatticeArgs {
+    const float* __restrict__ fsrc;   // 9 planes
+    float* __restrict__ fdst;
+    const float* __restrict__ gsrc;   // 5 * S planes
+    float* __restrict__ gdst;
+    int64_t nn;                       // nx * ny (plane stride)
+    int nx, ny, walls, ntx, nty;
+    float omega, rho0;
+    float omega_s[2], phi_ref[2];
+    int react[2];
+    float rc[2][4];
+    float bodyx, bodyy;
+    int kernel;
+    // immersed boundary: node records binned by lattice tile of their stencil origin
+    const int* __restrict__ bin_off;   // [nbins + 1]
+    const float4* __restrict__ rec;    // (sx, sy, Fx, Fy) per binned node
+    const int* __restrict__ rec_ij;    // packed stencil origin (i0 | j0 << 16)
+    int* __restrict__ bin_count;       // zeroed by the tile that owns the bin
+    float* __restrict__ uband;         // [2][ny][nx], written where a node stencil reaches
+    uint16_t* __restrict__ mask;       // domain IDs; read, then cleared for the next raster
+    // inspection output (spread field only)
+    double* __restrict__ e_out;
+};
+
+struct MembraneArgs {
+    const int* __restrict__ off;
+    double2* __restrict__ X;
+    float2* __restrict__ F;
+    const double* __restrict__ l0;
+    const double* __restrict__ A0;
+    double* __restrict__ area;
+    const float* __restrict__ uband;
+    int64_t nn;
+    int nx, ny, walls, kernel, ntx, nty;
+    double k_spring, phi_m, kappa;
+    int* __restrict__ key;
+    int* __restrict__ rank;
+    int* __restrict__ bin_count;
+    int* __restrict__ err;
+    int advect;
+};
+
+struct ScatterArgs {
+    const double2* __restrict__ X;
+    const float2* __restrict__ F;
+    const int* __restrict__ key;
+    const int* __restrict__ rank;
+    const int* __restrict__ bin_off;
+    float4* __restrict__ rec;
+    int* __restrict__ rec_ij;
+    int64_t n;
+    int nx, ny, walls;
+};
+
+struct RasterArgs {
+    const int* __restrict__ off;
+    const double2* __restrict__ X;
+    uint16_t* __restrict__ mask;
+    int nx, ny, walls;
+};
+
+// ---------------------------------------------------------------------------------------
+// 1-D kernel weights for the four stencil points i0 .. i0+3 of a node whose fractional
+// offset is s = X - floor(X) in [0, 1), i0 = floor(X) - 1, i.e. at distances
+// r = s+1, s, s-1, s-2.
+// Cosine kernel (Eq. 1Dkernel): with c = cos(pi s/2), n = sin(pi s/2) the four values are
+// (1-n)/4, (1+c)/4, (1+n)/4, (1-c)/4.
+// Peskin's 4-point kernel: with q = sqrt(1 + 4s - 4s^2) they are
+// (3-2s-q)/8, (3-2s+q)/8, (1+2s+q)/8, (1+2s-q)/8.
+// ---------------------------------------------------------------------------------------
+__device__ inline void delta_weights(int kernel, float s, float w[4])
+{
+    if (kernel == 0) {
+        float sn, cs;
+        sincospif(0.5f * s, &sn, &cs);
+        w[0] = 0.25f * (1.0f - sn);
+        w[1] = 0.25f * (1.0f + cs);
+        w[2] = 0.25f * (1.0f + sn);
+        w[3] = 0.25f * (1.0f - cs);
+    } else {
+        float q = sqrtf(1.0f + 4.0f * s - 4.0f * s * s);
+        w[0] = 0.125f * (3.0f - 2.0f * s - q);
+        w[1] = 0.125f * (3.0f - 2.0f * s + q);
+        w[2] = 0.125f * (1.0f + 2.0f * s + q);
+        w[3] = 0.125f * (1.0f + 2.0f * s - q);
+    }
+}
+
+__device__ inline int wrap_ll(long long i, int n)
+{
+    long long r = i % n;
+    return (int)(r < 0 ? r + n : r);
+}
+
+// tile (bin) key of a node's stencil origin; positions are unwrapped in x (and periodic y)
+__device__ inline int bin_key(double x, double y, int nx, int ny, int walls, int ntx)
+{
+    int i0 = wrap_ll((long long)floor(x) - 1, nx);
+    long long j = (long long)floor(y) - 1;
+    int j0;
+    if (walls) j0 = (int)(j < 0 ? 0 : (j >= ny ? ny - 1 : j));
+    else j0 = wrap_ll(j, ny);
+    return (j0 / TILE_Y) * ntx + i0 / TILE_X;
+}
+
+// XCD-aware workgroup order: the dispatcher deals workgroups round-robin over the 8 XCDs;
+// remap so each XCD walks a contiguous run of tiles (neighbouring tiles share cache lines
+// at their x edges, and each XCD has its own L2).
+__device__ inline int xcd_remap(int bid, int nblocks)
+{
+    const int NX = 8;
+    int xcd = bid % NX, local = bid / NX;
+    int q = nblocks / NX, r = nblocks % NX;
+    return (xcd < r) ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
+}  // namespace lbib

@@ -1,0 +1,97 @@
+// Host-side context and kernel launch wrappers of the lbib library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/lbib.h"
+#include "lbib_device.h"
+
+namespace lbib {
+
+// validation (pure C++, no HIP calls; validate.cpp)
+lbib_status check_params(const lbib_params* p, std::string& msg);
+lbib_status check_cells(const lbib_params* p, int32_t n_cells, const int32_t* offsets, const double* xy,
+                        const double* rest_len, const double* rest_area, std::string& msg);
+
+struct TimedLaunch {
+    int kernel;
+    hipEvent_t start, stop;
+};
+
+}  // namespace lbib
+
+struct lbib_ctx {
+    lbib_params p{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+
+    int64_t nn = 0;          // nx * ny
+    int S = 0;               // species
+    int ntx = 0, nty = 0, nbins = 0;
+    bool mask_needed = false;
+
+    // lattice state: post-collision deviations, A/B buffers
+    float* f[2] = {nullptr, nullptr};
+    float* g[2] = {nullptr, nullptr};
+    int cur = 0;
+    float* uband = nullptr;          // [2][ny][nx]
+    uint16_t* mask = nullptr;        // [ny][nx]
+
+    // membranes
+    int32_t n_cells = 0;
+    int64_t n_nodes = 0;
+    int max_cell_nodes = 0;
+    int* d_off = nullptr;
+    double2* d_X = nullptr;
+    float2* d_F = nullptr;
+    double* d_l0 = nullptr;
+    double* d_A0 = nullptr;
+    double* d_area = nullptr;
+    int* d_key = nullptr;
+    int* d_rank = nullptr;
+    float4* d_rec = nullptr;
+    int* d_rec_ij = nullptr;
+    int* d_bin_count = nullptr;      // [nbins]
+    int* d_bin_off = nullptr;        // [nbins + 1]
+    int* d_err = nullptr;            // device error flags
+
+    // staging
+    double* d_stage = nullptr;
+    size_t stage_bytes = 0;
+    double* d_partial = nullptr;     // reduction partials
+    size_t partial_count = 0;
+
+    size_t device_bytes = 0;
+
+    // timing
+    bool timing = false;
+    std::vector<lbib::TimedLaunch> pending;
+    std::vector<hipEvent_t> free_events;
+    double t_ms[LBIB_K_COUNT] = {0, 0, 0, 0, 0};
+    int64_t t_count[LBIB_K_COUNT] = {0, 0, 0, 0, 0};
+};
+
+namespace lbib {
+
+// kernel launchers (return the launch error)
+hipError_t launch_lattice(lbib_ctx* c, const LatticeArgs& a, bool nodes, bool mask);
+hipError_t launch_spread_inspect(lbib_ctx* c, const LatticeArgs& a);
+hipError_t launch_init(lbib_ctx* c, const double* stage_rho, const double* stage_u, const double* stage_phi,
+                       int has_rho, int has_u, int has_phi);
+hipError_t launch_moments(lbib_ctx* c, double* out);
+hipError_t launch_reduce(lbib_ctx* c, double* out_dev);
+hipError_t launch_membrane(lbib_ctx* c, const MembraneArgs& a);
+hipError_t launch_scan(lbib_ctx* c);
+hipError_t launch_scatter(lbib_ctx* c, const ScatterArgs& a);
+hipError_t launch_raster(lbib_ctx* c, const RasterArgs& a);
+hipError_t launch_fill_i32(lbib_ctx* c, int* p, int64_t n, int v);
+hipError_t launch_fill_u16(lbib_ctx* c, uint16_t* p, int64_t n);
+hipError_t launch_fill_f32(lbib_ctx* c, float* p, int64_t n);
+
+}  // namespace lbib

@@ -1,0 +1,269 @@
+"""Thin ctypes binding of ``liblbib.so`` (C ABI in ``include/lbib.h``).
+
+Argument marshalling only: every step of the coupled update runs in the library's HIP
+kernels.  There is no fallback: if the library is not built, or no GPU is usable, the
+calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbib.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5
+PERIODIC, WALLS = 0, 1
+DELTA_COS4, DELTA_PESKIN4 = 0, 1
+REACT_NONE, REACT_SOURCE_DECAY, REACT_SCHNAKENBERG = 0, 1, 2
+K_LATTICE, K_MEMBRANE, K_BIN_SCAN, K_BIN_SCATTER, K_RASTER = range(5)
+KERNEL_NAMES = ["lattice", "membrane", "bin_scan", "bin_scatter", "raster"]
+
+# every entry point declared in include/lbib.h
+EXPORTS = ["lbib_validate_params", "lbib_validate_cells", "lbib_create", "lbib_set_cells",
+           "lbib_set_fields", "lbib_step", "lbib_get_fields", "lbib_get_forces", "lbib_get_spread",
+           "lbib_reduce", "lbib_sync", "lbib_set_timing", "lbib_get_timing", "lbib_device_bytes",
+           "lbib_last_error", "lbib_status_string", "lbib_version", "lbib_destroy"]
+
+
+class Species(C.Structure):
+    _fields_ = [("D", C.c_double), ("phi_ref", C.c_double), ("reaction", C.c_int32),
+                ("reserved", C.c_int32), ("c", C.c_double * 4)]
+
+
+class Params(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("bc_y", C.c_int32), ("delta_kernel", C.c_int32),
+                ("tau", C.c_double), ("rho0", C.c_double), ("body_accel", C.c_double * 2),
+                ("k_spring", C.c_double), ("phi_m", C.c_double), ("kappa_area", C.c_double),
+                ("n_species", C.c_int32), ("storage", C.c_int32), ("species", Species * 2)]
+
+
+class LbibError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str = ""):
+        self.status = status
+        super().__init__(f"{where}: {_status_name(status)} {msg}".strip())
+
+
+_lib = None
+
+
+def _status_name(s: int) -> str:
+    return {0: "LBIB_OK", -1: "LBIB_EINVAL", -2: "LBIB_ENOMEM", -3: "LBIB_EDEVICE",
+            -4: "LBIB_ESTATE", -5: "LBIB_ENUMERIC"}.get(int(s), f"status {s}")
+
+
+def lib():
+    """Load ``liblbib.so`` (built in-tree by ``paper_1503_06726_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                           "(python -m paper_1503_06726_amd.build)")
+    L = C.CDLL(LIB_PATH)
+    vp, dp, ip = C.c_void_p, C.c_void_p, C.c_void_p
+    P = C.POINTER(Params)
+    st = C.c_int
+    L.lbib_validate_params.restype = st
+    L.lbib_validate_params.argtypes = [P, C.c_char_p, C.c_size_t]
+    L.lbib_validate_cells.restype = st
+    L.lbib_validate_cells.argtypes = [P, C.c_int32, ip, dp, dp, dp, C.c_char_p, C.c_size_t]
+    L.lbib_create.restype = st
+    L.lbib_create.argtypes = [P, vp, C.POINTER(C.c_void_p)]
+    L.lbib_set_cells.restype = st
+    L.lbib_set_cells.argtypes = [vp, C.c_int32, ip, dp, dp, dp]
+    L.lbib_set_fields.restype = st
+    L.lbib_set_fields.argtypes = [vp, dp, dp, dp]
+    L.lbib_step.restype = st
+    L.lbib_step.argtypes = [vp, C.c_int32]
+    L.lbib_get_fields.restype = st
+    L.lbib_get_fields.argtypes = [vp, dp, dp, dp, dp, ip]
+    L.lbib_get_forces.restype = st
+    L.lbib_get_forces.argtypes = [vp, dp, dp]
+    L.lbib_get_spread.restype = st
+    L.lbib_get_spread.argtypes = [vp, dp]
+    L.lbib_reduce.restype = st
+    L.lbib_reduce.argtypes = [vp, dp]
+    L.lbib_sync.restype = st
+    L.lbib_sync.argtypes = [vp]
+    L.lbib_set_timing.restype = st
+    L.lbib_set_timing.argtypes = [vp, C.c_int32]
+    L.lbib_get_timing.restype = st
+    L.lbib_get_timing.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.lbib_device_bytes.restype = st
+    L.lbib_device_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.lbib_last_error.restype = C.c_char_p
+    L.lbib_last_error.argtypes = [vp]
+    L.lbib_status_string.restype = C.c_char_p
+    L.lbib_status_string.argtypes = [C.c_int]
+    L.lbib_version.restype = C.c_int32
+    L.lbib_version.argtypes = []
+    L.lbib_destroy.restype = None
+    L.lbib_destroy.argtypes = [vp]
+    _lib = L
+    return L
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def make_params(d: dict) -> Params:
+    """lbib_params from a workload parameter dict (see ``workloads.Workload.params_dict``)."""
+    p = Params()
+    p.nx, p.ny, p.bc_y = int(d["nx"]), int(d["ny"]), int(d["bc_y"])
+    p.delta_kernel = int(d.get("delta_kernel", DELTA_COS4))
+    p.tau, p.rho0 = float(d["tau"]), float(d.get("rho0", 1.0))
+    b = d.get("body_accel", (0.0, 0.0))
+    p.body_accel[0], p.body_accel[1] = float(b[0]), float(b[1])
+    p.k_spring = float(d.get("k_spring", 0.0))
+    p.phi_m = float(d.get("phi_m", 0.0))
+    p.kappa_area = float(d.get("kappa_area", 0.0))
+    sp = d.get("species", [])
+    p.n_species = len(sp)
+    p.storage = 0
+    for s, spc in enumerate(sp[:2]):        # more than two is left to the validator to reject
+        p.species[s].D = float(spc["D"])
+        p.species[s].phi_ref = float(spc.get("phi_ref", 0.0))
+        p.species[s].reaction = int(spc.get("reaction", REACT_NONE))
+        p.species[s].reserved = 0
+        for k, v in enumerate(spc.get("c", (0.0, 0.0, 0.0, 0.0))):
+            p.species[s].c[k] = float(v)
+    return p
+
+
+def validate_params(d: dict):
+    msg = C.create_string_buffer(256)
+    p = make_params(d)
+    s = lib().lbib_validate_params(C.byref(p), msg, 256)
+    return s, msg.value.decode()
+
+
+def validate_cells(d: dict, offsets, xy, rest_len=None, rest_area=None):
+    msg = C.create_string_buffer(256)
+    p = make_params(d)
+    off = np.ascontiguousarray(offsets, np.int32)
+    xy = np.ascontiguousarray(xy, np.float64).reshape(-1, 2)
+    rl = None if rest_len is None else np.ascontiguousarray(rest_len, np.float64)
+    ra = None if rest_area is None else np.ascontiguousarray(rest_area, np.float64)
+    s = lib().lbib_validate_cells(C.byref(p), len(off) - 1, _p(off), _p(xy), _p(rl), _p(ra), msg, 256)
+    return s, msg.value.decode()
+
+
+class Simulation:
+    """One lbib context: ``create`` on construction, ``destroy`` on ``close``.
+
+    ``stream`` is a ``hipStream_t`` handle as an int (for instance
+    ``torch.cuda.current_stream().cuda_stream``); None lets the library own a stream."""
+
+    def __init__(self, params: dict, stream: int | None = None):
+        self.L = lib()
+        self.params = params
+        self._p = make_params(params)
+        h = C.c_void_p()
+        s = self.L.lbib_create(C.byref(self._p), C.c_void_p(stream) if stream else None, C.byref(h))
+        if s != OK:
+            raise LbibError(s, "lbib_create")
+        self.h = h
+        self.nx, self.ny, self.S = self._p.nx, self._p.ny, self._p.n_species
+        self.n_nodes = 0
+        self.n_cells = 0
+
+    # -- lifetime --------------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.lbib_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, s, where):
+        if s != OK:
+            raise LbibError(s, where, (self.L.lbib_last_error(self.h) or b"").decode())
+
+    # -- calls of the C ABI -------------------------------------------------------------------
+    def set_cells(self, offsets, xy, rest_len=None, rest_area=None):
+        off = np.ascontiguousarray(offsets, np.int32)
+        xy = np.ascontiguousarray(xy, np.float64).reshape(-1, 2)
+        rl = None if rest_len is None else np.ascontiguousarray(rest_len, np.float64)
+        ra = None if rest_area is None else np.ascontiguousarray(rest_area, np.float64)
+        self._check(self.L.lbib_set_cells(self.h, len(off) - 1, _p(off), _p(xy), _p(rl), _p(ra)),
+                    "lbib_set_cells")
+        self.n_nodes = xy.shape[0]
+        self.n_cells = len(off) - 1
+
+    def set_fields(self, rho=None, u=None, phi=None):
+        r = None if rho is None else np.ascontiguousarray(rho, np.float64)
+        uu = None if u is None else np.ascontiguousarray(u, np.float64)
+        ph = None if phi is None else np.ascontiguousarray(phi, np.float64)
+        self._check(self.L.lbib_set_fields(self.h, _p(r), _p(uu), _p(ph)), "lbib_set_fields")
+
+    def step(self, n: int = 1):
+        self._check(self.L.lbib_step(self.h, int(n)), "lbib_step")
+
+    def get_fields(self, rho=True, u=True, phi=True, xy=True, mask=True):
+        ny, nx, S = self.ny, self.nx, self.S
+        out = {}
+        r = np.empty((ny, nx)) if rho else None
+        uu = np.empty((2, ny, nx)) if u else None
+        ph = np.empty((S, ny, nx)) if (phi and S) else None
+        X = np.empty((self.n_nodes, 2)) if (xy and self.n_nodes) else None
+        m = np.empty((ny, nx), np.int32) if mask else None
+        self._check(self.L.lbib_get_fields(self.h, _p(r), _p(uu), _p(ph), _p(X), _p(m)), "lbib_get_fields")
+        out["rho"], out["u"] = r, uu
+        out["phi"] = ph if ph is not None else np.zeros((0, ny, nx))
+        out["xy"] = X if X is not None else np.zeros((0, 2))
+        out["mask"] = m
+        return out
+
+    def get_forces(self):
+        F = np.zeros((max(self.n_nodes, 1), 2))
+        A = np.zeros(max(self.n_cells, 1))
+        self._check(self.L.lbib_get_forces(self.h, _p(F), _p(A)), "lbib_get_forces")
+        return F[:self.n_nodes], A[:self.n_cells]
+
+    def get_spread(self):
+        e = np.empty((2, self.ny, self.nx))
+        self._check(self.L.lbib_get_spread(self.h, _p(e)), "lbib_get_spread")
+        return e
+
+    def reduce(self):
+        out = np.zeros(3 + self.S)
+        self._check(self.L.lbib_reduce(self.h, _p(out)), "lbib_reduce")
+        return out
+
+    def sync(self):
+        self._check(self.L.lbib_sync(self.h), "lbib_sync")
+
+    def set_timing(self, enable: bool):
+        self._check(self.L.lbib_set_timing(self.h, int(bool(enable))), "lbib_set_timing")
+
+    def get_timing(self, kernel: int):
+        ms = C.c_double()
+        n = C.c_int64()
+        self._check(self.L.lbib_get_timing(self.h, int(kernel), C.byref(ms), C.byref(n)), "lbib_get_timing")
+        return ms.value, n.value
+
+    def device_bytes(self) -> int:
+        b = C.c_size_t()
+        self._check(self.L.lbib_device_bytes(self.h, C.byref(b)), "lbib_device_bytes")
+        return int(b.value)
+
+
+def from_workload(w, stream: int | None = None) -> Simulation:
+    """A Simulation initialised from a ``workloads.Workload``."""
+    s = Simulation(w.params_dict(), stream=stream)
+    if w.rho_init is not None or w.u_init is not None or w.phi_init is not None:
+        s.set_fields(w.rho_init, w.u_init, w.phi_init)
+    if w.n_cells:
+        s.set_cells(w.offsets, w.xy, w.rest_len, w.rest_area)
+    return s

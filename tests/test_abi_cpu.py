@@ -1,0 +1,137 @@
+"""C ABI checks that need no GPU: the library loads and exports every declared entry
+point, the ctypes mirrors match the C struct layout, and the validation rules hold."""
+import ctypes as C
+import math
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_1503_06726_amd import lbib
+from paper_1503_06726_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbib.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbib_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lbib.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(lbib.EXPORTS) == names
+    assert L.lbib_version() == 1
+    assert L.lbib_status_string(-5) == b"LBIB_ENUMERIC"
+
+
+def test_ctypes_layout_matches_header():
+    src = r"""
+    #include <stdio.h>
+    #include <stddef.h>
+    #include "lbib.h"
+    int main(void) {
+      printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lbib_params), sizeof(lbib_species),
+             offsetof(lbib_params, tau), offsetof(lbib_params, body_accel), offsetof(lbib_params, kappa_area),
+             offsetof(lbib_params, n_species), offsetof(lbib_params, species), offsetof(lbib_species, c),
+             offsetof(lbib_species, reaction));
+      return 0; }
+    """
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "l.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "l")
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        vals = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
+    P, S = lbib.Params, lbib.Species
+    want = [C.sizeof(P), C.sizeof(S), P.tau.offset, P.body_accel.offset, P.kappa_area.offset,
+            P.n_species.offset, P.species.offset, S.c.offset, S.reaction.offset]
+    assert vals == want
+
+
+GOOD = W.tiny_cell().params_dict()
+
+
+@pytest.mark.parametrize("change,frag", [
+    (dict(tau=0.5), "tau"), (dict(tau=float("nan")), "tau"), (dict(nx=3), "lattice"),
+    (dict(ny=40000), "lattice"), (dict(bc_y=2), "bc_y"), (dict(delta_kernel=7), "delta_kernel"),
+    (dict(rho0=0.0), "rho0"), (dict(body_accel=(float("inf"), 0.0)), "body"),
+])
+def test_bad_params_rejected(change, frag):
+    d = dict(GOOD, **change)
+    s, msg = lbib.validate_params(d)
+    assert s == lbib.EINVAL and frag in msg
+
+
+def test_species_rules():
+    assert lbib.validate_params(GOOD)[0] == lbib.OK
+    d = dict(GOOD, species=[dict(D=-0.1)])
+    assert lbib.validate_params(d)[0] == lbib.EINVAL
+    sch = (0.1, 0.9, 0.01, 0.0)
+    d = dict(GOOD, species=[dict(D=0.1, reaction=2, c=sch)])
+    s, msg = lbib.validate_params(d)
+    assert s == lbib.EINVAL and "Schnakenberg" in msg
+    d = dict(GOOD, species=[dict(D=0.1, reaction=2, c=sch), dict(D=0.2, reaction=2, c=(0.1, 0.8, 0.01, 0))])
+    assert lbib.validate_params(d)[0] == lbib.EINVAL
+    d = dict(GOOD, species=[dict(D=0.1, reaction=2, c=sch), dict(D=0.2, reaction=2, c=sch)])
+    assert lbib.validate_params(d)[0] == lbib.OK
+    d = dict(GOOD, species=[dict(D=0.1), dict(D=0.1), dict(D=0.1)])
+    assert lbib.validate_params(d)[0] == lbib.EINVAL
+
+
+def _square(x0, y0, s, cw=False):
+    P = np.array([[x0, y0], [x0 + s, y0], [x0 + s, y0 + s], [x0, y0 + s]], float)
+    return P[::-1].copy() if cw else P
+
+
+def test_cell_validation():
+    w = W.tiny_cell()
+    assert lbib.validate_cells(GOOD, w.offsets, w.xy, w.rest_len, w.rest_area)[0] == lbib.OK
+    off = np.array([0, 4], np.int32)
+    s, msg = lbib.validate_cells(GOOD, off, _square(10.5, 10.5, 5, cw=True))
+    assert s == lbib.EINVAL and "counter-clockwise" in msg
+    bad = _square(10.5, 10.5, 5)
+    bad[2, 0] = float("nan")
+    assert lbib.validate_cells(GOOD, off, bad)[0] == lbib.EINVAL
+    assert lbib.validate_cells(GOOD, np.array([0, 2], np.int32), _square(10, 10, 3)[:2])[0] == lbib.EINVAL
+    assert lbib.validate_cells(GOOD, np.array([1, 4], np.int32), _square(10, 10, 3))[0] == lbib.EINVAL
+    walls = dict(GOOD, bc_y=W.WALLS)
+    s, msg = lbib.validate_cells(walls, off, _square(10.5, 1.0, 5))
+    assert s == lbib.EINVAL and "wall" in msg
+    assert lbib.validate_cells(walls, off, _square(10.5, 2.0, 5))[0] == lbib.OK
+    s, msg = lbib.validate_cells(walls, off, _square(10.5, 57.0, 5))
+    assert s == lbib.EINVAL
+    big = W.circle_cell(32, 32, 20, 4097, 0.0, None)
+    assert lbib.validate_cells(dict(GOOD, nx=128, ny=128), big[0], big[1])[0] == lbib.EINVAL
+    big = W.circle_cell(32, 32, 20, 4096, 0.0, None)
+    assert lbib.validate_cells(dict(GOOD, nx=128, ny=128), big[0], big[1])[0] == lbib.OK
+    assert lbib.validate_cells(GOOD, off, _square(2.5, 10.5, 60.0))[0] == lbib.EINVAL   # spans the lattice
+    rl = np.array([1.0, -1.0, 1.0, 1.0])
+    assert lbib.validate_cells(GOOD, off, _square(10.5, 10.5, 5), rest_len=rl)[0] == lbib.EINVAL
+    assert lbib.validate_cells(GOOD, np.zeros(1, np.int32), np.zeros((0, 2)))[0] == lbib.OK
+
+
+def test_create_rejects_bad_params_before_touching_a_device():
+    p = lbib.make_params(dict(GOOD, tau=0.4))
+    h = C.c_void_p()
+    assert lbib.lib().lbib_create(C.byref(p), None, C.byref(h)) == lbib.EINVAL
+    assert not h.value
+    assert lbib.lib().lbib_step(None, 1) == lbib.ESTATE
+    assert lbib.lib().lbib_last_error(None) == b""
+    lbib.lib().lbib_destroy(None)
+
+
+def test_workload_inputs_pass_validation():
+    for w in (W.tiny_cell(), W.small_tissue(), W.small_tissue(bc_y=W.PERIODIC, n_species=2, seed=3)):
+        assert lbib.validate_params(w.params_dict())[0] == lbib.OK
+        s, msg = lbib.validate_cells(w.params_dict(), w.offsets, w.xy, w.rest_len, w.rest_area)
+        assert s == lbib.OK, msg
