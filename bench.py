@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="large", choices=["large", "tissue", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run only a plain device copy of 1 GiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the lattice would shard into "
@@ -75,6 +77,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        # a copy of known size: 2^30 bytes read and 2^30 bytes written per launch
+        a = torch.ones(2 ** 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: 5 copies of 2^30 bytes")
+        return
     w = W.WORKLOADS[args.workload]()
     S = w.n_species
     mask = w.mask_needed()
@@ -94,7 +105,7 @@ def main():
     sim.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    timings = {lbib.KERNEL_NAMES[k]: sim.get_timing(k) for k in range(5)}
+    timings = {lbib.KERNEL_NAMES[k]: sim.get_timing(k) for k in range(len(lbib.KERNEL_NAMES))}
     sim.set_timing(False)
     log(f"timed {args.steps} steps: {dt:.3f} s")
     for k, (ms, n) in timings.items():

@@ -154,11 +154,11 @@ lbib_status lbib_reduce(lbib_ctx* ctx, double* out);
 lbib_status lbib_sync(lbib_ctx* ctx);
 
 /* Per-kernel timing with HIP events on the context's stream (0 disables, default).
- * Kernel ids: LBIB_K_LATTICE, LBIB_K_MEMBRANE, LBIB_K_BIN_SCAN, LBIB_K_BIN_SCATTER,
- * LBIB_K_RASTER.  lbib_get_timing synchronises and returns the summed milliseconds and
- * the number of timed launches since timing was last enabled. */
-enum { LBIB_K_LATTICE = 0, LBIB_K_MEMBRANE = 1, LBIB_K_BIN_SCAN = 2, LBIB_K_BIN_SCATTER = 3,
-       LBIB_K_RASTER = 4, LBIB_K_COUNT = 5 };
+ * Ids: LBIB_K_LATTICE (the lattice pass), LBIB_K_MEMBRANE (interpolation, advection, forces,
+ * domain IDs), LBIB_K_REBIN (refiling the nodes by lattice tile, every few steps).
+ * lbib_get_timing synchronises and returns the summed milliseconds and the number of timed
+ * launches since timing was last enabled. */
+enum { LBIB_K_LATTICE = 0, LBIB_K_MEMBRANE = 1, LBIB_K_REBIN = 2, LBIB_K_COUNT = 3 };
 lbib_status lbib_set_timing(lbib_ctx* ctx, int32_t enable);
 lbib_status lbib_get_timing(lbib_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches);
 

@@ -136,9 +136,8 @@ LatticeArgs lattice_args(lbib_ctx* c)
     a.bodyy = (float)p.body_accel[1];
     a.kernel = p.delta_kernel;
     a.bin_off = c->d_bin_off;
-    a.rec = c->d_rec;
-    a.rec_ij = c->d_rec_ij;
-    a.bin_count = c->d_bin_count;
+    a.rec = c->d_rec[c->rec_cur];
+    a.rec_ij = c->d_rec_ij[c->rec_cur];
     a.uband = c->uband;
     a.mask = c->mask;
     a.e_out = nullptr;
@@ -151,11 +150,16 @@ MembraneArgs membrane_args(lbib_ctx* c, int advect)
     std::memset(&a, 0, sizeof a);
     a.off = c->d_off;
     a.X = c->d_X;
-    a.F = c->d_F;
     a.l0 = c->d_l0;
     a.A0 = c->d_A0;
     a.area = c->d_area;
     a.uband = c->uband;
+    a.slot = c->d_slot;
+    a.key = c->d_key;
+    a.rec = c->d_rec[c->rec_cur];
+    a.rec_ij = c->d_rec_ij[c->rec_cur];
+    a.mask = c->mask;
+    a.err = c->d_err;
     a.nn = c->nn;
     a.nx = c->p.nx;
     a.ny = c->p.ny;
@@ -166,28 +170,32 @@ MembraneArgs membrane_args(lbib_ctx* c, int advect)
     a.k_spring = c->p.k_spring;
     a.phi_m = c->p.phi_m;
     a.kappa = c->p.kappa_area;
-    a.key = c->d_key;
-    a.rank = c->d_rank;
-    a.bin_count = c->d_bin_count;
-    a.err = c->d_err;
     a.advect = advect;
+    a.raster = c->mask_needed ? 1 : 0;
     return a;
 }
 
-ScatterArgs scatter_args(lbib_ctx* c)
+BinArgs bin_args(lbib_ctx* c, int copy)
 {
-    ScatterArgs a;
+    BinArgs a;
+    std::memset(&a, 0, sizeof a);
     a.X = c->d_X;
-    a.F = c->d_F;
     a.key = c->d_key;
     a.rank = c->d_rank;
-    a.bin_off = c->d_bin_off;
-    a.rec = c->d_rec;
-    a.rec_ij = c->d_rec_ij;
+    a.count = c->d_bin_count;
+    a.off = c->d_bin_off;
+    a.slot = c->d_slot;
+    a.rec_old = c->d_rec[c->rec_cur];
+    a.ij_old = c->d_rec_ij[c->rec_cur];
+    a.rec_new = c->d_rec[1 - c->rec_cur];
+    a.ij_new = c->d_rec_ij[1 - c->rec_cur];
     a.n = c->n_nodes;
     a.nx = c->p.nx;
     a.ny = c->p.ny;
     a.walls = c->p.bc_y == LBIB_WALLS;
+    a.ntx = c->ntx;
+    a.nbins = c->nbins;
+    a.copy = copy;
     return a;
 }
 
@@ -212,25 +220,24 @@ RasterArgs raster_args(lbib_ctx* c)
         }                                                                                    \
     } while (0)
 
-// forces of the current positions, binning, and (when a reaction reads it) the domain map
-lbib_status membrane_refresh(lbib_ctx* c, int advect)
+// File every node under the lattice tile of its current stencil origin; with copy set, the
+// records move from their old slots (the spare record buffer becomes the current one).
+lbib_status rebin(lbib_ctx* c, int copy)
 {
-    {
-        Timed tm(c, LBIB_K_MEMBRANE);
-        LBIB_LAUNCH(c, launch_membrane(c, membrane_args(c, advect)));
-    }
-    {
-        Timed tm(c, LBIB_K_BIN_SCAN);
-        LBIB_LAUNCH(c, launch_scan(c));
-    }
-    {
-        Timed tm(c, LBIB_K_BIN_SCATTER);
-        LBIB_LAUNCH(c, launch_scatter(c, scatter_args(c)));
-    }
-    if (c->mask_needed) {
-        Timed tm(c, LBIB_K_RASTER);
-        LBIB_LAUNCH(c, launch_raster(c, raster_args(c)));
-    }
+    Timed tm(c, LBIB_K_REBIN);
+    const BinArgs a = bin_args(c, copy);
+    for (int which = 0; which < 3; ++which) LBIB_LAUNCH(c, launch_rebin(c, a, which));
+    if (copy) c->rec_cur = 1 - c->rec_cur;
+    c->steps_since_rebin = 0;
+    return LBIB_OK;
+}
+
+// interpolation and advection (advect = 1), forces and records of the new positions, and,
+// when a reaction reads it, the domain map
+lbib_status membrane(lbib_ctx* c, int advect)
+{
+    Timed tm(c, LBIB_K_MEMBRANE);
+    LBIB_LAUNCH(c, launch_membrane(c, membrane_args(c, advect)));
     return LBIB_OK;
 }
 
@@ -252,8 +259,12 @@ lbib_status check_err_flag(lbib_ctx* c)
     int h = 0;
     LBIB_HIP(c, hipMemcpyAsync(&h, c->d_err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
-    if (h) {
+    if (h & ERR_NONFINITE) {
         c->err = "a membrane node position or force became non-finite";
+        return LBIB_ENUMERIC;
+    }
+    if (h & ERR_MARGIN) {
+        c->err = "a membrane node moved more than 2 lattice units between rebinnings (velocity too large)";
         return LBIB_ENUMERIC;
     }
     return LBIB_OK;
@@ -264,18 +275,22 @@ void free_nodes(lbib_ctx* c)
     const size_t N = (size_t)c->n_nodes, C = (size_t)c->n_cells;
     dev_free(c, c->d_off, C + 1);
     dev_free(c, c->d_X, N);
-    dev_free(c, c->d_F, N);
     dev_free(c, c->d_l0, N);
     dev_free(c, c->d_A0, C);
     dev_free(c, c->d_area, C);
     dev_free(c, c->d_key, N);
     dev_free(c, c->d_rank, N);
-    dev_free(c, c->d_rec, N);
-    dev_free(c, c->d_rec_ij, N);
+    dev_free(c, c->d_slot, N);
+    for (int b = 0; b < 2; ++b) {
+        dev_free(c, c->d_rec[b], N);
+        dev_free(c, c->d_rec_ij[b], N);
+    }
+    c->rec_cur = 0;
     c->n_nodes = 0;
     c->n_cells = 0;
     c->max_cell_nodes = 0;
     c->mask_needed = false;
+    c->steps_since_rebin = 0;
 }
 
 void free_all(lbib_ctx* c)
@@ -470,14 +485,16 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
     lbib_status s = LBIB_OK;
     s = dev_alloc(c, &c->d_off, C + 1);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_X, N);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_F, N);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_l0, N);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_A0, C);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_area, C);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_key, N);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_rank, N);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_rec, N);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_rec_ij, N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_slot, N);
+    for (int b = 0; b < 2 && s == LBIB_OK; ++b) {
+        s = dev_alloc(c, &c->d_rec[b], N);
+        if (s == LBIB_OK) s = dev_alloc(c, &c->d_rec_ij[b], N);
+    }
     c->n_cells = n_cells;
     c->n_nodes = (int64_t)N;
     if (s != LBIB_OK) {
@@ -493,7 +510,8 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
     LBIB_LAUNCH(c, launch_fill_i32(c, c->d_bin_count, c->nbins, 0));
     LBIB_LAUNCH(c, launch_fill_i32(c, c->d_err, 1, 0));
     if (c->mask_needed) LBIB_LAUNCH(c, launch_fill_u16(c, c->mask, c->nn));
-    LBIB_TRY(membrane_refresh(c, 0));
+    LBIB_TRY(rebin(c, 0));
+    LBIB_TRY(membrane(c, 0));
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
     return check_err_flag(c);
 }
@@ -534,7 +552,10 @@ lbib_status lbib_step(lbib_ctx* c, int32_t n)
             LBIB_LAUNCH(c, launch_lattice(c, lattice_args(c), nodes, c->mask_needed));
         }
         c->cur = 1 - c->cur;
-        if (nodes) LBIB_TRY(membrane_refresh(c, 1));
+        if (nodes) {
+            LBIB_TRY(membrane(c, 1));
+            if (++c->steps_since_rebin >= REBIN_PERIOD) LBIB_TRY(rebin(c, 1));
+        }
         if (c->timing && c->pending.size() > 4096) LBIB_TRY(harvest(c));
     }
     return LBIB_OK;
@@ -580,8 +601,10 @@ lbib_status lbib_get_forces(lbib_ctx* c, double* F, double* area)
     if (!c->n_cells) return LBIB_OK;
     const size_t N = (size_t)c->n_nodes;
     if (F) {
+        LBIB_TRY(ensure_stage(c, N));
+        LBIB_LAUNCH(c, launch_forces_out(c, (float2*)c->d_stage));
         std::vector<float> h(2 * N);
-        LBIB_HIP(c, hipMemcpyAsync(h.data(), c->d_F, N * sizeof(float2), hipMemcpyDeviceToHost, c->stream));
+        LBIB_HIP(c, hipMemcpyAsync(h.data(), c->d_stage, N * sizeof(float2), hipMemcpyDeviceToHost, c->stream));
         LBIB_HIP(c, hipStreamSynchronize(c->stream));
         for (size_t i = 0; i < 2 * N; ++i) F[i] = h[i];
     }

@@ -91,36 +91,46 @@ __device__ inline unsigned long long to_fixed(float v)
     return (unsigned long long)__float2ll_rn(v * FIX_SCALE);
 }
 
-// Spread the binned node forces into this tile's LDS accumulators.
+// do the cyclic intervals [a0, a0 + alen) and [b0, b0 + blen) of Z_n meet?
+__device__ inline bool cyc_meet(int a0, int alen, int b0, int blen, int n)
+{
+    if (alen + blen > n) return true;
+    const int d = wrap_ll((long long)a0 - b0, n);
+    return d < blen || d + alen > n;
+}
+
+// Spread the binned node forces into this tile's LDS accumulators.  A node filed in bin b
+// has its stencil origin within b's tile widened by BIN_MARGIN; the tile needs every node
+// whose origin lies in [x0 - 3, x1 - 1] x [y0 - 3, y1 - 1], so it reads every bin whose
+// widened tile meets that range (superfluous candidates contribute nothing).
 __device__ inline void spread_tile(const LatticeArgs& a, int tcol, int trow, int x0, int y0,
                                    unsigned long long* accx, unsigned long long* accy, int* tch)
 {
     const int t = threadIdx.x;
-    // bin columns whose origins reach the tile: origins in [x0-3, x0+TILE_X-1] (wrapped)
-    int cols[4], ncol = 0;
+    const int M = BIN_MARGIN;
+    const int x1 = min(x0 + TILE_X, a.nx), y1 = min(y0 + TILE_Y, a.ny);
+    int cols[5], ncol = 0;
     {
-        int xs = x0 - 3;
-        if (xs < 0) xs += a.nx;
-        int cc = xs / TILE_X;
-        for (;;) {
-            cols[ncol++] = cc;
-            if (cc == tcol || ncol == 4) break;
-            cc = (cc + 1 == a.ntx) ? 0 : cc + 1;
+        const int nc = a.ntx <= 5 ? a.ntx : 5;
+        for (int q = 0; q < nc; ++q) {
+            const int cc = a.ntx <= 5 ? q : wrap_ll((long long)tcol - 2 + q, a.ntx);
+            const int bx0 = cc * TILE_X, bw = min(TILE_X, a.nx - bx0);
+            if (cyc_meet(bx0 - M, bw + 2 * M, x0 - 3, x1 - x0 + 3, a.nx)) cols[ncol++] = cc;
         }
     }
-    int rows[4], nrow = 0;
-    {
-        int ys = y0 - 3;
-        if (a.walls) {
-            if (ys < 0) ys = 0;
-        } else if (ys < 0) {
-            ys += a.ny;
+    int rows[5], nrow = 0;
+    if (a.walls) {
+        for (int rr = max(trow - 2, 0); rr <= min(trow + 2, a.nty - 1); ++rr) {
+            const int by0 = rr * TILE_Y, bh = min(TILE_Y, a.ny - by0);
+            const int lo = (rr == 0) ? -1000000 : by0 - M;              // bin row 0 also holds j0 < 0
+            if (lo <= y1 - 1 && by0 + bh - 1 + M >= y0 - 3) rows[nrow++] = rr;
         }
-        int rr = ys / TILE_Y;
-        for (;;) {
-            rows[nrow++] = rr;
-            if (rr == trow || nrow == 4) break;
-            rr = (rr + 1 == a.nty) ? 0 : rr + 1;
+    } else {
+        const int nr = a.nty <= 5 ? a.nty : 5;
+        for (int q = 0; q < nr; ++q) {
+            const int rr = a.nty <= 5 ? q : wrap_ll((long long)trow - 2 + q, a.nty);
+            const int by0 = rr * TILE_Y, bh = min(TILE_Y, a.ny - by0);
+            if (cyc_meet(by0 - M, bh + 2 * M, y0 - 3, y1 - y0 + 3, a.ny)) rows[nrow++] = rr;
         }
     }
     for (int ir = 0; ir < nrow; ++ir) {
@@ -128,10 +138,21 @@ __device__ inline void spread_tile(const LatticeArgs& a, int tcol, int trow, int
             const int b = rows[ir] * a.ntx + cols[ic];
             const int beg = a.bin_off[b], end = a.bin_off[b + 1];
             for (int k = beg + t; k < end; k += TILE_N) {
-                const float4 r = a.rec[k];
                 const int ij = a.rec_ij[k];
                 const int i0 = ij & 0xFFFF;
                 const int j0 = ij >> 16;              // sign-extended 16-bit row
+                // quick rejection: does the 4x4 stencil at (i0, j0) reach the tile at all?
+                int dx = i0 - x0 + 3;                 // i0, x0 in [0, nx): one wrap at most
+                if (dx < 0) dx += a.nx;
+                else if (dx >= a.nx) dx -= a.nx;
+                if (dx >= TILE_X + 3) continue;
+                int dy = j0 - y0 + 3;
+                if (!a.walls) {
+                    if (dy < 0) dy += a.ny;
+                    else if (dy >= a.ny) dy -= a.ny;
+                }
+                if (dy < 0 || dy >= TILE_Y + 3) continue;
+                const float4 r = a.rec[k];
                 float wx[4], wy[4];
                 delta_weights(a.kernel, r.x, wx);
                 delta_weights(a.kernel, r.y, wy);
@@ -171,31 +192,44 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
     const int x0 = tcol * TILE_X, y0 = trow * TILE_Y;
     const int t = threadIdx.x;
     const int x = x0 + (t % TILE_X), y = y0 + (t / TILE_X);
+    const bool active = x < a.nx && y < a.ny;
+    const int64_t nn = a.nn;
+
+    __shared__ unsigned long long accx[NODES ? TILE_N : 1], accy[NODES ? TILE_N : 1];
+    __shared__ int tch[NODES ? TILE_N : 1];
+    if constexpr (NODES) {
+        accx[t] = 0ull;
+        accy[t] = 0ull;
+        tch[t] = 0;
+        __syncthreads();
+    }
+
+    // issue the population loads first: they are in flight while the forces are spread
+    Nbr n;
+    int64_t o = 0;
+    float f[9];
+    float g[S > 0 ? S : 1][5];
+    int m = 0;
+    if (active) {
+        n = neighbours(x, y, a.nx, a.ny, a.walls);
+        o = n.rc + x;
+        pull9(a.fsrc, nn, x, n, f);
+#pragma unroll
+        for (int s = 0; s < S; ++s) pull5(a.gsrc + (int64_t)5 * s * nn, nn, x, n, g[s]);
+        if constexpr (MASK) m = a.mask[o];
+    }
 
     float ex = a.bodyx, ey = a.bodyy;
     bool touched = false;
     if constexpr (NODES) {
-        __shared__ unsigned long long accx[TILE_N], accy[TILE_N];
-        __shared__ int tch[TILE_N];
-        accx[t] = 0ull;
-        accy[t] = 0ull;
-        tch[t] = 0;
-        if (t == 0) a.bin_count[tile] = 0;     // counts of the next binning
-        __syncthreads();
         spread_tile(a, tcol, trow, x0, y0, accx, accy, tch);
         __syncthreads();
         ex += __ll2float_rn((long long)accx[t]) * FIX_INV;
         ey += __ll2float_rn((long long)accy[t]) * FIX_INV;
         touched = tch[t] != 0;
     }
-    if (x >= a.nx || y >= a.ny) return;
+    if (!active) return;
 
-    const Nbr n = neighbours(x, y, a.nx, a.ny, a.walls);
-    const int64_t nn = a.nn;
-    const int64_t o = n.rc + x;
-
-    float f[9];
-    pull9(a.fsrc, nn, x, n, f);
     const float drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
     const float rho = a.rho0 + drho;
     const float jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
@@ -221,16 +255,11 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
         vu = ux - uy;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[8 * nn] = om1 * f[8] + om * eq + W5 * (fx - fy);
     }
 
+    if constexpr (MASK) a.mask[o] = 0;
     if constexpr (S > 0) {
-        int m = 0;
-        if constexpr (MASK) {
-            m = a.mask[o];
-            a.mask[o] = 0;
-        }
-        float g[S][5], dphi[S], phi[S], R[S];
+        float dphi[S], phi[S], R[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            pull5(a.gsrc + (int64_t)5 * s * nn, nn, x, n, g[s]);
             dphi[s] = ((g[s][0] + g[s][1]) + (g[s][2] + g[s][3])) + g[s][4];
             phi[s] = a.phi_ref[s] + dphi[s];
         }
@@ -258,8 +287,6 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
             d[3 * nn] = os1 * g[s][3] + os * Q1 * (dphi[s] - p3 * ux) + Q1 * R[s];
             d[4 * nn] = os1 * g[s][4] + os * Q1 * (dphi[s] - p3 * uy) + Q1 * R[s];
         }
-    } else if constexpr (MASK) {
-        a.mask[o] = 0;
     }
 
     if constexpr (NODES) {

@@ -4,12 +4,15 @@
 //   1. interpolates u^n to each node over the 4x4 stencil (Eq. conversion2 with the kernel
 //      of Eq. 1Dkernel) and moves the node explicitly, X^{n+1} = X^n + U (positions in FP64);
 //   2. stages the cell's new positions in LDS and reduces the polygon area (shoelace, FP64,
-//      fixed-order tree);
+//      fixed-order wave and LDS reduction);
 //   3. evaluates the nodal forces in the paper's per-node form: constant tension
-//      (Eq. membraneforce), Hookean springs, area pressure kappa (A0 - A) dA/dX;
-//   4. files the node under the lattice tile of its stencil origin for the next spreading.
-// k_bin_scan / k_bin_scatter turn the per-tile counts into a CSR of node records.
+//      (Eq. membraneforce), Hookean springs, area pressure kappa (A0 - A) dA/dX, and
+//      refreshes the node's spreading record (fractional offset, force, stencil origin) in
+//      its bin slot; a node that drifted beyond its bin margin raises an error flag;
+//   4. when a reaction reads them, rasterises the cell's domain IDs from the LDS positions.
+// k_bin_count / k_bin_scan / k_bin_scatter rebuild the bins (every few steps).
 #include "lbib_internal.h"
+#include "lbib_raster.h"
 
 namespace lbib {
 
@@ -47,30 +50,45 @@ __device__ inline float2 interp_u(const MembraneArgs& a, double X, double Y)
     return make_float2(ux, uy);
 }
 
-// finite and small enough for the integer stencil arithmetic (|coordinate| < 2^40)
-__device__ inline bool finite2(double x, double y)
+__device__ inline double wave_sum(double v)
 {
-    return fabs(x) < 1099511627776.0 && fabs(y) < 1099511627776.0;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// is the origin (i0, j0) within the widened tile of bin `key`?
+__device__ inline bool within_margin(int i0, int j0, int key, int nx, int ny, int walls, int ntx)
+{
+    const int bc = key % ntx, br = key / ntx;
+    const int bx0 = bc * TILE_X, bw = min(TILE_X, nx - bx0);
+    const int by0 = br * TILE_Y, bh = min(TILE_Y, ny - by0);
+    const int dx = wrap_ll((long long)i0 - bx0 + BIN_MARGIN, nx);
+    if (bw + 2 * BIN_MARGIN < nx && dx > bw - 1 + 2 * BIN_MARGIN) return false;
+    if (walls) {
+        const int jr = j0 < 0 ? 0 : (j0 >= ny ? ny - 1 : j0);
+        return jr >= by0 - BIN_MARGIN && jr <= by0 + bh - 1 + BIN_MARGIN;
+    }
+    const int dy = wrap_ll((long long)j0 - by0 + BIN_MARGIN, ny);
+    return !(bh + 2 * BIN_MARGIN < ny && dy > bh - 1 + 2 * BIN_MARGIN);
 }
 
 __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
 {
     extern __shared__ double2 xs[];
-    __shared__ double red[MEMBRANE_THREADS];
+    __shared__ double red[16];
+    __shared__ unsigned bm[RASTER_WORDS_FUSED];
     const int c = blockIdx.x;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const int beg = a.off[c];
     const int n = a.off[c + 1] - beg;
 
     for (int k = t; k < n; k += MEMBRANE_THREADS) {
         double2 X = a.X[beg + k];
-        if (a.advect) {
-            if (finite2(X.x, X.y)) {
-                const float2 U = interp_u(a, X.x, X.y);
-                X.x += (double)U.x;
-                X.y += (double)U.y;
-                a.X[beg + k] = X;
-            }
+        if (a.advect && finite2(X.x, X.y)) {
+            const float2 U = interp_u(a, X.x, X.y);
+            X.x += (double)U.x;
+            X.y += (double)U.y;
+            a.X[beg + k] = X;
         }
         xs[k] = X;
     }
@@ -83,16 +101,16 @@ __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
         const int kn = (k + 1 == n) ? 0 : k + 1;
         part += (xs[k].x - ox) * (xs[kn].y - oy) - (xs[kn].x - ox) * (xs[k].y - oy);
     }
-    red[t] = part;
+    part = wave_sum(part);
+    if (lane == 0) red[wid] = part;
     __syncthreads();
-    for (int w = MEMBRANE_THREADS / 2; w > 0; w >>= 1) {
-        if (t < w) red[t] += red[t + w];
-        __syncthreads();
-    }
-    const double A = 0.5 * red[0];
+    double A2 = 0.0;
+    for (int w = 0; w < MEMBRANE_THREADS / 64; ++w) A2 += red[w];
+    const double A = 0.5 * A2;
     if (t == 0) a.area[c] = A;
     const double s_area = a.kappa * (a.A0[c] - A);
 
+    int flags = 0;
     for (int k = t; k < n; k += MEMBRANE_THREADS) {
         const int kp = (k + 1 == n) ? 0 : k + 1;
         const int km = (k == 0) ? n - 1 : k - 1;
@@ -100,97 +118,145 @@ __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
         const double dpx = Xp.x - X.x, dpy = Xp.y - X.y;
         const double dmx = Xm.x - X.x, dmy = Xm.y - X.y;
         const double Lp = sqrt(dpx * dpx + dpy * dpy), Lm = sqrt(dmx * dmx + dmy * dmy);
-        // unit vectors towards the successor and the predecessor
-        const double tpx = dpx / Lp, tpy = dpy / Lp, tmx = dmx / Lm, tmy = dmy / Lm;
         // tension phi_m along both edges; springs k (L - l0) along each edge
-        const double sp = a.phi_m + a.k_spring * (Lp - a.l0[beg + k]);
-        const double sm = a.phi_m + a.k_spring * (Lm - a.l0[beg + km]);
-        double Fx = sp * tpx + sm * tmx;
-        double Fy = sp * tpy + sm * tmy;
+        const double sp = (a.phi_m + a.k_spring * (Lp - a.l0[beg + k])) / Lp;
+        const double sm = (a.phi_m + a.k_spring * (Lm - a.l0[beg + km])) / Lm;
+        double Fx = sp * dpx + sm * dmx;
+        double Fy = sp * dpy + sm * dmy;
         // area pressure: dA/dX_k = ((y_{k+1} - y_{k-1}) / 2, (x_{k-1} - x_{k+1}) / 2)
         Fx += s_area * 0.5 * (Xp.y - Xm.y);
         Fy += s_area * 0.5 * (Xm.x - Xp.x);
         const int node = beg + k;
-        int key = 0;
+        const int s = a.slot[node];
         if (finite2(X.x, X.y) && finite2(Fx, Fy)) {
-            a.F[node] = make_float2((float)Fx, (float)Fy);
-            key = bin_key(X.x, X.y, a.nx, a.ny, a.walls, a.ntx);
+            const double fx = floor(X.x), fy = floor(X.y);
+            int i0, j0;
+            stencil_origin(X.x, X.y, a.nx, a.ny, a.walls, i0, j0);
+            a.rec[s] = make_float4((float)(X.x - fx), (float)(X.y - fy), (float)Fx, (float)Fy);
+            a.rec_ij[s] = pack_ij(i0, j0);
+            if (!within_margin(i0, j0, a.key[node], a.nx, a.ny, a.walls, a.ntx)) flags |= ERR_MARGIN;
         } else {
-            a.F[node] = make_float2(0.0f, 0.0f);
-            atomicOr(a.err, 1);
+            a.rec[s] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            a.rec_ij[s] = 0;
+            flags |= ERR_NONFINITE;
         }
-        a.key[node] = key;
-        a.rank[node] = atomicAdd(&a.bin_count[key], 1);
     }
+    if (flags) atomicOr(a.err, flags);
+
+    if (a.raster) raster_cell(xs, n, (uint16_t)(c + 1), a.mask, a.nx, a.ny, a.walls, bm, RASTER_WORDS_FUSED, red);
 }
 
-// Exclusive scan of the per-tile counts into CSR offsets (one workgroup; runs of
-// SCAN_THREADS * 4 counts per pass with a running carry).
-__global__ __launch_bounds__(SCAN_THREADS) void k_bin_scan(const int* __restrict__ count, int* __restrict__ off,
-                                                           int nbins)
+// ---------------------------------------------------------------------------------------
+// rebinning
+// ---------------------------------------------------------------------------------------
+
+// bin of every node; a wavefront issues one counter increment per distinct bin among its
+// lanes (consecutive nodes of a membrane mostly share a tile) and hands out ranks within it
+__global__ void k_bin_count(BinArgs a)
 {
-    __shared__ int sh[SCAN_THREADS];
-    __shared__ int carry_sh;
-    const int t = threadIdx.x;
-    if (t == 0) carry_sh = 0;
-    __syncthreads();
-    for (int base = 0; base < nbins; base += SCAN_THREADS * 4) {
-        int v[4], s = 0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i = base + t * 4 + q;
-            v[q] = (i < nbins) ? count[i] : 0;
-            s += v[q];
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = l < a.n;
+    int key = -1;
+    if (live) {
+        const double2 X = a.X[l];
+        key = 0;
+        if (finite2(X.x, X.y)) {
+            int i0, j0;
+            stencil_origin(X.x, X.y, a.nx, a.ny, a.walls, i0, j0);
+            key = bin_of(i0, j0, a.ny, a.ntx);
         }
-        sh[t] = s;
-        __syncthreads();
-        // Hillis-Steele inclusive scan of the per-thread sums
-        for (int d = 1; d < SCAN_THREADS; d <<= 1) {
-            const int add = (t >= d) ? sh[t - d] : 0;
-            __syncthreads();
-            sh[t] += add;
-            __syncthreads();
-        }
-        const int carry = carry_sh;
-        int run = carry + sh[t] - s;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int i = base + t * 4 + q;
-            if (i < nbins) off[i] = run;
-            run += v[q];
-        }
-        __syncthreads();
-        if (t == SCAN_THREADS - 1) carry_sh = carry + sh[t];
-        __syncthreads();
     }
-    if (t == 0) off[nbins] = carry_sh;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    unsigned long long todo = __ballot(live);
+    int rank = 0;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int lkey = __shfl(key, leader, 64);
+        const unsigned long long grp = __ballot(live && key == lkey);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&a.count[lkey], __popcll(grp));
+        base = __shfl(base, leader, 64);
+        if (live && key == lkey) rank = base + __popcll(grp & below);
+        todo &= ~grp;
+    }
+    if (live) {
+        a.key[l] = key;
+        a.rank[l] = rank;
+    }
 }
 
-// Node records in bin order: (frac x, frac y, Fx, Fy) and the packed stencil origin.
-__global__ void k_bin_scatter(ScatterArgs a)
+// exclusive scan of the bin counts into offsets; counts are cleared for the next rebinning
+__global__ __launch_bounds__(SCAN_THREADS) void k_bin_scan(BinArgs a)
+{
+    constexpr int CHUNK = SCAN_THREADS * SCAN_PER_THREAD;
+    __shared__ int buf[CHUNK];
+    __shared__ int wsum[SCAN_THREADS / 64];
+    __shared__ int carry_sh;
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    if (t == 0) carry_sh = 0;
+    for (int base = 0; base < a.nbins; base += CHUNK) {
+        for (int i = t; i < CHUNK; i += SCAN_THREADS) {
+            const int b = base + i;
+            int v = 0;
+            if (b < a.nbins) {
+                v = a.count[b];
+                a.count[b] = 0;
+            }
+            buf[i] = v;
+        }
+        __syncthreads();
+        int s = 0;
+        for (int q = 0; q < SCAN_PER_THREAD; ++q) s += buf[t * SCAN_PER_THREAD + q];
+        // inclusive scan across the wavefront
+        int incl = s;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int up = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += up;
+        }
+        if (lane == 63) wsum[wid] = incl;
+        __syncthreads();
+        int pre = carry_sh;
+        for (int w = 0; w < wid; ++w) pre += wsum[w];
+        int run = pre + incl - s;
+        for (int q = 0; q < SCAN_PER_THREAD; ++q) {
+            const int v = buf[t * SCAN_PER_THREAD + q];
+            buf[t * SCAN_PER_THREAD + q] = run;
+            run += v;
+        }
+        __syncthreads();
+        for (int i = t; i < CHUNK; i += SCAN_THREADS) {
+            const int b = base + i;
+            if (b < a.nbins) a.off[b] = buf[i];
+        }
+        if (t == SCAN_THREADS - 1) carry_sh = run;
+        __syncthreads();
+    }
+    if (t == 0) a.off[a.nbins] = carry_sh;
+}
+
+// new slot of every node; its record moves there from the old slot when copy is set
+__global__ void k_bin_scatter(BinArgs a)
 {
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= a.n) return;
-    const double2 X = a.X[l];
-    const int slot = a.bin_off[a.key[l]] + a.rank[l];
-    float4 r = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    int ij = 0;
-    if (finite2(X.x, X.y)) {
-        const double fx = floor(X.x), fy = floor(X.y);
-        const float2 F = a.F[l];
-        r = make_float4((float)(X.x - fx), (float)(X.y - fy), F.x, F.y);
-        const int i0 = wrap_ll((long long)fx - 1, a.nx);
-        long long j0 = (long long)fy - 1;
-        if (a.walls) {
-            if (j0 < -4) j0 = -4;
-            if (j0 > a.ny) j0 = a.ny;
-        } else {
-            j0 = wrap_ll(j0, a.ny);
-        }
-        ij = (i0 & 0xFFFF) | (int)((unsigned)(j0 & 0xFFFF) << 16);
+    const int s = a.off[a.key[l]] + a.rank[l];
+    if (a.copy) {
+        const int o = a.slot[l];
+        a.rec_new[s] = a.rec_old[o];
+        a.ij_new[s] = a.ij_old[o];
     }
-    a.rec[slot] = r;
-    a.rec_ij[slot] = ij;
+    a.slot[l] = s;
+}
+
+// forces of every node, read back from the records (inspection)
+__global__ void k_forces_out(const int* __restrict__ slot, const float4* __restrict__ rec, float2* __restrict__ F,
+                             int64_t n)
+{
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n) return;
+    const float4 r = rec[slot[l]];
+    F[l] = make_float2(r.z, r.w);
 }
 
 __global__ void k_fill_i32(int* p, int64_t n, int v)
@@ -218,17 +284,20 @@ hipError_t launch_membrane(lbib_ctx* c, const MembraneArgs& a)
     return hipGetLastError();
 }
 
-hipError_t launch_scan(lbib_ctx* c)
+hipError_t launch_rebin(lbib_ctx* c, const BinArgs& a, int which)
 {
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(SCAN_THREADS), 0, c->stream, (const int*)c->d_bin_count,
-                       c->d_bin_off, c->nbins);
+    const unsigned nb = (unsigned)((a.n + 255) / 256);
+    if (which == 0) hipLaunchKernelGGL(k_bin_count, dim3(nb), dim3(256), 0, c->stream, a);
+    else if (which == 1) hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(SCAN_THREADS), 0, c->stream, a);
+    else hipLaunchKernelGGL(k_bin_scatter, dim3(nb), dim3(256), 0, c->stream, a);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(lbib_ctx* c, const ScatterArgs& a)
+hipError_t launch_forces_out(lbib_ctx* c, float2* F)
 {
-    const unsigned nb = (unsigned)((a.n + 255) / 256);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(nb), dim3(256), 0, c->stream, a);
+    const unsigned nb = (unsigned)((c->n_nodes + 255) / 256);
+    hipLaunchKernelGGL(k_forces_out, dim3(nb), dim3(256), 0, c->stream, (const int*)c->d_slot,
+                       (const float4*)c->d_rec[c->rec_cur], F, c->n_nodes);
     return hipGetLastError();
 }
 

@@ -5,6 +5,12 @@
 // [q][ny][nx] (x fastest).  The arrays hold post-collision, pre-streaming values; a
 // lattice pass pulls f_i(x) = f*_i(x - v_i) (or, across a wall, f*_opp(i)(x)), collides,
 // and stores f*_i(x) in place of x in the other buffer.
+//
+// Immersed-boundary nodes are filed in bins, one per lattice tile, by the tile of their
+// stencil origin (floor(X) - 1) at the last rebinning.  A node may drift up to BIN_MARGIN
+// lattice units from its bin's tile before the next rebinning (done every REBIN_PERIOD
+// steps); a lattice tile therefore reads every bin whose tile, widened by the margin,
+// reaches its stencil footprint.  The membrane kernel refreshes each node's record in place.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,17 +23,26 @@ constexpr int TILE_X = 64;
 constexpr int TILE_Y = 4;
 constexpr int TILE_N = TILE_X * TILE_Y;
 
+constexpr int BIN_MARGIN = 2;        // lattice units a node may drift from its bin's tile
+constexpr int REBIN_PERIOD = 8;      // steps between rebinnings
+
 constexpr int MEMBRANE_THREADS = 256;
 constexpr int MAX_CELL_NODES = 4096;            // LDS holds one cell's positions as double2
 constexpr int RASTER_THREADS = 256;
-constexpr int RASTER_LDS_WORDS = 8192;          // 32 KB bitmap per raster pass
+constexpr int RASTER_WORDS_FUSED = 1024;        // 4 KB bitmap inside the membrane kernel
+constexpr int RASTER_WORDS = 8192;              // 32 KB bitmap in the standalone rasteriser
 constexpr int SCAN_THREADS = 1024;
+constexpr int SCAN_PER_THREAD = 8;
 
 // Spread forces are summed in 64-bit fixed point (integer addition is associative, so the
 // sum does not depend on the order the nodes arrive in): value = integer * 2^-48.
 constexpr float FIX_SCALE = 281474976710656.0f;          // 2^48
 constexpr float FIX_INV = 1.0f / 281474976710656.0f;     // 2^-48 (exact)
 constexpr float FIX_CLAMP = 16384.0f;                    // |contribution| bound, keeps sums in range
+
+// error flags (device int, OR-ed)
+constexpr int ERR_NONFINITE = 1;     // a node position or force became non-finite
+constexpr int ERR_MARGIN = 2;        // a node drifted beyond its bin margin
 
 struct LatticeArgs {
     const float* __restrict__ fsrc;   // 9 planes
@@ -42,11 +57,10 @@ struct LatticeArgs {
     float rc[2][4];
     float bodyx, bodyy;
     int kernel;
-    // immersed boundary: node records binned by lattice tile of their stencil origin
+    // immersed boundary: node records binned by lattice tile
     const int* __restrict__ bin_off;   // [nbins + 1]
     const float4* __restrict__ rec;    // (sx, sy, Fx, Fy) per binned node
     const int* __restrict__ rec_ij;    // packed stencil origin (i0 | j0 << 16)
-    int* __restrict__ bin_count;       // zeroed by the tile that owns the bin
     float* __restrict__ uband;         // [2][ny][nx], written where a node stencil reaches
     uint16_t* __restrict__ mask;       // domain IDs; read, then cleared for the next raster
     // inspection output (spread field only)
@@ -56,31 +70,37 @@ struct LatticeArgs {
 struct MembraneArgs {
     const int* __restrict__ off;
     double2* __restrict__ X;
-    float2* __restrict__ F;
     const double* __restrict__ l0;
     const double* __restrict__ A0;
     double* __restrict__ area;
     const float* __restrict__ uband;
+    const int* __restrict__ slot;      // record slot of each node
+    const int* __restrict__ key;       // bin of each node at the last rebinning
+    float4* __restrict__ rec;
+    int* __restrict__ rec_ij;
+    uint16_t* __restrict__ mask;       // written when raster != 0
+    int* __restrict__ err;
     int64_t nn;
     int nx, ny, walls, kernel, ntx, nty;
     double k_spring, phi_m, kappa;
-    int* __restrict__ key;
-    int* __restrict__ rank;
-    int* __restrict__ bin_count;
-    int* __restrict__ err;
     int advect;
+    int raster;
 };
 
-struct ScatterArgs {
+struct BinArgs {
     const double2* __restrict__ X;
-    const float2* __restrict__ F;
-    const int* __restrict__ key;
-    const int* __restrict__ rank;
-    const int* __restrict__ bin_off;
-    float4* __restrict__ rec;
-    int* __restrict__ rec_ij;
+    int* __restrict__ key;
+    int* __restrict__ rank;
+    int* __restrict__ count;           // zeroed by the scan after use
+    int* __restrict__ off;
+    int* __restrict__ slot;
+    const float4* __restrict__ rec_old;
+    const int* __restrict__ ij_old;
+    float4* __restrict__ rec_new;
+    int* __restrict__ ij_new;
     int64_t n;
-    int nx, ny, walls;
+    int nx, ny, walls, ntx, nbins;
+    int copy;                          // 1: move records from their old slots
 };
 
 struct RasterArgs {
@@ -123,20 +143,37 @@ __device__ inline int wrap_ll(long long i, int n)
     return (int)(r < 0 ? r + n : r);
 }
 
-// tile (bin) key of a node's stencil origin; positions are unwrapped in x (and periodic y)
-__device__ inline int bin_key(double x, double y, int nx, int ny, int walls, int ntx)
+// finite and small enough for the integer stencil arithmetic (|coordinate| < 2^40)
+__device__ inline bool finite2(double x, double y)
 {
-    int i0 = wrap_ll((long long)floor(x) - 1, nx);
+    return fabs(x) < 1099511627776.0 && fabs(y) < 1099511627776.0;
+}
+
+// stencil origin of a node: column wrapped into [0, nx); row wrapped (periodic) or, next to
+// walls, clamped to [-4, ny] (rows outside the lattice receive nothing)
+__device__ inline void stencil_origin(double x, double y, int nx, int ny, int walls, int& i0, int& j0)
+{
+    i0 = wrap_ll((long long)floor(x) - 1, nx);
     long long j = (long long)floor(y) - 1;
-    int j0;
-    if (walls) j0 = (int)(j < 0 ? 0 : (j >= ny ? ny - 1 : j));
+    if (walls) j0 = (int)(j < -4 ? -4 : (j > ny ? ny : j));
     else j0 = wrap_ll(j, ny);
-    return (j0 / TILE_Y) * ntx + i0 / TILE_X;
+}
+
+// bin (lattice tile) of a stencil origin; rows beyond a wall go to the edge row of tiles
+__device__ inline int bin_of(int i0, int j0, int ny, int ntx)
+{
+    int jr = j0 < 0 ? 0 : (j0 >= ny ? ny - 1 : j0);
+    return (jr / TILE_Y) * ntx + i0 / TILE_X;
+}
+
+__device__ inline int pack_ij(int i0, int j0)
+{
+    return (i0 & 0xFFFF) | (int)((unsigned)(j0 & 0xFFFF) << 16);
 }
 
 // XCD-aware workgroup order: the dispatcher deals workgroups round-robin over the 8 XCDs;
 // remap so each XCD walks a contiguous run of tiles (neighbouring tiles share cache lines
-// at their x edges, and each XCD has its own L2).
+// at their x edges and read the same node bins, and each XCD has its own L2).
 __device__ inline int xcd_remap(int bid, int nblocks)
 {
     const int NX = 8;

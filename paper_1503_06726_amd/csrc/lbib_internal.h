@@ -49,17 +49,19 @@ struct lbib_ctx {
     int max_cell_nodes = 0;
     int* d_off = nullptr;
     double2* d_X = nullptr;
-    float2* d_F = nullptr;
     double* d_l0 = nullptr;
     double* d_A0 = nullptr;
     double* d_area = nullptr;
-    int* d_key = nullptr;
-    int* d_rank = nullptr;
-    float4* d_rec = nullptr;
-    int* d_rec_ij = nullptr;
-    int* d_bin_count = nullptr;      // [nbins]
+    int* d_key = nullptr;            // bin of each node at the last rebinning
+    int* d_rank = nullptr;           // rank within that bin
+    int* d_slot = nullptr;           // record slot of each node
+    float4* d_rec[2] = {nullptr, nullptr};   // spreading records, current and spare
+    int* d_rec_ij[2] = {nullptr, nullptr};
+    int rec_cur = 0;
+    int* d_bin_count = nullptr;      // [nbins], zero between rebinnings
     int* d_bin_off = nullptr;        // [nbins + 1]
     int* d_err = nullptr;            // device error flags
+    int steps_since_rebin = 0;
 
     // staging
     double* d_stage = nullptr;
@@ -73,8 +75,8 @@ struct lbib_ctx {
     bool timing = false;
     std::vector<lbib::TimedLaunch> pending;
     std::vector<hipEvent_t> free_events;
-    double t_ms[LBIB_K_COUNT] = {0, 0, 0, 0, 0};
-    int64_t t_count[LBIB_K_COUNT] = {0, 0, 0, 0, 0};
+    double t_ms[LBIB_K_COUNT] = {};
+    int64_t t_count[LBIB_K_COUNT] = {};
 };
 
 namespace lbib {
@@ -87,8 +89,8 @@ hipError_t launch_init(lbib_ctx* c, const double* stage_rho, const double* stage
 hipError_t launch_moments(lbib_ctx* c, double* out);
 hipError_t launch_reduce(lbib_ctx* c, double* out_dev);
 hipError_t launch_membrane(lbib_ctx* c, const MembraneArgs& a);
-hipError_t launch_scan(lbib_ctx* c);
-hipError_t launch_scatter(lbib_ctx* c, const ScatterArgs& a);
+hipError_t launch_rebin(lbib_ctx* c, const BinArgs& a, int which);   // 0 count, 1 scan, 2 scatter
+hipError_t launch_forces_out(lbib_ctx* c, float2* F);
 hipError_t launch_raster(lbib_ctx* c, const RasterArgs& a);
 hipError_t launch_fill_i32(lbib_ctx* c, int* p, int64_t n, int v);
 hipError_t launch_fill_u16(lbib_ctx* c, uint16_t* p, int64_t n);

@@ -18,8 +18,8 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5
 PERIODIC, WALLS = 0, 1
 DELTA_COS4, DELTA_PESKIN4 = 0, 1
 REACT_NONE, REACT_SOURCE_DECAY, REACT_SCHNAKENBERG = 0, 1, 2
-K_LATTICE, K_MEMBRANE, K_BIN_SCAN, K_BIN_SCATTER, K_RASTER = range(5)
-KERNEL_NAMES = ["lattice", "membrane", "bin_scan", "bin_scatter", "raster"]
+K_LATTICE, K_MEMBRANE, K_REBIN = range(3)
+KERNEL_NAMES = ["lattice", "membrane", "rebin"]
 
 # every entry point declared in include/lbib.h
 EXPORTS = ["lbib_validate_params", "lbib_validate_cells", "lbib_create", "lbib_set_cells",

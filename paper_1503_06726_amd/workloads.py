@@ -309,3 +309,12 @@ def random_fields(w: Workload, seed: int, amp_rho: float = 1e-3, amp_u: float = 
 
 
 WORKLOADS = {"tiny": tiny_cell, "tissue": tissue, "large": large}
+
+# parity-sized cell cases: ragged lattices, both boundary kinds, both kernels, every force law
+PARITY_CASES = {
+    "tiny": lambda: tiny_cell(),
+    "walls": lambda: small_tissue(stretch=0.9, kappa_area=1e-3, phi_m=1e-3),
+    "periodic": lambda: small_tissue(nx=150, ny=100, n_cells=9, bc_y=PERIODIC, n_species=2, seed=2,
+                                     stretch=1.1),
+    "peskin": lambda: small_tissue(nx=96, ny=70, n_cells=12, delta_kernel=DELTA_PESKIN4, seed=4, stretch=0.95),
+}

@@ -131,7 +131,9 @@ def test_create_rejects_bad_params_before_touching_a_device():
 
 
 def test_workload_inputs_pass_validation():
-    for w in (W.tiny_cell(), W.small_tissue(), W.small_tissue(bc_y=W.PERIODIC, n_species=2, seed=3)):
+    cases = [W.tiny_cell(), W.small_tissue(), W.small_tissue(bc_y=W.PERIODIC, n_species=2, seed=3), W.tissue(),
+             W.large()] + [f() for f in W.PARITY_CASES.values()]
+    for w in cases:
         assert lbib.validate_params(w.params_dict())[0] == lbib.OK
         s, msg = lbib.validate_cells(w.params_dict(), w.offsets, w.xy, w.rest_len, w.rest_area)
         assert s == lbib.OK, msg

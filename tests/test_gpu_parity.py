@@ -103,13 +103,7 @@ def test_lattice_only(bc, S, nx, ny):
 # ------------------------------------------------------------------------------------------
 # membrane rows at identical positions: forces, spreading, domain IDs
 # ------------------------------------------------------------------------------------------
-CELL_CASES = {
-    "tiny": lambda: W.tiny_cell(),
-    "walls": lambda: W.small_tissue(stretch=0.9, kappa_area=1e-3, phi_m=1e-3),
-    "periodic": lambda: W.small_tissue(nx=150, ny=100, n_cells=9, bc_y=W.PERIODIC, n_species=2, seed=2,
-                                       stretch=1.1),
-    "peskin": lambda: W.small_tissue(nx=96, ny=70, n_cells=5, delta_kernel=W.DELTA_PESKIN4, seed=4, stretch=0.95),
-}
+CELL_CASES = W.PARITY_CASES
 
 
 @pytest.mark.parametrize("case", list(CELL_CASES))
