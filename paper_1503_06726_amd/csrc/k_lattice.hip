@@ -95,16 +95,20 @@ __device__ inline unsigned long long to_fixed(float v)
 __device__ inline bool cyc_meet(int a0, int alen, int b0, int blen, int n)
 {
     if (alen + blen > n) return true;
-    const int d = wrap_ll((long long)a0 - b0, n);
+    const int d = wrap_i(a0 - b0, n);
     return d < blen || d + alen > n;
 }
 
-// Spread the binned node forces into this tile's LDS accumulators.  A node filed in bin b
-// has its stencil origin within b's tile widened by BIN_MARGIN; the tile needs every node
-// whose origin lies in [x0 - 3, x1 - 1] x [y0 - 3, y1 - 1], so it reads every bin whose
-// widened tile meets that range (superfluous candidates contribute nothing).
-__device__ inline void spread_tile(const LatticeArgs& a, int tcol, int trow, int x0, int y0,
-                                   unsigned long long* accx, unsigned long long* accy, int* tch)
+constexpr int MAX_RANGES = 25;     // bins read by one tile (at most 5 columns x 5 rows)
+constexpr int SPREAD_UNROLL = 4;   // candidates per thread whose loads are issued together
+
+// Bins a tile reads.  A node filed in bin b has its stencil origin within b's tile widened
+// by BIN_MARGIN; the tile needs every node whose origin lies in [x0 - 3, x1 - 1] x
+// [y0 - 3, y1 - 1], so it reads every bin whose widened tile meets that range (superfluous
+// candidates contribute nothing).  Lane q < (returned count) of the first wavefront loads
+// bin q's record range; its inclusive prefix over q goes to rpre, the range start to rbeg.
+__device__ inline void spread_ranges(const LatticeArgs& a, int tcol, int trow, int x0, int y0, int* rbeg,
+                                     int* rpre)
 {
     const int t = threadIdx.x;
     const int M = BIN_MARGIN;
@@ -113,7 +117,7 @@ __device__ inline void spread_tile(const LatticeArgs& a, int tcol, int trow, int
     {
         const int nc = a.ntx <= 5 ? a.ntx : 5;
         for (int q = 0; q < nc; ++q) {
-            const int cc = a.ntx <= 5 ? q : wrap_ll((long long)tcol - 2 + q, a.ntx);
+            const int cc = a.ntx <= 5 ? q : wrap_i(tcol - 2 + q, a.ntx);
             const int bx0 = cc * TILE_X, bw = min(TILE_X, a.nx - bx0);
             if (cyc_meet(bx0 - M, bw + 2 * M, x0 - 3, x1 - x0 + 3, a.nx)) cols[ncol++] = cc;
         }
@@ -128,56 +132,97 @@ __device__ inline void spread_tile(const LatticeArgs& a, int tcol, int trow, int
     } else {
         const int nr = a.nty <= 5 ? a.nty : 5;
         for (int q = 0; q < nr; ++q) {
-            const int rr = a.nty <= 5 ? q : wrap_ll((long long)trow - 2 + q, a.nty);
+            const int rr = a.nty <= 5 ? q : wrap_i(trow - 2 + q, a.nty);
             const int by0 = rr * TILE_Y, bh = min(TILE_Y, a.ny - by0);
             if (cyc_meet(by0 - M, bh + 2 * M, y0 - 3, y1 - y0 + 3, a.ny)) rows[nrow++] = rr;
         }
     }
-    for (int ir = 0; ir < nrow; ++ir) {
-        for (int ic = 0; ic < ncol; ++ic) {
-            const int b = rows[ir] * a.ntx + cols[ic];
-            const int beg = a.bin_off[b], end = a.bin_off[b + 1];
-            for (int k = beg + t; k < end; k += TILE_N) {
-                const int ij = a.rec_ij[k];
-                const int i0 = ij & 0xFFFF;
-                const int j0 = ij >> 16;              // sign-extended 16-bit row
-                // quick rejection: does the 4x4 stencil at (i0, j0) reach the tile at all?
-                int dx = i0 - x0 + 3;                 // i0, x0 in [0, nx): one wrap at most
-                if (dx < 0) dx += a.nx;
-                else if (dx >= a.nx) dx -= a.nx;
-                if (dx >= TILE_X + 3) continue;
-                int dy = j0 - y0 + 3;
-                if (!a.walls) {
-                    if (dy < 0) dy += a.ny;
-                    else if (dy >= a.ny) dy -= a.ny;
-                }
-                if (dy < 0 || dy >= TILE_Y + 3) continue;
-                const float4 r = a.rec[k];
-                float wx[4], wy[4];
-                delta_weights(a.kernel, r.x, wx);
-                delta_weights(a.kernel, r.y, wy);
+    if (t < 64) {
+        const int nsel = nrow * ncol;
+        int beg = 0, len = 0;
+        if (t < nsel) {
+            int r = 0, cc = 0;
 #pragma unroll
-                for (int bb = 0; bb < 4; ++bb) {
-                    int j = j0 + bb;
-                    if (a.walls) {
-                        if (j < 0 || j >= a.ny) continue;
-                    } else if (j >= a.ny) {
-                        j -= a.ny;
-                    }
-                    const int ly = j - y0;
-                    if ((unsigned)ly >= (unsigned)TILE_Y) continue;
+            for (int q = 0; q < 5; ++q)
+                if (q == t / ncol) r = rows[q];
 #pragma unroll
-                    for (int aa = 0; aa < 4; ++aa) {
-                        int i = i0 + aa;
-                        if (i >= a.nx) i -= a.nx;
-                        const int lx = i - x0;
-                        if ((unsigned)lx >= (unsigned)TILE_X) continue;
-                        const float w = wx[aa] * wy[bb];
-                        const int o = ly * TILE_X + lx;
-                        atomicAdd(&accx[o], to_fixed(w * r.z));
-                        atomicAdd(&accy[o], to_fixed(w * r.w));
-                        tch[o] = 1;
-                    }
+            for (int q = 0; q < 5; ++q)
+                if (q == t % ncol) cc = cols[q];
+            const int b = r * a.ntx + cc;
+            beg = a.bin_off[b];
+            len = a.bin_off[b + 1] - beg;
+        }
+        int incl = len;
+        for (int o = 1; o < 32; o <<= 1) {
+            const int up = __shfl_up(incl, o, 64);
+            if (t >= o) incl += up;
+        }
+        if (t < MAX_RANGES) {
+            rbeg[t] = beg;
+            rpre[t] = incl;
+        }
+    }
+}
+
+// Spread the candidates into this tile's LDS accumulators (after spread_ranges + barrier).
+__device__ inline void spread_tile(const LatticeArgs& a, int x0, int y0, const int* rbeg, const int* rpre,
+                                   unsigned long long* accx, unsigned long long* accy, int* tch)
+{
+    const int t = threadIdx.x;
+    const int x1 = min(x0 + TILE_X, a.nx), y1 = min(y0 + TILE_Y, a.ny);
+    const int total = rpre[MAX_RANGES - 1];
+    for (int base = 0; base < total; base += SPREAD_UNROLL * TILE_N) {
+        int ij[SPREAD_UNROLL];
+        float4 rc[SPREAD_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SPREAD_UNROLL; ++u) {
+            const int k = base + u * TILE_N + t;
+            ij[u] = 0x7FFF7FFF;                          // far away: rejected below
+            if (k < total) {
+                int q = 0;
+                while (k >= rpre[q]) ++q;
+                const int idx = rbeg[q] + k - (q ? rpre[q - 1] : 0);
+                ij[u] = a.rec_ij[idx];
+                rc[u] = a.rec[idx];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SPREAD_UNROLL; ++u) {
+            const int i0 = ij[u] & 0xFFFF;
+            const int j0 = ij[u] >> 16;                  // sign-extended 16-bit row
+            // tile coordinates of the four stencil columns and rows (each wrapped on its own,
+            // so a stencil that wraps onto the same tile twice is still counted correctly)
+            int lx[4], ly[4];
+            unsigned hx = 0u, hy = 0u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                int i = i0 + q;
+                if (i >= a.nx) i -= a.nx;
+                lx[q] = i - x0;
+                if ((unsigned)lx[q] < (unsigned)(x1 - x0)) hx |= 1u << q;
+                int j = j0 + q;
+                bool ok = true;
+                if (a.walls) ok = j >= 0 && j < a.ny;
+                else if (j >= a.ny) j -= a.ny;
+                ly[q] = j - y0;
+                if (ok && (unsigned)ly[q] < (unsigned)(y1 - y0)) hy |= 1u << q;
+            }
+            if (!hx || !hy) continue;
+            const float4 r = rc[u];
+            float wx[4], wy[4];
+            delta_weights(a.kernel, r.x, wx);
+            delta_weights(a.kernel, r.y, wy);
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) {
+                if (!((hy >> bb) & 1u)) continue;
+#pragma unroll
+                for (int aa = 0; aa < 4; ++aa) {
+                    if (!((hx >> aa) & 1u)) continue;
+                    const float w = wx[aa] * wy[bb];
+                    const int o = ly[bb] * TILE_X + lx[aa];
+                    atomicAdd(&accx[o], to_fixed(w * r.z));
+                    atomicAdd(&accy[o], to_fixed(w * r.w));
+                    tch[o] = 1;
                 }
             }
         }
@@ -197,14 +242,10 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
 
     __shared__ unsigned long long accx[NODES ? TILE_N : 1], accy[NODES ? TILE_N : 1];
     __shared__ int tch[NODES ? TILE_N : 1];
-    if constexpr (NODES) {
-        accx[t] = 0ull;
-        accy[t] = 0ull;
-        tch[t] = 0;
-        __syncthreads();
-    }
+    __shared__ int rbeg[NODES ? MAX_RANGES : 1], rpre[NODES ? MAX_RANGES : 1];
 
     // issue the population loads first: they are in flight while the forces are spread
+    // (a workgroup barrier waits for LDS operations only)
     Nbr n;
     int64_t o = 0;
     float f[9];
@@ -222,7 +263,12 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
     float ex = a.bodyx, ey = a.bodyy;
     bool touched = false;
     if constexpr (NODES) {
-        spread_tile(a, tcol, trow, x0, y0, accx, accy, tch);
+        accx[t] = 0ull;
+        accy[t] = 0ull;
+        tch[t] = 0;
+        spread_ranges(a, tcol, trow, x0, y0, rbeg, rpre);
+        __syncthreads();
+        spread_tile(a, x0, y0, rbeg, rpre, accx, accy, tch);
         __syncthreads();
         ex += __ll2float_rn((long long)accx[t]) * FIX_INV;
         ey += __ll2float_rn((long long)accy[t]) * FIX_INV;
@@ -307,11 +353,13 @@ __global__ __launch_bounds__(TILE_N) void k_spread_inspect(LatticeArgs a)
     const int x = x0 + (t % TILE_X), y = y0 + (t / TILE_X);
     __shared__ unsigned long long accx[TILE_N], accy[TILE_N];
     __shared__ int tch[TILE_N];
+    __shared__ int rbeg[MAX_RANGES], rpre[MAX_RANGES];
     accx[t] = 0ull;
     accy[t] = 0ull;
     tch[t] = 0;
+    if (a.bin_off) spread_ranges(a, tcol, trow, x0, y0, rbeg, rpre);
     __syncthreads();
-    if (a.bin_off) spread_tile(a, tcol, trow, x0, y0, accx, accy, tch);
+    if (a.bin_off) spread_tile(a, x0, y0, rbeg, rpre, accx, accy, tch);
     __syncthreads();
     if (x >= a.nx || y >= a.ny) return;
     const int64_t o = (int64_t)y * a.nx + x;

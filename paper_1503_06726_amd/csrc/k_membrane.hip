@@ -16,33 +16,37 @@
 
 namespace lbib {
 
+// u at a node (Eq. conversion2 over the 4x4 stencil); positions satisfy finite2
 __device__ inline float2 interp_u(const MembraneArgs& a, double X, double Y)
 {
     const double fx = floor(X), fy = floor(Y);
     float wx[4], wy[4];
     delta_weights(a.kernel, (float)(X - fx), wx);
     delta_weights(a.kernel, (float)(Y - fy), wy);
-    const int i0 = wrap_ll((long long)fx - 1, a.nx);
-    const long long j0 = (long long)fy - 1;
+    const int i0 = wrap_i((int)fx - 1, a.nx);
+    const int j0 = (int)fy - 1;
+    int col[4];
+#pragma unroll
+    for (int aa = 0; aa < 4; ++aa) {
+        int i = i0 + aa;
+        if (i >= a.nx) i -= a.nx;
+        col[aa] = i;
+    }
     float ux = 0.0f, uy = 0.0f;
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb) {
-        int j;
+        int j = j0 + bb;
         if (a.walls) {
-            const long long jj = j0 + bb;
-            if (jj < 0 || jj >= a.ny) continue;
-            j = (int)jj;
+            if (j < 0 || j >= a.ny) continue;
         } else {
-            j = wrap_ll(j0 + bb, a.ny);
+            j = wrap_i(j, a.ny);
         }
         const float* row = a.uband + (int64_t)j * a.nx;
         float sx = 0.0f, sy = 0.0f;
 #pragma unroll
         for (int aa = 0; aa < 4; ++aa) {
-            int i = i0 + aa;
-            if (i >= a.nx) i -= a.nx;
-            sx += wx[aa] * row[i];
-            sy += wx[aa] * row[a.nn + i];
+            sx += wx[aa] * row[col[aa]];
+            sy += wx[aa] * row[a.nn + col[aa]];
         }
         ux += wy[bb] * sx;
         uy += wy[bb] * sy;
@@ -62,15 +66,17 @@ __device__ inline bool within_margin(int i0, int j0, int key, int nx, int ny, in
     const int bc = key % ntx, br = key / ntx;
     const int bx0 = bc * TILE_X, bw = min(TILE_X, nx - bx0);
     const int by0 = br * TILE_Y, bh = min(TILE_Y, ny - by0);
-    const int dx = wrap_ll((long long)i0 - bx0 + BIN_MARGIN, nx);
+    const int dx = wrap_i(i0 - bx0 + BIN_MARGIN, nx);
     if (bw + 2 * BIN_MARGIN < nx && dx > bw - 1 + 2 * BIN_MARGIN) return false;
     if (walls) {
         const int jr = j0 < 0 ? 0 : (j0 >= ny ? ny - 1 : j0);
         return jr >= by0 - BIN_MARGIN && jr <= by0 + bh - 1 + BIN_MARGIN;
     }
-    const int dy = wrap_ll((long long)j0 - by0 + BIN_MARGIN, ny);
+    const int dy = wrap_i(j0 - by0 + BIN_MARGIN, ny);
     return !(bh + 2 * BIN_MARGIN < ny && dy > bh - 1 + 2 * BIN_MARGIN);
 }
+
+constexpr int MEM_UNROLL = 4;     // nodes per thread whose loads are issued together
 
 __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
 {
@@ -82,19 +88,30 @@ __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
     const int beg = a.off[c];
     const int n = a.off[c + 1] - beg;
 
-    for (int k = t; k < n; k += MEMBRANE_THREADS) {
-        double2 X = a.X[beg + k];
-        if (a.advect && finite2(X.x, X.y)) {
-            const float2 U = interp_u(a, X.x, X.y);
-            X.x += (double)U.x;
-            X.y += (double)U.y;
-            a.X[beg + k] = X;
+    // 1. interpolate and move
+    for (int base = 0; base < n; base += MEM_UNROLL * MEMBRANE_THREADS) {
+        double2 X[MEM_UNROLL];
+#pragma unroll
+        for (int u = 0; u < MEM_UNROLL; ++u) {
+            const int k = base + u * MEMBRANE_THREADS + t;
+            if (k < n) X[u] = a.X[beg + k];
         }
-        xs[k] = X;
+#pragma unroll
+        for (int u = 0; u < MEM_UNROLL; ++u) {
+            const int k = base + u * MEMBRANE_THREADS + t;
+            if (k >= n) continue;
+            if (a.advect && finite2(X[u].x, X[u].y)) {
+                const float2 U = interp_u(a, X[u].x, X[u].y);
+                X[u].x += (double)U.x;
+                X[u].y += (double)U.y;
+                a.X[beg + k] = X[u];
+            }
+            xs[k] = X[u];
+        }
     }
     __syncthreads();
 
-    // shoelace area about the first node (translation invariant, less cancellation)
+    // 2. shoelace area about the first node (translation invariant, less cancellation)
     const double ox = xs[0].x, oy = xs[0].y;
     double part = 0.0;
     for (int k = t; k < n; k += MEMBRANE_THREADS) {
@@ -110,39 +127,57 @@ __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
     if (t == 0) a.area[c] = A;
     const double s_area = a.kappa * (a.A0[c] - A);
 
+    // 3. forces and spreading records
     int flags = 0;
-    for (int k = t; k < n; k += MEMBRANE_THREADS) {
-        const int kp = (k + 1 == n) ? 0 : k + 1;
-        const int km = (k == 0) ? n - 1 : k - 1;
-        const double2 X = xs[k], Xp = xs[kp], Xm = xs[km];
-        const double dpx = Xp.x - X.x, dpy = Xp.y - X.y;
-        const double dmx = Xm.x - X.x, dmy = Xm.y - X.y;
-        const double Lp = sqrt(dpx * dpx + dpy * dpy), Lm = sqrt(dmx * dmx + dmy * dmy);
-        // tension phi_m along both edges; springs k (L - l0) along each edge
-        const double sp = (a.phi_m + a.k_spring * (Lp - a.l0[beg + k])) / Lp;
-        const double sm = (a.phi_m + a.k_spring * (Lm - a.l0[beg + km])) / Lm;
-        double Fx = sp * dpx + sm * dmx;
-        double Fy = sp * dpy + sm * dmy;
-        // area pressure: dA/dX_k = ((y_{k+1} - y_{k-1}) / 2, (x_{k-1} - x_{k+1}) / 2)
-        Fx += s_area * 0.5 * (Xp.y - Xm.y);
-        Fy += s_area * 0.5 * (Xm.x - Xp.x);
-        const int node = beg + k;
-        const int s = a.slot[node];
-        if (finite2(X.x, X.y) && finite2(Fx, Fy)) {
-            const double fx = floor(X.x), fy = floor(X.y);
-            int i0, j0;
-            stencil_origin(X.x, X.y, a.nx, a.ny, a.walls, i0, j0);
-            a.rec[s] = make_float4((float)(X.x - fx), (float)(X.y - fy), (float)Fx, (float)Fy);
-            a.rec_ij[s] = pack_ij(i0, j0);
-            if (!within_margin(i0, j0, a.key[node], a.nx, a.ny, a.walls, a.ntx)) flags |= ERR_MARGIN;
-        } else {
-            a.rec[s] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            a.rec_ij[s] = 0;
-            flags |= ERR_NONFINITE;
+    for (int base = 0; base < n; base += MEM_UNROLL * MEMBRANE_THREADS) {
+        double lp[MEM_UNROLL], lm[MEM_UNROLL];
+        int sl[MEM_UNROLL], ky[MEM_UNROLL];
+#pragma unroll
+        for (int u = 0; u < MEM_UNROLL; ++u) {
+            const int k = base + u * MEMBRANE_THREADS + t;
+            if (k >= n) continue;
+            const int km = (k == 0) ? n - 1 : k - 1;
+            lp[u] = a.l0[beg + k];
+            lm[u] = a.l0[beg + km];
+            sl[u] = a.slot[beg + k];
+            ky[u] = a.key[beg + k];
+        }
+#pragma unroll
+        for (int u = 0; u < MEM_UNROLL; ++u) {
+            const int k = base + u * MEMBRANE_THREADS + t;
+            if (k >= n) continue;
+            const int kp = (k + 1 == n) ? 0 : k + 1;
+            const int km = (k == 0) ? n - 1 : k - 1;
+            const double2 X = xs[k], Xp = xs[kp], Xm = xs[km];
+            const double dpx = Xp.x - X.x, dpy = Xp.y - X.y;
+            const double dmx = Xm.x - X.x, dmy = Xm.y - X.y;
+            const double Lp = sqrt(dpx * dpx + dpy * dpy), Lm = sqrt(dmx * dmx + dmy * dmy);
+            // tension phi_m along both edges; springs k (L - l0) along each edge
+            const double sp = (a.phi_m + a.k_spring * (Lp - lp[u])) / Lp;
+            const double sm = (a.phi_m + a.k_spring * (Lm - lm[u])) / Lm;
+            double Fx = sp * dpx + sm * dmx;
+            double Fy = sp * dpy + sm * dmy;
+            // area pressure: dA/dX_k = ((y_{k+1} - y_{k-1}) / 2, (x_{k-1} - x_{k+1}) / 2)
+            Fx += s_area * 0.5 * (Xp.y - Xm.y);
+            Fy += s_area * 0.5 * (Xm.x - Xp.x);
+            const int s = sl[u];
+            if (finite2(X.x, X.y) && finite2(Fx, Fy)) {
+                const double fx = floor(X.x), fy = floor(X.y);
+                int i0, j0;
+                stencil_origin(X.x, X.y, a.nx, a.ny, a.walls, i0, j0);
+                a.rec[s] = make_float4((float)(X.x - fx), (float)(X.y - fy), (float)Fx, (float)Fy);
+                a.rec_ij[s] = pack_ij(i0, j0);
+                if (!within_margin(i0, j0, ky[u], a.nx, a.ny, a.walls, a.ntx)) flags |= ERR_MARGIN;
+            } else {
+                a.rec[s] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                a.rec_ij[s] = 0;
+                flags |= ERR_NONFINITE;
+            }
         }
     }
     if (flags) atomicOr(a.err, flags);
 
+    // 4. domain IDs of the new positions
     if (a.raster) raster_cell(xs, n, (uint16_t)(c + 1), a.mask, a.nx, a.ny, a.walls, bm, RASTER_WORDS_FUSED, red);
 }
 

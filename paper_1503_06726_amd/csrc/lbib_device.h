@@ -137,26 +137,36 @@ __device__ inline void delta_weights(int kernel, float s, float w[4])
     }
 }
 
-__device__ inline int wrap_ll(long long i, int n)
+// i mod n for 32-bit i; the common case (one period off at most) avoids a division
+__device__ inline int wrap_i(int i, int n)
 {
-    long long r = i % n;
-    return (int)(r < 0 ? r + n : r);
+    if (i >= n) {
+        i -= n;
+        if (i >= n) i %= n;
+    } else if (i < 0) {
+        i += n;
+        if (i < 0) {
+            i %= n;
+            if (i < 0) i += n;
+        }
+    }
+    return i;
 }
 
-// finite and small enough for the integer stencil arithmetic (|coordinate| < 2^40)
+// finite and small enough for 32-bit stencil arithmetic (|coordinate| < 2^30)
 __device__ inline bool finite2(double x, double y)
 {
-    return fabs(x) < 1099511627776.0 && fabs(y) < 1099511627776.0;
+    return fabs(x) < 1073741824.0 && fabs(y) < 1073741824.0;
 }
 
-// stencil origin of a node: column wrapped into [0, nx); row wrapped (periodic) or, next to
-// walls, clamped to [-4, ny] (rows outside the lattice receive nothing)
+// stencil origin of a node (finite2 positions): column wrapped into [0, nx); row wrapped
+// (periodic) or, next to walls, clamped to [-4, ny] (rows outside the lattice receive nothing)
 __device__ inline void stencil_origin(double x, double y, int nx, int ny, int walls, int& i0, int& j0)
 {
-    i0 = wrap_ll((long long)floor(x) - 1, nx);
-    long long j = (long long)floor(y) - 1;
-    if (walls) j0 = (int)(j < -4 ? -4 : (j > ny ? ny : j));
-    else j0 = wrap_ll(j, ny);
+    i0 = wrap_i((int)floor(x) - 1, nx);
+    const int j = (int)floor(y) - 1;
+    if (walls) j0 = j < -4 ? -4 : (j > ny ? ny : j);
+    else j0 = wrap_i(j, ny);
 }
 
 // bin (lattice tile) of a stencil origin; rows beyond a wall go to the edge row of tiles

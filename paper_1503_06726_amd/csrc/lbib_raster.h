@@ -111,19 +111,24 @@ __device__ inline void raster_cell(const double2* P, int n, uint16_t id, uint16_
             }
         }
         __syncthreads();
-        for (int i = t; i < rows * W; i += nt) {
-            const int rr = i / W, col = i - rr * W;
-            if (!((bm[rr * WW + (col >> 5)] >> (col & 31)) & 1u)) continue;
-            const long long py = ry0 + r0 + rr;
+        // one wavefront per row, lanes along the row
+        const int cw = wrap_i((int)cx0, nx);
+        for (int rr = wid; rr < rows; rr += nt >> 6) {
+            const int py = (int)(ry0 + r0 + rr);
             int j;
             if (walls) {
                 if (py < 0 || py >= ny) continue;
-                j = (int)py;
+                j = py;
             } else {
-                j = wrap_ll(py, ny);
+                j = wrap_i(py, ny);
             }
-            const int ix = wrap_ll(cx0 + col, nx);
-            mask[(int64_t)j * nx + ix] = id;
+            uint16_t* row = mask + (int64_t)j * nx;
+            for (int col = lane; col < W; col += 64) {
+                if (!((bm[rr * WW + (col >> 5)] >> (col & 31)) & 1u)) continue;
+                int ix = cw + col;
+                if (ix >= nx) ix -= nx;
+                row[ix] = id;
+            }
         }
         __syncthreads();
     }
