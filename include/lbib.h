@@ -63,7 +63,11 @@ enum { LBIB_REACT_NONE = 0,
        LBIB_REACT_SCHNAKENBERG = 2 }; /* species 0: R = c[2] (c[0] - u + u^2 v),
                                          species 1: R = c[2] (c[1] - u^2 v), u = phi_0, v = phi_1;
                                          both species must name it, with equal c[0..2] */
-enum { LBIB_STORAGE_FP32 = 0 };       /* populations stored as FP32 deviations from rest */
+/* Population storage (collision always in FP32).  Populations are kept as deviations from
+ * rest, f_i - w_i rho0 and g_i - w_i phi_ref.  FP16 and BF16 store the deviation divided by
+ * w_i and multiplied by 2^10, which keeps FP16 clear of its subnormal range; FP16 then holds
+ * |deviation / w_i| up to 63. */
+enum { LBIB_STORAGE_FP32 = 0, LBIB_STORAGE_FP16 = 1, LBIB_STORAGE_BF16 = 2 };
 
 typedef struct {
     double D;          /* diffusivity, > 0; relaxation time tau_D = 3 D + 1/2 */
@@ -84,7 +88,7 @@ typedef struct {
     double phi_m;            /* constant membrane tension (0 disables) */
     double kappa_area;       /* area-pressure stiffness: energy kappa_A (A - A0)^2 / 2 (0 disables) */
     int32_t n_species;       /* 0, 1 or 2 */
-    int32_t storage;         /* LBIB_STORAGE_FP32 */
+    int32_t storage;         /* LBIB_STORAGE_* */
     lbib_species species[2];
 } lbib_params;
 

@@ -298,8 +298,11 @@ void free_all(lbib_ctx* c)
     free_nodes(c);
     const size_t nn = (size_t)c->nn;
     for (int b = 0; b < 2; ++b) {
-        dev_free(c, c->f[b], 9 * nn);
-        dev_free(c, c->g[b], 5 * (size_t)c->S * nn);
+        char* fb = (char*)c->f[b];
+        char* gb = (char*)c->g[b];
+        dev_free(c, fb, 9 * nn * c->pop_bytes);
+        dev_free(c, gb, 5 * (size_t)c->S * nn * c->pop_bytes);
+        c->f[b] = c->g[b] = nullptr;
     }
     dev_free(c, c->uband, 2 * nn);
     dev_free(c, c->mask, nn);
@@ -415,9 +418,16 @@ lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out)
     c->partial_count = 4096;
     const size_t nn = (size_t)c->nn;
     lbib_status s = LBIB_OK;
+    c->pop_bytes = (p->storage == LBIB_STORAGE_FP32) ? 4 : 2;
     for (int b = 0; b < 2 && s == LBIB_OK; ++b) {
-        s = dev_alloc(c, &c->f[b], 9 * nn);
-        if (s == LBIB_OK && c->S) s = dev_alloc(c, &c->g[b], 5 * (size_t)c->S * nn);
+        char* fb = nullptr;
+        char* gb = nullptr;
+        s = dev_alloc(c, &fb, 9 * nn * c->pop_bytes);
+        c->f[b] = fb;
+        if (s == LBIB_OK && c->S) {
+            s = dev_alloc(c, &gb, 5 * (size_t)c->S * nn * c->pop_bytes);
+            c->g[b] = gb;
+        }
     }
     if (s == LBIB_OK) s = dev_alloc(c, &c->uband, 2 * nn);
     if (s == LBIB_OK) s = dev_alloc(c, &c->mask, nn);

@@ -55,34 +55,41 @@ __device__ inline Nbr neighbours(int x, int y, int nx, int ny, int walls)
 
 // f_i(x) = s_i(x - v_i); across a wall the population returns reversed: s_opp(i)(x).
 // Velocities: 0 rest, 1 (1,0), 2 (0,1), 3 (-1,0), 4 (0,-1), 5 (1,1), 6 (-1,1), 7 (-1,-1), 8 (1,-1).
-__device__ inline void pull9(const float* __restrict__ s, int64_t nn, int x, const Nbr& n, float f[9])
+// Values come back as FP32 deviations (w_opp(i) = w_i, so the storage scale matches).
+template <int ST>
+__device__ inline void pull9(const void* sv, int64_t nn, int x, const Nbr& n, float f[9])
 {
-    const float* p2 = n.bot ? s + 4 * nn + n.rc + x : s + 2 * nn + n.rm + x;
-    const float* p4 = n.top ? s + 2 * nn + n.rc + x : s + 4 * nn + n.rp + x;
-    const float* p5 = n.bot ? s + 7 * nn + n.rc + x : s + 5 * nn + n.rm + n.xm;
-    const float* p6 = n.bot ? s + 8 * nn + n.rc + x : s + 6 * nn + n.rm + n.xp;
-    const float* p7 = n.top ? s + 5 * nn + n.rc + x : s + 7 * nn + n.rp + n.xp;
-    const float* p8 = n.top ? s + 6 * nn + n.rc + x : s + 8 * nn + n.rp + n.xm;
-    f[0] = s[n.rc + x];
-    f[1] = s[nn + n.rc + n.xm];
-    f[2] = *p2;
-    f[3] = s[3 * nn + n.rc + n.xp];
-    f[4] = *p4;
-    f[5] = *p5;
-    f[6] = *p6;
-    f[7] = *p7;
-    f[8] = *p8;
+    using T = typename Pop<ST>::T;
+    const T* __restrict__ s = (const T*)sv;
+    const T* p2 = n.bot ? s + 4 * nn + n.rc + x : s + 2 * nn + n.rm + x;
+    const T* p4 = n.top ? s + 2 * nn + n.rc + x : s + 4 * nn + n.rp + x;
+    const T* p5 = n.bot ? s + 7 * nn + n.rc + x : s + 5 * nn + n.rm + n.xm;
+    const T* p6 = n.bot ? s + 8 * nn + n.rc + x : s + 6 * nn + n.rm + n.xp;
+    const T* p7 = n.top ? s + 5 * nn + n.rc + x : s + 7 * nn + n.rp + n.xp;
+    const T* p8 = n.top ? s + 6 * nn + n.rc + x : s + 8 * nn + n.rp + n.xm;
+    f[0] = Pop<ST>::ld(s[n.rc + x], IS9[0]);
+    f[1] = Pop<ST>::ld(s[nn + n.rc + n.xm], IS9[1]);
+    f[2] = Pop<ST>::ld(*p2, IS9[2]);
+    f[3] = Pop<ST>::ld(s[3 * nn + n.rc + n.xp], IS9[3]);
+    f[4] = Pop<ST>::ld(*p4, IS9[4]);
+    f[5] = Pop<ST>::ld(*p5, IS9[5]);
+    f[6] = Pop<ST>::ld(*p6, IS9[6]);
+    f[7] = Pop<ST>::ld(*p7, IS9[7]);
+    f[8] = Pop<ST>::ld(*p8, IS9[8]);
 }
 
-__device__ inline void pull5(const float* __restrict__ s, int64_t nn, int x, const Nbr& n, float g[5])
+template <int ST>
+__device__ inline void pull5(const void* sv, int64_t nn, int x, const Nbr& n, float g[5])
 {
-    const float* p2 = n.bot ? s + 4 * nn + n.rc + x : s + 2 * nn + n.rm + x;
-    const float* p4 = n.top ? s + 2 * nn + n.rc + x : s + 4 * nn + n.rp + x;
-    g[0] = s[n.rc + x];
-    g[1] = s[nn + n.rc + n.xm];
-    g[2] = *p2;
-    g[3] = s[3 * nn + n.rc + n.xp];
-    g[4] = *p4;
+    using T = typename Pop<ST>::T;
+    const T* __restrict__ s = (const T*)sv;
+    const T* p2 = n.bot ? s + 4 * nn + n.rc + x : s + 2 * nn + n.rm + x;
+    const T* p4 = n.top ? s + 2 * nn + n.rc + x : s + 4 * nn + n.rp + x;
+    g[0] = Pop<ST>::ld(s[n.rc + x], IS5[0]);
+    g[1] = Pop<ST>::ld(s[nn + n.rc + n.xm], IS5[1]);
+    g[2] = Pop<ST>::ld(*p2, IS5[2]);
+    g[3] = Pop<ST>::ld(s[3 * nn + n.rc + n.xp], IS5[3]);
+    g[4] = Pop<ST>::ld(*p4, IS5[4]);
 }
 
 __device__ inline unsigned long long to_fixed(float v)
@@ -229,7 +236,7 @@ __device__ inline void spread_tile(const LatticeArgs& a, int x0, int y0, const i
     }
 }
 
-template <int S, bool NODES, bool MASK>
+template <int S, bool NODES, bool MASK, int ST>
 __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
 {
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
@@ -254,9 +261,10 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
     if (active) {
         n = neighbours(x, y, a.nx, a.ny, a.walls);
         o = n.rc + x;
-        pull9(a.fsrc, nn, x, n, f);
+        pull9<ST>(a.fsrc, nn, x, n, f);
 #pragma unroll
-        for (int s = 0; s < S; ++s) pull5(a.gsrc + (int64_t)5 * s * nn, nn, x, n, g[s]);
+        for (int s = 0; s < S; ++s)
+            pull5<ST>((const typename Pop<ST>::T*)a.gsrc + (int64_t)5 * s * nn, nn, x, n, g[s]);
         if constexpr (MASK) m = a.mask[o];
     }
 
@@ -288,17 +296,18 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
     const float fx = 3.0f * rho * ex, fy = 3.0f * rho * ey;
     {
         // equilibrium deviation w_i (drho + rho (3 vu + 4.5 vu^2 - 1.5 u^2))
-        float* __restrict__ d = a.fdst + o;
-        d[0] = om1 * f[0] + om * W0 * (drho - rho * usq);
+        using T = typename Pop<ST>::T;
+        T* __restrict__ d = (T*)a.fdst + o;
+        d[0] = Pop<ST>::st(om1 * f[0] + om * W0 * (drho - rho * usq), SC9[0]);
         float vu, eq;
-        vu = ux;       eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[nn]     = om1 * f[1] + om * eq + W1 * fx;
-        vu = uy;       eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[2 * nn] = om1 * f[2] + om * eq + W1 * fy;
-        vu = -ux;      eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[3 * nn] = om1 * f[3] + om * eq - W1 * fx;
-        vu = -uy;      eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[4 * nn] = om1 * f[4] + om * eq - W1 * fy;
-        vu = ux + uy;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[5 * nn] = om1 * f[5] + om * eq + W5 * (fx + fy);
-        vu = uy - ux;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[6 * nn] = om1 * f[6] + om * eq + W5 * (fy - fx);
-        vu = -ux - uy; eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[7 * nn] = om1 * f[7] + om * eq - W5 * (fx + fy);
-        vu = ux - uy;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[8 * nn] = om1 * f[8] + om * eq + W5 * (fx - fy);
+        vu = ux;       eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[nn]     = Pop<ST>::st(om1 * f[1] + om * eq + W1 * fx, SC9[1]);
+        vu = uy;       eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[2 * nn] = Pop<ST>::st(om1 * f[2] + om * eq + W1 * fy, SC9[2]);
+        vu = -ux;      eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[3 * nn] = Pop<ST>::st(om1 * f[3] + om * eq - W1 * fx, SC9[3]);
+        vu = -uy;      eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[4 * nn] = Pop<ST>::st(om1 * f[4] + om * eq - W1 * fy, SC9[4]);
+        vu = ux + uy;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[5 * nn] = Pop<ST>::st(om1 * f[5] + om * eq + W5 * (fx + fy), SC9[5]);
+        vu = uy - ux;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[6 * nn] = Pop<ST>::st(om1 * f[6] + om * eq + W5 * (fy - fx), SC9[6]);
+        vu = -ux - uy; eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[7 * nn] = Pop<ST>::st(om1 * f[7] + om * eq - W5 * (fx + fy), SC9[7]);
+        vu = ux - uy;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[8 * nn] = Pop<ST>::st(om1 * f[8] + om * eq + W5 * (fx - fy), SC9[8]);
     }
 
     if constexpr (MASK) a.mask[o] = 0;
@@ -325,13 +334,14 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
         for (int s = 0; s < S; ++s) {
             const float os = a.omega_s[s], os1 = 1.0f - a.omega_s[s];
             const float p3 = 3.0f * phi[s];
-            float* __restrict__ d = a.gdst + (int64_t)5 * s * nn + o;
+            using T = typename Pop<ST>::T;
+            T* __restrict__ d = (T*)a.gdst + (int64_t)5 * s * nn + o;
             // equilibrium deviation w_i (dphi + 3 phi v_i . u) and reaction w_i R
-            d[0]      = os1 * g[s][0] + os * Q0 * dphi[s] + Q0 * R[s];
-            d[nn]     = os1 * g[s][1] + os * Q1 * (dphi[s] + p3 * ux) + Q1 * R[s];
-            d[2 * nn] = os1 * g[s][2] + os * Q1 * (dphi[s] + p3 * uy) + Q1 * R[s];
-            d[3 * nn] = os1 * g[s][3] + os * Q1 * (dphi[s] - p3 * ux) + Q1 * R[s];
-            d[4 * nn] = os1 * g[s][4] + os * Q1 * (dphi[s] - p3 * uy) + Q1 * R[s];
+            d[0]      = Pop<ST>::st(os1 * g[s][0] + os * Q0 * dphi[s] + Q0 * R[s], SC5[0]);
+            d[nn]     = Pop<ST>::st(os1 * g[s][1] + os * Q1 * (dphi[s] + p3 * ux) + Q1 * R[s], SC5[1]);
+            d[2 * nn] = Pop<ST>::st(os1 * g[s][2] + os * Q1 * (dphi[s] + p3 * uy) + Q1 * R[s], SC5[2]);
+            d[3 * nn] = Pop<ST>::st(os1 * g[s][3] + os * Q1 * (dphi[s] - p3 * ux) + Q1 * R[s], SC5[3]);
+            d[4 * nn] = Pop<ST>::st(os1 * g[s][4] + os * Q1 * (dphi[s] - p3 * uy) + Q1 * R[s], SC5[4]);
         }
     }
 
@@ -371,8 +381,8 @@ __global__ __launch_bounds__(TILE_N) void k_spread_inspect(LatticeArgs a)
 // pull yields f_i(x) = f_i^eq(rho(x), u(x)): s_i(x - v_i) = f_i^eq(x), or across a wall
 // s_opp(i)(x) = f_i^eq(x).
 struct InitArgs {
-    float* f;
-    float* g;
+    void* f;
+    void* g;
     const double* rho;
     const double* u;
     const double* phi;
@@ -382,8 +392,10 @@ struct InitArgs {
     double phi_ref[2];
 };
 
+template <int ST>
 __global__ void k_init(InitArgs a)
 {
+    using T = typename Pop<ST>::T;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= a.nn) return;
     const int x = (int)(idx % a.nx), y = (int)(idx / a.nx);
@@ -396,25 +408,26 @@ __global__ void k_init(InitArgs a)
     const double ux = a.u ? a.u[idx] : 0.0, uy = a.u ? a.u[a.nn + idx] : 0.0;
     const double drho = rho - a.rho0;
     const double usq = 1.5 * (ux * ux + uy * uy);
+    T* f = (T*)a.f;
     for (int i = 0; i < 9; ++i) {
         const double vu = vx[i] * ux + vy[i] * uy;
-        const float val = (float)(w9[i] * (drho + rho * (3.0 * vu + 4.5 * vu * vu - usq)));
+        const T val = Pop<ST>::st((float)(w9[i] * (drho + rho * (3.0 * vu + 4.5 * vu * vu - usq))), SC9[i]);
         const int sy = y - vy[i];
         if (a.walls && (sy < 0 || sy >= a.ny)) {
-            a.f[(int64_t)opp[i] * a.nn + idx] = val;
+            f[(int64_t)opp[i] * a.nn + idx] = val;
         } else {
             const int sx = (x - vx[i] + a.nx) % a.nx;
             const int syy = (sy + a.ny) % a.ny;
-            a.f[(int64_t)i * a.nn + (int64_t)syy * a.nx + sx] = val;
+            f[(int64_t)i * a.nn + (int64_t)syy * a.nx + sx] = val;
         }
     }
     for (int s = 0; s < a.S; ++s) {
         const double phi = a.phi ? a.phi[(int64_t)s * a.nn + idx] : 0.0;
         const double dphi = phi - a.phi_ref[s];
-        float* gs = a.g + (int64_t)5 * s * a.nn;
+        T* gs = (T*)a.g + (int64_t)5 * s * a.nn;
         for (int i = 0; i < 5; ++i) {
             const double vu = vx[i] * ux + vy[i] * uy;
-            const float val = (float)(w5[i] * (dphi + 3.0 * phi * vu));
+            const T val = Pop<ST>::st((float)(w5[i] * (dphi + 3.0 * phi * vu)), SC5[i]);
             const int sy = y - vy[i];
             if (a.walls && (sy < 0 || sy >= a.ny)) {
                 gs[(int64_t)opp[i] * a.nn + idx] = val;
@@ -429,8 +442,8 @@ __global__ void k_init(InitArgs a)
 
 // Moments of the current state in FP64: planes rho, ux, uy, phi_0 .. phi_{S-1}.
 struct MomentArgs {
-    const float* f;
-    const float* g;
+    const void* f;
+    const void* g;
     double* out;
     int64_t nn;
     int nx, ny, walls, S;
@@ -438,32 +451,34 @@ struct MomentArgs {
     double phi_ref[2];
 };
 
+template <int ST>
 __device__ inline void node_moments(const MomentArgs& a, int x, int y, double& drho, double& jx,
                                     double& jy, double dphi[2])
 {
     const Nbr n = neighbours(x, y, a.nx, a.ny, a.walls);
     float f[9];
-    pull9(a.f, a.nn, x, n, f);
+    pull9<ST>(a.f, a.nn, x, n, f);
     drho = 0.0;
     for (int i = 0; i < 9; ++i) drho += (double)f[i];
     jx = ((double)f[1] - f[3]) + ((double)f[5] - f[6]) + ((double)f[8] - f[7]);
     jy = ((double)f[2] - f[4]) + ((double)f[5] + f[6]) - ((double)f[7] + f[8]);
     for (int s = 0; s < a.S; ++s) {
         float g[5];
-        pull5(a.g + (int64_t)5 * s * a.nn, a.nn, x, n, g);
+        pull5<ST>((const typename Pop<ST>::T*)a.g + (int64_t)5 * s * a.nn, a.nn, x, n, g);
         double t = 0.0;
         for (int i = 0; i < 5; ++i) t += (double)g[i];
         dphi[s] = t;
     }
 }
 
+template <int ST>
 __global__ void k_moments(MomentArgs a)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= a.nn) return;
     const int x = (int)(idx % a.nx), y = (int)(idx / a.nx);
     double drho, jx, jy, dphi[2] = {0.0, 0.0};
-    node_moments(a, x, y, drho, jx, jy, dphi);
+    node_moments<ST>(a, x, y, drho, jx, jy, dphi);
     const double rho = a.rho0 + drho;
     a.out[idx] = rho;
     a.out[a.nn + idx] = jx / rho;
@@ -476,6 +491,7 @@ __global__ void k_moments(MomentArgs a)
 constexpr int RED_THREADS = 256;
 constexpr int RED_MAXV = 5;
 
+template <int ST>
 __global__ __launch_bounds__(RED_THREADS) void k_reduce_partial(MomentArgs a, double* partial)
 {
     __shared__ double sh[RED_MAXV][RED_THREADS];
@@ -485,7 +501,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_partial(MomentArgs a, do
     for (int64_t idx = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; idx < a.nn; idx += stride) {
         const int x = (int)(idx % a.nx), y = (int)(idx / a.nx);
         double drho, jx, jy, dphi[2] = {0.0, 0.0};
-        node_moments(a, x, y, drho, jx, jy, dphi);
+        node_moments<ST>(a, x, y, drho, jx, jy, dphi);
         acc[0] += drho;
         acc[1] += jx;
         acc[2] += jy;
@@ -519,23 +535,33 @@ __global__ void k_reduce_final(const double* partial, int nblocks, int nv, doubl
 // ---------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------
-template <int S>
+template <int S, int ST>
 static hipError_t launch_lattice_s(lbib_ctx* c, const LatticeArgs& a, bool nodes, bool mask)
 {
     dim3 grid((unsigned)c->nbins), block(TILE_N);
-    if (nodes && mask) hipLaunchKernelGGL((k_lattice<S, true, true>), grid, block, 0, c->stream, a);
-    else if (nodes) hipLaunchKernelGGL((k_lattice<S, true, false>), grid, block, 0, c->stream, a);
-    else if (mask) hipLaunchKernelGGL((k_lattice<S, false, true>), grid, block, 0, c->stream, a);
-    else hipLaunchKernelGGL((k_lattice<S, false, false>), grid, block, 0, c->stream, a);
+    if (nodes && mask) hipLaunchKernelGGL((k_lattice<S, true, true, ST>), grid, block, 0, c->stream, a);
+    else if (nodes) hipLaunchKernelGGL((k_lattice<S, true, false, ST>), grid, block, 0, c->stream, a);
+    else if (mask) hipLaunchKernelGGL((k_lattice<S, false, true, ST>), grid, block, 0, c->stream, a);
+    else hipLaunchKernelGGL((k_lattice<S, false, false, ST>), grid, block, 0, c->stream, a);
     return hipGetLastError();
+}
+
+template <int ST>
+static hipError_t launch_lattice_st(lbib_ctx* c, const LatticeArgs& a, bool nodes, bool mask)
+{
+    switch (c->S) {
+    case 0: return launch_lattice_s<0, ST>(c, a, nodes, mask);
+    case 1: return launch_lattice_s<1, ST>(c, a, nodes, mask);
+    default: return launch_lattice_s<2, ST>(c, a, nodes, mask);
+    }
 }
 
 hipError_t launch_lattice(lbib_ctx* c, const LatticeArgs& a, bool nodes, bool mask)
 {
-    switch (c->S) {
-    case 0: return launch_lattice_s<0>(c, a, nodes, mask);
-    case 1: return launch_lattice_s<1>(c, a, nodes, mask);
-    default: return launch_lattice_s<2>(c, a, nodes, mask);
+    switch (c->p.storage) {
+    case LBIB_STORAGE_FP16: return launch_lattice_st<1>(c, a, nodes, mask);
+    case LBIB_STORAGE_BF16: return launch_lattice_st<2>(c, a, nodes, mask);
+    default: return launch_lattice_st<0>(c, a, nodes, mask);
     }
 }
 
@@ -563,7 +589,11 @@ hipError_t launch_init(lbib_ctx* c, const double* rho, const double* u, const do
     a.phi_ref[0] = c->p.species[0].phi_ref;
     a.phi_ref[1] = c->p.species[1].phi_ref;
     const unsigned nb = (unsigned)((c->nn + 255) / 256);
-    hipLaunchKernelGGL(k_init, dim3(nb), dim3(256), 0, c->stream, a);
+    switch (c->p.storage) {
+    case LBIB_STORAGE_FP16: hipLaunchKernelGGL(k_init<1>, dim3(nb), dim3(256), 0, c->stream, a); break;
+    case LBIB_STORAGE_BF16: hipLaunchKernelGGL(k_init<2>, dim3(nb), dim3(256), 0, c->stream, a); break;
+    default: hipLaunchKernelGGL(k_init<0>, dim3(nb), dim3(256), 0, c->stream, a); break;
+    }
     return hipGetLastError();
 }
 
@@ -588,7 +618,11 @@ hipError_t launch_moments(lbib_ctx* c, double* out)
 {
     MomentArgs a = moment_args(c, out);
     const unsigned nb = (unsigned)((c->nn + 255) / 256);
-    hipLaunchKernelGGL(k_moments, dim3(nb), dim3(256), 0, c->stream, a);
+    switch (c->p.storage) {
+    case LBIB_STORAGE_FP16: hipLaunchKernelGGL(k_moments<1>, dim3(nb), dim3(256), 0, c->stream, a); break;
+    case LBIB_STORAGE_BF16: hipLaunchKernelGGL(k_moments<2>, dim3(nb), dim3(256), 0, c->stream, a); break;
+    default: hipLaunchKernelGGL(k_moments<0>, dim3(nb), dim3(256), 0, c->stream, a); break;
+    }
     return hipGetLastError();
 }
 
@@ -598,7 +632,17 @@ hipError_t launch_reduce(lbib_ctx* c, double* out_dev)
     int nblocks = (int)((c->nn + RED_THREADS * 16 - 1) / (RED_THREADS * 16));
     if (nblocks > (int)c->partial_count) nblocks = (int)c->partial_count;
     if (nblocks < 1) nblocks = 1;
-    hipLaunchKernelGGL(k_reduce_partial, dim3(nblocks), dim3(RED_THREADS), 0, c->stream, a, c->d_partial);
+    switch (c->p.storage) {
+    case LBIB_STORAGE_FP16:
+        hipLaunchKernelGGL(k_reduce_partial<1>, dim3(nblocks), dim3(RED_THREADS), 0, c->stream, a, c->d_partial);
+        break;
+    case LBIB_STORAGE_BF16:
+        hipLaunchKernelGGL(k_reduce_partial<2>, dim3(nblocks), dim3(RED_THREADS), 0, c->stream, a, c->d_partial);
+        break;
+    default:
+        hipLaunchKernelGGL(k_reduce_partial<0>, dim3(nblocks), dim3(RED_THREADS), 0, c->stream, a, c->d_partial);
+        break;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const double rho_total = c->p.rho0 * (double)c->nn;

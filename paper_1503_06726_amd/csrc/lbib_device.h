@@ -45,10 +45,10 @@ constexpr int ERR_NONFINITE = 1;     // a node position or force became non-fini
 constexpr int ERR_MARGIN = 2;        // a node drifted beyond its bin margin
 
 struct LatticeArgs {
-    const float* __restrict__ fsrc;   // 9 planes
-    float* __restrict__ fdst;
-    const float* __restrict__ gsrc;   // 5 * S planes
-    float* __restrict__ gdst;
+    const void* __restrict__ fsrc;    // 9 planes of the storage type
+    void* __restrict__ fdst;
+    const void* __restrict__ gsrc;    // 5 * S planes
+    void* __restrict__ gdst;
     int64_t nn;                       // nx * ny (plane stride)
     int nx, ny, walls, ntx, nty;
     float omega, rho0;
@@ -180,6 +180,32 @@ __device__ inline int pack_ij(int i0, int j0)
 {
     return (i0 & 0xFFFF) | (int)((unsigned)(j0 & 0xFFFF) << 16);
 }
+
+// ---------------------------------------------------------------------------------------
+// population storage: FP32 keeps the plain deviation; FP16 / BF16 keep deviation / w_i * 2^10
+// ---------------------------------------------------------------------------------------
+template <int ST> struct Pop;
+template <> struct Pop<0> {
+    using T = float;
+    __device__ static float ld(T v, float) { return v; }
+    __device__ static T st(float v, float) { return v; }
+};
+template <> struct Pop<1> {
+    using T = _Float16;
+    __device__ static float ld(T v, float inv) { return (float)v * inv; }
+    __device__ static T st(float v, float sc) { return (T)(v * sc); }
+};
+template <> struct Pop<2> {
+    using T = __bf16;
+    __device__ static float ld(T v, float inv) { return (float)v * inv; }
+    __device__ static T st(float v, float sc) { return (T)(v * sc); }
+};
+// storage scale 2^10 / w_i (exact integers) and its inverse, D2Q9 and D2Q5
+__device__ constexpr float SC9[9] = {2304.0f, 9216.0f, 9216.0f, 9216.0f, 9216.0f, 36864.0f, 36864.0f, 36864.0f, 36864.0f};
+__device__ constexpr float IS9[9] = {1.0f / 2304.0f, 1.0f / 9216.0f, 1.0f / 9216.0f, 1.0f / 9216.0f, 1.0f / 9216.0f,
+                                     1.0f / 36864.0f, 1.0f / 36864.0f, 1.0f / 36864.0f, 1.0f / 36864.0f};
+__device__ constexpr float SC5[5] = {3072.0f, 6144.0f, 6144.0f, 6144.0f, 6144.0f};
+__device__ constexpr float IS5[5] = {1.0f / 3072.0f, 1.0f / 6144.0f, 1.0f / 6144.0f, 1.0f / 6144.0f, 1.0f / 6144.0f};
 
 // XCD-aware workgroup order: the dispatcher deals workgroups round-robin over the 8 XCDs;
 // remap so each XCD walks a contiguous run of tiles (neighbouring tiles share cache lines

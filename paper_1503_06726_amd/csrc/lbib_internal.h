@@ -36,9 +36,10 @@ struct lbib_ctx {
     int ntx = 0, nty = 0, nbins = 0;
     bool mask_needed = false;
 
-    // lattice state: post-collision deviations, A/B buffers
-    float* f[2] = {nullptr, nullptr};
-    float* g[2] = {nullptr, nullptr};
+    // lattice state: post-collision deviations (FP32, FP16 or BF16), A/B buffers
+    void* f[2] = {nullptr, nullptr};
+    void* g[2] = {nullptr, nullptr};
+    size_t pop_bytes = 4;            // bytes per stored population
     int cur = 0;
     float* uband = nullptr;          // [2][ny][nx]
     uint16_t* mask = nullptr;        // [ny][nx]

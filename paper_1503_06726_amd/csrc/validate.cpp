@@ -32,7 +32,8 @@ lbib_status check_params(const lbib_params* p, std::string& msg)
     if (!std::isfinite(p->k_spring) || !std::isfinite(p->phi_m) || !std::isfinite(p->kappa_area))
         return fail(msg, "force-law constants not finite");
     if (p->n_species < 0 || p->n_species > 2) return fail(msg, "n_species = %g outside 0..2", p->n_species);
-    if (p->storage != LBIB_STORAGE_FP32) return fail(msg, "storage %g not supported", p->storage);
+    if (p->storage < LBIB_STORAGE_FP32 || p->storage > LBIB_STORAGE_BF16)
+        return fail(msg, "storage %g unknown", p->storage);
     int n_sch = 0;
     for (int s = 0; s < p->n_species; ++s) {
         const lbib_species& sp = p->species[s];

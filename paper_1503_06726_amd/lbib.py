@@ -18,6 +18,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC = 0, -1, -2, -3, -4, -5
 PERIODIC, WALLS = 0, 1
 DELTA_COS4, DELTA_PESKIN4 = 0, 1
 REACT_NONE, REACT_SOURCE_DECAY, REACT_SCHNAKENBERG = 0, 1, 2
+STORAGE_FP32, STORAGE_FP16, STORAGE_BF16 = 0, 1, 2
 K_LATTICE, K_MEMBRANE, K_REBIN = range(3)
 KERNEL_NAMES = ["lattice", "membrane", "rebin"]
 
@@ -123,7 +124,7 @@ def make_params(d: dict) -> Params:
     p.kappa_area = float(d.get("kappa_area", 0.0))
     sp = d.get("species", [])
     p.n_species = len(sp)
-    p.storage = 0
+    p.storage = int(d.get("storage", STORAGE_FP32))
     for s, spc in enumerate(sp[:2]):        # more than two is left to the validator to reject
         p.species[s].D = float(spc["D"])
         p.species[s].phi_ref = float(spc.get("phi_ref", 0.0))

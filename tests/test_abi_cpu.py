@@ -64,7 +64,7 @@ GOOD = W.tiny_cell().params_dict()
 @pytest.mark.parametrize("change,frag", [
     (dict(tau=0.5), "tau"), (dict(tau=float("nan")), "tau"), (dict(nx=3), "lattice"),
     (dict(ny=40000), "lattice"), (dict(bc_y=2), "bc_y"), (dict(delta_kernel=7), "delta_kernel"),
-    (dict(rho0=0.0), "rho0"), (dict(body_accel=(float("inf"), 0.0)), "body"),
+    (dict(rho0=0.0), "rho0"), (dict(body_accel=(float("inf"), 0.0)), "body"), (dict(storage=3), "storage"),
 ])
 def test_bad_params_rejected(change, frag):
     d = dict(GOOD, **change)

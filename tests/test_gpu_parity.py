@@ -242,3 +242,34 @@ def test_invalid_cells_leave_state_unchanged():
     g.step(3)
     assert g.get_fields()["xy"].shape == (64, 2)
     g.close()
+
+
+# ------------------------------------------------------------------------------------------
+# reduced-precision population storage (FP16 / BF16 deviations, FP32 collision): the error
+# against the FP64 oracle is reported per field; the bound only catches gross mistakes
+# (a wrong storage scale or a direction mix-up gives O(1) errors)
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("storage,bound", [(lbib.STORAGE_FP16, 1e-2), (lbib.STORAGE_BF16, 1e-1)])
+@pytest.mark.parametrize("case", ["tiny", "walls", "periodic"])
+def test_reduced_precision_storage(storage, bound, case):
+    w = CELL_CASES[case]()
+    prm = dict(w.params_dict(), storage=storage)
+    say(f"case {case} storage {storage}")
+    g = lbib.Simulation(prm)
+    if w.phi_init is not None:
+        g.set_fields(phi=w.phi_init)
+    g.set_cells(w.offsets, w.xy, w.rest_len, w.rest_area)
+    g.step(60)
+    G = g.get_fields()
+    g.close()
+    o = O.from_workload(w)
+    o.step(60)
+    R = o.get_fields()
+    errs = {"rho": rel(G["rho"], R["rho"]), "drho": rel(G["rho"] - 1.0, R["rho"] - 1.0), "u": rel(G["u"], R["u"]),
+            "X": rel(G["xy"], R["xy"]), "disp": rel(G["xy"] - w.xy, R["xy"] - w.xy)}
+    if w.n_species:
+        errs["phi"] = rel(G["phi"], R["phi"])
+    say("  rel-L2:", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k in ("rho", "u", "X", "phi"):
+        if k in errs:
+            assert errs[k] < bound, (k, errs[k])
