@@ -138,7 +138,8 @@ LatticeArgs lattice_args(lbib_ctx* c)
     a.bin_off = c->d_bin_off;
     a.rec = c->d_rec[c->rec_cur];
     a.rec_ij = c->d_rec_ij[c->rec_cur];
-    a.uband = c->uband;
+    a.rec_node = c->d_rec_node[c->rec_cur];
+    a.U_acc = c->d_U;
     a.mask = c->mask;
     a.e_out = nullptr;
     return a;
@@ -153,9 +154,9 @@ MembraneArgs membrane_args(lbib_ctx* c, int advect)
     a.l0 = c->d_l0;
     a.A0 = c->d_A0;
     a.area = c->d_area;
-    a.uband = c->uband;
+    a.U_acc = c->d_U;
     a.slot = c->d_slot;
-    a.key = c->d_key;
+    a.ij_bin = c->d_ijbin;
     a.rec = c->d_rec[c->rec_cur];
     a.rec_ij = c->d_rec_ij[c->rec_cur];
     a.mask = c->mask;
@@ -180,6 +181,8 @@ BinArgs bin_args(lbib_ctx* c, int copy)
     BinArgs a;
     std::memset(&a, 0, sizeof a);
     a.X = c->d_X;
+    a.ij_bin = c->d_ijbin;
+    a.rec_node = c->d_rec_node[copy ? 1 - c->rec_cur : c->rec_cur];
     a.key = c->d_key;
     a.rank = c->d_rank;
     a.count = c->d_bin_count;
@@ -281,9 +284,12 @@ void free_nodes(lbib_ctx* c)
     dev_free(c, c->d_key, N);
     dev_free(c, c->d_rank, N);
     dev_free(c, c->d_slot, N);
+    dev_free(c, c->d_ijbin, N);
+    dev_free(c, c->d_U, 2 * N);
     for (int b = 0; b < 2; ++b) {
         dev_free(c, c->d_rec[b], N);
         dev_free(c, c->d_rec_ij[b], N);
+        dev_free(c, c->d_rec_node[b], N);
     }
     c->rec_cur = 0;
     c->n_nodes = 0;
@@ -304,7 +310,6 @@ void free_all(lbib_ctx* c)
         dev_free(c, gb, 5 * (size_t)c->S * nn * c->pop_bytes);
         c->f[b] = c->g[b] = nullptr;
     }
-    dev_free(c, c->uband, 2 * nn);
     dev_free(c, c->mask, nn);
     dev_free(c, c->d_bin_count, (size_t)c->nbins);
     dev_free(c, c->d_bin_off, (size_t)c->nbins + 1);
@@ -415,6 +420,8 @@ lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out)
     c->ntx = (p->nx + TILE_X - 1) / TILE_X;
     c->nty = (p->ny + TILE_Y - 1) / TILE_Y;
     c->nbins = c->ntx * c->nty;
+    c->nlty = (p->ny + TILE_Y * RPT - 1) / (TILE_Y * RPT);
+    c->nltiles = c->ntx * c->nlty;
     c->partial_count = 4096;
     const size_t nn = (size_t)c->nn;
     lbib_status s = LBIB_OK;
@@ -429,14 +436,12 @@ lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out)
             c->g[b] = gb;
         }
     }
-    if (s == LBIB_OK) s = dev_alloc(c, &c->uband, 2 * nn);
     if (s == LBIB_OK) s = dev_alloc(c, &c->mask, nn);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_bin_count, (size_t)c->nbins);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_bin_off, (size_t)c->nbins + 1);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_err, 1);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_partial, c->partial_count * 5);
-    if (s == LBIB_OK && (launch_fill_f32(c, c->uband, 2 * c->nn) != hipSuccess ||
-                         launch_fill_u16(c, c->mask, c->nn) != hipSuccess ||
+    if (s == LBIB_OK && (launch_fill_u16(c, c->mask, c->nn) != hipSuccess ||
                          launch_fill_i32(c, c->d_bin_count, c->nbins, 0) != hipSuccess ||
                          launch_fill_i32(c, c->d_bin_off, c->nbins + 1, 0) != hipSuccess ||
                          launch_fill_i32(c, c->d_err, 1, 0) != hipSuccess))
@@ -501,9 +506,12 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_key, N);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_rank, N);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_slot, N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_ijbin, N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_U, 2 * N);
     for (int b = 0; b < 2 && s == LBIB_OK; ++b) {
         s = dev_alloc(c, &c->d_rec[b], N);
         if (s == LBIB_OK) s = dev_alloc(c, &c->d_rec_ij[b], N);
+        if (s == LBIB_OK) s = dev_alloc(c, &c->d_rec_node[b], N);
     }
     c->n_cells = n_cells;
     c->n_nodes = (int64_t)N;
@@ -519,6 +527,7 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
     LBIB_HIP(c, hipMemcpyAsync(c->d_A0, A0.data(), C * sizeof(double), hipMemcpyHostToDevice, c->stream));
     LBIB_LAUNCH(c, launch_fill_i32(c, c->d_bin_count, c->nbins, 0));
     LBIB_LAUNCH(c, launch_fill_i32(c, c->d_err, 1, 0));
+    LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->d_U, 4 * (int64_t)N, 0));
     if (c->mask_needed) LBIB_LAUNCH(c, launch_fill_u16(c, c->mask, c->nn));
     LBIB_TRY(rebin(c, 0));
     LBIB_TRY(membrane(c, 0));

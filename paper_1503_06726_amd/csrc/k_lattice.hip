@@ -106,249 +106,330 @@ __device__ inline bool cyc_meet(int a0, int alen, int b0, int blen, int n)
     return d < blen || d + alen > n;
 }
 
-constexpr int MAX_RANGES = 25;     // bins read by one tile (at most 5 columns x 5 rows)
-constexpr int SPREAD_UNROLL = 4;   // candidates per thread whose loads are issued together
+constexpr int MAX_RANGES = 40;     // bins read by one tile (at most 5 columns x 8 rows)
+constexpr int SPREAD_UNROLL = 2;   // candidates per thread whose loads are issued together
 
-// Bins a tile reads.  A node filed in bin b has its stencil origin within b's tile widened
-// by BIN_MARGIN; the tile needs every node whose origin lies in [x0 - 3, x1 - 1] x
-// [y0 - 3, y1 - 1], so it reads every bin whose widened tile meets that range (superfluous
-// candidates contribute nothing).  Lane q < (returned count) of the first wavefront loads
-// bin q's record range; its inclusive prefix over q goes to rpre, the range start to rbeg.
-__device__ inline void spread_ranges(const LatticeArgs& a, int tcol, int trow, int x0, int y0, int* rbeg,
-                                     int* rpre)
+// Bins a lattice tile [x0, x1) x [y0, y1) reads.  A node filed in bin b has its stencil
+// origin within b's tile (TILE_X x TILE_Y) widened by BIN_MARGIN; the lattice tile needs every
+// node whose origin lies in [x0 - 3, x1 - 1] x [y0 - 3, y1 - 1], so it reads every bin whose
+// widened tile meets that range (superfluous candidates contribute nothing).  Lane q of the
+// first wavefront loads the record range of the q-th such bin (range_load); range_publish
+// then writes the range starts to rbeg and the inclusive prefix of their lengths to rpre.
+__device__ inline void range_load(const LatticeArgs& a, int x0, int x1, int y0, int y1, int& beg, int& len)
 {
     const int t = threadIdx.x;
     const int M = BIN_MARGIN;
-    const int x1 = min(x0 + TILE_X, a.nx), y1 = min(y0 + TILE_Y, a.ny);
+    beg = 0;
+    len = 0;
+    if (t >= 64) return;
     int cols[5], ncol = 0;
     {
+        const int c0 = x0 / TILE_X;
         const int nc = a.ntx <= 5 ? a.ntx : 5;
         for (int q = 0; q < nc; ++q) {
-            const int cc = a.ntx <= 5 ? q : wrap_i(tcol - 2 + q, a.ntx);
+            const int cc = a.ntx <= 5 ? q : wrap_i(c0 - 2 + q, a.ntx);
             const int bx0 = cc * TILE_X, bw = min(TILE_X, a.nx - bx0);
             if (cyc_meet(bx0 - M, bw + 2 * M, x0 - 3, x1 - x0 + 3, a.nx)) cols[ncol++] = cc;
         }
     }
-    int rows[5], nrow = 0;
-    if (a.walls) {
-        for (int rr = max(trow - 2, 0); rr <= min(trow + 2, a.nty - 1); ++rr) {
-            const int by0 = rr * TILE_Y, bh = min(TILE_Y, a.ny - by0);
-            const int lo = (rr == 0) ? -1000000 : by0 - M;              // bin row 0 also holds j0 < 0
-            if (lo <= y1 - 1 && by0 + bh - 1 + M >= y0 - 3) rows[nrow++] = rr;
-        }
-    } else {
-        const int nr = a.nty <= 5 ? a.nty : 5;
-        for (int q = 0; q < nr; ++q) {
-            const int rr = a.nty <= 5 ? q : wrap_i(trow - 2 + q, a.nty);
-            const int by0 = rr * TILE_Y, bh = min(TILE_Y, a.ny - by0);
-            if (cyc_meet(by0 - M, bh + 2 * M, y0 - 3, y1 - y0 + 3, a.ny)) rows[nrow++] = rr;
+    int rows[8], nrow = 0;
+    {
+        const int r0 = y0 / TILE_Y, r1 = (y1 - 1) / TILE_Y;      // bin rows the tile spans
+        if (a.walls) {
+            for (int rr = max(r0 - 2, 0); rr <= min(r1 + 1, a.nty - 1) && nrow < 8; ++rr) {
+                const int by0 = rr * TILE_Y, bh = min(TILE_Y, a.ny - by0);
+                const int lo = (rr == 0) ? -1000000 : by0 - M;              // bin row 0 also holds j0 < 0
+                if (lo <= y1 - 1 && by0 + bh - 1 + M >= y0 - 3) rows[nrow++] = rr;
+            }
+        } else {
+            const int span = r1 - r0 + 4;
+            const bool all = a.nty <= span;
+            const int nr = all ? a.nty : span;
+            for (int q = 0; q < nr && nrow < 8; ++q) {
+                const int rr = all ? q : wrap_i(r0 - 2 + q, a.nty);
+                const int by0 = rr * TILE_Y, bh = min(TILE_Y, a.ny - by0);
+                if (cyc_meet(by0 - M, bh + 2 * M, y0 - 3, y1 - y0 + 3, a.ny)) rows[nrow++] = rr;
+            }
         }
     }
-    if (t < 64) {
-        const int nsel = nrow * ncol;
-        int beg = 0, len = 0;
-        if (t < nsel) {
-            int r = 0, cc = 0;
+    const int nsel = nrow * ncol;
+    if (t < nsel) {
+        const int qr = t / ncol, qc = t - qr * ncol;
+        int r = 0, cc = 0;
 #pragma unroll
-            for (int q = 0; q < 5; ++q)
-                if (q == t / ncol) r = rows[q];
+        for (int q = 0; q < 8; ++q)
+            if (q == qr) r = rows[q];
 #pragma unroll
-            for (int q = 0; q < 5; ++q)
-                if (q == t % ncol) cc = cols[q];
-            const int b = r * a.ntx + cc;
-            beg = a.bin_off[b];
-            len = a.bin_off[b + 1] - beg;
-        }
-        int incl = len;
-        for (int o = 1; o < 32; o <<= 1) {
-            const int up = __shfl_up(incl, o, 64);
-            if (t >= o) incl += up;
-        }
-        if (t < MAX_RANGES) {
-            rbeg[t] = beg;
-            rpre[t] = incl;
-        }
+        for (int q = 0; q < 5; ++q)
+            if (q == qc) cc = cols[q];
+        const int b = r * a.ntx + cc;
+        beg = a.bin_off[b];
+        len = a.bin_off[b + 1] - beg;
     }
 }
 
-// Spread the candidates into this tile's LDS accumulators (after spread_ranges + barrier).
-__device__ inline void spread_tile(const LatticeArgs& a, int x0, int y0, const int* rbeg, const int* rpre,
-                                   unsigned long long* accx, unsigned long long* accy, int* tch)
+__device__ inline void range_publish(int beg, int len, int* rbeg, int* rpre)
 {
     const int t = threadIdx.x;
-    const int x1 = min(x0 + TILE_X, a.nx), y1 = min(y0 + TILE_Y, a.ny);
-    const int total = rpre[MAX_RANGES - 1];
-    for (int base = 0; base < total; base += SPREAD_UNROLL * TILE_N) {
-        int ij[SPREAD_UNROLL];
-        float4 rc[SPREAD_UNROLL];
+    if (t >= 64) return;
+    int incl = len;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int up = __shfl_up(incl, o, 64);
+        if (t >= o) incl += up;
+    }
+    if (t < MAX_RANGES) {
+        rbeg[t] = beg;
+        rpre[t] = incl;
+    }
+}
+
+__device__ inline unsigned long long to_ufixed(float v)
+{
+    v = fminf(fmaxf(v, -UFIX_CLAMP), UFIX_CLAMP);
+    return (unsigned long long)__float2ll_rn(v * UFIX_SCALE);
+}
+
+// Load one chunk of candidate records (up to SPREAD_UNROLL per thread).
+__device__ inline void load_candidates(const LatticeArgs& a, int base, int total, const int* rbeg, const int* rpre,
+                                       int ij[SPREAD_UNROLL], float4 rc[SPREAD_UNROLL], int nd[SPREAD_UNROLL],
+                                       bool with_node)
+{
+    const int t = threadIdx.x;
 #pragma unroll
-        for (int u = 0; u < SPREAD_UNROLL; ++u) {
-            const int k = base + u * TILE_N + t;
-            ij[u] = 0x7FFF7FFF;                          // far away: rejected below
-            if (k < total) {
-                int q = 0;
-                while (k >= rpre[q]) ++q;
-                const int idx = rbeg[q] + k - (q ? rpre[q - 1] : 0);
-                ij[u] = a.rec_ij[idx];
-                rc[u] = a.rec[idx];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < SPREAD_UNROLL; ++u) {
-            const int i0 = ij[u] & 0xFFFF;
-            const int j0 = ij[u] >> 16;                  // sign-extended 16-bit row
-            // tile coordinates of the four stencil columns and rows (each wrapped on its own,
-            // so a stencil that wraps onto the same tile twice is still counted correctly)
-            int lx[4], ly[4];
-            unsigned hx = 0u, hy = 0u;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                int i = i0 + q;
-                if (i >= a.nx) i -= a.nx;
-                lx[q] = i - x0;
-                if ((unsigned)lx[q] < (unsigned)(x1 - x0)) hx |= 1u << q;
-                int j = j0 + q;
-                bool ok = true;
-                if (a.walls) ok = j >= 0 && j < a.ny;
-                else if (j >= a.ny) j -= a.ny;
-                ly[q] = j - y0;
-                if (ok && (unsigned)ly[q] < (unsigned)(y1 - y0)) hy |= 1u << q;
-            }
-            if (!hx || !hy) continue;
-            const float4 r = rc[u];
-            float wx[4], wy[4];
-            delta_weights(a.kernel, r.x, wx);
-            delta_weights(a.kernel, r.y, wy);
-#pragma unroll
-            for (int bb = 0; bb < 4; ++bb) {
-                if (!((hy >> bb) & 1u)) continue;
-#pragma unroll
-                for (int aa = 0; aa < 4; ++aa) {
-                    if (!((hx >> aa) & 1u)) continue;
-                    const float w = wx[aa] * wy[bb];
-                    const int o = ly[bb] * TILE_X + lx[aa];
-                    atomicAdd(&accx[o], to_fixed(w * r.z));
-                    atomicAdd(&accy[o], to_fixed(w * r.w));
-                    tch[o] = 1;
-                }
-            }
+    for (int u = 0; u < SPREAD_UNROLL; ++u) {
+        const int k = base + u * TILE_N + t;
+        ij[u] = 0x7FFF7FFF;                              // far away: never hits
+        nd[u] = 0;
+        if (k < total) {
+            int q = 0;
+            while (k >= rpre[q]) ++q;
+            const int idx = rbeg[q] + k - (q ? rpre[q - 1] : 0);
+            ij[u] = a.rec_ij[idx];
+            rc[u] = a.rec[idx];
+            if (with_node) nd[u] = a.rec_node[idx];
         }
     }
 }
 
+// Couple one chunk of candidates with the tile [x0, x1) x [y0, y1) (LDS rows TILE_X apart):
+// spread each node's force into the LDS accumulators (Eq. forcedistribution), and, when
+// INTERP, add the node's share of the interpolated velocity from the tile's u (LDS) to its
+// fixed-point accumulator (Eq. conversion2; each tile contributes its own stencil points).
+template <bool INTERP>
+__device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0, int y1,
+                                    const int ij[SPREAD_UNROLL], const float4 rc[SPREAD_UNROLL],
+                                    const int nd[SPREAD_UNROLL], unsigned long long* accx, unsigned long long* accy,
+                                    const float* uxs, const float* uys)
+{
+#pragma unroll
+    for (int u = 0; u < SPREAD_UNROLL; ++u) {
+        const int i0 = ij[u] & 0xFFFF;
+        const int j0 = ij[u] >> 16;                      // sign-extended 16-bit row
+        // tile coordinates of the four stencil columns and rows (each wrapped on its own,
+        // so a stencil that wraps onto the same tile twice is still counted correctly)
+        int lx[4], ly[4];
+        unsigned hx = 0u, hy = 0u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int i = i0 + q;
+            if (i >= a.nx) i -= a.nx;
+            lx[q] = i - x0;
+            if ((unsigned)lx[q] < (unsigned)(x1 - x0)) hx |= 1u << q;
+            int j = j0 + q;
+            bool ok = true;
+            if (a.walls) ok = j >= 0 && j < a.ny;
+            else if (j >= a.ny) j -= a.ny;
+            ly[q] = j - y0;
+            if (ok && (unsigned)ly[q] < (unsigned)(y1 - y0)) hy |= 1u << q;
+        }
+        if (!hx || !hy) continue;
+        const float4 r = rc[u];
+        float wx[4], wy[4];
+        delta_weights(a.kernel, r.x, wx);
+        delta_weights(a.kernel, r.y, wy);
+        float Ux = 0.0f, Uy = 0.0f;
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+            if (!((hy >> bb) & 1u)) continue;
+            float sx = 0.0f, sy = 0.0f;
+#pragma unroll
+            for (int aa = 0; aa < 4; ++aa) {
+                if (!((hx >> aa) & 1u)) continue;
+                const float w = wx[aa] * wy[bb];
+                const int o = ly[bb] * TILE_X + lx[aa];
+                atomicAdd(&accx[o], to_fixed(w * r.z));
+                atomicAdd(&accy[o], to_fixed(w * r.w));
+                if constexpr (INTERP) {
+                    sx += wx[aa] * uxs[o];
+                    sy += wx[aa] * uys[o];
+                }
+            }
+            if constexpr (INTERP) {
+                Ux += wy[bb] * sx;
+                Uy += wy[bb] * sy;
+            }
+        }
+        if constexpr (INTERP) {
+            atomicAdd(&a.U_acc[2 * (int64_t)nd[u]], to_ufixed(Ux));
+            atomicAdd(&a.U_acc[2 * (int64_t)nd[u] + 1], to_ufixed(Uy));
+        }
+    }
+}
+
+// One lattice tile of TILE_X x (TILE_Y * RPT) nodes per workgroup; thread (lx, ly) handles
+// rows ly, ly + TILE_Y, ...  Order: record ranges and population loads issued; candidate
+// records loaded; moments (rho, u) of every row, u staged in LDS; candidates coupled (force
+// spread into LDS, velocity interpolated to the nodes); collision with the spread force and
+// stores.
 template <int S, bool NODES, bool MASK, int ST>
 __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
 {
+    constexpr int LY = TILE_Y * RPT;
+    constexpr int NL = NODES ? TILE_X * LY : 1;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int tcol = tile % a.ntx, trow = tile / a.ntx;
-    const int x0 = tcol * TILE_X, y0 = trow * TILE_Y;
+    const int x0 = tcol * TILE_X, y0 = trow * LY;
+    const int x1 = min(x0 + TILE_X, a.nx), y1 = min(y0 + LY, a.ny);
     const int t = threadIdx.x;
-    const int x = x0 + (t % TILE_X), y = y0 + (t / TILE_X);
-    const bool active = x < a.nx && y < a.ny;
+    const int x = x0 + (t % TILE_X);
     const int64_t nn = a.nn;
 
-    __shared__ unsigned long long accx[NODES ? TILE_N : 1], accy[NODES ? TILE_N : 1];
-    __shared__ int tch[NODES ? TILE_N : 1];
+    __shared__ unsigned long long accx[NL], accy[NL];
+    __shared__ float uxs[NL], uys[NL];
     __shared__ int rbeg[NODES ? MAX_RANGES : 1], rpre[NODES ? MAX_RANGES : 1];
 
-    // issue the population loads first: they are in flight while the forces are spread
-    // (a workgroup barrier waits for LDS operations only)
-    Nbr n;
-    int64_t o = 0;
-    float f[9];
-    float g[S > 0 ? S : 1][5];
-    int m = 0;
-    if (active) {
-        n = neighbours(x, y, a.nx, a.ny, a.walls);
-        o = n.rc + x;
-        pull9<ST>(a.fsrc, nn, x, n, f);
+    int rg_beg = 0, rg_len = 0;
+    if constexpr (NODES) range_load(a, x0, x1, y0, y1, rg_beg, rg_len);
+
+    Nbr n[RPT];
+    bool active[RPT];
+    float f[RPT][9];
+    float g[RPT][S > 0 ? S : 1][5];
+    int m[RPT];
 #pragma unroll
-        for (int s = 0; s < S; ++s)
-            pull5<ST>((const typename Pop<ST>::T*)a.gsrc + (int64_t)5 * s * nn, nn, x, n, g[s]);
-        if constexpr (MASK) m = a.mask[o];
+    for (int r = 0; r < RPT; ++r) {
+        const int y = y0 + t / TILE_X + r * TILE_Y;
+        active[r] = x < a.nx && y < a.ny;
+        m[r] = 0;
+        if (active[r]) {
+            n[r] = neighbours(x, y, a.nx, a.ny, a.walls);
+            pull9<ST>(a.fsrc, nn, x, n[r], f[r]);
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                pull5<ST>((const typename Pop<ST>::T*)a.gsrc + (int64_t)5 * s * nn, nn, x, n[r], g[r][s]);
+            if constexpr (MASK) m[r] = a.mask[n[r].rc + x];
+        }
     }
 
-    float ex = a.bodyx, ey = a.bodyy;
-    bool touched = false;
+    int total = 0;
+    int cij[SPREAD_UNROLL], cnd[SPREAD_UNROLL];
+    float4 crc[SPREAD_UNROLL];
     if constexpr (NODES) {
-        accx[t] = 0ull;
-        accy[t] = 0ull;
-        tch[t] = 0;
-        spread_ranges(a, tcol, trow, x0, y0, rbeg, rpre);
+        range_publish(rg_beg, rg_len, rbeg, rpre);
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            accx[t + r * TILE_N] = 0ull;
+            accy[t + r * TILE_N] = 0ull;
+        }
         __syncthreads();
-        spread_tile(a, x0, y0, rbeg, rpre, accx, accy, tch);
-        __syncthreads();
-        ex += __ll2float_rn((long long)accx[t]) * FIX_INV;
-        ey += __ll2float_rn((long long)accy[t]) * FIX_INV;
-        touched = tch[t] != 0;
-    }
-    if (!active) return;
-
-    const float drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-    const float rho = a.rho0 + drho;
-    const float jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-    const float jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-    const float inv = 1.0f / rho;
-    const float ux = jx * inv, uy = jy * inv;
-    const float usq = 1.5f * (ux * ux + uy * uy);
-    const float om = a.omega, om1 = 1.0f - a.omega;
-    // force term 3 w_i rho (v_i . e)
-    const float fx = 3.0f * rho * ex, fy = 3.0f * rho * ey;
-    {
-        // equilibrium deviation w_i (drho + rho (3 vu + 4.5 vu^2 - 1.5 u^2))
-        using T = typename Pop<ST>::T;
-        T* __restrict__ d = (T*)a.fdst + o;
-        d[0] = Pop<ST>::st(om1 * f[0] + om * W0 * (drho - rho * usq), SC9[0]);
-        float vu, eq;
-        vu = ux;       eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[nn]     = Pop<ST>::st(om1 * f[1] + om * eq + W1 * fx, SC9[1]);
-        vu = uy;       eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[2 * nn] = Pop<ST>::st(om1 * f[2] + om * eq + W1 * fy, SC9[2]);
-        vu = -ux;      eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[3 * nn] = Pop<ST>::st(om1 * f[3] + om * eq - W1 * fx, SC9[3]);
-        vu = -uy;      eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[4 * nn] = Pop<ST>::st(om1 * f[4] + om * eq - W1 * fy, SC9[4]);
-        vu = ux + uy;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[5 * nn] = Pop<ST>::st(om1 * f[5] + om * eq + W5 * (fx + fy), SC9[5]);
-        vu = uy - ux;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[6 * nn] = Pop<ST>::st(om1 * f[6] + om * eq + W5 * (fy - fx), SC9[6]);
-        vu = -ux - uy; eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[7 * nn] = Pop<ST>::st(om1 * f[7] + om * eq - W5 * (fx + fy), SC9[7]);
-        vu = ux - uy;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[8 * nn] = Pop<ST>::st(om1 * f[8] + om * eq + W5 * (fx - fy), SC9[8]);
+        total = rpre[MAX_RANGES - 1];
+        load_candidates(a, 0, total, rbeg, rpre, cij, crc, cnd, true);
     }
 
-    if constexpr (MASK) a.mask[o] = 0;
-    if constexpr (S > 0) {
-        float dphi[S], phi[S], R[S];
+    // moments of every row: rho^n, u^n = sum f v / rho
+    float rho_r[RPT], drho_r[RPT], ux_r[RPT], uy_r[RPT];
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            dphi[s] = ((g[s][0] + g[s][1]) + (g[s][2] + g[s][3])) + g[s][4];
-            phi[s] = a.phi_ref[s] + dphi[s];
+    for (int r = 0; r < RPT; ++r) {
+        const float* fr = f[r];
+        drho_r[r] = ((fr[0] + fr[1]) + (fr[2] + fr[3])) + ((fr[4] + fr[5]) + (fr[6] + fr[7])) + fr[8];
+        rho_r[r] = a.rho0 + drho_r[r];
+        const float jx = (fr[1] - fr[3]) + (fr[5] - fr[6]) + (fr[8] - fr[7]);
+        const float jy = (fr[2] - fr[4]) + (fr[5] + fr[6]) - (fr[7] + fr[8]);
+        const float inv = 1.0f / rho_r[r];
+        ux_r[r] = jx * inv;
+        uy_r[r] = jy * inv;
+        if constexpr (NODES) {
+            uxs[t + r * TILE_N] = ux_r[r];
+            uys[t + r * TILE_N] = uy_r[r];
         }
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const float* c = a.rc[s];
-            if (a.react[s] == 1) {
-                R[s] = (m != 0 ? c[0] : 0.0f) - c[1] * phi[s];
-            } else if (a.react[s] == 2 && S == 2) {
-                const float u2v = phi[0] * phi[0] * phi[S - 1];
-                R[s] = (s == 0) ? c[2] * (c[0] - phi[0] + u2v) : c[2] * (c[1] - u2v);
-            } else {
-                R[s] = 0.0f;
-            }
+    }
+
+    if constexpr (NODES) {
+        __syncthreads();
+        couple_chunk<true>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, uxs, uys);
+        for (int base = SPREAD_UNROLL * TILE_N; base < total; base += SPREAD_UNROLL * TILE_N) {
+            load_candidates(a, base, total, rbeg, rpre, cij, crc, cnd, true);
+            couple_chunk<true>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, uxs, uys);
         }
+        __syncthreads();
+    }
+
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const float os = a.omega_s[s], os1 = 1.0f - a.omega_s[s];
-            const float p3 = 3.0f * phi[s];
+    for (int r = 0; r < RPT; ++r) {
+        if (!active[r]) continue;
+        const int64_t o = n[r].rc + x;
+        float ex = a.bodyx, ey = a.bodyy;
+        if constexpr (NODES) {
+            const int l = t + r * TILE_N;
+            ex += __ll2float_rn((long long)accx[l]) * FIX_INV;
+            ey += __ll2float_rn((long long)accy[l]) * FIX_INV;
+        }
+        const float* fr = f[r];
+        const float drho = drho_r[r], rho = rho_r[r], ux = ux_r[r], uy = uy_r[r];
+        const float usq = 1.5f * (ux * ux + uy * uy);
+        const float om = a.omega, om1 = 1.0f - a.omega;
+        // force term 3 w_i rho (v_i . e)
+        const float fx = 3.0f * rho * ex, fy = 3.0f * rho * ey;
+        {
+            // equilibrium deviation w_i (drho + rho (3 vu + 4.5 vu^2 - 1.5 u^2))
             using T = typename Pop<ST>::T;
-            T* __restrict__ d = (T*)a.gdst + (int64_t)5 * s * nn + o;
-            // equilibrium deviation w_i (dphi + 3 phi v_i . u) and reaction w_i R
-            d[0]      = Pop<ST>::st(os1 * g[s][0] + os * Q0 * dphi[s] + Q0 * R[s], SC5[0]);
-            d[nn]     = Pop<ST>::st(os1 * g[s][1] + os * Q1 * (dphi[s] + p3 * ux) + Q1 * R[s], SC5[1]);
-            d[2 * nn] = Pop<ST>::st(os1 * g[s][2] + os * Q1 * (dphi[s] + p3 * uy) + Q1 * R[s], SC5[2]);
-            d[3 * nn] = Pop<ST>::st(os1 * g[s][3] + os * Q1 * (dphi[s] - p3 * ux) + Q1 * R[s], SC5[3]);
-            d[4 * nn] = Pop<ST>::st(os1 * g[s][4] + os * Q1 * (dphi[s] - p3 * uy) + Q1 * R[s], SC5[4]);
+            T* __restrict__ d = (T*)a.fdst + o;
+            d[0] = Pop<ST>::st(om1 * fr[0] + om * W0 * (drho - rho * usq), SC9[0]);
+            float vu, eq;
+            vu = ux;       eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[nn]     = Pop<ST>::st(om1 * fr[1] + om * eq + W1 * fx, SC9[1]);
+            vu = uy;       eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[2 * nn] = Pop<ST>::st(om1 * fr[2] + om * eq + W1 * fy, SC9[2]);
+            vu = -ux;      eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[3 * nn] = Pop<ST>::st(om1 * fr[3] + om * eq - W1 * fx, SC9[3]);
+            vu = -uy;      eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[4 * nn] = Pop<ST>::st(om1 * fr[4] + om * eq - W1 * fy, SC9[4]);
+            vu = ux + uy;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[5 * nn] = Pop<ST>::st(om1 * fr[5] + om * eq + W5 * (fx + fy), SC9[5]);
+            vu = uy - ux;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[6 * nn] = Pop<ST>::st(om1 * fr[6] + om * eq + W5 * (fy - fx), SC9[6]);
+            vu = -ux - uy; eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[7 * nn] = Pop<ST>::st(om1 * fr[7] + om * eq - W5 * (fx + fy), SC9[7]);
+            vu = ux - uy;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[8 * nn] = Pop<ST>::st(om1 * fr[8] + om * eq + W5 * (fx - fy), SC9[8]);
         }
-    }
 
-    if constexpr (NODES) {
-        if (touched) {
-            a.uband[o] = ux;
-            a.uband[nn + o] = uy;
+        if constexpr (MASK) a.mask[o] = 0;
+        if constexpr (S > 0) {
+            float dphi[S], phi[S], R[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                dphi[s] = ((g[r][s][0] + g[r][s][1]) + (g[r][s][2] + g[r][s][3])) + g[r][s][4];
+                phi[s] = a.phi_ref[s] + dphi[s];
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const float* c = a.rc[s];
+                if (a.react[s] == 1) {
+                    R[s] = (m[r] != 0 ? c[0] : 0.0f) - c[1] * phi[s];
+                } else if (a.react[s] == 2 && S == 2) {
+                    const float u2v = phi[0] * phi[0] * phi[S - 1];
+                    R[s] = (s == 0) ? c[2] * (c[0] - phi[0] + u2v) : c[2] * (c[1] - u2v);
+                } else {
+                    R[s] = 0.0f;
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const float os = a.omega_s[s], os1 = 1.0f - a.omega_s[s];
+                const float p3 = 3.0f * phi[s];
+                const float* gg = g[r][s];
+                using T = typename Pop<ST>::T;
+                T* __restrict__ d = (T*)a.gdst + (int64_t)5 * s * nn + o;
+                // equilibrium deviation w_i (dphi + 3 phi v_i . u) and reaction w_i R
+                d[0]      = Pop<ST>::st(os1 * gg[0] + os * Q0 * dphi[s] + Q0 * R[s], SC5[0]);
+                d[nn]     = Pop<ST>::st(os1 * gg[1] + os * Q1 * (dphi[s] + p3 * ux) + Q1 * R[s], SC5[1]);
+                d[2 * nn] = Pop<ST>::st(os1 * gg[2] + os * Q1 * (dphi[s] + p3 * uy) + Q1 * R[s], SC5[2]);
+                d[3 * nn] = Pop<ST>::st(os1 * gg[3] + os * Q1 * (dphi[s] - p3 * ux) + Q1 * R[s], SC5[3]);
+                d[4 * nn] = Pop<ST>::st(os1 * gg[4] + os * Q1 * (dphi[s] - p3 * uy) + Q1 * R[s], SC5[4]);
+            }
         }
     }
 }
@@ -356,25 +437,42 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
 // The spread force field alone (inspection): same tiling and summation as k_lattice.
 __global__ __launch_bounds__(TILE_N) void k_spread_inspect(LatticeArgs a)
 {
+    constexpr int LY = TILE_Y * RPT;
     const int tile = blockIdx.x;
     const int tcol = tile % a.ntx, trow = tile / a.ntx;
-    const int x0 = tcol * TILE_X, y0 = trow * TILE_Y;
+    const int x0 = tcol * TILE_X, y0 = trow * LY;
+    const int x1 = min(x0 + TILE_X, a.nx), y1 = min(y0 + LY, a.ny);
     const int t = threadIdx.x;
-    const int x = x0 + (t % TILE_X), y = y0 + (t / TILE_X);
-    __shared__ unsigned long long accx[TILE_N], accy[TILE_N];
-    __shared__ int tch[TILE_N];
+    __shared__ unsigned long long accx[TILE_X * LY], accy[TILE_X * LY];
     __shared__ int rbeg[MAX_RANGES], rpre[MAX_RANGES];
-    accx[t] = 0ull;
-    accy[t] = 0ull;
-    tch[t] = 0;
-    if (a.bin_off) spread_ranges(a, tcol, trow, x0, y0, rbeg, rpre);
+    for (int r = 0; r < RPT; ++r) {
+        accx[t + r * TILE_N] = 0ull;
+        accy[t + r * TILE_N] = 0ull;
+    }
+    if (a.bin_off) {
+        int beg, len;
+        range_load(a, x0, x1, y0, y1, beg, len);
+        range_publish(beg, len, rbeg, rpre);
+    }
     __syncthreads();
-    if (a.bin_off) spread_tile(a, x0, y0, rbeg, rpre, accx, accy, tch);
+    if (a.bin_off) {
+        const int total = rpre[MAX_RANGES - 1];
+        int cij[SPREAD_UNROLL], cnd[SPREAD_UNROLL];
+        float4 crc[SPREAD_UNROLL];
+        for (int base = 0; base < total; base += SPREAD_UNROLL * TILE_N) {
+            load_candidates(a, base, total, rbeg, rpre, cij, crc, cnd, false);
+            couple_chunk<false>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, nullptr, nullptr);
+        }
+    }
     __syncthreads();
-    if (x >= a.nx || y >= a.ny) return;
-    const int64_t o = (int64_t)y * a.nx + x;
-    a.e_out[o] = (double)(__ll2float_rn((long long)accx[t]) * FIX_INV + a.bodyx);
-    a.e_out[a.nn + o] = (double)(__ll2float_rn((long long)accy[t]) * FIX_INV + a.bodyy);
+    for (int r = 0; r < RPT; ++r) {
+        const int x = x0 + (t % TILE_X), y = y0 + t / TILE_X + r * TILE_Y;
+        if (x >= a.nx || y >= a.ny) continue;
+        const int l = t + r * TILE_N;
+        const int64_t o = (int64_t)y * a.nx + x;
+        a.e_out[o] = (double)(__ll2float_rn((long long)accx[l]) * FIX_INV + a.bodyx);
+        a.e_out[a.nn + o] = (double)(__ll2float_rn((long long)accy[l]) * FIX_INV + a.bodyy);
+    }
 }
 
 // Equilibrium initial state, written in the stored (pre-streaming) layout so that the next
@@ -538,7 +636,7 @@ __global__ void k_reduce_final(const double* partial, int nblocks, int nv, doubl
 template <int S, int ST>
 static hipError_t launch_lattice_s(lbib_ctx* c, const LatticeArgs& a, bool nodes, bool mask)
 {
-    dim3 grid((unsigned)c->nbins), block(TILE_N);
+    dim3 grid((unsigned)c->nltiles), block(TILE_N);
     if (nodes && mask) hipLaunchKernelGGL((k_lattice<S, true, true, ST>), grid, block, 0, c->stream, a);
     else if (nodes) hipLaunchKernelGGL((k_lattice<S, true, false, ST>), grid, block, 0, c->stream, a);
     else if (mask) hipLaunchKernelGGL((k_lattice<S, false, true, ST>), grid, block, 0, c->stream, a);
@@ -567,7 +665,7 @@ hipError_t launch_lattice(lbib_ctx* c, const LatticeArgs& a, bool nodes, bool ma
 
 hipError_t launch_spread_inspect(lbib_ctx* c, const LatticeArgs& a)
 {
-    hipLaunchKernelGGL(k_spread_inspect, dim3((unsigned)c->nbins), dim3(TILE_N), 0, c->stream, a);
+    hipLaunchKernelGGL(k_spread_inspect, dim3((unsigned)c->nltiles), dim3(TILE_N), 0, c->stream, a);
     return hipGetLastError();
 }
 

@@ -16,67 +16,35 @@
 
 namespace lbib {
 
-// u at a node (Eq. conversion2 over the 4x4 stencil); positions satisfy finite2
-__device__ inline float2 interp_u(const MembraneArgs& a, double X, double Y)
-{
-    const double fx = floor(X), fy = floor(Y);
-    float wx[4], wy[4];
-    delta_weights(a.kernel, (float)(X - fx), wx);
-    delta_weights(a.kernel, (float)(Y - fy), wy);
-    const int i0 = wrap_i((int)fx - 1, a.nx);
-    const int j0 = (int)fy - 1;
-    int col[4];
-#pragma unroll
-    for (int aa = 0; aa < 4; ++aa) {
-        int i = i0 + aa;
-        if (i >= a.nx) i -= a.nx;
-        col[aa] = i;
-    }
-    float ux = 0.0f, uy = 0.0f;
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb) {
-        int j = j0 + bb;
-        if (a.walls) {
-            if (j < 0 || j >= a.ny) continue;
-        } else {
-            j = wrap_i(j, a.ny);
-        }
-        const float* row = a.uband + (int64_t)j * a.nx;
-        float sx = 0.0f, sy = 0.0f;
-#pragma unroll
-        for (int aa = 0; aa < 4; ++aa) {
-            sx += wx[aa] * row[col[aa]];
-            sy += wx[aa] * row[a.nn + col[aa]];
-        }
-        ux += wy[bb] * sx;
-        uy += wy[bb] * sy;
-    }
-    return make_float2(ux, uy);
-}
-
 __device__ inline double wave_sum(double v)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
-// is the origin (i0, j0) within the widened tile of bin `key`?
-__device__ inline bool within_margin(int i0, int j0, int key, int nx, int ny, int walls, int ntx)
+// has the stencil origin (i0, j0) moved at most BIN_MARGIN from its value at the last
+// rebinning (packed in ijb)?  Then it is still inside its bin's widened tile.
+__device__ inline bool within_margin(int i0, int j0, int ijb, int nx, int ny, int walls)
 {
-    const int bc = key % ntx, br = key / ntx;
-    const int bx0 = bc * TILE_X, bw = min(TILE_X, nx - bx0);
-    const int by0 = br * TILE_Y, bh = min(TILE_Y, ny - by0);
-    const int dx = wrap_i(i0 - bx0 + BIN_MARGIN, nx);
-    if (bw + 2 * BIN_MARGIN < nx && dx > bw - 1 + 2 * BIN_MARGIN) return false;
+    const int ib = ijb & 0xFFFF, jb = ijb >> 16;
+    int di = i0 - ib;
+    if (di > nx / 2) di -= nx;
+    else if (di < -(nx / 2)) di += nx;
+    if (di > BIN_MARGIN || di < -BIN_MARGIN) return false;
+    int dj;
     if (walls) {
         const int jr = j0 < 0 ? 0 : (j0 >= ny ? ny - 1 : j0);
-        return jr >= by0 - BIN_MARGIN && jr <= by0 + bh - 1 + BIN_MARGIN;
+        const int jbr = jb < 0 ? 0 : (jb >= ny ? ny - 1 : jb);
+        dj = jr - jbr;
+    } else {
+        dj = j0 - jb;
+        if (dj > ny / 2) dj -= ny;
+        else if (dj < -(ny / 2)) dj += ny;
     }
-    const int dy = wrap_i(j0 - by0 + BIN_MARGIN, ny);
-    return !(bh + 2 * BIN_MARGIN < ny && dy > bh - 1 + 2 * BIN_MARGIN);
+    return dj <= BIN_MARGIN && dj >= -BIN_MARGIN;
 }
 
-constexpr int MEM_UNROLL = 4;     // nodes per thread whose loads are issued together
+constexpr int MEM_UNROLL = 2;     // nodes per thread whose loads are issued together
 
 __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
 {
@@ -88,23 +56,32 @@ __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
     const int beg = a.off[c];
     const int n = a.off[c + 1] - beg;
 
-    // 1. interpolate and move
+    // 1. move: X^{n+1} = X^n + U, U interpolated by the lattice pass (fixed point, cleared here)
     for (int base = 0; base < n; base += MEM_UNROLL * MEMBRANE_THREADS) {
         double2 X[MEM_UNROLL];
+        unsigned long long ux[MEM_UNROLL], uy[MEM_UNROLL];
 #pragma unroll
         for (int u = 0; u < MEM_UNROLL; ++u) {
             const int k = base + u * MEMBRANE_THREADS + t;
-            if (k < n) X[u] = a.X[beg + k];
+            if (k >= n) continue;
+            X[u] = a.X[beg + k];
+            if (a.advect) {
+                ux[u] = a.U_acc[2 * (int64_t)(beg + k)];
+                uy[u] = a.U_acc[2 * (int64_t)(beg + k) + 1];
+            }
         }
 #pragma unroll
         for (int u = 0; u < MEM_UNROLL; ++u) {
             const int k = base + u * MEMBRANE_THREADS + t;
             if (k >= n) continue;
-            if (a.advect && finite2(X[u].x, X[u].y)) {
-                const float2 U = interp_u(a, X[u].x, X[u].y);
-                X[u].x += (double)U.x;
-                X[u].y += (double)U.y;
-                a.X[beg + k] = X[u];
+            if (a.advect) {
+                a.U_acc[2 * (int64_t)(beg + k)] = 0ull;
+                a.U_acc[2 * (int64_t)(beg + k) + 1] = 0ull;
+                if (finite2(X[u].x, X[u].y)) {
+                    X[u].x += (double)(long long)ux[u] * UFIX_INV;
+                    X[u].y += (double)(long long)uy[u] * UFIX_INV;
+                    a.X[beg + k] = X[u];
+                }
             }
             xs[k] = X[u];
         }
@@ -140,7 +117,7 @@ __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
             lp[u] = a.l0[beg + k];
             lm[u] = a.l0[beg + km];
             sl[u] = a.slot[beg + k];
-            ky[u] = a.key[beg + k];
+            ky[u] = a.ij_bin[beg + k];
         }
 #pragma unroll
         for (int u = 0; u < MEM_UNROLL; ++u) {
@@ -167,7 +144,7 @@ __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
                 stencil_origin(X.x, X.y, a.nx, a.ny, a.walls, i0, j0);
                 a.rec[s] = make_float4((float)(X.x - fx), (float)(X.y - fy), (float)Fx, (float)Fy);
                 a.rec_ij[s] = pack_ij(i0, j0);
-                if (!within_margin(i0, j0, ky[u], a.nx, a.ny, a.walls, a.ntx)) flags |= ERR_MARGIN;
+                if (!within_margin(i0, j0, ky[u], a.nx, a.ny, a.walls)) flags |= ERR_MARGIN;
             } else {
                 a.rec[s] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 a.rec_ij[s] = 0;
@@ -195,11 +172,14 @@ __global__ void k_bin_count(BinArgs a)
     if (live) {
         const double2 X = a.X[l];
         key = 0;
+        int ij = 0;
         if (finite2(X.x, X.y)) {
             int i0, j0;
             stencil_origin(X.x, X.y, a.nx, a.ny, a.walls, i0, j0);
             key = bin_of(i0, j0, a.ny, a.ntx);
+            ij = pack_ij(i0, j0);
         }
+        a.ij_bin[l] = ij;
     }
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -276,6 +256,7 @@ __global__ void k_bin_scatter(BinArgs a)
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= a.n) return;
     const int s = a.off[a.key[l]] + a.rank[l];
+    a.rec_node[s] = (int)l;
     if (a.copy) {
         const int o = a.slot[l];
         a.rec_new[s] = a.rec_old[o];

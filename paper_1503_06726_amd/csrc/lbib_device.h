@@ -18,11 +18,12 @@
 
 namespace lbib {
 
-// lattice tile of one workgroup: 64 x 4 nodes, one 64-wide wavefront per row
+// bin tile: 64 x 4 nodes (a 256-thread workgroup, one 64-wide wavefront per row)
 constexpr int TILE_X = 64;
 constexpr int TILE_Y = 4;
 constexpr int TILE_N = TILE_X * TILE_Y;
 
+constexpr int RPT = 2;               // lattice rows per thread: a lattice tile is TILE_X x (TILE_Y * RPT)
 constexpr int BIN_MARGIN = 2;        // lattice units a node may drift from its bin's tile
 constexpr int REBIN_PERIOD = 8;      // steps between rebinnings
 
@@ -39,6 +40,11 @@ constexpr int SCAN_PER_THREAD = 8;
 constexpr float FIX_SCALE = 281474976710656.0f;          // 2^48
 constexpr float FIX_INV = 1.0f / 281474976710656.0f;     // 2^-48 (exact)
 constexpr float FIX_CLAMP = 16384.0f;                    // |contribution| bound, keeps sums in range
+// Interpolated node velocities are summed over lattice tiles in 64-bit fixed point too:
+// value = integer * 2^-44 (|U| stays far below the 2^19 range).
+constexpr float UFIX_SCALE = 17592186044416.0f;          // 2^44
+constexpr double UFIX_INV = 1.0 / 17592186044416.0;      // 2^-44 (exact)
+constexpr float UFIX_CLAMP = 4096.0f;
 
 // error flags (device int, OR-ed)
 constexpr int ERR_NONFINITE = 1;     // a node position or force became non-finite
@@ -61,7 +67,8 @@ struct LatticeArgs {
     const int* __restrict__ bin_off;   // [nbins + 1]
     const float4* __restrict__ rec;    // (sx, sy, Fx, Fy) per binned node
     const int* __restrict__ rec_ij;    // packed stencil origin (i0 | j0 << 16)
-    float* __restrict__ uband;         // [2][ny][nx], written where a node stencil reaches
+    const int* __restrict__ rec_node;  // node index of each record
+    unsigned long long* __restrict__ U_acc;   // [N][2] interpolated velocity, fixed point
     uint16_t* __restrict__ mask;       // domain IDs; read, then cleared for the next raster
     // inspection output (spread field only)
     double* __restrict__ e_out;
@@ -73,9 +80,9 @@ struct MembraneArgs {
     const double* __restrict__ l0;
     const double* __restrict__ A0;
     double* __restrict__ area;
-    const float* __restrict__ uband;
+    unsigned long long* __restrict__ U_acc;   // [N][2] interpolated velocity, read and cleared
     const int* __restrict__ slot;      // record slot of each node
-    const int* __restrict__ key;       // bin of each node at the last rebinning
+    const int* __restrict__ ij_bin;    // packed stencil origin of each node at the last rebinning
     float4* __restrict__ rec;
     int* __restrict__ rec_ij;
     uint16_t* __restrict__ mask;       // written when raster != 0
@@ -89,6 +96,8 @@ struct MembraneArgs {
 
 struct BinArgs {
     const double2* __restrict__ X;
+    int* __restrict__ ij_bin;          // stencil origin at this rebinning
+    int* __restrict__ rec_node;        // node index of each record slot (of the buffer in use next)
     int* __restrict__ key;
     int* __restrict__ rank;
     int* __restrict__ count;           // zeroed by the scan after use

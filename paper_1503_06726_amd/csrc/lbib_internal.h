@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lbib.h"
+#include "lbib.h"
 #include "lbib_device.h"
 
 namespace lbib {
@@ -33,7 +33,8 @@ struct lbib_ctx {
 
     int64_t nn = 0;          // nx * ny
     int S = 0;               // species
-    int ntx = 0, nty = 0, nbins = 0;
+    int ntx = 0, nty = 0, nbins = 0;   // bin tiles (TILE_X x TILE_Y)
+    int nlty = 0, nltiles = 0;         // lattice tiles (TILE_X x TILE_Y * RPT)
     bool mask_needed = false;
 
     // lattice state: post-collision deviations (FP32, FP16 or BF16), A/B buffers
@@ -41,7 +42,6 @@ struct lbib_ctx {
     void* g[2] = {nullptr, nullptr};
     size_t pop_bytes = 4;            // bytes per stored population
     int cur = 0;
-    float* uband = nullptr;          // [2][ny][nx]
     uint16_t* mask = nullptr;        // [ny][nx]
 
     // membranes
@@ -56,6 +56,9 @@ struct lbib_ctx {
     int* d_key = nullptr;            // bin of each node at the last rebinning
     int* d_rank = nullptr;           // rank within that bin
     int* d_slot = nullptr;           // record slot of each node
+    int* d_ijbin = nullptr;          // stencil origin of each node at the last rebinning
+    unsigned long long* d_U = nullptr;   // [N][2] interpolated velocities, fixed point
+    int* d_rec_node[2] = {nullptr, nullptr};
     float4* d_rec[2] = {nullptr, nullptr};   // spreading records, current and spare
     int* d_rec_ij[2] = {nullptr, nullptr};
     int rec_cur = 0;

@@ -5,7 +5,7 @@
 #include <cstring>
 #include <string>
 
-#include "../../include/lbib.h"
+#include "lbib.h"
 
 namespace lbib {
 
