@@ -362,6 +362,66 @@ lbib_status init_fields(lbib_ctx* c, const double* rho, const double* u, const d
     return LBIB_OK;
 }
 
+// one coupled step, launched directly on the context's stream
+lbib_status one_step(lbib_ctx* c)
+{
+    const bool nodes = c->n_cells > 0;
+    {
+        Timed tm(c, LBIB_K_LATTICE);
+        LBIB_LAUNCH(c, launch_lattice(c, lattice_args(c), nodes, c->mask_needed));
+    }
+    c->cur = 1 - c->cur;
+    if (nodes) {
+        LBIB_TRY(membrane(c, 1));
+        if (++c->steps_since_rebin >= REBIN_PERIOD) LBIB_TRY(rebin(c, 1));
+    }
+    if (c->timing && c->pending.size() > 4096) LBIB_TRY(harvest(c));
+    return LBIB_OK;
+}
+
+void drop_graphs(lbib_ctx* c)
+{
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            if (c->graph[i][j]) {
+                (void)hipGraphExecDestroy(c->graph[i][j]);
+                c->graph[i][j] = nullptr;
+            }
+}
+
+// Capture GRAPH_STEPS steps (kernels only: no memsets or copies) on a private stream.  The
+// kernels' arguments follow the buffer parities, which are back where they started after the
+// period, so the host-side state is restored once the capture ends.
+lbib_status capture_steps(lbib_ctx* c, hipGraphExec_t* out)
+{
+    if (!c->capture_stream) LBIB_HIP(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+    const int cur0 = c->cur, rec0 = c->rec_cur, since0 = c->steps_since_rebin;
+    hipStream_t user = c->stream;
+    c->stream = c->capture_stream;
+    hipGraph_t graph = nullptr;
+    lbib_status st = LBIB_OK;
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        st = LBIB_EDEVICE;
+    } else {
+        for (int k = 0; k < GRAPH_STEPS && st == LBIB_OK; ++k) st = one_step(c);
+        hipError_t e = hipStreamEndCapture(c->stream, &graph);
+        if (st == LBIB_OK && e != hipSuccess) st = LBIB_EDEVICE;
+    }
+    c->stream = user;
+    c->cur = cur0;
+    c->rec_cur = rec0;
+    c->steps_since_rebin = since0;
+    if (st == LBIB_OK && hipGraphInstantiate(out, graph, nullptr, nullptr, 0) != hipSuccess) st = LBIB_EDEVICE;
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st != LBIB_OK) {
+        *out = nullptr;
+        c->use_graphs = false;          // fall back to direct launches
+        if (c->err.empty()) c->err = "step graph capture failed; using direct launches";
+        return LBIB_OK;
+    }
+    return LBIB_OK;
+}
+
 }  // namespace
 
 // =======================================================================================
@@ -462,6 +522,8 @@ void lbib_destroy(lbib_ctx* c)
 {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     free_all(c);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
@@ -477,6 +539,7 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
         return LBIB_EINVAL;
     }
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
     free_nodes(c);
     if (n_cells == 0) return LBIB_OK;
     const size_t N = (size_t)off[n_cells], C = (size_t)n_cells;
@@ -564,18 +627,19 @@ lbib_status lbib_step(lbib_ctx* c, int32_t n)
         c->err = "negative step count";
         return LBIB_EINVAL;
     }
-    const bool nodes = c->n_cells > 0;
-    for (int32_t k = 0; k < n; ++k) {
-        {
-            Timed tm(c, LBIB_K_LATTICE);
-            LBIB_LAUNCH(c, launch_lattice(c, lattice_args(c), nodes, c->mask_needed));
+    while (n > 0) {
+        // whole periods of GRAPH_STEPS steps replay a captured graph (not while timing kernels)
+        if (c->use_graphs && !c->timing && n >= GRAPH_STEPS && c->steps_since_rebin == 0) {
+            hipGraphExec_t& g = c->graph[c->cur][c->rec_cur];
+            if (!g) LBIB_TRY(capture_steps(c, &g));
+            if (g) {
+                LBIB_HIP(c, hipGraphLaunch(g, c->stream));
+                n -= GRAPH_STEPS;        // buffer parities are the same again after the period
+                continue;
+            }
         }
-        c->cur = 1 - c->cur;
-        if (nodes) {
-            LBIB_TRY(membrane(c, 1));
-            if (++c->steps_since_rebin >= REBIN_PERIOD) LBIB_TRY(rebin(c, 1));
-        }
-        if (c->timing && c->pending.size() > 4096) LBIB_TRY(harvest(c));
+        LBIB_TRY(one_step(c));
+        --n;
     }
     return LBIB_OK;
 }

@@ -26,6 +26,7 @@ constexpr int TILE_N = TILE_X * TILE_Y;
 constexpr int RPT = 2;               // lattice rows per thread: a lattice tile is TILE_X x (TILE_Y * RPT)
 constexpr int BIN_MARGIN = 2;        // lattice units a node may drift from its bin's tile
 constexpr int REBIN_PERIOD = 8;      // steps between rebinnings
+constexpr int GRAPH_STEPS = 16;      // steps per captured graph: buffer parities repeat after it
 
 constexpr int MEMBRANE_THREADS = 256;
 constexpr int MAX_CELL_NODES = 4096;            // LDS holds one cell's positions as double2

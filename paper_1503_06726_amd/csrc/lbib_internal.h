@@ -75,6 +75,12 @@ struct lbib_ctx {
 
     size_t device_bytes = 0;
 
+    // captured step sequences: GRAPH_STEPS steps starting with no steps since the last
+    // rebinning, one graph per parity (cur, rec_cur) of the buffers at the start
+    bool use_graphs = true;
+    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipStream_t capture_stream = nullptr;
+
     // timing
     bool timing = false;
     std::vector<lbib::TimedLaunch> pending;

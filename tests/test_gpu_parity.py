@@ -273,3 +273,31 @@ def test_reduced_precision_storage(storage, bound, case):
     for k in ("rho", "u", "X", "phi"):
         if k in errs:
             assert errs[k] < bound, (k, errs[k])
+
+
+# ------------------------------------------------------------------------------------------
+# captured step graphs: whole 16-step periods replay a graph; single steps launch directly.
+# Every replay (with eager work and synchronisation in between) must match direct launches
+# bit for bit.
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["walls", "periodic"])
+def test_graph_replays_match_direct_launches(case):
+    w = CELL_CASES[case]()
+    a = lbib.from_workload(w)
+    b = lbib.from_workload(w)
+    for rep in range(4):
+        a.step(16)                       # one graph replay
+        for _ in range(16):
+            b.step(1)                    # direct launches
+        A, B = a.get_fields(), b.get_fields()
+        for k in ("rho", "u", "phi", "xy", "mask"):
+            assert np.array_equal(A[k], B[k]), (rep, k)
+        a.reduce()                       # eager work between replays
+    a.step(40)                           # 2 replays + 8 direct steps
+    for _ in range(40):
+        b.step(1)
+    A, B = a.get_fields(), b.get_fields()
+    for k in ("rho", "u", "phi", "xy", "mask"):
+        assert np.array_equal(A[k], B[k]), k
+    a.close()
+    b.close()
