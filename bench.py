@@ -20,23 +20,26 @@ METRIC = "coupled LBM+IB MLUPS at 2048²/2000 cells (% HBM peak); ADE iters-to-s
 HBM_PEAK_GBS = 8000.0
 # HBM traffic per launch of the lattice kernel measured with rocprofv3 --pmc (FETCH_SIZE,
 # WRITE_SIZE, scaled by a copy kernel of known size); None until taken for the current kernel
-LATTICE_TRAFFIC_BYTES = None
+LATTICE_TRAFFIC_BYTES = 543_985_664
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def lattice_bytes_per_update(S: int, mask: bool) -> int:
-    """Algorithmic bytes per lattice node of one lattice pass: every FP32 population read
-    once and written once, plus the 16-bit domain ID read."""
-    return 4 * 2 * (9 + 5 * S) + (2 if mask else 0)
+POP_BYTES = {"fp32": 4, "fp16": 2, "bf16": 2}
 
 
-def step_bytes_per_update(S: int, mask: bool, n_nodes: int, nn: int) -> float:
+def lattice_bytes_per_update(S: int, mask: bool, pop_bytes: int = 4) -> int:
+    """Algorithmic bytes per lattice node of one lattice pass: every population read once and
+    written once, plus the 16-bit domain ID read."""
+    return pop_bytes * 2 * (9 + 5 * S) + (2 if mask else 0)
+
+
+def step_bytes_per_update(S: int, mask: bool, n_nodes: int, nn: int, pop_bytes: int = 4) -> float:
     """Algorithmic bytes per lattice node of a whole step: the lattice pass plus the node
     positions read and written (16 B per node, FP64 x and y)."""
-    return lattice_bytes_per_update(S, mask) + 16.0 * n_nodes / nn
+    return lattice_bytes_per_update(S, mask, pop_bytes) + 16.0 * n_nodes / nn
 
 
 def cpu_baseline(w, budget_s: float = 12.0, max_steps: int = 30):
@@ -63,6 +66,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="large", choices=["large", "tissue", "tiny"])
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"],
+                    help="population storage (collision always in FP32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain device copy of 1 GiB (calibrates the HBM byte counters)")
@@ -91,23 +96,31 @@ def main():
     mask = w.mask_needed()
     log(f"workload: {w.name}, {w.n_nodes} nodes")
     stream = torch.cuda.current_stream().cuda_stream
-    sim = lbib.from_workload(w, stream=stream)
+    storage = {"fp32": lbib.STORAGE_FP32, "fp16": lbib.STORAGE_FP16, "bf16": lbib.STORAGE_BF16}[args.storage]
+    pb = POP_BYTES[args.storage]
+    sim = lbib.from_workload(w, stream=stream, storage=storage)
     log(f"device memory: {sim.device_bytes() / 2**20:.1f} MiB")
     sim.step(args.warmup)
     sim.sync()
     torch.cuda.synchronize()
     log(f"warmup {args.warmup} steps done")
 
-    sim.set_timing(True)
+    # timed region: the production path (whole 16-step periods replay captured graphs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(args.steps)
     sim.sync()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    log(f"timed {args.steps} steps: {dt:.3f} s")
+
+    # kernel durations: HIP events around every launch on the library's stream (direct
+    # launches; a kernel runs the same whether launched directly or from a graph)
+    kt_steps = min(args.steps, 256)
+    sim.set_timing(True)
+    sim.step(kt_steps)
     timings = {lbib.KERNEL_NAMES[k]: sim.get_timing(k) for k in range(len(lbib.KERNEL_NAMES))}
     sim.set_timing(False)
-    log(f"timed {args.steps} steps: {dt:.3f} s")
     for k, (ms, n) in timings.items():
         if n:
             log(f"  {k:12s} {ms / n * 1e3:9.2f} us/launch  ({n} launches)")
@@ -120,12 +133,12 @@ def main():
     mlups = nn * args.steps / dt / 1e6
     lat_ms, lat_n = timings["lattice"]
     lat_s = lat_ms / lat_n / 1e3
-    b_lat = lattice_bytes_per_update(S, mask)
+    b_lat = lattice_bytes_per_update(S, mask, pb)
     achieved = b_lat * nn / lat_s / 1e9
-    b_step = step_bytes_per_update(S, mask, w.n_nodes, nn)
+    b_step = step_bytes_per_update(S, mask, w.n_nodes, nn, pb)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": LATTICE_TRAFFIC_BYTES,
+            "traffic": LATTICE_TRAFFIC_BYTES if args.storage == "fp32" and w.name == "large" else None,
             "kernel": "k_lattice", "bytes_per_update": b_lat, "us_per_launch": round(lat_s * 1e6, 2),
             "step_bytes_per_update": round(b_step, 2),
             "step_frac": round(b_step * mlups * 1e6 / 1e9 / HBM_PEAK_GBS, 4)}
@@ -134,7 +147,7 @@ def main():
            "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic (seeded Voronoi tissue, SeedSequence(1503))",
            "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "n_cells": w.n_cells, "n_nodes": w.n_nodes,
-                      "species": S, "tau": w.tau, "storage": "fp32 deviations, fp64 node positions"},
+                      "species": S, "tau": w.tau, "storage": f"{args.storage} population deviations, fp64 node positions"},
            "roofline": roof,
            "kernels_us": {k: round(ms / n * 1e3, 2) for k, (ms, n) in timings.items() if n},
            "mass": red[0]}

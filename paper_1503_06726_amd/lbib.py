@@ -260,9 +260,13 @@ class Simulation:
         return int(b.value)
 
 
-def from_workload(w, stream: int | None = None) -> Simulation:
-    """A Simulation initialised from a ``workloads.Workload``."""
-    s = Simulation(w.params_dict(), stream=stream)
+def from_workload(w, stream: int | None = None, storage: int | None = None) -> Simulation:
+    """A Simulation initialised from a ``workloads.Workload`` (``storage`` overrides the
+    population storage, one of the STORAGE_* constants)."""
+    d = w.params_dict()
+    if storage is not None:
+        d["storage"] = storage
+    s = Simulation(d, stream=stream)
     if w.rho_init is not None or w.u_init is not None or w.phi_init is not None:
         s.set_fields(w.rho_init, w.u_init, w.phi_init)
     if w.n_cells:
