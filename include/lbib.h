@@ -159,10 +159,10 @@ lbib_status lbib_sync(lbib_ctx* ctx);
 
 /* Per-kernel timing with HIP events on the context's stream (0 disables, default).
  * Ids: LBIB_K_LATTICE (the lattice pass), LBIB_K_MEMBRANE (interpolation, advection, forces,
- * domain IDs), LBIB_K_REBIN (refiling the nodes by lattice tile, every few steps).
+ * domain IDs), LBIB_K_LISTS (rebuilding the per-tile lists of membrane nodes, every few steps).
  * lbib_get_timing synchronises and returns the summed milliseconds and the number of timed
  * launches since timing was last enabled. */
-enum { LBIB_K_LATTICE = 0, LBIB_K_MEMBRANE = 1, LBIB_K_REBIN = 2, LBIB_K_COUNT = 3 };
+enum { LBIB_K_LATTICE = 0, LBIB_K_MEMBRANE = 1, LBIB_K_LISTS = 2, LBIB_K_COUNT = 3 };
 lbib_status lbib_set_timing(lbib_ctx* ctx, int32_t enable);
 lbib_status lbib_get_timing(lbib_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches);
 

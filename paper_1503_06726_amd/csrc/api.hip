@@ -121,7 +121,6 @@ LatticeArgs lattice_args(lbib_ctx* c)
     a.ny = p.ny;
     a.walls = p.bc_y == LBIB_WALLS;
     a.ntx = c->ntx;
-    a.nty = c->nty;
     a.omega = (float)(1.0 / p.tau);
     a.rho0 = (float)p.rho0;
     for (int s = 0; s < 2; ++s) {
@@ -135,10 +134,10 @@ LatticeArgs lattice_args(lbib_ctx* c)
     a.bodyx = (float)p.body_accel[0];
     a.bodyy = (float)p.body_accel[1];
     a.kernel = p.delta_kernel;
-    a.bin_off = c->d_bin_off;
-    a.rec = c->d_rec[c->rec_cur];
-    a.rec_ij = c->d_rec_ij[c->rec_cur];
-    a.rec_node = c->d_rec_node[c->rec_cur];
+    a.t_off = c->n_cells ? c->d_t_off : nullptr;
+    a.t_list = c->d_list;
+    a.rec = c->d_rec;
+    a.rec_ij = c->d_rec_ij;
     a.U_acc = c->d_U;
     a.mask = c->mask;
     a.e_out = nullptr;
@@ -155,10 +154,9 @@ MembraneArgs membrane_args(lbib_ctx* c, int advect)
     a.A0 = c->d_A0;
     a.area = c->d_area;
     a.U_acc = c->d_U;
-    a.slot = c->d_slot;
-    a.ij_bin = c->d_ijbin;
-    a.rec = c->d_rec[c->rec_cur];
-    a.rec_ij = c->d_rec_ij[c->rec_cur];
+    a.ij_list = c->d_ijlist;
+    a.rec = c->d_rec;
+    a.rec_ij = c->d_rec_ij;
     a.mask = c->mask;
     a.err = c->d_err;
     a.nn = c->nn;
@@ -166,8 +164,6 @@ MembraneArgs membrane_args(lbib_ctx* c, int advect)
     a.ny = c->p.ny;
     a.walls = c->p.bc_y == LBIB_WALLS;
     a.kernel = c->p.delta_kernel;
-    a.ntx = c->ntx;
-    a.nty = c->nty;
     a.k_spring = c->p.k_spring;
     a.phi_m = c->p.phi_m;
     a.kappa = c->p.kappa_area;
@@ -176,29 +172,23 @@ MembraneArgs membrane_args(lbib_ctx* c, int advect)
     return a;
 }
 
-BinArgs bin_args(lbib_ctx* c, int copy)
+ListArgs list_args(lbib_ctx* c)
 {
-    BinArgs a;
+    ListArgs a;
     std::memset(&a, 0, sizeof a);
     a.X = c->d_X;
-    a.ij_bin = c->d_ijbin;
-    a.rec_node = c->d_rec_node[copy ? 1 - c->rec_cur : c->rec_cur];
-    a.key = c->d_key;
-    a.rank = c->d_rank;
-    a.count = c->d_bin_count;
-    a.off = c->d_bin_off;
-    a.slot = c->d_slot;
-    a.rec_old = c->d_rec[c->rec_cur];
-    a.ij_old = c->d_rec_ij[c->rec_cur];
-    a.rec_new = c->d_rec[1 - c->rec_cur];
-    a.ij_new = c->d_rec_ij[1 - c->rec_cur];
+    a.ij_list = c->d_ijlist;
+    a.count = c->d_t_count;
+    a.off = c->d_t_off;
+    a.cursor = c->d_t_cur;
+    a.list = c->d_list;
     a.n = c->n_nodes;
     a.nx = c->p.nx;
     a.ny = c->p.ny;
     a.walls = c->p.bc_y == LBIB_WALLS;
     a.ntx = c->ntx;
-    a.nbins = c->nbins;
-    a.copy = copy;
+    a.nlty = c->nlty;
+    a.ntiles = c->nltiles;
     return a;
 }
 
@@ -223,15 +213,14 @@ RasterArgs raster_args(lbib_ctx* c)
         }                                                                                    \
     } while (0)
 
-// File every node under the lattice tile of its current stencil origin; with copy set, the
-// records move from their old slots (the spare record buffer becomes the current one).
-lbib_status rebin(lbib_ctx* c, int copy)
+// List every node in the lattice tiles its stencil can reach from its current position
+// (within the drift margin).
+lbib_status build_lists(lbib_ctx* c)
 {
-    Timed tm(c, LBIB_K_REBIN);
-    const BinArgs a = bin_args(c, copy);
-    for (int which = 0; which < 3; ++which) LBIB_LAUNCH(c, launch_rebin(c, a, which));
-    if (copy) c->rec_cur = 1 - c->rec_cur;
-    c->steps_since_rebin = 0;
+    Timed tm(c, LBIB_K_LISTS);
+    const ListArgs a = list_args(c);
+    for (int which = 0; which < 3; ++which) LBIB_LAUNCH(c, launch_lists(c, a, which));
+    c->steps_since_lists = 0;
     return LBIB_OK;
 }
 
@@ -267,7 +256,7 @@ lbib_status check_err_flag(lbib_ctx* c)
         return LBIB_ENUMERIC;
     }
     if (h & ERR_MARGIN) {
-        c->err = "a membrane node moved more than 2 lattice units between rebinnings (velocity too large)";
+        c->err = "a membrane node moved more than 2 lattice units between list rebuilds (velocity too large)";
         return LBIB_ENUMERIC;
     }
     return LBIB_OK;
@@ -281,22 +270,16 @@ void free_nodes(lbib_ctx* c)
     dev_free(c, c->d_l0, N);
     dev_free(c, c->d_A0, C);
     dev_free(c, c->d_area, C);
-    dev_free(c, c->d_key, N);
-    dev_free(c, c->d_rank, N);
-    dev_free(c, c->d_slot, N);
-    dev_free(c, c->d_ijbin, N);
+    dev_free(c, c->d_ijlist, N);
     dev_free(c, c->d_U, 2 * N);
-    for (int b = 0; b < 2; ++b) {
-        dev_free(c, c->d_rec[b], N);
-        dev_free(c, c->d_rec_ij[b], N);
-        dev_free(c, c->d_rec_node[b], N);
-    }
-    c->rec_cur = 0;
+    dev_free(c, c->d_rec, N);
+    dev_free(c, c->d_rec_ij, N);
+    dev_free(c, c->d_list, N * MAX_NODE_TILES);
     c->n_nodes = 0;
     c->n_cells = 0;
     c->max_cell_nodes = 0;
     c->mask_needed = false;
-    c->steps_since_rebin = 0;
+    c->steps_since_lists = 0;
 }
 
 void free_all(lbib_ctx* c)
@@ -311,8 +294,9 @@ void free_all(lbib_ctx* c)
         c->f[b] = c->g[b] = nullptr;
     }
     dev_free(c, c->mask, nn);
-    dev_free(c, c->d_bin_count, (size_t)c->nbins);
-    dev_free(c, c->d_bin_off, (size_t)c->nbins + 1);
+    dev_free(c, c->d_t_count, (size_t)c->nltiles);
+    dev_free(c, c->d_t_off, (size_t)c->nltiles + 1);
+    dev_free(c, c->d_t_cur, (size_t)c->nltiles);
     dev_free(c, c->d_err, 1);
     dev_free(c, c->d_partial, c->partial_count * 5);
     if (c->d_stage) dev_free(c, c->d_stage, c->stage_bytes / sizeof(double));
@@ -373,7 +357,7 @@ lbib_status one_step(lbib_ctx* c)
     c->cur = 1 - c->cur;
     if (nodes) {
         LBIB_TRY(membrane(c, 1));
-        if (++c->steps_since_rebin >= REBIN_PERIOD) LBIB_TRY(rebin(c, 1));
+        if (++c->steps_since_lists >= LIST_PERIOD) LBIB_TRY(build_lists(c));
     }
     if (c->timing && c->pending.size() > 4096) LBIB_TRY(harvest(c));
     return LBIB_OK;
@@ -382,20 +366,19 @@ lbib_status one_step(lbib_ctx* c)
 void drop_graphs(lbib_ctx* c)
 {
     for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j)
-            if (c->graph[i][j]) {
-                (void)hipGraphExecDestroy(c->graph[i][j]);
-                c->graph[i][j] = nullptr;
-            }
+        if (c->graph[i]) {
+            (void)hipGraphExecDestroy(c->graph[i]);
+            c->graph[i] = nullptr;
+        }
 }
 
 // Capture GRAPH_STEPS steps (kernels only: no memsets or copies) on a private stream.  The
-// kernels' arguments follow the buffer parities, which are back where they started after the
+// kernels' arguments follow the buffer parity, which is back where it started after the
 // period, so the host-side state is restored once the capture ends.
 lbib_status capture_steps(lbib_ctx* c, hipGraphExec_t* out)
 {
     if (!c->capture_stream) LBIB_HIP(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
-    const int cur0 = c->cur, rec0 = c->rec_cur, since0 = c->steps_since_rebin;
+    const int cur0 = c->cur, since0 = c->steps_since_lists;
     hipStream_t user = c->stream;
     c->stream = c->capture_stream;
     hipGraph_t graph = nullptr;
@@ -409,8 +392,7 @@ lbib_status capture_steps(lbib_ctx* c, hipGraphExec_t* out)
     }
     c->stream = user;
     c->cur = cur0;
-    c->rec_cur = rec0;
-    c->steps_since_rebin = since0;
+    c->steps_since_lists = since0;
     if (st == LBIB_OK && hipGraphInstantiate(out, graph, nullptr, nullptr, 0) != hipSuccess) st = LBIB_EDEVICE;
     if (graph) (void)hipGraphDestroy(graph);
     if (st != LBIB_OK) {
@@ -478,9 +460,7 @@ lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out)
     c->nn = (int64_t)p->nx * p->ny;
     c->S = p->n_species;
     c->ntx = (p->nx + TILE_X - 1) / TILE_X;
-    c->nty = (p->ny + TILE_Y - 1) / TILE_Y;
-    c->nbins = c->ntx * c->nty;
-    c->nlty = (p->ny + TILE_Y * RPT - 1) / (TILE_Y * RPT);
+    c->nlty = (p->ny + LTILE_Y - 1) / LTILE_Y;
     c->nltiles = c->ntx * c->nlty;
     c->partial_count = 4096;
     const size_t nn = (size_t)c->nn;
@@ -497,13 +477,14 @@ lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out)
         }
     }
     if (s == LBIB_OK) s = dev_alloc(c, &c->mask, nn);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_bin_count, (size_t)c->nbins);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_bin_off, (size_t)c->nbins + 1);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_count, (size_t)c->nltiles);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_off, (size_t)c->nltiles + 1);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_cur, (size_t)c->nltiles);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_err, 1);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_partial, c->partial_count * 5);
     if (s == LBIB_OK && (launch_fill_u16(c, c->mask, c->nn) != hipSuccess ||
-                         launch_fill_i32(c, c->d_bin_count, c->nbins, 0) != hipSuccess ||
-                         launch_fill_i32(c, c->d_bin_off, c->nbins + 1, 0) != hipSuccess ||
+                         launch_fill_i32(c, c->d_t_count, c->nltiles, 0) != hipSuccess ||
+                         launch_fill_i32(c, c->d_t_off, c->nltiles + 1, 0) != hipSuccess ||
                          launch_fill_i32(c, c->d_err, 1, 0) != hipSuccess))
         s = LBIB_EDEVICE;
     if (s == LBIB_OK) s = init_fields(c, nullptr, nullptr, nullptr);
@@ -566,16 +547,11 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_l0, N);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_A0, C);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_area, C);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_key, N);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_rank, N);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_slot, N);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_ijbin, N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_ijlist, N);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_U, 2 * N);
-    for (int b = 0; b < 2 && s == LBIB_OK; ++b) {
-        s = dev_alloc(c, &c->d_rec[b], N);
-        if (s == LBIB_OK) s = dev_alloc(c, &c->d_rec_ij[b], N);
-        if (s == LBIB_OK) s = dev_alloc(c, &c->d_rec_node[b], N);
-    }
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_rec, N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_rec_ij, N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_list, N * MAX_NODE_TILES);
     c->n_cells = n_cells;
     c->n_nodes = (int64_t)N;
     if (s != LBIB_OK) {
@@ -588,11 +564,11 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
     LBIB_HIP(c, hipMemcpyAsync(c->d_X, xy, N * sizeof(double2), hipMemcpyHostToDevice, c->stream));
     LBIB_HIP(c, hipMemcpyAsync(c->d_l0, l0.data(), N * sizeof(double), hipMemcpyHostToDevice, c->stream));
     LBIB_HIP(c, hipMemcpyAsync(c->d_A0, A0.data(), C * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    LBIB_LAUNCH(c, launch_fill_i32(c, c->d_bin_count, c->nbins, 0));
+    LBIB_LAUNCH(c, launch_fill_i32(c, c->d_t_count, c->nltiles, 0));
     LBIB_LAUNCH(c, launch_fill_i32(c, c->d_err, 1, 0));
     LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->d_U, 4 * (int64_t)N, 0));
     if (c->mask_needed) LBIB_LAUNCH(c, launch_fill_u16(c, c->mask, c->nn));
-    LBIB_TRY(rebin(c, 0));
+    LBIB_TRY(build_lists(c));
     LBIB_TRY(membrane(c, 0));
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
     return check_err_flag(c);
@@ -629,8 +605,8 @@ lbib_status lbib_step(lbib_ctx* c, int32_t n)
     }
     while (n > 0) {
         // whole periods of GRAPH_STEPS steps replay a captured graph (not while timing kernels)
-        if (c->use_graphs && !c->timing && n >= GRAPH_STEPS && c->steps_since_rebin == 0) {
-            hipGraphExec_t& g = c->graph[c->cur][c->rec_cur];
+        if (c->use_graphs && !c->timing && n >= GRAPH_STEPS && c->steps_since_lists == 0) {
+            hipGraphExec_t& g = c->graph[c->cur];
             if (!g) LBIB_TRY(capture_steps(c, &g));
             if (g) {
                 LBIB_HIP(c, hipGraphLaunch(g, c->stream));
@@ -706,7 +682,7 @@ lbib_status lbib_get_spread(lbib_ctx* c, double* e)
     LBIB_TRY(ensure_stage(c, 2 * nn));
     LatticeArgs a = lattice_args(c);
     a.e_out = c->d_stage;
-    if (!c->n_cells) a.bin_off = nullptr;
+    if (!c->n_cells) a.t_off = nullptr;
     LBIB_LAUNCH(c, launch_spread_inspect(c, a));
     LBIB_HIP(c, hipMemcpyAsync(e, c->d_stage, 2 * nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     LBIB_HIP(c, hipStreamSynchronize(c->stream));

@@ -1,17 +1,18 @@
 // Lattice kernels of the coupled step (gfx950).
 //
-// k_lattice: one fused pass per time step over the whole lattice, one 64x4 tile per
+// k_lattice: one fused pass per time step over the whole lattice, one 64x8 tile per
 // workgroup.  Per tile:
-//   1. spread the membrane forces of the nodes whose 4x4 stencil reaches the tile
-//      (Eq. forcedistribution with the kernel of Eq. 1Dkernel), summed in LDS in 64-bit
-//      fixed point so the result does not depend on node order;
-//   2. per lattice node: pull the D2Q9 populations (streaming of Eq. bgkequation, halfway
-//      bounce-back at walls), take rho and u = sum f v / rho, collide with the BGK operator
-//      and the body-force term w_i rho (v_i . e) / cs2, store;
-//   3. per species: pull the D2Q5 populations, take phi, add the reaction, collide towards
-//      phi w_i (1 + v_i . u / cs2) with the fluid's u, store;
-//   4. write u where a node stencil reaches (read by the membrane kernel's interpolation),
-//      read the domain ID and clear it for the next rasterisation.
+//   1. per lattice node: pull the D2Q9 populations (streaming of Eq. bgkequation, halfway
+//      bounce-back at walls) and take rho and u = sum f v / rho (u staged in LDS);
+//   2. for every membrane node in the tile's list: spread its force over the stencil points
+//      inside the tile (Eq. forcedistribution with the kernel of Eq. 1Dkernel), summed in LDS
+//      in 64-bit fixed point so the result does not depend on node order, and add the tile's
+//      share of the interpolated velocity (Eq. conversion2) to the node's fixed-point
+//      accumulator;
+//   3. collide with the BGK operator and the body-force term w_i rho (v_i . e) / cs2, store;
+//   4. per species: pull the D2Q5 populations, take phi, add the reaction, collide towards
+//      phi w_i (1 + v_i . u / cs2) with the fluid's u, store; read the domain ID and clear it
+//      for the next rasterisation.
 // The pass reads every population once and writes it once: it is HBM-bandwidth bound.
 #include "lbib_internal.h"
 
@@ -98,90 +99,7 @@ __device__ inline unsigned long long to_fixed(float v)
     return (unsigned long long)__float2ll_rn(v * FIX_SCALE);
 }
 
-// do the cyclic intervals [a0, a0 + alen) and [b0, b0 + blen) of Z_n meet?
-__device__ inline bool cyc_meet(int a0, int alen, int b0, int blen, int n)
-{
-    if (alen + blen > n) return true;
-    const int d = wrap_i(a0 - b0, n);
-    return d < blen || d + alen > n;
-}
-
-constexpr int MAX_RANGES = 40;     // bins read by one tile (at most 5 columns x 8 rows)
-constexpr int SPREAD_UNROLL = 2;   // candidates per thread whose loads are issued together
-
-// Bins a lattice tile [x0, x1) x [y0, y1) reads.  A node filed in bin b has its stencil
-// origin within b's tile (TILE_X x TILE_Y) widened by BIN_MARGIN; the lattice tile needs every
-// node whose origin lies in [x0 - 3, x1 - 1] x [y0 - 3, y1 - 1], so it reads every bin whose
-// widened tile meets that range (superfluous candidates contribute nothing).  Lane q of the
-// first wavefront loads the record range of the q-th such bin (range_load); range_publish
-// then writes the range starts to rbeg and the inclusive prefix of their lengths to rpre.
-__device__ inline void range_load(const LatticeArgs& a, int x0, int x1, int y0, int y1, int& beg, int& len)
-{
-    const int t = threadIdx.x;
-    const int M = BIN_MARGIN;
-    beg = 0;
-    len = 0;
-    if (t >= 64) return;
-    int cols[5], ncol = 0;
-    {
-        const int c0 = x0 / TILE_X;
-        const int nc = a.ntx <= 5 ? a.ntx : 5;
-        for (int q = 0; q < nc; ++q) {
-            const int cc = a.ntx <= 5 ? q : wrap_i(c0 - 2 + q, a.ntx);
-            const int bx0 = cc * TILE_X, bw = min(TILE_X, a.nx - bx0);
-            if (cyc_meet(bx0 - M, bw + 2 * M, x0 - 3, x1 - x0 + 3, a.nx)) cols[ncol++] = cc;
-        }
-    }
-    int rows[8], nrow = 0;
-    {
-        const int r0 = y0 / TILE_Y, r1 = (y1 - 1) / TILE_Y;      // bin rows the tile spans
-        if (a.walls) {
-            for (int rr = max(r0 - 2, 0); rr <= min(r1 + 1, a.nty - 1) && nrow < 8; ++rr) {
-                const int by0 = rr * TILE_Y, bh = min(TILE_Y, a.ny - by0);
-                const int lo = (rr == 0) ? -1000000 : by0 - M;              // bin row 0 also holds j0 < 0
-                if (lo <= y1 - 1 && by0 + bh - 1 + M >= y0 - 3) rows[nrow++] = rr;
-            }
-        } else {
-            const int span = r1 - r0 + 4;
-            const bool all = a.nty <= span;
-            const int nr = all ? a.nty : span;
-            for (int q = 0; q < nr && nrow < 8; ++q) {
-                const int rr = all ? q : wrap_i(r0 - 2 + q, a.nty);
-                const int by0 = rr * TILE_Y, bh = min(TILE_Y, a.ny - by0);
-                if (cyc_meet(by0 - M, bh + 2 * M, y0 - 3, y1 - y0 + 3, a.ny)) rows[nrow++] = rr;
-            }
-        }
-    }
-    const int nsel = nrow * ncol;
-    if (t < nsel) {
-        const int qr = t / ncol, qc = t - qr * ncol;
-        int r = 0, cc = 0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (q == qr) r = rows[q];
-#pragma unroll
-        for (int q = 0; q < 5; ++q)
-            if (q == qc) cc = cols[q];
-        const int b = r * a.ntx + cc;
-        beg = a.bin_off[b];
-        len = a.bin_off[b + 1] - beg;
-    }
-}
-
-__device__ inline void range_publish(int beg, int len, int* rbeg, int* rpre)
-{
-    const int t = threadIdx.x;
-    if (t >= 64) return;
-    int incl = len;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int up = __shfl_up(incl, o, 64);
-        if (t >= o) incl += up;
-    }
-    if (t < MAX_RANGES) {
-        rbeg[t] = beg;
-        rpre[t] = incl;
-    }
-}
+constexpr int SPREAD_UNROLL = 1;   // listed nodes per thread whose loads are issued together
 
 __device__ inline unsigned long long to_ufixed(float v)
 {
@@ -189,29 +107,26 @@ __device__ inline unsigned long long to_ufixed(float v)
     return (unsigned long long)__float2ll_rn(v * UFIX_SCALE);
 }
 
-// Load one chunk of candidate records (up to SPREAD_UNROLL per thread).
-__device__ inline void load_candidates(const LatticeArgs& a, int base, int total, const int* rbeg, const int* rpre,
-                                       int ij[SPREAD_UNROLL], float4 rc[SPREAD_UNROLL], int nd[SPREAD_UNROLL],
-                                       bool with_node)
+// Load one chunk of the tile's listed nodes [beg, end): node index, stencil origin, record.
+__device__ inline void load_candidates(const LatticeArgs& a, int k0, int end, int ij[SPREAD_UNROLL],
+                                       float4 rc[SPREAD_UNROLL], int nd[SPREAD_UNROLL])
 {
     const int t = threadIdx.x;
 #pragma unroll
     for (int u = 0; u < SPREAD_UNROLL; ++u) {
-        const int k = base + u * TILE_N + t;
+        const int k = k0 + u * TILE_N + t;
         ij[u] = 0x7FFF7FFF;                              // far away: never hits
         nd[u] = 0;
-        if (k < total) {
-            int q = 0;
-            while (k >= rpre[q]) ++q;
-            const int idx = rbeg[q] + k - (q ? rpre[q - 1] : 0);
-            ij[u] = a.rec_ij[idx];
-            rc[u] = a.rec[idx];
-            if (with_node) nd[u] = a.rec_node[idx];
+        if (k < end) {
+            const int node = a.t_list[k];
+            nd[u] = node;
+            ij[u] = a.rec_ij[node];
+            rc[u] = a.rec[node];
         }
     }
 }
 
-// Couple one chunk of candidates with the tile [x0, x1) x [y0, y1) (LDS rows TILE_X apart):
+// Couple one chunk of listed nodes with the tile [x0, x1) x [y0, y1) (LDS rows TILE_X apart):
 // spread each node's force into the LDS accumulators (Eq. forcedistribution), and, when
 // INTERP, add the node's share of the interpolated velocity from the tile's u (LDS) to its
 // fixed-point accumulator (Eq. conversion2; each tile contributes its own stencil points).
@@ -284,7 +199,7 @@ __device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0
 template <int S, bool NODES, bool MASK, int ST>
 __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
 {
-    constexpr int LY = TILE_Y * RPT;
+    constexpr int LY = LTILE_Y;
     constexpr int NL = NODES ? TILE_X * LY : 1;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int tcol = tile % a.ntx, trow = tile / a.ntx;
@@ -296,10 +211,12 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
 
     __shared__ unsigned long long accx[NL], accy[NL];
     __shared__ float uxs[NL], uys[NL];
-    __shared__ int rbeg[NODES ? MAX_RANGES : 1], rpre[NODES ? MAX_RANGES : 1];
 
-    int rg_beg = 0, rg_len = 0;
-    if constexpr (NODES) range_load(a, x0, x1, y0, y1, rg_beg, rg_len);
+    int lbeg = 0, lend = 0;
+    if constexpr (NODES) {
+        lbeg = a.t_off[tile];
+        lend = a.t_off[tile + 1];
+    }
 
     Nbr n[RPT];
     bool active[RPT];
@@ -321,19 +238,15 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
         }
     }
 
-    int total = 0;
     int cij[SPREAD_UNROLL], cnd[SPREAD_UNROLL];
     float4 crc[SPREAD_UNROLL];
     if constexpr (NODES) {
-        range_publish(rg_beg, rg_len, rbeg, rpre);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             accx[t + r * TILE_N] = 0ull;
             accy[t + r * TILE_N] = 0ull;
         }
-        __syncthreads();
-        total = rpre[MAX_RANGES - 1];
-        load_candidates(a, 0, total, rbeg, rpre, cij, crc, cnd, true);
+        load_candidates(a, lbeg, lend, cij, crc, cnd);
     }
 
     // moments of every row: rho^n, u^n = sum f v / rho
@@ -357,8 +270,8 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
     if constexpr (NODES) {
         __syncthreads();
         couple_chunk<true>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, uxs, uys);
-        for (int base = SPREAD_UNROLL * TILE_N; base < total; base += SPREAD_UNROLL * TILE_N) {
-            load_candidates(a, base, total, rbeg, rpre, cij, crc, cnd, true);
+        for (int k0 = lbeg + SPREAD_UNROLL * TILE_N; k0 < lend; k0 += SPREAD_UNROLL * TILE_N) {
+            load_candidates(a, k0, lend, cij, crc, cnd);
             couple_chunk<true>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, uxs, uys);
         }
         __syncthreads();
@@ -437,30 +350,24 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
 // The spread force field alone (inspection): same tiling and summation as k_lattice.
 __global__ __launch_bounds__(TILE_N) void k_spread_inspect(LatticeArgs a)
 {
-    constexpr int LY = TILE_Y * RPT;
+    constexpr int LY = LTILE_Y;
     const int tile = blockIdx.x;
     const int tcol = tile % a.ntx, trow = tile / a.ntx;
     const int x0 = tcol * TILE_X, y0 = trow * LY;
     const int x1 = min(x0 + TILE_X, a.nx), y1 = min(y0 + LY, a.ny);
     const int t = threadIdx.x;
     __shared__ unsigned long long accx[TILE_X * LY], accy[TILE_X * LY];
-    __shared__ int rbeg[MAX_RANGES], rpre[MAX_RANGES];
     for (int r = 0; r < RPT; ++r) {
         accx[t + r * TILE_N] = 0ull;
         accy[t + r * TILE_N] = 0ull;
     }
-    if (a.bin_off) {
-        int beg, len;
-        range_load(a, x0, x1, y0, y1, beg, len);
-        range_publish(beg, len, rbeg, rpre);
-    }
     __syncthreads();
-    if (a.bin_off) {
-        const int total = rpre[MAX_RANGES - 1];
+    if (a.t_off) {
+        const int lbeg = a.t_off[tile], lend = a.t_off[tile + 1];
         int cij[SPREAD_UNROLL], cnd[SPREAD_UNROLL];
         float4 crc[SPREAD_UNROLL];
-        for (int base = 0; base < total; base += SPREAD_UNROLL * TILE_N) {
-            load_candidates(a, base, total, rbeg, rpre, cij, crc, cnd, false);
+        for (int k0 = lbeg; k0 < lend; k0 += SPREAD_UNROLL * TILE_N) {
+            load_candidates(a, k0, lend, cij, crc, cnd);
             couple_chunk<false>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, nullptr, nullptr);
         }
     }

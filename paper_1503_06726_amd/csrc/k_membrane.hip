@@ -7,10 +7,10 @@
 //      fixed-order wave and LDS reduction);
 //   3. evaluates the nodal forces in the paper's per-node form: constant tension
 //      (Eq. membraneforce), Hookean springs, area pressure kappa (A0 - A) dA/dX, and
-//      refreshes the node's spreading record (fractional offset, force, stencil origin) in
-//      its bin slot; a node that drifted beyond its bin margin raises an error flag;
+//      refreshes the node's spreading record (fractional offset, force, stencil origin); a
+//      node that drifted beyond its list margin raises an error flag;
 //   4. when a reaction reads them, rasterises the cell's domain IDs from the LDS positions.
-// k_bin_count / k_bin_scan / k_bin_scatter rebuild the bins (every few steps).
+// k_list_count / k_list_scan / k_list_fill rebuild the per-tile node lists (every few steps).
 #include "lbib_internal.h"
 #include "lbib_raster.h"
 
@@ -22,26 +22,24 @@ __device__ inline double wave_sum(double v)
     return v;
 }
 
-// has the stencil origin (i0, j0) moved at most BIN_MARGIN from its value at the last
-// rebinning (packed in ijb)?  Then it is still inside its bin's widened tile.
+// has the stencil origin (i0, j0) moved at most LIST_MARGIN from its value at the last list
+// build (packed in ijb)?  Then every tile its stencil reaches still lists the node.
 __device__ inline bool within_margin(int i0, int j0, int ijb, int nx, int ny, int walls)
 {
     const int ib = ijb & 0xFFFF, jb = ijb >> 16;
     int di = i0 - ib;
     if (di > nx / 2) di -= nx;
     else if (di < -(nx / 2)) di += nx;
-    if (di > BIN_MARGIN || di < -BIN_MARGIN) return false;
+    if (di > LIST_MARGIN || di < -LIST_MARGIN) return false;
     int dj;
     if (walls) {
-        const int jr = j0 < 0 ? 0 : (j0 >= ny ? ny - 1 : j0);
-        const int jbr = jb < 0 ? 0 : (jb >= ny ? ny - 1 : jb);
-        dj = jr - jbr;
+        dj = j0 - jb;
     } else {
         dj = j0 - jb;
         if (dj > ny / 2) dj -= ny;
         else if (dj < -(ny / 2)) dj += ny;
     }
-    return dj <= BIN_MARGIN && dj >= -BIN_MARGIN;
+    return dj <= LIST_MARGIN && dj >= -LIST_MARGIN;
 }
 
 constexpr int MEM_UNROLL = 2;     // nodes per thread whose loads are issued together
@@ -108,7 +106,7 @@ __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
     int flags = 0;
     for (int base = 0; base < n; base += MEM_UNROLL * MEMBRANE_THREADS) {
         double lp[MEM_UNROLL], lm[MEM_UNROLL];
-        int sl[MEM_UNROLL], ky[MEM_UNROLL];
+        int ky[MEM_UNROLL];
 #pragma unroll
         for (int u = 0; u < MEM_UNROLL; ++u) {
             const int k = base + u * MEMBRANE_THREADS + t;
@@ -116,8 +114,7 @@ __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
             const int km = (k == 0) ? n - 1 : k - 1;
             lp[u] = a.l0[beg + k];
             lm[u] = a.l0[beg + km];
-            sl[u] = a.slot[beg + k];
-            ky[u] = a.ij_bin[beg + k];
+            ky[u] = a.ij_list[beg + k];
         }
 #pragma unroll
         for (int u = 0; u < MEM_UNROLL; ++u) {
@@ -137,7 +134,7 @@ __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
             // area pressure: dA/dX_k = ((y_{k+1} - y_{k-1}) / 2, (x_{k-1} - x_{k+1}) / 2)
             Fx += s_area * 0.5 * (Xp.y - Xm.y);
             Fy += s_area * 0.5 * (Xm.x - Xp.x);
-            const int s = sl[u];
+            const int s = beg + k;
             if (finite2(X.x, X.y) && finite2(Fx, Fy)) {
                 const double fx = floor(X.x), fy = floor(X.y);
                 int i0, j0;
@@ -159,50 +156,95 @@ __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
 }
 
 // ---------------------------------------------------------------------------------------
-// rebinning
+// per-tile node lists
 // ---------------------------------------------------------------------------------------
 
-// bin of every node; a wavefront issues one counter increment per distinct bin among its
-// lanes (consecutive nodes of a membrane mostly share a tile) and hands out ranks within it
-__global__ void k_bin_count(BinArgs a)
+// Lattice tiles a node with stencil origin (i0, j0) is listed in: every tile that meets
+// columns i0 - M .. i0 + 3 + M and rows j0 - M .. j0 + 3 + M (M = LIST_MARGIN; columns cyclic,
+// rows cyclic or, next to walls, only those inside the lattice), each once.  Eight
+// consecutive columns touch at most three tile columns (the last tile may be narrow and the
+// range may wrap), and likewise for rows.  Tiles come out row by row in ascending order of
+// the range, so the list build is a pure function of the origin.
+__device__ inline int node_tiles(int i0, int j0, const ListArgs& a, int tiles[MAX_NODE_TILES])
 {
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = l < a.n;
-    int key = -1;
-    if (live) {
-        const double2 X = a.X[l];
-        key = 0;
-        int ij = 0;
-        if (finite2(X.x, X.y)) {
-            int i0, j0;
-            stencil_origin(X.x, X.y, a.nx, a.ny, a.walls, i0, j0);
-            key = bin_of(i0, j0, a.ny, a.ntx);
-            ij = pack_ij(i0, j0);
-        }
-        a.ij_bin[l] = ij;
+    constexpr int M = LIST_MARGIN;
+    int cols[3], nc = 0, rows[3], nr = 0;
+#pragma unroll
+    for (int q = -M; q <= 3 + M; ++q) {
+        const int cc = wrap_i(i0 + q, a.nx) / TILE_X;
+        bool seen = false;
+        for (int k = 0; k < nc; ++k) seen = seen || cols[k] == cc;
+        if (!seen && nc < 3) cols[nc++] = cc;
     }
+#pragma unroll
+    for (int q = -M; q <= 3 + M; ++q) {
+        int j = j0 + q;
+        if (a.walls) {
+            if (j < 0 || j >= a.ny) continue;
+        } else {
+            j = wrap_i(j, a.ny);
+        }
+        const int rr = j / LTILE_Y;
+        bool seen = false;
+        for (int k = 0; k < nr; ++k) seen = seen || rows[k] == rr;
+        if (!seen && nr < 3) rows[nr++] = rr;
+    }
+    int n = 0;
+    for (int r = 0; r < nr; ++r)
+        for (int k = 0; k < nc; ++k) tiles[n++] = rows[r] * a.ntx + cols[k];
+    return n;
+}
+
+// Wavefront-aggregated increment: every live lane adds 1 to counter[key]; one atomic per
+// distinct key among the lanes.  Returns the counter's previous value plus the lane's rank
+// among the lanes sharing its key.
+__device__ inline int wave_claim(int* counter, int key, bool live)
+{
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     unsigned long long todo = __ballot(live);
-    int rank = 0;
+    int pos = 0;
     while (todo) {
         const int leader = __ffsll((long long)todo) - 1;
         const int lkey = __shfl(key, leader, 64);
         const unsigned long long grp = __ballot(live && key == lkey);
         int base = 0;
-        if (lane == leader) base = atomicAdd(&a.count[lkey], __popcll(grp));
+        if (lane == leader) base = atomicAdd(&counter[lkey], __popcll(grp));
         base = __shfl(base, leader, 64);
-        if (live && key == lkey) rank = base + __popcll(grp & below);
+        if (live && key == lkey) pos = base + __popcll(grp & below);
         todo &= ~grp;
     }
+    return pos;
+}
+
+// stencil origin of every node at this build, and the length of every tile's list
+__global__ void k_list_count(ListArgs a)
+{
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = l < a.n;
+    int tiles[MAX_NODE_TILES];
+    int nt = 0;
     if (live) {
-        a.key[l] = key;
-        a.rank[l] = rank;
+        const double2 X = a.X[l];
+        int ij = 0;
+        if (finite2(X.x, X.y)) {
+            int i0, j0;
+            stencil_origin(X.x, X.y, a.nx, a.ny, a.walls, i0, j0);
+            ij = pack_ij(i0, j0);
+            nt = node_tiles(i0, j0, a, tiles);
+        }
+        a.ij_list[l] = ij;
+    }
+    for (int k = 0; k < MAX_NODE_TILES; ++k) {
+        const bool on = live && k < nt;
+        if (!__ballot(on)) break;
+        (void)wave_claim(a.count, on ? tiles[k] : 0, on);
     }
 }
 
-// exclusive scan of the bin counts into offsets; counts are cleared for the next rebinning
-__global__ __launch_bounds__(SCAN_THREADS) void k_bin_scan(BinArgs a)
+// exclusive scan of the list lengths into offsets (and fill cursors); counts are cleared for
+// the next build
+__global__ __launch_bounds__(SCAN_THREADS) void k_list_scan(ListArgs a)
 {
     constexpr int CHUNK = SCAN_THREADS * SCAN_PER_THREAD;
     __shared__ int buf[CHUNK];
@@ -210,11 +252,11 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_bin_scan(BinArgs a)
     __shared__ int carry_sh;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     if (t == 0) carry_sh = 0;
-    for (int base = 0; base < a.nbins; base += CHUNK) {
+    for (int base = 0; base < a.ntiles; base += CHUNK) {
         for (int i = t; i < CHUNK; i += SCAN_THREADS) {
             const int b = base + i;
             int v = 0;
-            if (b < a.nbins) {
+            if (b < a.ntiles) {
                 v = a.count[b];
                 a.count[b] = 0;
             }
@@ -242,36 +284,46 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_bin_scan(BinArgs a)
         __syncthreads();
         for (int i = t; i < CHUNK; i += SCAN_THREADS) {
             const int b = base + i;
-            if (b < a.nbins) a.off[b] = buf[i];
+            if (b < a.ntiles) {
+                a.off[b] = buf[i];
+                a.cursor[b] = buf[i];
+            }
         }
         if (t == SCAN_THREADS - 1) carry_sh = run;
         __syncthreads();
     }
-    if (t == 0) a.off[a.nbins] = carry_sh;
+    if (t == 0) a.off[a.ntiles] = carry_sh;
 }
 
-// new slot of every node; its record moves there from the old slot when copy is set
-__global__ void k_bin_scatter(BinArgs a)
+// every node enters the lists of its tiles (order within a list is immaterial: the lattice
+// pass sums in fixed point)
+__global__ void k_list_fill(ListArgs a)
 {
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= a.n) return;
-    const int s = a.off[a.key[l]] + a.rank[l];
-    a.rec_node[s] = (int)l;
-    if (a.copy) {
-        const int o = a.slot[l];
-        a.rec_new[s] = a.rec_old[o];
-        a.ij_new[s] = a.ij_old[o];
+    const bool live = l < a.n;
+    int tiles[MAX_NODE_TILES];
+    int nt = 0;
+    if (live) {
+        const double2 X = a.X[l];
+        if (finite2(X.x, X.y)) {
+            const int ij = a.ij_list[l];
+            nt = node_tiles(ij & 0xFFFF, ij >> 16, a, tiles);
+        }
     }
-    a.slot[l] = s;
+    for (int k = 0; k < MAX_NODE_TILES; ++k) {
+        const bool on = live && k < nt;
+        if (!__ballot(on)) break;
+        const int p = wave_claim(a.cursor, on ? tiles[k] : 0, on);
+        if (on) a.list[p] = (int)l;
+    }
 }
 
 // forces of every node, read back from the records (inspection)
-__global__ void k_forces_out(const int* __restrict__ slot, const float4* __restrict__ rec, float2* __restrict__ F,
-                             int64_t n)
+__global__ void k_forces_out(const float4* __restrict__ rec, float2* __restrict__ F, int64_t n)
 {
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= n) return;
-    const float4 r = rec[slot[l]];
+    const float4 r = rec[l];
     F[l] = make_float2(r.z, r.w);
 }
 
@@ -300,20 +352,19 @@ hipError_t launch_membrane(lbib_ctx* c, const MembraneArgs& a)
     return hipGetLastError();
 }
 
-hipError_t launch_rebin(lbib_ctx* c, const BinArgs& a, int which)
+hipError_t launch_lists(lbib_ctx* c, const ListArgs& a, int which)
 {
     const unsigned nb = (unsigned)((a.n + 255) / 256);
-    if (which == 0) hipLaunchKernelGGL(k_bin_count, dim3(nb), dim3(256), 0, c->stream, a);
-    else if (which == 1) hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(SCAN_THREADS), 0, c->stream, a);
-    else hipLaunchKernelGGL(k_bin_scatter, dim3(nb), dim3(256), 0, c->stream, a);
+    if (which == 0) hipLaunchKernelGGL(k_list_count, dim3(nb), dim3(256), 0, c->stream, a);
+    else if (which == 1) hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(SCAN_THREADS), 0, c->stream, a);
+    else hipLaunchKernelGGL(k_list_fill, dim3(nb), dim3(256), 0, c->stream, a);
     return hipGetLastError();
 }
 
 hipError_t launch_forces_out(lbib_ctx* c, float2* F)
 {
     const unsigned nb = (unsigned)((c->n_nodes + 255) / 256);
-    hipLaunchKernelGGL(k_forces_out, dim3(nb), dim3(256), 0, c->stream, (const int*)c->d_slot,
-                       (const float4*)c->d_rec[c->rec_cur], F, c->n_nodes);
+    hipLaunchKernelGGL(k_forces_out, dim3(nb), dim3(256), 0, c->stream, (const float4*)c->d_rec, F, c->n_nodes);
     return hipGetLastError();
 }
 

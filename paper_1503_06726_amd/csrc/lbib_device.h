@@ -1,16 +1,16 @@
 // Device-side definitions shared by the lbib HIP kernels (gfx950).
 //
-// Storage: every population is kept as an FP32 deviation from its rest value,
+// Storage: every population is kept as a deviation from its rest value,
 // df_i = f_i - w_i rho0 and dg_i = g_i - w_i phi_ref, in structure-of-arrays planes
 // [q][ny][nx] (x fastest).  The arrays hold post-collision, pre-streaming values; a
 // lattice pass pulls f_i(x) = f*_i(x - v_i) (or, across a wall, f*_opp(i)(x)), collides,
 // and stores f*_i(x) in place of x in the other buffer.
 //
-// Immersed-boundary nodes are filed in bins, one per lattice tile, by the tile of their
-// stencil origin (floor(X) - 1) at the last rebinning.  A node may drift up to BIN_MARGIN
-// lattice units from its bin's tile before the next rebinning (done every REBIN_PERIOD
-// steps); a lattice tile therefore reads every bin whose tile, widened by the margin,
-// reaches its stencil footprint.  The membrane kernel refreshes each node's record in place.
+// Immersed-boundary nodes are listed per lattice tile (TILE_X x LTILE_Y nodes): every few
+// steps (LIST_PERIOD) each node enters the list of every tile that its 4x4 stencil can reach
+// while its stencil origin (floor(X) - 1) stays within LIST_MARGIN lattice units of the origin
+// it had then.  The membrane kernel refreshes each node's spreading record at the node's own
+// index every step and flags a node that drifted further.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,15 +18,18 @@
 
 namespace lbib {
 
-// bin tile: 64 x 4 nodes (a 256-thread workgroup, one 64-wide wavefront per row)
+// workgroup of the lattice pass: 64 x 4 threads (one 64-wide wavefront per row), each thread
+// taking RPT rows, so a lattice tile is TILE_X x LTILE_Y nodes
 constexpr int TILE_X = 64;
 constexpr int TILE_Y = 4;
 constexpr int TILE_N = TILE_X * TILE_Y;
+constexpr int RPT = 2;
+constexpr int LTILE_Y = TILE_Y * RPT;
 
-constexpr int RPT = 2;               // lattice rows per thread: a lattice tile is TILE_X x (TILE_Y * RPT)
-constexpr int BIN_MARGIN = 2;        // lattice units a node may drift from its bin's tile
-constexpr int REBIN_PERIOD = 8;      // steps between rebinnings
-constexpr int GRAPH_STEPS = 16;      // steps per captured graph: buffer parities repeat after it
+constexpr int LIST_MARGIN = 2;       // lattice units a node may drift between list rebuilds
+constexpr int LIST_PERIOD = 8;       // steps between list rebuilds
+constexpr int MAX_NODE_TILES = 9;    // tiles one node can be listed in (3 columns x 3 rows at most)
+constexpr int GRAPH_STEPS = 16;      // steps per captured graph (a multiple of LIST_PERIOD)
 
 constexpr int MEMBRANE_THREADS = 256;
 constexpr int MAX_CELL_NODES = 4096;            // LDS holds one cell's positions as double2
@@ -49,7 +52,7 @@ constexpr float UFIX_CLAMP = 4096.0f;
 
 // error flags (device int, OR-ed)
 constexpr int ERR_NONFINITE = 1;     // a node position or force became non-finite
-constexpr int ERR_MARGIN = 2;        // a node drifted beyond its bin margin
+constexpr int ERR_MARGIN = 2;        // a node drifted beyond its list margin
 
 struct LatticeArgs {
     const void* __restrict__ fsrc;    // 9 planes of the storage type
@@ -57,18 +60,18 @@ struct LatticeArgs {
     const void* __restrict__ gsrc;    // 5 * S planes
     void* __restrict__ gdst;
     int64_t nn;                       // nx * ny (plane stride)
-    int nx, ny, walls, ntx, nty;
+    int nx, ny, walls, ntx;
     float omega, rho0;
     float omega_s[2], phi_ref[2];
     int react[2];
     float rc[2][4];
     float bodyx, bodyy;
     int kernel;
-    // immersed boundary: node records binned by lattice tile
-    const int* __restrict__ bin_off;   // [nbins + 1]
-    const float4* __restrict__ rec;    // (sx, sy, Fx, Fy) per binned node
-    const int* __restrict__ rec_ij;    // packed stencil origin (i0 | j0 << 16)
-    const int* __restrict__ rec_node;  // node index of each record
+    // immersed boundary: node lists per lattice tile, spreading records per node
+    const int* __restrict__ t_off;     // [ntiles + 1] list offsets (NULL: no nodes)
+    const int* __restrict__ t_list;    // node indices
+    const float4* __restrict__ rec;    // [N] (sx, sy, Fx, Fy): fractional offset and force
+    const int* __restrict__ rec_ij;    // [N] packed stencil origin (i0 | j0 << 16)
     unsigned long long* __restrict__ U_acc;   // [N][2] interpolated velocity, fixed point
     uint16_t* __restrict__ mask;       // domain IDs; read, then cleared for the next raster
     // inspection output (spread field only)
@@ -82,35 +85,27 @@ struct MembraneArgs {
     const double* __restrict__ A0;
     double* __restrict__ area;
     unsigned long long* __restrict__ U_acc;   // [N][2] interpolated velocity, read and cleared
-    const int* __restrict__ slot;      // record slot of each node
-    const int* __restrict__ ij_bin;    // packed stencil origin of each node at the last rebinning
-    float4* __restrict__ rec;
-    int* __restrict__ rec_ij;
+    const int* __restrict__ ij_list;   // packed stencil origin of each node at the last list build
+    float4* __restrict__ rec;          // [N]
+    int* __restrict__ rec_ij;          // [N]
     uint16_t* __restrict__ mask;       // written when raster != 0
     int* __restrict__ err;
     int64_t nn;
-    int nx, ny, walls, kernel, ntx, nty;
+    int nx, ny, walls, kernel;
     double k_spring, phi_m, kappa;
     int advect;
     int raster;
 };
 
-struct BinArgs {
+struct ListArgs {
     const double2* __restrict__ X;
-    int* __restrict__ ij_bin;          // stencil origin at this rebinning
-    int* __restrict__ rec_node;        // node index of each record slot (of the buffer in use next)
-    int* __restrict__ key;
-    int* __restrict__ rank;
-    int* __restrict__ count;           // zeroed by the scan after use
-    int* __restrict__ off;
-    int* __restrict__ slot;
-    const float4* __restrict__ rec_old;
-    const int* __restrict__ ij_old;
-    float4* __restrict__ rec_new;
-    int* __restrict__ ij_new;
+    int* __restrict__ ij_list;         // stencil origin of each node at this build
+    int* __restrict__ count;           // [ntiles], zero between builds (the scan clears it)
+    int* __restrict__ off;             // [ntiles + 1]
+    int* __restrict__ cursor;          // [ntiles] fill positions
+    int* __restrict__ list;            // [N * MAX_NODE_TILES] capacity
     int64_t n;
-    int nx, ny, walls, ntx, nbins;
-    int copy;                          // 1: move records from their old slots
+    int nx, ny, walls, ntx, nlty, ntiles;
 };
 
 struct RasterArgs {
@@ -179,13 +174,6 @@ __device__ inline void stencil_origin(double x, double y, int nx, int ny, int wa
     else j0 = wrap_i(j, ny);
 }
 
-// bin (lattice tile) of a stencil origin; rows beyond a wall go to the edge row of tiles
-__device__ inline int bin_of(int i0, int j0, int ny, int ntx)
-{
-    int jr = j0 < 0 ? 0 : (j0 >= ny ? ny - 1 : j0);
-    return (jr / TILE_Y) * ntx + i0 / TILE_X;
-}
-
 __device__ inline int pack_ij(int i0, int j0)
 {
     return (i0 & 0xFFFF) | (int)((unsigned)(j0 & 0xFFFF) << 16);
@@ -219,7 +207,7 @@ __device__ constexpr float IS5[5] = {1.0f / 3072.0f, 1.0f / 6144.0f, 1.0f / 6144
 
 // XCD-aware workgroup order: the dispatcher deals workgroups round-robin over the 8 XCDs;
 // remap so each XCD walks a contiguous run of tiles (neighbouring tiles share cache lines
-// at their x edges and read the same node bins, and each XCD has its own L2).
+// at their x edges and list many of the same membrane nodes, and each XCD has its own L2).
 __device__ inline int xcd_remap(int bid, int nblocks)
 {
     const int NX = 8;

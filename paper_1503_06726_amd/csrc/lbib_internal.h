@@ -33,8 +33,7 @@ struct lbib_ctx {
 
     int64_t nn = 0;          // nx * ny
     int S = 0;               // species
-    int ntx = 0, nty = 0, nbins = 0;   // bin tiles (TILE_X x TILE_Y)
-    int nlty = 0, nltiles = 0;         // lattice tiles (TILE_X x TILE_Y * RPT)
+    int ntx = 0, nlty = 0, nltiles = 0;   // lattice tiles (TILE_X x LTILE_Y): columns, rows, total
     bool mask_needed = false;
 
     // lattice state: post-collision deviations (FP32, FP16 or BF16), A/B buffers
@@ -53,19 +52,16 @@ struct lbib_ctx {
     double* d_l0 = nullptr;
     double* d_A0 = nullptr;
     double* d_area = nullptr;
-    int* d_key = nullptr;            // bin of each node at the last rebinning
-    int* d_rank = nullptr;           // rank within that bin
-    int* d_slot = nullptr;           // record slot of each node
-    int* d_ijbin = nullptr;          // stencil origin of each node at the last rebinning
+    int* d_ijlist = nullptr;         // stencil origin of each node at the last list build
     unsigned long long* d_U = nullptr;   // [N][2] interpolated velocities, fixed point
-    int* d_rec_node[2] = {nullptr, nullptr};
-    float4* d_rec[2] = {nullptr, nullptr};   // spreading records, current and spare
-    int* d_rec_ij[2] = {nullptr, nullptr};
-    int rec_cur = 0;
-    int* d_bin_count = nullptr;      // [nbins], zero between rebinnings
-    int* d_bin_off = nullptr;        // [nbins + 1]
+    float4* d_rec = nullptr;         // [N] spreading records (fractional offset, force)
+    int* d_rec_ij = nullptr;         // [N] current stencil origins
+    int* d_list = nullptr;           // [N * MAX_NODE_TILES] per-tile node lists
+    int* d_t_count = nullptr;        // [nltiles], zero between list builds
+    int* d_t_off = nullptr;          // [nltiles + 1]
+    int* d_t_cur = nullptr;          // [nltiles] fill cursors
     int* d_err = nullptr;            // device error flags
-    int steps_since_rebin = 0;
+    int steps_since_lists = 0;
 
     // staging
     double* d_stage = nullptr;
@@ -75,10 +71,10 @@ struct lbib_ctx {
 
     size_t device_bytes = 0;
 
-    // captured step sequences: GRAPH_STEPS steps starting with no steps since the last
-    // rebinning, one graph per parity (cur, rec_cur) of the buffers at the start
+    // captured step sequences: GRAPH_STEPS steps starting right after a list build, one graph
+    // per parity (cur) of the population buffers at the start
     bool use_graphs = true;
-    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipStream_t capture_stream = nullptr;
 
     // timing
@@ -99,7 +95,7 @@ hipError_t launch_init(lbib_ctx* c, const double* stage_rho, const double* stage
 hipError_t launch_moments(lbib_ctx* c, double* out);
 hipError_t launch_reduce(lbib_ctx* c, double* out_dev);
 hipError_t launch_membrane(lbib_ctx* c, const MembraneArgs& a);
-hipError_t launch_rebin(lbib_ctx* c, const BinArgs& a, int which);   // 0 count, 1 scan, 2 scatter
+hipError_t launch_lists(lbib_ctx* c, const ListArgs& a, int which);   // 0 count, 1 scan, 2 fill
 hipError_t launch_forces_out(lbib_ctx* c, float2* F);
 hipError_t launch_raster(lbib_ctx* c, const RasterArgs& a);
 hipError_t launch_fill_i32(lbib_ctx* c, int* p, int64_t n, int v);

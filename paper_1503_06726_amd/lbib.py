@@ -19,8 +19,8 @@ PERIODIC, WALLS = 0, 1
 DELTA_COS4, DELTA_PESKIN4 = 0, 1
 REACT_NONE, REACT_SOURCE_DECAY, REACT_SCHNAKENBERG = 0, 1, 2
 STORAGE_FP32, STORAGE_FP16, STORAGE_BF16 = 0, 1, 2
-K_LATTICE, K_MEMBRANE, K_REBIN = range(3)
-KERNEL_NAMES = ["lattice", "membrane", "rebin"]
+K_LATTICE, K_MEMBRANE, K_LISTS = range(3)
+KERNEL_NAMES = ["lattice", "membrane", "lists"]
 
 # every entry point declared in include/lbib.h
 EXPORTS = ["lbib_validate_params", "lbib_validate_cells", "lbib_create", "lbib_set_cells",
