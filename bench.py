@@ -20,7 +20,7 @@ METRIC = "coupled LBM+IB MLUPS at 2048²/2000 cells (% HBM peak); ADE iters-to-s
 HBM_PEAK_GBS = 8000.0
 # HBM traffic per launch of the lattice kernel measured with rocprofv3 --pmc (FETCH_SIZE,
 # WRITE_SIZE, scaled by a copy kernel of known size); None until taken for the current kernel
-LATTICE_TRAFFIC_BYTES = 543_985_664
+LATTICE_TRAFFIC_BYTES = None
 
 
 def log(*a):
@@ -30,10 +30,10 @@ def log(*a):
 POP_BYTES = {"fp32": 4, "fp16": 2, "bf16": 2}
 
 
-def lattice_bytes_per_update(S: int, mask: bool, pop_bytes: int = 4) -> int:
+def lattice_bytes_per_update(S: int, mask: bool, pop_bytes: int = 4) -> float:
     """Algorithmic bytes per lattice node of one lattice pass: every population read once and
-    written once, plus the 16-bit domain ID read."""
-    return pop_bytes * 2 * (9 + 5 * S) + (2 if mask else 0)
+    written once, plus the node's inside-any-cell bit read when a source term needs it."""
+    return pop_bytes * 2 * (9 + 5 * S) + (0.125 if mask else 0.0)
 
 
 def step_bytes_per_update(S: int, mask: bool, n_nodes: int, nn: int, pop_bytes: int = 4) -> float:

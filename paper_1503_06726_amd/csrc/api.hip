@@ -139,7 +139,9 @@ LatticeArgs lattice_args(lbib_ctx* c)
     a.rec = c->d_rec;
     a.rec_ij = c->d_rec_ij;
     a.U_acc = c->d_U;
-    a.mask = c->mask;
+    a.inside = c->inside[c->cur];
+    a.inside_clr = c->inside[1 - c->cur];
+    a.wpr = c->wpr;
     a.e_out = nullptr;
     return a;
 }
@@ -157,7 +159,8 @@ MembraneArgs membrane_args(lbib_ctx* c, int advect)
     a.ij_list = c->d_ijlist;
     a.rec = c->d_rec;
     a.rec_ij = c->d_rec_ij;
-    a.mask = c->mask;
+    a.inside = c->inside[c->cur];
+    a.wpr = c->wpr;
     a.err = c->d_err;
     a.nn = c->nn;
     a.nx = c->p.nx;
@@ -192,12 +195,12 @@ ListArgs list_args(lbib_ctx* c)
     return a;
 }
 
-RasterArgs raster_args(lbib_ctx* c)
+RasterArgs raster_args(lbib_ctx* c, uint16_t* ids)
 {
     RasterArgs a;
     a.off = c->d_off;
     a.X = c->d_X;
-    a.mask = c->mask;
+    a.mask = ids;
     a.nx = c->p.nx;
     a.ny = c->p.ny;
     a.walls = c->p.bc_y == LBIB_WALLS;
@@ -293,7 +296,7 @@ void free_all(lbib_ctx* c)
         dev_free(c, gb, 5 * (size_t)c->S * nn * c->pop_bytes);
         c->f[b] = c->g[b] = nullptr;
     }
-    dev_free(c, c->mask, nn);
+    for (int b = 0; b < 2; ++b) dev_free(c, c->inside[b], (size_t)c->ny_words());
     dev_free(c, c->d_t_count, (size_t)c->nltiles);
     dev_free(c, c->d_t_off, (size_t)c->nltiles + 1);
     dev_free(c, c->d_t_cur, (size_t)c->nltiles);
@@ -462,6 +465,7 @@ lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out)
     c->ntx = (p->nx + TILE_X - 1) / TILE_X;
     c->nlty = (p->ny + LTILE_Y - 1) / LTILE_Y;
     c->nltiles = c->ntx * c->nlty;
+    c->wpr = (p->nx + 31) / 32;
     c->partial_count = 4096;
     const size_t nn = (size_t)c->nn;
     lbib_status s = LBIB_OK;
@@ -476,13 +480,14 @@ lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out)
             c->g[b] = gb;
         }
     }
-    if (s == LBIB_OK) s = dev_alloc(c, &c->mask, nn);
+    for (int b = 0; b < 2 && s == LBIB_OK; ++b) s = dev_alloc(c, &c->inside[b], (size_t)c->ny_words());
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_count, (size_t)c->nltiles);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_off, (size_t)c->nltiles + 1);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_cur, (size_t)c->nltiles);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_err, 1);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_partial, c->partial_count * 5);
-    if (s == LBIB_OK && (launch_fill_u16(c, c->mask, c->nn) != hipSuccess ||
+    if (s == LBIB_OK && (launch_fill_i32(c, (int*)c->inside[0], c->ny_words(), 0) != hipSuccess ||
+                         launch_fill_i32(c, (int*)c->inside[1], c->ny_words(), 0) != hipSuccess ||
                          launch_fill_i32(c, c->d_t_count, c->nltiles, 0) != hipSuccess ||
                          launch_fill_i32(c, c->d_t_off, c->nltiles + 1, 0) != hipSuccess ||
                          launch_fill_i32(c, c->d_err, 1, 0) != hipSuccess))
@@ -567,7 +572,8 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
     LBIB_LAUNCH(c, launch_fill_i32(c, c->d_t_count, c->nltiles, 0));
     LBIB_LAUNCH(c, launch_fill_i32(c, c->d_err, 1, 0));
     LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->d_U, 4 * (int64_t)N, 0));
-    if (c->mask_needed) LBIB_LAUNCH(c, launch_fill_u16(c, c->mask, c->nn));
+    if (c->mask_needed)
+        for (int b = 0; b < 2; ++b) LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->inside[b], c->ny_words(), 0));
     LBIB_TRY(build_lists(c));
     LBIB_TRY(membrane(c, 0));
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
@@ -640,13 +646,15 @@ lbib_status lbib_get_fields(lbib_ctx* c, double* rho, double* u, double* phi, do
         LBIB_HIP(c, hipMemcpyAsync(xy, c->d_X, (size_t)c->n_nodes * sizeof(double2), hipMemcpyDeviceToHost,
                                    c->stream));
     if (cell_id_map) {
-        if (!c->mask_needed) {
-            // the map is only maintained when a reaction reads it: build it now
-            LBIB_LAUNCH(c, launch_fill_u16(c, c->mask, c->nn));
-            if (c->n_cells) LBIB_LAUNCH(c, launch_raster(c, raster_args(c)));
-        }
+        // the ID map is built on demand from the current positions
+        LBIB_HIP(c, hipStreamSynchronize(c->stream));         // the stage may hold the moments
+        uint16_t* ids = nullptr;
+        LBIB_TRY(ensure_stage(c, (nn + 3) / 4));
+        ids = (uint16_t*)c->d_stage;
+        LBIB_LAUNCH(c, launch_fill_u16(c, ids, c->nn));
+        if (c->n_cells) LBIB_LAUNCH(c, launch_raster(c, raster_args(c, ids)));
         std::vector<uint16_t> h(nn);
-        LBIB_HIP(c, hipMemcpyAsync(h.data(), c->mask, nn * sizeof(uint16_t), hipMemcpyDeviceToHost, c->stream));
+        LBIB_HIP(c, hipMemcpyAsync(h.data(), ids, nn * sizeof(uint16_t), hipMemcpyDeviceToHost, c->stream));
         LBIB_HIP(c, hipStreamSynchronize(c->stream));
         for (size_t i = 0; i < nn; ++i) cell_id_map[i] = h[i];
     }

@@ -11,8 +11,9 @@
 //      accumulator;
 //   3. collide with the BGK operator and the body-force term w_i rho (v_i . e) / cs2, store;
 //   4. per species: pull the D2Q5 populations, take phi, add the reaction, collide towards
-//      phi w_i (1 + v_i . u / cs2) with the fluid's u, store; read the domain ID and clear it
-//      for the next rasterisation.
+//      phi w_i (1 + v_i . u / cs2) with the fluid's u, store; the source term reads the
+//      inside-any-cell bit of the node (the word-aligned bits of the other buffer are cleared
+//      here for the membrane kernel to fill).
 // The pass reads every population once and writes it once: it is HBM-bandwidth bound.
 #include "lbib_internal.h"
 
@@ -191,11 +192,10 @@ __device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0
     }
 }
 
-// One lattice tile of TILE_X x (TILE_Y * RPT) nodes per workgroup; thread (lx, ly) handles
-// rows ly, ly + TILE_Y, ...  Order: record ranges and population loads issued; candidate
-// records loaded; moments (rho, u) of every row, u staged in LDS; candidates coupled (force
-// spread into LDS, velocity interpolated to the nodes); collision with the spread force and
-// stores.
+// One lattice tile of TILE_X x LTILE_Y nodes per workgroup; thread (lx, ly) handles rows
+// ly, ly + TILE_Y, ...  Order: listed nodes' records and the population loads issued; moments
+// (rho, u) of every row, u staged in LDS; listed nodes coupled (force spread into LDS, velocity
+// interpolated to the nodes); collision with the spread force and stores.
 template <int S, bool NODES, bool MASK, int ST>
 __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
 {
@@ -212,10 +212,20 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
     __shared__ unsigned long long accx[NL], accy[NL];
     __shared__ float uxs[NL], uys[NL];
 
+    // the first chunk of listed nodes is fetched before the populations: the record loads
+    // depend on the list entry, and issuing them first keeps them off the populations' queue
     int lbeg = 0, lend = 0;
+    int cij[SPREAD_UNROLL], cnd[SPREAD_UNROLL];
+    float4 crc[SPREAD_UNROLL];
     if constexpr (NODES) {
         lbeg = a.t_off[tile];
         lend = a.t_off[tile + 1];
+        load_candidates(a, lbeg, lend, cij, crc, cnd);
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            accx[t + r * TILE_N] = 0ull;
+            accy[t + r * TILE_N] = 0ull;
+        }
     }
 
     Nbr n[RPT];
@@ -234,19 +244,8 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
 #pragma unroll
             for (int s = 0; s < S; ++s)
                 pull5<ST>((const typename Pop<ST>::T*)a.gsrc + (int64_t)5 * s * nn, nn, x, n[r], g[r][s]);
-            if constexpr (MASK) m[r] = a.mask[n[r].rc + x];
+            if constexpr (MASK) m[r] = (a.inside[(int64_t)y * a.wpr + (x >> 5)] >> (x & 31)) & 1u;
         }
-    }
-
-    int cij[SPREAD_UNROLL], cnd[SPREAD_UNROLL];
-    float4 crc[SPREAD_UNROLL];
-    if constexpr (NODES) {
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            accx[t + r * TILE_N] = 0ull;
-            accy[t + r * TILE_N] = 0ull;
-        }
-        load_candidates(a, lbeg, lend, cij, crc, cnd);
     }
 
     // moments of every row: rho^n, u^n = sum f v / rho
@@ -309,7 +308,8 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
             vu = ux - uy;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[8 * nn] = Pop<ST>::st(om1 * fr[8] + om * eq + W5 * (fx - fy), SC9[8]);
         }
 
-        if constexpr (MASK) a.mask[o] = 0;
+        if constexpr (MASK)
+            if ((x & 31) == 0) a.inside_clr[(int64_t)(y0 + t / TILE_X + r * TILE_Y) * a.wpr + (x >> 5)] = 0u;
         if constexpr (S > 0) {
             float dphi[S], phi[S], R[S];
 #pragma unroll

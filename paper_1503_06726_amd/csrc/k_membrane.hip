@@ -9,7 +9,8 @@
 //      (Eq. membraneforce), Hookean springs, area pressure kappa (A0 - A) dA/dX, and
 //      refreshes the node's spreading record (fractional offset, force, stencil origin); a
 //      node that drifted beyond its list margin raises an error flag;
-//   4. when a reaction reads them, rasterises the cell's domain IDs from the LDS positions.
+//   4. when a reaction reads it, ORs the cell's interior into the inside-any-cell bit map
+//      (rasterised from the LDS positions).
 // k_list_count / k_list_scan / k_list_fill rebuild the per-tile node lists (every few steps).
 #include "lbib_internal.h"
 #include "lbib_raster.h"
@@ -42,117 +43,159 @@ __device__ inline bool within_margin(int i0, int j0, int ijb, int nx, int ny, in
     return dj <= LIST_MARGIN && dj >= -LIST_MARGIN;
 }
 
-constexpr int MEM_UNROLL = 2;     // nodes per thread whose loads are issued together
+// a value known to be equal in every lane, moved to scalar registers
+__device__ inline double uniform(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Block-wide sum of one double and minima of four (fixed order: waves, then LDS slots); the
+// results are uniform.
+__device__ inline void block_reduce5(double& sum, double m[4], double* red)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    sum = wave_sum(sum);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) m[q] = wave_min(m[q]);
+    if (lane == 0) {
+        red[wid * 5] = sum;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[wid * 5 + 1 + q] = m[q];
+    }
+    __syncthreads();
+    sum = red[0];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) m[q] = red[1 + q];
+    for (int w = 1; w < MEMBRANE_THREADS / 64; ++w) {
+        sum += red[w * 5];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) m[q] = fmin(m[q], red[w * 5 + 1 + q]);
+    }
+    sum = uniform(sum);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) m[q] = uniform(m[q]);
+}
 
 __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
 {
     extern __shared__ double2 xs[];
-    __shared__ double red[16];
+    __shared__ double red[5 * (MEMBRANE_THREADS / 64)];
     __shared__ unsigned bm[RASTER_WORDS_FUSED];
     const int c = blockIdx.x;
-    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    const int t = threadIdx.x;
     const int beg = a.off[c];
     const int n = a.off[c + 1] - beg;
 
-    // 1. move: X^{n+1} = X^n + U, U interpolated by the lattice pass (fixed point, cleared here)
-    for (int base = 0; base < n; base += MEM_UNROLL * MEMBRANE_THREADS) {
-        double2 X[MEM_UNROLL];
-        unsigned long long ux[MEM_UNROLL], uy[MEM_UNROLL];
-#pragma unroll
-        for (int u = 0; u < MEM_UNROLL; ++u) {
-            const int k = base + u * MEMBRANE_THREADS + t;
-            if (k >= n) continue;
-            X[u] = a.X[beg + k];
-            if (a.advect) {
-                ux[u] = a.U_acc[2 * (int64_t)(beg + k)];
-                uy[u] = a.U_acc[2 * (int64_t)(beg + k) + 1];
+    // rest lengths and list origin of the thread's first node, fetched with its position
+    double lp0 = 0.0, lm0 = 0.0;
+    int ky0 = 0;
+    if (t < n) {
+        lp0 = a.l0[beg + t];
+        lm0 = a.l0[beg + (t == 0 ? n - 1 : t - 1)];
+        ky0 = a.ij_list[beg + t];
+    }
+    if (a.raster)
+        for (int i = t; i < RASTER_WORDS_FUSED; i += MEMBRANE_THREADS) bm[i] = 0u;
+
+    // 1. move: X^{n+1} = X^n + U, U interpolated by the lattice pass (fixed point, cleared
+    //    here); stage the new positions in LDS and track their bounding box
+    double bb[4] = {INFINITY, INFINITY, INFINITY, INFINITY};     // min x, min y, -max x, -max y
+    for (int k = t; k < n; k += MEMBRANE_THREADS) {
+        double2 X = a.X[beg + k];
+        if (a.advect) {
+            const unsigned long long ux = a.U_acc[2 * (int64_t)(beg + k)];
+            const unsigned long long uy = a.U_acc[2 * (int64_t)(beg + k) + 1];
+            a.U_acc[2 * (int64_t)(beg + k)] = 0ull;
+            a.U_acc[2 * (int64_t)(beg + k) + 1] = 0ull;
+            if (finite2(X.x, X.y)) {
+                X.x += (double)(long long)ux * UFIX_INV;
+                X.y += (double)(long long)uy * UFIX_INV;
+                a.X[beg + k] = X;
             }
         }
-#pragma unroll
-        for (int u = 0; u < MEM_UNROLL; ++u) {
-            const int k = base + u * MEMBRANE_THREADS + t;
-            if (k >= n) continue;
-            if (a.advect) {
-                a.U_acc[2 * (int64_t)(beg + k)] = 0ull;
-                a.U_acc[2 * (int64_t)(beg + k) + 1] = 0ull;
-                if (finite2(X[u].x, X[u].y)) {
-                    X[u].x += (double)(long long)ux[u] * UFIX_INV;
-                    X[u].y += (double)(long long)uy[u] * UFIX_INV;
-                    a.X[beg + k] = X[u];
-                }
-            }
-            xs[k] = X[u];
-        }
+        xs[k] = X;
+        bb[0] = fmin(bb[0], X.x);
+        bb[1] = fmin(bb[1], X.y);
+        bb[2] = fmin(bb[2], -X.x);
+        bb[3] = fmin(bb[3], -X.y);
     }
     __syncthreads();
 
     // 2. shoelace area about the first node (translation invariant, less cancellation)
-    const double ox = xs[0].x, oy = xs[0].y;
-    double part = 0.0;
+    const double ox = uniform(xs[0].x), oy = uniform(xs[0].y);
+    double A2 = 0.0;
     for (int k = t; k < n; k += MEMBRANE_THREADS) {
         const int kn = (k + 1 == n) ? 0 : k + 1;
-        part += (xs[k].x - ox) * (xs[kn].y - oy) - (xs[kn].x - ox) * (xs[k].y - oy);
+        A2 += (xs[k].x - ox) * (xs[kn].y - oy) - (xs[kn].x - ox) * (xs[k].y - oy);
     }
-    part = wave_sum(part);
-    if (lane == 0) red[wid] = part;
-    __syncthreads();
-    double A2 = 0.0;
-    for (int w = 0; w < MEMBRANE_THREADS / 64; ++w) A2 += red[w];
+    block_reduce5(A2, bb, red);
     const double A = 0.5 * A2;
     if (t == 0) a.area[c] = A;
     const double s_area = a.kappa * (a.A0[c] - A);
 
     // 3. forces and spreading records
     int flags = 0;
-    for (int base = 0; base < n; base += MEM_UNROLL * MEMBRANE_THREADS) {
-        double lp[MEM_UNROLL], lm[MEM_UNROLL];
-        int ky[MEM_UNROLL];
-#pragma unroll
-        for (int u = 0; u < MEM_UNROLL; ++u) {
-            const int k = base + u * MEMBRANE_THREADS + t;
-            if (k >= n) continue;
-            const int km = (k == 0) ? n - 1 : k - 1;
-            lp[u] = a.l0[beg + k];
-            lm[u] = a.l0[beg + km];
-            ky[u] = a.ij_list[beg + k];
+    for (int k = t; k < n; k += MEMBRANE_THREADS) {
+        const int kp = (k + 1 == n) ? 0 : k + 1;
+        const int km = (k == 0) ? n - 1 : k - 1;
+        double lp = lp0, lm = lm0;
+        int ky = ky0;
+        if (k != t) {
+            lp = a.l0[beg + k];
+            lm = a.l0[beg + km];
+            ky = a.ij_list[beg + k];
         }
-#pragma unroll
-        for (int u = 0; u < MEM_UNROLL; ++u) {
-            const int k = base + u * MEMBRANE_THREADS + t;
-            if (k >= n) continue;
-            const int kp = (k + 1 == n) ? 0 : k + 1;
-            const int km = (k == 0) ? n - 1 : k - 1;
-            const double2 X = xs[k], Xp = xs[kp], Xm = xs[km];
-            const double dpx = Xp.x - X.x, dpy = Xp.y - X.y;
-            const double dmx = Xm.x - X.x, dmy = Xm.y - X.y;
-            const double Lp = sqrt(dpx * dpx + dpy * dpy), Lm = sqrt(dmx * dmx + dmy * dmy);
-            // tension phi_m along both edges; springs k (L - l0) along each edge
-            const double sp = (a.phi_m + a.k_spring * (Lp - lp[u])) / Lp;
-            const double sm = (a.phi_m + a.k_spring * (Lm - lm[u])) / Lm;
-            double Fx = sp * dpx + sm * dmx;
-            double Fy = sp * dpy + sm * dmy;
-            // area pressure: dA/dX_k = ((y_{k+1} - y_{k-1}) / 2, (x_{k-1} - x_{k+1}) / 2)
-            Fx += s_area * 0.5 * (Xp.y - Xm.y);
-            Fy += s_area * 0.5 * (Xm.x - Xp.x);
-            const int s = beg + k;
-            if (finite2(X.x, X.y) && finite2(Fx, Fy)) {
-                const double fx = floor(X.x), fy = floor(X.y);
-                int i0, j0;
-                stencil_origin(X.x, X.y, a.nx, a.ny, a.walls, i0, j0);
-                a.rec[s] = make_float4((float)(X.x - fx), (float)(X.y - fy), (float)Fx, (float)Fy);
-                a.rec_ij[s] = pack_ij(i0, j0);
-                if (!within_margin(i0, j0, ky[u], a.nx, a.ny, a.walls)) flags |= ERR_MARGIN;
-            } else {
-                a.rec[s] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                a.rec_ij[s] = 0;
-                flags |= ERR_NONFINITE;
-            }
+        const double2 X = xs[k], Xp = xs[kp], Xm = xs[km];
+        const double dpx = Xp.x - X.x, dpy = Xp.y - X.y;
+        const double dmx = Xm.x - X.x, dmy = Xm.y - X.y;
+        const double Lp = sqrt(dpx * dpx + dpy * dpy), Lm = sqrt(dmx * dmx + dmy * dmy);
+        // tension phi_m along both edges; springs k (L - l0) along each edge
+        const double sp = (a.phi_m + a.k_spring * (Lp - lp)) / Lp;
+        const double sm = (a.phi_m + a.k_spring * (Lm - lm)) / Lm;
+        double Fx = sp * dpx + sm * dmx;
+        double Fy = sp * dpy + sm * dmy;
+        // area pressure: dA/dX_k = ((y_{k+1} - y_{k-1}) / 2, (x_{k-1} - x_{k+1}) / 2)
+        Fx += s_area * 0.5 * (Xp.y - Xm.y);
+        Fy += s_area * 0.5 * (Xm.x - Xp.x);
+        const int s = beg + k;
+        if (finite2(X.x, X.y) && finite2(Fx, Fy)) {
+            const double fx = floor(X.x), fy = floor(X.y);
+            int i0, j0;
+            stencil_origin(X.x, X.y, a.nx, a.ny, a.walls, i0, j0);
+            a.rec[s] = make_float4((float)(X.x - fx), (float)(X.y - fy), (float)Fx, (float)Fy);
+            a.rec_ij[s] = pack_ij(i0, j0);
+            if (!within_margin(i0, j0, ky, a.nx, a.ny, a.walls)) flags |= ERR_MARGIN;
+        } else {
+            a.rec[s] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            a.rec_ij[s] = 0;
+            flags |= ERR_NONFINITE;
         }
     }
     if (flags) atomicOr(a.err, flags);
 
-    // 4. domain IDs of the new positions
-    if (a.raster) raster_cell(xs, n, (uint16_t)(c + 1), a.mask, a.nx, a.ny, a.walls, bm, RASTER_WORDS_FUSED, red);
+    // 4. inside-any-cell bits of the new positions (the bitmap was cleared above)
+    if (!a.raster) return;
+    const RasterBox b = raster_box(bb[0], bb[1], -bb[2], -bb[3], a.nx, a.ny);
+    if (!b.ok) return;                                               // uniform across the group
+    int CH = RASTER_WORDS_FUSED / b.WW;
+    if (CH < 1) CH = 1;
+    if (CH > b.H) CH = b.H;
+    for (int r0 = 0; r0 < b.H; r0 += CH) {
+        const int rows = (b.H - r0 < CH) ? b.H - r0 : CH;
+        if (r0 > 0) {
+            for (int i = t; i < rows * b.WW; i += MEMBRANE_THREADS) bm[i] = 0u;
+            __syncthreads();
+        }
+        raster_toggle(xs, n, b, r0, rows, bm);
+        __syncthreads();
+        raster_prefix(bm, rows, b.WW);
+        __syncthreads();
+        raster_or_bits(bm, b, r0, rows, a.inside, a.wpr, a.nx, a.ny, a.walls);
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------------------

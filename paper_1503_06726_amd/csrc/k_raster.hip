@@ -1,6 +1,6 @@
-// Standalone domain-ID rasterisation, one workgroup per cell (used when the map is not kept
-// up to date by the membrane kernel, i.e. when no reaction reads it).  The per-cell
-// algorithm is in lbib_raster.h.
+// Standalone domain-ID rasterisation, one workgroup per cell (the ID map is built on demand;
+// the time step keeps only the inside-any-cell bits).  The per-cell algorithm is in
+// lbib_raster.h.
 #include "lbib_internal.h"
 #include "lbib_raster.h"
 
@@ -13,7 +13,7 @@ __global__ __launch_bounds__(RASTER_THREADS) void k_raster(RasterArgs a)
     const int c = blockIdx.x;
     const int beg = a.off[c];
     const int n = a.off[c + 1] - beg;
-    raster_cell(a.X + beg, n, (uint16_t)(c + 1), a.mask, a.nx, a.ny, a.walls, bm, RASTER_WORDS, red);
+    raster_cell_ids(a.X + beg, n, (uint16_t)(c + 1), a.mask, a.nx, a.ny, a.walls, bm, RASTER_WORDS, red);
 }
 
 hipError_t launch_raster(lbib_ctx* c, const RasterArgs& a)

@@ -73,7 +73,9 @@ struct LatticeArgs {
     const float4* __restrict__ rec;    // [N] (sx, sy, Fx, Fy): fractional offset and force
     const int* __restrict__ rec_ij;    // [N] packed stencil origin (i0 | j0 << 16)
     unsigned long long* __restrict__ U_acc;   // [N][2] interpolated velocity, fixed point
-    uint16_t* __restrict__ mask;       // domain IDs; read, then cleared for the next raster
+    const unsigned* __restrict__ inside;   // inside-any-cell bits of this step, rows of wpr words
+    unsigned* __restrict__ inside_clr;     // the other buffer, cleared for the membrane kernel
+    int wpr;
     // inspection output (spread field only)
     double* __restrict__ e_out;
 };
@@ -88,7 +90,8 @@ struct MembraneArgs {
     const int* __restrict__ ij_list;   // packed stencil origin of each node at the last list build
     float4* __restrict__ rec;          // [N]
     int* __restrict__ rec_ij;          // [N]
-    uint16_t* __restrict__ mask;       // written when raster != 0
+    unsigned* __restrict__ inside;     // inside-any-cell bits, OR-ed into when raster != 0
+    int wpr;
     int* __restrict__ err;
     int64_t nn;
     int nx, ny, walls, kernel;

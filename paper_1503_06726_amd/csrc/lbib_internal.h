@@ -41,7 +41,9 @@ struct lbib_ctx {
     void* g[2] = {nullptr, nullptr};
     size_t pop_bytes = 4;            // bytes per stored population
     int cur = 0;
-    uint16_t* mask = nullptr;        // [ny][nx]
+    unsigned* inside[2] = {nullptr, nullptr};   // inside-any-cell bits [ny][wpr], by parity cur
+    int wpr = 0;                     // 32-bit words per lattice row
+    int64_t ny_words() const { return (int64_t)p.ny * wpr; }
 
     // membranes
     int32_t n_cells = 0;
