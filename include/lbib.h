@@ -149,6 +149,30 @@ lbib_status lbib_get_forces(lbib_ctx* ctx, double* F, double* area);
  * body acceleration, as [2][ny][nx] doubles (Eq. forcedistribution); synchronises. */
 lbib_status lbib_get_spread(lbib_ctx* ctx, double* e);
 
+/* Mark the cells whose interior is a source for the source/decay law (R = c[0] [inside a
+ * source cell] - c[1] phi): src[n_cells] host bytes, nonzero = source; NULL restores the
+ * default, every cell.  A node inside several cells is inside a source cell when any of them
+ * is one.  The cells must be set (LBIB_ESTATE otherwise); lbib_set_cells resets the choice.
+ * Synchronises. */
+lbib_status lbib_set_source_cells(lbib_ctx* ctx, const uint8_t* src);
+
+/* ADE-only iterations towards the steady state of the species (the "iterations to steady"
+ * measurement).  Every species lattice collides with u = 0 (equilibrium w_i phi) plus its
+ * reaction and streams (D2Q5 equations, halfway bounce-back at walls) while the fluid, the
+ * membranes and the source map stay frozen, starting from the current species state (set it
+ * with lbib_set_fields: zero, or a warm start), until for every species
+ *   ||phi^k - phi^{k-1}||_2 <= tol ||phi^k||_2,
+ * phi^k being the concentration after k iterations, or until k = max_iters.
+ *   fp64     1: iterate in FP64 (the state is copied to an FP64 working set and back);
+ *            0: iterate in FP32
+ *   iters    receives the first k meeting the criterion, 0 if none did within max_iters
+ *   change   receives the last relative change evaluated (maximum over species), or NULL
+ * Iterations run in captured batches of 128, so the species state left behind may be up to
+ * 127 iterations past k.  tol must be finite and >= 0, max_iters >= 0 (LBIB_EINVAL);
+ * LBIB_ENUMERIC if a change becomes non-finite.  Synchronises. */
+lbib_status lbib_ade_steady(lbib_ctx* ctx, double tol, int64_t max_iters, int32_t fp64, int64_t* iters,
+                            double* change);
+
 /* Global sums over the lattice in FP64, deterministic:
  *   out[0] = sum rho, out[1] = sum rho ux, out[2] = sum rho uy, out[3+s] = sum phi_s.
  * out has 3 + n_species doubles.  Returns LBIB_ENUMERIC if any sum is not finite. */

@@ -36,6 +36,12 @@
  *    a cell is tested with its periodic images; overlapping cells: the smallest ID wins.
  *  - Source/decay law: R = sigma [m != 0] - lambda phi.  Schnakenberg:
  *    R_0 = gamma (a - phi0 + phi0^2 phi1), R_1 = gamma (b - phi0^2 phi1).
+ *    With a source subset (orc_set_source_cells), [m != 0] becomes "inside at least one
+ *    source cell": the crossing test run over the source cells alone.
+ *  - ADE-only iteration (the steady-state measurement): the species lattices advance
+ *    with u = 0 while the fluid, the membranes and the domain map stay frozen; the
+ *    relative change after iteration k is ||phi^k - phi^{k-1}||_2 / ||phi^k||_2, with
+ *    phi^k = sum_i g_i after k collide-and-stream iterations (0 when both norms vanish).
  */
 #include "lbib_oracle.h"
 
@@ -67,6 +73,7 @@ struct orc_ctx {
     int64_t n_nodes;
     int32_t *off;
     double *X, *F, *l0, *A0, *area;
+    uint8_t *src;                 /* [n_cells] source cells of the source/decay law, NULL: all */
 };
 
 static int64_t wrapi(int64_t i, int64_t n) { int64_t r = i % n; return r < 0 ? r + n : r; }
@@ -302,6 +309,7 @@ void orc_destroy(orc_ctx* c)
     free(c->f); free(c->fnew); free(c->g); free(c->gnew);
     free(c->rho); free(c->ux); free(c->uy); free(c->ex); free(c->ey); free(c->mask);
     free(c->off); free(c->X); free(c->F); free(c->l0); free(c->A0); free(c->area);
+    free(c->src);
     free(c);
 }
 
@@ -309,6 +317,8 @@ int32_t orc_set_cells(orc_ctx* c, int32_t n_cells, const int32_t* off, const dou
                       const double* rest_len, const double* rest_area)
 {
     free(c->off); free(c->X); free(c->F); free(c->l0); free(c->A0); free(c->area);
+    free(c->src);
+    c->src = NULL;
     c->n_cells = n_cells;
     c->n_nodes = off[n_cells];
     size_t N = (size_t)c->n_nodes;
@@ -350,6 +360,49 @@ void orc_set_fields(orc_ctx* c, const double* rho, const double* u, const double
             for (int i = 0; i < 5; ++i) c->g[(s * 5 + i) * nn + x] = e5[i];
         }
     }
+}
+
+void orc_set_source_cells(orc_ctx* c, const uint8_t* src)
+{
+    free(c->src);
+    c->src = NULL;
+    if (!src || c->n_cells == 0) return;
+    c->src = (uint8_t*)malloc((size_t)c->n_cells);
+    memcpy(c->src, src, (size_t)c->n_cells);
+}
+
+/* The map the source/decay law reads: domain IDs of all cells, or, with a source subset,
+ * nonzero exactly at the nodes inside at least one source cell (the same crossing test
+ * over the source cells alone). */
+static void source_map(orc_ctx* c, int32_t* m)
+{
+    if (!c->src) {
+        orc_raster(&c->p, c->n_cells, c->off, c->X, m);
+        return;
+    }
+    int32_t ns = 0;
+    int64_t nodes = 0;
+    for (int32_t q = 0; q < c->n_cells; ++q)
+        if (c->src[q]) { ++ns; nodes += c->off[q + 1] - c->off[q]; }
+    int32_t* off = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ns + 1));
+    double* X = (double*)malloc(sizeof(double) * 2 * (size_t)(nodes ? nodes : 1));
+    off[0] = 0;
+    int32_t k = 0;
+    for (int32_t q = 0; q < c->n_cells; ++q) {
+        if (!c->src[q]) continue;
+        int64_t a = c->off[q], n = c->off[q + 1] - a;
+        memcpy(X + 2 * (int64_t)off[k], c->X + 2 * a, sizeof(double) * 2 * (size_t)n);
+        off[k + 1] = off[k] + (int32_t)n;
+        ++k;
+    }
+    orc_raster(&c->p, ns, off, X, m);
+    free(off);
+    free(X);
+}
+
+void orc_source_map(orc_ctx* c, int32_t* out)
+{
+    source_map(c, out);
 }
 
 static int needs_mask(const orc_params* p)
@@ -398,8 +451,8 @@ static void step_once(orc_ctx* c)
     }
     for (int64_t x = 0; x < nn; ++x) { c->ex[x] += p->body[0]; c->ey[x] += p->body[1]; }
 
-    /* 3: domain IDs */
-    if (needs_mask(p)) orc_raster(p, c->n_cells, c->off, c->X, c->mask);
+    /* 3: domain IDs (the map the source term reads) */
+    if (needs_mask(p)) source_map(c, c->mask);
     else memset(c->mask, 0, sizeof(int32_t) * (size_t)nn);
 
     /* 4: moments and collision (post-collision values into f / g in place) */
@@ -486,6 +539,74 @@ static void step_once(orc_ctx* c)
 void orc_step(orc_ctx* c, int32_t n)
 {
     for (int32_t k = 0; k < n; ++k) step_once(c);
+}
+
+/* n ADE-only iterations: every species collides with u = 0 (D2Q5 equilibrium w_i phi) plus
+ * its reaction, then streams with halfway bounce-back at walls; the fluid, the nodes and the
+ * domain map stay as they are.  change (NULL to skip) receives, per iteration k and species
+ * s, ||phi^{k+1} - phi^k||_2 / ||phi^{k+1}||_2 at change[k * S + s]. */
+void orc_ade_step(orc_ctx* c, int32_t n, double* change)
+{
+    const orc_params* p = &c->p;
+    int64_t nx = p->nx, ny = p->ny, nn = c->nn;
+    int S = p->n_species;
+    if (S == 0) return;
+    double tauD[2];
+    for (int s = 0; s < S; ++s) tauD[s] = 0.5 + p->D[s] / CS2;
+    if (needs_mask(p)) source_map(c, c->mask);
+    else memset(c->mask, 0, sizeof(int32_t) * (size_t)nn);
+    double* phi_old = (double*)malloc(sizeof(double) * (size_t)(S * nn));
+    for (int32_t k = 0; k < n; ++k) {
+        for (int s = 0; s < S; ++s)
+            for (int64_t x = 0; x < nn; ++x) {
+                double sum = 0.0;
+                for (int i = 0; i < 5; ++i) sum += c->g[(s * 5 + i) * nn + x];
+                phi_old[s * nn + x] = sum;
+            }
+        /* collision in place */
+#pragma omp parallel for schedule(static)
+        for (int64_t x = 0; x < nn; ++x) {
+            double phi[2] = {0.0, 0.0}, R[2];
+            for (int s = 0; s < S; ++s) phi[s] = phi_old[s * nn + x];
+            for (int s = 0; s < S; ++s) R[s] = orc_reaction(p, s, phi, c->mask[x]);
+            for (int s = 0; s < S; ++s)
+                for (int i = 0; i < 5; ++i) {
+                    double gi = c->g[(s * 5 + i) * nn + x];
+                    double geq = W5[i] * phi[s];
+                    c->g[(s * 5 + i) * nn + x] = gi - (gi - geq) / tauD[s] + R[s] * W5[i];
+                }
+        }
+        /* streaming */
+#pragma omp parallel for schedule(static)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                int64_t src = y * nx + x;
+                for (int s = 0; s < S; ++s)
+                    for (int i = 0; i < 5; ++i) {
+                        int64_t xd = wrapi(x + VX[i], nx), yd = y + VY[i];
+                        double v = c->g[(s * 5 + i) * nn + src];
+                        if (p->bc_y == ORC_WALLS && (yd < 0 || yd >= ny))
+                            c->gnew[(5 * s + OPP[i]) * nn + src] = v;
+                        else
+                            c->gnew[(s * 5 + i) * nn + wrapi(yd, ny) * nx + xd] = v;
+                    }
+            }
+        double* t = c->g; c->g = c->gnew; c->gnew = t;
+        if (change) {
+            for (int s = 0; s < S; ++s) {
+                double d2 = 0.0, p2 = 0.0;
+                for (int64_t x = 0; x < nn; ++x) {
+                    double sum = 0.0;
+                    for (int i = 0; i < 5; ++i) sum += c->g[(s * 5 + i) * nn + x];
+                    double d = sum - phi_old[s * nn + x];
+                    d2 += d * d;
+                    p2 += sum * sum;
+                }
+                change[(int64_t)k * S + s] = (d2 == 0.0) ? 0.0 : sqrt(d2) / sqrt(p2);
+            }
+        }
+    }
+    free(phi_old);
 }
 
 void orc_get_fields(orc_ctx* c, double* rho, double* u, double* phi, double* X, int32_t* mask)

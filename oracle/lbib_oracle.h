@@ -79,6 +79,9 @@ int32_t  orc_set_cells(orc_ctx* c, int32_t n_cells, const int32_t* off, const do
                        const double* rest_len, const double* rest_area);
 void     orc_set_fields(orc_ctx* c, const double* rho, const double* u, const double* phi);
 void     orc_step(orc_ctx* c, int32_t n);
+void     orc_set_source_cells(orc_ctx* c, const uint8_t* src);     /* [n_cells] flags, NULL: all */
+void     orc_ade_step(orc_ctx* c, int32_t n, double* change);      /* ADE-only, u = 0; change [n][S] */
+void     orc_source_map(orc_ctx* c, int32_t* out);                  /* [ny][nx], nonzero inside a source cell */
 void     orc_get_fields(orc_ctx* c, double* rho, double* u, double* phi, double* X, int32_t* mask);
 void     orc_get_populations(const orc_ctx* c, double* f, double* g);
 void     orc_set_populations(orc_ctx* c, const double* f, const double* g);

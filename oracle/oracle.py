@@ -76,6 +76,9 @@ def lib():
     L.orc_set_cells.argtypes = [C.c_void_p, C.c_int32, ip, dp, C.c_void_p, C.c_void_p]
     L.orc_set_fields.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.orc_step.argtypes = [C.c_void_p, C.c_int32]
+    L.orc_set_source_cells.argtypes = [C.c_void_p, C.c_void_p]
+    L.orc_ade_step.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
+    L.orc_source_map.argtypes = [C.c_void_p, C.c_void_p]
     L.orc_get_fields.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.orc_get_populations.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
     L.orc_set_populations.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -206,6 +209,40 @@ class Sim:
     def step(self, n: int = 1):
         self.L.orc_step(self.h, int(n))
 
+    def set_source_cells(self, src=None):
+        """Cells whose interior the source/decay law treats as a source (None: all)."""
+        a = None if src is None else np.ascontiguousarray(np.asarray(src) != 0, np.uint8)
+        self.L.orc_set_source_cells(self.h, _ptr(a))
+
+    def source_map(self) -> np.ndarray:
+        """[ny, nx] int32, nonzero exactly inside a source cell (the source/decay law's map)."""
+        m = np.zeros((self.ny, self.nx), np.int32)
+        self.L.orc_source_map(self.h, _ptr(m))
+        return m
+
+    def ade_step(self, n: int = 1) -> np.ndarray:
+        """n ADE-only iterations (u = 0, frozen fluid and membranes); returns the relative
+        change ||phi^{k+1} - phi^k|| / ||phi^{k+1}|| per iteration and species, [n][S]."""
+        ch = np.zeros((max(int(n), 1), max(self.S, 1)))
+        self.L.orc_ade_step(self.h, int(n), _ptr(ch))
+        return ch[:int(n), :self.S]
+
+    def ade_steady(self, tol: float, max_iters: int, chunk: int = 256):
+        """Iterate until every species' relative change is at most tol; returns (iterations,
+        change history [k][S]).  iterations is 0 when max_iters pass without convergence."""
+        hist = []
+        done = 0
+        while done < max_iters:
+            n = min(chunk, max_iters - done)
+            ch = self.ade_step(n)
+            for k in range(n):
+                hist.append(ch[k])
+                if np.all(ch[k] <= tol):
+                    # the state has advanced past the converged iteration: report, stop
+                    return done + k + 1, np.array(hist)
+            done += n
+        return 0, np.array(hist)
+
     def get_fields(self):
         ny, nx, S = self.ny, self.nx, self.S
         rho = np.zeros((ny, nx)); u = np.zeros((2, ny, nx)); phi = np.zeros((max(S, 1), ny, nx))
@@ -244,6 +281,8 @@ def from_workload(w, **kw) -> Sim:
     s = Sim(w.params_dict(), **kw)
     if w.n_cells:
         s.set_cells(w.offsets, w.xy, w.rest_len, w.rest_area)
+        if getattr(w, "source_cells", None) is not None:
+            s.set_source_cells(w.source_cells)
     if w.rho_init is not None or w.u_init is not None or w.phi_init is not None:
         s.set_fields(w.rho_init, w.u_init, w.phi_init)
     return s

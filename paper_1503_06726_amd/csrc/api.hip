@@ -160,6 +160,7 @@ MembraneArgs membrane_args(lbib_ctx* c, int advect)
     a.rec = c->d_rec;
     a.rec_ij = c->d_rec_ij;
     a.inside = c->inside[c->cur];
+    a.src = c->d_src;
     a.wpr = c->wpr;
     a.err = c->d_err;
     a.nn = c->nn;
@@ -278,6 +279,7 @@ void free_nodes(lbib_ctx* c)
     dev_free(c, c->d_rec, N);
     dev_free(c, c->d_rec_ij, N);
     dev_free(c, c->d_list, N * MAX_NODE_TILES);
+    dev_free(c, c->d_src, C);
     c->n_nodes = 0;
     c->n_cells = 0;
     c->max_cell_nodes = 0;
@@ -712,6 +714,167 @@ lbib_status lbib_reduce(lbib_ctx* c, double* out)
             return LBIB_ENUMERIC;
         }
     return LBIB_OK;
+}
+
+lbib_status lbib_set_source_cells(lbib_ctx* c, const uint8_t* src)
+{
+    if (!c) return LBIB_ESTATE;
+    if (c->n_cells == 0) {
+        c->err = "no cells are set";
+        return LBIB_ESTATE;
+    }
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    if (src) {
+        if (!c->d_src) LBIB_TRY(dev_alloc(c, &c->d_src, (size_t)c->n_cells));
+        LBIB_HIP(c, hipMemcpyAsync(c->d_src, src, (size_t)c->n_cells, hipMemcpyHostToDevice, c->stream));
+    } else {
+        dev_free(c, c->d_src, (size_t)c->n_cells);
+    }
+    if (c->mask_needed) {
+        // rebuild the source bits of the current positions (forces and records are recomputed
+        // from the same positions, unchanged)
+        LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->inside[c->cur], c->ny_words(), 0));
+        LBIB_TRY(membrane(c, 0));
+    }
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    return check_err_flag(c);
+}
+
+lbib_status lbib_ade_steady(lbib_ctx* c, double tol, int64_t max_iters, int32_t fp64, int64_t* iters,
+                            double* change)
+{
+    if (!c) return LBIB_ESTATE;
+    if (iters) *iters = 0;
+    if (change) *change = NAN;
+    if (c->S == 0) {
+        c->err = "no species to iterate";
+        return LBIB_EINVAL;
+    }
+    if (!std::isfinite(tol) || tol < 0.0 || max_iters < 0) {
+        c->err = "tol must be finite and >= 0, max_iters >= 0";
+        return LBIB_EINVAL;
+    }
+    if (max_iters == 0) return LBIB_OK;
+    constexpr int H = 128;                       // passes per captured batch (even)
+    const bool dbl = fp64 != 0;
+    const size_t wbytes = dbl ? sizeof(double) : sizeof(float);
+    const size_t nw = (size_t)5 * c->S * (size_t)c->nn;
+    const unsigned nb = ade_blocks(c->nn);
+    char* work[2] = {nullptr, nullptr};
+    double *phi_prev = nullptr, *partial = nullptr, *hist = nullptr;
+    int* counter = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<double> h((size_t)H * c->S);
+    lbib_status st = LBIB_OK;
+    int64_t found = 0, done = 0;
+    double last = NAN;
+    int wc = 0;
+    AdeArgs a;
+    std::memset(&a, 0, sizeof a);
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    for (int b = 0; b < 2 && st == LBIB_OK; ++b) st = dev_alloc(c, &work[b], nw * wbytes);
+    if (st == LBIB_OK) st = dev_alloc(c, &phi_prev, (size_t)c->S * (size_t)c->nn);
+    if (st == LBIB_OK) st = dev_alloc(c, &partial, (size_t)nb * 4);
+    if (st == LBIB_OK) st = dev_alloc(c, &hist, (size_t)H * c->S);
+    if (st == LBIB_OK) st = dev_alloc(c, &counter, 1);
+    if (st != LBIB_OK) goto out;
+    a.phi_prev = phi_prev;
+    a.inside = c->inside[c->cur];
+    a.wpr = c->wpr;
+    a.partial = partial;
+    a.counter = counter;
+    a.hist = hist;
+    a.nn = c->nn;
+    a.nx = c->p.nx;
+    a.ny = c->p.ny;
+    a.walls = c->p.bc_y == LBIB_WALLS;
+    a.S = c->S;
+    for (int s = 0; s < 2; ++s) {
+        const lbib_species& sp = c->p.species[s];
+        a.omega_s[s] = s < c->S ? 1.0 / (3.0 * sp.D + 0.5) : 0.0;
+        a.phi_ref[s] = sp.phi_ref;
+        a.react[s] = s < c->S ? sp.reaction : 0;
+        for (int k = 0; k < 4; ++k) a.rc[s][k] = sp.c[k];
+    }
+    if (launch_fill_i32(c, counter, 1, 0) != hipSuccess || launch_ade_copy(c, work[0], dbl, true) != hipSuccess) {
+        st = LBIB_EDEVICE;
+        goto out;
+    }
+    // first pass: phi^0 into phi_prev (no change yet), the state advances to iteration 1
+    a.src = work[0];
+    a.dst = work[1];
+    a.track = 0;
+    if (launch_ade(c, a, dbl, c->stream) != hipSuccess) {
+        st = LBIB_EDEVICE;
+        goto out;
+    }
+    wc = 1;
+    // H tracked passes per batch, captured once (the buffer parity repeats after H)
+    if (!c->capture_stream &&
+        hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        st = LBIB_EDEVICE;
+        goto out;
+    }
+    {
+        hipGraph_t graph = nullptr;
+        bool ok = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        for (int i = 0; i < H && ok; ++i) {
+            a.src = work[(wc + i) & 1];
+            a.dst = work[(wc + i + 1) & 1];
+            a.track = 1;
+            a.hslot = i;
+            ok = launch_ade(c, a, dbl, c->capture_stream) == hipSuccess;
+        }
+        const bool ended = hipStreamEndCapture(c->capture_stream, &graph) == hipSuccess;
+        ok = ok && ended && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) (void)hipGraphDestroy(graph);
+        if (!ok) {
+            c->err = "ADE batch capture failed";
+            st = LBIB_EDEVICE;
+            goto out;
+        }
+    }
+    while (done < max_iters && !found) {
+        if (hipGraphLaunch(exec, c->stream) != hipSuccess ||
+            hipMemcpyAsync(h.data(), hist, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess) {
+            c->err = "ADE batch failed";
+            st = LBIB_EDEVICE;
+            goto out;
+        }
+        for (int i = 0; i < H; ++i) {
+            const int64_t k = done + 1 + i;                  // the pass computed phi^k
+            if (k > max_iters) break;
+            double ch = 0.0;
+            for (int s = 0; s < c->S; ++s) ch = std::fmax(ch, h[(size_t)i * c->S + s]);
+            last = ch;
+            if (!std::isfinite(ch)) {
+                c->err = "non-finite concentration in the ADE iteration";
+                st = LBIB_ENUMERIC;
+                break;
+            }
+            if (ch <= tol) {
+                found = k;
+                break;
+            }
+        }
+        if (st != LBIB_OK) break;
+        done += H;
+    }
+    if (launch_ade_copy(c, work[wc], dbl, false) != hipSuccess) st = LBIB_EDEVICE;
+    if (hipStreamSynchronize(c->stream) != hipSuccess && st == LBIB_OK) st = LBIB_EDEVICE;
+    if (iters) *iters = found;
+    if (change) *change = last;
+out:
+    (void)hipStreamSynchronize(c->stream);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    for (int b = 0; b < 2; ++b) dev_free(c, work[b], nw * wbytes);
+    dev_free(c, phi_prev, (size_t)c->S * (size_t)c->nn);
+    dev_free(c, partial, (size_t)nb * 4);
+    dev_free(c, hist, (size_t)H * c->S);
+    dev_free(c, counter, 1);
+    return st;
 }
 
 lbib_status lbib_sync(lbib_ctx* c)

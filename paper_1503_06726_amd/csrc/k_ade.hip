@@ -1,0 +1,192 @@
+// ADE-only iterations of the species lattices (gfx950), the steady-state measurement: every
+// species collides with u = 0 (D2Q5 equilibrium w_i phi, Suppl. "Lattice Boltzmann Method")
+// plus its reaction and streams with halfway bounce-back at walls, while the fluid, the
+// membranes and the domain map stay frozen.  The iteration runs in a working set of float or
+// double deviations; each pass also reports the relative change ||phi^k - phi^{k-1}||_2 /
+// ||phi^k||_2 of every species through a deterministic two-level reduction (per-block sums,
+// then the last block to finish adds them in block order).
+#include "lbib_internal.h"
+
+namespace lbib {
+
+constexpr int ADE_THREADS = 256;
+
+template <typename WT>
+__device__ inline void pull5w(const WT* __restrict__ s, int64_t nn, int x, int y, int nx, int ny, int walls, WT g[5])
+{
+    const int xm = (x == 0) ? nx - 1 : x - 1, xp = (x == nx - 1) ? 0 : x + 1;
+    const int64_t rc = (int64_t)y * nx;
+    bool bot = false, top = false;
+    int ym, yp;
+    if (walls) {
+        bot = (y == 0);
+        top = (y == ny - 1);
+        ym = bot ? y : y - 1;
+        yp = top ? y : y + 1;
+    } else {
+        ym = (y == 0) ? ny - 1 : y - 1;
+        yp = (y == ny - 1) ? 0 : y + 1;
+    }
+    // g_i(x) = s_i(x - v_i); across a wall the population returns reversed: s_opp(i)(x)
+    g[0] = s[rc + x];
+    g[1] = s[nn + rc + xm];
+    g[2] = bot ? s[4 * nn + rc + x] : s[2 * nn + (int64_t)ym * nx + x];
+    g[3] = s[3 * nn + rc + xp];
+    g[4] = top ? s[2 * nn + rc + x] : s[4 * nn + (int64_t)yp * nx + x];
+}
+
+template <typename WT>
+__global__ __launch_bounds__(ADE_THREADS) void k_ade(AdeArgs a)
+{
+    __shared__ double sh[4][ADE_THREADS];
+    __shared__ int last;
+    const int t = threadIdx.x;
+    const int64_t idx = (int64_t)blockIdx.x * ADE_THREADS + t;
+    const WT w0 = WT(1) / WT(3), w1 = WT(1) / WT(6);
+    double d2[2] = {0.0, 0.0}, p2[2] = {0.0, 0.0};
+    if (idx < a.nn) {
+        const int x = (int)(idx % a.nx), y = (int)(idx / a.nx);
+        const WT* src = (const WT*)a.src;
+        WT* dst = (WT*)a.dst;
+        WT g[2][5], dphi[2], phi[2];
+        for (int s = 0; s < a.S; ++s) {
+            pull5w<WT>(src + (int64_t)5 * s * a.nn, a.nn, x, y, a.nx, a.ny, a.walls, g[s]);
+            dphi[s] = ((g[s][0] + g[s][1]) + (g[s][2] + g[s][3])) + g[s][4];
+            phi[s] = (WT)a.phi_ref[s] + dphi[s];
+        }
+        const int m = (int)((a.inside[(int64_t)y * a.wpr + (x >> 5)] >> (x & 31)) & 1u);
+        for (int s = 0; s < a.S; ++s) {
+            WT R = WT(0);
+            if (a.react[s] == LBIB_REACT_SOURCE_DECAY) {
+                R = (m ? (WT)a.rc[s][0] : WT(0)) - (WT)a.rc[s][1] * phi[s];
+            } else if (a.react[s] == LBIB_REACT_SCHNAKENBERG && a.S == 2) {
+                const WT u2v = phi[0] * phi[0] * phi[1];
+                R = (s == 0) ? (WT)a.rc[s][2] * ((WT)a.rc[s][0] - phi[0] + u2v) : (WT)a.rc[s][2] * ((WT)a.rc[s][1] - u2v);
+            }
+            const WT om = (WT)a.omega_s[s], om1 = WT(1) - om;
+            WT* d = dst + (int64_t)5 * s * a.nn + idx;
+            // deviation form: dg_i <- dg_i - omega (dg_i - w_i dphi) + w_i R
+            d[0] = om1 * g[s][0] + om * w0 * dphi[s] + w0 * R;
+            for (int i = 1; i < 5; ++i) d[i * a.nn] = om1 * g[s][i] + om * w1 * dphi[s] + w1 * R;
+            const double ph = (double)phi[s];
+            double* pp = a.phi_prev + (int64_t)s * a.nn + idx;
+            if (a.track) {
+                const double df = ph - *pp;
+                d2[s] = df * df;
+                p2[s] = ph * ph;
+            }
+            *pp = ph;
+        }
+    }
+    if (!a.track) return;                                   // uniform: no reduction on the first pass
+
+    // per-block sums (fixed tree), then the last block adds the blocks in order
+    for (int q = 0; q < 2; ++q) {
+        sh[2 * q][t] = d2[q];
+        sh[2 * q + 1][t] = p2[q];
+    }
+    __syncthreads();
+    for (int w = ADE_THREADS / 2; w > 0; w >>= 1) {
+        if (t < w)
+            for (int v = 0; v < 4; ++v) sh[v][t] += sh[v][t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        for (int v = 0; v < 2 * a.S; ++v)
+            __hip_atomic_store(&a.partial[(int64_t)blockIdx.x * 4 + v], sh[v][0], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        last = (atomicAdd(a.counter, 1) == (int)gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = t; b < (int)gridDim.x; b += ADE_THREADS)
+        for (int v = 0; v < 2 * a.S; ++v)
+            acc[v] += __hip_atomic_load(&a.partial[(int64_t)b * 4 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    for (int v = 0; v < 4; ++v) sh[v][t] = acc[v];
+    __syncthreads();
+    for (int w = ADE_THREADS / 2; w > 0; w >>= 1) {
+        if (t < w)
+            for (int v = 0; v < 4; ++v) sh[v][t] += sh[v][t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        for (int s = 0; s < a.S; ++s) {
+            const double dd = sh[2 * s][0], pp = sh[2 * s + 1][0];
+            a.hist[(int64_t)a.hslot * a.S + s] = (dd == 0.0) ? 0.0 : sqrt(dd) / sqrt(pp);
+        }
+        *a.counter = 0;
+    }
+}
+
+// working set <- the context's populations (storage ST), and back
+template <int ST, typename WT>
+__global__ void k_ade_load(const void* __restrict__ g, WT* __restrict__ w, int64_t nn, int S)
+{
+    using T = typename Pop<ST>::T;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nn) return;
+    const T* gs = (const T*)g;
+    for (int s = 0; s < S; ++s)
+        for (int i = 0; i < 5; ++i) {
+            const int64_t o = ((int64_t)5 * s + i) * nn + idx;
+            w[o] = (WT)Pop<ST>::ld(gs[o], IS5[i]);
+        }
+}
+
+template <int ST, typename WT>
+__global__ void k_ade_store(const WT* __restrict__ w, void* __restrict__ g, int64_t nn, int S)
+{
+    using T = typename Pop<ST>::T;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nn) return;
+    T* gs = (T*)g;
+    for (int s = 0; s < S; ++s)
+        for (int i = 0; i < 5; ++i) {
+            const int64_t o = ((int64_t)5 * s + i) * nn + idx;
+            gs[o] = Pop<ST>::st((float)w[o], SC5[i]);
+        }
+}
+
+hipError_t launch_ade(lbib_ctx* c, const AdeArgs& a, bool fp64, hipStream_t stream)
+{
+    const unsigned nb = (unsigned)((a.nn + ADE_THREADS - 1) / ADE_THREADS);
+    if (fp64) hipLaunchKernelGGL(k_ade<double>, dim3(nb), dim3(ADE_THREADS), 0, stream, a);
+    else hipLaunchKernelGGL(k_ade<float>, dim3(nb), dim3(ADE_THREADS), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <typename WT>
+static hipError_t ade_copy(lbib_ctx* c, void* work, bool to_work)
+{
+    const unsigned nb = (unsigned)((c->nn + 255) / 256);
+    const void* g = c->g[c->cur];
+    WT* w = (WT*)work;
+    switch (c->p.storage) {
+    case LBIB_STORAGE_FP16:
+        if (to_work) hipLaunchKernelGGL((k_ade_load<1, WT>), dim3(nb), dim3(256), 0, c->stream, g, w, c->nn, c->S);
+        else hipLaunchKernelGGL((k_ade_store<1, WT>), dim3(nb), dim3(256), 0, c->stream, w, c->g[c->cur], c->nn, c->S);
+        break;
+    case LBIB_STORAGE_BF16:
+        if (to_work) hipLaunchKernelGGL((k_ade_load<2, WT>), dim3(nb), dim3(256), 0, c->stream, g, w, c->nn, c->S);
+        else hipLaunchKernelGGL((k_ade_store<2, WT>), dim3(nb), dim3(256), 0, c->stream, w, c->g[c->cur], c->nn, c->S);
+        break;
+    default:
+        if (to_work) hipLaunchKernelGGL((k_ade_load<0, WT>), dim3(nb), dim3(256), 0, c->stream, g, w, c->nn, c->S);
+        else hipLaunchKernelGGL((k_ade_store<0, WT>), dim3(nb), dim3(256), 0, c->stream, w, c->g[c->cur], c->nn, c->S);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ade_copy(lbib_ctx* c, void* work, bool fp64, bool to_work)
+{
+    return fp64 ? ade_copy<double>(c, work, to_work) : ade_copy<float>(c, work, to_work);
+}
+
+unsigned ade_blocks(int64_t nn) { return (unsigned)((nn + ADE_THREADS - 1) / ADE_THREADS); }
+
+}  // namespace lbib

@@ -176,8 +176,9 @@ __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
     }
     if (flags) atomicOr(a.err, flags);
 
-    // 4. inside-any-cell bits of the new positions (the bitmap was cleared above)
-    if (!a.raster) return;
+    // 4. inside-any-cell bits of the new positions (the bitmap was cleared above); with a
+    //    source subset only the source cells are rasterised
+    if (!a.raster || (a.src && !a.src[c])) return;
     const RasterBox b = raster_box(bb[0], bb[1], -bb[2], -bb[3], a.nx, a.ny);
     if (!b.ok) return;                                               // uniform across the group
     int CH = RASTER_WORDS_FUSED / b.WW;
@@ -238,25 +239,28 @@ __device__ inline int node_tiles(int i0, int j0, const ListArgs& a, int tiles[MA
     return n;
 }
 
-// Wavefront-aggregated increment: every live lane adds 1 to counter[key]; one atomic per
-// distinct key among the lanes.  Returns the counter's previous value plus the lane's rank
-// among the lanes sharing its key.
+// Wavefront-aggregated increment: every live lane adds 1 to counter[key].  Lanes are grouped
+// into runs of consecutive lanes with the same key (consecutive membrane nodes mostly share a
+// tile); the first lane of each run adds the run length with one atomic, all runs at once.
+// Returns the counter's previous value plus the lane's rank within its run (when RET).
+template <bool RET>
 __device__ inline int wave_claim(int* counter, int key, bool live)
 {
     const int lane = threadIdx.x & 63;
-    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    unsigned long long todo = __ballot(live);
+    const int k = live ? key : -1;
+    const int prev = __shfl_up(k, 1, 64);
+    const bool head = lane == 0 || prev != k;
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+    const int first = 63 - __clzll((long long)(heads & upto));            // head of the lane's run
     int pos = 0;
-    while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const int lkey = __shfl(key, leader, 64);
-        const unsigned long long grp = __ballot(live && key == lkey);
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&counter[lkey], __popcll(grp));
-        base = __shfl(base, leader, 64);
-        if (live && key == lkey) pos = base + __popcll(grp & below);
-        todo &= ~grp;
+    if (head && live) {
+        const unsigned long long above = heads & ~upto;
+        const int next = above ? __ffsll((long long)above) - 1 : 64;    // head of the next run
+        if constexpr (RET) pos = atomicAdd(&counter[key], next - lane);
+        else atomicAdd(&counter[key], next - lane);
     }
+    if constexpr (RET) pos = __shfl(pos, first, 64) + (lane - first);
     return pos;
 }
 
@@ -281,7 +285,7 @@ __global__ void k_list_count(ListArgs a)
     for (int k = 0; k < MAX_NODE_TILES; ++k) {
         const bool on = live && k < nt;
         if (!__ballot(on)) break;
-        (void)wave_claim(a.count, on ? tiles[k] : 0, on);
+        (void)wave_claim<false>(a.count, on ? tiles[k] : 0, on);
     }
 }
 
@@ -356,7 +360,7 @@ __global__ void k_list_fill(ListArgs a)
     for (int k = 0; k < MAX_NODE_TILES; ++k) {
         const bool on = live && k < nt;
         if (!__ballot(on)) break;
-        const int p = wave_claim(a.cursor, on ? tiles[k] : 0, on);
+        const int p = wave_claim<true>(a.cursor, on ? tiles[k] : 0, on);
         if (on) a.list[p] = (int)l;
     }
 }

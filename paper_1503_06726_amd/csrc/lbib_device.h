@@ -27,7 +27,7 @@ constexpr int RPT = 2;
 constexpr int LTILE_Y = TILE_Y * RPT;
 
 constexpr int LIST_MARGIN = 2;       // lattice units a node may drift between list rebuilds
-constexpr int LIST_PERIOD = 8;       // steps between list rebuilds
+constexpr int LIST_PERIOD = 16;      // steps between list rebuilds (nodes may move 2/16 lu per step)
 constexpr int MAX_NODE_TILES = 9;    // tiles one node can be listed in (3 columns x 3 rows at most)
 constexpr int GRAPH_STEPS = 16;      // steps per captured graph (a multiple of LIST_PERIOD)
 
@@ -91,6 +91,7 @@ struct MembraneArgs {
     float4* __restrict__ rec;          // [N]
     int* __restrict__ rec_ij;          // [N]
     unsigned* __restrict__ inside;     // inside-any-cell bits, OR-ed into when raster != 0
+    const uint8_t* __restrict__ src;   // [n_cells] source cells (NULL: every cell is rasterised)
     int wpr;
     int* __restrict__ err;
     int64_t nn;
@@ -109,6 +110,26 @@ struct ListArgs {
     int* __restrict__ list;            // [N * MAX_NODE_TILES] capacity
     int64_t n;
     int nx, ny, walls, ntx, nlty, ntiles;
+};
+
+// ADE-only iteration (species with u = 0, fluid and membranes frozen) in a working set of
+// WT (float or double) deviations dg = g - w phi_ref, planes [S][5][ny][nx]
+struct AdeArgs {
+    const void* __restrict__ src;
+    void* __restrict__ dst;
+    double* __restrict__ phi_prev;     // [S][ny][nx] phi of the previous pass
+    const unsigned* __restrict__ inside;   // source bits (source/decay law)
+    int wpr;
+    double* __restrict__ partial;      // [nblocks][2 S] per-block sums
+    int* __restrict__ counter;         // blocks finished (the last one resets it)
+    double* __restrict__ hist;         // [slots][S] relative change per pass
+    int64_t nn;
+    int nx, ny, walls, S;
+    double omega_s[2], phi_ref[2];
+    int react[2];
+    double rc[2][4];
+    int hslot;                         // history slot of this pass
+    int track;                         // 0: first pass (phi_prev is only written)
 };
 
 struct RasterArgs {

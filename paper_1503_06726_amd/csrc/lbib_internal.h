@@ -63,6 +63,7 @@ struct lbib_ctx {
     int* d_t_off = nullptr;          // [nltiles + 1]
     int* d_t_cur = nullptr;          // [nltiles] fill cursors
     int* d_err = nullptr;            // device error flags
+    uint8_t* d_src = nullptr;        // [n_cells] source cells of the source/decay law (NULL: all)
     int steps_since_lists = 0;
 
     // staging
@@ -103,5 +104,8 @@ hipError_t launch_raster(lbib_ctx* c, const RasterArgs& a);
 hipError_t launch_fill_i32(lbib_ctx* c, int* p, int64_t n, int v);
 hipError_t launch_fill_u16(lbib_ctx* c, uint16_t* p, int64_t n);
 hipError_t launch_fill_f32(lbib_ctx* c, float* p, int64_t n);
+hipError_t launch_ade(lbib_ctx* c, const AdeArgs& a, bool fp64, hipStream_t stream);
+hipError_t launch_ade_copy(lbib_ctx* c, void* work, bool fp64, bool to_work);
+unsigned ade_blocks(int64_t nn);
 
 }  // namespace lbib

@@ -26,7 +26,8 @@ KERNEL_NAMES = ["lattice", "membrane", "lists"]
 EXPORTS = ["lbib_validate_params", "lbib_validate_cells", "lbib_create", "lbib_set_cells",
            "lbib_set_fields", "lbib_step", "lbib_get_fields", "lbib_get_forces", "lbib_get_spread",
            "lbib_reduce", "lbib_sync", "lbib_set_timing", "lbib_get_timing", "lbib_device_bytes",
-           "lbib_last_error", "lbib_status_string", "lbib_version", "lbib_destroy"]
+           "lbib_last_error", "lbib_status_string", "lbib_version", "lbib_destroy",
+           "lbib_set_source_cells", "lbib_ade_steady"]
 
 
 class Species(C.Structure):
@@ -103,6 +104,11 @@ def lib():
     L.lbib_version.argtypes = []
     L.lbib_destroy.restype = None
     L.lbib_destroy.argtypes = [vp]
+    L.lbib_set_source_cells.restype = st
+    L.lbib_set_source_cells.argtypes = [vp, vp]
+    L.lbib_ade_steady.restype = st
+    L.lbib_ade_steady.argtypes = [vp, C.c_double, C.c_int64, C.c_int32, C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_double)]
     _lib = L
     return L
 
@@ -242,6 +248,19 @@ class Simulation:
         self._check(self.L.lbib_reduce(self.h, _p(out)), "lbib_reduce")
         return out
 
+    def set_source_cells(self, src=None):
+        """Cells whose interior the source/decay law treats as a source (None: every cell)."""
+        a = None if src is None else np.ascontiguousarray(np.asarray(src) != 0, np.uint8)
+        self._check(self.L.lbib_set_source_cells(self.h, _p(a)), "lbib_set_source_cells")
+
+    def ade_steady(self, tol: float, max_iters: int, fp64: bool = True):
+        """ADE-only iterations (u = 0, frozen fluid and membranes) until the relative change of
+        every species is at most tol; returns (iterations, last relative change)."""
+        it, ch = C.c_int64(0), C.c_double(0.0)
+        self._check(self.L.lbib_ade_steady(self.h, float(tol), int(max_iters), 1 if fp64 else 0,
+                                           C.byref(it), C.byref(ch)), "lbib_ade_steady")
+        return int(it.value), float(ch.value)
+
     def sync(self):
         self._check(self.L.lbib_sync(self.h), "lbib_sync")
 
@@ -271,4 +290,6 @@ def from_workload(w, stream: int | None = None, storage: int | None = None) -> S
         s.set_fields(w.rho_init, w.u_init, w.phi_init)
     if w.n_cells:
         s.set_cells(w.offsets, w.xy, w.rest_len, w.rest_area)
+        if getattr(w, "source_cells", None) is not None:
+            s.set_source_cells(w.source_cells)
     return s

@@ -68,6 +68,7 @@ class Workload:
     xy: np.ndarray = None           # float64 [N, 2], CCW per cell
     rest_len: np.ndarray = None     # float64 [N] or None (initial); edge k joins node k and its successor
     rest_area: np.ndarray = None    # float64 [n_cells] or None (initial)
+    source_cells: np.ndarray = None  # uint8 [n_cells] source cells of the source/decay law, None: all
     # initial fields (None = rho0, u = 0, phi = phi_ref)
     rho_init: np.ndarray = None     # float64 [ny, nx]
     u_init: np.ndarray = None       # float64 [2, ny, nx]
@@ -305,6 +306,31 @@ def random_fields(w: Workload, seed: int, amp_rho: float = 1e-3, amp_u: float = 
     if w.n_species:
         base = np.array([s.phi_ref if s.phi_ref != 0 else 0.1 for s in w.species])[:, None, None]
         w.phi_init = base + amp_phi * rng.standard_normal((w.n_species, ny, nx))
+    return w
+
+
+def static_tissue(sample: int, held_out: bool = True, n: int = 256, source_p: float = 0.2) -> Workload:
+    """One steady-state sample: an n x n lattice (walls in y, periodic in x) holding a static
+    Voronoi tissue of 50..300 cells, of which each is a source with probability source_p
+    (at least one), and one species with diffusivity D ~ U(0.02, 0.5), source 1e-3 inside
+    the source cells and decay lambda ~ U(1e-5, 1e-3).  The fluid and the membranes stay at
+    rest (no forces); the species starts from zero.  Held-out samples and training samples
+    come from disjoint seed streams."""
+    rng = _rng(5 if held_out else 6, sample)
+    n_cells = int(rng.integers(50, 301))
+    offsets, xy = voronoi_tissue(n, n, n_cells, rng)
+    src = (rng.random(n_cells) < source_p).astype(np.uint8)
+    if not src.any():
+        src[int(rng.integers(n_cells))] = 1
+    D = float(rng.uniform(0.02, 0.5))
+    lam = float(rng.uniform(1e-5, 1e-3))
+    w = Workload(name=f"static tissue {n}x{n} walls-y, {n_cells} cells ({int(src.sum())} sources), "
+                      f"D = {D:.4g}, decay {lam:.3g}",
+                 nx=n, ny=n, bc_y=WALLS, tau=1.0, rho0=1.0, species=[
+                     Species(D=D, phi_ref=0.0, reaction=REACT_SOURCE_DECAY, c=(1e-3, lam, 0.0, 0.0))],
+                 steps=0)
+    w = _attach_geometry(w, offsets, xy)
+    w.source_cells = src
     return w
 
 

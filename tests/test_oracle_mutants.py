@@ -58,6 +58,12 @@ MUTANTS = {
     "raster parity": ("if (cnt & 1) {", "if (cnt > 0) {"),
     "specular walls": ("c->fnew[OPP[i] * nn + src] = v;", "c->fnew[i * nn + src] = v;"),
     "diffusivity relation": ("tauD[s] = p->D[s] / CS2 + 0.5;", "tauD[s] = p->D[s] * CS2 + 0.5;"),
+    "ade reaction without weights": ("+ R[s] * W5[i];", "+ R[s];"),
+    "ade diffusivity relation": ("tauD[s] = 0.5 + p->D[s] / CS2;", "tauD[s] = 0.5 + p->D[s] * CS2;"),
+    "ade change without root": ("(d2 == 0.0) ? 0.0 : sqrt(d2) / sqrt(p2);", "(d2 == 0.0) ? 0.0 : d2 / p2;"),
+    "ade equilibrium weight": ("double geq = W5[i] * phi[s];", "double geq = W5[0] * phi[s];"),
+    "ade specular walls": ("c->gnew[(5 * s + OPP[i]) * nn + src] = v;", "c->gnew[(5 * s + i) * nn + src] = v;"),
+    "source subset ignored": ("    if (!c->src) {\n        orc_raster(", "    if (1) {\n        orc_raster("),
     "body force overwrites spread": ("c->ex[x] += p->body[0];", "c->ex[x] = p->body[0];"),
     "moments velocity sign": ("jx += fi * VX[i];\n            jy += fi * VY[i];\n        }\n        c->rho[x] = r;",
                               "jx -= fi * VX[i];\n            jy += fi * VY[i];\n        }\n        c->rho[x] = r;"),
@@ -75,7 +81,8 @@ def _run_mutant(name, old, new, tmp):
                     "-I", os.path.join(ROOT, "oracle"), "-o", so, mpath, "-lm"], check=True)
     env = dict(os.environ, ORACLE_LIB=so, OMP_NUM_THREADS="1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-m", "not slow"],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_ade.py"), "-m", "not slow"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, r.returncode
 
