@@ -1,11 +1,13 @@
-"""Throughput of the coupled LBM + IB step on one MI355X.
+"""Throughput of the coupled LBM + IB step on one MI355X, and iterations to steady state.
 
-A step is one pass of the whole hot path (lattice pass with force spreading, membrane
-interpolation / advection / forces, node binning, domain-ID rasterisation) over the
-2048 x 2048 lattice with 2000 Voronoi cells.  Prints one JSON line (rank 0).
+A step is one pass of the whole hot path (lattice pass with force spreading and velocity
+interpolation, membrane advection / forces / source map, per-tile node lists) over the
+2048 x 2048 lattice with 2000 Voronoi cells.  The second half of the metric counts the
+iterations the species lattice alone needs to reach steady state on held-out 256 x 256
+static-tissue samples.  Prints one JSON line (rank 0).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|tissue|tiny]
-                  [--no-cpu-baseline]
+                  [--storage fp32|fp16|bf16] [--ade-samples N] [--no-cpu-baseline]
 """
 import argparse
 import json
@@ -42,6 +44,44 @@ def step_bytes_per_update(S: int, mask: bool, n_nodes: int, nn: int, pop_bytes: 
     return lattice_bytes_per_update(S, mask, pop_bytes) + 16.0 * n_nodes / nn
 
 
+ADE_TOL = 1e-6
+ADE_CAP = 1_000_000
+
+
+def ade_samples(n: int):
+    """The held-out static-tissue samples (generated on the host in a process pool, before the
+    GPU is touched)."""
+    import concurrent.futures as cf
+    from paper_1503_06726_amd import workloads as W
+    if n <= 0:
+        return []
+    with cf.ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        return list(ex.map(W.static_tissue, range(n)))
+
+
+def ade_half(samples, lbib, stream):
+    """Iterations to steady state of the species alone (u = 0, frozen membranes) from a zero
+    start, in FP64, stopping at ||phi^k - phi^{k-1}|| <= 1e-6 ||phi^k||."""
+    import numpy as np
+    its, secs, passes = [], 0.0, 0
+    for w in samples:
+        sim = lbib.from_workload(w, stream=stream)
+        sim.sync()
+        t0 = time.perf_counter()
+        k, _ = sim.ade_steady(ADE_TOL, ADE_CAP, fp64=True)
+        secs += time.perf_counter() - t0
+        sim.close()
+        its.append(k if k > 0 else ADE_CAP)
+        passes += 1 + 128 * (((k if k > 0 else ADE_CAP) + 127) // 128)
+    its = np.asarray(its)
+    return {"workload": "static tissue 256x256 walls-y, 50-300 Voronoi cells, seeded source cells, "
+                        "D ~ U(0.02, 0.5), decay ~ U(1e-5, 1e-3), source 1e-3; held-out seeds",
+            "samples": len(samples), "tol": ADE_TOL, "cap": ADE_CAP, "start": "zero", "precision": "f64",
+            "median_iters": float(np.median(its)), "mean_iters": round(float(its.mean()), 1),
+            "unconverged": int((its >= ADE_CAP).sum()),
+            "us_per_iter": round(secs / max(passes, 1) * 1e6, 3)}
+
+
 def cpu_baseline(w, budget_s: float = 12.0, max_steps: int = 30):
     from oracle import oracle as O
     log("cpu baseline: oracle on the same workload")
@@ -69,6 +109,8 @@ def main():
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"],
                     help="population storage (collision always in FP32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ade-samples", type=int, default=256,
+                    help="held-out static-tissue samples for the iterations-to-steady half (0 skips)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain device copy of 1 GiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -76,6 +118,8 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the lattice would shard into "
               "y-slabs across GPUs, which this build does not implement.", file=sys.stderr)
         sys.exit(2)
+
+    samples = [] if args.copy_probe else ade_samples(args.ade_samples)
 
     import torch
     from paper_1503_06726_amd import lbib, workloads as W
@@ -151,6 +195,10 @@ def main():
            "roofline": roof,
            "kernels_us": {k: round(ms / n * 1e3, 2) for k, (ms, n) in timings.items() if n},
            "mass": red[0]}
+    if samples:
+        log(f"iterations to steady: {len(samples)} samples")
+        out["ade_iters_to_steady"] = ade_half(samples, lbib, stream)
+        log(f"  {out['ade_iters_to_steady']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

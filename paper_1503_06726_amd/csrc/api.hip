@@ -763,7 +763,6 @@ lbib_status lbib_ade_steady(lbib_ctx* c, double tol, int64_t max_iters, int32_t 
     const unsigned nb = ade_blocks(c->nn);
     char* work[2] = {nullptr, nullptr};
     double *phi_prev = nullptr, *partial = nullptr, *hist = nullptr;
-    int* counter = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<double> h((size_t)H * c->S);
     lbib_status st = LBIB_OK;
@@ -775,16 +774,13 @@ lbib_status lbib_ade_steady(lbib_ctx* c, double tol, int64_t max_iters, int32_t 
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
     for (int b = 0; b < 2 && st == LBIB_OK; ++b) st = dev_alloc(c, &work[b], nw * wbytes);
     if (st == LBIB_OK) st = dev_alloc(c, &phi_prev, (size_t)c->S * (size_t)c->nn);
-    if (st == LBIB_OK) st = dev_alloc(c, &partial, (size_t)nb * 4);
+    if (st == LBIB_OK) st = dev_alloc(c, &partial, (size_t)H * nb * 4);
     if (st == LBIB_OK) st = dev_alloc(c, &hist, (size_t)H * c->S);
-    if (st == LBIB_OK) st = dev_alloc(c, &counter, 1);
     if (st != LBIB_OK) goto out;
     a.phi_prev = phi_prev;
     a.inside = c->inside[c->cur];
     a.wpr = c->wpr;
     a.partial = partial;
-    a.counter = counter;
-    a.hist = hist;
     a.nn = c->nn;
     a.nx = c->p.nx;
     a.ny = c->p.ny;
@@ -797,7 +793,7 @@ lbib_status lbib_ade_steady(lbib_ctx* c, double tol, int64_t max_iters, int32_t 
         a.react[s] = s < c->S ? sp.reaction : 0;
         for (int k = 0; k < 4; ++k) a.rc[s][k] = sp.c[k];
     }
-    if (launch_fill_i32(c, counter, 1, 0) != hipSuccess || launch_ade_copy(c, work[0], dbl, true) != hipSuccess) {
+    if (launch_ade_copy(c, work[0], dbl, true) != hipSuccess) {
         st = LBIB_EDEVICE;
         goto out;
     }
@@ -826,6 +822,7 @@ lbib_status lbib_ade_steady(lbib_ctx* c, double tol, int64_t max_iters, int32_t 
             a.hslot = i;
             ok = launch_ade(c, a, dbl, c->capture_stream) == hipSuccess;
         }
+        if (ok) ok = launch_ade_hist(partial, (int)nb, c->S, hist, H, c->capture_stream) == hipSuccess;
         const bool ended = hipStreamEndCapture(c->capture_stream, &graph) == hipSuccess;
         ok = ok && ended && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
         if (graph) (void)hipGraphDestroy(graph);
@@ -871,9 +868,8 @@ out:
     if (exec) (void)hipGraphExecDestroy(exec);
     for (int b = 0; b < 2; ++b) dev_free(c, work[b], nw * wbytes);
     dev_free(c, phi_prev, (size_t)c->S * (size_t)c->nn);
-    dev_free(c, partial, (size_t)nb * 4);
+    dev_free(c, partial, (size_t)H * nb * 4);
     dev_free(c, hist, (size_t)H * c->S);
-    dev_free(c, counter, 1);
     return st;
 }
 

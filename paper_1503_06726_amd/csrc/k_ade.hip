@@ -2,9 +2,9 @@
 // species collides with u = 0 (D2Q5 equilibrium w_i phi, Suppl. "Lattice Boltzmann Method")
 // plus its reaction and streams with halfway bounce-back at walls, while the fluid, the
 // membranes and the domain map stay frozen.  The iteration runs in a working set of float or
-// double deviations; each pass also reports the relative change ||phi^k - phi^{k-1}||_2 /
-// ||phi^k||_2 of every species through a deterministic two-level reduction (per-block sums,
-// then the last block to finish adds them in block order).
+// double deviations; each pass also leaves per-block sums of (phi^k - phi^{k-1})^2 and
+// (phi^k)^2, which one kernel per batch of passes turns into the relative changes
+// ||phi^k - phi^{k-1}||_2 / ||phi^k||_2 (fixed-order sums: deterministic).
 #include "lbib_internal.h"
 
 namespace lbib {
@@ -39,7 +39,6 @@ template <typename WT>
 __global__ __launch_bounds__(ADE_THREADS) void k_ade(AdeArgs a)
 {
     __shared__ double sh[4][ADE_THREADS];
-    __shared__ int last;
     const int t = threadIdx.x;
     const int64_t idx = (int64_t)blockIdx.x * ADE_THREADS + t;
     const WT w0 = WT(1) / WT(3), w1 = WT(1) / WT(6);
@@ -80,7 +79,7 @@ __global__ __launch_bounds__(ADE_THREADS) void k_ade(AdeArgs a)
     }
     if (!a.track) return;                                   // uniform: no reduction on the first pass
 
-    // per-block sums (fixed tree), then the last block adds the blocks in order
+    // per-block sums (fixed tree) into the pass's slot; k_ade_hist adds the blocks in order
     for (int q = 0; q < 2; ++q) {
         sh[2 * q][t] = d2[q];
         sh[2 * q + 1][t] = p2[q];
@@ -91,21 +90,19 @@ __global__ __launch_bounds__(ADE_THREADS) void k_ade(AdeArgs a)
             for (int v = 0; v < 4; ++v) sh[v][t] += sh[v][t + w];
         __syncthreads();
     }
-    if (t == 0) {
-        for (int v = 0; v < 2 * a.S; ++v)
-            __hip_atomic_store(&a.partial[(int64_t)blockIdx.x * 4 + v], sh[v][0], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        last = (atomicAdd(a.counter, 1) == (int)gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+    if (t < 4) a.partial[((int64_t)a.hslot * gridDim.x + blockIdx.x) * 4 + t] = sh[t][0];
+}
+
+// relative change of every species for each pass of a batch: one workgroup per pass adds
+// its per-block sums in block order (fixed tree)
+__global__ __launch_bounds__(ADE_THREADS) void k_ade_hist(const double* __restrict__ partial, int nblocks, int S,
+                                                          double* __restrict__ hist)
+{
+    __shared__ double sh[4][ADE_THREADS];
+    const int t = threadIdx.x, slot = blockIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = t; b < (int)gridDim.x; b += ADE_THREADS)
-        for (int v = 0; v < 2 * a.S; ++v)
-            acc[v] += __hip_atomic_load(&a.partial[(int64_t)b * 4 + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
+    for (int b = t; b < nblocks; b += ADE_THREADS)
+        for (int v = 0; v < 4; ++v) acc[v] += partial[((int64_t)slot * nblocks + b) * 4 + v];
     for (int v = 0; v < 4; ++v) sh[v][t] = acc[v];
     __syncthreads();
     for (int w = ADE_THREADS / 2; w > 0; w >>= 1) {
@@ -113,13 +110,11 @@ __global__ __launch_bounds__(ADE_THREADS) void k_ade(AdeArgs a)
             for (int v = 0; v < 4; ++v) sh[v][t] += sh[v][t + w];
         __syncthreads();
     }
-    if (t == 0) {
-        for (int s = 0; s < a.S; ++s) {
+    if (t == 0)
+        for (int s = 0; s < S; ++s) {
             const double dd = sh[2 * s][0], pp = sh[2 * s + 1][0];
-            a.hist[(int64_t)a.hslot * a.S + s] = (dd == 0.0) ? 0.0 : sqrt(dd) / sqrt(pp);
+            hist[(int64_t)slot * S + s] = (dd == 0.0) ? 0.0 : sqrt(dd) / sqrt(pp);
         }
-        *a.counter = 0;
-    }
 }
 
 // working set <- the context's populations (storage ST), and back
@@ -188,5 +183,11 @@ hipError_t launch_ade_copy(lbib_ctx* c, void* work, bool fp64, bool to_work)
 }
 
 unsigned ade_blocks(int64_t nn) { return (unsigned)((nn + ADE_THREADS - 1) / ADE_THREADS); }
+
+hipError_t launch_ade_hist(const double* partial, int nblocks, int S, double* hist, int slots, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_ade_hist, dim3((unsigned)slots), dim3(ADE_THREADS), 0, stream, partial, nblocks, S, hist);
+    return hipGetLastError();
+}
 
 }  // namespace lbib

@@ -120,9 +120,7 @@ struct AdeArgs {
     double* __restrict__ phi_prev;     // [S][ny][nx] phi of the previous pass
     const unsigned* __restrict__ inside;   // source bits (source/decay law)
     int wpr;
-    double* __restrict__ partial;      // [nblocks][2 S] per-block sums
-    int* __restrict__ counter;         // blocks finished (the last one resets it)
-    double* __restrict__ hist;         // [slots][S] relative change per pass
+    double* __restrict__ partial;      // [slots][nblocks][4] per-block sums of each pass
     int64_t nn;
     int nx, ny, walls, S;
     double omega_s[2], phi_ref[2];

@@ -107,5 +107,6 @@ hipError_t launch_fill_f32(lbib_ctx* c, float* p, int64_t n);
 hipError_t launch_ade(lbib_ctx* c, const AdeArgs& a, bool fp64, hipStream_t stream);
 hipError_t launch_ade_copy(lbib_ctx* c, void* work, bool fp64, bool to_work);
 unsigned ade_blocks(int64_t nn);
+hipError_t launch_ade_hist(const double* partial, int nblocks, int S, double* hist, int slots, hipStream_t stream);
 
 }  // namespace lbib
