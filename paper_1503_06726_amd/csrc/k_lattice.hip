@@ -131,14 +131,20 @@ __device__ inline void load_candidates(const LatticeArgs& a, int k0, int end, in
 // spread each node's force into the LDS accumulators (Eq. forcedistribution), and, when
 // INTERP, add the node's share of the interpolated velocity from the tile's u (LDS) to its
 // fixed-point accumulator (Eq. conversion2; each tile contributes its own stencil points).
-template <bool INTERP>
+//
+// DEFER keeps each node's velocity share in Ud, and its node index in Un (-1 when the
+// stencil misses the tile), for the caller to add after the tile's stores: a workgroup
+// barrier waits for every outstanding global memory operation, atomics included, and the
+// share is not needed before the end.
+template <bool INTERP, bool DEFER = false>
 __device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0, int y1,
                                     const int ij[SPREAD_UNROLL], const float4 rc[SPREAD_UNROLL],
                                     const int nd[SPREAD_UNROLL], unsigned long long* accx, unsigned long long* accy,
-                                    const float* uxs, const float* uys)
+                                    const float* uxs, const float* uys, float2* Ud = nullptr, int* Un = nullptr)
 {
 #pragma unroll
     for (int u = 0; u < SPREAD_UNROLL; ++u) {
+        if constexpr (DEFER) Un[u] = -1;
         const int i0 = ij[u] & 0xFFFF;
         const int j0 = ij[u] >> 16;                      // sign-extended 16-bit row
         // tile coordinates of the four stencil columns and rows (each wrapped on its own,
@@ -185,7 +191,10 @@ __device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0
                 Uy += wy[bb] * sy;
             }
         }
-        if constexpr (INTERP) {
+        if constexpr (INTERP && DEFER) {
+            Ud[u] = make_float2(Ux, Uy);
+            Un[u] = nd[u];
+        } else if constexpr (INTERP) {
             atomicAdd(&a.U_acc[2 * (int64_t)nd[u]], to_ufixed(Ux));
             atomicAdd(&a.U_acc[2 * (int64_t)nd[u] + 1], to_ufixed(Uy));
         }
@@ -217,6 +226,8 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
     int lbeg = 0, lend = 0;
     int cij[SPREAD_UNROLL], cnd[SPREAD_UNROLL];
     float4 crc[SPREAD_UNROLL];
+    float2 Ud[SPREAD_UNROLL];
+    int Un[SPREAD_UNROLL];
     if constexpr (NODES) {
         lbeg = a.t_off[tile];
         lend = a.t_off[tile + 1];
@@ -244,7 +255,14 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
 #pragma unroll
             for (int s = 0; s < S; ++s)
                 pull5<ST>((const typename Pop<ST>::T*)a.gsrc + (int64_t)5 * s * nn, nn, x, n[r], g[r][s]);
-            if constexpr (MASK) m[r] = (a.inside[(int64_t)y * a.wpr + (x >> 5)] >> (x & 31)) & 1u;
+            if constexpr (MASK) {
+                // the row's two bit words are the same for the whole wavefront: scalar loads
+                const int wy = __builtin_amdgcn_readfirstlane(y);
+                const unsigned* row = a.inside + (int64_t)wy * a.wpr + (x0 >> 5);
+                const unsigned w0 = row[0];
+                const unsigned w1 = (x0 + 32 < a.nx) ? row[1] : 0u;
+                m[r] = (((x & 32) ? w1 : w0) >> (x & 31)) & 1u;
+            }
         }
     }
 
@@ -268,7 +286,7 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
 
     if constexpr (NODES) {
         __syncthreads();
-        couple_chunk<true>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, uxs, uys);
+        couple_chunk<true, true>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, uxs, uys, Ud, Un);
         for (int k0 = lbeg + SPREAD_UNROLL * TILE_N; k0 < lend; k0 += SPREAD_UNROLL * TILE_N) {
             load_candidates(a, k0, lend, cij, crc, cnd);
             couple_chunk<true>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, uxs, uys);
@@ -343,6 +361,16 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
                 d[3 * nn] = Pop<ST>::st(os1 * gg[3] + os * Q1 * (dphi[s] - p3 * ux) + Q1 * R[s], SC5[3]);
                 d[4 * nn] = Pop<ST>::st(os1 * gg[4] + os * Q1 * (dphi[s] - p3 * uy) + Q1 * R[s], SC5[4]);
             }
+        }
+    }
+
+    // the first chunk's velocity shares, deferred past the barrier
+    if constexpr (NODES) {
+#pragma unroll
+        for (int u = 0; u < SPREAD_UNROLL; ++u) {
+            if (Un[u] < 0) continue;                          // the stencil missed the tile
+            atomicAdd(&a.U_acc[2 * (int64_t)Un[u]], to_ufixed(Ud[u].x));
+            atomicAdd(&a.U_acc[2 * (int64_t)Un[u] + 1], to_ufixed(Ud[u].y));
         }
     }
 }
