@@ -112,7 +112,7 @@ lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out);
 /* Set the membranes (Section "Cell Representation": closed CCW polygons, the cell's ID is
  * c+1 for the c-th polygon, 0 is the extracellular space).
  *   offsets   [n_cells+1] host int32, CSR as above; 0 <= n_cells <= 65535;
- *             3 .. 4096 nodes per cell
+ *             3 .. 4096 nodes per cell, at most 2e8 nodes in total
  *   xy        [N][2] host doubles, N = offsets[n_cells]; finite, |coordinate| < 2^20
  *   rest_len  [N] host doubles (edge k's rest length) or NULL for the initial edge lengths
  *   rest_area [n_cells] host doubles or NULL for the initial areas

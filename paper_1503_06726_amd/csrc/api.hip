@@ -138,7 +138,8 @@ LatticeArgs lattice_args(lbib_ctx* c)
     a.t_list = c->d_list;
     a.rec = c->d_rec;
     a.rec_ij = c->d_rec_ij;
-    a.U_acc = c->d_U;
+    a.part = c->d_part;
+    a.n_nodes = c->n_nodes;
     a.inside = c->inside[c->cur];
     a.inside_clr = c->inside[1 - c->cur];
     a.wpr = c->wpr;
@@ -155,7 +156,9 @@ MembraneArgs membrane_args(lbib_ctx* c, int advect)
     a.l0 = c->d_l0;
     a.A0 = c->d_A0;
     a.area = c->d_area;
-    a.U_acc = c->d_U;
+    a.part = c->d_part;
+    a.cnt = c->d_cnt;
+    a.n_nodes = c->n_nodes;
     a.ij_list = c->d_ijlist;
     a.rec = c->d_rec;
     a.rec_ij = c->d_rec_ij;
@@ -186,6 +189,7 @@ ListArgs list_args(lbib_ctx* c)
     a.off = c->d_t_off;
     a.cursor = c->d_t_cur;
     a.list = c->d_list;
+    a.cnt = c->d_cnt;
     a.n = c->n_nodes;
     a.nx = c->p.nx;
     a.ny = c->p.ny;
@@ -275,7 +279,8 @@ void free_nodes(lbib_ctx* c)
     dev_free(c, c->d_A0, C);
     dev_free(c, c->d_area, C);
     dev_free(c, c->d_ijlist, N);
-    dev_free(c, c->d_U, 2 * N);
+    dev_free(c, c->d_part, N * MAX_NODE_TILES);
+    dev_free(c, c->d_cnt, N);
     dev_free(c, c->d_rec, N);
     dev_free(c, c->d_rec_ij, N);
     dev_free(c, c->d_list, N * MAX_NODE_TILES);
@@ -555,7 +560,8 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_A0, C);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_area, C);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_ijlist, N);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_U, 2 * N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_part, N * MAX_NODE_TILES);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_cnt, N);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_rec, N);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_rec_ij, N);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_list, N * MAX_NODE_TILES);
@@ -573,7 +579,6 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
     LBIB_HIP(c, hipMemcpyAsync(c->d_A0, A0.data(), C * sizeof(double), hipMemcpyHostToDevice, c->stream));
     LBIB_LAUNCH(c, launch_fill_i32(c, c->d_t_count, c->nltiles, 0));
     LBIB_LAUNCH(c, launch_fill_i32(c, c->d_err, 1, 0));
-    LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->d_U, 4 * (int64_t)N, 0));
     if (c->mask_needed)
         for (int b = 0; b < 2; ++b) LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->inside[b], c->ny_words(), 0));
     LBIB_TRY(build_lists(c));

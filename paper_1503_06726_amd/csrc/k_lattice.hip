@@ -6,9 +6,9 @@
 //      bounce-back at walls) and take rho and u = sum f v / rho (u staged in LDS);
 //   2. for every membrane node in the tile's list: spread its force over the stencil points
 //      inside the tile (Eq. forcedistribution with the kernel of Eq. 1Dkernel), summed in LDS
-//      in 64-bit fixed point so the result does not depend on node order, and add the tile's
-//      share of the interpolated velocity (Eq. conversion2) to the node's fixed-point
-//      accumulator;
+//      in 64-bit fixed point so the result does not depend on node order, and store the
+//      tile's share of the node's interpolated velocity (Eq. conversion2) in the node's slot
+//      for this tile;
 //   3. collide with the BGK operator and the body-force term w_i rho (v_i . e) / cs2, store;
 //   4. per species: pull the D2Q5 populations, take phi, add the reaction, collide towards
 //      phi w_i (1 + v_i . u / cs2) with the fluid's u, store; the source term reads the
@@ -102,49 +102,49 @@ __device__ inline unsigned long long to_fixed(float v)
 
 constexpr int SPREAD_UNROLL = 1;   // listed nodes per thread whose loads are issued together
 
-__device__ inline unsigned long long to_ufixed(float v)
-{
-    v = fminf(fmaxf(v, -UFIX_CLAMP), UFIX_CLAMP);
-    return (unsigned long long)__float2ll_rn(v * UFIX_SCALE);
-}
-
-// Load one chunk of the tile's listed nodes [beg, end): node index, stencil origin, record.
+// Load one chunk of the tile's listed nodes [beg, end): list entry (node << 4 | rank of this
+// tile among the node's tiles; -1, which names no node, past the end), stencil origin, record.
 __device__ inline void load_candidates(const LatticeArgs& a, int k0, int end, int ij[SPREAD_UNROLL],
-                                       float4 rc[SPREAD_UNROLL], int nd[SPREAD_UNROLL])
+                                       float4 rc[SPREAD_UNROLL], int ent[SPREAD_UNROLL])
 {
     const int t = threadIdx.x;
 #pragma unroll
     for (int u = 0; u < SPREAD_UNROLL; ++u) {
         const int k = k0 + u * TILE_N + t;
         ij[u] = 0x7FFF7FFF;                              // far away: never hits
-        nd[u] = 0;
+        ent[u] = -1;
         if (k < end) {
-            const int node = a.t_list[k];
-            nd[u] = node;
+            const int e = a.t_list[k];
+            const int node = (int)((unsigned)e >> 4);
+            ent[u] = e;
             ij[u] = a.rec_ij[node];
             rc[u] = a.rec[node];
         }
     }
 }
 
+// slot of a list entry's velocity share: [rank of the tile][node]
+__device__ inline int64_t share_slot(const LatticeArgs& a, int e)
+{
+    return (int64_t)(e & 15) * a.n_nodes + (int64_t)((unsigned)e >> 4);
+}
+
 // Couple one chunk of listed nodes with the tile [x0, x1) x [y0, y1) (LDS rows TILE_X apart):
 // spread each node's force into the LDS accumulators (Eq. forcedistribution), and, when
-// INTERP, add the node's share of the interpolated velocity from the tile's u (LDS) to its
-// fixed-point accumulator (Eq. conversion2; each tile contributes its own stencil points).
-//
-// DEFER keeps each node's velocity share in Ud, and its node index in Un (-1 when the
-// stencil misses the tile), for the caller to add after the tile's stores: a workgroup
-// barrier waits for every outstanding global memory operation, atomics included, and the
-// share is not needed before the end.
+// INTERP, compute the node's share of the interpolated velocity from the tile's u (LDS) over
+// the tile's own stencil points (Eq. conversion2) into Ud (zero when the stencil misses).
+// The caller stores the shares by node and tile rank; DEFER leaves that to after the tile's
+// population stores, because a workgroup barrier waits for every outstanding global memory
+// operation and the shares are not needed before the end.
 template <bool INTERP, bool DEFER = false>
 __device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0, int y1,
                                     const int ij[SPREAD_UNROLL], const float4 rc[SPREAD_UNROLL],
-                                    const int nd[SPREAD_UNROLL], unsigned long long* accx, unsigned long long* accy,
-                                    const float* uxs, const float* uys, float2* Ud = nullptr, int* Un = nullptr)
+                                    const int ent[SPREAD_UNROLL], unsigned long long* accx, unsigned long long* accy,
+                                    const float* uxs, const float* uys, float2* Ud = nullptr)
 {
 #pragma unroll
     for (int u = 0; u < SPREAD_UNROLL; ++u) {
-        if constexpr (DEFER) Un[u] = -1;
+        if constexpr (INTERP) Ud[u] = make_float2(0.0f, 0.0f);
         const int i0 = ij[u] & 0xFFFF;
         const int j0 = ij[u] >> 16;                      // sign-extended 16-bit row
         // tile coordinates of the four stencil columns and rows (each wrapped on its own,
@@ -191,13 +191,12 @@ __device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0
                 Uy += wy[bb] * sy;
             }
         }
-        if constexpr (INTERP && DEFER) {
-            Ud[u] = make_float2(Ux, Uy);
-            Un[u] = nd[u];
-        } else if constexpr (INTERP) {
-            atomicAdd(&a.U_acc[2 * (int64_t)nd[u]], to_ufixed(Ux));
-            atomicAdd(&a.U_acc[2 * (int64_t)nd[u] + 1], to_ufixed(Uy));
-        }
+        if constexpr (INTERP) Ud[u] = make_float2(Ux, Uy);
+    }
+    if constexpr (INTERP && !DEFER) {
+#pragma unroll
+        for (int u = 0; u < SPREAD_UNROLL; ++u)
+            if (ent[u] != -1) a.part[share_slot(a, ent[u])] = Ud[u];
     }
 }
 
@@ -227,7 +226,6 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
     int cij[SPREAD_UNROLL], cnd[SPREAD_UNROLL];
     float4 crc[SPREAD_UNROLL];
     float2 Ud[SPREAD_UNROLL];
-    int Un[SPREAD_UNROLL];
     if constexpr (NODES) {
         lbeg = a.t_off[tile];
         lend = a.t_off[tile + 1];
@@ -286,10 +284,18 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
 
     if constexpr (NODES) {
         __syncthreads();
-        couple_chunk<true, true>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, uxs, uys, Ud, Un);
-        for (int k0 = lbeg + SPREAD_UNROLL * TILE_N; k0 < lend; k0 += SPREAD_UNROLL * TILE_N) {
-            load_candidates(a, k0, lend, cij, crc, cnd);
-            couple_chunk<true>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, uxs, uys);
+        couple_chunk<true, true>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, uxs, uys, Ud);
+        if (lend - lbeg > SPREAD_UNROLL * TILE_N) {
+            int ent0[SPREAD_UNROLL];                      // the first chunk's entries, stored last
+#pragma unroll
+            for (int u = 0; u < SPREAD_UNROLL; ++u) ent0[u] = cnd[u];
+            float2 Ux[SPREAD_UNROLL];
+            for (int k0 = lbeg + SPREAD_UNROLL * TILE_N; k0 < lend; k0 += SPREAD_UNROLL * TILE_N) {
+                load_candidates(a, k0, lend, cij, crc, cnd);
+                couple_chunk<true>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, uxs, uys, Ux);
+            }
+#pragma unroll
+            for (int u = 0; u < SPREAD_UNROLL; ++u) cnd[u] = ent0[u];
         }
         __syncthreads();
     }
@@ -367,11 +373,8 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
     // the first chunk's velocity shares, deferred past the barrier
     if constexpr (NODES) {
 #pragma unroll
-        for (int u = 0; u < SPREAD_UNROLL; ++u) {
-            if (Un[u] < 0) continue;                          // the stencil missed the tile
-            atomicAdd(&a.U_acc[2 * (int64_t)Un[u]], to_ufixed(Ud[u].x));
-            atomicAdd(&a.U_acc[2 * (int64_t)Un[u] + 1], to_ufixed(Ud[u].y));
-        }
+        for (int u = 0; u < SPREAD_UNROLL; ++u)
+            if (cnd[u] != -1) a.part[share_slot(a, cnd[u])] = Ud[u];
     }
 }
 

@@ -1,8 +1,10 @@
 // Membrane kernels of the coupled step (gfx950).
 //
 // k_membrane: one workgroup per cell.  In a time step it
-//   1. interpolates u^n to each node over the 4x4 stencil (Eq. conversion2 with the kernel
-//      of Eq. 1Dkernel) and moves the node explicitly, X^{n+1} = X^n + U (positions in FP64);
+//   1. adds the node's interpolated velocity U (Eq. conversion2 with the kernel of
+//      Eq. 1Dkernel; the lattice pass leaves one share per listed tile, added here in the
+//      order of the node's tiles) and moves the node explicitly, X^{n+1} = X^n + U
+//      (positions in FP64);
 //   2. stages the cell's new positions in LDS and reduces the polygon area (shoelace, FP64,
 //      fixed-order wave and LDS reduction);
 //   3. evaluates the nodal forces in the paper's per-node form: constant tension
@@ -100,20 +102,35 @@ __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
     if (a.raster)
         for (int i = t; i < RASTER_WORDS_FUSED; i += MEMBRANE_THREADS) bm[i] = 0u;
 
-    // 1. move: X^{n+1} = X^n + U, U interpolated by the lattice pass (fixed point, cleared
-    //    here); stage the new positions in LDS and track their bounding box
+    // 1. move: X^{n+1} = X^n + U, U interpolated by the lattice pass as one share per listed
+    //    tile, added in the order of the node's tiles; stage the new positions in LDS and
+    //    track their bounding box
     double bb[4] = {INFINITY, INFINITY, INFINITY, INFINITY};     // min x, min y, -max x, -max y
     for (int k = t; k < n; k += MEMBRANE_THREADS) {
-        double2 X = a.X[beg + k];
+        const int64_t l = beg + k;
+        double2 X = a.X[l];
         if (a.advect) {
-            const unsigned long long ux = a.U_acc[2 * (int64_t)(beg + k)];
-            const unsigned long long uy = a.U_acc[2 * (int64_t)(beg + k) + 1];
-            a.U_acc[2 * (int64_t)(beg + k)] = 0ull;
-            a.U_acc[2 * (int64_t)(beg + k) + 1] = 0ull;
+            // the first two shares are read alongside the count (most nodes have two)
+            const int nt = a.cnt[l];
+            const float2 s0 = a.part[l], s1 = a.part[a.n_nodes + l];
+            double ux = 0.0, uy = 0.0;
+            if (nt > 0) {
+                ux += (double)s0.x;
+                uy += (double)s0.y;
+            }
+            if (nt > 1) {
+                ux += (double)s1.x;
+                uy += (double)s1.y;
+            }
+            for (int q = 2; q < nt; ++q) {
+                const float2 s = a.part[q * a.n_nodes + l];
+                ux += (double)s.x;
+                uy += (double)s.y;
+            }
             if (finite2(X.x, X.y)) {
-                X.x += (double)(long long)ux * UFIX_INV;
-                X.y += (double)(long long)uy * UFIX_INV;
-                a.X[beg + k] = X;
+                X.x += ux;
+                X.y += uy;
+                a.X[l] = X;
             }
         }
         xs[k] = X;
@@ -342,8 +359,9 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_list_scan(ListArgs a)
     if (t == 0) a.off[a.ntiles] = carry_sh;
 }
 
-// every node enters the lists of its tiles (order within a list is immaterial: the lattice
-// pass sums in fixed point)
+// every node enters the lists of its tiles, each entry naming the node and the rank of the
+// tile among the node's tiles (order within a list is immaterial: the lattice pass sums
+// forces in fixed point, and each velocity share goes to its own [rank][node] slot)
 __global__ void k_list_fill(ListArgs a)
 {
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -357,11 +375,12 @@ __global__ void k_list_fill(ListArgs a)
             nt = node_tiles(ij & 0xFFFF, ij >> 16, a, tiles);
         }
     }
+    if (live) a.cnt[l] = (uint8_t)nt;
     for (int k = 0; k < MAX_NODE_TILES; ++k) {
         const bool on = live && k < nt;
         if (!__ballot(on)) break;
         const int p = wave_claim<true>(a.cursor, on ? tiles[k] : 0, on);
-        if (on) a.list[p] = (int)l;
+        if (on) a.list[p] = (int)(((unsigned)l << 4) | (unsigned)k);
     }
 }
 

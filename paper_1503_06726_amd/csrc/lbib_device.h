@@ -10,7 +10,9 @@
 // steps (LIST_PERIOD) each node enters the list of every tile that its 4x4 stencil can reach
 // while its stencil origin (floor(X) - 1) stays within LIST_MARGIN lattice units of the origin
 // it had then.  The membrane kernel refreshes each node's spreading record at the node's own
-// index every step and flags a node that drifted further.
+// index every step and flags a node that drifted further.  Each list entry also receives,
+// every step, the tile's share of its node's interpolated velocity; the membrane kernel adds
+// a node's shares in the order of its tiles.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -44,11 +46,6 @@ constexpr int SCAN_PER_THREAD = 8;
 constexpr float FIX_SCALE = 281474976710656.0f;          // 2^48
 constexpr float FIX_INV = 1.0f / 281474976710656.0f;     // 2^-48 (exact)
 constexpr float FIX_CLAMP = 16384.0f;                    // |contribution| bound, keeps sums in range
-// Interpolated node velocities are summed over lattice tiles in 64-bit fixed point too:
-// value = integer * 2^-44 (|U| stays far below the 2^19 range).
-constexpr float UFIX_SCALE = 17592186044416.0f;          // 2^44
-constexpr double UFIX_INV = 1.0 / 17592186044416.0;      // 2^-44 (exact)
-constexpr float UFIX_CLAMP = 4096.0f;
 
 // error flags (device int, OR-ed)
 constexpr int ERR_NONFINITE = 1;     // a node position or force became non-finite
@@ -69,10 +66,11 @@ struct LatticeArgs {
     int kernel;
     // immersed boundary: node lists per lattice tile, spreading records per node
     const int* __restrict__ t_off;     // [ntiles + 1] list offsets (NULL: no nodes)
-    const int* __restrict__ t_list;    // node indices
+    const int* __restrict__ t_list;    // entries: node index << 4 | the tile's rank among the node's tiles
     const float4* __restrict__ rec;    // [N] (sx, sy, Fx, Fy): fractional offset and force
     const int* __restrict__ rec_ij;    // [N] packed stencil origin (i0 | j0 << 16)
-    unsigned long long* __restrict__ U_acc;   // [N][2] interpolated velocity, fixed point
+    float2* __restrict__ part;         // [MAX_NODE_TILES][N] share of the node's velocity per tile
+    int64_t n_nodes;
     const unsigned* __restrict__ inside;   // inside-any-cell bits of this step, rows of wpr words
     unsigned* __restrict__ inside_clr;     // the other buffer, cleared for the membrane kernel
     int wpr;
@@ -86,7 +84,9 @@ struct MembraneArgs {
     const double* __restrict__ l0;
     const double* __restrict__ A0;
     double* __restrict__ area;
-    unsigned long long* __restrict__ U_acc;   // [N][2] interpolated velocity, read and cleared
+    const float2* __restrict__ part;   // [MAX_NODE_TILES][N] velocity shares (from the lattice pass)
+    const uint8_t* __restrict__ cnt;   // [N] number of tiles each node is listed in
+    int64_t n_nodes;
     const int* __restrict__ ij_list;   // packed stencil origin of each node at the last list build
     float4* __restrict__ rec;          // [N]
     int* __restrict__ rec_ij;          // [N]
@@ -107,7 +107,8 @@ struct ListArgs {
     int* __restrict__ count;           // [ntiles], zero between builds (the scan clears it)
     int* __restrict__ off;             // [ntiles + 1]
     int* __restrict__ cursor;          // [ntiles] fill positions
-    int* __restrict__ list;            // [N * MAX_NODE_TILES] capacity
+    int* __restrict__ list;            // [N * MAX_NODE_TILES] capacity: node << 4 | rank of the tile
+    uint8_t* __restrict__ cnt;         // [N] tiles the node is listed in
     int64_t n;
     int nx, ny, walls, ntx, nlty, ntiles;
 };

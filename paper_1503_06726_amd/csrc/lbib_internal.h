@@ -55,7 +55,8 @@ struct lbib_ctx {
     double* d_A0 = nullptr;
     double* d_area = nullptr;
     int* d_ijlist = nullptr;         // stencil origin of each node at the last list build
-    unsigned long long* d_U = nullptr;   // [N][2] interpolated velocities, fixed point
+    float2* d_part = nullptr;        // [MAX_NODE_TILES][N] velocity shares by tile rank and node
+    uint8_t* d_cnt = nullptr;        // [N] tiles each node is listed in
     float4* d_rec = nullptr;         // [N] spreading records (fractional offset, force)
     int* d_rec_ij = nullptr;         // [N] current stencil origins
     int* d_list = nullptr;           // [N * MAX_NODE_TILES] per-tile node lists

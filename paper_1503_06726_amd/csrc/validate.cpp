@@ -69,6 +69,7 @@ lbib_status check_cells(const lbib_params* p, int32_t n_cells, const int32_t* of
         if (n > 4096) return fail(msg, "cell %g has %g nodes (limit 4096)", c, (double)n);
     }
     const long long N = off[n_cells];
+    if (N > 200000000LL) return fail(msg, "%g nodes in total (limit 2e8)", (double)N);
     for (long long i = 0; i < 2 * N; ++i)
         if (!std::isfinite(xy[i]) || std::fabs(xy[i]) >= 1048576.0)
             return fail(msg, "node coordinate %g not finite or beyond 2^20", (double)(i / 2));
