@@ -275,6 +275,33 @@ def test_reduced_precision_storage(storage, bound, case):
             assert errs[k] < bound, (k, errs[k])
 
 
+# per-field error of reduced-precision storage at the bench workload (2048^2, 2000 cells),
+# against the FP64 oracle, next to the FP32 path on the same steps
+@pytest.mark.parametrize("storage,bound", [(lbib.STORAGE_FP32, 1e-5), (lbib.STORAGE_FP16, 1e-2),
+                                           (lbib.STORAGE_BF16, 1e-1)])
+def test_precision_per_field_at_large(storage, bound, large_oracle_fields):
+    w, R, steps = large_oracle_fields
+    say(f"large workload, storage {storage}, {steps} steps")
+    g = lbib.from_workload(w, storage=storage)
+    g.step(steps)
+    G = g.get_fields(mask=False)
+    g.close()
+    errs = {"rho": rel(G["rho"], R["rho"]), "u": rel(G["u"], R["u"]), "phi": rel(G["phi"], R["phi"]),
+            "X": rel(G["xy"], R["xy"]), "disp": rel(G["xy"] - w.xy, R["xy"] - w.xy)}
+    say("  rel-L2:", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k in ("rho", "u", "X", "phi"):
+        assert errs[k] < bound, (k, errs[k])
+
+
+@pytest.fixture(scope="module")
+def large_oracle_fields():
+    w = W.large()
+    steps = 4
+    o = O.from_workload(w)
+    o.step(steps)
+    return w, o.get_fields(), steps
+
+
 # ------------------------------------------------------------------------------------------
 # captured step graphs: whole 16-step periods replay a graph; single steps launch directly.
 # Every replay (with eager work and synchronisation in between) must match direct launches
