@@ -173,6 +173,25 @@ lbib_status lbib_set_source_cells(lbib_ctx* ctx, const uint8_t* src);
 lbib_status lbib_ade_steady(lbib_ctx* ctx, double tol, int64_t max_iters, int32_t fp64, int64_t* iters,
                             double* change);
 
+/* Batched ADE-only steady states (no context): `batch` independent single-species problems on
+ * one nx x ny lattice (x periodic, y per bc_y), each iterated as in lbib_ade_steady with the
+ * source/decay law R = sigma[b] m_b(x) - decay[b] phi and relaxation tau_D = 3 D[b] + 1/2.
+ *   source   [batch][ny][nx] host bytes, m_b(x) = 1 where nonzero (inside a source cell)
+ *   phi      [batch][ny][nx] host doubles: the start (equilibrium populations w_i phi),
+ *            ignored when zero_start != 0; on return the final concentrations
+ *   iters    [batch] out: the first k with ||phi^k - phi^{k-1}||_2 <= tol ||phi^k||_2, 0 when
+ *            max_iters passed first
+ *   fp64     1 iterates in FP64, 0 in FP32;  hip_stream as in lbib_create (NULL: private)
+ * All problems advance together in captured batches of 64 iterations; a converged problem
+ * stops after the batch in which it converged, so its returned field may be up to 63
+ * iterations past its k.  Device memory is allocated for the call and freed before it
+ * returns.  LBIB_EINVAL for bad sizes or parameters, LBIB_ENUMERIC if a change became
+ * non-finite (the other problems still finish).  Synchronises. */
+lbib_status lbib_ade_batch(int32_t nx, int32_t ny, int32_t bc_y, int32_t batch, const uint8_t* source,
+                           const double* D, const double* sigma, const double* decay, double* phi,
+                           int32_t zero_start, double tol, int64_t max_iters, int32_t fp64, int64_t* iters,
+                           void* hip_stream);
+
 /* Global sums over the lattice in FP64, deterministic:
  *   out[0] = sum rho, out[1] = sum rho ux, out[2] = sum rho uy, out[3+s] = sum phi_s.
  * out has 3 + n_species doubles.  Returns LBIB_ENUMERIC if any sum is not finite. */

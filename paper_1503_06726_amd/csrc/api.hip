@@ -878,6 +878,162 @@ out:
     return st;
 }
 
+lbib_status lbib_ade_batch(int32_t nx, int32_t ny, int32_t bc_y, int32_t batch, const uint8_t* source,
+                           const double* D, const double* sigma, const double* decay, double* phi, int32_t zero_start,
+                           double tol, int64_t max_iters, int32_t fp64, int64_t* iters, void* hip_stream)
+{
+    if (nx < 4 || nx > 32767 || ny < 4 || ny > 32767 || (bc_y != LBIB_PERIODIC && bc_y != LBIB_WALLS) || batch < 1 ||
+        batch > 65535 || !source || !D || !sigma || !decay || !phi || !iters || !std::isfinite(tol) || tol < 0.0 ||
+        max_iters < 0)
+        return LBIB_EINVAL;
+    for (int b = 0; b < batch; ++b)
+        if (!std::isfinite(D[b]) || !(D[b] > 0.0) || !std::isfinite(sigma[b]) || !std::isfinite(decay[b]))
+            return LBIB_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return LBIB_EDEVICE;
+    for (int b = 0; b < batch; ++b) iters[b] = 0;
+
+    constexpr int H = ADE_BATCH_SLOTS;
+    const int64_t nn = (int64_t)nx * ny;
+    const bool dbl = fp64 != 0;
+    const size_t wbytes = dbl ? sizeof(double) : sizeof(float);
+    const int nblocks = (int)ade_blocks(nn);
+    hipStream_t st = (hipStream_t)hip_stream, cap = nullptr;
+    bool own = false;
+    lbib_status res = LBIB_OK;
+    char *work[2] = {nullptr, nullptr}, *src = nullptr;
+    double *phi_prev = nullptr, *partial = nullptr, *hist = nullptr, *prm = nullptr, *dphi = nullptr;
+    int* active = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<double> hh((size_t)H * batch), p((size_t)3 * batch);
+    std::vector<int> act((size_t)batch, 1);
+    AdeBatchArgs a;
+    std::memset(&a, 0, sizeof a);
+    int64_t done = 0, left = batch;
+    int wc = 0;
+    auto fail = [&](lbib_status s) { res = s; };
+#define ADE_B_HIP(call)                                                               \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            fail(e_ == hipErrorOutOfMemory ? LBIB_ENOMEM : LBIB_EDEVICE);             \
+            goto out;                                                                 \
+        }                                                                             \
+    } while (0)
+    if (!st) {
+        ADE_B_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        own = true;
+    }
+    ADE_B_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    for (int b = 0; b < 2; ++b) ADE_B_HIP(hipMalloc((void**)&work[b], (size_t)5 * batch * nn * wbytes));
+    ADE_B_HIP(hipMalloc((void**)&src, (size_t)batch * nn));
+    ADE_B_HIP(hipMalloc((void**)&phi_prev, (size_t)batch * nn * sizeof(double)));
+    ADE_B_HIP(hipMalloc((void**)&dphi, (size_t)batch * nn * sizeof(double)));
+    ADE_B_HIP(hipMalloc((void**)&partial, (size_t)H * batch * nblocks * 2 * sizeof(double)));
+    ADE_B_HIP(hipMalloc((void**)&hist, (size_t)H * batch * sizeof(double)));
+    ADE_B_HIP(hipMalloc((void**)&prm, (size_t)3 * batch * sizeof(double)));
+    ADE_B_HIP(hipMalloc((void**)&active, (size_t)batch * sizeof(int)));
+    for (int b = 0; b < batch; ++b) {
+        p[b] = 1.0 / (3.0 * D[b] + 0.5);
+        p[batch + b] = sigma[b];
+        p[2 * batch + b] = decay[b];
+    }
+    ADE_B_HIP(hipMemcpyAsync(src, source, (size_t)batch * nn, hipMemcpyHostToDevice, st));
+    ADE_B_HIP(hipMemcpyAsync(prm, p.data(), p.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    ADE_B_HIP(hipMemcpyAsync(active, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    if (!zero_start)
+        ADE_B_HIP(hipMemcpyAsync(dphi, phi, (size_t)batch * nn * sizeof(double), hipMemcpyHostToDevice, st));
+    ADE_B_HIP(ade_batch_init_launch(zero_start ? nullptr : dphi, work[0], nn, nx, ny, bc_y == LBIB_WALLS, batch, dbl, st));
+
+    a.phi_prev = phi_prev;
+    a.source = (const uint8_t*)src;
+    a.omega = prm;
+    a.sigma = prm + batch;
+    a.decay = prm + 2 * batch;
+    a.active = active;
+    a.partial = partial;
+    a.nn = nn;
+    a.nx = nx;
+    a.ny = ny;
+    a.walls = bc_y == LBIB_WALLS;
+    a.B = batch;
+    a.nblocks = nblocks;
+    // first pass: phi^0 into phi_prev, the state advances to iteration 1
+    a.src = work[0];
+    a.dst = work[1];
+    a.track = 0;
+    ADE_B_HIP(ade_batch_launch(a, dbl, st));
+    wc = 1;
+    ADE_B_HIP(hipStreamSynchronize(st));
+    ADE_B_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    {
+        bool ok = true;
+        for (int i = 0; i < H && ok; ++i) {
+            a.src = work[(wc + i) & 1];
+            a.dst = work[(wc + i + 1) & 1];
+            a.track = 1;
+            a.hslot = i;
+            ok = ade_batch_launch(a, dbl, cap) == hipSuccess;
+        }
+        if (ok) ok = ade_batch_hist_launch(a, hist, cap) == hipSuccess;
+        const bool ended = hipStreamEndCapture(cap, &graph) == hipSuccess;
+        if (!ok || !ended || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            fail(LBIB_EDEVICE);
+            goto out;
+        }
+    }
+    while (done < max_iters && left > 0) {
+        ADE_B_HIP(hipGraphLaunch(exec, st));
+        ADE_B_HIP(hipMemcpyAsync(hh.data(), hist, hh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        ADE_B_HIP(hipStreamSynchronize(st));
+        bool changed = false;
+        for (int b = 0; b < batch; ++b) {
+            if (!act[b]) continue;
+            for (int i = 0; i < H; ++i) {
+                const int64_t k = done + 1 + i;             // the pass computed phi^k
+                if (k > max_iters) break;
+                const double ch = hh[(size_t)i * batch + b];
+                if (!std::isfinite(ch)) {
+                    res = LBIB_ENUMERIC;
+                    act[b] = 0;
+                    changed = true;
+                    break;
+                }
+                if (ch <= tol) {
+                    iters[b] = k;
+                    act[b] = 0;
+                    changed = true;
+                    break;
+                }
+            }
+            if (!act[b]) --left;
+        }
+        if (changed) ADE_B_HIP(hipMemcpyAsync(active, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        done += H;
+    }
+    ADE_B_HIP(ade_batch_phi_launch(work[wc], dphi, nn, nx, ny, bc_y == LBIB_WALLS, batch, dbl, st));
+    ADE_B_HIP(hipMemcpyAsync(phi, dphi, (size_t)batch * nn * sizeof(double), hipMemcpyDeviceToHost, st));
+    ADE_B_HIP(hipStreamSynchronize(st));
+#undef ADE_B_HIP
+out:
+    if (st) (void)hipStreamSynchronize(st);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (int b = 0; b < 2; ++b)
+        if (work[b]) (void)hipFree(work[b]);
+    if (src) (void)hipFree(src);
+    if (phi_prev) (void)hipFree(phi_prev);
+    if (dphi) (void)hipFree(dphi);
+    if (partial) (void)hipFree(partial);
+    if (hist) (void)hipFree(hist);
+    if (prm) (void)hipFree(prm);
+    if (active) (void)hipFree(active);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (own) (void)hipStreamDestroy(st);
+    return res;
+}
+
 lbib_status lbib_sync(lbib_ctx* c)
 {
     if (!c) return LBIB_ESTATE;

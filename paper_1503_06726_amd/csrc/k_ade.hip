@@ -191,3 +191,159 @@ hipError_t launch_ade_hist(const double* partial, int nblocks, int S, double* hi
 }
 
 }  // namespace lbib
+
+// ---------------------------------------------------------------------------------------
+// batched ADE-only iterations: B independent single-species problems of one lattice size
+// (source/decay law, u = 0), one grid row per sample; a converged sample stops updating.
+// ---------------------------------------------------------------------------------------
+namespace lbib {
+
+
+template <typename WT>
+__global__ __launch_bounds__(ADE_THREADS) void k_ade_batch(AdeBatchArgs a)
+{
+    __shared__ double sh[2][ADE_THREADS];
+    const int b = blockIdx.y, t = threadIdx.x;
+    if (!a.active[b]) return;                                // uniform across the block
+    const int64_t idx = (int64_t)blockIdx.x * ADE_THREADS + t;
+    const WT w0 = WT(1) / WT(3), w1 = WT(1) / WT(6);
+    double d2 = 0.0, p2 = 0.0;
+    if (idx < a.nn) {
+        const int x = (int)(idx % a.nx), y = (int)(idx / a.nx);
+        const WT* src = (const WT*)a.src + (int64_t)5 * b * a.nn;
+        WT* dst = (WT*)a.dst + (int64_t)5 * b * a.nn;
+        WT g[5];
+        pull5w<WT>(src, a.nn, x, y, a.nx, a.ny, a.walls, g);
+        const WT phi = ((g[0] + g[1]) + (g[2] + g[3])) + g[4];
+        const WT R = (a.source[(int64_t)b * a.nn + idx] ? (WT)a.sigma[b] : WT(0)) - (WT)a.decay[b] * phi;
+        const WT om = (WT)a.omega[b], om1 = WT(1) - om;
+        // g_i <- g_i - omega (g_i - w_i phi) + w_i R
+        dst[idx] = om1 * g[0] + om * w0 * phi + w0 * R;
+        for (int i = 1; i < 5; ++i) dst[i * a.nn + idx] = om1 * g[i] + om * w1 * phi + w1 * R;
+        const double ph = (double)phi;
+        double* pp = a.phi_prev + (int64_t)b * a.nn + idx;
+        if (a.track) {
+            const double df = ph - *pp;
+            d2 = df * df;
+            p2 = ph * ph;
+        }
+        *pp = ph;
+    }
+    if (!a.track) return;
+    sh[0][t] = d2;
+    sh[1][t] = p2;
+    __syncthreads();
+    for (int w = ADE_THREADS / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            sh[0][t] += sh[0][t + w];
+            sh[1][t] += sh[1][t + w];
+        }
+        __syncthreads();
+    }
+    if (t < 2) a.partial[(((int64_t)a.hslot * a.B + b) * a.nblocks + blockIdx.x) * 2 + t] = sh[t][0];
+}
+
+// relative change per (pass, sample): one workgroup each, blocks added in order
+__global__ __launch_bounds__(ADE_THREADS) void k_ade_batch_hist(const double* __restrict__ partial, int nblocks, int B,
+                                                                const int* __restrict__ active, double* __restrict__ hist)
+{
+    __shared__ double sh[2][ADE_THREADS];
+    const int t = threadIdx.x, slot = blockIdx.x, b = blockIdx.y;
+    if (!active[b]) {
+        if (t == 0) hist[(int64_t)slot * B + b] = -1.0;        // not iterated in this pass
+        return;
+    }
+    double acc[2] = {0.0, 0.0};
+    for (int k = t; k < nblocks; k += ADE_THREADS)
+        for (int v = 0; v < 2; ++v) acc[v] += partial[(((int64_t)slot * B + b) * nblocks + k) * 2 + v];
+    sh[0][t] = acc[0];
+    sh[1][t] = acc[1];
+    __syncthreads();
+    for (int w = ADE_THREADS / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            sh[0][t] += sh[0][t + w];
+            sh[1][t] += sh[1][t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) hist[(int64_t)slot * B + b] = (sh[0][0] == 0.0) ? 0.0 : sqrt(sh[0][0]) / sqrt(sh[1][0]);
+}
+
+// equilibrium start g_i = w_i phi (u = 0), written in the stored (pre-streaming) layout so
+// that the first pull yields g_i(x) = w_i phi(x): s_i(x - v_i) = w_i phi(x), or, across a wall,
+// s_opp(i)(x) = w_i phi(x); and read-back of phi = sum_i g_i
+template <typename WT>
+__global__ void k_ade_batch_init(const double* __restrict__ phi, WT* __restrict__ g, int64_t nn, int nx, int ny,
+                                 int walls, int B)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (idx >= nn) return;
+    const int x = (int)(idx % nx), y = (int)(idx / nx);
+    const int vx[5] = {0, 1, 0, -1, 0}, vy[5] = {0, 0, 1, 0, -1}, opp[5] = {0, 3, 4, 1, 2};
+    const double p = phi ? phi[(int64_t)b * nn + idx] : 0.0;
+    WT* gb = g + (int64_t)5 * b * nn;
+    for (int i = 0; i < 5; ++i) {
+        const WT v = (WT)(p * (i == 0 ? 1.0 / 3.0 : 1.0 / 6.0));
+        const int sy = y - vy[i];
+        if (walls && (sy < 0 || sy >= ny)) {
+            gb[(int64_t)opp[i] * nn + idx] = v;
+        } else {
+            const int sx = (x - vx[i] + nx) % nx, syy = (sy + ny) % ny;
+            gb[(int64_t)i * nn + (int64_t)syy * nx + sx] = v;
+        }
+    }
+}
+
+template <typename WT>
+__global__ void k_ade_batch_phi(const WT* __restrict__ g, double* __restrict__ phi, int64_t nn, int nx, int ny,
+                                int walls, int B)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (idx >= nn) return;
+    // the stored values are post-collision: phi is the sum of the populations pulled to the node
+    WT q[5];
+    pull5w<WT>(g + (int64_t)5 * b * nn, nn, (int)(idx % nx), (int)(idx / nx), nx, ny, walls, q);
+    phi[(int64_t)b * nn + idx] = (double)(((q[0] + q[1]) + (q[2] + q[3])) + q[4]);
+}
+
+}  // namespace lbib
+
+namespace lbib {
+
+hipError_t ade_batch_launch(const AdeBatchArgs& a, bool fp64, hipStream_t s)
+{
+    const dim3 grid((unsigned)a.nblocks, (unsigned)a.B);
+    if (fp64) hipLaunchKernelGGL(k_ade_batch<double>, grid, dim3(ADE_THREADS), 0, s, a);
+    else hipLaunchKernelGGL(k_ade_batch<float>, grid, dim3(ADE_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t ade_batch_hist_launch(const AdeBatchArgs& a, double* hist, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ade_batch_hist, dim3(ADE_BATCH_SLOTS, (unsigned)a.B), dim3(ADE_THREADS), 0, s,
+                       (const double*)a.partial, a.nblocks, a.B, a.active, hist);
+    return hipGetLastError();
+}
+
+hipError_t ade_batch_init_launch(const double* phi, void* g, int64_t nn, int nx, int ny, int walls, int B, bool fp64,
+                                 hipStream_t s)
+{
+    const dim3 grid((unsigned)((nn + 255) / 256), (unsigned)B);
+    if (fp64) hipLaunchKernelGGL(k_ade_batch_init<double>, grid, dim3(256), 0, s, phi, (double*)g, nn, nx, ny, walls, B);
+    else hipLaunchKernelGGL(k_ade_batch_init<float>, grid, dim3(256), 0, s, phi, (float*)g, nn, nx, ny, walls, B);
+    return hipGetLastError();
+}
+
+hipError_t ade_batch_phi_launch(const void* g, double* phi, int64_t nn, int nx, int ny, int walls, int B, bool fp64,
+                                hipStream_t s)
+{
+    const dim3 grid((unsigned)((nn + 255) / 256), (unsigned)B);
+    if (fp64)
+        hipLaunchKernelGGL(k_ade_batch_phi<double>, grid, dim3(256), 0, s, (const double*)g, phi, nn, nx, ny, walls, B);
+    else hipLaunchKernelGGL(k_ade_batch_phi<float>, grid, dim3(256), 0, s, (const float*)g, phi, nn, nx, ny, walls, B);
+    return hipGetLastError();
+}
+
+}  // namespace lbib

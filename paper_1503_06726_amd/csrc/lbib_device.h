@@ -131,6 +131,24 @@ struct AdeArgs {
     int track;                         // 0: first pass (phi_prev is only written)
 };
 
+// batched ADE-only iterations: B single-species problems (source/decay, u = 0) on one lattice
+// size, absolute populations in the working type
+constexpr int ADE_BATCH_SLOTS = 64;   // passes per captured batch of the batched solver
+struct AdeBatchArgs {
+    const void* __restrict__ src;      // [B][5][ny][nx] working populations (absolute values)
+    void* __restrict__ dst;
+    double* __restrict__ phi_prev;     // [B][ny][nx]
+    const uint8_t* __restrict__ source;   // [B][ny][nx] 1 inside a source cell
+    const double* __restrict__ omega;  // [B] 1 / tau_D
+    const double* __restrict__ sigma;  // [B] source rate
+    const double* __restrict__ decay;  // [B]
+    const int* __restrict__ active;    // [B] 0 once converged
+    double* __restrict__ partial;      // [slots][B][nblocks][2]
+    int64_t nn;
+    int nx, ny, walls, B, nblocks;
+    int hslot, track;
+};
+
 struct RasterArgs {
     const int* __restrict__ off;
     const double2* __restrict__ X;

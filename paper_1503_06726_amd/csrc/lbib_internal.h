@@ -110,4 +110,12 @@ hipError_t launch_ade_copy(lbib_ctx* c, void* work, bool fp64, bool to_work);
 unsigned ade_blocks(int64_t nn);
 hipError_t launch_ade_hist(const double* partial, int nblocks, int S, double* hist, int slots, hipStream_t stream);
 
+// batched single-species ADE-only iterations (k_ade.hip)
+hipError_t ade_batch_launch(const AdeBatchArgs& a, bool fp64, hipStream_t s);
+hipError_t ade_batch_hist_launch(const AdeBatchArgs& a, double* hist, hipStream_t s);
+hipError_t ade_batch_init_launch(const double* phi, void* g, int64_t nn, int nx, int ny, int walls, int B, bool fp64,
+                                 hipStream_t s);
+hipError_t ade_batch_phi_launch(const void* g, double* phi, int64_t nn, int nx, int ny, int walls, int B, bool fp64,
+                                hipStream_t s);
+
 }  // namespace lbib

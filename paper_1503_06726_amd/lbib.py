@@ -27,7 +27,7 @@ EXPORTS = ["lbib_validate_params", "lbib_validate_cells", "lbib_create", "lbib_s
            "lbib_set_fields", "lbib_step", "lbib_get_fields", "lbib_get_forces", "lbib_get_spread",
            "lbib_reduce", "lbib_sync", "lbib_set_timing", "lbib_get_timing", "lbib_device_bytes",
            "lbib_last_error", "lbib_status_string", "lbib_version", "lbib_destroy",
-           "lbib_set_source_cells", "lbib_ade_steady"]
+           "lbib_set_source_cells", "lbib_ade_steady", "lbib_ade_batch"]
 
 
 class Species(C.Structure):
@@ -106,6 +106,9 @@ def lib():
     L.lbib_destroy.argtypes = [vp]
     L.lbib_set_source_cells.restype = st
     L.lbib_set_source_cells.argtypes = [vp, vp]
+    L.lbib_ade_batch.restype = st
+    L.lbib_ade_batch.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp, vp, vp, C.c_int32,
+                                 C.c_double, C.c_int64, C.c_int32, vp, vp]
     L.lbib_ade_steady.restype = st
     L.lbib_ade_steady.argtypes = [vp, C.c_double, C.c_int64, C.c_int32, C.POINTER(C.c_int64),
                                   C.POINTER(C.c_double)]
@@ -277,6 +280,28 @@ class Simulation:
         b = C.c_size_t()
         self._check(self.L.lbib_device_bytes(self.h, C.byref(b)), "lbib_device_bytes")
         return int(b.value)
+
+
+def ade_batch(nx: int, ny: int, bc_y: int, source, D, sigma, decay, phi0=None, tol: float = 1e-6,
+              max_iters: int = 1_000_000, fp64: bool = True, stream: int | None = None):
+    """Batched ADE-only steady states (see lbib_ade_batch); source [B, ny, nx] (nonzero inside a
+    source cell), D / sigma / decay [B], phi0 [B, ny, nx] or None (zero start).  Returns
+    (iterations [B] int64, final phi [B, ny, nx])."""
+    L = lib()
+    src = np.ascontiguousarray(np.asarray(source) != 0, np.uint8)
+    B = src.shape[0]
+    Dv = np.ascontiguousarray(D, np.float64).reshape(B)
+    sv = np.ascontiguousarray(sigma, np.float64).reshape(B)
+    dv = np.ascontiguousarray(decay, np.float64).reshape(B)
+    phi = (np.zeros((B, ny, nx)) if phi0 is None else np.array(phi0, np.float64).reshape(B, ny, nx))
+    phi = np.ascontiguousarray(phi)
+    its = np.zeros(B, np.int64)
+    s = L.lbib_ade_batch(int(nx), int(ny), int(bc_y), int(B), _p(src), _p(Dv), _p(sv), _p(dv), _p(phi),
+                         1 if phi0 is None else 0, float(tol), int(max_iters), 1 if fp64 else 0, _p(its),
+                         C.c_void_p(stream) if stream else None)
+    if s != OK:
+        raise LbibError(s, "lbib_ade_batch")
+    return its, phi
 
 
 def from_workload(w, stream: int | None = None, storage: int | None = None) -> Simulation:

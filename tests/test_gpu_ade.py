@@ -157,3 +157,56 @@ def test_ade_and_source_errors():
         g.ade_steady(-1.0, 10)
     assert e.value.status == lbib.EINVAL
     g.close()
+
+
+# ------------------------------------------------------------------------------------------
+# batched ADE-only solver: many problems of one lattice size per launch
+# ------------------------------------------------------------------------------------------
+def _source_mask(w):
+    """Source indicator of a workload from the oracle's map (test side)."""
+    o = O.from_workload(w)
+    return (o.source_map() != 0).astype(np.uint8), o
+
+
+def test_ade_batch_iterations_equal_oracle():
+    ws = [small_static(60, 44, 6, s, D, lam) for s, D, lam in [(10, 0.2, 2e-3), (11, 0.08, 5e-3), (12, 0.3, 8e-4)]]
+    masks, counts = [], []
+    for w in ws:
+        m, o = _source_mask(w)
+        masks.append(m)
+        k, _ = o.ade_steady(1e-6, 100000, chunk=1024)
+        counts.append(k)
+    its, phi = lbib.ade_batch(60, 44, W.WALLS, np.stack(masks), [w.species[0].D for w in ws], [1e-3] * 3,
+                              [w.species[0].c[1] for w in ws], tol=1e-6, max_iters=100000, fp64=True)
+    say(f"  batched {its.tolist()}, oracle {counts}")
+    assert its.tolist() == counts
+
+
+def test_ade_batch_equals_single_context_solver():
+    ws = [W.static_tissue(i) for i in range(3)]
+    masks = [_source_mask(w)[0] for w in ws]
+    its, phi = lbib.ade_batch(256, 256, W.WALLS, np.stack(masks), [w.species[0].D for w in ws], [1e-3] * 3,
+                              [w.species[0].c[1] for w in ws], tol=1e-6, max_iters=1_000_000, fp64=True)
+    single = []
+    for w in ws:
+        g = lbib.from_workload(w)
+        k, _ = g.ade_steady(1e-6, 1_000_000, fp64=True)
+        g.close()
+        single.append(k)
+    say(f"  batched {its.tolist()}, one context each {single}")
+    assert its.tolist() == single and min(single) > 0
+
+
+def test_ade_batch_fixed_iterations_state():
+    # tol = 0: one first pass plus whole batches of 64 passes
+    w = small_static(48, 40, 5, 20, 0.15, 3e-3)
+    m, o = _source_mask(w)
+    phi0 = np.random.default_rng(0).random((48 * 40,)).reshape(1, 40, 48) * 0.5
+    its, phi = lbib.ade_batch(48, 40, W.WALLS, m[None], [0.15], [1e-3], [3e-3], phi0=phi0, tol=0.0,
+                              max_iters=100, fp64=True)
+    o.set_fields(phi=phi0)
+    o.ade_step(1 + 64 * 2)
+    R = o.get_fields()["phi"][0]
+    r = rel(phi[0], R)
+    say(f"  phi rel-L2 {r:.2e}")
+    assert its[0] == 0 and r <= 1e-12
