@@ -192,6 +192,50 @@ lbib_status lbib_ade_batch(int32_t nx, int32_t ny, int32_t bc_y, int32_t batch, 
                            int32_t zero_start, double tol, int64_t max_iters, int32_t fp64, int64_t* iters,
                            void* hip_stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Learned warm start of the steady state: a convolutional surrogate (four-level U-Net on BF16
+ * with FP32 accumulation) mapping, per lattice node, [source mask, cell-boundary mask,
+ * normalised diffusivity, normalised log decay] to the dimensionless steady concentration
+ * phi * decay / source, trained and evaluated entirely by the library's kernels.  It is not a
+ * passage of the paper: it seeds the D2Q5 populations, and lbib_ade_steady / lbib_ade_batch
+ * still iterate to the same tolerance, so a poor prediction costs iterations, not accuracy.
+ *
+ * Architecture (15 convolutions, all 3x3, zero padding, stride 1; ReLU after each but the
+ * last; channels in parentheses; "pool" is a 2x2 average, "up" a 2x nearest upsample, "+" adds
+ * the encoder output of the same level after the convolution's ReLU):
+ *   input(4, zero-padded to 16) -c0-> (32) -c1-> s0(32) pool -c2-> (64) -c3-> s1(64) pool
+ *   -c4-> (128) -c5-> s2(128) pool -c6-> (256) -c7-> (256) up -c8-> (128) + s2 -c9-> (128)
+ *   up -c10-> (64) + s1 -c11-> (64) up -c12-> (32) + s0 -c13-> (32) -c14-> (16); output = channel 0
+ * Parameters, packed in layer order l = 0..14: W_l [Cout][9 Cin] (index (3 ky + kx) Cin + ci,
+ * reading the input at (y + ky - 1, x + kx - 1)), then b_l [Cout].  FP32 host arrays.
+ * Tensors handed to the calls below are DEVICE pointers: inputs [B][h][w][4] float, targets
+ * and predictions [B][h][w] float.  h and w are multiples of 8.  Loss: mean over nodes of
+ * (prediction - target)^2.  Training uses Adam (0.9, 0.999, 1e-8) on FP32 master weights.
+ * --------------------------------------------------------------------------------------- */
+typedef struct lbib_net lbib_net;
+
+/* Create a network for h x w inputs and batches of at most max_batch, all parameters zero.
+ * hip_stream as in lbib_create.  LBIB_EINVAL for bad sizes. */
+lbib_status lbib_net_create(int32_t h, int32_t w, int32_t max_batch, void* hip_stream, lbib_net** out);
+/* Number of packed parameters. */
+lbib_status lbib_net_param_count(const lbib_net* net, int64_t* count);
+/* Copy in / out all parameters (host FP32, packed as above); setting resets Adam's moments.
+ * LBIB_EINVAL for non-finite values. */
+lbib_status lbib_net_set_params(lbib_net* net, const float* params);
+lbib_status lbib_net_get_params(lbib_net* net, float* params);
+/* Predictions for B <= max_batch inputs (device pointers); synchronises. */
+lbib_status lbib_net_predict(lbib_net* net, const float* inputs, int32_t B, float* out);
+/* Loss and, when grad (host, packed like the parameters) is not NULL, its gradient for one
+ * batch; synchronises. */
+lbib_status lbib_net_loss_grad(lbib_net* net, const float* inputs, const float* targets, int32_t B, double* loss,
+                               float* grad);
+/* One Adam step with learning rate lr on one batch; *loss (optional) is the batch loss before
+ * the step.  Synchronises for the loss. */
+lbib_status lbib_net_train_step(lbib_net* net, const float* inputs, const float* targets, int32_t B, float lr,
+                                double* loss);
+/* Free the network (NULL is ignored). */
+void lbib_net_destroy(lbib_net* net);
+
 /* Global sums over the lattice in FP64, deterministic:
  *   out[0] = sum rho, out[1] = sum rho ux, out[2] = sum rho uy, out[3+s] = sum phi_s.
  * out has 3 + n_species doubles.  Returns LBIB_ENUMERIC if any sum is not finite. */

@@ -27,7 +27,9 @@ EXPORTS = ["lbib_validate_params", "lbib_validate_cells", "lbib_create", "lbib_s
            "lbib_set_fields", "lbib_step", "lbib_get_fields", "lbib_get_forces", "lbib_get_spread",
            "lbib_reduce", "lbib_sync", "lbib_set_timing", "lbib_get_timing", "lbib_device_bytes",
            "lbib_last_error", "lbib_status_string", "lbib_version", "lbib_destroy",
-           "lbib_set_source_cells", "lbib_ade_steady", "lbib_ade_batch"]
+           "lbib_set_source_cells", "lbib_ade_steady", "lbib_ade_batch",
+           "lbib_net_create", "lbib_net_param_count", "lbib_net_set_params", "lbib_net_get_params",
+           "lbib_net_predict", "lbib_net_loss_grad", "lbib_net_train_step", "lbib_net_destroy"]
 
 
 class Species(C.Structure):
@@ -106,6 +108,22 @@ def lib():
     L.lbib_destroy.argtypes = [vp]
     L.lbib_set_source_cells.restype = st
     L.lbib_set_source_cells.argtypes = [vp, vp]
+    L.lbib_net_create.restype = st
+    L.lbib_net_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, C.POINTER(C.c_void_p)]
+    L.lbib_net_param_count.restype = st
+    L.lbib_net_param_count.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.lbib_net_set_params.restype = st
+    L.lbib_net_set_params.argtypes = [vp, vp]
+    L.lbib_net_get_params.restype = st
+    L.lbib_net_get_params.argtypes = [vp, vp]
+    L.lbib_net_predict.restype = st
+    L.lbib_net_predict.argtypes = [vp, vp, C.c_int32, vp]
+    L.lbib_net_loss_grad.restype = st
+    L.lbib_net_loss_grad.argtypes = [vp, vp, vp, C.c_int32, C.POINTER(C.c_double), vp]
+    L.lbib_net_train_step.restype = st
+    L.lbib_net_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, C.POINTER(C.c_double)]
+    L.lbib_net_destroy.restype = None
+    L.lbib_net_destroy.argtypes = [vp]
     L.lbib_ade_batch.restype = st
     L.lbib_ade_batch.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp, vp, vp, C.c_int32,
                                  C.c_double, C.c_int64, C.c_int32, vp, vp]
@@ -302,6 +320,64 @@ def ade_batch(nx: int, ny: int, bc_y: int, source, D, sigma, decay, phi0=None, t
     if s != OK:
         raise LbibError(s, "lbib_ade_batch")
     return its, phi
+
+
+class Net:
+    """The steady-state surrogate network (lbib_net_*).  Tensors passed to predict / loss_grad /
+    train_step are device addresses (e.g. ``torch.Tensor.data_ptr()`` of CUDA tensors):
+    inputs [B, h, w, 4] float32, targets and outputs [B, h, w] float32."""
+
+    def __init__(self, h: int, w: int, max_batch: int, stream: int | None = None):
+        self.L = lib()
+        self.h = None
+        hh = C.c_void_p()
+        s = self.L.lbib_net_create(int(h), int(w), int(max_batch), C.c_void_p(stream) if stream else None,
+                                   C.byref(hh))
+        if s != OK:
+            raise LbibError(s, "lbib_net_create")
+        self.h = hh
+        n = C.c_int64(0)
+        self.L.lbib_net_param_count(self.h, C.byref(n))
+        self.n_params = int(n.value)
+
+    def close(self):
+        if self.h:
+            self.L.lbib_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, s, where):
+        if s != OK:
+            raise LbibError(s, where)
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, np.float32)
+        assert a.size == self.n_params
+        self._check(self.L.lbib_net_set_params(self.h, _p(a)), "lbib_net_set_params")
+
+    def get_params(self) -> np.ndarray:
+        a = np.zeros(self.n_params, np.float32)
+        self._check(self.L.lbib_net_get_params(self.h, _p(a)), "lbib_net_get_params")
+        return a
+
+    def predict(self, inputs_ptr: int, B: int, out_ptr: int):
+        self._check(self.L.lbib_net_predict(self.h, C.c_void_p(inputs_ptr), int(B), C.c_void_p(out_ptr)),
+                    "lbib_net_predict")
+
+    def loss_grad(self, inputs_ptr: int, targets_ptr: int, B: int, want_grad: bool = True):
+        loss = C.c_double(0.0)
+        g = np.zeros(self.n_params, np.float32) if want_grad else None
+        self._check(self.L.lbib_net_loss_grad(self.h, C.c_void_p(inputs_ptr), C.c_void_p(targets_ptr), int(B),
+                                              C.byref(loss), _p(g)), "lbib_net_loss_grad")
+        return float(loss.value), g
+
+    def train_step(self, inputs_ptr: int, targets_ptr: int, B: int, lr: float) -> float:
+        loss = C.c_double(0.0)
+        self._check(self.L.lbib_net_train_step(self.h, C.c_void_p(inputs_ptr), C.c_void_p(targets_ptr), int(B),
+                                               float(lr), C.byref(loss)), "lbib_net_train_step")
+        return float(loss.value)
 
 
 def from_workload(w, stream: int | None = None, storage: int | None = None) -> Simulation:
