@@ -51,35 +51,47 @@ ADE_CAP = 1_000_000
 def ade_samples(n: int):
     """The held-out static-tissue samples (generated on the host in a process pool, before the
     GPU is touched)."""
-    import concurrent.futures as cf
-    from paper_1503_06726_amd import workloads as W
+    from paper_1503_06726_amd import warmstart as WS
     if n <= 0:
         return []
-    with cf.ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
-        return list(ex.map(W.static_tissue, range(n)))
+    return WS.generate(range(n), held_out=True, workers=min(8, os.cpu_count() or 1))
 
 
 def ade_half(samples, lbib, stream):
-    """Iterations to steady state of the species alone (u = 0, frozen membranes) from a zero
-    start, in FP64, stopping at ||phi^k - phi^{k-1}|| <= 1e-6 ||phi^k||."""
+    """Iterations to steady state of the species alone (u = 0, frozen membranes), in FP64,
+    stopping at ||phi^k - phi^{k-1}|| <= 1e-6 ||phi^k||: from zero, and from the trained
+    surrogate's prediction."""
     import numpy as np
-    its, secs, passes = [], 0.0, 0
-    for w in samples:
-        sim = lbib.from_workload(w, stream=stream)
-        sim.sync()
-        t0 = time.perf_counter()
-        k, _ = sim.ade_steady(ADE_TOL, ADE_CAP, fp64=True)
-        secs += time.perf_counter() - t0
-        sim.close()
-        its.append(k if k > 0 else ADE_CAP)
-        passes += 1 + 128 * (((k if k > 0 else ADE_CAP) + 127) // 128)
-    its = np.asarray(its)
+    from paper_1503_06726_amd import warmstart as WS
+    src, _, feat = WS.prepare(samples, stream)
+    t0 = time.perf_counter()
+    k0, _ = WS.solve(samples, src, tol=ADE_TOL, max_iters=ADE_CAP, stream=stream)
+    t_zero = time.perf_counter() - t0
+    params, meta = WS.load()
+    net = lbib.Net(samples[0].ny, samples[0].nx, 16, stream=stream)
+    net.set_params(params)
+    t0 = time.perf_counter()
+    phi_hat = WS.predict(net, feat, samples)
+    t_pred = time.perf_counter() - t0
+    net.close()
+    t0 = time.perf_counter()
+    kw, _ = WS.solve(samples, src, phi0=phi_hat, tol=ADE_TOL, max_iters=ADE_CAP, stream=stream)
+    t_warm = time.perf_counter() - t0
+
+    def stats(k):
+        kk = np.where(k > 0, k, ADE_CAP)
+        return {"median_iters": float(np.median(kk)), "mean_iters": round(float(kk.mean()), 1),
+                "unconverged": int((k == 0).sum())}
+    z, wm = stats(k0), stats(kw)
     return {"workload": "static tissue 256x256 walls-y, 50-300 Voronoi cells, seeded source cells, "
                         "D ~ U(0.02, 0.5), decay ~ U(1e-5, 1e-3), source 1e-3; held-out seeds",
-            "samples": len(samples), "tol": ADE_TOL, "cap": ADE_CAP, "start": "zero", "precision": "f64",
-            "median_iters": float(np.median(its)), "mean_iters": round(float(its.mean()), 1),
-            "unconverged": int((its >= ADE_CAP).sum()),
-            "us_per_iter": round(secs / max(passes, 1) * 1e6, 3)}
+            "samples": len(samples), "tol": ADE_TOL, "cap": ADE_CAP, "precision": "f64",
+            "zero_start": z, "warm_start": wm,
+            "speedup_median": round(z["median_iters"] / wm["median_iters"], 3),
+            "speedup_mean": round(z["mean_iters"] / wm["mean_iters"], 3),
+            "seconds": {"zero_start_solves": round(t_zero, 2), "prediction": round(t_pred, 3),
+                        "warm_start_solves": round(t_warm, 2)},
+            "net": f"BF16 U-Net, {meta['samples']} training samples, {meta['epochs']} epochs"}
 
 
 def cpu_baseline(w, budget_s: float = 12.0, max_steps: int = 30):

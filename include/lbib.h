@@ -194,21 +194,23 @@ lbib_status lbib_ade_batch(int32_t nx, int32_t ny, int32_t bc_y, int32_t batch, 
 
 /* ---------------------------------------------------------------------------------------
  * Learned warm start of the steady state: a convolutional surrogate (four-level U-Net on BF16
- * with FP32 accumulation) mapping, per lattice node, [source mask, cell-boundary mask,
- * normalised diffusivity, normalised log decay] to the dimensionless steady concentration
- * phi * decay / source, trained and evaluated entirely by the library's kernels.  It is not a
+ * with FP32 accumulation) mapping, per lattice node, eight input channels (the caller's
+ * features; the warm-start module uses source mask, cell-boundary mask, normalised diffusivity,
+ * normalised log decay and the domain's source fraction, and leaves three at zero) to the
+ * dimensionless steady concentration phi * decay / source, trained and evaluated entirely by
+ * the library's kernels.  It is not a
  * passage of the paper: it seeds the D2Q5 populations, and lbib_ade_steady / lbib_ade_batch
  * still iterate to the same tolerance, so a poor prediction costs iterations, not accuracy.
  *
  * Architecture (15 convolutions, all 3x3, zero padding, stride 1; ReLU after each but the
  * last; channels in parentheses; "pool" is a 2x2 average, "up" a 2x nearest upsample, "+" adds
  * the encoder output of the same level after the convolution's ReLU):
- *   input(4, zero-padded to 16) -c0-> (32) -c1-> s0(32) pool -c2-> (64) -c3-> s1(64) pool
+ *   input(8, zero-padded to 16) -c0-> (32) -c1-> s0(32) pool -c2-> (64) -c3-> s1(64) pool
  *   -c4-> (128) -c5-> s2(128) pool -c6-> (256) -c7-> (256) up -c8-> (128) + s2 -c9-> (128)
  *   up -c10-> (64) + s1 -c11-> (64) up -c12-> (32) + s0 -c13-> (32) -c14-> (16); output = channel 0
  * Parameters, packed in layer order l = 0..14: W_l [Cout][9 Cin] (index (3 ky + kx) Cin + ci,
  * reading the input at (y + ky - 1, x + kx - 1)), then b_l [Cout].  FP32 host arrays.
- * Tensors handed to the calls below are DEVICE pointers: inputs [B][h][w][4] float, targets
+ * Tensors handed to the calls below are DEVICE pointers: inputs [B][h][w][8] float, targets
  * and predictions [B][h][w] float.  h and w are multiples of 8.  Loss: mean over nodes of
  * (prediction - target)^2.  Training uses Adam (0.9, 0.999, 1e-8) on FP32 master weights.
  * --------------------------------------------------------------------------------------- */

@@ -89,9 +89,9 @@ def relu(z):
 
 
 def pack_input(inputs):
-    """[B, H, W, 4] -> [B, H, W, 16] with channels 4..15 zero."""
+    """[B, H, W, 8] -> [B, H, W, 16] with channels 8..15 zero."""
     x = np.zeros(inputs.shape[:3] + (16,))
-    x[..., :4] = inputs
+    x[..., :8] = inputs
     return x
 
 

@@ -1,8 +1,9 @@
 // Convolutional surrogate of the species' steady state (gfx950): a four-level U-Net on BF16
 // activations and weights with FP32 accumulation on MFMA, trained by the kernels below (forward,
-// backward, Adam).  It maps [source mask, cell-boundary mask, diffusivity, decay] to the
-// dimensionless steady concentration phi * decay / source, which seeds the D2Q5 populations
-// before the ADE-only iteration runs to its tolerance.
+// backward, Adam).  It maps per-node features of a static tissue (source mask, cell-boundary
+// mask, diffusivity, decay, source fraction; eight input channels) to the dimensionless steady
+// concentration phi * decay / source, which seeds the D2Q5 populations before the ADE-only
+// iteration runs to its tolerance.
 //
 // Tensors are NHWC with the channel count a multiple of 16.  A 3x3 convolution (zero padding,
 // stride 1) is an implicit GEMM: M = output pixels, N = output channels, K = 9 * Cin ordered
@@ -162,14 +163,14 @@ __global__ __launch_bounds__(THREADS) void k_conv_wgrad(const bf16* __restrict__
 // ---------------------------------------------------------------------------------------
 // elementwise pieces
 // ---------------------------------------------------------------------------------------
-// inputs [B][H][W][4] float -> [B][H][W][16] bf16 (channels 4..15 zero)
+// inputs [B][H][W][8] float -> [B][H][W][16] bf16 (channels 8..15 zero)
 __global__ void k_pack_input(const float* __restrict__ src, bf16* __restrict__ dst, int64_t npix)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= npix * 16) return;
     const int64_t p = i >> 4;
     const int c = (int)(i & 15);
-    dst[i] = c < 4 ? f2bf(src[p * 4 + c]) : (bf16)0;
+    dst[i] = c < 8 ? f2bf(src[p * 8 + c]) : (bf16)0;
 }
 
 // 2x2 average pool: [B][H][W][C] -> [B][H/2][W/2][C]

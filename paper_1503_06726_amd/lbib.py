@@ -325,7 +325,7 @@ def ade_batch(nx: int, ny: int, bc_y: int, source, D, sigma, decay, phi0=None, t
 class Net:
     """The steady-state surrogate network (lbib_net_*).  Tensors passed to predict / loss_grad /
     train_step are device addresses (e.g. ``torch.Tensor.data_ptr()`` of CUDA tensors):
-    inputs [B, h, w, 4] float32, targets and outputs [B, h, w] float32."""
+    inputs [B, h, w, 8] float32, targets and outputs [B, h, w] float32."""
 
     def __init__(self, h: int, w: int, max_batch: int, stream: int | None = None):
         self.L = lib()

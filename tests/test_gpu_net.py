@@ -41,11 +41,12 @@ def random_case(seed, B, H, W):
         Wl = rng.standard_normal((co, 9 * ci)) * np.sqrt(2.0 / (9 * ci))
         bl = 0.05 * rng.standard_normal(co)
         layers.append((Wl, bl))
-    inputs = np.zeros((B, H, W, 4))
+    inputs = np.zeros((B, H, W, 8))
     inputs[..., 0] = rng.random((B, H, W)) < 0.3
     inputs[..., 1] = rng.random((B, H, W)) < 0.1
     inputs[..., 2] = rng.uniform(-1, 1, (B, 1, 1))
     inputs[..., 3] = rng.uniform(-1, 1, (B, 1, 1))
+    inputs[..., 4] = rng.uniform(-1, 1, (B, 1, 1))
     targets = rng.random((B, H, W))
     return layers, inputs, targets
 
@@ -81,7 +82,7 @@ def test_net_training_reduces_loss():
     # a small learnable map: the target is a fixed smoothing of the first input channel
     rng = np.random.default_rng(3)
     B, H, W = 4, 32, 32
-    inputs = np.zeros((B, H, W, 4))
+    inputs = np.zeros((B, H, W, 8))
     inputs[..., 0] = rng.random((B, H, W)) < 0.2
     k = np.ones(5) / 5
     sm = inputs[..., 0]
