@@ -7,7 +7,11 @@ iterations the species lattice alone needs to reach steady state on held-out 256
 static-tissue samples.  Prints one JSON line (rank 0).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|tissue|tiny]
-                  [--storage fp32|fp16|bf16] [--ade-samples N] [--no-cpu-baseline]
+                  [--storage fp32|fp16|bf16] [--ade-samples N] [--sweep-sims N] [--sweep-steps K]
+                  [--no-cpu-baseline]
+
+The batched sweep (64 uneven simulations in one batch, against the same simulations run one
+after another) is reported beside the headline number.
 """
 import argparse
 import json
@@ -94,6 +98,74 @@ def ade_half(samples, lbib, stream):
             "net": f"BF16 U-Net, {meta['samples']} training samples, {meta['epochs']} epochs"}
 
 
+def sweep_workloads(n: int):
+    """The sweep's simulations (host geometry, in a process pool before the GPU is touched)."""
+    import concurrent.futures as cf
+    from paper_1503_06726_amd import workloads as W
+    if n <= 0:
+        return []
+    with cf.ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        return list(ex.map(W.sweep_member, range(n)))
+
+
+def sweep_half(ws, steps: int, lbib, stream):
+    """Batched parameter sweep: every simulation advanced `steps` steps by one batch (tile
+    height autotuned, whole 16-step periods replayed from one graph), against the same
+    simulations stepped one after another with lbib_step.  Total MLUPS of both."""
+    import numpy as np
+    import torch
+    steps = max(16, steps - steps % 16)
+    A = [lbib.from_workload(w, stream=stream) for w in ws]
+    B = [lbib.from_workload(w, stream=stream) for w in ws]
+    nn = sum(w.nx * w.ny for w in ws)
+    for s in A:                                     # warm-up: one period each (captures graphs)
+        s.step(16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in A:
+        s.step(steps)
+    for s in A:
+        s.sync()
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    log(f"sweep: sequential {steps} steps of {len(ws)} simulations: {t_seq:.3f} s")
+    batch = lbib.Batch(B, stream=stream)
+    rows, tune = batch.autotune(periods=4)
+    log(f"sweep: autotuned tile height {rows} rows; ms per step {tune}")
+    batch.step(16)
+    batch.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(steps)
+    batch.sync()
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    log(f"sweep: batched {steps} steps: {t_bat:.3f} s")
+    # both sets have now taken 16 + steps steps; at the default tile height they agree bit for bit
+    same = None
+    if rows == 8:
+        i = int(np.argmin([w.nx * w.ny for w in ws]))
+        fa, fb = A[i].get_fields(mask=False), B[i].get_fields(mask=False)
+        same = all(np.array_equal(fa[k], fb[k]) for k in ("rho", "u", "phi", "xy"))
+    batch.close()
+    for s in A + B:
+        s.close()
+    bat = nn * steps / t_bat / 1e6
+    seq = nn * steps / t_seq / 1e6
+    b_up = lattice_bytes_per_update(1, True)
+    return {"workload": f"{len(ws)} simulations, nx and ny log-uniform in [128, 1024], walls-y, "
+                        "min(U{10..500}, nx ny / 100) Voronoi cells, tau ~ U(0.55, 1.2), k ~ U(0.005, 0.05), "
+                        "body 1e-6 x, 1 D2Q5 species (source/decay)",
+            "sims": len(ws), "lattice_nodes": nn, "membrane_nodes": int(sum(w.n_nodes for w in ws)),
+            "cells": int(sum(w.n_cells for w in ws)), "steps": steps, "storage": "fp32",
+            "batched_mlups": round(bat, 1), "sequential_mlups": round(seq, 1), "speedup": round(bat / seq, 3),
+            "batched_ms_per_step": round(t_bat / steps * 1e3, 4),
+            "sequential_ms_per_step": round(t_seq / steps * 1e3, 4),
+            "batched_lattice_bytes_frac_of_hbm": round(b_up * bat * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
+            "tile_rows": rows, "autotune_ms_per_step": {str(k): round(v, 4) for k, v in tune.items()},
+            "smallest_member_bit_identical": same}
+
+
 def cpu_baseline(w, budget_s: float = 12.0, max_steps: int = 30):
     from oracle import oracle as O
     log("cpu baseline: oracle on the same workload")
@@ -123,6 +195,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ade-samples", type=int, default=256,
                     help="held-out static-tissue samples for the iterations-to-steady half (0 skips)")
+    ap.add_argument("--sweep-sims", type=int, default=64,
+                    help="simulations of the batched sweep (0 skips)")
+    ap.add_argument("--sweep-steps", type=int, default=2000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain device copy of 1 GiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -132,6 +207,7 @@ def main():
         sys.exit(2)
 
     samples = [] if args.copy_probe else ade_samples(args.ade_samples)
+    sweep = [] if args.copy_probe else sweep_workloads(args.sweep_sims)
 
     import torch
     from paper_1503_06726_amd import lbib, workloads as W
@@ -211,6 +287,9 @@ def main():
         log(f"iterations to steady: {len(samples)} samples")
         out["ade_iters_to_steady"] = ade_half(samples, lbib, stream)
         log(f"  {out['ade_iters_to_steady']}")
+    if sweep:
+        out["batched_sweep"] = sweep_half(sweep, args.sweep_steps, lbib, stream)
+        log(f"  {out['batched_sweep']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -193,6 +193,58 @@ lbib_status lbib_ade_batch(int32_t nx, int32_t ny, int32_t bc_y, int32_t batch, 
                            void* hip_stream);
 
 /* ---------------------------------------------------------------------------------------
+ * Batched stepping of many independent simulations (parameter sweeps).  The paper runs one
+ * tissue at a time; a batch adopts existing contexts, of any lattice sizes and cell counts,
+ * and advances them together: each kernel of the step (Fig. "Algorithm Overview": lattice
+ * pass with spreading and interpolation, node advection and forces, list rebuild) runs once
+ * per step over every simulation, and whole list periods (16 steps) replay one captured HIP
+ * graph.  Each simulation's arithmetic is that of lbib_step: with the default tile height (8
+ * rows) a batched simulation is bit-identical to the same simulation stepped alone; another
+ * tile height changes only the grouping of the interpolation sums (round-off level).
+ * While adopted, a context's own lbib_step, lbib_set_cells, lbib_set_fields,
+ * lbib_set_source_cells and lbib_ade_steady return LBIB_ESTATE; its reads (lbib_get_fields,
+ * lbib_get_forces, lbib_get_spread, lbib_reduce, lbib_sync) wait for the batch's last
+ * enqueued work.  Destroying an adopted context leaves the batch unusable (LBIB_ESTATE).
+ * --------------------------------------------------------------------------------------- */
+typedef struct lbib_batch lbib_batch;
+
+/* Adopt n >= 1 contexts (host array of distinct, non-adopted contexts on the current device,
+ * each with cells set, all with the same species count, storage type and source law).  Any
+ * context between list rebuilds has its lists rebuilt first.  hip_stream as in lbib_create
+ * (the batch's work runs there).  The contexts stay owned by the caller and must outlive the
+ * batch.  LBIB_EINVAL for a bad set; *out is NULL on failure. */
+lbib_status lbib_batch_create(lbib_ctx* const* sims, int32_t n, void* hip_stream, lbib_batch** out);
+
+/* Enqueue n >= 0 steps of every simulation on the batch's stream (asynchronous). */
+lbib_status lbib_batch_step(lbib_batch* b, int32_t n);
+
+/* Wait for the batch's work and check every simulation's error flags (LBIB_ENUMERIC, naming
+ * the simulation, when a node became non-finite or outran its list margin). */
+lbib_status lbib_batch_sync(lbib_batch* b);
+
+/* Lattice tile height (rows; tiles are 64 columns wide) of the batched lattice pass: 4, 8
+ * (default) or 16.  4 needs walls or ny divisible by 4 in every simulation (LBIB_EINVAL).
+ * Changing it is allowed only after a whole number of 16-step periods (LBIB_ESTATE); the
+ * lists are rebuilt for the new tiles. */
+lbib_status lbib_batch_get_tile(const lbib_batch* b, int32_t* rows);
+lbib_status lbib_batch_set_tile(lbib_batch* b, int32_t rows);
+
+/* Autotuner: time `periods` 16-step periods (after one warm-up period) of the batch at every
+ * admissible tile height, on a copy of the simulations' state that is restored afterwards
+ * (the simulations do not advance), and keep the fastest.  rows receives it; ms_per_step
+ * (NULL, or 3 host doubles) receives the time per step of heights 4, 8, 16 (-1 where not
+ * admissible).  Needs device memory for one copy of every simulation's state; only after a
+ * whole number of periods (LBIB_ESTATE); synchronises. */
+lbib_status lbib_batch_autotune(lbib_batch* b, int32_t periods, int32_t* rows, double* ms_per_step);
+
+/* Last error message of the batch (never NULL). */
+const char* lbib_batch_last_error(const lbib_batch* b);
+
+/* Release the contexts (waiting for the batch's work; lists of a non-default tile height are
+ * rebuilt for the contexts' own steps) and free the batch.  NULL is ignored. */
+void lbib_batch_destroy(lbib_batch* b);
+
+/* ---------------------------------------------------------------------------------------
  * Learned warm start of the steady state: a convolutional surrogate (four-level U-Net on BF16
  * with FP32 accumulation) mapping, per lattice node, eight input channels (the caller's
  * features; the warm-start module uses source mask, cell-boundary mask, normalised diffusivity,

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbib.so")
 ARCH = os.environ.get("LBIB_OFFLOAD_ARCH", "gfx950")
 
-HIP_SOURCES = ["api.hip", "k_lattice.hip", "k_membrane.hip", "k_raster.hip", "k_ade.hip", "k_net.hip"]
+HIP_SOURCES = ["api.hip", "batch.hip", "k_lattice.hip", "k_membrane.hip", "k_raster.hip", "k_ade.hip", "k_net.hip"]
 CXX_SOURCES = ["validate.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"), "-I", CSRC]

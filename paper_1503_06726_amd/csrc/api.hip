@@ -107,15 +107,19 @@ struct Timed {
 // -------------------------------------------------------------------------------------
 // kernel argument builders
 // -------------------------------------------------------------------------------------
-LatticeArgs lattice_args(lbib_ctx* c)
+}  // namespace
+
+namespace lbib {
+
+LatticeArgs lattice_args_at(lbib_ctx* c, int cur)
 {
     LatticeArgs a;
     std::memset(&a, 0, sizeof a);
     const lbib_params& p = c->p;
-    a.fsrc = c->f[c->cur];
-    a.fdst = c->f[1 - c->cur];
-    a.gsrc = c->g[c->cur];
-    a.gdst = c->g[1 - c->cur];
+    a.fsrc = c->f[cur];
+    a.fdst = c->f[1 - cur];
+    a.gsrc = c->g[cur];
+    a.gdst = c->g[1 - cur];
     a.nn = c->nn;
     a.nx = p.nx;
     a.ny = p.ny;
@@ -140,14 +144,14 @@ LatticeArgs lattice_args(lbib_ctx* c)
     a.rec_ij = c->d_rec_ij;
     a.part = c->d_part;
     a.n_nodes = c->n_nodes;
-    a.inside = c->inside[c->cur];
-    a.inside_clr = c->inside[1 - c->cur];
+    a.inside = c->inside[cur];
+    a.inside_clr = c->inside[1 - cur];
     a.wpr = c->wpr;
     a.e_out = nullptr;
     return a;
 }
 
-MembraneArgs membrane_args(lbib_ctx* c, int advect)
+MembraneArgs membrane_args_at(lbib_ctx* c, int cur, int advect)
 {
     MembraneArgs a;
     std::memset(&a, 0, sizeof a);
@@ -162,7 +166,7 @@ MembraneArgs membrane_args(lbib_ctx* c, int advect)
     a.ij_list = c->d_ijlist;
     a.rec = c->d_rec;
     a.rec_ij = c->d_rec_ij;
-    a.inside = c->inside[c->cur];
+    a.inside = c->inside[cur];
     a.src = c->d_src;
     a.wpr = c->wpr;
     a.err = c->d_err;
@@ -179,7 +183,8 @@ MembraneArgs membrane_args(lbib_ctx* c, int advect)
     return a;
 }
 
-ListArgs list_args(lbib_ctx* c)
+// lists for lattice tiles of lty rows
+ListArgs list_args_h(lbib_ctx* c, int lty)
 {
     ListArgs a;
     std::memset(&a, 0, sizeof a);
@@ -195,10 +200,19 @@ ListArgs list_args(lbib_ctx* c)
     a.ny = c->p.ny;
     a.walls = c->p.bc_y == LBIB_WALLS;
     a.ntx = c->ntx;
-    a.nlty = c->nlty;
-    a.ntiles = c->nltiles;
+    a.nlty = (c->p.ny + lty - 1) / lty;
+    a.ntiles = c->ntx * a.nlty;
+    a.lty = lty;
     return a;
 }
+
+}  // namespace lbib
+
+namespace {
+
+LatticeArgs lattice_args(lbib_ctx* c) { return lattice_args_at(c, c->cur); }
+MembraneArgs membrane_args(lbib_ctx* c, int advect) { return membrane_args_at(c, c->cur, advect); }
+ListArgs list_args(lbib_ctx* c) { return list_args_h(c, LTILE_Y); }
 
 RasterArgs raster_args(lbib_ctx* c, uint16_t* ids)
 {
@@ -221,9 +235,11 @@ RasterArgs raster_args(lbib_ctx* c, uint16_t* ids)
         }                                                                                    \
     } while (0)
 
+}  // namespace
+
 // List every node in the lattice tiles its stencil can reach from its current position
 // (within the drift margin).
-lbib_status build_lists(lbib_ctx* c)
+lbib_status lbib::build_lists(lbib_ctx* c)
 {
     Timed tm(c, LBIB_K_LISTS);
     const ListArgs a = list_args(c);
@@ -231,6 +247,8 @@ lbib_status build_lists(lbib_ctx* c)
     c->steps_since_lists = 0;
     return LBIB_OK;
 }
+
+namespace {
 
 // interpolation and advection (advect = 1), forces and records of the new positions, and,
 // when a reaction reads it, the domain map
@@ -254,7 +272,9 @@ lbib_status ensure_stage(lbib_ctx* c, size_t doubles)
     return LBIB_OK;
 }
 
-lbib_status check_err_flag(lbib_ctx* c)
+}  // namespace
+
+lbib_status lbib::check_err_flag(lbib_ctx* c)
 {
     int h = 0;
     LBIB_HIP(c, hipMemcpyAsync(&h, c->d_err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -269,6 +289,8 @@ lbib_status check_err_flag(lbib_ctx* c)
     }
     return LBIB_OK;
 }
+
+namespace {
 
 void free_nodes(lbib_ctx* c)
 {
@@ -304,9 +326,9 @@ void free_all(lbib_ctx* c)
         c->f[b] = c->g[b] = nullptr;
     }
     for (int b = 0; b < 2; ++b) dev_free(c, c->inside[b], (size_t)c->ny_words());
-    dev_free(c, c->d_t_count, (size_t)c->nltiles);
-    dev_free(c, c->d_t_off, (size_t)c->nltiles + 1);
-    dev_free(c, c->d_t_cur, (size_t)c->nltiles);
+    dev_free(c, c->d_t_count, (size_t)c->tile_cap);
+    dev_free(c, c->d_t_off, (size_t)c->tile_cap + 1);
+    dev_free(c, c->d_t_cur, (size_t)c->tile_cap);
     dev_free(c, c->d_err, 1);
     dev_free(c, c->d_partial, c->partial_count * 5);
     if (c->d_stage) dev_free(c, c->d_stage, c->stage_bytes / sizeof(double));
@@ -414,6 +436,21 @@ lbib_status capture_steps(lbib_ctx* c, hipGraphExec_t* out)
     return LBIB_OK;
 }
 
+// A context adopted by a batch is stepped on the batch's stream: changes are refused, reads
+// wait for the batch's last work.
+lbib_status refuse_if_batched(lbib_ctx* c)
+{
+    if (!c->batch) return LBIB_OK;
+    c->err = "the context is stepped by a batch; destroy the batch first";
+    return LBIB_ESTATE;
+}
+
+lbib_status join_batch(lbib_ctx* c)
+{
+    if (c->batch && c->batch_done) LBIB_HIP(c, hipStreamWaitEvent(c->stream, c->batch_done, 0));
+    return LBIB_OK;
+}
+
 }  // namespace
 
 // =======================================================================================
@@ -472,6 +509,7 @@ lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out)
     c->ntx = (p->nx + TILE_X - 1) / TILE_X;
     c->nlty = (p->ny + LTILE_Y - 1) / LTILE_Y;
     c->nltiles = c->ntx * c->nlty;
+    c->tile_cap = c->ntx * ((p->ny + MIN_LTILE_Y - 1) / MIN_LTILE_Y);
     c->wpr = (p->nx + 31) / 32;
     c->partial_count = 4096;
     const size_t nn = (size_t)c->nn;
@@ -488,15 +526,15 @@ lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out)
         }
     }
     for (int b = 0; b < 2 && s == LBIB_OK; ++b) s = dev_alloc(c, &c->inside[b], (size_t)c->ny_words());
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_count, (size_t)c->nltiles);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_off, (size_t)c->nltiles + 1);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_cur, (size_t)c->nltiles);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_count, (size_t)c->tile_cap);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_off, (size_t)c->tile_cap + 1);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_cur, (size_t)c->tile_cap);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_err, 1);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_partial, c->partial_count * 5);
     if (s == LBIB_OK && (launch_fill_i32(c, (int*)c->inside[0], c->ny_words(), 0) != hipSuccess ||
                          launch_fill_i32(c, (int*)c->inside[1], c->ny_words(), 0) != hipSuccess ||
-                         launch_fill_i32(c, c->d_t_count, c->nltiles, 0) != hipSuccess ||
-                         launch_fill_i32(c, c->d_t_off, c->nltiles + 1, 0) != hipSuccess ||
+                         launch_fill_i32(c, c->d_t_count, c->tile_cap, 0) != hipSuccess ||
+                         launch_fill_i32(c, c->d_t_off, c->tile_cap + 1, 0) != hipSuccess ||
                          launch_fill_i32(c, c->d_err, 1, 0) != hipSuccess))
         s = LBIB_EDEVICE;
     if (s == LBIB_OK) s = init_fields(c, nullptr, nullptr, nullptr);
@@ -514,6 +552,14 @@ lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out)
 void lbib_destroy(lbib_ctx* c)
 {
     if (!c) return;
+    if (c->batch) {
+        // the batch can no longer step; its work on this context ends first
+        (void)hipStreamSynchronize(c->batch->stream);
+        c->batch->broken = true;
+        for (auto& q : c->batch->sims)
+            if (q == c) q = nullptr;
+        c->batch = nullptr;
+    }
     (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
@@ -526,6 +572,7 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
                            const double* rest_len, const double* rest_area)
 {
     if (!c) return LBIB_ESTATE;
+    LBIB_TRY(refuse_if_batched(c));
     std::string msg;
     if (check_cells(&c->p, n_cells, off, xy, rest_len, rest_area, msg) != LBIB_OK) {
         c->err = msg;
@@ -577,7 +624,7 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
     LBIB_HIP(c, hipMemcpyAsync(c->d_X, xy, N * sizeof(double2), hipMemcpyHostToDevice, c->stream));
     LBIB_HIP(c, hipMemcpyAsync(c->d_l0, l0.data(), N * sizeof(double), hipMemcpyHostToDevice, c->stream));
     LBIB_HIP(c, hipMemcpyAsync(c->d_A0, A0.data(), C * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    LBIB_LAUNCH(c, launch_fill_i32(c, c->d_t_count, c->nltiles, 0));
+    LBIB_LAUNCH(c, launch_fill_i32(c, c->d_t_count, c->tile_cap, 0));
     LBIB_LAUNCH(c, launch_fill_i32(c, c->d_err, 1, 0));
     if (c->mask_needed)
         for (int b = 0; b < 2; ++b) LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->inside[b], c->ny_words(), 0));
@@ -590,6 +637,7 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
 lbib_status lbib_set_fields(lbib_ctx* c, const double* rho, const double* u, const double* phi)
 {
     if (!c) return LBIB_ESTATE;
+    LBIB_TRY(refuse_if_batched(c));
     const int64_t nn = c->nn;
     for (int64_t i = 0; rho && i < nn; ++i)
         if (!std::isfinite(rho[i]) || !(rho[i] > 0.0)) {
@@ -612,6 +660,7 @@ lbib_status lbib_set_fields(lbib_ctx* c, const double* rho, const double* u, con
 lbib_status lbib_step(lbib_ctx* c, int32_t n)
 {
     if (!c) return LBIB_ESTATE;
+    LBIB_TRY(refuse_if_batched(c));
     if (n < 0) {
         c->err = "negative step count";
         return LBIB_EINVAL;
@@ -636,6 +685,7 @@ lbib_status lbib_step(lbib_ctx* c, int32_t n)
 lbib_status lbib_get_fields(lbib_ctx* c, double* rho, double* u, double* phi, double* xy, int32_t* cell_id_map)
 {
     if (!c) return LBIB_ESTATE;
+    LBIB_TRY(join_batch(c));
     const size_t nn = (size_t)c->nn;
     if (rho || u || (phi && c->S)) {
         LBIB_TRY(ensure_stage(c, nn * (size_t)(3 + c->S)));
@@ -672,6 +722,7 @@ lbib_status lbib_get_fields(lbib_ctx* c, double* rho, double* u, double* phi, do
 lbib_status lbib_get_forces(lbib_ctx* c, double* F, double* area)
 {
     if (!c) return LBIB_ESTATE;
+    LBIB_TRY(join_batch(c));
     if (!c->n_cells) return LBIB_OK;
     const size_t N = (size_t)c->n_nodes;
     if (F) {
@@ -692,6 +743,7 @@ lbib_status lbib_get_forces(lbib_ctx* c, double* F, double* area)
 lbib_status lbib_get_spread(lbib_ctx* c, double* e)
 {
     if (!c) return LBIB_ESTATE;
+    LBIB_TRY(join_batch(c));
     if (!e) return LBIB_EINVAL;
     const size_t nn = (size_t)c->nn;
     LBIB_TRY(ensure_stage(c, 2 * nn));
@@ -707,6 +759,7 @@ lbib_status lbib_get_spread(lbib_ctx* c, double* e)
 lbib_status lbib_reduce(lbib_ctx* c, double* out)
 {
     if (!c) return LBIB_ESTATE;
+    LBIB_TRY(join_batch(c));
     if (!out) return LBIB_EINVAL;
     const int nv = 3 + c->S;
     LBIB_TRY(ensure_stage(c, 8));
@@ -724,6 +777,7 @@ lbib_status lbib_reduce(lbib_ctx* c, double* out)
 lbib_status lbib_set_source_cells(lbib_ctx* c, const uint8_t* src)
 {
     if (!c) return LBIB_ESTATE;
+    LBIB_TRY(refuse_if_batched(c));
     if (c->n_cells == 0) {
         c->err = "no cells are set";
         return LBIB_ESTATE;
@@ -750,6 +804,7 @@ lbib_status lbib_ade_steady(lbib_ctx* c, double tol, int64_t max_iters, int32_t 
                             double* change)
 {
     if (!c) return LBIB_ESTATE;
+    LBIB_TRY(refuse_if_batched(c));
     if (iters) *iters = 0;
     if (change) *change = NAN;
     if (c->S == 0) {
@@ -1037,6 +1092,7 @@ out:
 lbib_status lbib_sync(lbib_ctx* c)
 {
     if (!c) return LBIB_ESTATE;
+    LBIB_TRY(join_batch(c));
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
     return LBIB_OK;
 }

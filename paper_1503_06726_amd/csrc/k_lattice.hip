@@ -204,12 +204,11 @@ __device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0
 // ly, ly + TILE_Y, ...  Order: listed nodes' records and the population loads issued; moments
 // (rho, u) of every row, u staged in LDS; listed nodes coupled (force spread into LDS, velocity
 // interpolated to the nodes); collision with the spread force and stores.
-template <int S, bool NODES, bool MASK, int ST>
-__global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
+template <int S, bool NODES, bool MASK, int ST, int RP>
+__device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int tile)
 {
-    constexpr int LY = LTILE_Y;
+    constexpr int LY = TILE_Y * RP;
     constexpr int NL = NODES ? TILE_X * LY : 1;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int tcol = tile % a.ntx, trow = tile / a.ntx;
     const int x0 = tcol * TILE_X, y0 = trow * LY;
     const int x1 = min(x0 + TILE_X, a.nx), y1 = min(y0 + LY, a.ny);
@@ -231,19 +230,19 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
         lend = a.t_off[tile + 1];
         load_candidates(a, lbeg, lend, cij, crc, cnd);
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) {
+        for (int r = 0; r < RP; ++r) {
             accx[t + r * TILE_N] = 0ull;
             accy[t + r * TILE_N] = 0ull;
         }
     }
 
-    Nbr n[RPT];
-    bool active[RPT];
-    float f[RPT][9];
-    float g[RPT][S > 0 ? S : 1][5];
-    int m[RPT];
+    Nbr n[RP];
+    bool active[RP];
+    float f[RP][9];
+    float g[RP][S > 0 ? S : 1][5];
+    int m[RP];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
+    for (int r = 0; r < RP; ++r) {
         const int y = y0 + t / TILE_X + r * TILE_Y;
         active[r] = x < a.nx && y < a.ny;
         m[r] = 0;
@@ -265,9 +264,9 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
     }
 
     // moments of every row: rho^n, u^n = sum f v / rho
-    float rho_r[RPT], drho_r[RPT], ux_r[RPT], uy_r[RPT];
+    float rho_r[RP], drho_r[RP], ux_r[RP], uy_r[RP];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
+    for (int r = 0; r < RP; ++r) {
         const float* fr = f[r];
         drho_r[r] = ((fr[0] + fr[1]) + (fr[2] + fr[3])) + ((fr[4] + fr[5]) + (fr[6] + fr[7])) + fr[8];
         rho_r[r] = a.rho0 + drho_r[r];
@@ -301,7 +300,7 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
     }
 
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
+    for (int r = 0; r < RP; ++r) {
         if (!active[r]) continue;
         const int64_t o = n[r].rc + x;
         float ex = a.bodyx, ey = a.bodyy;
@@ -376,6 +375,24 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
         for (int u = 0; u < SPREAD_UNROLL; ++u)
             if (cnd[u] != -1) a.part[share_slot(a, cnd[u])] = Ud[u];
     }
+}
+
+template <int S, bool NODES, bool MASK, int ST>
+__global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
+{
+    lattice_tile<S, NODES, MASK, ST, RPT>(a, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// Batched form: every workgroup takes one (simulation, tile) work item; the simulation's
+// arguments come from a device table (independent lattices of any sizes in one launch), and
+// the tile height TILE_Y RP is a parameter of the launch.
+template <int S, bool NODES, bool MASK, int ST, int RP>
+__global__ __launch_bounds__(TILE_N) void k_lattice_batch(const LatticeArgs* __restrict__ tab,
+                                                          const int2* __restrict__ work)
+{
+    const int2 wk = work[xcd_remap(blockIdx.x, gridDim.x)];
+    const LatticeArgs a = tab[wk.x];
+    lattice_tile<S, NODES, MASK, ST, RP>(a, wk.y);
 }
 
 // The spread force field alone (inspection): same tiling and summation as k_lattice.
@@ -599,6 +616,46 @@ hipError_t launch_lattice(lbib_ctx* c, const LatticeArgs& a, bool nodes, bool ma
     case LBIB_STORAGE_BF16: return launch_lattice_st<2>(c, a, nodes, mask);
     default: return launch_lattice_st<0>(c, a, nodes, mask);
     }
+}
+
+template <int S, int ST, int RP>
+static hipError_t launch_lattice_batch_r(const LatticeArgs* tab, const int2* work, int nwork, bool mask,
+                                         hipStream_t stream)
+{
+    dim3 grid((unsigned)nwork), block(TILE_N);
+    if (mask) hipLaunchKernelGGL((k_lattice_batch<S, true, true, ST, RP>), grid, block, 0, stream, tab, work);
+    else hipLaunchKernelGGL((k_lattice_batch<S, true, false, ST, RP>), grid, block, 0, stream, tab, work);
+    return hipGetLastError();
+}
+
+template <int S, int ST>
+static hipError_t launch_lattice_batch_s(const LatticeArgs* tab, const int2* work, int nwork, int rows, bool mask,
+                                         hipStream_t stream)
+{
+    if (rows == 1) return launch_lattice_batch_r<S, ST, 1>(tab, work, nwork, mask, stream);
+    if (rows == 4) return launch_lattice_batch_r<S, ST, 4>(tab, work, nwork, mask, stream);
+    return launch_lattice_batch_r<S, ST, 2>(tab, work, nwork, mask, stream);
+}
+
+hipError_t launch_lattice_batch(const LatticeArgs* tab, const int2* work, int nwork, int S, int storage, int rows,
+                                bool mask, hipStream_t stream)
+{
+    if (nwork <= 0) return hipSuccess;
+#define LB(SS, TT) return launch_lattice_batch_s<SS, TT>(tab, work, nwork, rows, mask, stream)
+    if (storage == LBIB_STORAGE_FP16) {
+        if (S == 0) LB(0, 1);
+        if (S == 1) LB(1, 1);
+        LB(2, 1);
+    }
+    if (storage == LBIB_STORAGE_BF16) {
+        if (S == 0) LB(0, 2);
+        if (S == 1) LB(1, 2);
+        LB(2, 2);
+    }
+    if (S == 0) LB(0, 0);
+    if (S == 1) LB(1, 0);
+    LB(2, 0);
+#undef LB
 }
 
 hipError_t launch_spread_inspect(lbib_ctx* c, const LatticeArgs& a)

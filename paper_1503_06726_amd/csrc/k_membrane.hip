@@ -14,6 +14,8 @@
 //   4. when a reaction reads it, ORs the cell's interior into the inside-any-cell bit map
 //      (rasterised from the LDS positions).
 // k_list_count / k_list_scan / k_list_fill rebuild the per-tile node lists (every few steps).
+// The *_batch forms run the same per-cell, per-node and per-simulation work for many
+// independent simulations in one launch, each work item naming its simulation's arguments.
 #include "lbib_internal.h"
 #include "lbib_raster.h"
 
@@ -81,12 +83,11 @@ __device__ inline void block_reduce5(double& sum, double m[4], double* red)
     for (int q = 0; q < 4; ++q) m[q] = uniform(m[q]);
 }
 
-__global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
+// One cell per workgroup: xs holds the cell's positions (dynamic LDS), red the reduction
+// slots, bm the raster bitmap.
+__device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c, double2* xs, double* red,
+                                              unsigned* bm)
 {
-    extern __shared__ double2 xs[];
-    __shared__ double red[5 * (MEMBRANE_THREADS / 64)];
-    __shared__ unsigned bm[RASTER_WORDS_FUSED];
-    const int c = blockIdx.x;
     const int t = threadIdx.x;
     const int beg = a.off[c];
     const int n = a.off[c + 1] - beg;
@@ -216,6 +217,27 @@ __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
     }
 }
 
+__global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
+{
+    extern __shared__ double2 xs[];
+    __shared__ double red[5 * (MEMBRANE_THREADS / 64)];
+    __shared__ unsigned bm[RASTER_WORDS_FUSED];
+    membrane_cell(a, blockIdx.x, xs, red, bm);
+}
+
+// Batched form: one (simulation, cell) work item per workgroup, the simulation's arguments
+// from a device table.
+__global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane_batch(const MembraneArgs* __restrict__ tab,
+                                                                     const int2* __restrict__ work)
+{
+    extern __shared__ double2 xs[];
+    __shared__ double red[5 * (MEMBRANE_THREADS / 64)];
+    __shared__ unsigned bm[RASTER_WORDS_FUSED];
+    const int2 wk = work[blockIdx.x];
+    const MembraneArgs a = tab[wk.x];
+    membrane_cell(a, wk.y, xs, red, bm);
+}
+
 // ---------------------------------------------------------------------------------------
 // per-tile node lists
 // ---------------------------------------------------------------------------------------
@@ -224,8 +246,10 @@ __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
 // columns i0 - M .. i0 + 3 + M and rows j0 - M .. j0 + 3 + M (M = LIST_MARGIN; columns cyclic,
 // rows cyclic or, next to walls, only those inside the lattice), each once.  Eight
 // consecutive columns touch at most three tile columns (the last tile may be narrow and the
-// range may wrap), and likewise for rows.  Tiles come out row by row in ascending order of
-// the range, so the list build is a pure function of the origin.
+// range may wrap), and so do eight rows for tiles of at least 8 rows, or of 4 rows when the
+// rows do not wrap onto a narrow last tile (walls, or ny a multiple of 4; the host admits no
+// other tile height).  Tiles come out row by row in ascending order of the range, so the list
+// build is a pure function of the origin and the tile shape.
 __device__ inline int node_tiles(int i0, int j0, const ListArgs& a, int tiles[MAX_NODE_TILES])
 {
     constexpr int M = LIST_MARGIN;
@@ -245,7 +269,7 @@ __device__ inline int node_tiles(int i0, int j0, const ListArgs& a, int tiles[MA
         } else {
             j = wrap_i(j, a.ny);
         }
-        const int rr = j / LTILE_Y;
+        const int rr = j / a.lty;
         bool seen = false;
         for (int k = 0; k < nr; ++k) seen = seen || rows[k] == rr;
         if (!seen && nr < 3) rows[nr++] = rr;
@@ -281,10 +305,10 @@ __device__ inline int wave_claim(int* counter, int key, bool live)
     return pos;
 }
 
-// stencil origin of every node at this build, and the length of every tile's list
-__global__ void k_list_count(ListArgs a)
+// stencil origin of every node at this build, and the length of every tile's list (node l
+// of a block whose wavefronts all take part)
+__device__ __forceinline__ void list_count_node(const ListArgs& a, const int64_t l)
 {
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = l < a.n;
     int tiles[MAX_NODE_TILES];
     int nt = 0;
@@ -306,14 +330,25 @@ __global__ void k_list_count(ListArgs a)
     }
 }
 
+__global__ void k_list_count(ListArgs a)
+{
+    list_count_node(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// batched: work items (simulation, block of LIST_THREADS nodes)
+__global__ __launch_bounds__(LIST_THREADS) void k_list_count_batch(const ListArgs* __restrict__ tab,
+                                                                   const int2* __restrict__ work)
+{
+    const int2 wk = work[blockIdx.x];
+    const ListArgs a = tab[wk.x];
+    list_count_node(a, (int64_t)wk.y * LIST_THREADS + threadIdx.x);
+}
+
 // exclusive scan of the list lengths into offsets (and fill cursors); counts are cleared for
-// the next build
-__global__ __launch_bounds__(SCAN_THREADS) void k_list_scan(ListArgs a)
+// the next build (one workgroup per simulation)
+__device__ __forceinline__ void list_scan(const ListArgs& a, int* buf, int* wsum, int& carry_sh)
 {
     constexpr int CHUNK = SCAN_THREADS * SCAN_PER_THREAD;
-    __shared__ int buf[CHUNK];
-    __shared__ int wsum[SCAN_THREADS / 64];
-    __shared__ int carry_sh;
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     if (t == 0) carry_sh = 0;
     for (int base = 0; base < a.ntiles; base += CHUNK) {
@@ -359,12 +394,28 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_list_scan(ListArgs a)
     if (t == 0) a.off[a.ntiles] = carry_sh;
 }
 
+__global__ __launch_bounds__(SCAN_THREADS) void k_list_scan(ListArgs a)
+{
+    __shared__ int buf[SCAN_THREADS * SCAN_PER_THREAD];
+    __shared__ int wsum[SCAN_THREADS / 64];
+    __shared__ int carry_sh;
+    list_scan(a, buf, wsum, carry_sh);
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_list_scan_batch(const ListArgs* __restrict__ tab)
+{
+    __shared__ int buf[SCAN_THREADS * SCAN_PER_THREAD];
+    __shared__ int wsum[SCAN_THREADS / 64];
+    __shared__ int carry_sh;
+    const ListArgs a = tab[blockIdx.x];
+    list_scan(a, buf, wsum, carry_sh);
+}
+
 // every node enters the lists of its tiles, each entry naming the node and the rank of the
 // tile among the node's tiles (order within a list is immaterial: the lattice pass sums
 // forces in fixed point, and each velocity share goes to its own [rank][node] slot)
-__global__ void k_list_fill(ListArgs a)
+__device__ __forceinline__ void list_fill_node(const ListArgs& a, const int64_t l)
 {
-    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = l < a.n;
     int tiles[MAX_NODE_TILES];
     int nt = 0;
@@ -382,6 +433,19 @@ __global__ void k_list_fill(ListArgs a)
         const int p = wave_claim<true>(a.cursor, on ? tiles[k] : 0, on);
         if (on) a.list[p] = (int)(((unsigned)l << 4) | (unsigned)k);
     }
+}
+
+__global__ void k_list_fill(ListArgs a)
+{
+    list_fill_node(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(LIST_THREADS) void k_list_fill_batch(const ListArgs* __restrict__ tab,
+                                                                  const int2* __restrict__ work)
+{
+    const int2 wk = work[blockIdx.x];
+    const ListArgs a = tab[wk.x];
+    list_fill_node(a, (int64_t)wk.y * LIST_THREADS + threadIdx.x);
 }
 
 // forces of every node, read back from the records (inspection)
@@ -420,10 +484,31 @@ hipError_t launch_membrane(lbib_ctx* c, const MembraneArgs& a)
 
 hipError_t launch_lists(lbib_ctx* c, const ListArgs& a, int which)
 {
-    const unsigned nb = (unsigned)((a.n + 255) / 256);
-    if (which == 0) hipLaunchKernelGGL(k_list_count, dim3(nb), dim3(256), 0, c->stream, a);
+    const unsigned nb = (unsigned)((a.n + LIST_THREADS - 1) / LIST_THREADS);
+    if (which == 0) hipLaunchKernelGGL(k_list_count, dim3(nb), dim3(LIST_THREADS), 0, c->stream, a);
     else if (which == 1) hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(SCAN_THREADS), 0, c->stream, a);
-    else hipLaunchKernelGGL(k_list_fill, dim3(nb), dim3(256), 0, c->stream, a);
+    else hipLaunchKernelGGL(k_list_fill, dim3(nb), dim3(LIST_THREADS), 0, c->stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_membrane_batch(const MembraneArgs* tab, const int2* work, int nwork, int max_cell_nodes,
+                                 hipStream_t stream)
+{
+    if (nwork <= 0) return hipSuccess;
+    const size_t lds = sizeof(double2) * (size_t)(max_cell_nodes > 0 ? max_cell_nodes : 1);
+    hipLaunchKernelGGL(k_membrane_batch, dim3((unsigned)nwork), dim3(MEMBRANE_THREADS), lds, stream, tab, work);
+    return hipGetLastError();
+}
+
+hipError_t launch_lists_batch(const ListArgs* tab, const int2* work, int nwork, int nsims, int which,
+                              hipStream_t stream)
+{
+    if (which == 1) {
+        if (nsims > 0) hipLaunchKernelGGL(k_list_scan_batch, dim3((unsigned)nsims), dim3(SCAN_THREADS), 0, stream, tab);
+    } else if (nwork > 0) {
+        if (which == 0) hipLaunchKernelGGL(k_list_count_batch, dim3((unsigned)nwork), dim3(LIST_THREADS), 0, stream, tab, work);
+        else hipLaunchKernelGGL(k_list_fill_batch, dim3((unsigned)nwork), dim3(LIST_THREADS), 0, stream, tab, work);
+    }
     return hipGetLastError();
 }
 

@@ -25,8 +25,9 @@ namespace lbib {
 constexpr int TILE_X = 64;
 constexpr int TILE_Y = 4;
 constexpr int TILE_N = TILE_X * TILE_Y;
-constexpr int RPT = 2;
+constexpr int RPT = 2;                // rows per thread of a single simulation's pass
 constexpr int LTILE_Y = TILE_Y * RPT;
+constexpr int MIN_LTILE_Y = TILE_Y;   // the shortest tile (one row per thread) sizes the tile arrays
 
 constexpr int LIST_MARGIN = 2;       // lattice units a node may drift between list rebuilds
 constexpr int LIST_PERIOD = 16;      // steps between list rebuilds (nodes may move 2/16 lu per step)
@@ -39,6 +40,7 @@ constexpr int RASTER_THREADS = 256;
 constexpr int RASTER_WORDS_FUSED = 1024;        // 4 KB bitmap inside the membrane kernel
 constexpr int RASTER_WORDS = 8192;              // 32 KB bitmap in the standalone rasteriser
 constexpr int SCAN_THREADS = 1024;
+constexpr int LIST_THREADS = 256;             // nodes per workgroup of the list build
 constexpr int SCAN_PER_THREAD = 8;
 
 // Spread forces are summed in 64-bit fixed point (integer addition is associative, so the
@@ -111,6 +113,7 @@ struct ListArgs {
     uint8_t* __restrict__ cnt;         // [N] tiles the node is listed in
     int64_t n;
     int nx, ny, walls, ntx, nlty, ntiles;
+    int lty;                           // rows per lattice tile (TILE_Y times the rows per thread)
 };
 
 // ADE-only iteration (species with u = 0, fluid and membranes frozen) in a working set of

@@ -24,6 +24,8 @@ struct TimedLaunch {
 
 }  // namespace lbib
 
+struct lbib_batch;
+
 struct lbib_ctx {
     lbib_params p{};
     int device = 0;
@@ -34,6 +36,7 @@ struct lbib_ctx {
     int64_t nn = 0;          // nx * ny
     int S = 0;               // species
     int ntx = 0, nlty = 0, nltiles = 0;   // lattice tiles (TILE_X x LTILE_Y): columns, rows, total
+    int tile_cap = 0;                     // tiles of the shortest tile shape (sizes the tile arrays)
     bool mask_needed = false;
 
     // lattice state: post-collision deviations (FP32, FP16 or BF16), A/B buffers
@@ -60,9 +63,9 @@ struct lbib_ctx {
     float4* d_rec = nullptr;         // [N] spreading records (fractional offset, force)
     int* d_rec_ij = nullptr;         // [N] current stencil origins
     int* d_list = nullptr;           // [N * MAX_NODE_TILES] per-tile node lists
-    int* d_t_count = nullptr;        // [nltiles], zero between list builds
-    int* d_t_off = nullptr;          // [nltiles + 1]
-    int* d_t_cur = nullptr;          // [nltiles] fill cursors
+    int* d_t_count = nullptr;        // [tile_cap], zero between list builds
+    int* d_t_off = nullptr;          // [tile_cap + 1]
+    int* d_t_cur = nullptr;          // [tile_cap] fill cursors
     int* d_err = nullptr;            // device error flags
     uint8_t* d_src = nullptr;        // [n_cells] source cells of the source/decay law (NULL: all)
     int steps_since_lists = 0;
@@ -80,6 +83,11 @@ struct lbib_ctx {
     bool use_graphs = true;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     hipStream_t capture_stream = nullptr;
+
+    // a batch that has adopted this context steps it on the batch's stream; reads wait for
+    // the batch's last work (done), changes are refused until the batch releases it
+    lbib_batch* batch = nullptr;
+    hipEvent_t batch_done = nullptr;
 
     // timing
     bool timing = false;
@@ -100,6 +108,13 @@ hipError_t launch_moments(lbib_ctx* c, double* out);
 hipError_t launch_reduce(lbib_ctx* c, double* out_dev);
 hipError_t launch_membrane(lbib_ctx* c, const MembraneArgs& a);
 hipError_t launch_lists(lbib_ctx* c, const ListArgs& a, int which);   // 0 count, 1 scan, 2 fill
+// batched forms: one launch over (simulation, work unit) items named by device tables
+hipError_t launch_lattice_batch(const LatticeArgs* tab, const int2* work, int nwork, int S, int storage, int rows,
+                                bool mask, hipStream_t stream);
+hipError_t launch_membrane_batch(const MembraneArgs* tab, const int2* work, int nwork, int max_cell_nodes,
+                                 hipStream_t stream);
+hipError_t launch_lists_batch(const ListArgs* tab, const int2* work, int nwork, int nsims, int which,
+                              hipStream_t stream);
 hipError_t launch_forces_out(lbib_ctx* c, float2* F);
 hipError_t launch_raster(lbib_ctx* c, const RasterArgs& a);
 hipError_t launch_fill_i32(lbib_ctx* c, int* p, int64_t n, int v);
@@ -119,3 +134,45 @@ hipError_t ade_batch_phi_launch(const void* g, double* phi, int64_t nn, int nx, 
                                 hipStream_t s);
 
 }  // namespace lbib
+
+namespace lbib {
+
+// kernel arguments of a context at a given buffer parity / tile height (api.hip)
+LatticeArgs lattice_args_at(lbib_ctx* c, int cur);
+MembraneArgs membrane_args_at(lbib_ctx* c, int cur, int advect);
+ListArgs list_args_h(lbib_ctx* c, int lty);
+lbib_status build_lists(lbib_ctx* c);
+lbib_status check_err_flag(lbib_ctx* c);
+
+}  // namespace lbib
+
+// Many contexts stepped together (batch.hip): each launch of the step covers every adopted
+// simulation, with per-simulation arguments in device tables (one per buffer parity).
+struct lbib_batch {
+    std::vector<lbib_ctx*> sims;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipEvent_t done = nullptr;
+    std::string err;
+    bool broken = false;             // an adopted context was destroyed
+
+    int S = 0, storage = 0;
+    bool mask = false;
+    int lty = 0;                     // lattice tile height (rows) of the batched pass
+    int max_cell_nodes = 0;
+    int since = 0;                   // steps since the last list build
+    int par = 0;                     // parity of the steps taken (buffer parity relative to cur0)
+    std::vector<int> cur0;
+
+    lbib::LatticeArgs* d_lat[2] = {nullptr, nullptr};    // [sims] per parity
+    lbib::MembraneArgs* d_mem[2] = {nullptr, nullptr};
+    lbib::ListArgs* d_list = nullptr;
+    int2* d_lat_work = nullptr;      // (simulation, tile)
+    int2* d_mem_work = nullptr;      // (simulation, cell)
+    int2* d_node_work = nullptr;     // (simulation, block of LIST_THREADS nodes)
+    int n_lat_work = 0, n_mem_work = 0, n_node_work = 0;
+    int64_t updates_per_step = 0;    // lattice nodes of all simulations
+
+    hipGraphExec_t graph = nullptr;  // LIST_PERIOD steps from an aligned state
+    hipStream_t capture_stream = nullptr;
+};

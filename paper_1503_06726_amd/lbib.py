@@ -29,7 +29,9 @@ EXPORTS = ["lbib_validate_params", "lbib_validate_cells", "lbib_create", "lbib_s
            "lbib_last_error", "lbib_status_string", "lbib_version", "lbib_destroy",
            "lbib_set_source_cells", "lbib_ade_steady", "lbib_ade_batch",
            "lbib_net_create", "lbib_net_param_count", "lbib_net_set_params", "lbib_net_get_params",
-           "lbib_net_predict", "lbib_net_loss_grad", "lbib_net_train_step", "lbib_net_destroy"]
+           "lbib_net_predict", "lbib_net_loss_grad", "lbib_net_train_step", "lbib_net_destroy",
+           "lbib_batch_create", "lbib_batch_step", "lbib_batch_sync", "lbib_batch_get_tile",
+           "lbib_batch_set_tile", "lbib_batch_autotune", "lbib_batch_last_error", "lbib_batch_destroy"]
 
 
 class Species(C.Structure):
@@ -130,6 +132,22 @@ def lib():
     L.lbib_ade_steady.restype = st
     L.lbib_ade_steady.argtypes = [vp, C.c_double, C.c_int64, C.c_int32, C.POINTER(C.c_int64),
                                   C.POINTER(C.c_double)]
+    L.lbib_batch_create.restype = st
+    L.lbib_batch_create.argtypes = [C.POINTER(C.c_void_p), C.c_int32, vp, C.POINTER(C.c_void_p)]
+    L.lbib_batch_step.restype = st
+    L.lbib_batch_step.argtypes = [vp, C.c_int32]
+    L.lbib_batch_sync.restype = st
+    L.lbib_batch_sync.argtypes = [vp]
+    L.lbib_batch_get_tile.restype = st
+    L.lbib_batch_get_tile.argtypes = [vp, C.POINTER(C.c_int32)]
+    L.lbib_batch_set_tile.restype = st
+    L.lbib_batch_set_tile.argtypes = [vp, C.c_int32]
+    L.lbib_batch_autotune.restype = st
+    L.lbib_batch_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), vp]
+    L.lbib_batch_last_error.restype = C.c_char_p
+    L.lbib_batch_last_error.argtypes = [vp]
+    L.lbib_batch_destroy.restype = None
+    L.lbib_batch_destroy.argtypes = [vp]
     _lib = L
     return L
 
@@ -320,6 +338,65 @@ def ade_batch(nx: int, ny: int, bc_y: int, source, D, sigma, decay, phi0=None, t
     if s != OK:
         raise LbibError(s, "lbib_ade_batch")
     return its, phi
+
+
+class Batch:
+    """Many Simulations stepped together (lbib_batch_*).  The batch holds references to its
+    simulations, which stay usable for reads; ``close`` releases them."""
+
+    def __init__(self, sims, stream: int | None = None):
+        self.L = lib()
+        self.h = None
+        self.sims = list(sims)
+        arr = (C.c_void_p * len(self.sims))(*[s.h.value for s in self.sims])
+        hh = C.c_void_p()
+        s = self.L.lbib_batch_create(arr, len(self.sims), C.c_void_p(stream) if stream else None, C.byref(hh))
+        if s != OK:
+            msgs = [(self.L.lbib_last_error(x.h) or b"").decode() for x in self.sims if x.h]
+            raise LbibError(s, "lbib_batch_create", next((m for m in msgs if m), ""))
+        self.h = hh
+        self.updates_per_step = sum(x.nx * x.ny for x in self.sims)
+
+    def close(self):
+        if self.h:
+            self.L.lbib_batch_destroy(self.h)
+            self.h = None
+        self.sims = []
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, s, where):
+        if s != OK:
+            raise LbibError(s, where, (self.L.lbib_batch_last_error(self.h) or b"").decode())
+
+    def step(self, n: int = 1):
+        self._check(self.L.lbib_batch_step(self.h, int(n)), "lbib_batch_step")
+
+    def sync(self):
+        self._check(self.L.lbib_batch_sync(self.h), "lbib_batch_sync")
+
+    @property
+    def tile(self) -> int:
+        r = C.c_int32(0)
+        self._check(self.L.lbib_batch_get_tile(self.h, C.byref(r)), "lbib_batch_get_tile")
+        return int(r.value)
+
+    def set_tile(self, rows: int):
+        self._check(self.L.lbib_batch_set_tile(self.h, int(rows)), "lbib_batch_set_tile")
+
+    def autotune(self, periods: int = 2):
+        """(chosen tile height, {height: ms per step} of the admissible heights)."""
+        r = C.c_int32(0)
+        ms = np.zeros(3)
+        self._check(self.L.lbib_batch_autotune(self.h, int(periods), C.byref(r), _p(ms)), "lbib_batch_autotune")
+        return int(r.value), {h: float(v) for h, v in zip((4, 8, 16), ms) if v >= 0}
 
 
 class Net:

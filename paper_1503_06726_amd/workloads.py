@@ -334,6 +334,40 @@ def static_tissue(sample: int, held_out: bool = True, n: int = 256, source_p: fl
     return w
 
 
+def sweep_member(sim: int, steps: int = 2000, side_lo: float = 128.0, side_hi: float = 1024.0) -> Workload:
+    """Simulation ``sim`` of the batched parameter sweep: nx and ny each drawn log-uniformly
+    from [side_lo, side_hi] (rounded), walls in y and periodic in x, min(max(U{10..500},
+    ceil(8 max(nx, ny) / min(nx, ny))), floor(nx ny / 100)) Voronoi cells at 0.5 lu node
+    spacing (seeds redrawn while a cell would span the lattice), tau ~ U(0.55, 1.2), spring
+    stiffness k ~ U(0.005, 0.05) at the initial lengths, body acceleration 1e-6 along x, and
+    one species with the tiny workload's source/decay law (D = 0.1, source 1e-3 inside cells,
+    decay 1e-4)."""
+    rng = _rng(4, sim)
+    lo, hi = math.log(side_lo), math.log(side_hi)
+    nx = int(round(math.exp(rng.uniform(lo, hi))))
+    ny = int(round(math.exp(rng.uniform(lo, hi))))
+    # at least ~8 cells across the longer side keeps every cell narrower than the lattice
+    n_min = math.ceil(8.0 * max(nx, ny) / min(nx, ny))
+    n_cells = min(max(int(rng.integers(10, 501)), n_min), nx * ny // 100)
+    tau = float(rng.uniform(0.55, 1.2))
+    k = float(rng.uniform(0.005, 0.05))
+    while True:                     # redraw the seeds while a cell spans the lattice
+        offsets, xy = voronoi_tissue(nx, ny, n_cells, rng)
+        span = max(max(np.ptp(xy[a:b, 0]) - nx, np.ptp(xy[a:b, 1]) - ny)
+                   for a, b in zip(offsets[:-1], offsets[1:]))
+        if span < -4.0:
+            break
+    w = Workload(name=f"sweep {sim}: {nx}x{ny} walls-y, {n_cells} cells, tau {tau:.3f}, k {k:.4f}",
+                 nx=nx, ny=ny, bc_y=WALLS, tau=tau, rho0=1.0, body_accel=(1e-6, 0.0),
+                 k_spring=k, delta_kernel=DELTA_COS4,
+                 species=[Species(D=0.1, phi_ref=0.0, reaction=REACT_SOURCE_DECAY,
+                                  c=(1e-3, 1e-4, 0.0, 0.0))],
+                 steps=steps)
+    return _attach_geometry(w, offsets, xy)
+
+
+SWEEP_SIMS = 64
+
 WORKLOADS = {"tiny": tiny_cell, "tissue": tissue, "large": large}
 
 # parity-sized cell cases: ragged lattices, both boundary kinds, both kernels, every force law

@@ -1,0 +1,206 @@
+"""Batched stepping (lbib_batch_*) through the C ABI.
+
+Bars:
+  * at the default tile height a batched simulation is bit-identical to the same simulation
+    stepped alone (same kernels' arithmetic; list order is immaterial), across graph periods,
+    odd step counts and the release of the batch;
+  * another tile height changes only the grouping of the interpolation sums: every field
+    within 1e-6 relative L2 of the simulation stepped alone;
+  * the autotuner leaves every simulation's state bit-for-bit as it found it;
+  * a batched simulation at a non-default tile height matches the FP64 oracle within the
+    parity bar (1e-5 relative L2).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1503_06726_amd import lbib
+from paper_1503_06726_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0)
+
+
+def small_sweep(n=6, periodic_ny=98):
+    """Uneven little lattices of the sweep recipe plus one periodic-y tissue (ny = 98 rules out
+    tiles of 4 rows, ny = 96 admits them)."""
+    ws = [W.sweep_member(i, side_lo=64.0, side_hi=190.0) for i in range(n - 1)]
+    ws.append(W.small_tissue(nx=150, ny=periodic_ny, n_cells=10, bc_y=W.PERIODIC, n_species=1, seed=3))
+    return ws
+
+
+def make(ws):
+    return [lbib.from_workload(w) for w in ws]
+
+
+def fields(sims):
+    return [s.get_fields() for s in sims]
+
+
+def assert_bit_equal(FA, FB, what):
+    for i, (a, b) in enumerate(zip(FA, FB)):
+        for k in ("rho", "u", "phi", "xy", "mask"):
+            assert np.array_equal(a[k], b[k]), f"{what}: simulation {i}, field {k} differs"
+
+
+def close_all(*groups):
+    for g in groups:
+        for s in g:
+            s.close()
+
+
+def test_batched_bit_identical_to_alone():
+    ws = small_sweep()
+    say("sizes:", [(w.nx, w.ny, w.n_cells) for w in ws])
+    A, B = make(ws), make(ws)
+    batch = lbib.Batch(B)
+    assert batch.tile == 8
+    for n in (40, 13, 16):          # two graph periods + 8 direct steps, an odd count, one more period
+        for s in A:
+            s.step(n)
+        batch.step(n)
+        batch.sync()
+        assert_bit_equal(fields(A), fields(B), f"after {n} more steps")
+        say(f"  +{n} steps: bit-identical")
+    batch.close()
+    for s in A + B:
+        s.step(7)
+    assert_bit_equal(fields(A), fields(B), "after the release")
+    close_all(A, B)
+
+
+@pytest.mark.parametrize("rows", [4, 16])
+def test_other_tile_heights_round_off_only(rows):
+    ws = small_sweep(periodic_ny=96)
+    A, B = make(ws), make(ws)
+    batch = lbib.Batch(B)
+    batch.set_tile(rows)
+    assert batch.tile == rows
+    for s in A:
+        s.step(48)
+    batch.step(48)
+    batch.sync()
+    worst = 0.0
+    for i, (a, b) in enumerate(zip(fields(A), fields(B))):
+        for k in ("rho", "u", "phi", "xy"):
+            e = rel(b[k], a[k])
+            worst = max(worst, e)
+            assert e <= 1e-6, (rows, i, k, e)
+    say(f"  tile height {rows}: worst rel-L2 {worst:.2e}")
+    batch.close()
+    # released contexts step on alone with their own lists
+    for s in A + B:
+        s.step(5)
+    for a, b in zip(fields(A), fields(B)):
+        assert rel(b["u"], a["u"]) <= 1e-6
+    close_all(A, B)
+
+
+def test_autotune_restores_state_and_keeps_parity():
+    ws = small_sweep()
+    A, B = make(ws), make(ws)
+    batch = lbib.Batch(B)
+    batch.step(16)
+    for s in A:
+        s.step(16)
+    before = fields(B)
+    rows, ms = batch.autotune(periods=1)
+    say(f"  autotune: {rows} rows; ms per step {ms}")
+    assert rows in ms and set(ms) <= {4, 8, 16} and 8 in ms and 16 in ms
+    assert 4 not in ms                                 # the periodic member has ny = 98
+    assert_bit_equal(before, fields(B), "after autotuning")
+    batch.step(32)
+    for s in A:
+        s.step(32)
+    batch.sync()
+    for a, b in zip(fields(A), fields(B)):
+        for k in ("rho", "u", "phi", "xy"):
+            assert rel(b[k], a[k]) <= 1e-6
+    batch.close()
+    close_all(A, B)
+
+
+def test_batched_matches_oracle():
+    w = W.sweep_member(3, steps=60, side_lo=64.0, side_hi=130.0)
+    others = [W.sweep_member(i, side_lo=64.0, side_hi=130.0) for i in (5, 9)]
+    say(f"case {w.name}: 60 steps batched at tile height 16, and the oracle")
+    sims = make([w] + others)
+    batch = lbib.Batch(sims)
+    batch.set_tile(16)
+    batch.step(60)
+    batch.sync()
+    G = sims[0].get_fields()
+    o = O.from_workload(w)
+    o.step(60)
+    R = o.get_fields()
+    out = {k: rel(G[k], R[k]) for k in ("rho", "u", "phi", "xy")}
+    say("  rel-L2:", {k: f"{v:.2e}" for k, v in out.items()})
+    for k, v in out.items():
+        assert v <= 1e-5, (k, v)
+    batch.close()
+    close_all(sims)
+
+
+def test_batch_errors():
+    ws = small_sweep(3)
+    A = make(ws)
+    with pytest.raises(lbib.LbibError):
+        lbib.Batch([A[0], A[0]])                      # repeated
+    empty = lbib.Simulation(ws[0].params_dict())
+    with pytest.raises(lbib.LbibError):
+        lbib.Batch([A[0], empty])                     # no cells
+    two = lbib.from_workload(W.small_tissue(nx=96, ny=70, n_cells=4, n_species=2, seed=1))
+    with pytest.raises(lbib.LbibError):
+        lbib.Batch([A[0], two])                       # species counts differ
+    batch = lbib.Batch(A)
+    with pytest.raises(lbib.LbibError):
+        lbib.Batch([A[1]])                            # already adopted
+    with pytest.raises(lbib.LbibError) as e:
+        A[0].step(1)                                  # stepped by the batch
+    assert e.value.status == lbib.ESTATE
+    with pytest.raises(lbib.LbibError):
+        batch.set_tile(5)
+    batch.step(3)
+    with pytest.raises(lbib.LbibError) as e:
+        batch.set_tile(16)                            # between list periods
+    assert e.value.status == lbib.ESTATE
+    with pytest.raises(lbib.LbibError):
+        batch.autotune(1)
+    A[2].close()                                      # the batch can no longer step
+    with pytest.raises(lbib.LbibError) as e:
+        batch.step(1)
+    assert e.value.status == lbib.ESTATE
+    batch.close()
+    A[0].step(2)                                      # released
+    close_all(A, [empty, two])
+
+
+def test_full_sweep_sampled_members_bit_identical():
+    """The 64-simulation sweep at its real sizes: three members stepped alone match their
+    batched selves bit for bit over two list periods."""
+    ws = [W.sweep_member(i) for i in range(W.SWEEP_SIMS)]
+    say(f"sweep: {sum(w.nx * w.ny for w in ws)} lattice nodes, {sum(w.n_nodes for w in ws)} membrane nodes")
+    B = make(ws)
+    batch = lbib.Batch(B)
+    batch.step(32)
+    batch.sync()
+    for i in (0, 31, 63):
+        a = lbib.from_workload(ws[i])
+        a.step(32)
+        FA, FB = a.get_fields(), B[i].get_fields()
+        for k in ("rho", "u", "phi", "xy", "mask"):
+            assert np.array_equal(FA[k], FB[k]), (i, k)
+        a.close()
+        say(f"  member {i} ({ws[i].nx}x{ws[i].ny}, {ws[i].n_cells} cells): bit-identical")
+    batch.close()
+    close_all(B)
