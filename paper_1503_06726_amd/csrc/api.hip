@@ -121,6 +121,9 @@ LatticeArgs lattice_args_at(lbib_ctx* c, int cur)
     a.gsrc = c->g[cur];
     a.gdst = c->g[1 - cur];
     a.nn = c->nn;
+    a.frow = c->frow();
+    a.grow = c->grow();
+    a.gchunk = c->gchunk();
     a.nx = p.nx;
     a.ny = p.ny;
     a.walls = p.bc_y == LBIB_WALLS;
@@ -321,8 +324,8 @@ void free_all(lbib_ctx* c)
     for (int b = 0; b < 2; ++b) {
         char* fb = (char*)c->f[b];
         char* gb = (char*)c->g[b];
-        dev_free(c, fb, 9 * nn * c->pop_bytes);
-        dev_free(c, gb, 5 * (size_t)c->S * nn * c->pop_bytes);
+        dev_free(c, fb, c->f_elems() * c->pop_bytes);
+        dev_free(c, gb, c->g_elems() * c->pop_bytes);
         c->f[b] = c->g[b] = nullptr;
     }
     for (int b = 0; b < 2; ++b) dev_free(c, c->inside[b], (size_t)c->ny_words());
@@ -518,10 +521,10 @@ lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out)
     for (int b = 0; b < 2 && s == LBIB_OK; ++b) {
         char* fb = nullptr;
         char* gb = nullptr;
-        s = dev_alloc(c, &fb, 9 * nn * c->pop_bytes);
+        s = dev_alloc(c, &fb, c->f_elems() * c->pop_bytes);
         c->f[b] = fb;
         if (s == LBIB_OK && c->S) {
-            s = dev_alloc(c, &gb, 5 * (size_t)c->S * nn * c->pop_bytes);
+            s = dev_alloc(c, &gb, c->g_elems() * c->pop_bytes);
             c->g[b] = gb;
         }
     }

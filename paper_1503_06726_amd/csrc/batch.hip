@@ -225,9 +225,9 @@ struct Part {
 
 std::vector<Part> state_parts(lbib_ctx* c)
 {
-    const size_t nn = (size_t)c->nn, N = (size_t)c->n_nodes, C = (size_t)c->n_cells;
-    return {{c->f[c->cur], 9 * nn * c->pop_bytes},
-            {c->g[c->cur], 5 * (size_t)c->S * nn * c->pop_bytes},
+    const size_t N = (size_t)c->n_nodes, C = (size_t)c->n_cells;
+    return {{c->f[c->cur], c->f_elems() * c->pop_bytes},
+            {c->g[c->cur], c->g_elems() * c->pop_bytes},
             {c->d_X, N * sizeof(double2)},
             {c->d_rec, N * sizeof(float4)},
             {c->d_rec_ij, N * sizeof(int)},

@@ -119,30 +119,34 @@ __global__ __launch_bounds__(ADE_THREADS) void k_ade_hist(const double* __restri
 
 // working set <- the context's populations (storage ST), and back
 template <int ST, typename WT>
-__global__ void k_ade_load(const void* __restrict__ g, WT* __restrict__ w, int64_t nn, int S)
+__global__ void k_ade_load(const void* __restrict__ g, WT* __restrict__ w, int64_t nn, int nx, int64_t grow,
+                           int gchunk, int S)
 {
     using T = typename Pop<ST>::T;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nn) return;
+    const int x = (int)(idx % nx), y = (int)(idx / nx);
     const T* gs = (const T*)g;
     for (int s = 0; s < S; ++s)
         for (int i = 0; i < 5; ++i) {
             const int64_t o = ((int64_t)5 * s + i) * nn + idx;
-            w[o] = (WT)Pop<ST>::ld(gs[o], IS5[i]);
+            w[o] = (WT)Pop<ST>::ld(gs[pop_at(grow, gchunk, 5 * s + i, y, x)], IS5[i]);
         }
 }
 
 template <int ST, typename WT>
-__global__ void k_ade_store(const WT* __restrict__ w, void* __restrict__ g, int64_t nn, int S)
+__global__ void k_ade_store(const WT* __restrict__ w, void* __restrict__ g, int64_t nn, int nx, int64_t grow,
+                            int gchunk, int S)
 {
     using T = typename Pop<ST>::T;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= nn) return;
+    const int x = (int)(idx % nx), y = (int)(idx / nx);
     T* gs = (T*)g;
     for (int s = 0; s < S; ++s)
         for (int i = 0; i < 5; ++i) {
             const int64_t o = ((int64_t)5 * s + i) * nn + idx;
-            gs[o] = Pop<ST>::st((float)w[o], SC5[i]);
+            gs[pop_at(grow, gchunk, 5 * s + i, y, x)] = Pop<ST>::st((float)w[o], SC5[i]);
         }
 }
 
@@ -162,16 +166,16 @@ static hipError_t ade_copy(lbib_ctx* c, void* work, bool to_work)
     WT* w = (WT*)work;
     switch (c->p.storage) {
     case LBIB_STORAGE_FP16:
-        if (to_work) hipLaunchKernelGGL((k_ade_load<1, WT>), dim3(nb), dim3(256), 0, c->stream, g, w, c->nn, c->S);
-        else hipLaunchKernelGGL((k_ade_store<1, WT>), dim3(nb), dim3(256), 0, c->stream, w, c->g[c->cur], c->nn, c->S);
+        if (to_work) hipLaunchKernelGGL((k_ade_load<1, WT>), dim3(nb), dim3(256), 0, c->stream, g, w, c->nn, c->p.nx, c->grow(), c->gchunk(), c->S);
+        else hipLaunchKernelGGL((k_ade_store<1, WT>), dim3(nb), dim3(256), 0, c->stream, w, c->g[c->cur], c->nn, c->p.nx, c->grow(), c->gchunk(), c->S);
         break;
     case LBIB_STORAGE_BF16:
-        if (to_work) hipLaunchKernelGGL((k_ade_load<2, WT>), dim3(nb), dim3(256), 0, c->stream, g, w, c->nn, c->S);
-        else hipLaunchKernelGGL((k_ade_store<2, WT>), dim3(nb), dim3(256), 0, c->stream, w, c->g[c->cur], c->nn, c->S);
+        if (to_work) hipLaunchKernelGGL((k_ade_load<2, WT>), dim3(nb), dim3(256), 0, c->stream, g, w, c->nn, c->p.nx, c->grow(), c->gchunk(), c->S);
+        else hipLaunchKernelGGL((k_ade_store<2, WT>), dim3(nb), dim3(256), 0, c->stream, w, c->g[c->cur], c->nn, c->p.nx, c->grow(), c->gchunk(), c->S);
         break;
     default:
-        if (to_work) hipLaunchKernelGGL((k_ade_load<0, WT>), dim3(nb), dim3(256), 0, c->stream, g, w, c->nn, c->S);
-        else hipLaunchKernelGGL((k_ade_store<0, WT>), dim3(nb), dim3(256), 0, c->stream, w, c->g[c->cur], c->nn, c->S);
+        if (to_work) hipLaunchKernelGGL((k_ade_load<0, WT>), dim3(nb), dim3(256), 0, c->stream, g, w, c->nn, c->p.nx, c->grow(), c->gchunk(), c->S);
+        else hipLaunchKernelGGL((k_ade_store<0, WT>), dim3(nb), dim3(256), 0, c->stream, w, c->g[c->cur], c->nn, c->p.nx, c->grow(), c->gchunk(), c->S);
         break;
     }
     return hipGetLastError();

@@ -28,51 +28,58 @@ namespace lbib {
 #define Q1 (1.0f / 6.0f)
 
 struct Nbr {
-    int64_t rc, rm, rp;   // row offsets of y, y-1, y+1 (clamped at walls)
-    int xm, xp;
+    int y, ym, yp;        // rows y, y-1, y+1 (clamped at walls)
+    int x, xm, xp;        // columns x, x-1, x+1 (periodic)
     bool bot, top;        // y-1 (y+1) lies beyond a wall
 };
 
 __device__ inline Nbr neighbours(int x, int y, int nx, int ny, int walls)
 {
     Nbr n;
+    n.x = x;
+    n.y = y;
     n.xm = (x == 0) ? nx - 1 : x - 1;
     n.xp = (x == nx - 1) ? 0 : x + 1;
-    int ym, yp;
     if (walls) {
         n.bot = (y == 0);
         n.top = (y == ny - 1);
-        ym = n.bot ? y : y - 1;
-        yp = n.top ? y : y + 1;
+        n.ym = n.bot ? y : y - 1;
+        n.yp = n.top ? y : y + 1;
     } else {
         n.bot = n.top = false;
-        ym = (y == 0) ? ny - 1 : y - 1;
-        yp = (y == ny - 1) ? 0 : y + 1;
+        n.ym = (y == 0) ? ny - 1 : y - 1;
+        n.yp = (y == ny - 1) ? 0 : y + 1;
     }
-    n.rc = (int64_t)y * nx;
-    n.rm = (int64_t)ym * nx;
-    n.rp = (int64_t)yp * nx;
     return n;
 }
+
+// offset of column x within its row of a chunked array (chunk = Q TILE_X elements)
+__device__ inline int chunk_col(int x, int chunk) { return (x / TILE_X) * chunk + (x % TILE_X); }
 
 // f_i(x) = s_i(x - v_i); across a wall the population returns reversed: s_opp(i)(x).
 // Velocities: 0 rest, 1 (1,0), 2 (0,1), 3 (-1,0), 4 (0,-1), 5 (1,1), 6 (-1,1), 7 (-1,-1), 8 (1,-1).
 // Values come back as FP32 deviations (w_opp(i) = w_i, so the storage scale matches).
+// s: the chunked fluid array (rows of `row` elements, chunks of 9 TILE_X).
 template <int ST>
-__device__ inline void pull9(const void* sv, int64_t nn, int x, const Nbr& n, float f[9])
+__device__ inline void pull9(const void* sv, int64_t row, const Nbr& n, float f[9])
 {
     using T = typename Pop<ST>::T;
+    constexpr int C = 9 * TILE_X, P = TILE_X;
     const T* __restrict__ s = (const T*)sv;
-    const T* p2 = n.bot ? s + 4 * nn + n.rc + x : s + 2 * nn + n.rm + x;
-    const T* p4 = n.top ? s + 2 * nn + n.rc + x : s + 4 * nn + n.rp + x;
-    const T* p5 = n.bot ? s + 7 * nn + n.rc + x : s + 5 * nn + n.rm + n.xm;
-    const T* p6 = n.bot ? s + 8 * nn + n.rc + x : s + 6 * nn + n.rm + n.xp;
-    const T* p7 = n.top ? s + 5 * nn + n.rc + x : s + 7 * nn + n.rp + n.xp;
-    const T* p8 = n.top ? s + 6 * nn + n.rc + x : s + 8 * nn + n.rp + n.xm;
-    f[0] = Pop<ST>::ld(s[n.rc + x], IS9[0]);
-    f[1] = Pop<ST>::ld(s[nn + n.rc + n.xm], IS9[1]);
+    const T* rc = s + (int64_t)n.y * row;
+    const T* rm = s + (int64_t)n.ym * row;
+    const T* rp = s + (int64_t)n.yp * row;
+    const int cx = chunk_col(n.x, C), cm = chunk_col(n.xm, C), cp = chunk_col(n.xp, C);
+    const T* p2 = n.bot ? rc + cx + 4 * P : rm + cx + 2 * P;
+    const T* p4 = n.top ? rc + cx + 2 * P : rp + cx + 4 * P;
+    const T* p5 = n.bot ? rc + cx + 7 * P : rm + cm + 5 * P;
+    const T* p6 = n.bot ? rc + cx + 8 * P : rm + cp + 6 * P;
+    const T* p7 = n.top ? rc + cx + 5 * P : rp + cp + 7 * P;
+    const T* p8 = n.top ? rc + cx + 6 * P : rp + cm + 8 * P;
+    f[0] = Pop<ST>::ld(rc[cx], IS9[0]);
+    f[1] = Pop<ST>::ld(rc[cm + P], IS9[1]);
     f[2] = Pop<ST>::ld(*p2, IS9[2]);
-    f[3] = Pop<ST>::ld(s[3 * nn + n.rc + n.xp], IS9[3]);
+    f[3] = Pop<ST>::ld(rc[cp + 3 * P], IS9[3]);
     f[4] = Pop<ST>::ld(*p4, IS9[4]);
     f[5] = Pop<ST>::ld(*p5, IS9[5]);
     f[6] = Pop<ST>::ld(*p6, IS9[6]);
@@ -80,18 +87,33 @@ __device__ inline void pull9(const void* sv, int64_t nn, int x, const Nbr& n, fl
     f[8] = Pop<ST>::ld(*p8, IS9[8]);
 }
 
+// one species: s points at the species' first plane within the chunked species array
+// (rows of `row` elements, chunks of `chunk` = 5 S TILE_X)
 template <int ST>
-__device__ inline void pull5(const void* sv, int64_t nn, int x, const Nbr& n, float g[5])
+__device__ inline void pull5(const void* sv, int64_t row, int chunk, const Nbr& n, float g[5])
 {
     using T = typename Pop<ST>::T;
+    constexpr int P = TILE_X;
     const T* __restrict__ s = (const T*)sv;
-    const T* p2 = n.bot ? s + 4 * nn + n.rc + x : s + 2 * nn + n.rm + x;
-    const T* p4 = n.top ? s + 2 * nn + n.rc + x : s + 4 * nn + n.rp + x;
-    g[0] = Pop<ST>::ld(s[n.rc + x], IS5[0]);
-    g[1] = Pop<ST>::ld(s[nn + n.rc + n.xm], IS5[1]);
+    const T* rc = s + (int64_t)n.y * row;
+    const T* rm = s + (int64_t)n.ym * row;
+    const T* rp = s + (int64_t)n.yp * row;
+    const int cx = chunk_col(n.x, chunk), cm = chunk_col(n.xm, chunk), cp = chunk_col(n.xp, chunk);
+    const T* p2 = n.bot ? rc + cx + 4 * P : rm + cx + 2 * P;
+    const T* p4 = n.top ? rc + cx + 2 * P : rp + cx + 4 * P;
+    g[0] = Pop<ST>::ld(rc[cx], IS5[0]);
+    g[1] = Pop<ST>::ld(rc[cm + P], IS5[1]);
     g[2] = Pop<ST>::ld(*p2, IS5[2]);
-    g[3] = Pop<ST>::ld(s[3 * nn + n.rc + n.xp], IS5[3]);
+    g[3] = Pop<ST>::ld(rc[cp + 3 * P], IS5[3]);
     g[4] = Pop<ST>::ld(*p4, IS5[4]);
+}
+
+// streaming store that bypasses the caches' retention (the next pass reads it from HBM)
+template <typename T>
+__device__ inline void store_nt(T* p, T v)
+{
+    if constexpr (sizeof(T) == 4) __builtin_nontemporal_store(__builtin_bit_cast(unsigned, v), (unsigned*)p);
+    else __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, v), (unsigned short*)p);
 }
 
 __device__ inline unsigned long long to_fixed(float v)
@@ -120,6 +142,31 @@ __device__ inline void load_candidates(const LatticeArgs& a, int k0, int end, in
             ij[u] = a.rec_ij[node];
             rc[u] = a.rec[node];
         }
+    }
+}
+
+// The same in two halves, so that other loads can be issued between them: the list entries
+// of the chunk, then (once they are back) the stencil origins and records they name.
+__device__ inline void load_entries(const LatticeArgs& a, int k0, int end, int ent[SPREAD_UNROLL])
+{
+#pragma unroll
+    for (int u = 0; u < SPREAD_UNROLL; ++u) {
+        const int k = k0 + u * TILE_N + (int)threadIdx.x;
+        ent[u] = (k < end) ? a.t_list[k] : -1;
+    }
+}
+
+// (loads without branches: a lane past the end reads node 0's record and discards it, which
+// lets the compiler wait for exactly the loads each use needs)
+__device__ inline void load_records(const LatticeArgs& a, const int ent[SPREAD_UNROLL], int ij[SPREAD_UNROLL],
+                                    float4 rc[SPREAD_UNROLL])
+{
+#pragma unroll
+    for (int u = 0; u < SPREAD_UNROLL; ++u) {
+        const int node = (ent[u] != -1) ? (int)((unsigned)ent[u] >> 4) : 0;
+        const int v = a.rec_ij[node];
+        rc[u] = a.rec[node];
+        ij[u] = (ent[u] != -1) ? v : 0x7FFF7FFF;        // far away: never hits
     }
 }
 
@@ -214,13 +261,13 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
     const int x1 = min(x0 + TILE_X, a.nx), y1 = min(y0 + LY, a.ny);
     const int t = threadIdx.x;
     const int x = x0 + (t % TILE_X);
-    const int64_t nn = a.nn;
 
     __shared__ unsigned long long accx[NL], accy[NL];
     __shared__ float uxs[NL], uys[NL];
 
-    // the first chunk of listed nodes is fetched before the populations: the record loads
-    // depend on the list entry, and issuing them first keeps them off the populations' queue
+    // Load order: the first chunk's list entries, the populations, then the records the entries
+    // name.  Loads complete in order, so waiting for the entries does not wait for the
+    // populations, and the entry -> record round trip overlaps the population loads.
     int lbeg = 0, lend = 0;
     int cij[SPREAD_UNROLL], cnd[SPREAD_UNROLL];
     float4 crc[SPREAD_UNROLL];
@@ -228,7 +275,7 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
     if constexpr (NODES) {
         lbeg = a.t_off[tile];
         lend = a.t_off[tile + 1];
-        load_candidates(a, lbeg, lend, cij, crc, cnd);
+        load_entries(a, lbeg, lend, cnd);
 #pragma unroll
         for (int r = 0; r < RP; ++r) {
             accx[t + r * TILE_N] = 0ull;
@@ -241,27 +288,29 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
     float f[RP][9];
     float g[RP][S > 0 ? S : 1][5];
     int m[RP];
+    // every lane loads (lanes beyond a ragged edge read the last column / row and discard it):
+    // without branches around the loads the compiler waits for exactly the ones each use needs
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
         const int y = y0 + t / TILE_X + r * TILE_Y;
         active[r] = x < a.nx && y < a.ny;
-        m[r] = 0;
-        if (active[r]) {
-            n[r] = neighbours(x, y, a.nx, a.ny, a.walls);
-            pull9<ST>(a.fsrc, nn, x, n[r], f[r]);
+        const int xl = min(x, a.nx - 1), yl = min(y, a.ny - 1);
+        n[r] = neighbours(xl, yl, a.nx, a.ny, a.walls);
+        pull9<ST>(a.fsrc, a.frow, n[r], f[r]);
 #pragma unroll
-            for (int s = 0; s < S; ++s)
-                pull5<ST>((const typename Pop<ST>::T*)a.gsrc + (int64_t)5 * s * nn, nn, x, n[r], g[r][s]);
-            if constexpr (MASK) {
-                // the row's two bit words are the same for the whole wavefront: scalar loads
-                const int wy = __builtin_amdgcn_readfirstlane(y);
-                const unsigned* row = a.inside + (int64_t)wy * a.wpr + (x0 >> 5);
-                const unsigned w0 = row[0];
-                const unsigned w1 = (x0 + 32 < a.nx) ? row[1] : 0u;
-                m[r] = (((x & 32) ? w1 : w0) >> (x & 31)) & 1u;
-            }
+        for (int s = 0; s < S; ++s)
+            pull5<ST>((const typename Pop<ST>::T*)a.gsrc + 5 * s * TILE_X, a.grow, a.gchunk, n[r], g[r][s]);
+        m[r] = 0;
+        if constexpr (MASK) {
+            // the row's two bit words are the same for the whole wavefront: scalar loads
+            const int wy = __builtin_amdgcn_readfirstlane(yl);
+            const unsigned* row = a.inside + (int64_t)wy * a.wpr + (x0 >> 5);
+            const unsigned w0 = row[0];
+            const unsigned w1 = (x0 + 32 < a.nx) ? row[1] : 0u;
+            m[r] = (((x & 32) ? w1 : w0) >> (x & 31)) & 1u;
         }
     }
+    if constexpr (NODES) load_records(a, cnd, cij, crc);
 
     // moments of every row: rho^n, u^n = sum f v / rho
     float rho_r[RP], drho_r[RP], ux_r[RP], uy_r[RP];
@@ -302,7 +351,6 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
         if (!active[r]) continue;
-        const int64_t o = n[r].rc + x;
         float ex = a.bodyx, ey = a.bodyy;
         if constexpr (NODES) {
             const int l = t + r * TILE_N;
@@ -318,17 +366,18 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
         {
             // equilibrium deviation w_i (drho + rho (3 vu + 4.5 vu^2 - 1.5 u^2))
             using T = typename Pop<ST>::T;
-            T* __restrict__ d = (T*)a.fdst + o;
-            d[0] = Pop<ST>::st(om1 * fr[0] + om * W0 * (drho - rho * usq), SC9[0]);
+            constexpr int P = TILE_X;
+            T* __restrict__ d = (T*)a.fdst + (int64_t)n[r].y * a.frow + chunk_col(x, 9 * TILE_X);
+            store_nt(d, Pop<ST>::st(om1 * fr[0] + om * W0 * (drho - rho * usq), SC9[0]));
             float vu, eq;
-            vu = ux;       eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[nn]     = Pop<ST>::st(om1 * fr[1] + om * eq + W1 * fx, SC9[1]);
-            vu = uy;       eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[2 * nn] = Pop<ST>::st(om1 * fr[2] + om * eq + W1 * fy, SC9[2]);
-            vu = -ux;      eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[3 * nn] = Pop<ST>::st(om1 * fr[3] + om * eq - W1 * fx, SC9[3]);
-            vu = -uy;      eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[4 * nn] = Pop<ST>::st(om1 * fr[4] + om * eq - W1 * fy, SC9[4]);
-            vu = ux + uy;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[5 * nn] = Pop<ST>::st(om1 * fr[5] + om * eq + W5 * (fx + fy), SC9[5]);
-            vu = uy - ux;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[6 * nn] = Pop<ST>::st(om1 * fr[6] + om * eq + W5 * (fy - fx), SC9[6]);
-            vu = -ux - uy; eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[7 * nn] = Pop<ST>::st(om1 * fr[7] + om * eq - W5 * (fx + fy), SC9[7]);
-            vu = ux - uy;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); d[8 * nn] = Pop<ST>::st(om1 * fr[8] + om * eq + W5 * (fx - fy), SC9[8]);
+            vu = ux;       eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); store_nt(d + P,     Pop<ST>::st(om1 * fr[1] + om * eq + W1 * fx, SC9[1]));
+            vu = uy;       eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); store_nt(d + 2 * P, Pop<ST>::st(om1 * fr[2] + om * eq + W1 * fy, SC9[2]));
+            vu = -ux;      eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); store_nt(d + 3 * P, Pop<ST>::st(om1 * fr[3] + om * eq - W1 * fx, SC9[3]));
+            vu = -uy;      eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); store_nt(d + 4 * P, Pop<ST>::st(om1 * fr[4] + om * eq - W1 * fy, SC9[4]));
+            vu = ux + uy;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); store_nt(d + 5 * P, Pop<ST>::st(om1 * fr[5] + om * eq + W5 * (fx + fy), SC9[5]));
+            vu = uy - ux;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); store_nt(d + 6 * P, Pop<ST>::st(om1 * fr[6] + om * eq + W5 * (fy - fx), SC9[6]));
+            vu = -ux - uy; eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); store_nt(d + 7 * P, Pop<ST>::st(om1 * fr[7] + om * eq - W5 * (fx + fy), SC9[7]));
+            vu = ux - uy;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); store_nt(d + 8 * P, Pop<ST>::st(om1 * fr[8] + om * eq + W5 * (fx - fy), SC9[8]));
         }
 
         if constexpr (MASK)
@@ -358,13 +407,14 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
                 const float p3 = 3.0f * phi[s];
                 const float* gg = g[r][s];
                 using T = typename Pop<ST>::T;
-                T* __restrict__ d = (T*)a.gdst + (int64_t)5 * s * nn + o;
+                constexpr int P = TILE_X;
+                T* __restrict__ d = (T*)a.gdst + (int64_t)n[r].y * a.grow + chunk_col(x, a.gchunk) + 5 * s * P;
                 // equilibrium deviation w_i (dphi + 3 phi v_i . u) and reaction w_i R
-                d[0]      = Pop<ST>::st(os1 * gg[0] + os * Q0 * dphi[s] + Q0 * R[s], SC5[0]);
-                d[nn]     = Pop<ST>::st(os1 * gg[1] + os * Q1 * (dphi[s] + p3 * ux) + Q1 * R[s], SC5[1]);
-                d[2 * nn] = Pop<ST>::st(os1 * gg[2] + os * Q1 * (dphi[s] + p3 * uy) + Q1 * R[s], SC5[2]);
-                d[3 * nn] = Pop<ST>::st(os1 * gg[3] + os * Q1 * (dphi[s] - p3 * ux) + Q1 * R[s], SC5[3]);
-                d[4 * nn] = Pop<ST>::st(os1 * gg[4] + os * Q1 * (dphi[s] - p3 * uy) + Q1 * R[s], SC5[4]);
+                store_nt(d,         Pop<ST>::st(os1 * gg[0] + os * Q0 * dphi[s] + Q0 * R[s], SC5[0]));
+                store_nt(d + P,     Pop<ST>::st(os1 * gg[1] + os * Q1 * (dphi[s] + p3 * ux) + Q1 * R[s], SC5[1]));
+                store_nt(d + 2 * P, Pop<ST>::st(os1 * gg[2] + os * Q1 * (dphi[s] + p3 * uy) + Q1 * R[s], SC5[2]));
+                store_nt(d + 3 * P, Pop<ST>::st(os1 * gg[3] + os * Q1 * (dphi[s] - p3 * ux) + Q1 * R[s], SC5[3]));
+                store_nt(d + 4 * P, Pop<ST>::st(os1 * gg[4] + os * Q1 * (dphi[s] - p3 * uy) + Q1 * R[s], SC5[4]));
             }
         }
     }
@@ -377,8 +427,16 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
     }
 }
 
+// Waves per SIMD the lattice pass is compiled for: the register budget that keeps the
+// population loads of RP rows in flight without spilling (96 VGPRs at two rows and one species;
+// the batched form, whose arguments come from a table, needs a few more).
+constexpr int lattice_waves(int S, int RP, bool batch)
+{
+    return RP == 1 ? 6 : RP == 2 ? ((S <= 1 && !batch) ? 5 : 4) : 3;
+}
+
 template <int S, bool NODES, bool MASK, int ST>
-__global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
+__global__ __launch_bounds__(TILE_N) __attribute__((amdgpu_waves_per_eu(lattice_waves(S, RPT, false)))) void k_lattice(LatticeArgs a)
 {
     lattice_tile<S, NODES, MASK, ST, RPT>(a, xcd_remap(blockIdx.x, gridDim.x));
 }
@@ -387,7 +445,7 @@ __global__ __launch_bounds__(TILE_N) void k_lattice(LatticeArgs a)
 // arguments come from a device table (independent lattices of any sizes in one launch), and
 // the tile height TILE_Y RP is a parameter of the launch.
 template <int S, bool NODES, bool MASK, int ST, int RP>
-__global__ __launch_bounds__(TILE_N) void k_lattice_batch(const LatticeArgs* __restrict__ tab,
+__global__ __launch_bounds__(TILE_N) __attribute__((amdgpu_waves_per_eu(lattice_waves(S, RP, true)))) void k_lattice_batch(const LatticeArgs* __restrict__ tab,
                                                           const int2* __restrict__ work)
 {
     const int2 wk = work[xcd_remap(blockIdx.x, gridDim.x)];
@@ -434,12 +492,14 @@ __global__ __launch_bounds__(TILE_N) void k_spread_inspect(LatticeArgs a)
 // pull yields f_i(x) = f_i^eq(rho(x), u(x)): s_i(x - v_i) = f_i^eq(x), or across a wall
 // s_opp(i)(x) = f_i^eq(x).
 struct InitArgs {
-    void* f;
+    void* f;                          // chunked arrays
     void* g;
-    const double* rho;
+    const double* rho;                // planar [ny][nx] inputs
     const double* u;
     const double* phi;
     int64_t nn;
+    int64_t frow, grow;
+    int gchunk;
     int nx, ny, walls, S;
     double rho0;
     double phi_ref[2];
@@ -467,27 +527,27 @@ __global__ void k_init(InitArgs a)
         const T val = Pop<ST>::st((float)(w9[i] * (drho + rho * (3.0 * vu + 4.5 * vu * vu - usq))), SC9[i]);
         const int sy = y - vy[i];
         if (a.walls && (sy < 0 || sy >= a.ny)) {
-            f[(int64_t)opp[i] * a.nn + idx] = val;
+            f[pop_at(a.frow, 9 * TILE_X, opp[i], y, x)] = val;
         } else {
             const int sx = (x - vx[i] + a.nx) % a.nx;
             const int syy = (sy + a.ny) % a.ny;
-            f[(int64_t)i * a.nn + (int64_t)syy * a.nx + sx] = val;
+            f[pop_at(a.frow, 9 * TILE_X, i, syy, sx)] = val;
         }
     }
     for (int s = 0; s < a.S; ++s) {
         const double phi = a.phi ? a.phi[(int64_t)s * a.nn + idx] : 0.0;
         const double dphi = phi - a.phi_ref[s];
-        T* gs = (T*)a.g + (int64_t)5 * s * a.nn;
+        T* gs = (T*)a.g;
         for (int i = 0; i < 5; ++i) {
             const double vu = vx[i] * ux + vy[i] * uy;
             const T val = Pop<ST>::st((float)(w5[i] * (dphi + 3.0 * phi * vu)), SC5[i]);
             const int sy = y - vy[i];
             if (a.walls && (sy < 0 || sy >= a.ny)) {
-                gs[(int64_t)opp[i] * a.nn + idx] = val;
+                gs[pop_at(a.grow, a.gchunk, 5 * s + opp[i], y, x)] = val;
             } else {
                 const int sx = (x - vx[i] + a.nx) % a.nx;
                 const int syy = (sy + a.ny) % a.ny;
-                gs[(int64_t)i * a.nn + (int64_t)syy * a.nx + sx] = val;
+                gs[pop_at(a.grow, a.gchunk, 5 * s + i, syy, sx)] = val;
             }
         }
     }
@@ -495,10 +555,12 @@ __global__ void k_init(InitArgs a)
 
 // Moments of the current state in FP64: planes rho, ux, uy, phi_0 .. phi_{S-1}.
 struct MomentArgs {
-    const void* f;
+    const void* f;                    // chunked arrays
     const void* g;
-    double* out;
+    double* out;                      // planar outputs
     int64_t nn;
+    int64_t frow, grow;
+    int gchunk;
     int nx, ny, walls, S;
     double rho0;
     double phi_ref[2];
@@ -510,14 +572,14 @@ __device__ inline void node_moments(const MomentArgs& a, int x, int y, double& d
 {
     const Nbr n = neighbours(x, y, a.nx, a.ny, a.walls);
     float f[9];
-    pull9<ST>(a.f, a.nn, x, n, f);
+    pull9<ST>(a.f, a.frow, n, f);
     drho = 0.0;
     for (int i = 0; i < 9; ++i) drho += (double)f[i];
     jx = ((double)f[1] - f[3]) + ((double)f[5] - f[6]) + ((double)f[8] - f[7]);
     jy = ((double)f[2] - f[4]) + ((double)f[5] + f[6]) - ((double)f[7] + f[8]);
     for (int s = 0; s < a.S; ++s) {
         float g[5];
-        pull5<ST>((const typename Pop<ST>::T*)a.g + (int64_t)5 * s * a.nn, a.nn, x, n, g);
+        pull5<ST>((const typename Pop<ST>::T*)a.g + 5 * s * TILE_X, a.grow, a.gchunk, n, g);
         double t = 0.0;
         for (int i = 0; i < 5; ++i) t += (double)g[i];
         dphi[s] = t;
@@ -674,6 +736,9 @@ hipError_t launch_init(lbib_ctx* c, const double* rho, const double* u, const do
     a.u = has_u ? u : nullptr;
     a.phi = has_phi ? phi : nullptr;
     a.nn = c->nn;
+    a.frow = c->frow();
+    a.grow = c->grow();
+    a.gchunk = c->gchunk();
     a.nx = c->p.nx;
     a.ny = c->p.ny;
     a.walls = c->p.bc_y == LBIB_WALLS;
@@ -697,6 +762,9 @@ static MomentArgs moment_args(lbib_ctx* c, double* out)
     a.g = c->g[c->cur];
     a.out = out;
     a.nn = c->nn;
+    a.frow = c->frow();
+    a.grow = c->grow();
+    a.gchunk = c->gchunk();
     a.nx = c->p.nx;
     a.ny = c->p.ny;
     a.walls = c->p.bc_y == LBIB_WALLS;

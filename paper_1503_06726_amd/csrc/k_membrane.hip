@@ -7,12 +7,14 @@
 //      (positions in FP64);
 //   2. stages the cell's new positions in LDS and reduces the polygon area (shoelace, FP64,
 //      fixed-order wave and LDS reduction);
-//   3. evaluates the nodal forces in the paper's per-node form: constant tension
-//      (Eq. membraneforce), Hookean springs, area pressure kappa (A0 - A) dA/dX, and
-//      refreshes the node's spreading record (fractional offset, force, stencil origin); a
-//      node that drifted beyond its list margin raises an error flag;
-//   4. when a reaction reads it, ORs the cell's interior into the inside-any-cell bit map
-//      (rasterised from the LDS positions).
+//   3. when a reaction reads it, ORs the cell's interior into the inside-any-cell bit map
+//      (rasterised from the LDS positions);
+//   4. evaluates the nodal forces in the paper's per-node form: constant tension
+//      (Eq. membraneforce), Hookean springs, area pressure kappa (A0 - A) dA/dX, refreshes
+//      the node's spreading record (fractional offset, force, stencil origin) and stores the
+//      new position; a node that drifted beyond its list margin raises an error flag.
+// Every global store comes after the last workgroup barrier, which would otherwise wait for
+// them.
 // k_list_count / k_list_scan / k_list_fill rebuild the per-tile node lists (every few steps).
 // The *_batch forms run the same per-cell, per-node and per-simulation work for many
 // independent simulations in one launch, each work item naming its simulation's arguments.
@@ -105,15 +107,19 @@ __device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c
 
     // 1. move: X^{n+1} = X^n + U, U interpolated by the lattice pass as one share per listed
     //    tile, added in the order of the node's tiles; stage the new positions in LDS and
-    //    track their bounding box
+    //    track their bounding box.  The positions reach global memory only at the end: a
+    //    workgroup barrier waits for every outstanding store.
     double bb[4] = {INFINITY, INFINITY, INFINITY, INFINITY};     // min x, min y, -max x, -max y
     for (int k = t; k < n; k += MEMBRANE_THREADS) {
         const int64_t l = beg + k;
         double2 X = a.X[l];
         if (a.advect) {
-            // the first two shares are read alongside the count (most nodes have two)
+            // the first four shares are read alongside the count (a node has at most four
+            // tiles unless its list range wraps onto a narrow last tile); slots beyond the
+            // count are never added
+            const int64_t N = a.n_nodes;
             const int nt = a.cnt[l];
-            const float2 s0 = a.part[l], s1 = a.part[a.n_nodes + l];
+            const float2 s0 = a.part[l], s1 = a.part[N + l], s2 = a.part[2 * N + l], s3 = a.part[3 * N + l];
             double ux = 0.0, uy = 0.0;
             if (nt > 0) {
                 ux += (double)s0.x;
@@ -123,15 +129,22 @@ __device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c
                 ux += (double)s1.x;
                 uy += (double)s1.y;
             }
-            for (int q = 2; q < nt; ++q) {
-                const float2 s = a.part[q * a.n_nodes + l];
-                ux += (double)s.x;
-                uy += (double)s.y;
+            if (nt > 2) {
+                ux += (double)s2.x;
+                uy += (double)s2.y;
+            }
+            if (nt > 3) {
+                ux += (double)s3.x;
+                uy += (double)s3.y;
+            }
+            for (int q = 4; q < nt; ++q) {
+                const float2 sq = a.part[q * N + l];
+                ux += (double)sq.x;
+                uy += (double)sq.y;
             }
             if (finite2(X.x, X.y)) {
                 X.x += ux;
                 X.y += uy;
-                a.X[l] = X;
             }
         }
         xs[k] = X;
@@ -151,10 +164,35 @@ __device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c
     }
     block_reduce5(A2, bb, red);
     const double A = 0.5 * A2;
-    if (t == 0) a.area[c] = A;
     const double s_area = a.kappa * (a.A0[c] - A);
 
-    // 3. forces and spreading records
+    // 3. inside-any-cell bits of the new positions (the bitmap was cleared above); with a
+    //    source subset only the source cells are rasterised.  No barrier follows the last
+    //    chunk, so its atomics drain during the force pass.
+    if (a.raster && !(a.src && !a.src[c])) {
+        const RasterBox b = raster_box(bb[0], bb[1], -bb[2], -bb[3], a.nx, a.ny);
+        if (b.ok) {                                                  // uniform across the group
+            int CH = RASTER_WORDS_FUSED / b.WW;
+            if (CH < 1) CH = 1;
+            if (CH > b.H) CH = b.H;
+            for (int r0 = 0; r0 < b.H; r0 += CH) {
+                const int rows = (b.H - r0 < CH) ? b.H - r0 : CH;
+                if (r0 > 0) {
+                    for (int i = t; i < rows * b.WW; i += MEMBRANE_THREADS) bm[i] = 0u;
+                    __syncthreads();
+                }
+                raster_toggle(xs, n, b, r0, rows, bm);
+                __syncthreads();
+                raster_prefix(bm, rows, b.WW);
+                __syncthreads();
+                raster_or_bits(bm, b, r0, rows, a.inside, a.wpr, a.nx, a.ny, a.walls);
+                if (r0 + CH < b.H) __syncthreads();
+            }
+        }
+    }
+
+    // 4. forces, spreading records and the new positions (no barrier follows: the stores
+    //    drain while the workgroup retires)
     int flags = 0;
     for (int k = t; k < n; k += MEMBRANE_THREADS) {
         const int kp = (k + 1 == n) ? 0 : k + 1;
@@ -179,6 +217,7 @@ __device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c
         Fx += s_area * 0.5 * (Xp.y - Xm.y);
         Fy += s_area * 0.5 * (Xm.x - Xp.x);
         const int s = beg + k;
+        if (a.advect) a.X[s] = X;
         if (finite2(X.x, X.y) && finite2(Fx, Fy)) {
             const double fx = floor(X.x), fy = floor(X.y);
             int i0, j0;
@@ -192,32 +231,12 @@ __device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c
             flags |= ERR_NONFINITE;
         }
     }
+    if (t == 0) a.area[c] = A;
     if (flags) atomicOr(a.err, flags);
-
-    // 4. inside-any-cell bits of the new positions (the bitmap was cleared above); with a
-    //    source subset only the source cells are rasterised
-    if (!a.raster || (a.src && !a.src[c])) return;
-    const RasterBox b = raster_box(bb[0], bb[1], -bb[2], -bb[3], a.nx, a.ny);
-    if (!b.ok) return;                                               // uniform across the group
-    int CH = RASTER_WORDS_FUSED / b.WW;
-    if (CH < 1) CH = 1;
-    if (CH > b.H) CH = b.H;
-    for (int r0 = 0; r0 < b.H; r0 += CH) {
-        const int rows = (b.H - r0 < CH) ? b.H - r0 : CH;
-        if (r0 > 0) {
-            for (int i = t; i < rows * b.WW; i += MEMBRANE_THREADS) bm[i] = 0u;
-            __syncthreads();
-        }
-        raster_toggle(xs, n, b, r0, rows, bm);
-        __syncthreads();
-        raster_prefix(bm, rows, b.WW);
-        __syncthreads();
-        raster_or_bits(bm, b, r0, rows, a.inside, a.wpr, a.nx, a.ny, a.walls);
-        __syncthreads();
-    }
 }
 
-__global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
+// 8 waves per SIMD keep every workgroup of a 2000-cell step resident at once
+__global__ __launch_bounds__(MEMBRANE_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_membrane(MembraneArgs a)
 {
     extern __shared__ double2 xs[];
     __shared__ double red[5 * (MEMBRANE_THREADS / 64)];
@@ -227,7 +246,7 @@ __global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane(MembraneArgs a)
 
 // Batched form: one (simulation, cell) work item per workgroup, the simulation's arguments
 // from a device table.
-__global__ __launch_bounds__(MEMBRANE_THREADS) void k_membrane_batch(const MembraneArgs* __restrict__ tab,
+__global__ __launch_bounds__(MEMBRANE_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_membrane_batch(const MembraneArgs* __restrict__ tab,
                                                                      const int2* __restrict__ work)
 {
     extern __shared__ double2 xs[];

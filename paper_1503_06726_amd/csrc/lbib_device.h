@@ -1,10 +1,14 @@
 // Device-side definitions shared by the lbib HIP kernels (gfx950).
 //
 // Storage: every population is kept as a deviation from its rest value,
-// df_i = f_i - w_i rho0 and dg_i = g_i - w_i phi_ref, in structure-of-arrays planes
-// [q][ny][nx] (x fastest).  The arrays hold post-collision, pre-streaming values; a
-// lattice pass pulls f_i(x) = f*_i(x - v_i) (or, across a wall, f*_opp(i)(x)), collides,
-// and stores f*_i(x) in place of x in the other buffer.
+// df_i = f_i - w_i rho0 and dg_i = g_i - w_i phi_ref, in arrays chunked by TILE_X columns:
+// a lattice row is a run of chunks, each holding the Q planes of its 64 columns one after the
+// other ([ny][ceil(nx / 64)][Q][64], x fastest; the last chunk of a row is padded).  A
+// workgroup's loads and stores then fall into a few contiguous kilobyte runs instead of 2Q
+// separate streams, which DRAM serves markedly faster.  Q = 9 for the fluid and 5 S for the
+// species (species s in planes 5 s .. 5 s + 4).  The arrays hold post-collision,
+// pre-streaming values; a lattice pass pulls f_i(x) = f*_i(x - v_i) (or, across a wall,
+// f*_opp(i)(x)), collides, and stores f*_i(x) in place of x in the other buffer.
 //
 // Immersed-boundary nodes are listed per lattice tile (TILE_X x LTILE_Y nodes): every few
 // steps (LIST_PERIOD) each node enters the list of every tile that its 4x4 stencil can reach
@@ -53,12 +57,21 @@ constexpr float FIX_CLAMP = 16384.0f;                    // |contribution| bound
 constexpr int ERR_NONFINITE = 1;     // a node position or force became non-finite
 constexpr int ERR_MARGIN = 2;        // a node drifted beyond its list margin
 
+// Element (plane p, row y, column x) of a chunked population array whose rows hold `row`
+// elements and whose chunks hold `chunk` = Q * TILE_X elements.
+__device__ inline int64_t pop_at(int64_t row, int chunk, int p, int y, int x)
+{
+    return (int64_t)y * row + (int64_t)(x / TILE_X) * chunk + p * TILE_X + (x % TILE_X);
+}
+
 struct LatticeArgs {
-    const void* __restrict__ fsrc;    // 9 planes of the storage type
+    const void* __restrict__ fsrc;    // 9 planes of the storage type, chunked
     void* __restrict__ fdst;
-    const void* __restrict__ gsrc;    // 5 * S planes
+    const void* __restrict__ gsrc;    // 5 * S planes, chunked
     void* __restrict__ gdst;
-    int64_t nn;                       // nx * ny (plane stride)
+    int64_t nn;                       // nx * ny
+    int64_t frow, grow;               // elements per lattice row of the fluid / species arrays
+    int gchunk;                       // elements per chunk of the species array (5 S TILE_X)
     int nx, ny, walls, ntx;
     float omega, rho0;
     float omega_s[2], phi_ref[2];

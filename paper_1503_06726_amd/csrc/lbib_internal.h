@@ -43,6 +43,12 @@ struct lbib_ctx {
     void* f[2] = {nullptr, nullptr};
     void* g[2] = {nullptr, nullptr};
     size_t pop_bytes = 4;            // bytes per stored population
+    // chunked arrays (lbib_device.h): ntx chunks of TILE_X columns per row
+    int gchunk() const { return 5 * S * lbib::TILE_X; }
+    int64_t frow() const { return (int64_t)ntx * 9 * lbib::TILE_X; }
+    int64_t grow() const { return (int64_t)ntx * gchunk(); }
+    size_t f_elems() const { return (size_t)p.ny * (size_t)frow(); }
+    size_t g_elems() const { return (size_t)p.ny * (size_t)grow(); }
     int cur = 0;
     unsigned* inside[2] = {nullptr, nullptr};   // inside-any-cell bits [ny][wpr], by parity cur
     int wpr = 0;                     // 32-bit words per lattice row
