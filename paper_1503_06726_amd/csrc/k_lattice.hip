@@ -56,6 +56,20 @@ __device__ inline Nbr neighbours(int x, int y, int nx, int ny, int walls)
 // offset of column x within its row of a chunked array (chunk = Q TILE_X elements)
 __device__ inline int chunk_col(int x, int chunk) { return (x / TILE_X) * chunk + (x % TILE_X); }
 
+// Element `idx` of a row whose base address is the same for the whole wavefront: the base
+// stays in scalar registers and each lane adds a 32-bit byte offset (a row holds far fewer
+// than 2^30 elements), which spares the 64-bit address arithmetic per load and store.
+template <typename T>
+__device__ inline const T& row_at(const T* base, int idx)
+{
+    return *(const T*)((const char*)base + (unsigned)((unsigned)idx * (unsigned)sizeof(T)));
+}
+template <typename T>
+__device__ inline T* row_ptr(T* base, int idx)
+{
+    return (T*)((char*)base + (unsigned)((unsigned)idx * (unsigned)sizeof(T)));
+}
+
 // f_i(x) = s_i(x - v_i); across a wall the population returns reversed: s_opp(i)(x).
 // Velocities: 0 rest, 1 (1,0), 2 (0,1), 3 (-1,0), 4 (0,-1), 5 (1,1), 6 (-1,1), 7 (-1,-1), 8 (1,-1).
 // Values come back as FP32 deviations (w_opp(i) = w_i, so the storage scale matches).
@@ -70,21 +84,16 @@ __device__ inline void pull9(const void* sv, int64_t row, const Nbr& n, float f[
     const T* rm = s + (int64_t)n.ym * row;
     const T* rp = s + (int64_t)n.yp * row;
     const int cx = chunk_col(n.x, C), cm = chunk_col(n.xm, C), cp = chunk_col(n.xp, C);
-    const T* p2 = n.bot ? rc + cx + 4 * P : rm + cx + 2 * P;
-    const T* p4 = n.top ? rc + cx + 2 * P : rp + cx + 4 * P;
-    const T* p5 = n.bot ? rc + cx + 7 * P : rm + cm + 5 * P;
-    const T* p6 = n.bot ? rc + cx + 8 * P : rm + cp + 6 * P;
-    const T* p7 = n.top ? rc + cx + 5 * P : rp + cp + 7 * P;
-    const T* p8 = n.top ? rc + cx + 6 * P : rp + cm + 8 * P;
-    f[0] = Pop<ST>::ld(rc[cx], IS9[0]);
-    f[1] = Pop<ST>::ld(rc[cm + P], IS9[1]);
-    f[2] = Pop<ST>::ld(*p2, IS9[2]);
-    f[3] = Pop<ST>::ld(rc[cp + 3 * P], IS9[3]);
-    f[4] = Pop<ST>::ld(*p4, IS9[4]);
-    f[5] = Pop<ST>::ld(*p5, IS9[5]);
-    f[6] = Pop<ST>::ld(*p6, IS9[6]);
-    f[7] = Pop<ST>::ld(*p7, IS9[7]);
-    f[8] = Pop<ST>::ld(*p8, IS9[8]);
+    // across a wall the row is the node's own and the plane the opposite one
+    f[0] = Pop<ST>::ld(row_at(rc, cx), IS9[0]);
+    f[1] = Pop<ST>::ld(row_at(rc, cm + P), IS9[1]);
+    f[2] = Pop<ST>::ld(row_at(n.bot ? rc : rm, cx + (n.bot ? 4 : 2) * P), IS9[2]);
+    f[3] = Pop<ST>::ld(row_at(rc, cp + 3 * P), IS9[3]);
+    f[4] = Pop<ST>::ld(row_at(n.top ? rc : rp, cx + (n.top ? 2 : 4) * P), IS9[4]);
+    f[5] = Pop<ST>::ld(row_at(n.bot ? rc : rm, n.bot ? cx + 7 * P : cm + 5 * P), IS9[5]);
+    f[6] = Pop<ST>::ld(row_at(n.bot ? rc : rm, n.bot ? cx + 8 * P : cp + 6 * P), IS9[6]);
+    f[7] = Pop<ST>::ld(row_at(n.top ? rc : rp, n.top ? cx + 5 * P : cp + 7 * P), IS9[7]);
+    f[8] = Pop<ST>::ld(row_at(n.top ? rc : rp, n.top ? cx + 6 * P : cm + 8 * P), IS9[8]);
 }
 
 // one species: s points at the species' first plane within the chunked species array
@@ -99,13 +108,11 @@ __device__ inline void pull5(const void* sv, int64_t row, int chunk, const Nbr& 
     const T* rm = s + (int64_t)n.ym * row;
     const T* rp = s + (int64_t)n.yp * row;
     const int cx = chunk_col(n.x, chunk), cm = chunk_col(n.xm, chunk), cp = chunk_col(n.xp, chunk);
-    const T* p2 = n.bot ? rc + cx + 4 * P : rm + cx + 2 * P;
-    const T* p4 = n.top ? rc + cx + 2 * P : rp + cx + 4 * P;
-    g[0] = Pop<ST>::ld(rc[cx], IS5[0]);
-    g[1] = Pop<ST>::ld(rc[cm + P], IS5[1]);
-    g[2] = Pop<ST>::ld(*p2, IS5[2]);
-    g[3] = Pop<ST>::ld(rc[cp + 3 * P], IS5[3]);
-    g[4] = Pop<ST>::ld(*p4, IS5[4]);
+    g[0] = Pop<ST>::ld(row_at(rc, cx), IS5[0]);
+    g[1] = Pop<ST>::ld(row_at(rc, cm + P), IS5[1]);
+    g[2] = Pop<ST>::ld(row_at(n.bot ? rc : rm, cx + (n.bot ? 4 : 2) * P), IS5[2]);
+    g[3] = Pop<ST>::ld(row_at(rc, cp + 3 * P), IS5[3]);
+    g[4] = Pop<ST>::ld(row_at(n.top ? rc : rp, cx + (n.top ? 2 : 4) * P), IS5[4]);
 }
 
 // streaming store that bypasses the caches' retention (the next pass reads it from HBM)
@@ -294,7 +301,8 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
     for (int r = 0; r < RP; ++r) {
         const int y = y0 + t / TILE_X + r * TILE_Y;
         active[r] = x < a.nx && y < a.ny;
-        const int xl = min(x, a.nx - 1), yl = min(y, a.ny - 1);
+        const int xl = min(x, a.nx - 1);
+        const int yl = __builtin_amdgcn_readfirstlane(min(y, a.ny - 1));   // one row per wavefront
         n[r] = neighbours(xl, yl, a.nx, a.ny, a.walls);
         pull9<ST>(a.fsrc, a.frow, n[r], f[r]);
 #pragma unroll
@@ -303,8 +311,7 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
         m[r] = 0;
         if constexpr (MASK) {
             // the row's two bit words are the same for the whole wavefront: scalar loads
-            const int wy = __builtin_amdgcn_readfirstlane(yl);
-            const unsigned* row = a.inside + (int64_t)wy * a.wpr + (x0 >> 5);
+            const unsigned* row = a.inside + (int64_t)yl * a.wpr + (x0 >> 5);
             const unsigned w0 = row[0];
             const unsigned w1 = (x0 + 32 < a.nx) ? row[1] : 0u;
             m[r] = (((x & 32) ? w1 : w0) >> (x & 31)) & 1u;
@@ -367,7 +374,7 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
             // equilibrium deviation w_i (drho + rho (3 vu + 4.5 vu^2 - 1.5 u^2))
             using T = typename Pop<ST>::T;
             constexpr int P = TILE_X;
-            T* __restrict__ d = (T*)a.fdst + (int64_t)n[r].y * a.frow + chunk_col(x, 9 * TILE_X);
+            T* __restrict__ d = row_ptr((T*)a.fdst + (int64_t)n[r].y * a.frow, chunk_col(x, 9 * TILE_X));
             store_nt(d, Pop<ST>::st(om1 * fr[0] + om * W0 * (drho - rho * usq), SC9[0]));
             float vu, eq;
             vu = ux;       eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); store_nt(d + P,     Pop<ST>::st(om1 * fr[1] + om * eq + W1 * fx, SC9[1]));
@@ -408,7 +415,7 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
                 const float* gg = g[r][s];
                 using T = typename Pop<ST>::T;
                 constexpr int P = TILE_X;
-                T* __restrict__ d = (T*)a.gdst + (int64_t)n[r].y * a.grow + chunk_col(x, a.gchunk) + 5 * s * P;
+                T* __restrict__ d = row_ptr((T*)a.gdst + (int64_t)n[r].y * a.grow, chunk_col(x, a.gchunk) + 5 * s * P);
                 // equilibrium deviation w_i (dphi + 3 phi v_i . u) and reaction w_i R
                 store_nt(d,         Pop<ST>::st(os1 * gg[0] + os * Q0 * dphi[s] + Q0 * R[s], SC5[0]));
                 store_nt(d + P,     Pop<ST>::st(os1 * gg[1] + os * Q1 * (dphi[s] + p3 * ux) + Q1 * R[s], SC5[1]));
@@ -428,11 +435,11 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
 }
 
 // Waves per SIMD the lattice pass is compiled for: the register budget that keeps the
-// population loads of RP rows in flight without spilling (96 VGPRs at two rows and one species;
-// the batched form, whose arguments come from a table, needs a few more).
-constexpr int lattice_waves(int S, int RP, bool batch)
+// population loads of RP rows in flight without spilling (96 VGPRs at two rows and one species,
+// for the single and the batched pass; a budget that spills costs far more than a wave).
+constexpr int lattice_waves(int S, int RP, bool)
 {
-    return RP == 1 ? 6 : RP == 2 ? ((S <= 1 && !batch) ? 5 : 4) : 3;
+    return RP == 1 ? 6 : RP == 2 ? (S <= 1 ? 5 : 4) : 3;
 }
 
 template <int S, bool NODES, bool MASK, int ST>
