@@ -166,6 +166,46 @@ def sweep_half(ws, steps: int, lbib, stream):
             "smallest_member_bit_identical": same}
 
 
+def storage_half(w, ref, warmup: int, steps: int, kt_steps: int, mlups32: float, lbib, stream):
+    """The same run with FP16 and BF16 population storage (collision in FP32): MLUPS, the
+    lattice kernel's time, and the relative L2 distance of each field from the FP32 run after
+    the same steps (ref: the FP32 run's fields)."""
+    import numpy as np
+    import torch
+    out = {}
+    nn = w.nx * w.ny
+
+    def rel(a, b):
+        nb = float(np.linalg.norm(b))
+        return float(np.linalg.norm(np.asarray(a) - np.asarray(b))) / (nb if nb > 0 else 1.0)
+    for name, st in (("fp16", lbib.STORAGE_FP16), ("bf16", lbib.STORAGE_BF16)):
+        sim = lbib.from_workload(w, stream=stream, storage=st)
+        sim.step(warmup)
+        sim.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.sync()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sim.set_timing(True)
+        sim.step(kt_steps)
+        ms, n = sim.get_timing(lbib.K_LATTICE)
+        sim.set_timing(False)
+        F = sim.get_fields(mask=False)
+        sim.close()
+        mlups = nn * steps / dt / 1e6
+        b_lat = lattice_bytes_per_update(w.n_species, w.mask_needed(), 2)
+        out[name] = {"value": round(mlups, 1), "speedup_vs_fp32": round(mlups / mlups32, 3),
+                     "lattice_us": round(ms / n * 1e3, 2),
+                     "lattice_frac_of_hbm": round(b_lat * nn / (ms / n / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "rel_l2_vs_fp32": {"rho-rho0": rel(F["rho"] - w.rho0, ref["rho"] - w.rho0), "u": rel(F["u"], ref["u"]),
+                                        "phi": rel(F["phi"], ref["phi"]), "X-X0": rel(F["xy"] - w.xy, ref["xy"] - w.xy)}}
+        log(f"storage {name}: {out[name]}")
+    out["steps_compared"] = warmup + steps + kt_steps
+    return out
+
+
 def cpu_baseline(w, budget_s: float = 12.0, max_steps: int = 30):
     from oracle import oracle as O
     log("cpu baseline: oracle on the same workload")
@@ -195,6 +235,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ade-samples", type=int, default=256,
                     help="held-out static-tissue samples for the iterations-to-steady half (0 skips)")
+    ap.add_argument("--no-storage-variants", action="store_true",
+                    help="skip the FP16 / BF16 storage runs reported beside the FP32 number")
     ap.add_argument("--sweep-sims", type=int, default=64,
                     help="simulations of the batched sweep (0 skips)")
     ap.add_argument("--sweep-steps", type=int, default=2000)
@@ -259,6 +301,7 @@ def main():
 
     # sanity: the state is finite after the timed run
     red = sim.reduce()
+    ref = sim.get_fields(mask=False) if args.storage == "fp32" and not args.no_storage_variants else None
     sim.close()
 
     nn = w.nx * w.ny
@@ -283,6 +326,8 @@ def main():
            "roofline": roof,
            "kernels_us": {k: round(ms / n * 1e3, 2) for k, (ms, n) in timings.items() if n},
            "mass": red[0]}
+    if ref is not None:
+        out["storage_variants"] = storage_half(w, ref, args.warmup, args.steps, kt_steps, mlups, lbib, stream)
     if samples:
         log(f"iterations to steady: {len(samples)} samples")
         out["ade_iters_to_steady"] = ade_half(samples, lbib, stream)

@@ -131,6 +131,15 @@ __device__ inline unsigned long long to_fixed(float v)
 
 constexpr int SPREAD_UNROLL = 1;   // listed nodes per thread whose loads are issued together
 
+// The tile's LDS arrays (spread force accumulators, staged velocity) hold rows of TILE_X + 1
+// entries: with the padding, stencil points of different rows in the same column fall into
+// different LDS banks (the membrane nodes a wavefront couples lie close together, so unpadded
+// rows made their atomics collide in the same banks).
+constexpr int LDS_ROW = TILE_X + 1;
+
+// LDS slot of row r of thread t (thread t covers column t % TILE_X of rows t / TILE_X + r TILE_Y)
+__device__ inline int lds_slot(int t, int r) { return (t / TILE_X + r * TILE_Y) * LDS_ROW + (t % TILE_X); }
+
 // Load one chunk of the tile's listed nodes [beg, end): list entry (node << 4 | rank of this
 // tile among the node's tiles; -1, which names no node, past the end), stencil origin, record.
 __device__ inline void load_candidates(const LatticeArgs& a, int k0, int end, int ij[SPREAD_UNROLL],
@@ -232,7 +241,7 @@ __device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0
             for (int aa = 0; aa < 4; ++aa) {
                 if (!((hx >> aa) & 1u)) continue;
                 const float w = wx[aa] * wy[bb];
-                const int o = ly[bb] * TILE_X + lx[aa];
+                const int o = ly[bb] * LDS_ROW + lx[aa];
                 atomicAdd(&accx[o], to_fixed(w * r.z));
                 atomicAdd(&accy[o], to_fixed(w * r.w));
                 if constexpr (INTERP) {
@@ -262,7 +271,7 @@ template <int S, bool NODES, bool MASK, int ST, int RP>
 __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int tile)
 {
     constexpr int LY = TILE_Y * RP;
-    constexpr int NL = NODES ? TILE_X * LY : 1;
+    constexpr int NL = NODES ? LDS_ROW * LY : 1;
     const int tcol = tile % a.ntx, trow = tile / a.ntx;
     const int x0 = tcol * TILE_X, y0 = trow * LY;
     const int x1 = min(x0 + TILE_X, a.nx), y1 = min(y0 + LY, a.ny);
@@ -285,8 +294,8 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
         load_entries(a, lbeg, lend, cnd);
 #pragma unroll
         for (int r = 0; r < RP; ++r) {
-            accx[t + r * TILE_N] = 0ull;
-            accy[t + r * TILE_N] = 0ull;
+            accx[lds_slot(t, r)] = 0ull;
+            accy[lds_slot(t, r)] = 0ull;
         }
     }
 
@@ -332,8 +341,8 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
         ux_r[r] = jx * inv;
         uy_r[r] = jy * inv;
         if constexpr (NODES) {
-            uxs[t + r * TILE_N] = ux_r[r];
-            uys[t + r * TILE_N] = uy_r[r];
+            uxs[lds_slot(t, r)] = ux_r[r];
+            uys[lds_slot(t, r)] = uy_r[r];
         }
     }
 
@@ -360,7 +369,7 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
         if (!active[r]) continue;
         float ex = a.bodyx, ey = a.bodyy;
         if constexpr (NODES) {
-            const int l = t + r * TILE_N;
+            const int l = lds_slot(t, r);
             ex += __ll2float_rn((long long)accx[l]) * FIX_INV;
             ey += __ll2float_rn((long long)accy[l]) * FIX_INV;
         }
@@ -469,10 +478,10 @@ __global__ __launch_bounds__(TILE_N) void k_spread_inspect(LatticeArgs a)
     const int x0 = tcol * TILE_X, y0 = trow * LY;
     const int x1 = min(x0 + TILE_X, a.nx), y1 = min(y0 + LY, a.ny);
     const int t = threadIdx.x;
-    __shared__ unsigned long long accx[TILE_X * LY], accy[TILE_X * LY];
+    __shared__ unsigned long long accx[LDS_ROW * LY], accy[LDS_ROW * LY];
     for (int r = 0; r < RPT; ++r) {
-        accx[t + r * TILE_N] = 0ull;
-        accy[t + r * TILE_N] = 0ull;
+        accx[lds_slot(t, r)] = 0ull;
+        accy[lds_slot(t, r)] = 0ull;
     }
     __syncthreads();
     if (a.t_off) {
@@ -488,7 +497,7 @@ __global__ __launch_bounds__(TILE_N) void k_spread_inspect(LatticeArgs a)
     for (int r = 0; r < RPT; ++r) {
         const int x = x0 + (t % TILE_X), y = y0 + t / TILE_X + r * TILE_Y;
         if (x >= a.nx || y >= a.ny) continue;
-        const int l = t + r * TILE_N;
+        const int l = lds_slot(t, r);
         const int64_t o = (int64_t)y * a.nx + x;
         a.e_out[o] = (double)(__ll2float_rn((long long)accx[l]) * FIX_INV + a.bodyx);
         a.e_out[a.nn + o] = (double)(__ll2float_rn((long long)accy[l]) * FIX_INV + a.bodyy);
