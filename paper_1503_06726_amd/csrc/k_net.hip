@@ -41,123 +41,228 @@ __device__ __host__ inline bf16 f2bf(float f)
     return (bf16)(r >> 16);
 }
 
-constexpr int NT_MAX = 4;
 constexpr int THREADS = 256;
 
 // ---------------------------------------------------------------------------------------
-// 3x3 convolution, forward: out[p][co] = act(sum_k patch[p][k] W[co][k] + bias[co])
-// block: 64 pixels (4 waves x 16) x 16 NT output channels
+// 3x3 convolution, forward, LDS-tiled: a workgroup computes CT_BM = 128 output pixels x BN
+// output channels.  K (9 taps x Cin) is walked in steps of KC channels of one tap; each step
+// stages the 128 x KC slice of the input patches and the BN x KC slice of the weights in LDS
+// (the next step's slices are fetched into registers while the current ones are multiplied),
+// and each wave multiplies 32 pixels x BN channels on MFMA 16x16x16.  Rows of the LDS tiles
+// are padded by 8 elements (16 bytes) to spread the fragment reads over the banks.
 // ---------------------------------------------------------------------------------------
-template <int NT, bool RELU, bool OUT_F32>
-__global__ __launch_bounds__(THREADS) void k_conv_fwd(const bf16* __restrict__ in, const bf16* __restrict__ W,
-                                                      const float* __restrict__ bias, void* __restrict__ out, int P,
-                                                      int H, int Wd, int Cin, int Cout)
+constexpr int CT_BM = 128;
+
+template <int BN, int KC, bool RELU, bool OUT_F32>
+__global__ __launch_bounds__(THREADS) void k_conv_tile(const bf16* __restrict__ in, const bf16* __restrict__ W,
+                                                       const float* __restrict__ bias, void* __restrict__ out, int P,
+                                                       int H, int Wd, int Cin, int Cout)
 {
-    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    constexpr int AROW = KC + 8;
+    constexpr int PPR = KC / 8;                                   // 16-byte pieces per row
+    constexpr int AP = (CT_BM * PPR + THREADS - 1) / THREADS;     // A pieces per thread
+    constexpr int BPIECES = BN * PPR;
+    constexpr int BPT = (BPIECES + THREADS - 1) / THREADS;        // B pieces per thread
+    constexpr int NJ = BN / 16;
+    __shared__ __attribute__((aligned(16))) bf16 As[CT_BM * AROW];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[BN * AROW];
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
     const int m = l & 15, kq = l >> 4;
-    const int p = blockIdx.x * 64 + w * 16 + m;                  // this lane's A row (pixel)
-    const int co0 = blockIdx.y * 16 * NT;
+    const int p0 = blockIdx.x * CT_BM;
+    const int co0 = blockIdx.y * BN;
     const int K = 9 * Cin;
     const int hw = H * Wd;
-    const int n = p / hw, rem = p - n * hw, y = rem / Wd, x = rem - y * Wd;
-    v4f acc[NT];
+
+    // the pieces this thread moves: A (pixel row, channel offset), B (channel row, offset)
+    int arow[AP], acol[AP], an[AP], ay[AP], ax[AP];
+    bool aok[AP];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int tap = 0; tap < 9; ++tap) {
-        const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-        const bool ok = p < P && yy >= 0 && yy < H && xx >= 0 && xx < Wd;
-        const bf16* arow = in + ((int64_t)(n * H + yy) * Wd + xx) * Cin + 4 * kq;
-        const bf16* brow = W + (int64_t)(co0 + m) * K + tap * Cin + 4 * kq;
-        for (int ci0 = 0; ci0 < Cin; ci0 += 16) {
-            v4s a = v4s{0, 0, 0, 0};
-            if (ok) a = *(const v4s*)(arow + ci0);
+    for (int i = 0; i < AP; ++i) {
+        const int idx = t + i * THREADS;
+        arow[i] = idx / PPR;
+        acol[i] = (idx % PPR) * 8;
+        const int p = p0 + arow[i];
+        aok[i] = idx < CT_BM * PPR && p < P;
+        const int pp = aok[i] ? p : 0;
+        an[i] = pp / hw;
+        const int rem = pp - an[i] * hw;
+        ay[i] = rem / Wd;
+        ax[i] = rem - ay[i] * Wd;
+    }
+    int brow[BPT], bcol[BPT];
+    bool bok[BPT];
 #pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const v4s b = *(const v4s*)(brow + (int64_t)16 * j * K + ci0);
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+    for (int i = 0; i < BPT; ++i) {
+        const int idx = t + i * THREADS;
+        bok[i] = idx < BPIECES;
+        brow[i] = bok[i] ? idx / PPR : 0;
+        bcol[i] = (idx % PPR) * 8;
+    }
+    uint4 ra[AP], rb[BPT];
+    auto fetch = [&](int step) {
+        const int tap = step / (Cin / KC), c0 = (step % (Cin / KC)) * KC;
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+#pragma unroll
+        for (int i = 0; i < AP; ++i) {
+            const int yy = ay[i] + dy, xx = ax[i] + dx;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (aok[i] && yy >= 0 && yy < H && xx >= 0 && xx < Wd)
+                v = *(const uint4*)(in + ((int64_t)(an[i] * H + yy) * Wd + xx) * Cin + c0 + acol[i]);
+            ra[i] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < BPT; ++i)
+            if (bok[i]) rb[i] = *(const uint4*)(W + (int64_t)(co0 + brow[i]) * K + tap * Cin + c0 + bcol[i]);
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int i = 0; i < AP; ++i)
+            if (t + i * THREADS < CT_BM * PPR) *(uint4*)(As + arow[i] * AROW + acol[i]) = ra[i];
+#pragma unroll
+        for (int i = 0; i < BPT; ++i)
+            if (bok[i]) *(uint4*)(Bs + brow[i] * AROW + bcol[i]) = rb[i];
+    };
+
+    v4f acc[2][NJ];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int nsteps = 9 * (Cin / KC);
+    fetch(0);
+    for (int st = 0; st < nsteps; ++st) {
+        stash();
+        __syncthreads();
+        if (st + 1 < nsteps) fetch(st + 1);
+#pragma unroll
+        for (int k0 = 0; k0 < KC; k0 += 16) {
+            v4s b[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) b[j] = *(const v4s*)(Bs + (16 * j + m) * AROW + k0 + 4 * kq);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const v4s a = *(const v4s*)(As + (32 * w + 16 * i + m) * AROW + k0 + 4 * kq);
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[j], acc[i][j], 0, 0, 0);
             }
         }
+        __syncthreads();
     }
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
+    for (int j = 0; j < NJ; ++j) {
         const int co = co0 + 16 * j + m;
         const float bv = bias ? bias[co] : 0.0f;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int po = blockIdx.x * 64 + w * 16 + 4 * kq + i;
-            if (po >= P) continue;
-            float v = acc[j][i] + bv;
-            if (RELU) v = fmaxf(v, 0.0f);
-            if (OUT_F32) ((float*)out)[(int64_t)po * Cout + co] = v;
-            else ((bf16*)out)[(int64_t)po * Cout + co] = f2bf(v);
-        }
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int po = p0 + 32 * w + 16 * i + 4 * kq + e;
+                if (po >= P) continue;
+                float v = acc[i][j][e] + bv;
+                if (RELU) v = fmaxf(v, 0.0f);
+                if (OUT_F32) ((float*)out)[(int64_t)po * Cout + co] = v;
+                else ((bf16*)out)[(int64_t)po * Cout + co] = f2bf(v);
+            }
     }
 }
 
 // ---------------------------------------------------------------------------------------
-// weight gradient: dW[co][k] += sum_p dZ[p][co] patch[p][k]  (MFMA over 16-pixel steps), and
-// the bias gradient db[co] += sum_p dZ[p][co].  block: 4 waves, each a share of the pixel chunk;
-// a wave's tile is 16 output channels x 16 NT values of k; partial tiles are added atomically.
+// weight gradient, LDS-tiled: dW[co][k] += sum_p dZ[p][co] patch[p][k] for a tile of BM output
+// channels x 64 values of k over a chunk of pixels, 64 pixels per step.  Both operands are
+// staged transposed ([co][pixel], [k][pixel]) so that a lane's MFMA fragment is four
+// consecutive pixels; a staging thread moves 4 pixels x 8 channels and writes each channel's
+// four pixels with one 8-byte LDS store.  Each wave owns 16 values of k.  Chunks of pixels are
+// added atomically.  The first k tile also sums the bias gradient db[co] += sum_p dZ[p][co].
 // ---------------------------------------------------------------------------------------
-template <int NT>
-__global__ __launch_bounds__(THREADS) void k_conv_wgrad(const bf16* __restrict__ in, const bf16* __restrict__ dZ,
-                                                        float* __restrict__ dW, float* __restrict__ db, int P, int H,
-                                                        int Wd, int Cin, int Cout, int chunk)
+constexpr int WG_PX = 64;
+
+// four pixels' value of one channel, packed for one LDS store
+__device__ inline uint2 pack4(const uint4 v[4], int q)
 {
-    const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const bf16 e0 = ((const bf16*)&v[0])[q], e1 = ((const bf16*)&v[1])[q];
+    const bf16 e2 = ((const bf16*)&v[2])[q], e3 = ((const bf16*)&v[3])[q];
+    return make_uint2((uint32_t)e0 | ((uint32_t)e1 << 16), (uint32_t)e2 | ((uint32_t)e3 << 16));
+}
+
+template <int BM>
+__global__ __launch_bounds__(THREADS) void k_conv_wgrad_tile(const bf16* __restrict__ in, const bf16* __restrict__ dZ,
+                                                             float* __restrict__ dW, float* __restrict__ db, int P,
+                                                             int H, int Wd, int Cin, int Cout, int chunk)
+{
+    constexpr int PR = WG_PX + 8;                                      // padded LDS row (pixels)
+    constexpr int NI = BM / 16;
+    constexpr int NA = (WG_PX / 4) * (BM / 8);                         // dZ pieces (<= 128)
+    constexpr int NB = (WG_PX / 4) * 8;                                // patch pieces (128)
+    __shared__ __attribute__((aligned(16))) bf16 At[BM * PR];          // dZ^T
+    __shared__ __attribute__((aligned(16))) bf16 Bt[64 * PR];          // patch^T
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
     const int m = l & 15, kq = l >> 4;
     const int K = 9 * Cin;
-    const int k0 = blockIdx.x * 16 * NT, co0 = blockIdx.y * 16;
+    const int k0 = blockIdx.x * 64, co0 = blockIdx.y * BM;
     const int pbeg = blockIdx.z * chunk, pend = min(P, pbeg + chunk);
     const int hw = H * Wd;
-    v4f acc[NT];
+    v4f acc[NI];
 #pragma unroll
-    for (int j = 0; j < NT; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < NI; ++i) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.0f;
-    // k columns of this lane for each j: tap and channel
-    int tapj[NT], cij[NT];
-#pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        const int k = k0 + 16 * j + m;
-        tapj[j] = k / Cin;
-        cij[j] = k - tapj[j] * Cin;
+    const bool bias_tile = db && blockIdx.x == 0;
+    // the staging piece of this thread: threads [0, NA) move dZ, [128, 128 + NB) the patches
+    const bool isA = t < NA, isB = t >= 128 && t - 128 < NB;
+    const int pa = isA ? t : t - 128;
+    const int px4 = (pa / (isA ? BM / 8 : 8)) * 4;                     // first of the four pixels
+    const int cp = (pa % (isA ? BM / 8 : 8)) * 8;                      // first channel / k
+    int tap = 0, ci = 0;
+    if (isB && k0 + cp < K) {
+        tap = (k0 + cp) / Cin;
+        ci = k0 + cp - tap * Cin;
     }
-    for (int pb = pbeg + 16 * w; pb < pend; pb += 64) {
-        v4s a;
-        short bj[NT][4];
+    for (int pb = pbeg; pb < pend; pb += WG_PX) {
+        uint4 v[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int pp = pb + 4 * kq + i;
-            bf16 dz = 0;
-            if (pp < pend) dz = dZ[(int64_t)pp * Cout + co0 + m];
-            a[i] = (short)dz;
-            const int n = pp / hw, rem = pp - n * hw, y = rem / Wd, x = rem - y * Wd;
-#pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const int yy = y + tapj[j] / 3 - 1, xx = x + tapj[j] % 3 - 1;
-                bf16 v = 0;
-                if (pp < pend && yy >= 0 && yy < H && xx >= 0 && xx < Wd)
-                    v = in[((int64_t)(n * H + yy) * Wd + xx) * Cin + cij[j]];
-                bj[j][i] = (short)v;
+        for (int j = 0; j < 4; ++j) {
+            v[j] = make_uint4(0u, 0u, 0u, 0u);
+            const int p = pb + px4 + j;
+            if (p >= pend) continue;
+            if (isA) {
+                v[j] = *(const uint4*)(dZ + (int64_t)p * Cout + co0 + cp);
+            } else if (isB && k0 + cp < K) {
+                const int n = p / hw, rem = p - n * hw, y = rem / Wd, x = rem - y * Wd;
+                const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+                if (yy >= 0 && yy < H && xx >= 0 && xx < Wd)
+                    v[j] = *(const uint4*)(in + ((int64_t)(n * H + yy) * Wd + xx) * Cin + ci);
             }
         }
-        // lane (m, kq) holds dZ of channel co0 + m at 4 of the 16 pixels: the four lane groups
-        // together cover them all, once (the first k tile only)
-        if (db && blockIdx.x == 0) bsum += bf2f((bf16)a[0]) + bf2f((bf16)a[1]) + bf2f((bf16)a[2]) + bf2f((bf16)a[3]);
+        if (isA) {
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const v4s b = v4s{bj[j][0], bj[j][1], bj[j][2], bj[j][3]};
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+            for (int q = 0; q < 8; ++q) *(uint2*)(At + (cp + q) * PR + px4) = pack4(v, q);
+        } else if (isB) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) *(uint2*)(Bt + (cp + q) * PR + px4) = pack4(v, q);
         }
+        __syncthreads();
+        if (bias_tile && t < BM)
+            for (int px = 0; px < WG_PX; ++px) bsum += bf2f(At[t * PR + px]);
+#pragma unroll
+        for (int r0 = 0; r0 < WG_PX; r0 += 16) {
+            const v4s b = *(const v4s*)(Bt + (16 * w + m) * PR + r0 + 4 * kq);
+#pragma unroll
+            for (int i = 0; i < NI; ++i) {
+                const v4s a = *(const v4s*)(At + (16 * i + m) * PR + r0 + 4 * kq);
+                acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[i], 0, 0, 0);
+            }
+        }
+        __syncthreads();
     }
+    const int k = k0 + 16 * w + m;
+    if (k < K)
 #pragma unroll
-    for (int j = 0; j < NT; ++j)
+        for (int i = 0; i < NI; ++i)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int co = co0 + 4 * kq + i, k = k0 + 16 * j + m;
-            if (acc[j][i] != 0.0f) atomicAdd(&dW[(int64_t)co * K + k], acc[j][i]);
-        }
-    if (db && blockIdx.x == 0 && bsum != 0.0f) atomicAdd(&db[co0 + m], bsum);
+            for (int e = 0; e < 4; ++e) {
+                const int co = co0 + 16 * i + 4 * kq + e;
+                if (acc[i][e] != 0.0f) atomicAdd(&dW[(int64_t)co * K + k], acc[i][e]);
+            }
+    if (bias_tile && t < BM && bsum != 0.0f) atomicAdd(&db[co0 + t], bsum);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -173,69 +278,102 @@ __global__ void k_pack_input(const float* __restrict__ src, bf16* __restrict__ d
     dst[i] = c < 8 ? f2bf(src[p * 8 + c]) : (bf16)0;
 }
 
+// The elementwise layers move eight channels (16 bytes) per thread: every channel count is a
+// multiple of 16.
+struct bf8 {
+    uint4 v;
+    __device__ float get(int q) const { return bf2f(((const bf16*)&v)[q]); }
+    __device__ void set(int q, float f) { ((bf16*)&v)[q] = f2bf(f); }
+};
+__device__ inline bf8 ld8(const bf16* p) { return bf8{*(const uint4*)p}; }
+__device__ inline void st8(bf16* p, const bf8& x) { *(uint4*)p = x.v; }
+
 // 2x2 average pool: [B][H][W][C] -> [B][H/2][W/2][C]
 __global__ void k_pool(const bf16* __restrict__ in, bf16* __restrict__ out, int B, int H, int Wd, int C)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int h2 = H / 2, w2 = Wd / 2;
-    if (i >= (int64_t)B * h2 * w2 * C) return;
-    const int c = (int)(i % C);
-    const int64_t q = i / C;
+    const int h2 = H / 2, w2 = Wd / 2, C8 = C / 8;
+    if (i >= (int64_t)B * h2 * w2 * C8) return;
+    const int c = (int)(i % C8) * 8;
+    const int64_t q = i / C8;
     const int x = (int)(q % w2), y = (int)((q / w2) % h2), n = (int)(q / ((int64_t)w2 * h2));
     const bf16* s = in + ((int64_t)(n * H + 2 * y) * Wd + 2 * x) * C + c;
-    const float v = (bf2f(s[0]) + bf2f(s[C])) + (bf2f(s[(int64_t)Wd * C]) + bf2f(s[(int64_t)Wd * C + C]));
-    out[i] = f2bf(0.25f * v);
+    const bf8 a = ld8(s), b = ld8(s + C), d = ld8(s + (int64_t)Wd * C), e = ld8(s + (int64_t)Wd * C + C);
+    bf8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o.set(k, 0.25f * ((a.get(k) + b.get(k)) + (d.get(k) + e.get(k))));
+    st8(out + q * C + c, o);
 }
 
 // gradient of the pool: dIn (+)= dOut / 4 at the four inputs
 __global__ void k_pool_bwd(const bf16* __restrict__ dout, bf16* __restrict__ din, int B, int H, int Wd, int C, int add)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)B * H * Wd * C) return;
-    const int c = (int)(i % C);
-    const int64_t q = i / C;
+    const int C8 = C / 8;
+    if (i >= (int64_t)B * H * Wd * C8) return;
+    const int c = (int)(i % C8) * 8;
+    const int64_t q = i / C8;
     const int x = (int)(q % Wd), y = (int)((q / Wd) % H), n = (int)(q / ((int64_t)Wd * H));
-    float v = 0.25f * bf2f(dout[((int64_t)(n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * C + c]);
-    if (add) v += bf2f(din[i]);
-    din[i] = f2bf(v);
+    const bf8 g = ld8(dout + ((int64_t)(n * (H / 2) + y / 2) * (Wd / 2) + x / 2) * C + c);
+    bf8 o{make_uint4(0u, 0u, 0u, 0u)};
+    if (add) o = ld8(din + q * C + c);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o.set(k, 0.25f * g.get(k) + (add ? o.get(k) : 0.0f));
+    st8(din + q * C + c, o);
 }
 
 // nearest 2x upsample: [B][H][W][C] -> [B][2H][2W][C]
 __global__ void k_up(const bf16* __restrict__ in, bf16* __restrict__ out, int B, int H, int Wd, int C)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int H2 = 2 * H, W2 = 2 * Wd;
-    if (i >= (int64_t)B * H2 * W2 * C) return;
-    const int c = (int)(i % C);
-    const int64_t q = i / C;
+    const int H2 = 2 * H, W2 = 2 * Wd, C8 = C / 8;
+    if (i >= (int64_t)B * H2 * W2 * C8) return;
+    const int c = (int)(i % C8) * 8;
+    const int64_t q = i / C8;
     const int x = (int)(q % W2), y = (int)((q / W2) % H2), n = (int)(q / ((int64_t)W2 * H2));
-    out[i] = in[((int64_t)(n * H + y / 2) * Wd + x / 2) * C + c];
+    st8(out + q * C + c, ld8(in + ((int64_t)(n * H + y / 2) * Wd + x / 2) * C + c));
 }
 
 // gradient of the upsample: dIn = sum of the four dOut
 __global__ void k_up_bwd(const bf16* __restrict__ dout, bf16* __restrict__ din, int B, int H, int Wd, int C)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)B * H * Wd * C) return;
-    const int c = (int)(i % C);
-    const int64_t q = i / C;
+    const int C8 = C / 8;
+    if (i >= (int64_t)B * H * Wd * C8) return;
+    const int c = (int)(i % C8) * 8;
+    const int64_t q = i / C8;
     const int x = (int)(q % Wd), y = (int)((q / Wd) % H), n = (int)(q / ((int64_t)Wd * H));
     const int64_t W2 = 2 * Wd;
     const bf16* s = dout + ((int64_t)(n * 2 * H + 2 * y) * W2 + 2 * x) * C + c;
-    din[i] = f2bf((bf2f(s[0]) + bf2f(s[C])) + (bf2f(s[W2 * C]) + bf2f(s[W2 * C + C])));
+    const bf8 a = ld8(s), b = ld8(s + C), d = ld8(s + W2 * C), e = ld8(s + W2 * C + C);
+    bf8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o.set(k, (a.get(k) + b.get(k)) + (d.get(k) + e.get(k)));
+    st8(din + q * C + c, o);
 }
 
-__global__ void k_add(const bf16* __restrict__ a, const bf16* __restrict__ b, bf16* __restrict__ out, int64_t n)
+// n8: number of eight-channel groups
+__global__ void k_add(const bf16* __restrict__ a, const bf16* __restrict__ b, bf16* __restrict__ out, int64_t n8)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = f2bf(bf2f(a[i]) + bf2f(b[i]));
+    if (i >= n8) return;
+    const bf8 x = ld8(a + 8 * i), y = ld8(b + 8 * i);
+    bf8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o.set(k, x.get(k) + y.get(k));
+    st8(out + 8 * i, o);
 }
 
 // dZ = dY * [Y > 0]
-__global__ void k_relu_bwd(const bf16* __restrict__ dy, const bf16* __restrict__ y, bf16* __restrict__ dz, int64_t n)
+__global__ void k_relu_bwd(const bf16* __restrict__ dy, const bf16* __restrict__ y, bf16* __restrict__ dz, int64_t n8)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dz[i] = bf2f(y[i]) > 0.0f ? dy[i] : (bf16)0;
+    if (i >= n8) return;
+    const bf8 g = ld8(dy + 8 * i), v = ld8(y + 8 * i);
+    bf8 o;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ((bf16*)&o.v)[k] = v.get(k) > 0.0f ? ((const bf16*)&g.v)[k] : (bf16)0;
+    st8(dz + 8 * i, o);
 }
 
 // weights for the data gradient: Wf[ci][tap * Cout + co] = W[co][(8 - tap) * Cin + ci]
@@ -384,31 +522,39 @@ bool nalloc(lbib_net* n, T** p, size_t count)
         if (hipGetLastError() != hipSuccess) return false; \
     } while (0)
 
+template <int BN, int KC>
+bool conv_tile(hipStream_t s, const bf16* in, void* out, bool relu, bool out_f32, const bf16* W, const float* bias,
+               int P, int H, int Wd, int Cin, int Cout)
+{
+    const dim3 grid((unsigned)((P + CT_BM - 1) / CT_BM), (unsigned)(Cout / BN));
+    if (out_f32) {
+        NET_K(hipLaunchKernelGGL((k_conv_tile<BN, KC, false, true>), grid, dim3(THREADS), 0, s, in, W, bias, out, P, H, Wd,
+                                 Cin, Cout));
+    } else if (relu) {
+        NET_K(hipLaunchKernelGGL((k_conv_tile<BN, KC, true, false>), grid, dim3(THREADS), 0, s, in, W, bias, out, P, H, Wd,
+                                 Cin, Cout));
+    } else {
+        NET_K(hipLaunchKernelGGL((k_conv_tile<BN, KC, false, false>), grid, dim3(THREADS), 0, s, in, W, bias, out, P, H,
+                                 Wd, Cin, Cout));
+    }
+    return true;
+}
+
+// Cin and Cout are multiples of 16 (the activations' channel counts)
 bool conv_fwd(lbib_net* n, int l, const bf16* in, void* out, int B, bool relu, bool out_f32, const bf16* W,
               const float* bias, int Cin, int Cout)
 {
     const int div = LAYER_DIV[l];
     const int H = n->H / div, Wd = n->Wd / div;
     const int P = B * H * Wd;
-    const int NT = (Cout % 64 == 0) ? 4 : (Cout % 32 == 0 ? 2 : 1);
-    const dim3 grid((unsigned)((P + 63) / 64), (unsigned)(Cout / (16 * NT)));
     hipStream_t s = n->stream;
-    if (out_f32) {
-        NET_K(hipLaunchKernelGGL((k_conv_fwd<1, false, true>), dim3(grid.x, Cout / 16), dim3(THREADS), 0, s, in, W,
-                                 bias, out, P, H, Wd, Cin, Cout));
-        return true;
-    }
-    if (NT == 4) {
-        if (relu) NET_K(hipLaunchKernelGGL((k_conv_fwd<4, true, false>), grid, dim3(THREADS), 0, s, in, W, bias, out, P, H, Wd, Cin, Cout));
-        else NET_K(hipLaunchKernelGGL((k_conv_fwd<4, false, false>), grid, dim3(THREADS), 0, s, in, W, bias, out, P, H, Wd, Cin, Cout));
-    } else if (NT == 2) {
-        if (relu) NET_K(hipLaunchKernelGGL((k_conv_fwd<2, true, false>), grid, dim3(THREADS), 0, s, in, W, bias, out, P, H, Wd, Cin, Cout));
-        else NET_K(hipLaunchKernelGGL((k_conv_fwd<2, false, false>), grid, dim3(THREADS), 0, s, in, W, bias, out, P, H, Wd, Cin, Cout));
-    } else {
-        if (relu) NET_K(hipLaunchKernelGGL((k_conv_fwd<1, true, false>), grid, dim3(THREADS), 0, s, in, W, bias, out, P, H, Wd, Cin, Cout));
-        else NET_K(hipLaunchKernelGGL((k_conv_fwd<1, false, false>), grid, dim3(THREADS), 0, s, in, W, bias, out, P, H, Wd, Cin, Cout));
-    }
-    return true;
+    const bool k32 = Cin % 32 == 0;
+    if (Cout % 64 == 0) return k32 ? conv_tile<64, 32>(s, in, out, relu, out_f32, W, bias, P, H, Wd, Cin, Cout)
+                                   : conv_tile<64, 16>(s, in, out, relu, out_f32, W, bias, P, H, Wd, Cin, Cout);
+    if (Cout % 32 == 0) return k32 ? conv_tile<32, 32>(s, in, out, relu, out_f32, W, bias, P, H, Wd, Cin, Cout)
+                                   : conv_tile<32, 16>(s, in, out, relu, out_f32, W, bias, P, H, Wd, Cin, Cout);
+    return k32 ? conv_tile<16, 32>(s, in, out, relu, out_f32, W, bias, P, H, Wd, Cin, Cout)
+               : conv_tile<16, 16>(s, in, out, relu, out_f32, W, bias, P, H, Wd, Cin, Cout);
 }
 
 const bf16* WB(lbib_net* n, int l) { return n->wbf + n->woff[l]; }
@@ -425,19 +571,19 @@ bool forward(lbib_net* n, const float* inputs, int B)
     };
     auto pool = [&](int in, int out) {
         const int div = ACT_SHAPE[in].div;
-        hipLaunchKernelGGL(k_pool, dim3(nblk(act_elems(n, out, B))), dim3(THREADS), 0, s, A(in), A(out), B,
+        hipLaunchKernelGGL(k_pool, dim3(nblk(act_elems(n, out, B) / 8)), dim3(THREADS), 0, s, A(in), A(out), B,
                            n->H / div, n->Wd / div, ACT_SHAPE[in].C);
         return hipGetLastError() == hipSuccess;
     };
     auto up = [&](int in, int out) {
         const int div = ACT_SHAPE[in].div;
-        hipLaunchKernelGGL(k_up, dim3(nblk(act_elems(n, out, B))), dim3(THREADS), 0, s, A(in), A(out), B,
+        hipLaunchKernelGGL(k_up, dim3(nblk(act_elems(n, out, B) / 8)), dim3(THREADS), 0, s, A(in), A(out), B,
                            n->H / div, n->Wd / div, ACT_SHAPE[in].C);
         return hipGetLastError() == hipSuccess;
     };
     auto add = [&](int a, int b, int out) {
-        hipLaunchKernelGGL(k_add, dim3(nblk(act_elems(n, out, B))), dim3(THREADS), 0, s, A(a), A(b), A(out),
-                           act_elems(n, out, B));
+        hipLaunchKernelGGL(k_add, dim3(nblk(act_elems(n, out, B) / 8)), dim3(THREADS), 0, s, A(a), A(b), A(out),
+                           act_elems(n, out, B) / 8);
         return hipGetLastError() == hipSuccess;
     };
     bool ok = conv(0, X0, A0, true) && conv(1, A0, S0, true) && pool(S0, P0) && conv(2, P0, A1, true) &&
@@ -458,16 +604,22 @@ bool conv_bwd(lbib_net* n, int l, const bf16* in, const bf16* dz, bf16* din, int
     const int div = LAYER_DIV[l];
     const int H = n->H / div, Wd = n->Wd / div, P = B * H * Wd;
     const int Cin = LAYER_CIN[l], Cout = LAYER_COUT[l], K = 9 * Cin;
-    const int chunk = 4096;
-    const unsigned nz = (unsigned)((P + chunk - 1) / chunk);
     float* dW = n->grad + n->woff[l];
     float* db = n->grad + n->boff[l];
-    if (K % 64 == 0)
-        NET_K(hipLaunchKernelGGL(k_conv_wgrad<4>, dim3(K / 64, Cout / 16, nz), dim3(THREADS), 0, s, in, dz, dW, db, P, H,
-                                 Wd, Cin, Cout, chunk));
+    // pixel chunks: about 2048 workgroups in all, at least ~1024 pixels each
+    const int BM = Cout >= 64 ? 64 : Cout;
+    const int tiles = ((K + 63) / 64) * (Cout / BM);
+    int nchunk = std::max(1, std::min(2048 / tiles, (P + 1023) / 1024));
+    int chunk = (P + nchunk - 1) / nchunk;
+    chunk = (chunk + WG_PX - 1) / WG_PX * WG_PX;
+    nchunk = (P + chunk - 1) / chunk;
+    const dim3 grid((unsigned)((K + 63) / 64), (unsigned)(Cout / BM), (unsigned)nchunk);
+    if (BM == 64)
+        NET_K(hipLaunchKernelGGL(k_conv_wgrad_tile<64>, grid, dim3(THREADS), 0, s, in, dz, dW, db, P, H, Wd, Cin, Cout, chunk));
+    else if (BM == 32)
+        NET_K(hipLaunchKernelGGL(k_conv_wgrad_tile<32>, grid, dim3(THREADS), 0, s, in, dz, dW, db, P, H, Wd, Cin, Cout, chunk));
     else
-        NET_K(hipLaunchKernelGGL(k_conv_wgrad<1>, dim3(K / 16, Cout / 16, nz), dim3(THREADS), 0, s, in, dz, dW, db, P, H,
-                                 Wd, Cin, Cout, chunk));
+        NET_K(hipLaunchKernelGGL(k_conv_wgrad_tile<16>, grid, dim3(THREADS), 0, s, in, dz, dW, db, P, H, Wd, Cin, Cout, chunk));
     if (din) {
         NET_K(hipLaunchKernelGGL(k_flip, dim3(nblk((int64_t)9 * Cin * Cout)), dim3(THREADS), 0, s, WB(n, l), n->wflip, Cin,
                                  Cout));
@@ -483,19 +635,19 @@ bool backward(lbib_net* n, int B)
     auto G = [&](int k) { return n->gr[k]; };
     auto relu_bwd = [&](int y, bf16* dy, bf16* dz) {
         const int64_t e = act_elems(n, y, B);
-        hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(e)), dim3(THREADS), 0, s, dy, A(y), dz, e);
+        hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(e / 8)), dim3(THREADS), 0, s, dy, A(y), dz, e / 8);
         return hipGetLastError() == hipSuccess;
     };
     auto up_bwd = [&](int up_out, int in_slot, bf16* dout, bf16* din) {
         const int div = ACT_SHAPE[in_slot].div;
-        hipLaunchKernelGGL(k_up_bwd, dim3(nblk(act_elems(n, in_slot, B))), dim3(THREADS), 0, s, dout, din, B,
+        hipLaunchKernelGGL(k_up_bwd, dim3(nblk(act_elems(n, in_slot, B) / 8)), dim3(THREADS), 0, s, dout, din, B,
                            n->H / div, n->Wd / div, ACT_SHAPE[in_slot].C);
         (void)up_out;
         return hipGetLastError() == hipSuccess;
     };
     auto pool_bwd = [&](int in_slot, bf16* dout, bf16* din, int add) {
         const int div = ACT_SHAPE[in_slot].div;
-        hipLaunchKernelGGL(k_pool_bwd, dim3(nblk(act_elems(n, in_slot, B))), dim3(THREADS), 0, s, dout, din, B,
+        hipLaunchKernelGGL(k_pool_bwd, dim3(nblk(act_elems(n, in_slot, B) / 8)), dim3(THREADS), 0, s, dout, din, B,
                            n->H / div, n->Wd / div, ACT_SHAPE[in_slot].C, add);
         return hipGetLastError() == hipSuccess;
     };
