@@ -26,7 +26,7 @@ METRIC = "coupled LBM+IB MLUPS at 2048²/2000 cells (% HBM peak); ADE iters-to-s
 HBM_PEAK_GBS = 8000.0
 # HBM traffic per launch of the lattice kernel measured with rocprofv3 --pmc (FETCH_SIZE,
 # WRITE_SIZE, scaled by a copy kernel of known size); None until taken for the current kernel
-LATTICE_TRAFFIC_BYTES = 507_884_743
+LATTICE_TRAFFIC_BYTES = 507_895_893
 
 
 def log(*a):
@@ -130,8 +130,8 @@ def sweep_half(ws, steps: int, lbib, stream):
     t_seq = time.perf_counter() - t0
     log(f"sweep: sequential {steps} steps of {len(ws)} simulations: {t_seq:.3f} s")
     batch = lbib.Batch(B, stream=stream)
-    rows, tune = batch.autotune(periods=4)
-    log(f"sweep: autotuned tile height {rows} rows; ms per step {tune}")
+    rows, groups, tune = batch.autotune(periods=4)
+    log(f"sweep: autotuned tile height {rows} rows, {groups} groups; ms per step {tune}")
     batch.step(16)
     batch.sync()
     torch.cuda.synchronize()
@@ -143,7 +143,7 @@ def sweep_half(ws, steps: int, lbib, stream):
     log(f"sweep: batched {steps} steps: {t_bat:.3f} s")
     # both sets have now taken 16 + steps steps; at the default tile height they agree bit for bit
     same = None
-    if rows == 8:
+    if rows == 8:                          # (either grouping)
         i = int(np.argmin([w.nx * w.ny for w in ws]))
         fa, fb = A[i].get_fields(mask=False), B[i].get_fields(mask=False)
         same = all(np.array_equal(fa[k], fb[k]) for k in ("rho", "u", "phi", "xy"))
@@ -162,7 +162,8 @@ def sweep_half(ws, steps: int, lbib, stream):
             "batched_ms_per_step": round(t_bat / steps * 1e3, 4),
             "sequential_ms_per_step": round(t_seq / steps * 1e3, 4),
             "batched_lattice_bytes_frac_of_hbm": round(b_up * bat * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
-            "tile_rows": rows, "autotune_ms_per_step": {str(k): round(v, 4) for k, v in tune.items()},
+            "tile_rows": rows, "groups": groups,
+            "autotune_ms_per_step": {f"{g} groups, {h} rows": round(v, 4) for (g, h), v in tune.items()},
             "smallest_member_bit_identical": same}
 
 

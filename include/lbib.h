@@ -197,10 +197,13 @@ lbib_status lbib_ade_batch(int32_t nx, int32_t ny, int32_t bc_y, int32_t batch, 
  * tissue at a time; a batch adopts existing contexts, of any lattice sizes and cell counts,
  * and advances them together: each kernel of the step (Fig. "Algorithm Overview": lattice
  * pass with spreading and interpolation, node advection and forces, list rebuild) runs once
- * per step over every simulation, and whole list periods (16 steps) replay one captured HIP
- * graph.  Each simulation's arithmetic is that of lbib_step: with the default tile height (8
- * rows) a batched simulation is bit-identical to the same simulation stepped alone; another
- * tile height changes only the grouping of the interpolation sums (round-off level).
+ * per step over every simulation of a group, and whole list periods (16 steps) replay one
+ * captured HIP graph.  The simulations form one group, or two groups of about equal lattice
+ * size whose step chains run on two streams (one group's latency-bound membrane and list
+ * kernels then overlap the other's lattice pass).  Each simulation's arithmetic is that of
+ * lbib_step: with the default tile height (8 rows) a batched simulation is bit-identical to
+ * the same simulation stepped alone, in either grouping; another tile height changes only the
+ * grouping of the interpolation sums (round-off level).
  * While adopted, a context's own lbib_step, lbib_set_cells, lbib_set_fields,
  * lbib_set_source_cells and lbib_ade_steady return LBIB_ESTATE; its reads (lbib_get_fields,
  * lbib_get_forces, lbib_get_spread, lbib_reduce, lbib_sync) wait for the batch's last
@@ -229,13 +232,19 @@ lbib_status lbib_batch_sync(lbib_batch* b);
 lbib_status lbib_batch_get_tile(const lbib_batch* b, int32_t* rows);
 lbib_status lbib_batch_set_tile(lbib_batch* b, int32_t rows);
 
+/* Number of groups (1, the default, or 2; LBIB_EINVAL otherwise).  Changing it is allowed only
+ * after a whole number of 16-step periods (LBIB_ESTATE). */
+lbib_status lbib_batch_get_groups(const lbib_batch* b, int32_t* groups);
+lbib_status lbib_batch_set_groups(lbib_batch* b, int32_t groups);
+
 /* Autotuner: time `periods` 16-step periods (after one warm-up period) of the batch at every
- * admissible tile height, on a copy of the simulations' state that is restored afterwards
- * (the simulations do not advance), and keep the fastest.  rows receives it; ms_per_step
- * (NULL, or 3 host doubles) receives the time per step of heights 4, 8, 16 (-1 where not
- * admissible).  Needs device memory for one copy of every simulation's state; only after a
- * whole number of periods (LBIB_ESTATE); synchronises. */
-lbib_status lbib_batch_autotune(lbib_batch* b, int32_t periods, int32_t* rows, double* ms_per_step);
+ * admissible tile height in one and in two groups, on a copy of the simulations' state that is
+ * restored afterwards (the simulations do not advance), and keep the fastest.  rows and groups
+ * (each NULL or one host int32) receive it; ms_per_step (NULL, or 6 host doubles) receives the
+ * time per step of heights 4, 8, 16 in one group, then in two (-1 where not admissible).
+ * Needs device memory for one copy of every simulation's state; only after a whole number of
+ * periods (LBIB_ESTATE); synchronises. */
+lbib_status lbib_batch_autotune(lbib_batch* b, int32_t periods, int32_t* rows, int32_t* groups, double* ms_per_step);
 
 /* Last error message of the batch (never NULL). */
 const char* lbib_batch_last_error(const lbib_batch* b);

@@ -2,12 +2,16 @@
 // advanced together.  Every kernel of the coupled step runs once per step for the whole batch:
 // a work table lists (simulation, tile), (simulation, cell) or (simulation, node block) items
 // and a per-simulation argument table, one per buffer parity, names each simulation's buffers.
-// Whole list periods are captured as one HIP graph and replayed.  The arithmetic is that of
-// the single-simulation kernels (the same device functions), so with the default tile shape a
-// batched simulation is bit-identical to the same simulation stepped alone.
+// Whole list periods are captured as one HIP graph and replayed.  The simulations form one or
+// two groups of about equal lattice size; two groups step as two chains on two streams (one
+// graph), so that one group's latency-bound membrane and list kernels run beside the other's
+// bandwidth-bound lattice pass.  The arithmetic is that of the single-simulation kernels (the
+// same device functions), so with the default tile shape a batched simulation is
+// bit-identical to the same simulation stepped alone, whatever the grouping.
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <numeric>
 #include <set>
 #include <vector>
 
@@ -74,46 +78,85 @@ void drop_graph(lbib_batch* b)
     b->graph = nullptr;
 }
 
-// argument tables of both parities and the list table / work tables for tile height lty
+void free_groups(lbib_batch* b)
+{
+    for (lbib_batch_group& g : b->groups) {
+        for (int p = 0; p < 2; ++p) {
+            free_dev(g.d_lat[p]);
+            free_dev(g.d_mem[p]);
+        }
+        free_dev(g.d_list);
+        free_dev(g.d_lat_work);
+        free_dev(g.d_mem_work);
+        free_dev(g.d_node_work);
+    }
+    b->groups.clear();
+}
+
+// the simulations split into ngroups groups of about equal lattice size (largest first, each
+// into the lightest group), then, per group, the argument tables of both parities, the list
+// table and the work tables for tile height lty
 lbib_status build_tables(lbib_batch* b, int lty)
 {
     const int n = (int)b->sims.size();
-    std::vector<LatticeArgs> lat[2];
-    std::vector<MembraneArgs> mem[2];
-    std::vector<ListArgs> lst;
-    std::vector<int2> wl, wm, wn;
-    for (int s = 0; s < n; ++s) {
-        lbib_ctx* c = b->sims[s];
-        for (int p = 0; p < 2; ++p) {
-            lat[p].push_back(lattice_args_at(c, b->cur0[s] ^ p));
-            // the membrane pass of a step reads and writes the buffers of the step's end
-            mem[p].push_back(membrane_args_at(c, b->cur0[s] ^ p ^ 1, 1));
+    const int G = std::max(1, std::min(b->ngroups, n));
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->sims[x]->nn > b->sims[y]->nn; });
+    std::vector<std::vector<int>> members(G);
+    std::vector<int64_t> load(G, 0);
+    for (int s : order) {
+        const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        members[g].push_back(s);
+        load[g] += b->sims[s]->nn;
+    }
+    free_groups(b);
+    b->groups.resize(G);
+    for (int g = 0; g < G; ++g) {
+        lbib_batch_group& grp = b->groups[g];
+        grp.sims = members[g];
+        std::sort(grp.sims.begin(), grp.sims.end());
+        std::vector<LatticeArgs> lat[2];
+        std::vector<MembraneArgs> mem[2];
+        std::vector<ListArgs> lst;
+        std::vector<int2> wl, wm, wn;
+        for (int gs = 0; gs < (int)grp.sims.size(); ++gs) {
+            const int s = grp.sims[gs];
+            lbib_ctx* c = b->sims[s];
+            for (int p = 0; p < 2; ++p) {
+                lat[p].push_back(lattice_args_at(c, b->cur0[s] ^ p));
+                // the membrane pass of a step reads and writes the buffers of the step's end
+                mem[p].push_back(membrane_args_at(c, b->cur0[s] ^ p ^ 1, 1));
+            }
+            const ListArgs la = list_args_h(c, lty);
+            lst.push_back(la);
+            for (int t = 0; t < la.ntiles; ++t) wl.push_back(make_int2(gs, t));
+            for (int q = 0; q < c->n_cells; ++q) wm.push_back(make_int2(gs, q));
+            const int64_t nb = (c->n_nodes + LIST_THREADS - 1) / LIST_THREADS;
+            for (int64_t q = 0; q < nb; ++q) wn.push_back(make_int2(gs, (int)q));
+            grp.max_cell_nodes = std::max(grp.max_cell_nodes, c->max_cell_nodes);
         }
-        const ListArgs la = list_args_h(c, lty);
-        lst.push_back(la);
-        for (int t = 0; t < la.ntiles; ++t) wl.push_back(make_int2(s, t));
-        for (int q = 0; q < c->n_cells; ++q) wm.push_back(make_int2(s, q));
-        const int64_t nb = (c->n_nodes + LIST_THREADS - 1) / LIST_THREADS;
-        for (int64_t q = 0; q < nb; ++q) wn.push_back(make_int2(s, (int)q));
+        if (wl.size() > 0x7FFFFFFF || wm.size() > 0x7FFFFFFF || wn.size() > 0x7FFFFFFF) {
+            b->err = "batch too large for one launch";
+            return LBIB_EINVAL;
+        }
+        for (int p = 0; p < 2; ++p) {
+            BATCH_TRY(upload(b, grp.d_lat[p], lat[p]));
+            BATCH_TRY(upload(b, grp.d_mem[p], mem[p]));
+        }
+        BATCH_TRY(upload(b, grp.d_list, lst));
+        BATCH_TRY(upload(b, grp.d_lat_work, wl));
+        BATCH_TRY(upload(b, grp.d_mem_work, wm));
+        BATCH_TRY(upload(b, grp.d_node_work, wn));
+        grp.n_lat_work = (int)wl.size();
+        grp.n_mem_work = (int)wm.size();
+        grp.n_node_work = (int)wn.size();
     }
-    if (wl.size() > 0x7FFFFFFF || wm.size() > 0x7FFFFFFF || wn.size() > 0x7FFFFFFF) {
-        b->err = "batch too large for one launch";
-        return LBIB_EINVAL;
-    }
-    for (int p = 0; p < 2; ++p) {
-        BATCH_TRY(upload(b, b->d_lat[p], lat[p]));
-        BATCH_TRY(upload(b, b->d_mem[p], mem[p]));
-    }
-    BATCH_TRY(upload(b, b->d_list, lst));
-    BATCH_TRY(upload(b, b->d_lat_work, wl));
-    BATCH_TRY(upload(b, b->d_mem_work, wm));
-    BATCH_TRY(upload(b, b->d_node_work, wn));
-    b->n_lat_work = (int)wl.size();
-    b->n_mem_work = (int)wm.size();
-    b->n_node_work = (int)wn.size();
     b->lty = lty;
     return LBIB_OK;
 }
+
+hipStream_t group_stream(const lbib_batch* b, int g) { return g == 0 ? b->stream : b->side; }
 
 #define BATCH_LAUNCH(b, call)                                                                \
     do {                                                                                     \
@@ -126,27 +169,52 @@ lbib_status build_tables(lbib_batch* b, int lty)
 
 lbib_status lists(lbib_batch* b)
 {
-    for (int which = 0; which < 3; ++which)
-        BATCH_LAUNCH(b, launch_lists_batch(b->d_list, b->d_node_work, b->n_node_work, (int)b->sims.size(), which,
-                                           b->stream));
+    for (int g = 0; g < (int)b->groups.size(); ++g) {
+        const lbib_batch_group& grp = b->groups[g];
+        for (int which = 0; which < 3; ++which)
+            BATCH_LAUNCH(b, launch_lists_batch(grp.d_list, grp.d_node_work, grp.n_node_work, (int)grp.sims.size(),
+                                               which, group_stream(b, g)));
+    }
     b->since = 0;
     return LBIB_OK;
 }
 
 // one coupled step of every simulation: lattice pass, membrane pass, and every LIST_PERIOD
-// steps the list build (the order of a single context's step)
+// steps the list build (the order of a single context's step), each group on its stream
 lbib_status one_step(lbib_batch* b)
 {
     const int p = b->par;
-    BATCH_LAUNCH(b, launch_lattice_batch(b->d_lat[p], b->d_lat_work, b->n_lat_work, b->S, b->storage,
-                                         b->lty / TILE_Y, b->mask, b->stream));
-    BATCH_LAUNCH(b, launch_membrane_batch(b->d_mem[p], b->d_mem_work, b->n_mem_work, b->max_cell_nodes, b->stream));
+    for (int g = 0; g < (int)b->groups.size(); ++g) {
+        const lbib_batch_group& grp = b->groups[g];
+        const hipStream_t st = group_stream(b, g);
+        BATCH_LAUNCH(b, launch_lattice_batch(grp.d_lat[p], grp.d_lat_work, grp.n_lat_work, b->S, b->storage,
+                                             b->lty / TILE_Y, b->mask, st));
+        BATCH_LAUNCH(b, launch_membrane_batch(grp.d_mem[p], grp.d_mem_work, grp.n_mem_work, grp.max_cell_nodes, st));
+    }
     b->par ^= 1;
     if (++b->since >= LIST_PERIOD) BATCH_TRY(lists(b));
     return LBIB_OK;
 }
 
-// LIST_PERIOD steps from an aligned state (since = par = 0, which they are again at the end)
+// the second group's stream starts after, and the batch's stream continues after, all work so far
+lbib_status fork_groups(lbib_batch* b)
+{
+    if (b->groups.size() < 2) return LBIB_OK;
+    BATCH_HIP(b, hipEventRecord(b->fork, b->stream));
+    BATCH_HIP(b, hipStreamWaitEvent(b->side, b->fork, 0));
+    return LBIB_OK;
+}
+
+lbib_status join_groups(lbib_batch* b)
+{
+    if (b->groups.size() < 2) return LBIB_OK;
+    BATCH_HIP(b, hipEventRecord(b->join, b->side));
+    BATCH_HIP(b, hipStreamWaitEvent(b->stream, b->join, 0));
+    return LBIB_OK;
+}
+
+// LIST_PERIOD steps from an aligned state (since = par = 0, which they are again at the end);
+// the groups' chains fork at the start and join at the end of the period
 lbib_status capture(lbib_batch* b)
 {
     if (!b->capture_stream) BATCH_HIP(b, hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
@@ -157,7 +225,9 @@ lbib_status capture(lbib_batch* b)
     if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         st = LBIB_EDEVICE;
     } else {
+        st = fork_groups(b);
         for (int k = 0; k < LIST_PERIOD && st == LBIB_OK; ++k) st = one_step(b);
+        if (st == LBIB_OK) st = join_groups(b);
         const hipError_t e = hipStreamEndCapture(b->stream, &g);
         if (st == LBIB_OK && e != hipSuccess) st = LBIB_EDEVICE;
     }
@@ -173,18 +243,22 @@ lbib_status capture(lbib_batch* b)
     return st;
 }
 
-// advance n steps; whole aligned periods replay the captured graph
+// advance n steps; whole aligned periods replay the captured graph, other steps are launched
+// directly (up to the next list build, or the remainder)
 lbib_status advance(lbib_batch* b, int64_t n)
 {
     while (n > 0) {
-        if (n >= LIST_PERIOD && b->since == 0 && b->par == 0) {
+        if (n >= LIST_PERIOD && b->since == 0) {
             if (!b->graph) BATCH_TRY(capture(b));
             BATCH_HIP(b, hipGraphLaunch(b->graph, b->stream));
             n -= LIST_PERIOD;
             continue;
         }
-        BATCH_TRY(one_step(b));
-        --n;
+        const int64_t m = std::min<int64_t>(n, LIST_PERIOD - b->since);
+        BATCH_TRY(fork_groups(b));
+        for (int64_t k = 0; k < m; ++k) BATCH_TRY(one_step(b));
+        BATCH_TRY(join_groups(b));
+        n -= m;
     }
     return LBIB_OK;
 }
@@ -207,8 +281,19 @@ lbib_status set_tile(lbib_batch* b, int lty)
     BATCH_HIP(b, hipStreamSynchronize(b->stream));
     drop_graph(b);
     BATCH_TRY(build_tables(b, lty));
+    BATCH_TRY(fork_groups(b));
     BATCH_TRY(lists(b));
+    BATCH_TRY(join_groups(b));
     return LBIB_OK;
+}
+
+// regroup at an aligned state (the lists stay as they are)
+lbib_status set_groups(lbib_batch* b, int ngroups)
+{
+    BATCH_HIP(b, hipStreamSynchronize(b->stream));
+    drop_graph(b);
+    b->ngroups = ngroups;
+    return build_tables(b, b->lty);
 }
 
 // copy of the state a step starts from: populations of the current parity, positions,
@@ -318,14 +403,17 @@ lbib_status lbib_batch_create(lbib_ctx* const* sims, int32_t n, void* hip_stream
     } else {
         b->own_stream = true;
     }
-    if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) st = LBIB_EDEVICE;
+    if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess)
+        st = LBIB_EDEVICE;
     // every simulation starts aligned: its lists built at the current positions
     for (int s = 0; s < n && st == LBIB_OK; ++s) {
         lbib_ctx* c = sims[s];
         if (c->steps_since_lists != 0) st = build_lists(c);
         if (st == LBIB_OK && hipStreamSynchronize(c->stream) != hipSuccess) st = LBIB_EDEVICE;
         b->cur0.push_back(c->cur);
-        b->max_cell_nodes = std::max(b->max_cell_nodes, c->max_cell_nodes);
         b->updates_per_step += c->nn;
     }
     if (st == LBIB_OK) st = build_tables(b, LTILE_Y);
@@ -346,6 +434,7 @@ void lbib_batch_destroy(lbib_batch* b)
 {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->side) (void)hipStreamSynchronize(b->side);
     for (lbib_ctx* c : b->sims) {
         if (!c || c->batch != b) continue;
         c->batch = nullptr;
@@ -357,15 +446,11 @@ void lbib_batch_destroy(lbib_batch* b)
         }
     }
     drop_graph(b);
-    for (int p = 0; p < 2; ++p) {
-        free_dev(b->d_lat[p]);
-        free_dev(b->d_mem[p]);
-    }
-    free_dev(b->d_list);
-    free_dev(b->d_lat_work);
-    free_dev(b->d_mem_work);
-    free_dev(b->d_node_work);
+    free_groups(b);
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->join) (void)hipEventDestroy(b->join);
     if (b->done) (void)hipEventDestroy(b->done);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
@@ -434,7 +519,32 @@ lbib_status lbib_batch_set_tile(lbib_batch* b, int32_t rows)
     return LBIB_OK;
 }
 
-lbib_status lbib_batch_autotune(lbib_batch* b, int32_t periods, int32_t* rows, double* ms_per_step)
+lbib_status lbib_batch_get_groups(const lbib_batch* b, int32_t* groups)
+{
+    if (!b || !groups) return LBIB_EINVAL;
+    *groups = (int32_t)b->groups.size();
+    return LBIB_OK;
+}
+
+lbib_status lbib_batch_set_groups(lbib_batch* b, int32_t groups)
+{
+    if (!b) return LBIB_ESTATE;
+    BATCH_TRY(usable(b));
+    if (groups != 1 && groups != 2) {
+        b->err = "a batch steps in 1 or 2 groups";
+        return LBIB_EINVAL;
+    }
+    if (b->since != 0 || b->par != 0) {
+        b->err = "the grouping can change only after a whole number of list periods";
+        return LBIB_ESTATE;
+    }
+    if (groups == (int)b->groups.size()) return LBIB_OK;
+    BATCH_TRY(set_groups(b, groups));
+    publish(b);
+    return LBIB_OK;
+}
+
+lbib_status lbib_batch_autotune(lbib_batch* b, int32_t periods, int32_t* rows, int32_t* groups, double* ms_per_step)
 {
     if (!b) return LBIB_ESTATE;
     BATCH_TRY(usable(b));
@@ -446,47 +556,56 @@ lbib_status lbib_batch_autotune(lbib_batch* b, int32_t periods, int32_t* rows, d
         b->err = "autotuning starts only after a whole number of list periods";
         return LBIB_ESTATE;
     }
-    for (int k = 0; k < 3 && ms_per_step; ++k) ms_per_step[k] = -1.0;
+    for (int k = 0; k < 6 && ms_per_step; ++k) ms_per_step[k] = -1.0;
     BATCH_HIP(b, hipStreamSynchronize(b->stream));
     Snapshot snap;
     lbib_status st = snapshot(b, snap, false);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (st == LBIB_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) st = LBIB_EDEVICE;
-    const int start = b->lty;
-    int best = start;
+    const int start = b->lty, start_groups = (int)b->groups.size();
+    int best = start, best_groups = start_groups;
     double best_ms = -1.0;
-    for (int k = 0; k < 3 && st == LBIB_OK; ++k) {
-        const int lty = TILE_CHOICES[k];
-        if (!tile_ok_all(b, lty)) continue;
-        st = set_tile(b, lty);
-        if (st == LBIB_OK) st = advance(b, LIST_PERIOD);            // warm-up (captures the graph)
-        if (st == LBIB_OK && hipEventRecord(e0, b->stream) != hipSuccess) st = LBIB_EDEVICE;
-        if (st == LBIB_OK) st = advance(b, (int64_t)periods * LIST_PERIOD);
-        if (st == LBIB_OK && hipEventRecord(e1, b->stream) != hipSuccess) st = LBIB_EDEVICE;
-        if (st == LBIB_OK && hipEventSynchronize(e1) != hipSuccess) st = LBIB_EDEVICE;
-        float ms = 0.0f;
-        if (st == LBIB_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = LBIB_EDEVICE;
-        if (st != LBIB_OK) break;
-        const double per = (double)ms / ((double)periods * LIST_PERIOD);
-        if (ms_per_step) ms_per_step[k] = per;
-        if (best_ms < 0.0 || per < best_ms) {
-            best_ms = per;
-            best = lty;
+    const int max_groups = b->sims.size() >= 2 ? 2 : 1;
+    for (int gi = 0; gi < max_groups && st == LBIB_OK; ++gi) {
+        b->ngroups = gi + 1;
+        for (int k = 0; k < 3 && st == LBIB_OK; ++k) {
+            const int lty = TILE_CHOICES[k];
+            if (!tile_ok_all(b, lty)) continue;
+            st = set_tile(b, lty);
+            if (st == LBIB_OK) st = advance(b, LIST_PERIOD);            // warm-up (captures the graph)
+            if (st == LBIB_OK && hipEventRecord(e0, b->stream) != hipSuccess) st = LBIB_EDEVICE;
+            if (st == LBIB_OK) st = advance(b, (int64_t)periods * LIST_PERIOD);
+            if (st == LBIB_OK && hipEventRecord(e1, b->stream) != hipSuccess) st = LBIB_EDEVICE;
+            if (st == LBIB_OK && hipEventSynchronize(e1) != hipSuccess) st = LBIB_EDEVICE;
+            float ms = 0.0f;
+            if (st == LBIB_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = LBIB_EDEVICE;
+            if (st != LBIB_OK) break;
+            const double per = (double)ms / ((double)periods * LIST_PERIOD);
+            if (ms_per_step) ms_per_step[3 * gi + k] = per;
+            if (best_ms < 0.0 || per < best_ms) {
+                best_ms = per;
+                best = lty;
+                best_groups = gi + 1;
+            }
+            st = snapshot(b, snap, true);                              // back to the starting state
         }
-        st = snapshot(b, snap, true);                                  // back to the starting state
     }
     if (st == LBIB_OK) {
+        b->ngroups = best_groups;
         st = set_tile(b, best);
     } else if (!snap.buf.empty() && snap.buf[0]) {
-        // a failed candidate: back to the starting state and tile height, lists rebuilt
+        // a failed candidate: back to the starting state, grouping and tile height, lists rebuilt
         (void)hipStreamSynchronize(b->stream);
+        (void)hipStreamSynchronize(b->side);
         (void)snapshot(b, snap, true);
+        b->ngroups = start_groups;
         (void)set_tile(b, start);
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     free_snapshot(snap);
     if (st == LBIB_OK && rows) *rows = best;
+    if (st == LBIB_OK && groups) *groups = best_groups;
     publish(b);
     return st;
 }

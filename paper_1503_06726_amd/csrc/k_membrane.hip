@@ -1,6 +1,6 @@
 // Membrane kernels of the coupled step (gfx950).
 //
-// k_membrane: one workgroup per cell.  In a time step it
+// k_membrane: one workgroup (two wavefronts) per cell.  In a time step it
 //   1. adds the node's interpolated velocity U (Eq. conversion2 with the kernel of
 //      Eq. 1Dkernel; the lattice pass leaves one share per listed tile, added here in the
 //      order of the node's tiles) and moves the node explicitly, X^{n+1} = X^n + U
@@ -75,7 +75,7 @@ __device__ inline void block_reduce5(double& sum, double m[4], double* red)
     sum = red[0];
 #pragma unroll
     for (int q = 0; q < 4; ++q) m[q] = red[1 + q];
-    for (int w = 1; w < MEMBRANE_THREADS / 64; ++w) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
         sum += red[w * 5];
 #pragma unroll
         for (int q = 0; q < 4; ++q) m[q] = fmin(m[q], red[w * 5 + 1 + q]);
@@ -90,75 +90,74 @@ __device__ inline void block_reduce5(double& sum, double m[4], double* red)
 __device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c, double2* xs, double* red,
                                               unsigned* bm)
 {
+    constexpr int NT = MEMBRANE_THREADS, NB = MEMBRANE_BATCH;
     const int t = threadIdx.x;
     const int beg = a.off[c];
     const int n = a.off[c + 1] - beg;
-
-    // rest lengths and list origin of the thread's first node, fetched with its position
-    double lp0 = 0.0, lm0 = 0.0;
-    int ky0 = 0;
-    if (t < n) {
-        lp0 = a.l0[beg + t];
-        lm0 = a.l0[beg + (t == 0 ? n - 1 : t - 1)];
-        ky0 = a.ij_list[beg + t];
-    }
+    const int64_t N = a.n_nodes;
     if (a.raster)
-        for (int i = t; i < RASTER_WORDS_FUSED; i += MEMBRANE_THREADS) bm[i] = 0u;
+        for (int i = t; i < RASTER_WORDS_FUSED; i += NT) bm[i] = 0u;
 
     // 1. move: X^{n+1} = X^n + U, U interpolated by the lattice pass as one share per listed
-    //    tile, added in the order of the node's tiles; stage the new positions in LDS and
-    //    track their bounding box.  The positions reach global memory only at the end: a
-    //    workgroup barrier waits for every outstanding store.
+    //    tile, added in the order of the node's tiles; stage the new positions in LDS and track
+    //    their bounding box.  A lane takes NB nodes per pass and issues all their loads first
+    //    (a lane past the end loads the cell's last node and discards it: no branches around
+    //    the loads).  The first four shares are read with the count (a node has at most four
+    //    tiles unless its list range wraps onto a narrow last tile); slots beyond the count are
+    //    never added.  Positions reach global memory only at the end: a workgroup barrier
+    //    waits for every outstanding store.
     double bb[4] = {INFINITY, INFINITY, INFINITY, INFINITY};     // min x, min y, -max x, -max y
-    for (int k = t; k < n; k += MEMBRANE_THREADS) {
-        const int64_t l = beg + k;
-        double2 X = a.X[l];
-        if (a.advect) {
-            // the first four shares are read alongside the count (a node has at most four
-            // tiles unless its list range wraps onto a narrow last tile); slots beyond the
-            // count are never added
-            const int64_t N = a.n_nodes;
-            const int nt = a.cnt[l];
-            const float2 s0 = a.part[l], s1 = a.part[N + l], s2 = a.part[2 * N + l], s3 = a.part[3 * N + l];
-            double ux = 0.0, uy = 0.0;
-            if (nt > 0) {
-                ux += (double)s0.x;
-                uy += (double)s0.y;
-            }
-            if (nt > 1) {
-                ux += (double)s1.x;
-                uy += (double)s1.y;
-            }
-            if (nt > 2) {
-                ux += (double)s2.x;
-                uy += (double)s2.y;
-            }
-            if (nt > 3) {
-                ux += (double)s3.x;
-                uy += (double)s3.y;
-            }
-            for (int q = 4; q < nt; ++q) {
-                const float2 sq = a.part[q * N + l];
-                ux += (double)sq.x;
-                uy += (double)sq.y;
-            }
-            if (finite2(X.x, X.y)) {
-                X.x += ux;
-                X.y += uy;
+    for (int base = 0; base < n; base += NT * NB) {
+        double2 X[NB];
+        float2 sh[NB][4];
+        int nt[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int64_t l = beg + min(base + j * NT + t, n - 1);
+            X[j] = a.X[l];
+            nt[j] = 0;
+            if (a.advect) {
+                nt[j] = a.cnt[l];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) sh[j][q] = a.part[q * N + l];
             }
         }
-        xs[k] = X;
-        bb[0] = fmin(bb[0], X.x);
-        bb[1] = fmin(bb[1], X.y);
-        bb[2] = fmin(bb[2], -X.x);
-        bb[3] = fmin(bb[3], -X.y);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int k = base + j * NT + t;
+            if (k >= n) continue;
+            double2 x = X[j];
+            if (a.advect) {
+                double ux = 0.0, uy = 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (nt[j] > q) {
+                        ux += (double)sh[j][q].x;
+                        uy += (double)sh[j][q].y;
+                    }
+                for (int q = 4; q < nt[j]; ++q) {
+                    const float2 sq = a.part[q * N + beg + k];
+                    ux += (double)sq.x;
+                    uy += (double)sq.y;
+                }
+                if (finite2(x.x, x.y)) {
+                    x.x += ux;
+                    x.y += uy;
+                }
+            }
+            xs[k] = x;
+            bb[0] = fmin(bb[0], x.x);
+            bb[1] = fmin(bb[1], x.y);
+            bb[2] = fmin(bb[2], -x.x);
+            bb[3] = fmin(bb[3], -x.y);
+        }
     }
     __syncthreads();
 
     // 2. shoelace area about the first node (translation invariant, less cancellation)
     const double ox = uniform(xs[0].x), oy = uniform(xs[0].y);
     double A2 = 0.0;
-    for (int k = t; k < n; k += MEMBRANE_THREADS) {
+    for (int k = t; k < n; k += NT) {
         const int kn = (k + 1 == n) ? 0 : k + 1;
         A2 += (xs[k].x - ox) * (xs[kn].y - oy) - (xs[kn].x - ox) * (xs[k].y - oy);
     }
@@ -178,7 +177,7 @@ __device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c
             for (int r0 = 0; r0 < b.H; r0 += CH) {
                 const int rows = (b.H - r0 < CH) ? b.H - r0 : CH;
                 if (r0 > 0) {
-                    for (int i = t; i < rows * b.WW; i += MEMBRANE_THREADS) bm[i] = 0u;
+                    for (int i = t; i < rows * b.WW; i += NT) bm[i] = 0u;
                     __syncthreads();
                 }
                 raster_toggle(xs, n, b, r0, rows, bm);
@@ -192,51 +191,61 @@ __device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c
     }
 
     // 4. forces, spreading records and the new positions (no barrier follows: the stores
-    //    drain while the workgroup retires)
+    //    drain while the workgroup retires); rest lengths and list origins of a lane's NB
+    //    nodes are loaded first
     int flags = 0;
-    for (int k = t; k < n; k += MEMBRANE_THREADS) {
-        const int kp = (k + 1 == n) ? 0 : k + 1;
-        const int km = (k == 0) ? n - 1 : k - 1;
-        double lp = lp0, lm = lm0;
-        int ky = ky0;
-        if (k != t) {
-            lp = a.l0[beg + k];
-            lm = a.l0[beg + km];
-            ky = a.ij_list[beg + k];
+    for (int base = 0; base < n; base += NT * NB) {
+        double lpv[NB], lmv[NB];
+        int kyv[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int k = min(base + j * NT + t, n - 1);
+            lpv[j] = a.l0[beg + k];
+            lmv[j] = a.l0[beg + (k == 0 ? n - 1 : k - 1)];
+            kyv[j] = a.ij_list[beg + k];
         }
-        const double2 X = xs[k], Xp = xs[kp], Xm = xs[km];
-        const double dpx = Xp.x - X.x, dpy = Xp.y - X.y;
-        const double dmx = Xm.x - X.x, dmy = Xm.y - X.y;
-        const double Lp = sqrt(dpx * dpx + dpy * dpy), Lm = sqrt(dmx * dmx + dmy * dmy);
-        // tension phi_m along both edges; springs k (L - l0) along each edge
-        const double sp = (a.phi_m + a.k_spring * (Lp - lp)) / Lp;
-        const double sm = (a.phi_m + a.k_spring * (Lm - lm)) / Lm;
-        double Fx = sp * dpx + sm * dmx;
-        double Fy = sp * dpy + sm * dmy;
-        // area pressure: dA/dX_k = ((y_{k+1} - y_{k-1}) / 2, (x_{k-1} - x_{k+1}) / 2)
-        Fx += s_area * 0.5 * (Xp.y - Xm.y);
-        Fy += s_area * 0.5 * (Xm.x - Xp.x);
-        const int s = beg + k;
-        if (a.advect) a.X[s] = X;
-        if (finite2(X.x, X.y) && finite2(Fx, Fy)) {
-            const double fx = floor(X.x), fy = floor(X.y);
-            int i0, j0;
-            stencil_origin(X.x, X.y, a.nx, a.ny, a.walls, i0, j0);
-            a.rec[s] = make_float4((float)(X.x - fx), (float)(X.y - fy), (float)Fx, (float)Fy);
-            a.rec_ij[s] = pack_ij(i0, j0);
-            if (!within_margin(i0, j0, ky, a.nx, a.ny, a.walls)) flags |= ERR_MARGIN;
-        } else {
-            a.rec[s] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            a.rec_ij[s] = 0;
-            flags |= ERR_NONFINITE;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int k = base + j * NT + t;
+            if (k >= n) continue;
+            const int kp = (k + 1 == n) ? 0 : k + 1;
+            const int km = (k == 0) ? n - 1 : k - 1;
+            const double lp = lpv[j], lm = lmv[j];
+            const double2 X = xs[k], Xp = xs[kp], Xm = xs[km];
+            const double dpx = Xp.x - X.x, dpy = Xp.y - X.y;
+            const double dmx = Xm.x - X.x, dmy = Xm.y - X.y;
+            const double Lp = sqrt(dpx * dpx + dpy * dpy), Lm = sqrt(dmx * dmx + dmy * dmy);
+            // tension phi_m along both edges; springs k (L - l0) along each edge
+            const double sp = (a.phi_m + a.k_spring * (Lp - lp)) / Lp;
+            const double sm = (a.phi_m + a.k_spring * (Lm - lm)) / Lm;
+            double Fx = sp * dpx + sm * dmx;
+            double Fy = sp * dpy + sm * dmy;
+            // area pressure: dA/dX_k = ((y_{k+1} - y_{k-1}) / 2, (x_{k-1} - x_{k+1}) / 2)
+            Fx += s_area * 0.5 * (Xp.y - Xm.y);
+            Fy += s_area * 0.5 * (Xm.x - Xp.x);
+            const int s = beg + k;
+            if (a.advect) a.X[s] = X;
+            if (finite2(X.x, X.y) && finite2(Fx, Fy)) {
+                const double fx = floor(X.x), fy = floor(X.y);
+                int i0, j0;
+                stencil_origin(X.x, X.y, a.nx, a.ny, a.walls, i0, j0);
+                a.rec[s] = make_float4((float)(X.x - fx), (float)(X.y - fy), (float)Fx, (float)Fy);
+                a.rec_ij[s] = pack_ij(i0, j0);
+                if (!within_margin(i0, j0, kyv[j], a.nx, a.ny, a.walls)) flags |= ERR_MARGIN;
+            } else {
+                a.rec[s] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                a.rec_ij[s] = 0;
+                flags |= ERR_NONFINITE;
+            }
         }
     }
     if (t == 0) a.area[c] = A;
     if (flags) atomicOr(a.err, flags);
 }
 
-// 8 waves per SIMD keep every workgroup of a 2000-cell step resident at once
-__global__ __launch_bounds__(MEMBRANE_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_membrane(MembraneArgs a)
+// Two wavefronts per cell: 5 waves per SIMD keep every workgroup of a 2000-cell step resident
+// at once, with the registers for the loads of MEMBRANE_BATCH nodes per lane
+__global__ __launch_bounds__(MEMBRANE_THREADS) __attribute__((amdgpu_waves_per_eu(5))) void k_membrane(MembraneArgs a)
 {
     extern __shared__ double2 xs[];
     __shared__ double red[5 * (MEMBRANE_THREADS / 64)];
@@ -246,7 +255,7 @@ __global__ __launch_bounds__(MEMBRANE_THREADS) __attribute__((amdgpu_waves_per_e
 
 // Batched form: one (simulation, cell) work item per workgroup, the simulation's arguments
 // from a device table.
-__global__ __launch_bounds__(MEMBRANE_THREADS) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_membrane_batch(const MembraneArgs* __restrict__ tab,
+__global__ __launch_bounds__(MEMBRANE_THREADS) __attribute__((amdgpu_waves_per_eu(5))) void k_membrane_batch(const MembraneArgs* __restrict__ tab,
                                                                      const int2* __restrict__ work)
 {
     extern __shared__ double2 xs[];

@@ -152,12 +152,28 @@ lbib_status check_err_flag(lbib_ctx* c);
 
 }  // namespace lbib
 
-// Many contexts stepped together (batch.hip): each launch of the step covers every adopted
-// simulation, with per-simulation arguments in device tables (one per buffer parity).
+// Many contexts stepped together (batch.hip): each launch of the step covers every simulation
+// of a group, with per-simulation arguments in device tables (one per buffer parity).  With two
+// groups the groups' step chains run on two streams, so that one group's latency-bound
+// membrane and list kernels overlap the other's bandwidth-bound lattice pass.
+struct lbib_batch_group {
+    std::vector<int> sims;           // indices into lbib_batch::sims
+    lbib::LatticeArgs* d_lat[2] = {nullptr, nullptr};    // [group sims] per parity
+    lbib::MembraneArgs* d_mem[2] = {nullptr, nullptr};
+    lbib::ListArgs* d_list = nullptr;
+    int2* d_lat_work = nullptr;      // (group simulation, tile)
+    int2* d_mem_work = nullptr;      // (group simulation, cell)
+    int2* d_node_work = nullptr;     // (group simulation, block of LIST_THREADS nodes)
+    int n_lat_work = 0, n_mem_work = 0, n_node_work = 0;
+    int max_cell_nodes = 0;
+};
+
 struct lbib_batch {
     std::vector<lbib_ctx*> sims;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipStream_t side = nullptr;      // the second group's stream
+    hipEvent_t fork = nullptr, join = nullptr;
     hipEvent_t done = nullptr;
     std::string err;
     bool broken = false;             // an adopted context was destroyed
@@ -165,18 +181,11 @@ struct lbib_batch {
     int S = 0, storage = 0;
     bool mask = false;
     int lty = 0;                     // lattice tile height (rows) of the batched pass
-    int max_cell_nodes = 0;
+    int ngroups = 1;
     int since = 0;                   // steps since the last list build
     int par = 0;                     // parity of the steps taken (buffer parity relative to cur0)
     std::vector<int> cur0;
-
-    lbib::LatticeArgs* d_lat[2] = {nullptr, nullptr};    // [sims] per parity
-    lbib::MembraneArgs* d_mem[2] = {nullptr, nullptr};
-    lbib::ListArgs* d_list = nullptr;
-    int2* d_lat_work = nullptr;      // (simulation, tile)
-    int2* d_mem_work = nullptr;      // (simulation, cell)
-    int2* d_node_work = nullptr;     // (simulation, block of LIST_THREADS nodes)
-    int n_lat_work = 0, n_mem_work = 0, n_node_work = 0;
+    std::vector<lbib_batch_group> groups;
     int64_t updates_per_step = 0;    // lattice nodes of all simulations
 
     hipGraphExec_t graph = nullptr;  // LIST_PERIOD steps from an aligned state

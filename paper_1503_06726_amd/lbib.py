@@ -31,7 +31,8 @@ EXPORTS = ["lbib_validate_params", "lbib_validate_cells", "lbib_create", "lbib_s
            "lbib_net_create", "lbib_net_param_count", "lbib_net_set_params", "lbib_net_get_params",
            "lbib_net_predict", "lbib_net_loss_grad", "lbib_net_train_step", "lbib_net_destroy",
            "lbib_batch_create", "lbib_batch_step", "lbib_batch_sync", "lbib_batch_get_tile",
-           "lbib_batch_set_tile", "lbib_batch_autotune", "lbib_batch_last_error", "lbib_batch_destroy"]
+           "lbib_batch_set_tile", "lbib_batch_get_groups", "lbib_batch_set_groups", "lbib_batch_autotune",
+           "lbib_batch_last_error", "lbib_batch_destroy"]
 
 
 class Species(C.Structure):
@@ -142,8 +143,12 @@ def lib():
     L.lbib_batch_get_tile.argtypes = [vp, C.POINTER(C.c_int32)]
     L.lbib_batch_set_tile.restype = st
     L.lbib_batch_set_tile.argtypes = [vp, C.c_int32]
+    L.lbib_batch_get_groups.restype = st
+    L.lbib_batch_get_groups.argtypes = [vp, C.POINTER(C.c_int32)]
+    L.lbib_batch_set_groups.restype = st
+    L.lbib_batch_set_groups.argtypes = [vp, C.c_int32]
     L.lbib_batch_autotune.restype = st
-    L.lbib_batch_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), vp]
+    L.lbib_batch_autotune.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), vp]
     L.lbib_batch_last_error.restype = C.c_char_p
     L.lbib_batch_last_error.argtypes = [vp]
     L.lbib_batch_destroy.restype = None
@@ -391,12 +396,24 @@ class Batch:
     def set_tile(self, rows: int):
         self._check(self.L.lbib_batch_set_tile(self.h, int(rows)), "lbib_batch_set_tile")
 
+    @property
+    def groups(self) -> int:
+        g = C.c_int32(0)
+        self._check(self.L.lbib_batch_get_groups(self.h, C.byref(g)), "lbib_batch_get_groups")
+        return int(g.value)
+
+    def set_groups(self, groups: int):
+        self._check(self.L.lbib_batch_set_groups(self.h, int(groups)), "lbib_batch_set_groups")
+
     def autotune(self, periods: int = 2):
-        """(chosen tile height, {height: ms per step} of the admissible heights)."""
-        r = C.c_int32(0)
-        ms = np.zeros(3)
-        self._check(self.L.lbib_batch_autotune(self.h, int(periods), C.byref(r), _p(ms)), "lbib_batch_autotune")
-        return int(r.value), {h: float(v) for h, v in zip((4, 8, 16), ms) if v >= 0}
+        """(chosen tile height, chosen groups, {(groups, height): ms per step} of the
+        admissible configurations)."""
+        r, g = C.c_int32(0), C.c_int32(0)
+        ms = np.zeros(6)
+        self._check(self.L.lbib_batch_autotune(self.h, int(periods), C.byref(r), C.byref(g), _p(ms)),
+                    "lbib_batch_autotune")
+        keys = [(1, 4), (1, 8), (1, 16), (2, 4), (2, 8), (2, 16)]
+        return int(r.value), int(g.value), {k: float(v) for k, v in zip(keys, ms) if v >= 0}
 
 
 class Net:

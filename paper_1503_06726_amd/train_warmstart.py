@@ -2,12 +2,16 @@
 warm start on held-out ones.
 
   python -m paper_1503_06726_amd.train_warmstart [--samples N] [--epochs E] [--batch B]
-                                                 [--eval M] [--out PATH]
+                                                 [--eval M] [--out PATH] [--warm-targets PATH]
+                                                 [--target-budget SECONDS]
 
 1. N training samples (seed stream of the training set) and M held-out samples are generated
    on the host;
 2. every training sample's steady state is solved by the library's batched ADE-only iteration
-   (FP64, relative change 1e-8) and scaled to phi * decay / source;
+   (FP64, relative change 1e-8) and scaled to phi * decay / source; with --warm-targets the
+   solves start from the prediction of an earlier network (the stopping rule, not the start,
+   fixes the target), and --target-budget stops solving after that many seconds and trains on
+   the samples solved so far;
 3. the network (library kernels) is trained with Adam and a cosine learning-rate decay;
 4. the held-out samples are solved to 1e-6 from zero and from the network's prediction, and
    the iteration counts are printed; the parameters and a summary are saved to PATH.
@@ -30,6 +34,8 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--target-tol", type=float, default=1e-8)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--warm-targets", default=None, help="weights (.npz) whose predictions start the target solves")
+    ap.add_argument("--target-budget", type=float, default=None, help="seconds for the target solves")
     args = ap.parse_args(argv)
 
     import numpy as np
@@ -49,18 +55,34 @@ def main(argv=None):
 
     src, _, feat = WS.prepare(train_ws)
     log(f"masks and features ({time.perf_counter() - t0:.0f} s)")
+    net0 = None
+    if args.warm_targets:
+        p0, _ = WS.load(args.warm_targets)
+        net0 = lbib.Net(src.shape[1], src.shape[2], 16)
+        net0.set_params(p0)
     targets = np.zeros((len(train_ws),) + src.shape[1:], np.float32)
     its_all = np.zeros(len(train_ws), np.int64)
     chunk = 512
+    t_tgt = time.perf_counter()
+    n_done = 0
     for k in range(0, len(train_ws), chunk):
-        its, phi = WS.solve(train_ws[k:k + chunk], src[k:k + chunk], tol=args.target_tol)
+        if args.target_budget is not None and time.perf_counter() - t_tgt > args.target_budget:
+            log(f"target budget reached after {n_done} samples")
+            break
+        phi0 = None if net0 is None else WS.predict(net0, feat[k:k + chunk], train_ws[k:k + chunk])
+        its, phi = WS.solve(train_ws[k:k + chunk], src[k:k + chunk], phi0=phi0, tol=args.target_tol)
         for j in range(phi.shape[0]):
             targets[k + j] = phi[j] / WS.scale(train_ws[k + j])
         its_all[k:k + chunk] = its
-        log(f"  targets {k + phi.shape[0]}/{len(train_ws)} (median {int(np.median(its))} iterations; "
+        n_done = k + phi.shape[0]
+        log(f"  targets {n_done}/{len(train_ws)} (median {int(np.median(its))} iterations; "
             f"{time.perf_counter() - t0:.0f} s)")
-    if (its_all == 0).any():
-        log(f"warning: {int((its_all == 0).sum())} training targets did not converge")
+    if net0 is not None:
+        net0.close()
+    keep = np.flatnonzero(its_all[:n_done] > 0)
+    if len(keep) < n_done:
+        log(f"warning: {n_done - len(keep)} training targets did not converge and are left out")
+    feat, targets, train_ws = feat[keep], targets[keep], [train_ws[i] for i in keep]
 
     fx = torch.tensor(feat, dtype=torch.float32, device="cuda")
     ty = torch.tensor(targets, dtype=torch.float32, device="cuda")
@@ -79,7 +101,7 @@ def main(argv=None):
     kw, _ = WS.solve(held_ws, hsrc, phi0=phi_hat, tol=1e-6)
     net.close()
     summary = {
-        "samples": len(train_ws), "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "seed": args.seed,
+        "samples": len(train_ws), "warm_targets": bool(args.warm_targets), "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "seed": args.seed,
         "target_tol": args.target_tol, "loss_per_epoch": [float(h) for h in hist],
         "held_out": len(held_ws), "zero_start_median": float(np.median(k0)), "zero_start_mean": float(k0.mean()),
         "warm_start_median": float(np.median(kw)), "warm_start_mean": float(kw.mean()),

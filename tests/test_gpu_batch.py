@@ -79,6 +79,32 @@ def test_batched_bit_identical_to_alone():
     close_all(A, B)
 
 
+def test_two_groups_bit_identical_to_alone():
+    """Two groups on two streams (one graph per period): still the same arithmetic per simulation."""
+    ws = small_sweep()
+    A, B = make(ws), make(ws)
+    batch = lbib.Batch(B)
+    batch.set_groups(2)
+    assert batch.groups == 2
+    for n in (37, 16):                 # two graph periods + 5 direct steps, then one more period
+        for s in A:
+            s.step(n)
+        batch.step(n)
+        batch.sync()
+        assert_bit_equal(fields(A), fields(B), f"two groups, after {n} more steps")
+    batch.step(11)                     # back to a period boundary (64 steps) before regrouping
+    for s in A:
+        s.step(11)
+    batch.set_groups(1)
+    batch.step(16)
+    for s in A:
+        s.step(16)
+    batch.sync()
+    assert_bit_equal(fields(A), fields(B), "after regrouping")
+    batch.close()
+    close_all(A, B)
+
+
 @pytest.mark.parametrize("rows", [4, 16])
 def test_other_tile_heights_round_off_only(rows):
     ws = small_sweep(periodic_ny=96)
@@ -114,10 +140,11 @@ def test_autotune_restores_state_and_keeps_parity():
     for s in A:
         s.step(16)
     before = fields(B)
-    rows, ms = batch.autotune(periods=1)
-    say(f"  autotune: {rows} rows; ms per step {ms}")
-    assert rows in ms and set(ms) <= {4, 8, 16} and 8 in ms and 16 in ms
-    assert 4 not in ms                                 # the periodic member has ny = 98
+    rows, groups, ms = batch.autotune(periods=1)
+    say(f"  autotune: {rows} rows, {groups} groups; ms per step {ms}")
+    assert (groups, rows) in ms and batch.tile == rows and batch.groups == groups
+    assert {(1, 8), (1, 16), (2, 8), (2, 16)} <= set(ms)
+    assert (1, 4) not in ms and (2, 4) not in ms       # the periodic member has ny = 98
     assert_bit_equal(before, fields(B), "after autotuning")
     batch.step(32)
     for s in A:
@@ -176,6 +203,10 @@ def test_batch_errors():
     assert e.value.status == lbib.ESTATE
     with pytest.raises(lbib.LbibError):
         batch.autotune(1)
+    with pytest.raises(lbib.LbibError):
+        batch.set_groups(2)                           # between list periods
+    with pytest.raises(lbib.LbibError):
+        batch.set_groups(3)
     A[2].close()                                      # the batch can no longer step
     with pytest.raises(lbib.LbibError) as e:
         batch.step(1)
