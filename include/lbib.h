@@ -26,7 +26,8 @@
  *                   its cyclic successor in the same cell.
  *
  * Ownership: every input is copied before the call returns; outputs go to caller buffers.
- * The context owns its device memory (hipMalloc) and launches on the stream given at creation.
+ * The context owns its device memory (hipMalloc), or keeps its state in a workspace the caller
+ * binds (lbib_bind_workspace), and launches on the stream given at creation.
  *
  * Errors: every call returns an lbib_status; nothing prints or aborts.  A call that fails
  * validation leaves the context unchanged.  lbib_last_error() gives a message.
@@ -108,6 +109,43 @@ lbib_status lbib_validate_cells(const lbib_params* p, int32_t n_cells, const int
  * every concentration 0, no cells.  On failure *out is NULL and the status says why
  * (LBIB_EINVAL, LBIB_EDEVICE when no GPU is usable, LBIB_ENOMEM). */
 lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out);
+
+/* Caller-owned device memory for the solver states (Section "Input and Output": the fluid
+ * and reaction-advection-diffusion solver states, the geometry points and their connections;
+ * Figure "Iterative Processing in the Solver": these states persist from one iteration to the
+ * next).  A workspace holds, in one caller allocation, every array a context keeps between
+ * calls: both population buffers of the fluid and species lattices, the inside-cell bits, the
+ * tile lists and counters, the reduction partials, a staging area for read-backs, and the
+ * membrane arrays (positions, rest lengths and areas, spreading records, velocity shares,
+ * per-tile node lists, source-cell flags) for up to a stated number of nodes.
+ *
+ * lbib_workspace_size: bytes of a workspace for a context with parameters p whose cell sets
+ * have at most n_nodes membrane nodes in total (any number of cells).  Pure host function; the
+ * value depends on p and n_nodes only.  LBIB_EINVAL for invalid parameters or n_nodes < 0. */
+lbib_status lbib_workspace_size(const lbib_params* p, int64_t n_nodes, size_t* bytes);
+
+/* Move the context's state into the caller's workspace [device_ptr, device_ptr + bytes).
+ *   device_ptr  device memory of the context's device (hipMalloc, or a torch tensor's
+ *               storage), 256-byte aligned, with bytes inside one allocation; or NULL with
+ *               bytes = 0 to move the state back into memory the library allocates
+ *   bytes       at least lbib_workspace_size(p, N) for the current node count N; the node
+ *               capacity is the largest n with lbib_workspace_size(p, n) <= bytes
+ * The state is copied (the simulation continues unchanged, bit for bit) on the context's
+ * stream, which is synchronised; the library's own memory for it is then released, or, when
+ * moving from one workspace to another, the old workspace is no longer used and may be freed.
+ * While bound, lbib_set_cells with more nodes than the capacity returns LBIB_ENOMEM (state
+ * unchanged), and nothing of the state is allocated or freed by the library.  lbib_ade_steady
+ * still allocates its own working set for the length of that call.
+ * The caller keeps the workspace alive and untouched until the context is destroyed or moved
+ * elsewhere; the contents are the library's and their layout is private.
+ * Errors: LBIB_EINVAL for a misaligned pointer, memory that is not device memory of the
+ * context's device, a range past the end of its allocation, or a range overlapping the
+ * workspace currently bound; LBIB_ENOMEM when bytes is below what the current state needs;
+ * LBIB_ESTATE while a batch has adopted the context.  On failure the context is unchanged. */
+lbib_status lbib_bind_workspace(lbib_ctx* ctx, void* device_ptr, size_t bytes);
+
+/* Membrane nodes the bound workspace holds, or -1 when no workspace is bound. */
+lbib_status lbib_workspace_nodes(const lbib_ctx* ctx, int64_t* n_nodes);
 
 /* Set the membranes (Section "Cell Representation": closed CCW polygons, the cell's ID is
  * c+1 for the c-th polygon, 0 is the extracellular space).
@@ -316,7 +354,8 @@ enum { LBIB_K_LATTICE = 0, LBIB_K_MEMBRANE = 1, LBIB_K_LISTS = 2, LBIB_K_COUNT =
 lbib_status lbib_set_timing(lbib_ctx* ctx, int32_t enable);
 lbib_status lbib_get_timing(lbib_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches);
 
-/* Bytes of device memory the context holds. */
+/* Bytes of device memory the library has allocated for the context (a bound workspace is
+ * the caller's and is not counted). */
 lbib_status lbib_device_bytes(const lbib_ctx* ctx, size_t* bytes);
 
 /* Last error message of the context (never NULL; "" when none). */

@@ -1,5 +1,6 @@
 // C ABI of the lbib library: context management, validation, the step loop and data
 // movement.  All device work is issued on the context's stream.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -45,6 +46,16 @@ void dev_free(lbib_ctx* c, T*& p, size_t count)
         c->device_bytes -= (count ? count : 1) * sizeof(T);
     }
     p = nullptr;
+}
+
+// persistent arrays: a bound workspace owns their memory, so only the pointer is dropped
+template <typename T>
+void state_free(lbib_ctx* c, T*& p, size_t count)
+{
+    if (c->ws)
+        p = nullptr;
+    else
+        dev_free(c, p, count);
 }
 
 #define LBIB_TRY(expr)                  \
@@ -265,6 +276,12 @@ lbib_status membrane(lbib_ctx* c, int advect)
 lbib_status ensure_stage(lbib_ctx* c, size_t doubles)
 {
     if (c->stage_bytes >= doubles * sizeof(double)) return LBIB_OK;
+    if (c->ws) {
+        // the workspace's staging area is sized for every read-back of its node capacity
+        c->err = "the workspace's staging area holds " + std::to_string(c->ws_stage_doubles) +
+                 " doubles; " + std::to_string(doubles) + " are needed";
+        return LBIB_ENOMEM;
+    }
     if (c->d_stage) {
         LBIB_HIP(c, hipStreamSynchronize(c->stream));
         dev_free(c, c->d_stage, c->stage_bytes / sizeof(double));
@@ -298,18 +315,19 @@ namespace {
 void free_nodes(lbib_ctx* c)
 {
     const size_t N = (size_t)c->n_nodes, C = (size_t)c->n_cells;
-    dev_free(c, c->d_off, C + 1);
-    dev_free(c, c->d_X, N);
-    dev_free(c, c->d_l0, N);
-    dev_free(c, c->d_A0, C);
-    dev_free(c, c->d_area, C);
-    dev_free(c, c->d_ijlist, N);
-    dev_free(c, c->d_part, N * MAX_NODE_TILES);
-    dev_free(c, c->d_cnt, N);
-    dev_free(c, c->d_rec, N);
-    dev_free(c, c->d_rec_ij, N);
-    dev_free(c, c->d_list, N * MAX_NODE_TILES);
-    dev_free(c, c->d_src, C);
+    state_free(c, c->d_off, C + 1);
+    state_free(c, c->d_X, N);
+    state_free(c, c->d_l0, N);
+    state_free(c, c->d_A0, C);
+    state_free(c, c->d_area, C);
+    state_free(c, c->d_ijlist, N);
+    state_free(c, c->d_part, N * MAX_NODE_TILES);
+    state_free(c, c->d_cnt, N);
+    state_free(c, c->d_rec, N);
+    state_free(c, c->d_rec_ij, N);
+    state_free(c, c->d_list, N * MAX_NODE_TILES);
+    state_free(c, c->d_src, C);
+    c->ws_src = nullptr;
     c->n_nodes = 0;
     c->n_cells = 0;
     c->max_cell_nodes = 0;
@@ -324,17 +342,17 @@ void free_all(lbib_ctx* c)
     for (int b = 0; b < 2; ++b) {
         char* fb = (char*)c->f[b];
         char* gb = (char*)c->g[b];
-        dev_free(c, fb, c->f_elems() * c->pop_bytes);
-        dev_free(c, gb, c->g_elems() * c->pop_bytes);
+        state_free(c, fb, c->f_elems() * c->pop_bytes);
+        state_free(c, gb, c->g_elems() * c->pop_bytes);
         c->f[b] = c->g[b] = nullptr;
     }
-    for (int b = 0; b < 2; ++b) dev_free(c, c->inside[b], (size_t)c->ny_words());
-    dev_free(c, c->d_t_count, (size_t)c->tile_cap);
-    dev_free(c, c->d_t_off, (size_t)c->tile_cap + 1);
-    dev_free(c, c->d_t_cur, (size_t)c->tile_cap);
-    dev_free(c, c->d_err, 1);
-    dev_free(c, c->d_partial, c->partial_count * 5);
-    if (c->d_stage) dev_free(c, c->d_stage, c->stage_bytes / sizeof(double));
+    for (int b = 0; b < 2; ++b) state_free(c, c->inside[b], (size_t)c->ny_words());
+    state_free(c, c->d_t_count, (size_t)c->tile_cap);
+    state_free(c, c->d_t_off, (size_t)c->tile_cap + 1);
+    state_free(c, c->d_t_cur, (size_t)c->tile_cap);
+    state_free(c, c->d_err, 1);
+    state_free(c, c->d_partial, c->partial_count * 5);
+    if (c->d_stage) state_free(c, c->d_stage, c->stage_bytes / sizeof(double));
     c->stage_bytes = 0;
     for (auto& t : c->pending) {
         (void)hipEventDestroy(t.start);
@@ -343,6 +361,228 @@ void free_all(lbib_ctx* c)
     c->pending.clear();
     for (auto e : c->free_events) (void)hipEventDestroy(e);
     c->free_events.clear();
+}
+
+// -------------------------------------------------------------------------------------
+// workspace layout: the persistent arrays in a fixed order, each piece starting on a
+// WS_ALIGN boundary.  The lattice part depends on the parameters only; the node part follows
+// it and is laid out for the current nodes and cells (every piece grows with N and C, and
+// C <= N / 3 since a cell has at least 3 nodes, so a part sized for N nodes holds any set of
+// at most N nodes).
+// -------------------------------------------------------------------------------------
+enum Piece {
+    PC_F0, PC_F1, PC_G0, PC_G1, PC_IN0, PC_IN1, PC_TCOUNT, PC_TOFF, PC_TCUR, PC_ERR, PC_PARTIAL, PC_STAGE,
+    PC_OFF, PC_X, PC_L0, PC_A0, PC_AREA, PC_IJ, PC_PART, PC_CNT, PC_REC, PC_RECIJ, PC_LIST, PC_SRC,
+    PC_COUNT
+};
+constexpr int PC_NODE0 = PC_OFF;
+constexpr size_t WS_ALIGN = 256;
+
+size_t ws_round(size_t b) { return (b + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN; }
+
+// lattice geometry of a context (everything the layout and the launches derive from params)
+void set_geometry(lbib_ctx* c, const lbib_params* p)
+{
+    c->p = *p;
+    c->nn = (int64_t)p->nx * p->ny;
+    c->S = p->n_species;
+    c->ntx = (p->nx + TILE_X - 1) / TILE_X;
+    c->nlty = (p->ny + LTILE_Y - 1) / LTILE_Y;
+    c->nltiles = c->ntx * c->nlty;
+    c->tile_cap = c->ntx * ((p->ny + MIN_LTILE_Y - 1) / MIN_LTILE_Y);
+    c->wpr = (p->nx + 31) / 32;
+    c->partial_count = 4096;
+    c->pop_bytes = (p->storage == LBIB_STORAGE_FP32) ? 4 : 2;
+}
+
+// staging a workspace provides: the largest read-back (moments, spread field, node forces)
+size_t ws_stage_doubles(const lbib_ctx& c, int64_t node_cap)
+{
+    return std::max<size_t>({(size_t)c.nn * (size_t)(3 + c.S), (size_t)node_cap, 8});
+}
+
+void piece_bytes(const lbib_ctx& c, int64_t n_nodes, int64_t n_cells, size_t stage_doubles, size_t b[PC_COUNT])
+{
+    const size_t N = (size_t)n_nodes, C = (size_t)n_cells;
+    b[PC_F0] = b[PC_F1] = c.f_elems() * c.pop_bytes;
+    b[PC_G0] = b[PC_G1] = c.S ? c.g_elems() * c.pop_bytes : 0;
+    b[PC_IN0] = b[PC_IN1] = (size_t)c.ny_words() * sizeof(unsigned);
+    b[PC_TCOUNT] = b[PC_TCUR] = (size_t)c.tile_cap * sizeof(int);
+    b[PC_TOFF] = ((size_t)c.tile_cap + 1) * sizeof(int);
+    b[PC_ERR] = sizeof(int);
+    b[PC_PARTIAL] = c.partial_count * 5 * sizeof(double);
+    b[PC_STAGE] = stage_doubles * sizeof(double);
+    b[PC_OFF] = N ? (C + 1) * sizeof(int) : 0;
+    b[PC_X] = N * sizeof(double2);
+    b[PC_L0] = N * sizeof(double);
+    b[PC_A0] = b[PC_AREA] = C * sizeof(double);
+    b[PC_IJ] = b[PC_RECIJ] = N * sizeof(int);
+    b[PC_PART] = N * MAX_NODE_TILES * sizeof(float2);
+    b[PC_CNT] = N;
+    b[PC_REC] = N * sizeof(float4);
+    b[PC_LIST] = N * MAX_NODE_TILES * sizeof(int);
+    b[PC_SRC] = C;
+}
+
+void** piece_slot(lbib_ctx* c, int i)
+{
+    switch (i) {
+    case PC_F0: return &c->f[0];
+    case PC_F1: return &c->f[1];
+    case PC_G0: return &c->g[0];
+    case PC_G1: return &c->g[1];
+    case PC_IN0: return reinterpret_cast<void**>(&c->inside[0]);
+    case PC_IN1: return reinterpret_cast<void**>(&c->inside[1]);
+    case PC_TCOUNT: return reinterpret_cast<void**>(&c->d_t_count);
+    case PC_TOFF: return reinterpret_cast<void**>(&c->d_t_off);
+    case PC_TCUR: return reinterpret_cast<void**>(&c->d_t_cur);
+    case PC_ERR: return reinterpret_cast<void**>(&c->d_err);
+    case PC_PARTIAL: return reinterpret_cast<void**>(&c->d_partial);
+    case PC_STAGE: return reinterpret_cast<void**>(&c->d_stage);
+    case PC_OFF: return reinterpret_cast<void**>(&c->d_off);
+    case PC_X: return reinterpret_cast<void**>(&c->d_X);
+    case PC_L0: return reinterpret_cast<void**>(&c->d_l0);
+    case PC_A0: return reinterpret_cast<void**>(&c->d_A0);
+    case PC_AREA: return reinterpret_cast<void**>(&c->d_area);
+    case PC_IJ: return reinterpret_cast<void**>(&c->d_ijlist);
+    case PC_PART: return reinterpret_cast<void**>(&c->d_part);
+    case PC_CNT: return reinterpret_cast<void**>(&c->d_cnt);
+    case PC_REC: return reinterpret_cast<void**>(&c->d_rec);
+    case PC_RECIJ: return reinterpret_cast<void**>(&c->d_rec_ij);
+    case PC_LIST: return reinterpret_cast<void**>(&c->d_list);
+    default: return reinterpret_cast<void**>(&c->d_src);
+    }
+}
+
+// bytes of a workspace holding the lattice part and a node part for node_cap nodes
+size_t ws_total(const lbib_ctx& c, int64_t node_cap)
+{
+    size_t b[PC_COUNT];
+    piece_bytes(c, node_cap, node_cap / 3, ws_stage_doubles(c, node_cap), b);
+    size_t t = 0;
+    for (int i = 0; i < PC_COUNT; ++i) t += ws_round(b[i]);
+    return t;
+}
+
+size_t ws_lattice_part(const lbib_ctx& c, size_t stage_doubles)
+{
+    size_t b[PC_COUNT];
+    piece_bytes(c, 0, 0, stage_doubles, b);
+    size_t t = 0;
+    for (int i = 0; i < PC_NODE0; ++i) t += ws_round(b[i]);
+    return t;
+}
+
+// node pieces of the bound workspace for N nodes in C cells (N <= ws_node_cap)
+void carve_nodes(lbib_ctx* c, int64_t N, int64_t C)
+{
+    size_t b[PC_COUNT];
+    piece_bytes(*c, N, C, 0, b);
+    size_t off = c->ws_node_base;
+    for (int i = PC_NODE0; i < PC_COUNT; ++i) {
+        void* q = b[i] ? (void*)(c->ws + off) : nullptr;
+        if (i == PC_SRC)
+            c->ws_src = (uint8_t*)q;     // claimed by lbib_set_source_cells
+        else
+            *piece_slot(c, i) = q;
+        off += ws_round(b[i]);
+    }
+}
+
+lbib_status alloc_nodes(lbib_ctx* c, size_t N, size_t C)
+{
+    if (c->ws) {
+        carve_nodes(c, (int64_t)N, (int64_t)C);
+        return LBIB_OK;
+    }
+    lbib_status s = dev_alloc(c, &c->d_off, C + 1);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_X, N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_l0, N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_A0, C);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_area, C);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_ijlist, N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_part, N * MAX_NODE_TILES);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_cnt, N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_rec, N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_rec_ij, N);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_list, N * MAX_NODE_TILES);
+    return s;
+}
+
+// Moves every persistent array into the workspace [base, base + bytes) with room for
+// node_cap nodes, or, with base NULL, into memory the library allocates.  The contents are
+// copied on the context's stream; the old memory is released only after all copies
+// succeeded, so on failure the context is unchanged.
+lbib_status relocate(lbib_ctx* c, char* base, size_t bytes, int64_t node_cap)
+{
+    const size_t stage_d = base ? ws_stage_doubles(*c, node_cap) : 0;
+    size_t b[PC_COUNT];
+    piece_bytes(*c, c->n_nodes, c->n_cells, stage_d, b);
+    void* nw[PC_COUNT] = {};
+    uint8_t* new_src_slot = nullptr;
+    size_t new_bytes = 0;
+    lbib_status s = LBIB_OK;
+    if (base) {
+        size_t off = 0;
+        for (int i = 0; i < PC_COUNT; ++i) {
+            if (i == PC_NODE0) off = ws_lattice_part(*c, stage_d);
+            if (b[i]) nw[i] = base + off;
+            off += ws_round(b[i]);
+        }
+        new_src_slot = (uint8_t*)nw[PC_SRC];
+        if (!c->d_src) nw[PC_SRC] = nullptr;
+    } else {
+        for (int i = 0; i < PC_COUNT && s == LBIB_OK; ++i) {
+            if (!b[i] || i == PC_STAGE || (i == PC_SRC && !c->d_src)) continue;
+            hipError_t e = hipMalloc(&nw[i], b[i]);
+            if (e != hipSuccess) {
+                nw[i] = nullptr;
+                c->err = std::string("hipMalloc of ") + std::to_string(b[i]) + " bytes failed: " +
+                         hipGetErrorString(e);
+                s = e == hipErrorOutOfMemory ? LBIB_ENOMEM : LBIB_EDEVICE;
+            } else {
+                new_bytes += b[i];
+            }
+        }
+    }
+    for (int i = 0; i < PC_COUNT && s == LBIB_OK; ++i) {
+        void* old = *piece_slot(c, i);
+        if (i == PC_STAGE || !old || !nw[i]) continue;
+        hipError_t e = hipMemcpyAsync(nw[i], old, b[i], hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) {
+            c->err = std::string("hipMemcpyAsync of the state failed: ") + hipGetErrorString(e);
+            s = LBIB_EDEVICE;
+        }
+    }
+    if (s == LBIB_OK) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            c->err = std::string("hipStreamSynchronize failed: ") + hipGetErrorString(e);
+            s = LBIB_EDEVICE;
+        }
+    }
+    if (s != LBIB_OK) {
+        if (!base)
+            for (int i = 0; i < PC_COUNT; ++i)
+                if (nw[i]) (void)hipFree(nw[i]);
+        return s;
+    }
+    if (!c->ws) {
+        for (int i = 0; i < PC_COUNT; ++i) {
+            void* old = *piece_slot(c, i);
+            if (old) (void)hipFree(old);
+        }
+    }
+    for (int i = 0; i < PC_COUNT; ++i) *piece_slot(c, i) = nw[i];
+    c->device_bytes = new_bytes;
+    c->ws = base;
+    c->ws_bytes = base ? bytes : 0;
+    c->ws_node_cap = base ? node_cap : 0;
+    c->ws_node_base = base ? ws_lattice_part(*c, stage_d) : 0;
+    c->ws_stage_doubles = stage_d;
+    c->ws_src = new_src_slot;
+    c->stage_bytes = stage_d * sizeof(double);
+    return LBIB_OK;
 }
 
 bool any_source_decay(const lbib_params& p)
@@ -493,7 +733,7 @@ lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out)
 
     lbib_ctx* c = new (std::nothrow) lbib_ctx();
     if (!c) return LBIB_ENOMEM;
-    c->p = *p;
+    set_geometry(c, p);
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return LBIB_EDEVICE;
@@ -507,17 +747,7 @@ lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out)
         }
         c->own_stream = true;
     }
-    c->nn = (int64_t)p->nx * p->ny;
-    c->S = p->n_species;
-    c->ntx = (p->nx + TILE_X - 1) / TILE_X;
-    c->nlty = (p->ny + LTILE_Y - 1) / LTILE_Y;
-    c->nltiles = c->ntx * c->nlty;
-    c->tile_cap = c->ntx * ((p->ny + MIN_LTILE_Y - 1) / MIN_LTILE_Y);
-    c->wpr = (p->nx + 31) / 32;
-    c->partial_count = 4096;
-    const size_t nn = (size_t)c->nn;
     lbib_status s = LBIB_OK;
-    c->pop_bytes = (p->storage == LBIB_STORAGE_FP32) ? 4 : 2;
     for (int b = 0; b < 2 && s == LBIB_OK; ++b) {
         char* fb = nullptr;
         char* gb = nullptr;
@@ -581,6 +811,11 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
         c->err = msg;
         return LBIB_EINVAL;
     }
+    if (c->ws && (int64_t)off[n_cells] > c->ws_node_cap) {
+        c->err = "the bound workspace holds " + std::to_string(c->ws_node_cap) + " membrane nodes; " +
+                 std::to_string(off[n_cells]) + " were given";
+        return LBIB_ENOMEM;
+    }
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
     drop_graphs(c);
     free_nodes(c);
@@ -603,18 +838,7 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
         }
         A0[q] = rest_area ? rest_area[q] : 0.5 * A;
     }
-    lbib_status s = LBIB_OK;
-    s = dev_alloc(c, &c->d_off, C + 1);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_X, N);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_l0, N);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_A0, C);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_area, C);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_ijlist, N);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_part, N * MAX_NODE_TILES);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_cnt, N);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_rec, N);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_rec_ij, N);
-    if (s == LBIB_OK) s = dev_alloc(c, &c->d_list, N * MAX_NODE_TILES);
+    lbib_status s = alloc_nodes(c, N, C);
     c->n_cells = n_cells;
     c->n_nodes = (int64_t)N;
     if (s != LBIB_OK) {
@@ -788,10 +1012,15 @@ lbib_status lbib_set_source_cells(lbib_ctx* c, const uint8_t* src)
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
     drop_graphs(c);
     if (src) {
-        if (!c->d_src) LBIB_TRY(dev_alloc(c, &c->d_src, (size_t)c->n_cells));
+        if (!c->d_src) {
+            if (c->ws)
+                c->d_src = c->ws_src;
+            else
+                LBIB_TRY(dev_alloc(c, &c->d_src, (size_t)c->n_cells));
+        }
         LBIB_HIP(c, hipMemcpyAsync(c->d_src, src, (size_t)c->n_cells, hipMemcpyHostToDevice, c->stream));
     } else {
-        dev_free(c, c->d_src, (size_t)c->n_cells);
+        state_free(c, c->d_src, (size_t)c->n_cells);
     }
     if (c->mask_needed) {
         // rebuild the source bits of the current positions (forces and records are recomputed
@@ -1119,6 +1348,85 @@ lbib_status lbib_get_timing(lbib_ctx* c, int32_t kernel, double* total_ms, int64
     LBIB_TRY(harvest(c));
     if (total_ms) *total_ms = c->t_ms[kernel];
     if (launches) *launches = c->t_count[kernel];
+    return LBIB_OK;
+}
+
+lbib_status lbib_workspace_size(const lbib_params* p, int64_t n_nodes, size_t* bytes)
+{
+    if (!bytes) return LBIB_EINVAL;
+    *bytes = 0;
+    std::string msg;
+    if (check_params(p, msg) != LBIB_OK || n_nodes < 0) return LBIB_EINVAL;
+    lbib_ctx g;
+    set_geometry(&g, p);
+    *bytes = ws_total(g, n_nodes);
+    return LBIB_OK;
+}
+
+lbib_status lbib_bind_workspace(lbib_ctx* c, void* device_ptr, size_t bytes)
+{
+    if (!c) return LBIB_ESTATE;
+    LBIB_TRY(refuse_if_batched(c));
+    char* base = (char*)device_ptr;
+    if (!base) {
+        if (bytes) {
+            c->err = "a NULL workspace must have 0 bytes";
+            return LBIB_EINVAL;
+        }
+        if (!c->ws) return LBIB_OK;
+    } else {
+        if ((uintptr_t)base % WS_ALIGN) {
+            c->err = "the workspace must start on a " + std::to_string(WS_ALIGN) + "-byte boundary";
+            return LBIB_EINVAL;
+        }
+        if (c->ws && base < c->ws + c->ws_bytes && c->ws < base + bytes) {
+            c->err = "the new workspace overlaps the bound one";
+            return LBIB_EINVAL;
+        }
+        hipPointerAttribute_t at{};
+        if (hipPointerGetAttributes(&at, base) != hipSuccess || at.type != hipMemoryTypeDevice ||
+            at.device != c->device) {
+            (void)hipGetLastError();
+            c->err = "the workspace is not device memory of the context's device";
+            return LBIB_EINVAL;
+        }
+        void* abase = nullptr;
+        size_t asize = 0;
+        if (hipMemGetAddressRange(&abase, &asize, base) != hipSuccess ||
+            base + bytes > (char*)abase + asize) {
+            (void)hipGetLastError();
+            c->err = "the workspace extends past the end of its allocation";
+            return LBIB_EINVAL;
+        }
+    }
+    int64_t cap = 0;
+    if (base) {
+        const size_t need = ws_total(*c, c->n_nodes);
+        if (bytes < need) {
+            c->err = "the workspace has " + std::to_string(bytes) + " bytes; " + std::to_string(need) +
+                     " are needed for the lattice and " + std::to_string(c->n_nodes) + " membrane nodes";
+            return LBIB_ENOMEM;
+        }
+        // largest node capacity that fits (ws_total grows with it by >= 16 bytes a node)
+        int64_t lo = c->n_nodes, hi = (int64_t)(bytes / 16) + 1;
+        while (hi - lo > 1) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if (ws_total(*c, mid) <= bytes)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        cap = lo;
+    }
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    return relocate(c, base, bytes, cap);
+}
+
+lbib_status lbib_workspace_nodes(const lbib_ctx* c, int64_t* n_nodes)
+{
+    if (!c || !n_nodes) return LBIB_EINVAL;
+    *n_nodes = c->ws ? c->ws_node_cap : -1;
     return LBIB_OK;
 }
 

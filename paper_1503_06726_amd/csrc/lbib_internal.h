@@ -82,7 +82,17 @@ struct lbib_ctx {
     double* d_partial = nullptr;     // reduction partials
     size_t partial_count = 0;
 
-    size_t device_bytes = 0;
+    size_t device_bytes = 0;         // bytes the library allocated itself
+
+    // caller-owned workspace (lbib_bind_workspace): while ws is set, every persistent array
+    // above lives in it, in the order of the workspace layout, and none is allocated or freed
+    // by the library
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    size_t ws_node_base = 0;         // byte offset of the node part
+    int64_t ws_node_cap = 0;         // membrane nodes the node part holds
+    size_t ws_stage_doubles = 0;     // staging capacity
+    uint8_t* ws_src = nullptr;       // the source-cell slot of the node part
 
     // captured step sequences: GRAPH_STEPS steps starting right after a list build, one graph
     // per parity (cur) of the population buffers at the start

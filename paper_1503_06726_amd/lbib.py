@@ -32,7 +32,8 @@ EXPORTS = ["lbib_validate_params", "lbib_validate_cells", "lbib_create", "lbib_s
            "lbib_net_predict", "lbib_net_loss_grad", "lbib_net_train_step", "lbib_net_destroy",
            "lbib_batch_create", "lbib_batch_step", "lbib_batch_sync", "lbib_batch_get_tile",
            "lbib_batch_set_tile", "lbib_batch_get_groups", "lbib_batch_set_groups", "lbib_batch_autotune",
-           "lbib_batch_last_error", "lbib_batch_destroy"]
+           "lbib_batch_last_error", "lbib_batch_destroy",
+           "lbib_workspace_size", "lbib_bind_workspace", "lbib_workspace_nodes"]
 
 
 class Species(C.Structure):
@@ -109,6 +110,12 @@ def lib():
     L.lbib_version.argtypes = []
     L.lbib_destroy.restype = None
     L.lbib_destroy.argtypes = [vp]
+    L.lbib_workspace_size.restype = st
+    L.lbib_workspace_size.argtypes = [P, C.c_int64, C.POINTER(C.c_size_t)]
+    L.lbib_bind_workspace.restype = st
+    L.lbib_bind_workspace.argtypes = [vp, vp, C.c_size_t]
+    L.lbib_workspace_nodes.restype = st
+    L.lbib_workspace_nodes.argtypes = [vp, C.POINTER(C.c_int64)]
     L.lbib_set_source_cells.restype = st
     L.lbib_set_source_cells.argtypes = [vp, vp]
     L.lbib_net_create.restype = st
@@ -203,6 +210,17 @@ def validate_cells(d: dict, offsets, xy, rest_len=None, rest_area=None):
     return s, msg.value.decode()
 
 
+def workspace_size(params: dict, n_nodes: int) -> int:
+    """Bytes of a workspace for ``params`` and at most ``n_nodes`` membrane nodes
+    (lbib_workspace_size)."""
+    p = make_params(params)
+    b = C.c_size_t()
+    s = lib().lbib_workspace_size(C.byref(p), int(n_nodes), C.byref(b))
+    if s != OK:
+        raise LbibError(s, "lbib_workspace_size")
+    return int(b.value)
+
+
 class Simulation:
     """One lbib context: ``create`` on construction, ``destroy`` on ``close``.
 
@@ -227,6 +245,7 @@ class Simulation:
         if getattr(self, "h", None):
             self.L.lbib_destroy(self.h)
             self.h = None
+        self._ws_owner = None
 
     def __del__(self):
         self.close()
@@ -316,6 +335,19 @@ class Simulation:
         n = C.c_int64()
         self._check(self.L.lbib_get_timing(self.h, int(kernel), C.byref(ms), C.byref(n)), "lbib_get_timing")
         return ms.value, n.value
+
+    def bind_workspace(self, ptr: int | None, nbytes: int = 0, owner=None):
+        """Move the state into caller device memory at ``ptr`` (lbib_bind_workspace); None moves
+        it back into library memory.  ``owner`` (a torch tensor, say) is kept alive while bound."""
+        self._check(self.L.lbib_bind_workspace(self.h, C.c_void_p(ptr) if ptr else None,
+                                               int(nbytes) if ptr else 0), "lbib_bind_workspace")
+        self._ws_owner = owner if ptr else None
+
+    def workspace_nodes(self) -> int:
+        """Node capacity of the bound workspace, -1 when none is bound."""
+        n = C.c_int64()
+        self._check(self.L.lbib_workspace_nodes(self.h, C.byref(n)), "lbib_workspace_nodes")
+        return int(n.value)
 
     def device_bytes(self) -> int:
         b = C.c_size_t()

@@ -137,3 +137,48 @@ def test_workload_inputs_pass_validation():
         assert lbib.validate_params(w.params_dict())[0] == lbib.OK
         s, msg = lbib.validate_cells(w.params_dict(), w.offsets, w.xy, w.rest_len, w.rest_area)
         assert s == lbib.OK, msg
+
+
+# ---- lbib_workspace_size: a pure host function of the parameters and the node capacity ----
+def _ws(d, n):
+    return lbib.workspace_size(d, n)
+
+
+def test_workspace_size_covers_the_state():
+    """At least the bytes of the state it holds (two population buffers per lattice, the
+    membrane arrays per node), monotone in the node capacity, and only padding beyond that."""
+    d = dict(W.small_tissue(nx=200, ny=130, n_species=1).params_dict())
+    nx, ny, S = d["nx"], d["ny"], len(d["species"])
+    pops = 2 * (9 + 5 * S) * ny * (-(-nx // 64) * 64) * 4          # FP32, rows padded to 64 columns
+    base = _ws(d, 0)
+    assert base >= pops
+    assert base - pops < (3 + S) * nx * ny * 8 + 256 * 1024         # + staging of the moments, partial sums, bits
+    sizes = [_ws(d, n) for n in (0, 3, 300, 3000, 30000, 300000)]
+    assert sizes == sorted(sizes)
+    per_node = (sizes[-1] - sizes[-2]) / 270000
+    # position 16 + rest length 8 + stencil origins 8 + shares 72 + count 1 + record 16 + lists 36,
+    # cells (<= n/3) 8 + 8 + 4 + 1 bytes each; and the staging grows once n exceeds (3+S) nx ny
+    assert 150 <= per_node <= 200, per_node
+
+
+def test_workspace_size_follows_storage_and_species():
+    d = dict(W.small_tissue(nx=200, ny=130, n_species=1).params_dict())
+    h = dict(d, storage=lbib.STORAGE_FP16)
+    n0 = dict(d, species=[])
+    assert _ws(h, 100) < _ws(d, 100)
+    assert _ws(n0, 100) < _ws(d, 100)
+    # FP16 halves the population buffers, nothing else
+    nxp = -(-d["nx"] // 64) * 64
+    saved = _ws(d, 100) - _ws(h, 100)
+    want = 2 * (9 + 5) * d["ny"] * nxp * 2
+    assert abs(saved - want) <= 4 * 256
+
+
+def test_workspace_size_rejects_bad_input():
+    d = dict(GOOD)
+    with pytest.raises(lbib.LbibError) as e:
+        _ws(d, -1)
+    assert e.value.status == lbib.EINVAL
+    with pytest.raises(lbib.LbibError) as e:
+        _ws(dict(d, tau=0.5), 10)
+    assert e.value.status == lbib.EINVAL
