@@ -231,6 +231,33 @@ def tiny_cell(steps: int = 200) -> Workload:
     return _attach_geometry(w, offsets, xy, rest_len=l0, rest_area=np.array([math.pi * 100.0]))
 
 
+LEAKAGE_LEVELS = 4                     # lattice resolutions of the leakage study
+LEAKAGE_MAXLENGTHS = (0.1, 0.5, 2.5)   # largest node spacing, in lattice units
+
+
+def leakage_case(level: int, maxlength: float, steps: int | None = None) -> Workload:
+    """The membrane-leakage validation (Section "Validation", Case IV): one circular cell under
+    a constant membrane tension and nothing else (no springs, no area term, no mass source,
+    no species), at resolution ``level`` = 0..3 of the paper's study:
+      lattice 100 * 2^level squared, periodic in x and y, tau = 1 (nu = 1/6);
+      cell diameter 10 * 2^level lattice units (the unit circle of area pi / 4 at dx =
+      0.1 / 2^level), centred in the lattice;
+      tension phi_m = 1e-3 / 2^level (the tabulated lattice force of each resolution);
+      ceil(pi D / maxlength) equally spaced nodes, so no edge exceeds ``maxlength``;
+      10^4 * 4^level steps (one unit of non-dimensional time, dt = 1e-4 / 4^level)."""
+    if not 0 <= level < LEAKAGE_LEVELS:
+        raise ValueError("level must be 0..3")
+    L = 100 * 2 ** level
+    D = 10.0 * 2 ** level
+    n = int(math.ceil(math.pi * D / maxlength))
+    offsets, xy = circle_cell(L / 2.0, L / 2.0, D / 2.0, n, 0.0, None)
+    w = Workload(name=f"leakage level {level}: {L}x{L} periodic, one {n}-node circle of diameter {D:g}, "
+                      f"max spacing {maxlength:g}",
+                 nx=L, ny=L, bc_y=PERIODIC, tau=1.0, rho0=1.0, phi_m=1e-3 / 2 ** level,
+                 delta_kernel=DELTA_COS4, steps=10000 * 4 ** level if steps is None else steps)
+    return _attach_geometry(w, offsets, xy)
+
+
 def tissue(steps: int = 10000) -> Workload:
     """512x512, no-slip walls in y, periodic in x, tau = 0.8, 100 Voronoi cells at 0.5 lu
     node spacing, springs k = 0.02 at their initial lengths, body acceleration 1e-6 along x,
