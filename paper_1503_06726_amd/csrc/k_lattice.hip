@@ -129,6 +129,33 @@ __device__ inline unsigned long long to_fixed(float v)
     return (unsigned long long)__float2ll_rn(v * FIX_SCALE);
 }
 
+// A node's force component F in fixed point (F 2^48), split for the weighted contributions
+struct FixedForce {
+    int hi;           // signed upper word
+    unsigned lo;      // lower word
+};
+
+__device__ inline FixedForce fixed_force(float v)
+{
+    const long long q = (long long)to_fixed(v);
+    int hi = (int)(q >> 32);
+    // an empty asm statement: the compiler then treats hi as a plain 32-bit integer and
+    // multiplies it with one signed 32 x 32 -> 64 multiply-add, not a 64-bit product
+    asm volatile("" : "+v"(hi));
+    return {hi, (unsigned)q};
+}
+
+// floor(F 2^48 * wq / 2^32) for a stencil weight wq = w 2^32 (0 <= w <= 1/4, so wq < 2^31):
+// the spread contribution w F in the same fixed point, from two integer products (exact but
+// for the floor): a signed 32 x 32 -> 64 multiply-add of the upper word and the high half of
+// the lower word's product
+__device__ inline unsigned long long weighted_fixed(FixedForce f, unsigned wq)
+{
+    return (unsigned long long)((long long)f.hi * (long long)(int)wq + (long long)__umulhi(f.lo, wq));
+}
+
+constexpr float WQ_SCALE = 4294967296.0f;   // 2^32
+
 constexpr int SPREAD_UNROLL = 1;   // listed nodes per thread whose loads are issued together
 
 // The tile's LDS arrays (spread force accumulators, staged velocity) hold rows of TILE_X + 1
@@ -203,7 +230,7 @@ template <bool INTERP, bool DEFER = false>
 __device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0, int y1,
                                     const int ij[SPREAD_UNROLL], const float4 rc[SPREAD_UNROLL],
                                     const int ent[SPREAD_UNROLL], unsigned long long* accx, unsigned long long* accy,
-                                    const float* uxs, const float* uys, float2* Ud = nullptr)
+                                    const float2* us, float2* Ud = nullptr)
 {
 #pragma unroll
     for (int u = 0; u < SPREAD_UNROLL; ++u) {
@@ -232,6 +259,7 @@ __device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0
         float wx[4], wy[4];
         delta_weights(a.kernel, r.x, wx);
         delta_weights(a.kernel, r.y, wy);
+        const FixedForce fx = fixed_force(r.z), fy = fixed_force(r.w);
         float Ux = 0.0f, Uy = 0.0f;
 #pragma unroll
         for (int bb = 0; bb < 4; ++bb) {
@@ -240,13 +268,15 @@ __device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0
 #pragma unroll
             for (int aa = 0; aa < 4; ++aa) {
                 if (!((hx >> aa) & 1u)) continue;
-                const float w = wx[aa] * wy[bb];
                 const int o = ly[bb] * LDS_ROW + lx[aa];
-                atomicAdd(&accx[o], to_fixed(w * r.z));
-                atomicAdd(&accy[o], to_fixed(w * r.w));
+                float2 uv;
+                if constexpr (INTERP) uv = us[o];          // read first: the atomics need not wait for it
+                const unsigned wq = (unsigned)(wx[aa] * wy[bb] * WQ_SCALE);
+                atomicAdd(&accx[o], weighted_fixed(fx, wq));
+                atomicAdd(&accy[o], weighted_fixed(fy, wq));
                 if constexpr (INTERP) {
-                    sx += wx[aa] * uxs[o];
-                    sy += wx[aa] * uys[o];
+                    sx += wx[aa] * uv.x;
+                    sy += wx[aa] * uv.y;
                 }
             }
             if constexpr (INTERP) {
@@ -279,7 +309,7 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
     const int x = x0 + (t % TILE_X);
 
     __shared__ unsigned long long accx[NL], accy[NL];
-    __shared__ float uxs[NL], uys[NL];
+    __shared__ float2 us[NL];
 
     // Load order: the first chunk's list entries, the populations, then the records the entries
     // name.  Loads complete in order, so waiting for the entries does not wait for the
@@ -341,14 +371,13 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
         ux_r[r] = jx * inv;
         uy_r[r] = jy * inv;
         if constexpr (NODES) {
-            uxs[lds_slot(t, r)] = ux_r[r];
-            uys[lds_slot(t, r)] = uy_r[r];
+            us[lds_slot(t, r)] = make_float2(ux_r[r], uy_r[r]);
         }
     }
 
     if constexpr (NODES) {
         __syncthreads();
-        couple_chunk<true, true>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, uxs, uys, Ud);
+        couple_chunk<true, true>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, us, Ud);
         if (lend - lbeg > SPREAD_UNROLL * TILE_N) {
             int ent0[SPREAD_UNROLL];                      // the first chunk's entries, stored last
 #pragma unroll
@@ -356,7 +385,7 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
             float2 Ux[SPREAD_UNROLL];
             for (int k0 = lbeg + SPREAD_UNROLL * TILE_N; k0 < lend; k0 += SPREAD_UNROLL * TILE_N) {
                 load_candidates(a, k0, lend, cij, crc, cnd);
-                couple_chunk<true>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, uxs, uys, Ux);
+                couple_chunk<true>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, us, Ux);
             }
 #pragma unroll
             for (int u = 0; u < SPREAD_UNROLL; ++u) cnd[u] = ent0[u];
@@ -490,7 +519,7 @@ __global__ __launch_bounds__(TILE_N) void k_spread_inspect(LatticeArgs a)
         float4 crc[SPREAD_UNROLL];
         for (int k0 = lbeg; k0 < lend; k0 += SPREAD_UNROLL * TILE_N) {
             load_candidates(a, k0, lend, cij, crc, cnd);
-            couple_chunk<false>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, nullptr, nullptr);
+            couple_chunk<false>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, nullptr);
         }
     }
     __syncthreads();
