@@ -265,18 +265,20 @@ __device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0
         for (int bb = 0; bb < 4; ++bb) {
             if (!((hy >> bb) & 1u)) continue;
             float sx = 0.0f, sy = 0.0f;
+            // the row's four columns without branches: a column outside the tile adds zero to
+            // the row's first slot and contributes nothing to the velocity
 #pragma unroll
             for (int aa = 0; aa < 4; ++aa) {
-                if (!((hx >> aa) & 1u)) continue;
-                const int o = ly[bb] * LDS_ROW + lx[aa];
+                const bool in = (hx >> aa) & 1u;
+                const int o = ly[bb] * LDS_ROW + (in ? lx[aa] : 0);
                 float2 uv;
                 if constexpr (INTERP) uv = us[o];          // read first: the atomics need not wait for it
-                const unsigned wq = (unsigned)(wx[aa] * wy[bb] * WQ_SCALE);
+                const unsigned wq = in ? (unsigned)(wx[aa] * wy[bb] * WQ_SCALE) : 0u;
                 atomicAdd(&accx[o], weighted_fixed(fx, wq));
                 atomicAdd(&accy[o], weighted_fixed(fy, wq));
                 if constexpr (INTERP) {
-                    sx += wx[aa] * uv.x;
-                    sy += wx[aa] * uv.y;
+                    sx += in ? wx[aa] * uv.x : 0.0f;
+                    sy += in ? wx[aa] * uv.y : 0.0f;
                 }
             }
             if constexpr (INTERP) {
