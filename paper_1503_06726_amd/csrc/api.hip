@@ -217,6 +217,8 @@ ListArgs list_args_h(lbib_ctx* c, int lty)
     a.nlty = (c->p.ny + lty - 1) / lty;
     a.ntiles = c->ntx * a.nlty;
     a.lty = lty;
+    a.lty_shift = 0;
+    while ((1 << a.lty_shift) < lty) ++a.lty_shift;
     return a;
 }
 

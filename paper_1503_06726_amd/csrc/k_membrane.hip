@@ -297,7 +297,7 @@ __device__ inline int node_tiles(int i0, int j0, const ListArgs& a, int tiles[MA
         } else {
             j = wrap_i(j, a.ny);
         }
-        const int rr = j / a.lty;
+        const int rr = j >> a.lty_shift;                      // j >= 0 here
         bool seen = false;
         for (int k = 0; k < nr; ++k) seen = seen || rows[k] == rr;
         if (!seen && nr < 3) rows[nr++] = rr;

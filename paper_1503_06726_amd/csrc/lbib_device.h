@@ -128,6 +128,7 @@ struct ListArgs {
     int64_t n;
     int nx, ny, walls, ntx, nlty, ntiles;
     int lty;                           // rows per lattice tile (TILE_Y times the rows per thread)
+    int lty_shift;                     // log2(lty): tile heights are powers of two
 };
 
 // ADE-only iteration (species with u = 0, fluid and membranes frozen) in a working set of
