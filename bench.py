@@ -314,7 +314,7 @@ def main():
     b_step = step_bytes_per_update(S, mask, w.n_nodes, nn, pb)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": LATTICE_TRAFFIC_BYTES if args.storage == "fp32" and w.name == "large" else None,
+            "traffic": LATTICE_TRAFFIC_BYTES if args.storage == "fp32" and args.workload == "large" else None,
             "kernel": "k_lattice", "bytes_per_update": b_lat, "us_per_launch": round(lat_s * 1e6, 2),
             "step_bytes_per_update": round(b_step, 2),
             "step_frac": round(b_step * mlups * 1e6 / 1e9 / HBM_PEAK_GBS, 4)}

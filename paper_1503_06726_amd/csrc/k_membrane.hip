@@ -1,6 +1,6 @@
 // Membrane kernels of the coupled step (gfx950).
 //
-// k_membrane: one workgroup (two wavefronts) per cell.  In a time step it
+// k_membrane: one workgroup (three wavefronts) per cell.  In a time step it
 //   1. adds the node's interpolated velocity U (Eq. conversion2 with the kernel of
 //      Eq. 1Dkernel; the lattice pass leaves one share per listed tile, added here in the
 //      order of the node's tiles) and moves the node explicitly, X^{n+1} = X^n + U
@@ -87,10 +87,10 @@ __device__ inline void block_reduce5(double& sum, double m[4], double* red)
 
 // One cell per workgroup: xs holds the cell's positions (dynamic LDS), red the reduction
 // slots, bm the raster bitmap.
+template <int NT, int NB>
 __device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c, double2* xs, double* red,
                                               unsigned* bm)
 {
-    constexpr int NT = MEMBRANE_THREADS, NB = MEMBRANE_BATCH;
     const int t = threadIdx.x;
     const int beg = a.off[c];
     const int n = a.off[c + 1] - beg;
@@ -243,27 +243,29 @@ __device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c
     if (flags) atomicOr(a.err, flags);
 }
 
-// Two wavefronts per cell: 5 waves per SIMD keep every workgroup of a 2000-cell step resident
-// at once, with the registers for the loads of MEMBRANE_BATCH nodes per lane
-__global__ __launch_bounds__(MEMBRANE_THREADS) __attribute__((amdgpu_waves_per_eu(5))) void k_membrane(MembraneArgs a)
+// Three wavefronts per cell with two nodes per lane: a pass covers 384 nodes, and 6 waves per
+// SIMD keep every workgroup of a 2000-cell step resident at once (more nodes per pass cost
+// the registers that residency needs; a cell beyond a pass takes another)
+__global__ __launch_bounds__(MEMBRANE_THREADS) __attribute__((amdgpu_waves_per_eu(6))) void k_membrane(MembraneArgs a)
 {
     extern __shared__ double2 xs[];
     __shared__ double red[5 * (MEMBRANE_THREADS / 64)];
     __shared__ unsigned bm[RASTER_WORDS_FUSED];
-    membrane_cell(a, blockIdx.x, xs, red, bm);
+    membrane_cell<MEMBRANE_THREADS, MEMBRANE_BATCH>(a, blockIdx.x, xs, red, bm);
 }
 
 // Batched form: one (simulation, cell) work item per workgroup, the simulation's arguments
-// from a device table.
-__global__ __launch_bounds__(MEMBRANE_THREADS) __attribute__((amdgpu_waves_per_eu(5))) void k_membrane_batch(const MembraneArgs* __restrict__ tab,
+// from a device table.  The cells of many simulations take several rounds of workgroups,
+// where two wavefronts per cell with three nodes per lane keep more cells in flight.
+__global__ __launch_bounds__(MEMBRANE_THREADS_MANY) __attribute__((amdgpu_waves_per_eu(5))) void k_membrane_batch(const MembraneArgs* __restrict__ tab,
                                                                      const int2* __restrict__ work)
 {
     extern __shared__ double2 xs[];
-    __shared__ double red[5 * (MEMBRANE_THREADS / 64)];
+    __shared__ double red[5 * (MEMBRANE_THREADS_MANY / 64)];
     __shared__ unsigned bm[RASTER_WORDS_FUSED];
     const int2 wk = work[blockIdx.x];
     const MembraneArgs a = tab[wk.x];
-    membrane_cell(a, wk.y, xs, red, bm);
+    membrane_cell<MEMBRANE_THREADS_MANY, MEMBRANE_BATCH_MANY>(a, wk.y, xs, red, bm);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -524,7 +526,7 @@ hipError_t launch_membrane_batch(const MembraneArgs* tab, const int2* work, int 
 {
     if (nwork <= 0) return hipSuccess;
     const size_t lds = sizeof(double2) * (size_t)(max_cell_nodes > 0 ? max_cell_nodes : 1);
-    hipLaunchKernelGGL(k_membrane_batch, dim3((unsigned)nwork), dim3(MEMBRANE_THREADS), lds, stream, tab, work);
+    hipLaunchKernelGGL(k_membrane_batch, dim3((unsigned)nwork), dim3(MEMBRANE_THREADS_MANY), lds, stream, tab, work);
     return hipGetLastError();
 }
 

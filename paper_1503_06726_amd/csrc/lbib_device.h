@@ -38,8 +38,10 @@ constexpr int LIST_PERIOD = 16;      // steps between list rebuilds (nodes may m
 constexpr int MAX_NODE_TILES = 9;    // tiles one node can be listed in (3 columns x 3 rows at most)
 constexpr int GRAPH_STEPS = 16;      // steps per captured graph (a multiple of LIST_PERIOD)
 
-constexpr int MEMBRANE_THREADS = 128;             // two wavefronts per cell
-constexpr int MEMBRANE_BATCH = 3;               // nodes per lane whose loads are issued together
+constexpr int MEMBRANE_THREADS = 192;             // three wavefronts per cell
+constexpr int MEMBRANE_BATCH = 2;               // nodes per lane whose loads are issued together
+constexpr int MEMBRANE_THREADS_MANY = 128;        // the batched form: two wavefronts per cell,
+constexpr int MEMBRANE_BATCH_MANY = 3;           // three nodes per lane (several rounds of cells)
 constexpr int MAX_CELL_NODES = 4096;            // LDS holds one cell's positions as double2
 constexpr int RASTER_THREADS = 256;
 constexpr int RASTER_WORDS_FUSED = 1024;        // 4 KB bitmap inside the membrane kernel
