@@ -482,10 +482,16 @@ constexpr int lattice_waves(int S, int RP, bool)
     return RP == 1 ? 6 : RP == 2 ? (S <= 1 ? 5 : 4) : 3;
 }
 
+// Workgroups take tiles in plain row-major order.  The dispatcher deals workgroups round-robin
+// over the 8 XCDs, so the whole chip sweeps one band of the lattice at a time (the HBM
+// channels see neighbouring addresses), and with a multiple of 8 tile columns every tile
+// column stays on one XCD, whose L2 then serves the records and halo rows that vertically
+// adjacent tiles share.  Giving each XCD a contiguous eighth of the lattice instead was 4 %
+// slower at 2048^2.
 template <int S, bool NODES, bool MASK, int ST>
 __global__ __launch_bounds__(TILE_N) __attribute__((amdgpu_waves_per_eu(lattice_waves(S, RPT, false)))) void k_lattice(LatticeArgs a)
 {
-    lattice_tile<S, NODES, MASK, ST, RPT>(a, xcd_remap(blockIdx.x, gridDim.x));
+    lattice_tile<S, NODES, MASK, ST, RPT>(a, (int)blockIdx.x);
 }
 
 // Batched form: every workgroup takes one (simulation, tile) work item; the simulation's
@@ -495,7 +501,7 @@ template <int S, bool NODES, bool MASK, int ST, int RP>
 __global__ __launch_bounds__(TILE_N) __attribute__((amdgpu_waves_per_eu(lattice_waves(S, RP, true)))) void k_lattice_batch(const LatticeArgs* __restrict__ tab,
                                                           const int2* __restrict__ work)
 {
-    const int2 wk = work[xcd_remap(blockIdx.x, gridDim.x)];
+    const int2 wk = work[blockIdx.x];
     const LatticeArgs a = tab[wk.x];
     lattice_tile<S, NODES, MASK, ST, RP>(a, wk.y);
 }

@@ -266,15 +266,5 @@ __device__ constexpr float IS9[9] = {1.0f / 2304.0f, 1.0f / 9216.0f, 1.0f / 9216
 __device__ constexpr float SC5[5] = {3072.0f, 6144.0f, 6144.0f, 6144.0f, 6144.0f};
 __device__ constexpr float IS5[5] = {1.0f / 3072.0f, 1.0f / 6144.0f, 1.0f / 6144.0f, 1.0f / 6144.0f, 1.0f / 6144.0f};
 
-// XCD-aware workgroup order: the dispatcher deals workgroups round-robin over the 8 XCDs;
-// remap so each XCD walks a contiguous run of tiles (neighbouring tiles share cache lines
-// at their x edges and list many of the same membrane nodes, and each XCD has its own L2).
-__device__ inline int xcd_remap(int bid, int nblocks)
-{
-    const int NX = 8;
-    int xcd = bid % NX, local = bid / NX;
-    int q = nblocks / NX, r = nblocks % NX;
-    return (xcd < r) ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
-}
 
 }  // namespace lbib
