@@ -85,7 +85,10 @@ def run_pair(w, steps):
 # lattice alone (rows: D2Q9 collide/stream with body force, D2Q5 per species, walls)
 # ------------------------------------------------------------------------------------------
 @pytest.mark.parametrize("bc,S,nx,ny", [(0, 0, 200, 130), (1, 1, 200, 130), (1, 2, 67, 45), (0, 2, 64, 64),
-                                        (0, 1, 4, 4), (1, 0, 131, 9)])
+                                        (0, 1, 4, 4), (1, 0, 131, 9),
+                                        # tile orders: 8 or 16 tile columns with an odd or even
+                                        # number of 8-row tile rows
+                                        (0, 1, 512, 72), (1, 1, 1024, 40), (0, 0, 512, 64)])
 def test_lattice_only(bc, S, nx, ny):
     w = W.Workload(name=f"lattice {nx}x{ny} bc={bc} S={S}", nx=nx, ny=ny, bc_y=bc, tau=0.8,
                    body_accel=(2e-5, -1e-5))
