@@ -130,7 +130,7 @@ lbib_status build_tables(lbib_batch* b, int lty)
             }
             const ListArgs la = list_args_h(c, lty);
             lst.push_back(la);
-            for (int t = 0; t < la.ntiles; ++t) wl.push_back(make_int2(gs, t));
+            for (int t = 0; t < la.ntiles; ++t) wl.push_back(make_int2(gs, tile_of_block(t, la.ntx, la.nlty)));
             for (int q = 0; q < c->n_cells; ++q) wm.push_back(make_int2(gs, q));
             const int64_t nb = (c->n_nodes + LIST_THREADS - 1) / LIST_THREADS;
             for (int64_t q = 0; q < nb; ++q) wn.push_back(make_int2(gs, (int)q));

@@ -482,24 +482,6 @@ constexpr int lattice_waves(int S, int RP, bool)
     return RP == 1 ? 6 : RP == 2 ? (S <= 1 ? 5 : 4) : 3;
 }
 
-// Tile of a workgroup.  The dispatcher deals workgroups round-robin over the 8 XCDs.  Tiles
-// go out by bands of two tile rows, so the whole chip sweeps one band of the lattice at a time
-// (the HBM channels see neighbouring addresses); when the column count allows, each XCD takes
-// a contiguous eighth of the columns and keeps those columns in every band, visiting the two
-// rows of a column one after the other.  An XCD's L2 then serves the halo columns that
-// horizontally adjacent tiles share, and the records and halo rows of vertically adjacent
-// ones.  At 2048^2 this order beats plain row-major order by 3 % and giving each XCD a
-// contiguous eighth of the lattice by 7 %.  With an odd number of tile rows the band is one
-// row; with a column count that is not a multiple of 8, the order is plain row-major.
-__device__ inline int tile_of_block(int bid, int ntx, int nlty)
-{
-    if (ntx & 7) return bid;
-    const int g = ntx >> 3, xcd = bid & 7, k = bid >> 3;
-    if (nlty & 1) return (k / g) * ntx + xcd * g + (k % g);
-    const int row = (k / (2 * g)) * 2 + (k & 1), col = xcd * g + (k >> 1) % g;
-    return row * ntx + col;
-}
-
 template <int S, bool NODES, bool MASK, int ST>
 __global__ __launch_bounds__(TILE_N) __attribute__((amdgpu_waves_per_eu(lattice_waves(S, RPT, false)))) void k_lattice(LatticeArgs a)
 {
