@@ -411,20 +411,27 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
         // force term 3 w_i rho (v_i . e)
         const float fx = 3.0f * rho * ex, fy = 3.0f * rho * ey;
         {
-            // equilibrium deviation w_i (drho + rho (3 vu + 4.5 vu^2 - 1.5 u^2))
+            // equilibrium deviation w_i (drho + rho (3 vu + 4.5 vu^2 - 1.5 u^2)), vu = v_i . u,
+            // for pairs of opposite directions: the part even in v_i is shared, the odd part
+            // (with the force term) changes sign
             using T = typename Pop<ST>::T;
             constexpr int P = TILE_X;
             T* __restrict__ d = row_ptr((T*)a.fdst + (int64_t)n[r].y * a.frow, chunk_col(x, 9 * TILE_X));
+            const float rs = 3.0f * om * rho;
             store_nt(d, Pop<ST>::st(om1 * fr[0] + om * W0 * (drho - rho * usq), SC9[0]));
-            float vu, eq;
-            vu = ux;       eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); store_nt(d + P,     Pop<ST>::st(om1 * fr[1] + om * eq + W1 * fx, SC9[1]));
-            vu = uy;       eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); store_nt(d + 2 * P, Pop<ST>::st(om1 * fr[2] + om * eq + W1 * fy, SC9[2]));
-            vu = -ux;      eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); store_nt(d + 3 * P, Pop<ST>::st(om1 * fr[3] + om * eq - W1 * fx, SC9[3]));
-            vu = -uy;      eq = W1 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); store_nt(d + 4 * P, Pop<ST>::st(om1 * fr[4] + om * eq - W1 * fy, SC9[4]));
-            vu = ux + uy;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); store_nt(d + 5 * P, Pop<ST>::st(om1 * fr[5] + om * eq + W5 * (fx + fy), SC9[5]));
-            vu = uy - ux;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); store_nt(d + 6 * P, Pop<ST>::st(om1 * fr[6] + om * eq + W5 * (fy - fx), SC9[6]));
-            vu = -ux - uy; eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); store_nt(d + 7 * P, Pop<ST>::st(om1 * fr[7] + om * eq - W5 * (fx + fy), SC9[7]));
-            vu = ux - uy;  eq = W5 * (drho + rho * (3.0f * vu + 4.5f * vu * vu - usq)); store_nt(d + 8 * P, Pop<ST>::st(om1 * fr[8] + om * eq + W5 * (fx - fy), SC9[8]));
+            float vu, ev, od;
+            vu = ux;      ev = om * W1 * (drho + rho * (4.5f * vu * vu - usq)); od = W1 * (rs * vu + fx);
+            store_nt(d + P,     Pop<ST>::st(om1 * fr[1] + ev + od, SC9[1]));
+            store_nt(d + 3 * P, Pop<ST>::st(om1 * fr[3] + ev - od, SC9[3]));
+            vu = uy;      ev = om * W1 * (drho + rho * (4.5f * vu * vu - usq)); od = W1 * (rs * vu + fy);
+            store_nt(d + 2 * P, Pop<ST>::st(om1 * fr[2] + ev + od, SC9[2]));
+            store_nt(d + 4 * P, Pop<ST>::st(om1 * fr[4] + ev - od, SC9[4]));
+            vu = ux + uy; ev = om * W5 * (drho + rho * (4.5f * vu * vu - usq)); od = W5 * (rs * vu + fx + fy);
+            store_nt(d + 5 * P, Pop<ST>::st(om1 * fr[5] + ev + od, SC9[5]));
+            store_nt(d + 7 * P, Pop<ST>::st(om1 * fr[7] + ev - od, SC9[7]));
+            vu = uy - ux; ev = om * W5 * (drho + rho * (4.5f * vu * vu - usq)); od = W5 * (rs * vu + fy - fx);
+            store_nt(d + 6 * P, Pop<ST>::st(om1 * fr[6] + ev + od, SC9[6]));
+            store_nt(d + 8 * P, Pop<ST>::st(om1 * fr[8] + ev - od, SC9[8]));
         }
 
         if constexpr (MASK)
@@ -456,12 +463,14 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
                 using T = typename Pop<ST>::T;
                 constexpr int P = TILE_X;
                 T* __restrict__ d = row_ptr((T*)a.gdst + (int64_t)n[r].y * a.grow, chunk_col(x, a.gchunk) + 5 * s * P);
-                // equilibrium deviation w_i (dphi + 3 phi v_i . u) and reaction w_i R
-                store_nt(d,         Pop<ST>::st(os1 * gg[0] + os * Q0 * dphi[s] + Q0 * R[s], SC5[0]));
-                store_nt(d + P,     Pop<ST>::st(os1 * gg[1] + os * Q1 * (dphi[s] + p3 * ux) + Q1 * R[s], SC5[1]));
-                store_nt(d + 2 * P, Pop<ST>::st(os1 * gg[2] + os * Q1 * (dphi[s] + p3 * uy) + Q1 * R[s], SC5[2]));
-                store_nt(d + 3 * P, Pop<ST>::st(os1 * gg[3] + os * Q1 * (dphi[s] - p3 * ux) + Q1 * R[s], SC5[3]));
-                store_nt(d + 4 * P, Pop<ST>::st(os1 * gg[4] + os * Q1 * (dphi[s] - p3 * uy) + Q1 * R[s], SC5[4]));
+                // equilibrium deviation w_i (dphi + 3 phi v_i . u) and reaction w_i R, by pairs of
+                // opposite directions (shared even part, odd part of changing sign)
+                const float ev = Q1 * (os * dphi[s] + R[s]), ox = Q1 * os * p3 * ux, oy = Q1 * os * p3 * uy;
+                store_nt(d,         Pop<ST>::st(os1 * gg[0] + Q0 * (os * dphi[s] + R[s]), SC5[0]));
+                store_nt(d + P,     Pop<ST>::st(os1 * gg[1] + ev + ox, SC5[1]));
+                store_nt(d + 2 * P, Pop<ST>::st(os1 * gg[2] + ev + oy, SC5[2]));
+                store_nt(d + 3 * P, Pop<ST>::st(os1 * gg[3] + ev - ox, SC5[3]));
+                store_nt(d + 4 * P, Pop<ST>::st(os1 * gg[4] + ev - oy, SC5[4]));
             }
         }
     }
