@@ -1,0 +1,60 @@
+"""The lattice pass's workgroup-to-tile order (tile_of_block in csrc/lbib_device.h) is a
+permutation of the tiles for every lattice shape: each tile is visited exactly once, whatever
+the column and row counts (the XCD grouping applies only when they allow it).
+
+The function is compiled for the host (hipcc, host pass only) and checked exhaustively for
+up to 64 x 64 tiles; no GPU is needed."""
+import os
+import shutil
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1503_06726_amd", "csrc")
+
+SRC = r"""
+#include "lbib_device.h"
+#include <cstdio>
+#include <vector>
+int main() {
+    long checked = 0;
+    for (int ntx = 1; ntx <= 64; ++ntx)
+        for (int nlty = 1; nlty <= 64; ++nlty) {
+            const int n = ntx * nlty;
+            std::vector<int> seen(n, 0);
+            for (int b = 0; b < n; ++b) {
+                const int t = lbib::tile_of_block(b, ntx, nlty);
+                if (t < 0 || t >= n || seen[t]++) {
+                    std::printf("not a permutation: %d x %d tiles, block %d -> tile %d\n", ntx, nlty, b, t);
+                    return 1;
+                }
+            }
+            checked += n;
+        }
+    std::printf("%ld\n", checked);
+    return 0;
+}
+"""
+
+
+def _hipcc():
+    for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if c and os.path.exists(c):
+            return c
+    return None
+
+
+@pytest.mark.skipif(_hipcc() is None, reason="hipcc is needed to compile the device header for the host")
+def test_tile_order_is_a_permutation():
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "tile_order.cpp")
+        exe = os.path.join(d, "tile_order")
+        with open(src, "w") as f:
+            f.write(SRC)
+        subprocess.run([_hipcc(), "-x", "hip", "--cuda-host-only", "-O1", "-std=c++17", "-I", CSRC, src, "-o", exe],
+                       check=True, capture_output=True)
+        out = subprocess.run([exe], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout
+    assert int(out.stdout.split()[-1]) == sum(a * b for a in range(1, 65) for b in range(1, 65))
