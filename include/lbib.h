@@ -70,11 +70,28 @@ enum { LBIB_REACT_NONE = 0,
  * |deviation / w_i| up to 63. */
 enum { LBIB_STORAGE_FP32 = 0, LBIB_STORAGE_FP16 = 1, LBIB_STORAGE_BF16 = 2 };
 
+/* Species flags.
+ * LBIB_SPECIES_NO_FLUX: the cell membranes are no-flux boundaries for the species (Section
+ * "Signalling": compounds that exist only inside or only outside the cells; Suppl. "No-flux
+ * Boundary Condition for Reaction-Advection-Diffusion Equations": missing populations are
+ * replaced by equilibria).  A D2Q5 link crosses a membrane when one of its two nodes lies
+ * inside a cell and the other does not (the inside-cell map of the step's positions).  A
+ * population arriving across such a link is replaced by the equilibrium w_i phi_b at zero
+ * velocity (the wall's), phi_b being the node's own concentration, solved from the
+ * populations that did arrive: phi_b = sum_known g_j / (1 - sum_missing w_i).  This is the
+ * zeroth-order form of the paper's condition (its first-order interpolation and
+ * extrapolation need moments of nodes further inside).  Inside and outside then exchange
+ * nothing: a concentration confined to one side stays there exactly.  Cells must keep at
+ * least one lattice unit of extracellular space between them (two cells in contact share
+ * the inside map).  Not with a source subset (lbib_set_source_cells), a batch, or
+ * lbib_ade_steady (LBIB_EINVAL / LBIB_ESTATE). */
+enum { LBIB_SPECIES_NO_FLUX = 1 };
+
 typedef struct {
     double D;          /* diffusivity, > 0; relaxation time tau_D = 3 D + 1/2 */
     double phi_ref;    /* storage reference concentration (deviation storage); any finite value */
     int32_t reaction;  /* LBIB_REACT_* */
-    int32_t reserved;  /* must be 0 */
+    int32_t flags;     /* LBIB_SPECIES_* (0: the membranes are invisible to the species) */
     double c[4];       /* reaction constants (per step), see LBIB_REACT_* */
 } lbib_species;
 

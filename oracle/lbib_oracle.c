@@ -38,6 +38,14 @@
  *    R_0 = gamma (a - phi0 + phi0^2 phi1), R_1 = gamma (b - phi0^2 phi1).
  *    With a source subset (orc_set_source_cells), [m != 0] becomes "inside at least one
  *    source cell": the crossing test run over the source cells alone.
+ *  - No-flux membranes (a species flag; Suppl. "No-flux Boundary Condition for
+ *    Reaction-Advection-Diffusion Equations"), zeroth-order reading: the clauses of
+ *    first-order interpolation and extrapolation are dropped; a population arriving
+ *    across a membrane (the inside map [m != 0] of this step differs between the link's
+ *    ends) becomes the zero-velocity equilibrium w_i phi_b, with phi_b the node's own
+ *    concentration solved from the populations that did arrive.  Applied to the streamed
+ *    populations before the moments of the step; the reported fields are the streamed
+ *    populations' sums.
  *  - ADE-only iteration (the steady-state measurement): the species lattices advance
  *    with u = 0 while the fluid, the membranes and the domain map stay frozen; the
  *    relative change after iteration k is ||phi^k - phi^{k-1}||_2 / ||phi^k||_2, with
@@ -408,8 +416,43 @@ void orc_source_map(orc_ctx* c, int32_t* out)
 static int needs_mask(const orc_params* p)
 {
     for (int s = 0; s < p->n_species; ++s)
-        if (p->reaction[s] == ORC_REACT_SOURCE_DECAY) return 1;
+        if (p->reaction[s] == ORC_REACT_SOURCE_DECAY || p->no_flux[s]) return 1;
     return 0;
+}
+
+/* No-flux membranes for a species (Section "Signalling"; Suppl. "No-flux Boundary Condition
+ * for Reaction-Advection-Diffusion Equations"), zeroth-order reading: a population that
+ * arrived at x across a membrane (its upstream node x - v_i lies inside a cell and x does
+ * not, or the reverse; m is the domain map of this step's positions) is missing and becomes
+ * the equilibrium at the wall's zero velocity, w_i phi_b, with phi_b the node's own
+ * concentration: phi_b = (populations that arrived) + (sum of the missing w_i) phi_b.  A
+ * population reflected by a wall is not missing. */
+static void no_flux_replace(orc_ctx* c, const int32_t* m, double* g)
+{
+    const orc_params* p = &c->p;
+    int64_t nx = p->nx, ny = p->ny, nn = c->nn;
+    for (int s = 0; s < p->n_species; ++s) {
+        if (!p->no_flux[s]) continue;
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                int64_t k = y * nx + x;
+                int in = m[k] != 0;
+                double known = g[(s * 5) * nn + k], wm = 0.0;
+                int miss[5] = {0, 0, 0, 0, 0};
+                for (int i = 1; i < 5; ++i) {
+                    int64_t yu = y - VY[i], xu = wrapi(x - VX[i], nx);
+                    int across = 0;
+                    if (!(p->bc_y == ORC_WALLS && (yu < 0 || yu >= ny)))
+                        across = (m[wrapi(yu, ny) * nx + xu] != 0) != in;
+                    if (across) { miss[i] = 1; wm += W5[i]; }
+                    else known += g[(s * 5 + i) * nn + k];
+                }
+                if (wm == 0.0) continue;
+                double phib = known / (1.0 - wm);
+                for (int i = 1; i < 5; ++i)
+                    if (miss[i]) g[(s * 5 + i) * nn + k] = W5[i] * phib;
+            }
+    }
 }
 
 static void moments(orc_ctx* c)
@@ -451,9 +494,11 @@ static void step_once(orc_ctx* c)
     }
     for (int64_t x = 0; x < nn; ++x) { c->ex[x] += p->body[0]; c->ey[x] += p->body[1]; }
 
-    /* 3: domain IDs (the map the source term reads) */
+    /* 3: domain IDs (the map the source term and no-flux membranes read); populations that
+     * arrived across a no-flux membrane are replaced before the moments */
     if (needs_mask(p)) source_map(c, c->mask);
     else memset(c->mask, 0, sizeof(int32_t) * (size_t)nn);
+    no_flux_replace(c, c->mask, c->g);
 
     /* 4: moments and collision (post-collision values into f / g in place) */
     moments(c);
@@ -612,6 +657,21 @@ void orc_ade_step(orc_ctx* c, int32_t n, double* change)
 void orc_get_fields(orc_ctx* c, double* rho, double* u, double* phi, double* X, int32_t* mask)
 {
     int64_t nn = c->nn;
+    /* the concentrations the next collision sees: with no-flux membranes, the populations
+     * that arrived across one are replaced first (on a copy; the replacement is the one the
+     * next step makes) */
+    double* g = c->g;
+    int nf = 0;
+    for (int s = 0; s < c->p.n_species; ++s) nf |= c->p.no_flux[s];
+    if (phi && nf && c->n_cells > 0) {
+        size_t bytes = sizeof(double) * 5 * (size_t)c->p.n_species * (size_t)nn;
+        int32_t* m = (int32_t*)malloc(sizeof(int32_t) * (size_t)nn);
+        g = (double*)malloc(bytes);
+        memcpy(g, c->g, bytes);
+        source_map(c, m);
+        no_flux_replace(c, m, g);
+        free(m);
+    }
     for (int64_t x = 0; x < nn; ++x) {
         double r = 0.0, jx = 0.0, jy = 0.0;
         for (int i = 0; i < 9; ++i) {
@@ -623,11 +683,12 @@ void orc_get_fields(orc_ctx* c, double* rho, double* u, double* phi, double* X, 
         if (phi) {
             for (int s = 0; s < c->p.n_species; ++s) {
                 double sum = 0.0;
-                for (int i = 0; i < 5; ++i) sum += c->g[(s * 5 + i) * nn + x];
+                for (int i = 0; i < 5; ++i) sum += g[(s * 5 + i) * nn + x];
                 phi[s * nn + x] = sum;
             }
         }
     }
+    if (g != c->g) free(g);
     if (X && c->n_nodes) memcpy(X, c->X, sizeof(double) * 2 * (size_t)c->n_nodes);
     if (mask) orc_raster(&c->p, c->n_cells, c->off, c->X, mask);
 }

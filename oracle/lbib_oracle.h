@@ -54,6 +54,7 @@ typedef struct {
     int32_t reaction[2];
     double rc[2][4];             /* reaction constants, see orc_reaction() */
     double wall_u_top;           /* x-velocity of the top wall (moving-wall test hook) */
+    int32_t no_flux[2];          /* 1: the cell membranes are no-flux boundaries for species s */
 } orc_params;
 
 typedef struct orc_ctx orc_ctx;

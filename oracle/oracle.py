@@ -39,7 +39,7 @@ class Params(C.Structure):
                 ("tau", C.c_double), ("rho0", C.c_double), ("body", C.c_double * 2),
                 ("k_spring", C.c_double), ("phi_m", C.c_double), ("kappa_area", C.c_double),
                 ("D", C.c_double * 2), ("reaction", C.c_int32 * 2),
-                ("rc", (C.c_double * 4) * 2), ("wall_u_top", C.c_double)]
+                ("rc", (C.c_double * 4) * 2), ("wall_u_top", C.c_double), ("no_flux", C.c_int32 * 2)]
 
 
 _lib = None
@@ -114,6 +114,7 @@ def make_params(d: dict, interp_new_u: bool = False, wall_u_top: float = 0.0) ->
         p.reaction[s] = int(spc.get("reaction", 0))
         for k, v in enumerate(spc.get("c", (0, 0, 0, 0))):
             p.rc[s][k] = float(v)
+        p.no_flux[s] = 1 if spc.get("no_flux", False) else 0
     p.wall_u_top = float(wall_u_top)
     return p
 

@@ -161,6 +161,7 @@ LatticeArgs lattice_args_at(lbib_ctx* c, int cur)
     a.inside = c->inside[cur];
     a.inside_clr = c->inside[1 - cur];
     a.wpr = c->wpr;
+    a.noflux = c->n_cells ? no_flux_bits(p) : 0;
     a.e_out = nullptr;
     return a;
 }
@@ -848,7 +849,7 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
         return s;
     }
     c->max_cell_nodes = max_n;
-    c->mask_needed = any_source_decay(c->p);
+    c->mask_needed = any_source_decay(c->p) || no_flux_bits(c->p) != 0;   // the step keeps the inside map
     LBIB_HIP(c, hipMemcpyAsync(c->d_off, off, (C + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream));
     LBIB_HIP(c, hipMemcpyAsync(c->d_X, xy, N * sizeof(double2), hipMemcpyHostToDevice, c->stream));
     LBIB_HIP(c, hipMemcpyAsync(c->d_l0, l0.data(), N * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -1011,6 +1012,10 @@ lbib_status lbib_set_source_cells(lbib_ctx* c, const uint8_t* src)
         c->err = "no cells are set";
         return LBIB_ESTATE;
     }
+    if (src && no_flux_bits(c->p)) {
+        c->err = "a source subset cannot be combined with no-flux membranes (they share the inside map)";
+        return LBIB_EINVAL;
+    }
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
     drop_graphs(c);
     if (src) {
@@ -1043,6 +1048,10 @@ lbib_status lbib_ade_steady(lbib_ctx* c, double tol, int64_t max_iters, int32_t 
     if (change) *change = NAN;
     if (c->S == 0) {
         c->err = "no species to iterate";
+        return LBIB_EINVAL;
+    }
+    if (no_flux_bits(c->p)) {
+        c->err = "the ADE-only iteration has no no-flux membranes";
         return LBIB_EINVAL;
     }
     if (!std::isfinite(tol) || tol < 0.0 || max_iters < 0) {

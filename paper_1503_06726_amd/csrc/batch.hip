@@ -387,6 +387,10 @@ lbib_status lbib_batch_create(lbib_ctx* const* sims, int32_t n, void* hip_stream
                      "storage type and source law";
             return LBIB_EINVAL;
         }
+        if (no_flux_bits(c->p)) {
+            c->err = "the batched pass has no no-flux membranes";
+            return LBIB_EINVAL;
+        }
     }
     lbib_batch* b = new (std::nothrow) lbib_batch();
     if (!b) return LBIB_ENOMEM;

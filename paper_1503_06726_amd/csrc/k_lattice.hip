@@ -53,6 +53,12 @@ __device__ inline Nbr neighbours(int x, int y, int nx, int ny, int walls)
     return n;
 }
 
+// bit of node (x, y) in the inside-cell map (x, y inside the lattice)
+__device__ inline unsigned inside_bit(const LatticeArgs& a, int x, int y)
+{
+    return (a.inside[(int64_t)y * a.wpr + (x >> 5)] >> (x & 31)) & 1u;
+}
+
 // offset of column x within its row of a chunked array (chunk = Q TILE_X elements)
 __device__ inline int chunk_col(int x, int chunk) { return (x / TILE_X) * chunk + (x % TILE_X); }
 
@@ -299,7 +305,7 @@ __device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0
 // ly, ly + TILE_Y, ...  Order: listed nodes' records and the population loads issued; moments
 // (rho, u) of every row, u staged in LDS; listed nodes coupled (force spread into LDS, velocity
 // interpolated to the nodes); collision with the spread force and stores.
-template <int S, bool NODES, bool MASK, int ST, int RP>
+template <int S, bool NODES, bool MASK, int ST, int RP, bool NF = false>
 __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int tile)
 {
     constexpr int LY = TILE_Y * RP;
@@ -336,6 +342,7 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
     float f[RP][9];
     float g[RP][S > 0 ? S : 1][5];
     int m[RP];
+    unsigned miss[RP];            // no-flux membranes: D2Q5 directions 1..4 that arrived across one
     // every lane loads (lanes beyond a ragged edge read the last column / row and discard it):
     // without branches around the loads the compiler waits for exactly the ones each use needs
 #pragma unroll
@@ -356,6 +363,20 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
             const unsigned w0 = row[0];
             const unsigned w1 = (x0 + 32 < a.nx) ? row[1] : 0u;
             m[r] = (((x & 32) ? w1 : w0) >> (x & 31)) & 1u;
+        }
+        miss[r] = 0u;
+        if constexpr (NF) {
+            // direction i arrives from x - v_i: +x from x-1, +y from y-1, -x from x+1, -y from
+            // y+1; it crossed a membrane when the inside map differs between the two nodes
+            // (a population reflected by a wall did not)
+            const Nbr& q = n[r];
+            const unsigned me = inside_bit(a, q.x, q.y);
+            unsigned ms = 0u;
+            if (inside_bit(a, q.xm, q.y) != me) ms |= 2u;
+            if (!q.bot && inside_bit(a, q.x, q.ym) != me) ms |= 4u;
+            if (inside_bit(a, q.xp, q.y) != me) ms |= 8u;
+            if (!q.top && inside_bit(a, q.x, q.yp) != me) ms |= 16u;
+            miss[r] = ms;
         }
     }
     if constexpr (NODES) load_records(a, cnd, cij, crc);
@@ -437,6 +458,27 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
         if constexpr (MASK)
             if ((x & 31) == 0) a.inside_clr[(int64_t)(y0 + t / TILE_X + r * TILE_Y) * a.wpr + (x >> 5)] = 0u;
         if constexpr (S > 0) {
+            if constexpr (NF) {
+                // populations that arrived across a no-flux membrane become the equilibrium at
+                // the wall's zero velocity, w_i phi_b, phi_b the node's own concentration:
+                // in deviations, dphi_b = (sum of the arrived dg_j) / (1 - sum of missing w_i)
+                if (miss[r]) {
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        if (!((a.noflux >> s) & 1)) continue;
+                        float known = g[r][s][0], wm = 0.0f;
+#pragma unroll
+                        for (int i = 1; i < 5; ++i) {
+                            if ((miss[r] >> i) & 1u) wm += Q1;
+                            else known += g[r][s][i];
+                        }
+                        const float db = known / (1.0f - wm);
+#pragma unroll
+                        for (int i = 1; i < 5; ++i)
+                            if ((miss[r] >> i) & 1u) g[r][s][i] = Q1 * db;
+                    }
+                }
+            }
             float dphi[S], phi[S], R[S];
 #pragma unroll
             for (int s = 0; s < S; ++s) {
@@ -491,10 +533,10 @@ constexpr int lattice_waves(int S, int RP, bool)
     return RP == 1 ? 6 : RP == 2 ? (S <= 1 ? 5 : 4) : 3;
 }
 
-template <int S, bool NODES, bool MASK, int ST>
+template <int S, bool NODES, bool MASK, int ST, bool NF = false>
 __global__ __launch_bounds__(TILE_N) __attribute__((amdgpu_waves_per_eu(lattice_waves(S, RPT, false)))) void k_lattice(LatticeArgs a)
 {
-    lattice_tile<S, NODES, MASK, ST, RPT>(a, tile_of_block((int)blockIdx.x, a.ntx, (a.ny + LTILE_Y - 1) / LTILE_Y));
+    lattice_tile<S, NODES, MASK, ST, RPT, NF>(a, tile_of_block((int)blockIdx.x, a.ntx, (a.ny + LTILE_Y - 1) / LTILE_Y));
 }
 
 // Batched form: every workgroup takes one (simulation, tile) work item; the simulation's
@@ -620,6 +662,9 @@ struct MomentArgs {
     int nx, ny, walls, S;
     double rho0;
     double phi_ref[2];
+    const unsigned* inside;           // inside-cell map of the current positions (no-flux membranes)
+    int wpr;
+    int noflux;                       // bit s: no-flux membranes for species s
 };
 
 template <int ST>
@@ -633,9 +678,30 @@ __device__ inline void node_moments(const MomentArgs& a, int x, int y, double& d
     for (int i = 0; i < 9; ++i) drho += (double)f[i];
     jx = ((double)f[1] - f[3]) + ((double)f[5] - f[6]) + ((double)f[8] - f[7]);
     jy = ((double)f[2] - f[4]) + ((double)f[5] + f[6]) - ((double)f[7] + f[8]);
+    unsigned miss = 0u;
+    if (a.noflux) {
+        // populations that arrived across a no-flux membrane (as in the lattice pass)
+        auto bit = [&](int xx, int yy) { return (a.inside[(int64_t)yy * a.wpr + (xx >> 5)] >> (xx & 31)) & 1u; };
+        const unsigned me = bit(n.x, n.y);
+        if (bit(n.xm, n.y) != me) miss |= 2u;
+        if (!n.bot && bit(n.x, n.ym) != me) miss |= 4u;
+        if (bit(n.xp, n.y) != me) miss |= 8u;
+        if (!n.top && bit(n.x, n.yp) != me) miss |= 16u;
+    }
     for (int s = 0; s < a.S; ++s) {
         float g[5];
         pull5<ST>((const typename Pop<ST>::T*)a.g + 5 * s * TILE_X, a.grow, a.gchunk, n, g);
+        if (miss && ((a.noflux >> s) & 1)) {
+            // the concentration the next collision sees: the missing populations become
+            // w_i phi_b, so the sum is (sum of the arrived ones) / (1 - sum of the missing w_i)
+            double known = (double)g[0], wm = 0.0;
+            for (int i = 1; i < 5; ++i) {
+                if ((miss >> i) & 1u) wm += 1.0 / 6.0;
+                else known += (double)g[i];
+            }
+            dphi[s] = known / (1.0 - wm);
+            continue;
+        }
         double t = 0.0;
         for (int i = 0; i < 5; ++i) t += (double)g[i];
         dphi[s] = t;
@@ -710,6 +776,13 @@ template <int S, int ST>
 static hipError_t launch_lattice_s(lbib_ctx* c, const LatticeArgs& a, bool nodes, bool mask)
 {
     dim3 grid((unsigned)c->nltiles), block(TILE_N);
+    if constexpr (S > 0) {
+        if (a.noflux) {                 // no-flux membranes read the inside map (mask is set)
+            if (nodes) hipLaunchKernelGGL((k_lattice<S, true, true, ST, true>), grid, block, 0, c->stream, a);
+            else hipLaunchKernelGGL((k_lattice<S, false, true, ST, true>), grid, block, 0, c->stream, a);
+            return hipGetLastError();
+        }
+    }
     if (nodes && mask) hipLaunchKernelGGL((k_lattice<S, true, true, ST>), grid, block, 0, c->stream, a);
     else if (nodes) hipLaunchKernelGGL((k_lattice<S, true, false, ST>), grid, block, 0, c->stream, a);
     else if (mask) hipLaunchKernelGGL((k_lattice<S, false, true, ST>), grid, block, 0, c->stream, a);
@@ -828,6 +901,9 @@ static MomentArgs moment_args(lbib_ctx* c, double* out)
     a.rho0 = c->p.rho0;
     a.phi_ref[0] = c->p.species[0].phi_ref;
     a.phi_ref[1] = c->p.species[1].phi_ref;
+    a.inside = c->inside[c->cur];
+    a.wpr = c->wpr;
+    a.noflux = c->n_cells ? no_flux_bits(c->p) : 0;
     return a;
 }
 

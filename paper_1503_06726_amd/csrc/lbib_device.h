@@ -92,6 +92,7 @@ struct LatticeArgs {
     const unsigned* __restrict__ inside;   // inside-any-cell bits of this step, rows of wpr words
     unsigned* __restrict__ inside_clr;     // the other buffer, cleared for the membrane kernel
     int wpr;
+    int noflux;                            // bit s: the membranes are no-flux boundaries for species s
     // inspection output (spread field only)
     double* __restrict__ e_out;
 };

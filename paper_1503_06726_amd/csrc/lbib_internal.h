@@ -115,6 +115,15 @@ struct lbib_ctx {
 
 namespace lbib {
 
+// species whose cell membranes are no-flux boundaries (bit s for species s)
+inline int no_flux_bits(const lbib_params& p)
+{
+    int b = 0;
+    for (int s = 0; s < p.n_species; ++s)
+        if (p.species[s].flags & LBIB_SPECIES_NO_FLUX) b |= 1 << s;
+    return b;
+}
+
 // kernel launchers (return the launch error)
 hipError_t launch_lattice(lbib_ctx* c, const LatticeArgs& a, bool nodes, bool mask);
 hipError_t launch_spread_inspect(lbib_ctx* c, const LatticeArgs& a);

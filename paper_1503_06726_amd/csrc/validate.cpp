@@ -39,7 +39,7 @@ lbib_status check_params(const lbib_params* p, std::string& msg)
         const lbib_species& sp = p->species[s];
         if (!std::isfinite(sp.D) || !(sp.D > 0.0)) return fail(msg, "species %g: D = %g must be positive", s, sp.D);
         if (!std::isfinite(sp.phi_ref)) return fail(msg, "species %g: phi_ref not finite", s);
-        if (sp.reserved != 0) return fail(msg, "species %g: reserved field must be 0", s);
+        if (sp.flags & ~LBIB_SPECIES_NO_FLUX) return fail(msg, "species %g: unknown flags", s);
         for (int k = 0; k < 4; ++k)
             if (!std::isfinite(sp.c[k])) return fail(msg, "species %g: reaction constant %g not finite", s, k);
         if (sp.reaction < LBIB_REACT_NONE || sp.reaction > LBIB_REACT_SCHNAKENBERG)

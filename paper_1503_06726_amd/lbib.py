@@ -19,6 +19,7 @@ PERIODIC, WALLS = 0, 1
 DELTA_COS4, DELTA_PESKIN4 = 0, 1
 REACT_NONE, REACT_SOURCE_DECAY, REACT_SCHNAKENBERG = 0, 1, 2
 STORAGE_FP32, STORAGE_FP16, STORAGE_BF16 = 0, 1, 2
+SPECIES_NO_FLUX = 1
 K_LATTICE, K_MEMBRANE, K_LISTS = range(3)
 KERNEL_NAMES = ["lattice", "membrane", "lists"]
 
@@ -38,7 +39,7 @@ EXPORTS = ["lbib_validate_params", "lbib_validate_cells", "lbib_create", "lbib_s
 
 class Species(C.Structure):
     _fields_ = [("D", C.c_double), ("phi_ref", C.c_double), ("reaction", C.c_int32),
-                ("reserved", C.c_int32), ("c", C.c_double * 4)]
+                ("flags", C.c_int32), ("c", C.c_double * 4)]
 
 
 class Params(C.Structure):
@@ -186,7 +187,7 @@ def make_params(d: dict) -> Params:
         p.species[s].D = float(spc["D"])
         p.species[s].phi_ref = float(spc.get("phi_ref", 0.0))
         p.species[s].reaction = int(spc.get("reaction", REACT_NONE))
-        p.species[s].reserved = 0
+        p.species[s].flags = SPECIES_NO_FLUX if spc.get("no_flux", False) else 0
         for k, v in enumerate(spc.get("c", (0.0, 0.0, 0.0, 0.0))):
             p.species[s].c[k] = float(v)
     return p

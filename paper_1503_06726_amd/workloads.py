@@ -45,6 +45,7 @@ class Species:
     phi_ref: float = 0.0
     reaction: int = REACT_NONE
     c: tuple = (0.0, 0.0, 0.0, 0.0)
+    no_flux: bool = False       # the membranes are no-flux boundaries for the species
 
 
 @dataclass
@@ -90,8 +91,8 @@ class Workload:
         return dict(nx=self.nx, ny=self.ny, bc_y=self.bc_y, tau=self.tau, rho0=self.rho0,
                     body_accel=tuple(self.body_accel), delta_kernel=self.delta_kernel,
                     k_spring=self.k_spring, phi_m=self.phi_m, kappa_area=self.kappa_area,
-                    species=[dict(D=s.D, phi_ref=s.phi_ref, reaction=s.reaction, c=tuple(s.c))
-                             for s in self.species])
+                    species=[dict(D=s.D, phi_ref=s.phi_ref, reaction=s.reaction, c=tuple(s.c),
+                                  no_flux=bool(s.no_flux)) for s in self.species])
 
     def mask_needed(self) -> bool:
         return any(s.reaction == REACT_SOURCE_DECAY for s in self.species)
@@ -405,3 +406,18 @@ PARITY_CASES = {
                                      stretch=1.1),
     "peskin": lambda: small_tissue(nx=96, ny=70, n_cells=12, delta_kernel=DELTA_PESKIN4, seed=4, stretch=0.95),
 }
+
+
+def no_flux_tissue(static: bool = True, no_flux: bool = True, seed: int = 7, nx: int = 120, ny: int = 90,
+                   n_cells: int = 8, steps: int = 100) -> Workload:
+    """A small walled tissue whose one species (source inside the cells, linear decay) sees the
+    membranes as no-flux boundaries (Section "Signalling"). ``static``: no forces and no body
+    acceleration, so the fluid stays at rest and the membranes where they are; otherwise
+    pre-stretched springs and a body acceleration move both."""
+    w = small_tissue(nx=nx, ny=ny, n_cells=n_cells, n_species=1, seed=seed,
+                     body=(0.0, 0.0) if static else (2e-5, 0.0),
+                     k_spring=0.0 if static else 0.02, stretch=1.0 if static else 0.9, steps=steps)
+    w.species[0].no_flux = no_flux
+    w.name = f"no-flux tissue {nx}x{ny}, {n_cells} cells, {'static' if static else 'moving'}" + \
+             ("" if no_flux else ", membranes invisible")
+    return w

@@ -182,3 +182,15 @@ def test_workspace_size_rejects_bad_input():
     with pytest.raises(lbib.LbibError) as e:
         _ws(dict(d, tau=0.5), 10)
     assert e.value.status == lbib.EINVAL
+
+
+def test_species_flags_validated():
+    d = dict(W.no_flux_tissue().params_dict())
+    assert lbib.validate_params(d)[0] == lbib.OK
+    assert d["species"][0]["no_flux"] is True
+    p = lbib.make_params(d)
+    assert p.species[0].flags == lbib.SPECIES_NO_FLUX
+    p.species[0].flags = 2
+    buf = C.create_string_buffer(256)
+    assert lbib.lib().lbib_validate_params(C.byref(p), buf, 256) == lbib.EINVAL
+    assert b"flags" in buf.value

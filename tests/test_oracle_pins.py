@@ -520,3 +520,66 @@ def test_laplace_pressure_of_tensioned_circle():
     dp = phim / (Rnow * math.cos(math.pi / N))
     # p = rho cs2 (Suppl. "Lattice Boltzmann Method")
     assert abs((rin - rout) / 3.0 - dp) < 0.05 * dp
+
+
+# ---- no-flux membranes (Section "Signalling"; zeroth-order reading of the supplement's condition) ----
+def _inside(o):
+    return o.get_fields()["mask"] != 0
+
+
+def test_no_flux_keeps_a_uniform_field_uniform():
+    """A uniform concentration at rest is an equilibrium on both sides of every membrane, and
+    the replacement equilibrium w_i phi_b rebuilds exactly the populations that would have
+    arrived: the field stays uniform (to round-off)."""
+    w = W.no_flux_tissue(static=True)
+    w.species[0].reaction = W.REACT_NONE
+    w.phi_init = np.full((1, w.ny, w.nx), 0.7)
+    o = O.from_workload(w)
+    o.step(60)
+    phi = o.get_fields()["phi"][0]
+    assert np.max(np.abs(phi - 0.7)) < 1e-13
+
+
+def test_no_flux_confines_a_cell_source_to_the_cells():
+    """Static cells with a source inside them and the membranes as no-flux boundaries: the
+    extracellular concentration stays exactly zero while the cells fill; with the membranes
+    invisible, the source leaks out by diffusion."""
+    o = O.from_workload(W.no_flux_tissue(static=True, no_flux=True))
+    o.step(100)
+    inside = _inside(o)
+    phi = o.get_fields()["phi"][0]
+    assert inside.any() and (~inside).any()
+    assert np.all(phi[~inside] == 0.0)
+    assert np.min(phi[inside]) > 0.0
+    o2 = O.from_workload(W.no_flux_tissue(static=True, no_flux=False))
+    o2.step(100)
+    phi2 = o2.get_fields()["phi"][0]
+    assert np.max(phi2[~inside]) > 1e-4 * np.max(phi2[inside])
+
+
+def test_no_flux_changes_only_nodes_next_to_a_membrane():
+    """After one step the no-flux run differs from the membranes-invisible run only at nodes
+    with a lattice neighbour on the other side of a membrane (where populations were
+    replaced); everywhere else the two agree exactly."""
+    wa = W.no_flux_tissue(static=True, no_flux=True)
+    wb = W.no_flux_tissue(static=True, no_flux=False)
+    phi0 = 0.1 + 0.05 * np.random.default_rng(3).random((1, wa.ny, wa.nx))
+    wa.phi_init = phi0
+    wb.phi_init = phi0
+    oa, ob = O.from_workload(wa), O.from_workload(wb)
+    inside = _inside(oa)
+    oa.step(1)
+    ob.step(1)
+    pa, pb = oa.get_fields()["phi"][0], ob.get_fields()["phi"][0]
+    edge = np.zeros_like(inside)
+    for dy, dx in ((0, 1), (0, -1), (1, 0), (-1, 0)):
+        nb = np.roll(inside, (dy, dx), axis=(0, 1))
+        if dy:                      # walls in y: no link across the top and bottom rows
+            nb[0 if dy == 1 else -1, :] = inside[0 if dy == 1 else -1, :]
+        edge |= nb != inside
+    # a node's streamed value depends on its neighbours' replacement one step earlier
+    near = edge.copy()
+    for dy, dx in ((0, 1), (0, -1), (1, 0), (-1, 0)):
+        near |= np.roll(edge, (dy, dx), axis=(0, 1))
+    assert np.array_equal(pa[~near], pb[~near])
+    assert not np.array_equal(pa[edge], pb[edge])
