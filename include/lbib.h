@@ -108,6 +108,18 @@ typedef struct {
     int32_t n_species;       /* 0, 1 or 2 */
     int32_t storage;         /* LBIB_STORAGE_* */
     lbib_species species[2];
+    /* Mass sources and area control (Section "Control of Cell Area": a proportional
+     * controller S_k = alpha (A0_k - A_k) of each cell's area; Suppl. Table of parameters:
+     * the lattice source is a density added per node and step).  Every lattice node inside
+     * cell k (the domain map of the step's positions; a node inside two cells belongs to the
+     * lower index) gains S_k = mass_source + area_alpha (A0_k - A_k) per step, A0_k the
+     * cell's reference area (lbib_set_cells) and A_k its area at the step's positions.  The
+     * added mass moves with the local fluid: S_k f_i^eq(1, u) joins the post-collision
+     * populations, so the node's density rises by S_k and its velocity is unchanged.  Both 0
+     * disable the source.  Not with a source subset (lbib_set_source_cells) or a batch
+     * (LBIB_EINVAL / LBIB_ESTATE). */
+    double mass_source;      /* constant mass source per inside node and step (Case II's uniform source) */
+    double area_alpha;       /* proportional constant alpha of the area controller, >= 0 */
 } lbib_params;
 
 typedef struct lbib_ctx lbib_ctx;

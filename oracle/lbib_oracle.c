@@ -46,6 +46,13 @@
  *    concentration solved from the populations that did arrive.  Applied to the streamed
  *    populations before the moments of the step; the reported fields are the streamed
  *    populations' sums.
+ *  - Mass sources and area control (Section "Control of Cell Area"; the supplement's
+ *    parameter table makes the lattice source a density per node and step): every node
+ *    of cell k in the domain map gains S_k = mass_source + area_alpha (A0_k - A_k) per
+ *    step, A_k the shoelace area of the step's positions.  The paper does not say how the
+ *    source enters the lattice Boltzmann equation; the added mass is taken to move with
+ *    the local fluid, S_k f^eq_i(1, u) added after collision, so rho rises by S_k and u
+ *    is unchanged.
  *  - ADE-only iteration (the steady-state measurement): the species lattices advance
  *    with u = 0 while the fluid, the membranes and the domain map stay frozen; the
  *    relative change after iteration k is ||phi^k - phi^{k-1}||_2 / ||phi^k||_2, with
@@ -417,7 +424,7 @@ static int needs_mask(const orc_params* p)
 {
     for (int s = 0; s < p->n_species; ++s)
         if (p->reaction[s] == ORC_REACT_SOURCE_DECAY || p->no_flux[s]) return 1;
-    return 0;
+    return p->mass_source != 0.0 || p->area_alpha != 0.0;
 }
 
 /* No-flux membranes for a species (Section "Signalling"; Suppl. "No-flux Boundary Condition
@@ -500,6 +507,15 @@ static void step_once(orc_ctx* c)
     else memset(c->mask, 0, sizeof(int32_t) * (size_t)nn);
     no_flux_replace(c, c->mask, c->g);
 
+    /* the cell of every node for the mass sources: the domain map, or, when a source subset
+     * narrowed that map, the crossing test over all cells */
+    const int mass = p->mass_source != 0.0 || p->area_alpha != 0.0;
+    int32_t* cell_map = c->mask;
+    if (mass && c->src) {
+        cell_map = (int32_t*)malloc(sizeof(int32_t) * (size_t)nn);
+        orc_raster(p, c->n_cells, c->off, c->X, cell_map);
+    }
+
     /* 4: moments and collision (post-collision values into f / g in place) */
     moments(c);
     double tauD[2];
@@ -513,6 +529,14 @@ static void step_once(orc_ctx* c)
             double fi = c->f[i * nn + x];
             double force = r * W9[i] * (VX[i] * c->ex[x] + VY[i] * c->ey[x]) / CS2;
             c->f[i * nn + x] = fi - (fi - feq[i]) / p->tau + force;
+        }
+        /* mass source of the node's cell (the map holds cell + 1), moving with the fluid */
+        if (mass && cell_map[x] > 0) {
+            int32_t k = cell_map[x] - 1;
+            double S_k = p->mass_source + p->area_alpha * (c->A0[k] - c->area[k]);
+            double e1[9];
+            orc_equilibrium9(1.0, vx, vy, e1);
+            for (int i = 0; i < 9; ++i) c->f[i * nn + x] += S_k * e1[i];
         }
         for (int s = 0; s < S; ++s) {
             double sum = 0.0;
@@ -528,6 +552,8 @@ static void step_once(orc_ctx* c)
             }
         }
     }
+
+    if (cell_map != c->mask) free(cell_map);
 
     /* 5: streaming f(x + v_i, t + 1) = f*(x, t); a population leaving through a wall
      * returns to its node in the opposite direction (halfway bounce-back). */

@@ -55,6 +55,8 @@ typedef struct {
     double rc[2][4];             /* reaction constants, see orc_reaction() */
     double wall_u_top;           /* x-velocity of the top wall (moving-wall test hook) */
     int32_t no_flux[2];          /* 1: the cell membranes are no-flux boundaries for species s */
+    double mass_source;          /* constant mass source per node inside a cell and step */
+    double area_alpha;           /* area controller: S_k = mass_source + area_alpha (A0_k - A_k) */
 } orc_params;
 
 typedef struct orc_ctx orc_ctx;

@@ -39,7 +39,8 @@ class Params(C.Structure):
                 ("tau", C.c_double), ("rho0", C.c_double), ("body", C.c_double * 2),
                 ("k_spring", C.c_double), ("phi_m", C.c_double), ("kappa_area", C.c_double),
                 ("D", C.c_double * 2), ("reaction", C.c_int32 * 2),
-                ("rc", (C.c_double * 4) * 2), ("wall_u_top", C.c_double), ("no_flux", C.c_int32 * 2)]
+                ("rc", (C.c_double * 4) * 2), ("wall_u_top", C.c_double), ("no_flux", C.c_int32 * 2),
+                ("mass_source", C.c_double), ("area_alpha", C.c_double)]
 
 
 _lib = None
@@ -116,6 +117,8 @@ def make_params(d: dict, interp_new_u: bool = False, wall_u_top: float = 0.0) ->
             p.rc[s][k] = float(v)
         p.no_flux[s] = 1 if spc.get("no_flux", False) else 0
     p.wall_u_top = float(wall_u_top)
+    p.mass_source = float(d.get("mass_source", 0.0))
+    p.area_alpha = float(d.get("area_alpha", 0.0))
     return p
 
 

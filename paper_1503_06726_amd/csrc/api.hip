@@ -162,6 +162,11 @@ LatticeArgs lattice_args_at(lbib_ctx* c, int cur)
     a.inside_clr = c->inside[1 - cur];
     a.wpr = c->wpr;
     a.noflux = c->n_cells ? no_flux_bits(p) : 0;
+    a.cmap = c->n_cells ? c->cmap : nullptr;
+    a.A0 = c->d_A0;
+    a.area = c->d_area;
+    a.msrc = p.mass_source;
+    a.alpha = p.area_alpha;
     a.e_out = nullptr;
     return a;
 }
@@ -183,6 +188,7 @@ MembraneArgs membrane_args_at(lbib_ctx* c, int cur, int advect)
     a.rec_ij = c->d_rec_ij;
     a.inside = c->inside[cur];
     a.src = c->d_src;
+    a.cmap = c->cmap;
     a.wpr = c->wpr;
     a.err = c->d_err;
     a.nn = c->nn;
@@ -350,6 +356,7 @@ void free_all(lbib_ctx* c)
         c->f[b] = c->g[b] = nullptr;
     }
     for (int b = 0; b < 2; ++b) state_free(c, c->inside[b], (size_t)c->ny_words());
+    state_free(c, c->cmap, (size_t)c->nn);
     state_free(c, c->d_t_count, (size_t)c->tile_cap);
     state_free(c, c->d_t_off, (size_t)c->tile_cap + 1);
     state_free(c, c->d_t_cur, (size_t)c->tile_cap);
@@ -374,7 +381,7 @@ void free_all(lbib_ctx* c)
 // at most N nodes).
 // -------------------------------------------------------------------------------------
 enum Piece {
-    PC_F0, PC_F1, PC_G0, PC_G1, PC_IN0, PC_IN1, PC_TCOUNT, PC_TOFF, PC_TCUR, PC_ERR, PC_PARTIAL, PC_STAGE,
+    PC_F0, PC_F1, PC_G0, PC_G1, PC_IN0, PC_IN1, PC_CMAP, PC_TCOUNT, PC_TOFF, PC_TCUR, PC_ERR, PC_PARTIAL, PC_STAGE,
     PC_OFF, PC_X, PC_L0, PC_A0, PC_AREA, PC_IJ, PC_PART, PC_CNT, PC_REC, PC_RECIJ, PC_LIST, PC_SRC,
     PC_COUNT
 };
@@ -410,6 +417,7 @@ void piece_bytes(const lbib_ctx& c, int64_t n_nodes, int64_t n_cells, size_t sta
     b[PC_F0] = b[PC_F1] = c.f_elems() * c.pop_bytes;
     b[PC_G0] = b[PC_G1] = c.S ? c.g_elems() * c.pop_bytes : 0;
     b[PC_IN0] = b[PC_IN1] = (size_t)c.ny_words() * sizeof(unsigned);
+    b[PC_CMAP] = mass_sources(c.p) ? (size_t)c.nn * sizeof(unsigned) : 0;
     b[PC_TCOUNT] = b[PC_TCUR] = (size_t)c.tile_cap * sizeof(int);
     b[PC_TOFF] = ((size_t)c.tile_cap + 1) * sizeof(int);
     b[PC_ERR] = sizeof(int);
@@ -436,6 +444,7 @@ void** piece_slot(lbib_ctx* c, int i)
     case PC_G1: return &c->g[1];
     case PC_IN0: return reinterpret_cast<void**>(&c->inside[0]);
     case PC_IN1: return reinterpret_cast<void**>(&c->inside[1]);
+    case PC_CMAP: return reinterpret_cast<void**>(&c->cmap);
     case PC_TCOUNT: return reinterpret_cast<void**>(&c->d_t_count);
     case PC_TOFF: return reinterpret_cast<void**>(&c->d_t_off);
     case PC_TCUR: return reinterpret_cast<void**>(&c->d_t_cur);
@@ -762,6 +771,10 @@ lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out)
         }
     }
     for (int b = 0; b < 2 && s == LBIB_OK; ++b) s = dev_alloc(c, &c->inside[b], (size_t)c->ny_words());
+    if (s == LBIB_OK && mass_sources(c->p)) {
+        s = dev_alloc(c, &c->cmap, (size_t)c->nn);
+        if (s == LBIB_OK && launch_fill_i32(c, (int*)c->cmap, c->nn, -1) != hipSuccess) s = LBIB_EDEVICE;
+    }
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_count, (size_t)c->tile_cap);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_off, (size_t)c->tile_cap + 1);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_cur, (size_t)c->tile_cap);
@@ -849,7 +862,8 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
         return s;
     }
     c->max_cell_nodes = max_n;
-    c->mask_needed = any_source_decay(c->p) || no_flux_bits(c->p) != 0;   // the step keeps the inside map
+    // the step keeps the inside map (and, with mass sources, the cell map)
+    c->mask_needed = any_source_decay(c->p) || no_flux_bits(c->p) != 0 || mass_sources(c->p);
     LBIB_HIP(c, hipMemcpyAsync(c->d_off, off, (C + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream));
     LBIB_HIP(c, hipMemcpyAsync(c->d_X, xy, N * sizeof(double2), hipMemcpyHostToDevice, c->stream));
     LBIB_HIP(c, hipMemcpyAsync(c->d_l0, l0.data(), N * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -858,6 +872,7 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
     LBIB_LAUNCH(c, launch_fill_i32(c, c->d_err, 1, 0));
     if (c->mask_needed)
         for (int b = 0; b < 2; ++b) LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->inside[b], c->ny_words(), 0));
+    if (c->cmap) LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->cmap, c->nn, -1));   // claims of earlier cells
     LBIB_TRY(build_lists(c));
     LBIB_TRY(membrane(c, 0));
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
@@ -1016,6 +1031,10 @@ lbib_status lbib_set_source_cells(lbib_ctx* c, const uint8_t* src)
         c->err = "a source subset cannot be combined with no-flux membranes (they share the inside map)";
         return LBIB_EINVAL;
     }
+    if (src && mass_sources(c->p)) {
+        c->err = "a source subset cannot be combined with mass sources (they share the inside map)";
+        return LBIB_EINVAL;
+    }
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
     drop_graphs(c);
     if (src) {
@@ -1033,6 +1052,7 @@ lbib_status lbib_set_source_cells(lbib_ctx* c, const uint8_t* src)
         // rebuild the source bits of the current positions (forces and records are recomputed
         // from the same positions, unchanged)
         LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->inside[c->cur], c->ny_words(), 0));
+        if (c->cmap) LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->cmap, c->nn, -1));
         LBIB_TRY(membrane(c, 0));
     }
     LBIB_HIP(c, hipStreamSynchronize(c->stream));

@@ -391,6 +391,10 @@ lbib_status lbib_batch_create(lbib_ctx* const* sims, int32_t n, void* hip_stream
             c->err = "the batched pass has no no-flux membranes";
             return LBIB_EINVAL;
         }
+        if (mass_sources(c->p)) {
+            c->err = "the batched pass has no mass sources";
+            return LBIB_EINVAL;
+        }
     }
     lbib_batch* b = new (std::nothrow) lbib_batch();
     if (!b) return LBIB_ENOMEM;

@@ -305,7 +305,7 @@ __device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0
 // ly, ly + TILE_Y, ...  Order: listed nodes' records and the population loads issued; moments
 // (rho, u) of every row, u staged in LDS; listed nodes coupled (force spread into LDS, velocity
 // interpolated to the nodes); collision with the spread force and stores.
-template <int S, bool NODES, bool MASK, int ST, int RP, bool NF = false>
+template <int S, bool NODES, bool MASK, int ST, int RP, bool NF = false, bool MS = false>
 __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int tile)
 {
     constexpr int LY = TILE_Y * RP;
@@ -343,6 +343,7 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
     float g[RP][S > 0 ? S : 1][5];
     int m[RP];
     unsigned miss[RP];            // no-flux membranes: D2Q5 directions 1..4 that arrived across one
+    unsigned cell[RP];            // mass sources: the cell the node lies in (~0: none)
     // every lane loads (lanes beyond a ragged edge read the last column / row and discard it):
     // without branches around the loads the compiler waits for exactly the ones each use needs
 #pragma unroll
@@ -378,6 +379,8 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
             if (!q.top && inside_bit(a, q.x, q.yp) != me) ms |= 16u;
             miss[r] = ms;
         }
+        cell[r] = ~0u;
+        if constexpr (MS) cell[r] = a.cmap[(int64_t)yl * a.nx + xl];
     }
     if constexpr (NODES) load_records(a, cnd, cij, crc);
 
@@ -431,7 +434,35 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
         const float om = a.omega, om1 = 1.0f - a.omega;
         // force term 3 w_i rho (v_i . e)
         const float fx = 3.0f * rho * ex, fy = 3.0f * rho * ey;
-        {
+        if constexpr (MS) {
+            // mass source S of the node's cell, added as S f_i^eq(1, u) (the added mass moves
+            // with the fluid): the even part gains w_i S (1 + 4.5 vu^2 - 1.5 u^2), the odd part
+            // w_i 3 S vu, so rho om becomes rr = rho om + S in both
+            float sig = 0.0f;
+            if (cell[r] != ~0u) {
+                const unsigned k = cell[r];
+                sig = (float)(a.msrc + a.alpha * (a.A0[k] - a.area[k]));
+                a.cmap[(int64_t)n[r].y * a.nx + x] = ~0u;        // reset for the next step's claims
+            }
+            using T = typename Pop<ST>::T;
+            constexpr int P = TILE_X;
+            T* __restrict__ d = row_ptr((T*)a.fdst + (int64_t)n[r].y * a.frow, chunk_col(x, 9 * TILE_X));
+            const float rr = om * rho + sig, od0 = om * drho + sig, rs = 3.0f * rr;
+            store_nt(d, Pop<ST>::st(om1 * fr[0] + W0 * (od0 - rr * usq), SC9[0]));
+            float vu, ev, od;
+            vu = ux;      ev = W1 * (od0 + rr * (4.5f * vu * vu - usq)); od = W1 * (rs * vu + fx);
+            store_nt(d + P,     Pop<ST>::st(om1 * fr[1] + ev + od, SC9[1]));
+            store_nt(d + 3 * P, Pop<ST>::st(om1 * fr[3] + ev - od, SC9[3]));
+            vu = uy;      ev = W1 * (od0 + rr * (4.5f * vu * vu - usq)); od = W1 * (rs * vu + fy);
+            store_nt(d + 2 * P, Pop<ST>::st(om1 * fr[2] + ev + od, SC9[2]));
+            store_nt(d + 4 * P, Pop<ST>::st(om1 * fr[4] + ev - od, SC9[4]));
+            vu = ux + uy; ev = W5 * (od0 + rr * (4.5f * vu * vu - usq)); od = W5 * (rs * vu + fx + fy);
+            store_nt(d + 5 * P, Pop<ST>::st(om1 * fr[5] + ev + od, SC9[5]));
+            store_nt(d + 7 * P, Pop<ST>::st(om1 * fr[7] + ev - od, SC9[7]));
+            vu = uy - ux; ev = W5 * (od0 + rr * (4.5f * vu * vu - usq)); od = W5 * (rs * vu + fy - fx);
+            store_nt(d + 6 * P, Pop<ST>::st(om1 * fr[6] + ev + od, SC9[6]));
+            store_nt(d + 8 * P, Pop<ST>::st(om1 * fr[8] + ev - od, SC9[8]));
+        } else {
             // equilibrium deviation w_i (drho + rho (3 vu + 4.5 vu^2 - 1.5 u^2)), vu = v_i . u,
             // for pairs of opposite directions: the part even in v_i is shared, the odd part
             // (with the force term) changes sign
@@ -533,10 +564,10 @@ constexpr int lattice_waves(int S, int RP, bool)
     return RP == 1 ? 6 : RP == 2 ? (S <= 1 ? 5 : 4) : 3;
 }
 
-template <int S, bool NODES, bool MASK, int ST, bool NF = false>
+template <int S, bool NODES, bool MASK, int ST, bool NF = false, bool MS = false>
 __global__ __launch_bounds__(TILE_N) __attribute__((amdgpu_waves_per_eu(lattice_waves(S, RPT, false)))) void k_lattice(LatticeArgs a)
 {
-    lattice_tile<S, NODES, MASK, ST, RPT, NF>(a, tile_of_block((int)blockIdx.x, a.ntx, (a.ny + LTILE_Y - 1) / LTILE_Y));
+    lattice_tile<S, NODES, MASK, ST, RPT, NF, MS>(a, tile_of_block((int)blockIdx.x, a.ntx, (a.ny + LTILE_Y - 1) / LTILE_Y));
 }
 
 // Batched form: every workgroup takes one (simulation, tile) work item; the simulation's
@@ -776,6 +807,15 @@ template <int S, int ST>
 static hipError_t launch_lattice_s(lbib_ctx* c, const LatticeArgs& a, bool nodes, bool mask)
 {
     dim3 grid((unsigned)c->nltiles), block(TILE_N);
+    if (a.cmap && nodes) {              // mass sources read the cell map (mask is set)
+        if constexpr (S > 0)
+            if (a.noflux) {
+                hipLaunchKernelGGL((k_lattice<S, true, true, ST, true, true>), grid, block, 0, c->stream, a);
+                return hipGetLastError();
+            }
+        hipLaunchKernelGGL((k_lattice<S, true, true, ST, false, true>), grid, block, 0, c->stream, a);
+        return hipGetLastError();
+    }
     if constexpr (S > 0) {
         if (a.noflux) {                 // no-flux membranes read the inside map (mask is set)
             if (nodes) hipLaunchKernelGGL((k_lattice<S, true, true, ST, true>), grid, block, 0, c->stream, a);

@@ -7,8 +7,9 @@
 //      (positions in FP64);
 //   2. stages the cell's new positions in LDS and reduces the polygon area (shoelace, FP64,
 //      fixed-order wave and LDS reduction);
-//   3. when a reaction reads it, ORs the cell's interior into the inside-any-cell bit map
-//      (rasterised from the LDS positions);
+//   3. when a reaction, no-flux membranes or mass sources read it, ORs the cell's interior
+//      into the inside-any-cell bit map (rasterised from the LDS positions); with mass
+//      sources it also claims the interior's nodes in the cell map;
 //   4. evaluates the nodal forces in the paper's per-node form: constant tension
 //      (Eq. membraneforce), Hookean springs, area pressure kappa (A0 - A) dA/dX, refreshes
 //      the node's spreading record (fractional offset, force, stencil origin) and stores the
@@ -185,6 +186,7 @@ __device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c
                 raster_prefix(bm, rows, b.WW);
                 __syncthreads();
                 raster_or_bits(bm, b, r0, rows, a.inside, a.wpr, a.nx, a.ny, a.walls);
+                if (a.cmap) raster_claim_cells(bm, b, r0, rows, (unsigned)c, a.cmap, a.nx, a.ny, a.walls);
                 if (r0 + CH < b.H) __syncthreads();
             }
         }

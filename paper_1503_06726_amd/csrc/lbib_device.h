@@ -93,6 +93,12 @@ struct LatticeArgs {
     unsigned* __restrict__ inside_clr;     // the other buffer, cleared for the membrane kernel
     int wpr;
     int noflux;                            // bit s: the membranes are no-flux boundaries for species s
+    // mass sources: the cell each node lies in (read and reset to ~0 here; NULL: no sources),
+    // S_k = msrc + alpha (A0_k - A_k) from the reference and current areas
+    unsigned* __restrict__ cmap;
+    const double* __restrict__ A0;
+    const double* __restrict__ area;
+    double msrc, alpha;
     // inspection output (spread field only)
     double* __restrict__ e_out;
 };
@@ -111,6 +117,8 @@ struct MembraneArgs {
     int* __restrict__ rec_ij;          // [N]
     unsigned* __restrict__ inside;     // inside-any-cell bits, OR-ed into when raster != 0
     const uint8_t* __restrict__ src;   // [n_cells] source cells (NULL: every cell is rasterised)
+    unsigned* __restrict__ cmap;       // mass sources: [ny][nx] cell of each node, the lowest index
+                                       // claiming it (reset to ~0 by the lattice pass); NULL: none
     int wpr;
     int* __restrict__ err;
     int64_t nn;

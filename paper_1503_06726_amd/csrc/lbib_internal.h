@@ -51,6 +51,7 @@ struct lbib_ctx {
     size_t g_elems() const { return (size_t)p.ny * (size_t)grow(); }
     int cur = 0;
     unsigned* inside[2] = {nullptr, nullptr};   // inside-any-cell bits [ny][wpr], by parity cur
+    unsigned* cmap = nullptr;   // mass sources: [ny][nx] index of the cell each node lies in (~0: none)
     int wpr = 0;                     // 32-bit words per lattice row
     int64_t ny_words() const { return (int64_t)p.ny * wpr; }
 
@@ -123,6 +124,9 @@ inline int no_flux_bits(const lbib_params& p)
         if (p.species[s].flags & LBIB_SPECIES_NO_FLUX) b |= 1 << s;
     return b;
 }
+
+// does the step add mass inside the cells (constant source or area controller)?
+inline bool mass_sources(const lbib_params& p) { return p.mass_source != 0.0 || p.area_alpha != 0.0; }
 
 // kernel launchers (return the launch error)
 hipError_t launch_lattice(lbib_ctx* c, const LatticeArgs& a, bool nodes, bool mask);

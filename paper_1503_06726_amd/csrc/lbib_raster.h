@@ -118,6 +118,27 @@ __device__ inline void raster_write_ids(const unsigned* bm, const RasterBox& b, 
     }
 }
 
+// claim the odd pixels of box rows r0 .. r0 + rows - 1 for cell `cell` in the cell map: the
+// lowest index claiming a node keeps it (atomic minimum over a map reset to ~0), so the result
+// does not depend on the order of the cells' workgroups (one wavefront per row)
+__device__ inline void raster_claim_cells(const unsigned* bm, const RasterBox& b, int r0, int rows, unsigned cell,
+                                          unsigned* __restrict__ cmap, int nx, int ny, int walls)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int cw = wrap_i(b.cx0, nx);
+    for (int rr = wid; rr < rows; rr += nw) {
+        const int j = raster_row(b.ry0 + r0 + rr, ny, walls);
+        if (j < 0) continue;
+        unsigned* row = cmap + (int64_t)j * nx;
+        for (int col = lane; col < b.W; col += 64) {
+            if (!((bm[rr * b.WW + (col >> 5)] >> (col & 31)) & 1u)) continue;
+            int ix = cw + col;
+            if (ix >= nx) ix -= nx;
+            atomicMin(&row[ix], cell);
+        }
+    }
+}
+
 // Bits of relative columns c0 .. c0 + 31 of bitmap row `row` (WW words, W valid columns);
 // columns outside 0 .. W - 1 read as 0.
 __device__ inline unsigned bitmap_bits(const unsigned* row, int WW, int W, int c0)

@@ -46,7 +46,8 @@ class Params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("bc_y", C.c_int32), ("delta_kernel", C.c_int32),
                 ("tau", C.c_double), ("rho0", C.c_double), ("body_accel", C.c_double * 2),
                 ("k_spring", C.c_double), ("phi_m", C.c_double), ("kappa_area", C.c_double),
-                ("n_species", C.c_int32), ("storage", C.c_int32), ("species", Species * 2)]
+                ("n_species", C.c_int32), ("storage", C.c_int32), ("species", Species * 2),
+                ("mass_source", C.c_double), ("area_alpha", C.c_double)]
 
 
 class LbibError(RuntimeError):
@@ -190,6 +191,8 @@ def make_params(d: dict) -> Params:
         p.species[s].flags = SPECIES_NO_FLUX if spc.get("no_flux", False) else 0
         for k, v in enumerate(spc.get("c", (0.0, 0.0, 0.0, 0.0))):
             p.species[s].c[k] = float(v)
+    p.mass_source = float(d.get("mass_source", 0.0))
+    p.area_alpha = float(d.get("area_alpha", 0.0))
     return p
 
 

@@ -63,6 +63,8 @@ class Workload:
     phi_m: float = 0.0
     kappa_area: float = 0.0
     species: list = field(default_factory=list)
+    mass_source: float = 0.0        # constant mass source per node inside a cell and step
+    area_alpha: float = 0.0         # area controller: S_k = mass_source + area_alpha (A0_k - A_k)
     steps: int = 1
     # geometry (may be empty)
     offsets: np.ndarray = None      # int32 [n_cells+1]
@@ -92,7 +94,8 @@ class Workload:
                     body_accel=tuple(self.body_accel), delta_kernel=self.delta_kernel,
                     k_spring=self.k_spring, phi_m=self.phi_m, kappa_area=self.kappa_area,
                     species=[dict(D=s.D, phi_ref=s.phi_ref, reaction=s.reaction, c=tuple(s.c),
-                                  no_flux=bool(s.no_flux)) for s in self.species])
+                                  no_flux=bool(s.no_flux)) for s in self.species],
+                    mass_source=self.mass_source, area_alpha=self.area_alpha)
 
     def mask_needed(self) -> bool:
         return any(s.reaction == REACT_SOURCE_DECAY for s in self.species)
@@ -420,4 +423,25 @@ def no_flux_tissue(static: bool = True, no_flux: bool = True, seed: int = 7, nx:
     w.species[0].no_flux = no_flux
     w.name = f"no-flux tissue {nx}x{ny}, {n_cells} cells, {'static' if static else 'moving'}" + \
              ("" if no_flux else ", membranes invisible")
+    return w
+
+
+def mass_source_tissue(static: bool = False, mass_source: float = 1e-4, area_alpha: float = 1e-6,
+                       target: float = 1.2, no_flux: bool = False, seed: int = 11, nx: int = 120,
+                       ny: int = 90, n_cells: int = 8, steps: int = 60) -> Workload:
+    """A small walled tissue with mass sources inside the cells (Section "Control of Cell
+    Area"): every cell's reference area is ``target`` times the mean area nx ny / n_cells, so
+    the area controller grows the smaller cells and shrinks the larger ones, on top of the
+    constant source.  ``static``: no forces and no body acceleration; otherwise pre-stretched
+    springs and a body acceleration.  ``no_flux``: the species sees the membranes as no-flux
+    boundaries."""
+    w = small_tissue(nx=nx, ny=ny, n_cells=n_cells, n_species=1, seed=seed,
+                     body=(0.0, 0.0) if static else (2e-5, 0.0),
+                     k_spring=0.0 if static else 0.02, stretch=1.0 if static else 0.9, steps=steps)
+    w.mass_source = mass_source
+    w.area_alpha = area_alpha
+    w.species[0].no_flux = no_flux
+    w.rest_area = np.full(n_cells, target * nx * ny / n_cells)
+    w.name = f"mass-source tissue {nx}x{ny}, {n_cells} cells, source {mass_source:g}, alpha {area_alpha:g}" + \
+             (", static" if static else "") + (", no-flux species" if no_flux else "")
     return w

@@ -40,10 +40,10 @@ def test_ctypes_layout_matches_header():
     #include <stddef.h>
     #include "lbib.h"
     int main(void) {
-      printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lbib_params), sizeof(lbib_species),
+      printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lbib_params), sizeof(lbib_species),
              offsetof(lbib_params, tau), offsetof(lbib_params, body_accel), offsetof(lbib_params, kappa_area),
              offsetof(lbib_params, n_species), offsetof(lbib_params, species), offsetof(lbib_species, c),
-             offsetof(lbib_species, reaction));
+             offsetof(lbib_species, reaction), offsetof(lbib_params, mass_source), offsetof(lbib_params, area_alpha));
       return 0; }
     """
     with tempfile.TemporaryDirectory() as d:
@@ -54,7 +54,8 @@ def test_ctypes_layout_matches_header():
         vals = [int(v) for v in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
     P, S = lbib.Params, lbib.Species
     want = [C.sizeof(P), C.sizeof(S), P.tau.offset, P.body_accel.offset, P.kappa_area.offset,
-            P.n_species.offset, P.species.offset, S.c.offset, S.reaction.offset]
+            P.n_species.offset, P.species.offset, S.c.offset, S.reaction.offset, P.mass_source.offset,
+            P.area_alpha.offset]
     assert vals == want
 
 
@@ -194,3 +195,26 @@ def test_species_flags_validated():
     buf = C.create_string_buffer(256)
     assert lbib.lib().lbib_validate_params(C.byref(p), buf, 256) == lbib.EINVAL
     assert b"flags" in buf.value
+
+
+def test_mass_source_constants_validated():
+    d = dict(W.mass_source_tissue().params_dict())
+    assert lbib.validate_params(d)[0] == lbib.OK
+    p = lbib.make_params(d)
+    assert p.mass_source == d["mass_source"] and p.area_alpha == d["area_alpha"]
+    for field, bad, word in (("area_alpha", -1e-6, b"area_alpha"), ("mass_source", float("nan"), b"mass-source"),
+                             ("area_alpha", float("inf"), b"mass-source")):
+        q = lbib.make_params(d)
+        setattr(q, field, bad)
+        buf = C.create_string_buffer(256)
+        assert lbib.lib().lbib_validate_params(C.byref(q), buf, 256) == lbib.EINVAL
+        assert word in buf.value
+
+
+def test_workspace_size_holds_the_cell_map_of_mass_sources():
+    """Mass sources keep one 32-bit cell index per lattice node."""
+    d = dict(W.small_tissue(nx=200, ny=130, n_species=1).params_dict())
+    m = dict(d, mass_source=1e-4)
+    extra = _ws(m, 100) - _ws(d, 100)
+    assert 200 * 130 * 4 <= extra < 200 * 130 * 4 + 256
+    assert _ws(dict(d, area_alpha=1e-6), 100) == _ws(m, 100)

@@ -1,0 +1,110 @@
+"""Mass sources and area control (Section "Control of Cell Area") through the C ABI.
+
+Bars:
+  * a moving tissue (springs, body acceleration) with a constant source and the area
+    controller in every cell follows the FP64 oracle within the parity bar (1e-5 relative
+    L2 for rho, u, phi and the node positions) over 60 steps in FP32 storage: with one
+    species, with the species seeing the membranes as no-flux boundaries, and with no
+    species at all;
+  * replacing the cells by fewer ones mid-run (the cell map of the old cells must not
+    survive) still follows the oracle;
+  * the lattice gains the mass the sources add: sum rho grows by sum_k S_k N_k per step,
+    with the library's own areas and domain map, to FP32 round-off;
+  * a source subset and a batch are refused.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1503_06726_amd import lbib
+from paper_1503_06726_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0)
+
+
+def compare(g, o, what):
+    G, R = g.get_fields(), o.get_fields()
+    keys = ("rho", "u", "phi", "xy") if g.S else ("rho", "u", "xy")
+    errs = {k: rel(G[k], R[k]) for k in keys}
+    say(f"  {what} rel-L2:", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= 1e-5, (what, k, v)
+    assert np.array_equal(G["mask"], R["mask"]), what
+
+
+@pytest.mark.parametrize("variant", ["one species", "no-flux species", "no species"])
+def test_mass_sources_match_oracle(variant):
+    w = W.mass_source_tissue(no_flux=variant == "no-flux species")
+    if variant == "no species":
+        w.species = []
+    say(f"case {w.name} ({variant}): 60 steps")
+    g = lbib.from_workload(w)
+    o = O.from_workload(w)
+    g.step(60)
+    o.step(60)
+    compare(g, o, "60 steps")
+    g.close()
+
+
+def test_mass_sources_after_replacing_the_cells():
+    w = W.mass_source_tissue()
+    say(f"case {w.name}: 20 steps, then the first 3 cells alone for 30")
+    g = lbib.from_workload(w)
+    o = O.from_workload(w)
+    g.step(20)
+    o.step(20)
+    n3 = int(w.offsets[3])
+    xy = o.get_fields()["xy"][:n3].copy()
+    xg = g.get_fields()["xy"][:n3]
+    assert rel(xg, xy) <= 1e-5
+    off = w.offsets[:4].copy()
+    rest = None if w.rest_len is None else w.rest_len[:n3]
+    for s in (g, o):
+        s.set_cells(off, xy, rest, w.rest_area[:3])
+    g.step(30)
+    o.step(30)
+    compare(g, o, "after the replacement")
+    g.close()
+
+
+def test_mass_balance_on_the_gpu():
+    w = W.mass_source_tissue(nx=256, ny=200, n_cells=40, mass_source=2e-4, area_alpha=3e-6)
+    say(f"case {w.name}: mass balance over 5 steps")
+    g = lbib.from_workload(w)
+    off = w.offsets
+    g.step(3)
+    for _ in range(5):
+        F = g.get_fields()
+        _, A = g.get_forces()
+        want = sum((w.mass_source + w.area_alpha * (w.rest_area[k] - A[k])) * np.count_nonzero(F["mask"] == k + 1)
+                   for k in range(w.n_cells))
+        g.step(1)
+        got = g.get_fields()["rho"].sum() - F["rho"].sum()
+        say(f"  added {got:.6f}, sources {want:.6f}")
+        # FP32 populations: each node's deviation rounds to ~6e-8 of its size
+        assert abs(got - want) < 1e-3 * abs(want) + 1e-7 * w.nx * w.ny, (got, want)
+    g.close()
+
+
+def test_mass_source_refusals():
+    w = W.mass_source_tissue()
+    g = lbib.from_workload(w)
+    with pytest.raises(lbib.LbibError) as e:
+        g.set_source_cells(np.ones(w.n_cells, np.uint8))
+    assert e.value.status == lbib.EINVAL
+    with pytest.raises(lbib.LbibError):
+        lbib.Batch([g])
+    g.set_source_cells(None)             # all cells: accepted
+    g.step(3)
+    g.close()

@@ -45,13 +45,18 @@ def assert_same(a, b, what):
         assert np.array_equal(FA[k], FB[k]), f"{what}: field {k} differs"
 
 
-def tissue(seed=2, n_cells=10):
-    return W.small_tissue(nx=150, ny=98, n_cells=n_cells, n_species=1, seed=seed, stretch=1.1)
+def tissue(seed=2, n_cells=10, mass=False):
+    w = W.small_tissue(nx=150, ny=98, n_cells=n_cells, n_species=1, seed=seed, stretch=1.1)
+    if mass:                             # mass sources keep a cell map in the lattice part
+        w.mass_source, w.area_alpha = 1e-4, 1e-6
+        w.rest_area = np.full(n_cells, 1.2 * 150 * 98 / n_cells)
+    return w
 
 
-@pytest.mark.parametrize("storage", [lbib.STORAGE_FP32, lbib.STORAGE_FP16])
-def test_bound_state_bit_identical_through_moves(storage):
-    w = tissue()
+@pytest.mark.parametrize("storage,mass", [(lbib.STORAGE_FP32, False), (lbib.STORAGE_FP16, False),
+                                          (lbib.STORAGE_FP32, True)])
+def test_bound_state_bit_identical_through_moves(storage, mass):
+    w = tissue(mass=mass)
     d = dict(w.params_dict(), storage=storage)
     say(f"case {w.name}, storage {storage}: {w.n_nodes} nodes")
     A = lbib.from_workload(w, storage=storage)

@@ -583,3 +583,83 @@ def test_no_flux_changes_only_nodes_next_to_a_membrane():
         near |= np.roll(edge, (dy, dx), axis=(0, 1))
     assert np.array_equal(pa[~near], pb[~near])
     assert not np.array_equal(pa[edge], pb[edge])
+
+
+# ---- mass sources and area control (Section "Control of Cell Area") ----
+def _circle(n, cx, cy, r):
+    t = 2.0 * np.pi * np.arange(n) / n
+    return np.stack([cx + r * np.cos(t), cy + r * np.sin(t)], 1)
+
+
+def _shoelace(P):
+    x, y = P[:, 0], P[:, 1]
+    return 0.5 * float(np.sum(x * np.roll(y, -1) - np.roll(x, -1) * y))
+
+
+def test_mass_source_moves_with_the_fluid():
+    """A uniform flow at rest density, one static cell (no forces) with a constant source s:
+    each node of the cell collides to f^eq(1, u0) + s f^eq(1, u0) = f^eq(1 + s, u0), so after
+    one step nodes whose upstream neighbours all lie in the cell have density 1 + s and still
+    the velocity u0, and nodes whose neighbours all lie outside keep density 1 and u0."""
+    nx, ny, s = 48, 40, 1e-3
+    u0 = (0.02, -0.01)
+    o = O.Sim(dict(nx=nx, ny=ny, bc_y=0, tau=0.8, mass_source=s))
+    cx, cy, R = 24.3, 20.1, 8.0
+    o.set_cells(np.array([0, 48], np.int32), _circle(48, cx, cy, R))
+    u = np.zeros((2, ny, nx))
+    u[0], u[1] = u0
+    o.set_fields(rho=np.ones((ny, nx)), u=u)
+    o.step(1)
+    f = o.get_fields()
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    d = np.hypot(xx - cx, yy - cy)
+    inner, outer = d < R - 2.5, d > R + 2.5
+    assert inner.sum() > 60 and outer.sum() > 1000
+    np.testing.assert_allclose(f["rho"][inner], 1.0 + s, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(f["rho"][outer], 1.0, rtol=0, atol=1e-14)
+    for q in range(2):
+        np.testing.assert_allclose(f["u"][q][inner | outer], u0[q], rtol=0, atol=1e-14)
+
+
+def test_mass_source_adds_exactly_the_controlled_mass():
+    """In a walled box (collision, forcing, streaming and halfway bounce-back all conserve
+    mass) each step adds sum_k S_k N_k, S_k = s + alpha (A0_k - A_k) with A_k the shoelace area
+    of the step's positions and N_k the nodes of cell k in the domain map, while springs and a
+    body force move the cells."""
+    w = W.mass_source_tissue(static=False, mass_source=2e-4, area_alpha=3e-6)
+    off = w.offsets
+    o = O.from_workload(w)
+    for _ in range(8):
+        f0 = o.get_fields()
+        X, m = f0["xy"], f0["mask"]
+        want = 0.0
+        for k in range(w.n_cells):
+            A = _shoelace(X[off[k]:off[k + 1]])
+            want += (w.mass_source + w.area_alpha * (w.rest_area[k] - A)) * np.count_nonzero(m == k + 1)
+        o.step(1)
+        got = o.get_fields()["rho"].sum() - f0["rho"].sum()
+        assert abs(got - want) < 1e-10 * f0["rho"].sum(), (got, want)
+
+
+@pytest.mark.parametrize("A0", [420.0, 220.0])
+def test_area_controller_follows_its_rate_law(A0):
+    """One free circular cell (no membrane forces) under the area controller alone: the added
+    mass S A per step becomes cell area, so A follows dA/dt = alpha (A0 - A) A.  The lattice
+    fluid is weakly compressible (part of the mass raises the density instead), so the area
+    stays within 15 % of the initial gap of that law's solution, and approaches A0
+    monotonically from either side."""
+    alpha = 2e-5
+    o = O.Sim(dict(nx=64, ny=64, bc_y=0, tau=0.8, area_alpha=alpha))
+    o.set_cells(np.array([0, 64], np.int32), _circle(64, 32.3, 31.7, 10.0), rest_area=np.array([A0]))
+    A = _shoelace(o.get_fields()["xy"])
+    gap0 = A0 - A
+    law, prev = A, A
+    for _ in range(5):
+        o.step(80)
+        for _k in range(80):
+            law += alpha * (A0 - law) * law
+        now = _shoelace(o.get_fields()["xy"])
+        assert abs(now - law) < 0.15 * abs(gap0), (now, law)
+        assert (now - prev) * gap0 > 0
+        prev = now
+    assert abs(A0 - prev) < 0.2 * abs(gap0)
