@@ -120,6 +120,15 @@ typedef struct {
      * (LBIB_EINVAL / LBIB_ESTATE). */
     double mass_source;      /* constant mass source per inside node and step (Case II's uniform source) */
     double area_alpha;       /* proportional constant alpha of the area controller, >= 0 */
+    /* Pressure boundary (Suppl. "Pressure Boundary Condition for the Fluid Equations"; the
+     * iso-pressure outflow of the validation cases): with pressure_ring = 1 every node of the
+     * lattice's outer ring (columns 0 and nx-1, rows 0 and ny-1) is a point of prescribed
+     * density rho0.  Its streamed populations are rescaled by gamma = rho0 / rho before the
+     * collision; the velocity is unchanged, since gamma cancels in it.  Reported fields and
+     * sums are those after the rescaling.  This is the mass sink that lets cells grow under
+     * mass sources.  Not with a batch (LBIB_EINVAL). */
+    int32_t pressure_ring;   /* 0 or 1 */
+    int32_t reserved;        /* 0 */
 } lbib_params;
 
 typedef struct lbib_ctx lbib_ctx;

@@ -53,6 +53,11 @@
  *    source enters the lattice Boltzmann equation; the added mass is taken to move with
  *    the local fluid, S_k f^eq_i(1, u) added after collision, so rho rises by S_k and u
  *    is unchanged.
+ *  - Pressure boundary (Suppl. "Pressure Boundary Condition for the Fluid Equations"),
+ *    used as the iso-pressure outflow of the validation cases: the nodes of the lattice's
+ *    outer ring hold the density rho0; at the start of each step their populations are
+ *    multiplied by rho0 / rho (the velocity is unchanged).  Reported fields and sums are
+ *    those after the rescaling.
  *  - ADE-only iteration (the steady-state measurement): the species lattices advance
  *    with u = 0 while the fluid, the membranes and the domain map stay frozen; the
  *    relative change after iteration k is ||phi^k - phi^{k-1}||_2 / ||phi^k||_2, with
@@ -486,11 +491,35 @@ static void moments(orc_ctx* c)
  *  4 collision of fluid (Eq. bgkequation) and species (D2Q5 equation) with u^n;
  *  5 streaming (free flight), halfway bounce-back at walls;
  *  6 interpolation of u^n to the nodes (Eq. conversion2) and explicit move. */
+/* is node x (row-major index) on the lattice's outer ring? */
+static int on_ring(const orc_params* p, int64_t x)
+{
+    int64_t i = x % p->nx, j = x / p->nx;
+    return i == 0 || i == p->nx - 1 || j == 0 || j == p->ny - 1;
+}
+
+/* Pressure boundary: the populations of every ring node scaled by gamma = rho0 / rho, so the
+ * node's density becomes rho0 and its velocity sum f v / sum f stays as it was. */
+static void pressure_ring(orc_ctx* c)
+{
+    int64_t nn = c->nn;
+    for (int64_t x = 0; x < nn; ++x) {
+        if (!on_ring(&c->p, x)) continue;
+        double r = 0.0;
+        for (int i = 0; i < 9; ++i) r += c->f[i * nn + x];
+        double gamma = c->p.rho0 / r;
+        for (int i = 0; i < 9; ++i) c->f[i * nn + x] *= gamma;
+    }
+}
+
 static void step_once(orc_ctx* c)
 {
     const orc_params* p = &c->p;
     int64_t nx = p->nx, ny = p->ny, nn = c->nn;
     int S = p->n_species;
+
+    /* 0: pressure boundary on the outer ring */
+    if (p->pressure_ring) pressure_ring(c);
 
     /* 1-2: forces and spreading */
     memset(c->ex, 0, sizeof(double) * (size_t)nn);
@@ -704,6 +733,11 @@ void orc_get_fields(orc_ctx* c, double* rho, double* u, double* phi, double* X, 
             double fi = c->f[i * nn + x];
             r += fi; jx += fi * VX[i]; jy += fi * VY[i];
         }
+        if (c->p.pressure_ring && on_ring(&c->p, x)) {
+            /* as the next step's rescaling leaves the node */
+            double gamma = c->p.rho0 / r;
+            r *= gamma; jx *= gamma; jy *= gamma;
+        }
         if (rho) rho[x] = r;
         if (u) { u[x] = jx / r; u[nn + x] = jy / r; }
         if (phi) {
@@ -757,11 +791,18 @@ void orc_invariants(const orc_ctx* c, double* out)
     /* long double accumulators: the sums are used to check conservation to round-off */
     int64_t nn = c->nn;
     long double m = 0.0L, px = 0.0L, py = 0.0L;
-    for (int64_t x = 0; x < nn; ++x)
+    for (int64_t x = 0; x < nn; ++x) {
+        double gamma = 1.0;
+        if (c->p.pressure_ring && on_ring(&c->p, x)) {
+            double r = 0.0;
+            for (int i = 0; i < 9; ++i) r += c->f[i * nn + x];
+            gamma = c->p.rho0 / r;
+        }
         for (int i = 0; i < 9; ++i) {
-            double fi = c->f[i * nn + x];
+            double fi = gamma * c->f[i * nn + x];
             m += fi; px += fi * VX[i]; py += fi * VY[i];
         }
+    }
     out[0] = (double)m; out[1] = (double)px; out[2] = (double)py;
     for (int s = 0; s < c->p.n_species; ++s) {
         long double t = 0.0L;

@@ -57,6 +57,8 @@ typedef struct {
     int32_t no_flux[2];          /* 1: the cell membranes are no-flux boundaries for species s */
     double mass_source;          /* constant mass source per node inside a cell and step */
     double area_alpha;           /* area controller: S_k = mass_source + area_alpha (A0_k - A_k) */
+    int32_t pressure_ring;       /* 1: the lattice's outer ring is a pressure boundary at rho0 */
+    int32_t reserved;
 } orc_params;
 
 typedef struct orc_ctx orc_ctx;

@@ -40,7 +40,8 @@ class Params(C.Structure):
                 ("k_spring", C.c_double), ("phi_m", C.c_double), ("kappa_area", C.c_double),
                 ("D", C.c_double * 2), ("reaction", C.c_int32 * 2),
                 ("rc", (C.c_double * 4) * 2), ("wall_u_top", C.c_double), ("no_flux", C.c_int32 * 2),
-                ("mass_source", C.c_double), ("area_alpha", C.c_double)]
+                ("mass_source", C.c_double), ("area_alpha", C.c_double),
+                ("pressure_ring", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -119,6 +120,7 @@ def make_params(d: dict, interp_new_u: bool = False, wall_u_top: float = 0.0) ->
     p.wall_u_top = float(wall_u_top)
     p.mass_source = float(d.get("mass_source", 0.0))
     p.area_alpha = float(d.get("area_alpha", 0.0))
+    p.pressure_ring = int(bool(d.get("pressure_ring", False)))
     return p
 
 

@@ -167,6 +167,7 @@ LatticeArgs lattice_args_at(lbib_ctx* c, int cur)
     a.area = c->d_area;
     a.msrc = p.mass_source;
     a.alpha = p.area_alpha;
+    a.pring = p.pressure_ring;
     a.e_out = nullptr;
     return a;
 }

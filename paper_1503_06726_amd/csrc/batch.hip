@@ -391,8 +391,8 @@ lbib_status lbib_batch_create(lbib_ctx* const* sims, int32_t n, void* hip_stream
             c->err = "the batched pass has no no-flux membranes";
             return LBIB_EINVAL;
         }
-        if (mass_sources(c->p)) {
-            c->err = "the batched pass has no mass sources";
+        if (mass_sources(c->p) || c->p.pressure_ring) {
+            c->err = "the batched pass has no mass sources or pressure boundaries";
             return LBIB_EINVAL;
         }
     }

@@ -380,7 +380,9 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
             miss[r] = ms;
         }
         cell[r] = ~0u;
-        if constexpr (MS) cell[r] = a.cmap[(int64_t)yl * a.nx + xl];
+        if constexpr (MS) {
+            if (a.cmap) cell[r] = a.cmap[(int64_t)yl * a.nx + xl];
+        }
     }
     if constexpr (NODES) load_records(a, cnd, cij, crc);
 
@@ -388,6 +390,21 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
     float rho_r[RP], drho_r[RP], ux_r[RP], uy_r[RP];
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
+        if constexpr (MS) {
+            // pressure boundary on the outer ring: f_i -> gamma f_i with gamma = rho0 / rho, in
+            // deviations d_i -> gamma (d_i - w_i drho); the velocity is unchanged
+            const int y = y0 + t / TILE_X + r * TILE_Y;
+            if (a.pring && (x == 0 || x == a.nx - 1 || y == 0 || y == a.ny - 1)) {
+                float* fr = f[r];
+                const float d = ((fr[0] + fr[1]) + (fr[2] + fr[3])) + ((fr[4] + fr[5]) + (fr[6] + fr[7])) + fr[8];
+                const float gm = a.rho0 / (a.rho0 + d);
+                fr[0] = gm * (fr[0] - W0 * d);
+#pragma unroll
+                for (int i = 1; i < 5; ++i) fr[i] = gm * (fr[i] - W1 * d);
+#pragma unroll
+                for (int i = 5; i < 9; ++i) fr[i] = gm * (fr[i] - W5 * d);
+            }
+        }
         const float* fr = f[r];
         drho_r[r] = ((fr[0] + fr[1]) + (fr[2] + fr[3])) + ((fr[4] + fr[5]) + (fr[6] + fr[7])) + fr[8];
         rho_r[r] = a.rho0 + drho_r[r];
@@ -696,6 +713,7 @@ struct MomentArgs {
     const unsigned* inside;           // inside-cell map of the current positions (no-flux membranes)
     int wpr;
     int noflux;                       // bit s: no-flux membranes for species s
+    int pring;                        // the outer ring is held at rho0 (pressure boundary)
 };
 
 template <int ST>
@@ -709,6 +727,13 @@ __device__ inline void node_moments(const MomentArgs& a, int x, int y, double& d
     for (int i = 0; i < 9; ++i) drho += (double)f[i];
     jx = ((double)f[1] - f[3]) + ((double)f[5] - f[6]) + ((double)f[8] - f[7]);
     jy = ((double)f[2] - f[4]) + ((double)f[5] + f[6]) - ((double)f[7] + f[8]);
+    if (a.pring && (x == 0 || x == a.nx - 1 || y == 0 || y == a.ny - 1)) {
+        // the density the next collision sees on the pressure ring: rho0, momentum rescaled
+        const double gm = a.rho0 / (a.rho0 + drho);
+        jx *= gm;
+        jy *= gm;
+        drho = 0.0;
+    }
     unsigned miss = 0u;
     if (a.noflux) {
         // populations that arrived across a no-flux membrane (as in the lattice pass)
@@ -807,13 +832,15 @@ template <int S, int ST>
 static hipError_t launch_lattice_s(lbib_ctx* c, const LatticeArgs& a, bool nodes, bool mask)
 {
     dim3 grid((unsigned)c->nltiles), block(TILE_N);
-    if (a.cmap && nodes) {              // mass sources read the cell map (mask is set)
+    if ((a.cmap && nodes) || a.pring) {  // mass sources (the cell map; mask is set) or pressure ring
         if constexpr (S > 0)
             if (a.noflux) {
-                hipLaunchKernelGGL((k_lattice<S, true, true, ST, true, true>), grid, block, 0, c->stream, a);
+                if (nodes) hipLaunchKernelGGL((k_lattice<S, true, true, ST, true, true>), grid, block, 0, c->stream, a);
+                else hipLaunchKernelGGL((k_lattice<S, false, true, ST, true, true>), grid, block, 0, c->stream, a);
                 return hipGetLastError();
             }
-        hipLaunchKernelGGL((k_lattice<S, true, true, ST, false, true>), grid, block, 0, c->stream, a);
+        if (nodes) hipLaunchKernelGGL((k_lattice<S, true, true, ST, false, true>), grid, block, 0, c->stream, a);
+        else hipLaunchKernelGGL((k_lattice<S, false, true, ST, false, true>), grid, block, 0, c->stream, a);
         return hipGetLastError();
     }
     if constexpr (S > 0) {
@@ -944,6 +971,7 @@ static MomentArgs moment_args(lbib_ctx* c, double* out)
     a.inside = c->inside[c->cur];
     a.wpr = c->wpr;
     a.noflux = c->n_cells ? no_flux_bits(c->p) : 0;
+    a.pring = c->p.pressure_ring;
     return a;
 }
 

@@ -99,6 +99,7 @@ struct LatticeArgs {
     const double* __restrict__ A0;
     const double* __restrict__ area;
     double msrc, alpha;
+    int pring;                             // the outer ring of nodes is held at density rho0
     // inspection output (spread field only)
     double* __restrict__ e_out;
 };

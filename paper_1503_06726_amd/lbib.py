@@ -47,7 +47,8 @@ class Params(C.Structure):
                 ("tau", C.c_double), ("rho0", C.c_double), ("body_accel", C.c_double * 2),
                 ("k_spring", C.c_double), ("phi_m", C.c_double), ("kappa_area", C.c_double),
                 ("n_species", C.c_int32), ("storage", C.c_int32), ("species", Species * 2),
-                ("mass_source", C.c_double), ("area_alpha", C.c_double)]
+                ("mass_source", C.c_double), ("area_alpha", C.c_double),
+                ("pressure_ring", C.c_int32), ("reserved", C.c_int32)]
 
 
 class LbibError(RuntimeError):
@@ -193,6 +194,7 @@ def make_params(d: dict) -> Params:
             p.species[s].c[k] = float(v)
     p.mass_source = float(d.get("mass_source", 0.0))
     p.area_alpha = float(d.get("area_alpha", 0.0))
+    p.pressure_ring = int(bool(d.get("pressure_ring", False)))
     return p
 
 

@@ -65,6 +65,7 @@ class Workload:
     species: list = field(default_factory=list)
     mass_source: float = 0.0        # constant mass source per node inside a cell and step
     area_alpha: float = 0.0         # area controller: S_k = mass_source + area_alpha (A0_k - A_k)
+    pressure_ring: bool = False     # the lattice's outer ring holds the density at rho0 (outflow)
     steps: int = 1
     # geometry (may be empty)
     offsets: np.ndarray = None      # int32 [n_cells+1]
@@ -95,7 +96,8 @@ class Workload:
                     k_spring=self.k_spring, phi_m=self.phi_m, kappa_area=self.kappa_area,
                     species=[dict(D=s.D, phi_ref=s.phi_ref, reaction=s.reaction, c=tuple(s.c),
                                   no_flux=bool(s.no_flux)) for s in self.species],
-                    mass_source=self.mass_source, area_alpha=self.area_alpha)
+                    mass_source=self.mass_source, area_alpha=self.area_alpha,
+                    pressure_ring=self.pressure_ring)
 
     def mask_needed(self) -> bool:
         return any(s.reaction == REACT_SOURCE_DECAY for s in self.species)

@@ -40,10 +40,11 @@ def test_ctypes_layout_matches_header():
     #include <stddef.h>
     #include "lbib.h"
     int main(void) {
-      printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lbib_params), sizeof(lbib_species),
+      printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lbib_params), sizeof(lbib_species),
              offsetof(lbib_params, tau), offsetof(lbib_params, body_accel), offsetof(lbib_params, kappa_area),
              offsetof(lbib_params, n_species), offsetof(lbib_params, species), offsetof(lbib_species, c),
-             offsetof(lbib_species, reaction), offsetof(lbib_params, mass_source), offsetof(lbib_params, area_alpha));
+             offsetof(lbib_species, reaction), offsetof(lbib_params, mass_source), offsetof(lbib_params, area_alpha),
+             offsetof(lbib_params, pressure_ring));
       return 0; }
     """
     with tempfile.TemporaryDirectory() as d:
@@ -55,7 +56,7 @@ def test_ctypes_layout_matches_header():
     P, S = lbib.Params, lbib.Species
     want = [C.sizeof(P), C.sizeof(S), P.tau.offset, P.body_accel.offset, P.kappa_area.offset,
             P.n_species.offset, P.species.offset, S.c.offset, S.reaction.offset, P.mass_source.offset,
-            P.area_alpha.offset]
+            P.area_alpha.offset, P.pressure_ring.offset]
     assert vals == want
 
 
@@ -203,7 +204,8 @@ def test_mass_source_constants_validated():
     p = lbib.make_params(d)
     assert p.mass_source == d["mass_source"] and p.area_alpha == d["area_alpha"]
     for field, bad, word in (("area_alpha", -1e-6, b"area_alpha"), ("mass_source", float("nan"), b"mass-source"),
-                             ("area_alpha", float("inf"), b"mass-source")):
+                             ("area_alpha", float("inf"), b"mass-source"), ("pressure_ring", 2, b"pressure_ring"),
+                             ("reserved", 1, b"reserved")):
         q = lbib.make_params(d)
         setattr(q, field, bad)
         buf = C.create_string_buffer(256)

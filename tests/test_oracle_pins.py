@@ -663,3 +663,58 @@ def test_area_controller_follows_its_rate_law(A0):
         assert (now - prev) * gap0 > 0
         prev = now
     assert abs(A0 - prev) < 0.2 * abs(gap0)
+
+
+# ---- pressure boundary (Suppl. "Pressure Boundary Condition for the Fluid Equations") ----
+def test_pressure_ring_holds_rho0_and_keeps_the_velocity():
+    """Random fields after a few steps: every ring node reports density rho0 and the velocity
+    sum f v / sum f of its stored populations (the rescaling cancels in it); interior nodes
+    report the plain moments."""
+    nx, ny = 40, 30
+    rng = np.random.default_rng(5)
+    o = O.Sim(dict(nx=nx, ny=ny, bc_y=1, tau=0.7, rho0=1.0, pressure_ring=True, body_accel=(1e-5, 0.0)))
+    o.set_fields(rho=1.0 + 0.01 * rng.random((ny, nx)), u=0.01 * rng.standard_normal((2, ny, nx)))
+    o.step(5)
+    F = o.get_fields()
+    f, _ = o.populations()
+    r = f.sum(0)
+    vx = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1]); vy = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+    ux = np.tensordot(vx, f, 1) / r
+    uy = np.tensordot(vy, f, 1) / r
+    ring = np.zeros((ny, nx), bool)
+    ring[0, :] = ring[-1, :] = ring[:, 0] = ring[:, -1] = True
+    assert np.max(np.abs(F["rho"][ring] - 1.0)) < 1e-15
+    assert np.max(np.abs(r[ring] - 1.0)) > 1e-5           # the stored populations were not rescaled yet
+    np.testing.assert_array_equal(F["rho"][~ring], r[~ring])
+    np.testing.assert_allclose(F["u"][0], ux, rtol=0, atol=1e-16)
+    np.testing.assert_allclose(F["u"][1], uy, rtol=0, atol=1e-16)
+
+
+def test_uniform_source_grows_a_cell_exponentially():
+    """Case II of the supplement's validation: a free circular cell with a uniform mass source
+    s per node and step in a domain whose boundary holds the pressure.  With an incompressible
+    fluid and an impermeable membrane the area would follow A0 exp(s t); the lattice fluid and
+    the immersed boundary lose a few per cent of it (compression, leakage), less on the finer
+    lattice.  Without the pressure ring the closed box compresses instead."""
+    s = 1e-3
+
+    def run(n, R, nodes, ring):
+        o = O.Sim(dict(nx=n, ny=n, bc_y=0, tau=1.0, mass_source=s, pressure_ring=ring))
+        o.set_cells(np.array([0, nodes], np.int32), _circle(nodes, n / 2 + 0.3, n / 2 - 0.3, R))
+        A0 = _shoelace(o.get_fields()["xy"])
+        out = []
+        for k in range(1, 8):
+            o.step(100)
+            out.append(_shoelace(o.get_fields()["xy"]) / A0)
+        return np.array(out), o.get_fields()["rho"].mean()
+
+    law = np.exp(s * 100 * np.arange(1, 8))
+    coarse, rho_c = run(100, 10.0, 64, True)
+    assert np.all(np.abs(coarse / law - 1.0) < 0.06), coarse / law
+    assert coarse[-1] > 1.9                                  # doubled by t = 700 > ln 2 / s
+    fine, _ = run(160, 16.0, 100, True)
+    # past the start-up transient (the first 100 steps), the finer lattice is closer to the law
+    assert np.all(np.abs(fine / law - 1.0)[1:] < np.abs(coarse / law - 1.0)[1:])
+    closed, rho_closed = run(100, 10.0, 64, False)
+    assert abs(rho_c - 1.0) < 3e-3 and rho_closed - 1.0 > 0.02
+    assert closed[-1] < coarse[-1]
