@@ -26,7 +26,7 @@ METRIC = "coupled LBM+IB MLUPS at 2048²/2000 cells (% HBM peak); ADE iters-to-s
 HBM_PEAK_GBS = 8000.0
 # HBM traffic per launch of the lattice kernel measured with rocprofv3 --pmc (FETCH_SIZE,
 # WRITE_SIZE, scaled by a copy kernel of known size); None until taken for the current kernel
-LATTICE_TRAFFIC_BYTES = 525_867_934
+LATTICE_TRAFFIC_BYTES = 525_301_116
 
 
 def log(*a):

@@ -70,6 +70,19 @@ __device__ inline const T& row_at(const T* base, int idx)
 {
     return *(const T*)((const char*)base + (unsigned)((unsigned)idx * (unsigned)sizeof(T)));
 }
+// The same element loaded with the non-temporal hint, for the planes whose cache lines one
+// tile reads whole (v_x = 0: each line holds the 64 columns of one chunk, and every element
+// is pulled by a node of the same tile).  The lines of the other planes are shared by two
+// horizontally adjacent tiles (one column crosses the chunk edge) and keep the default
+// policy, so the second tile still finds them in the L2; the lines the hint spares leave room
+// for them and for the node data the membrane kernel reads next.
+template <typename T>
+__device__ inline T row_nt(const T* base, int idx)
+{
+    const T* q = (const T*)((const char*)base + (unsigned)((unsigned)idx * (unsigned)sizeof(T)));
+    if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_nontemporal_load((const unsigned*)q));
+    else return __builtin_bit_cast(T, __builtin_nontemporal_load((const unsigned short*)q));
+}
 template <typename T>
 __device__ inline T* row_ptr(T* base, int idx)
 {
@@ -91,11 +104,11 @@ __device__ inline void pull9(const void* sv, int64_t row, const Nbr& n, float f[
     const T* rp = s + (int64_t)n.yp * row;
     const int cx = chunk_col(n.x, C), cm = chunk_col(n.xm, C), cp = chunk_col(n.xp, C);
     // across a wall the row is the node's own and the plane the opposite one
-    f[0] = Pop<ST>::ld(row_at(rc, cx), IS9[0]);
+    f[0] = Pop<ST>::ld(row_nt(rc, cx), IS9[0]);
     f[1] = Pop<ST>::ld(row_at(rc, cm + P), IS9[1]);
-    f[2] = Pop<ST>::ld(row_at(n.bot ? rc : rm, cx + (n.bot ? 4 : 2) * P), IS9[2]);
+    f[2] = Pop<ST>::ld(row_nt(n.bot ? rc : rm, cx + (n.bot ? 4 : 2) * P), IS9[2]);
     f[3] = Pop<ST>::ld(row_at(rc, cp + 3 * P), IS9[3]);
-    f[4] = Pop<ST>::ld(row_at(n.top ? rc : rp, cx + (n.top ? 2 : 4) * P), IS9[4]);
+    f[4] = Pop<ST>::ld(row_nt(n.top ? rc : rp, cx + (n.top ? 2 : 4) * P), IS9[4]);
     f[5] = Pop<ST>::ld(row_at(n.bot ? rc : rm, n.bot ? cx + 7 * P : cm + 5 * P), IS9[5]);
     f[6] = Pop<ST>::ld(row_at(n.bot ? rc : rm, n.bot ? cx + 8 * P : cp + 6 * P), IS9[6]);
     f[7] = Pop<ST>::ld(row_at(n.top ? rc : rp, n.top ? cx + 5 * P : cp + 7 * P), IS9[7]);
@@ -114,11 +127,11 @@ __device__ inline void pull5(const void* sv, int64_t row, int chunk, const Nbr& 
     const T* rm = s + (int64_t)n.ym * row;
     const T* rp = s + (int64_t)n.yp * row;
     const int cx = chunk_col(n.x, chunk), cm = chunk_col(n.xm, chunk), cp = chunk_col(n.xp, chunk);
-    g[0] = Pop<ST>::ld(row_at(rc, cx), IS5[0]);
+    g[0] = Pop<ST>::ld(row_nt(rc, cx), IS5[0]);
     g[1] = Pop<ST>::ld(row_at(rc, cm + P), IS5[1]);
-    g[2] = Pop<ST>::ld(row_at(n.bot ? rc : rm, cx + (n.bot ? 4 : 2) * P), IS5[2]);
+    g[2] = Pop<ST>::ld(row_nt(n.bot ? rc : rm, cx + (n.bot ? 4 : 2) * P), IS5[2]);
     g[3] = Pop<ST>::ld(row_at(rc, cp + 3 * P), IS5[3]);
-    g[4] = Pop<ST>::ld(row_at(n.top ? rc : rp, cx + (n.top ? 2 : 4) * P), IS5[4]);
+    g[4] = Pop<ST>::ld(row_nt(n.top ? rc : rp, cx + (n.top ? 2 : 4) * P), IS5[4]);
 }
 
 // streaming store that bypasses the caches' retention (the next pass reads it from HBM)
