@@ -229,7 +229,8 @@ lbib_status lbib_get_spread(lbib_ctx* ctx, double* e);
  * source cell] - c[1] phi): src[n_cells] host bytes, nonzero = source; NULL restores the
  * default, every cell.  A node inside several cells is inside a source cell when any of them
  * is one.  The cells must be set (LBIB_ESTATE otherwise); lbib_set_cells resets the choice.
- * Synchronises. */
+ * A subset (src not NULL) is refused with LBIB_EINVAL when a species has no-flux membranes or
+ * mass sources are on: they read the same inside map.  Synchronises. */
 lbib_status lbib_set_source_cells(lbib_ctx* ctx, const uint8_t* src);
 
 /* ADE-only iterations towards the steady state of the species (the "iterations to steady"
@@ -291,7 +292,8 @@ typedef struct lbib_batch lbib_batch;
  * each with cells set, all with the same species count, storage type and source law).  Any
  * context between list rebuilds has its lists rebuilt first.  hip_stream as in lbib_create
  * (the batch's work runs there).  The contexts stay owned by the caller and must outlive the
- * batch.  LBIB_EINVAL for a bad set; *out is NULL on failure. */
+ * batch.  LBIB_EINVAL for a bad set, and for a context with no-flux species, mass sources or
+ * the pressure ring (the batched pass has none of them); *out is NULL on failure. */
 lbib_status lbib_batch_create(lbib_ctx* const* sims, int32_t n, void* hip_stream, lbib_batch** out);
 
 /* Enqueue n >= 0 steps of every simulation on the batch's stream (asynchronous). */
