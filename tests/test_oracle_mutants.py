@@ -67,6 +67,14 @@ MUTANTS = {
     "body force overwrites spread": ("c->ex[x] += p->body[0];", "c->ex[x] = p->body[0];"),
     "moments velocity sign": ("jx += fi * VX[i];\n            jy += fi * VY[i];\n        }\n        c->rho[x] = r;",
                               "jx -= fi * VX[i];\n            jy += fi * VY[i];\n        }\n        c->rho[x] = r;"),
+    "no-flux boundary value without the missing weights": ("double phib = known / (1.0 - wm);", "double phib = known;"),
+    "no-flux upstream neighbour reversed": ("int64_t yu = y - VY[i], xu = wrapi(x - VX[i], nx);",
+                                            "int64_t yu = y + VY[i], xu = wrapi(x + VX[i], nx);"),
+    "area controller sign": ("p->mass_source + p->area_alpha * (c->A0[k] - c->area[k]);",
+                             "p->mass_source + p->area_alpha * (c->area[k] - c->A0[k]);"),
+    "mass source added at rest": ("orc_equilibrium9(1.0, vx, vy, e1);", "orc_equilibrium9(1.0, 0.0, 0.0, e1);"),
+    "pressure ring gamma inverted": ("double gamma = c->p.rho0 / r;\n        for (int i = 0; i < 9; ++i) c->f[i * nn + x] *= gamma;",
+                                     "double gamma = r / c->p.rho0;\n        for (int i = 0; i < 9; ++i) c->f[i * nn + x] *= gamma;"),
 }
 
 
