@@ -382,6 +382,25 @@ void lbib_net_destroy(lbib_net* net);
  * out has 3 + n_species doubles.  Returns LBIB_ENUMERIC if any sum is not finite. */
 lbib_status lbib_reduce(lbib_ctx* ctx, double* out);
 
+/* The sums of lbib_reduce, for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine) and does not synchronise: it
+ * enqueues on the context's stream the same two kernels as lbib_reduce, which write
+ * out_device[0 .. 2 + n_species] in the same order, bit for bit the values lbib_reduce returns
+ * for the same state.
+ *   out_device  device memory of the context's device, 3 + n_species doubles, caller-owned;
+ *               valid once the context's stream has reached the call
+ * The per-block partial sums live in a scratch array that the library holds in each GPU's
+ * memory for the life of the process: 4096 partials of 5 doubles (160 KiB), enough for any
+ * lattice (each block loops over its share of the nodes).  Every context on a GPU shares that
+ * GPU's scratch, and it keeps the last call's partials: calls on one GPU that overlap (on
+ * different streams, or from different threads) race and must be ordered by the caller.
+ * No check for non-finite sums is made (the values stay on the device).
+ * Errors: LBIB_ESTATE for a NULL context; LBIB_EINVAL for a NULL pointer or memory that is not
+ * device memory of the context's device; LBIB_EDEVICE when the scratch has no device address
+ * or a launch fails. */
+lbib_status lbib_reduce_device(lbib_ctx* ctx, double* out_device);
+
 /* Wait for all queued work on the context's stream. */
 lbib_status lbib_sync(lbib_ctx* ctx);
 

@@ -751,6 +751,9 @@ lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out)
         delete c;
         return LBIB_EDEVICE;
     }
+    // the device address of the reduction scratch on this device (lbib_reduce_device); a
+    // failure is reported by that call, not here
+    c->scratch_ok = reduce_scratch_init(c->device) == hipSuccess;
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
     } else {
@@ -1009,7 +1012,7 @@ lbib_status lbib_reduce(lbib_ctx* c, double* out)
     if (!out) return LBIB_EINVAL;
     const int nv = 3 + c->S;
     LBIB_TRY(ensure_stage(c, 8));
-    LBIB_LAUNCH(c, launch_reduce(c, c->d_stage));
+    LBIB_LAUNCH(c, launch_reduce(c, c->d_partial, c->d_stage));
     LBIB_HIP(c, hipMemcpyAsync(out, c->d_stage, (size_t)nv * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
     for (int v = 0; v < nv; ++v)
@@ -1017,6 +1020,34 @@ lbib_status lbib_reduce(lbib_ctx* c, double* out)
             c->err = "non-finite lattice sum";
             return LBIB_ENUMERIC;
         }
+    return LBIB_OK;
+}
+
+lbib_status lbib_reduce_device(lbib_ctx* c, double* out_device)
+{
+    if (!c) return LBIB_ESTATE;
+    if (!out_device) {
+        c->err = "out_device is NULL";
+        return LBIB_EINVAL;
+    }
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, out_device) != hipSuccess || at.type != hipMemoryTypeDevice ||
+        at.device != c->device) {
+        (void)hipGetLastError();
+        c->err = "out_device is not device memory of the context's device";
+        return LBIB_EINVAL;
+    }
+    double* scratch = c->scratch_ok ? reduce_scratch_ptr(c->device) : nullptr;
+    if (!scratch) {
+        c->err = "the reduction scratch has no device address on this device";
+        return LBIB_EDEVICE;
+    }
+    if (reduce_blocks(c->nn) > reduce_scratch_blocks()) {
+        c->err = "the lattice needs more reduction blocks than the scratch holds";
+        return LBIB_EINVAL;
+    }
+    LBIB_TRY(join_batch(c));
+    LBIB_LAUNCH(c, launch_reduce(c, scratch, out_device));
     return LBIB_OK;
 }
 

@@ -17,6 +17,8 @@
 // The pass reads every population once and writes it once: it is HBM-bandwidth bound.
 #include "lbib_internal.h"
 
+#include <mutex>
+
 namespace lbib {
 
 // D2Q9 weights (Suppl. "Lattice Boltzmann Method": 4/9, 1/9 x4, 1/36 x4)
@@ -824,19 +826,66 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_partial(MomentArgs a, do
         for (int v = 0; v < nv; ++v) partial[(int64_t)blockIdx.x * RED_MAXV + v] = sh[v][0];
 }
 
-__global__ void k_reduce_final(const double* partial, int nblocks, int nv, double rho_total,
-                               double phi_tot0, double phi_tot1, double* out)
+// Final stage, one workgroup: thread t adds the partials of blocks t, t + RED_THREADS, ... in
+// that order, then a fixed LDS tree adds the threads' sums; the order depends on nblocks only,
+// so the result is the same from run to run.
+__global__ __launch_bounds__(RED_THREADS) void k_reduce_final(const double* partial, int nblocks, int nv,
+                                                              double rho_total, double phi_tot0, double phi_tot1,
+                                                              double* out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double sh[RED_MAXV][RED_THREADS];
     double acc[RED_MAXV] = {0, 0, 0, 0, 0};
-    for (int b = 0; b < nblocks; ++b)
+    for (int b = threadIdx.x; b < nblocks; b += RED_THREADS)
         for (int v = 0; v < nv; ++v) acc[v] += partial[(int64_t)b * RED_MAXV + v];
-    out[0] = rho_total + acc[0];
-    out[1] = acc[1];
-    out[2] = acc[2];
-    if (nv > 3) out[3] = phi_tot0 + acc[3];
-    if (nv > 4) out[4] = phi_tot1 + acc[4];
+    for (int v = 0; v < nv; ++v) sh[v][threadIdx.x] = acc[v];
+    __syncthreads();
+    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int v = 0; v < nv; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = rho_total + sh[0][0];
+        out[1] = sh[1][0];
+        out[2] = sh[2][0];
+        if (nv > 3) out[3] = phi_tot0 + sh[3][0];
+        if (nv > 4) out[4] = phi_tot1 + sh[4][0];
+    }
 }
+
+// Block partials of the sums for the entry point that allocates nothing: a file-scope array
+// each GPU holds once for the life of the process (REDUCE_SCRATCH_BLOCKS partials of RED_MAXV
+// doubles, 160 KiB).  Host code names it only through the device address that
+// hipGetSymbolAddress returns for the current device (reduce_scratch_ptr).
+constexpr int REDUCE_SCRATCH_BLOCKS = 4096;
+static __device__ __align__(256) double scratch[REDUCE_SCRATCH_BLOCKS * RED_MAXV];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_dev[SCRATCH_MAX_DEVICES] = {};
+}  // namespace
+
+hipError_t reduce_scratch_init(int device)
+{
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_dev[device]) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_dev[device] = (double*)ptr;
+    return hipSuccess;
+}
+
+double* reduce_scratch_ptr(int device)
+{
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    return scratch_dev[device];
+}
+
+int reduce_scratch_blocks() { return REDUCE_SCRATCH_BLOCKS; }
 
 // ---------------------------------------------------------------------------------------
 // launchers
@@ -1000,21 +1049,28 @@ hipError_t launch_moments(lbib_ctx* c, double* out)
     return hipGetLastError();
 }
 
-hipError_t launch_reduce(lbib_ctx* c, double* out_dev)
+// blocks of the partial stage for a lattice of nn nodes: 16 nodes per thread, at most
+// REDUCE_SCRATCH_BLOCKS (a grid-stride loop covers the rest)
+int reduce_blocks(int64_t nn)
+{
+    int64_t nb = (nn + RED_THREADS * 16 - 1) / (RED_THREADS * 16);
+    if (nb > REDUCE_SCRATCH_BLOCKS) nb = REDUCE_SCRATCH_BLOCKS;
+    return nb < 1 ? 1 : (int)nb;
+}
+
+hipError_t launch_reduce(lbib_ctx* c, double* partial, double* out_dev)
 {
     MomentArgs a = moment_args(c, nullptr);
-    int nblocks = (int)((c->nn + RED_THREADS * 16 - 1) / (RED_THREADS * 16));
-    if (nblocks > (int)c->partial_count) nblocks = (int)c->partial_count;
-    if (nblocks < 1) nblocks = 1;
+    const int nblocks = reduce_blocks(c->nn);
     switch (c->p.storage) {
     case LBIB_STORAGE_FP16:
-        hipLaunchKernelGGL(k_reduce_partial<1>, dim3(nblocks), dim3(RED_THREADS), 0, c->stream, a, c->d_partial);
+        hipLaunchKernelGGL(k_reduce_partial<1>, dim3(nblocks), dim3(RED_THREADS), 0, c->stream, a, partial);
         break;
     case LBIB_STORAGE_BF16:
-        hipLaunchKernelGGL(k_reduce_partial<2>, dim3(nblocks), dim3(RED_THREADS), 0, c->stream, a, c->d_partial);
+        hipLaunchKernelGGL(k_reduce_partial<2>, dim3(nblocks), dim3(RED_THREADS), 0, c->stream, a, partial);
         break;
     default:
-        hipLaunchKernelGGL(k_reduce_partial<0>, dim3(nblocks), dim3(RED_THREADS), 0, c->stream, a, c->d_partial);
+        hipLaunchKernelGGL(k_reduce_partial<0>, dim3(nblocks), dim3(RED_THREADS), 0, c->stream, a, partial);
         break;
     }
     hipError_t e = hipGetLastError();
@@ -1022,7 +1078,7 @@ hipError_t launch_reduce(lbib_ctx* c, double* out_dev)
     const double rho_total = c->p.rho0 * (double)c->nn;
     const double p0 = c->p.species[0].phi_ref * (double)c->nn;
     const double p1 = c->p.species[1].phi_ref * (double)c->nn;
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, c->stream, (const double*)c->d_partial, nblocks,
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, c->stream, (const double*)partial, nblocks,
                        3 + c->S, rho_total, p0, p1, out_dev);
     return hipGetLastError();
 }

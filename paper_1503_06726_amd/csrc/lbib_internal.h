@@ -82,6 +82,7 @@ struct lbib_ctx {
     size_t stage_bytes = 0;
     double* d_partial = nullptr;     // reduction partials
     size_t partial_count = 0;
+    bool scratch_ok = false;         // the static reduction scratch has an address on this device
 
     size_t device_bytes = 0;         // bytes the library allocated itself
 
@@ -134,7 +135,13 @@ hipError_t launch_spread_inspect(lbib_ctx* c, const LatticeArgs& a);
 hipError_t launch_init(lbib_ctx* c, const double* stage_rho, const double* stage_u, const double* stage_phi,
                        int has_rho, int has_u, int has_phi);
 hipError_t launch_moments(lbib_ctx* c, double* out);
-hipError_t launch_reduce(lbib_ctx* c, double* out_dev);
+hipError_t launch_reduce(lbib_ctx* c, double* partial, double* out_dev);   // partial: reduce_blocks(nn) x 5 doubles
+int reduce_blocks(int64_t nn);
+// the file-scope scratch of the reduction that allocates nothing (k_lattice.hip): its device
+// address on a device, resolved once per device by reduce_scratch_init (with that device current)
+hipError_t reduce_scratch_init(int device);
+double* reduce_scratch_ptr(int device);
+int reduce_scratch_blocks();
 hipError_t launch_membrane(lbib_ctx* c, const MembraneArgs& a);
 hipError_t launch_lists(lbib_ctx* c, const ListArgs& a, int which);   // 0 count, 1 scan, 2 fill
 // batched forms: one launch over (simulation, work unit) items named by device tables

@@ -34,7 +34,7 @@ EXPORTS = ["lbib_validate_params", "lbib_validate_cells", "lbib_create", "lbib_s
            "lbib_batch_create", "lbib_batch_step", "lbib_batch_sync", "lbib_batch_get_tile",
            "lbib_batch_set_tile", "lbib_batch_get_groups", "lbib_batch_set_groups", "lbib_batch_autotune",
            "lbib_batch_last_error", "lbib_batch_destroy",
-           "lbib_workspace_size", "lbib_bind_workspace", "lbib_workspace_nodes"]
+           "lbib_workspace_size", "lbib_bind_workspace", "lbib_workspace_nodes", "lbib_reduce_device"]
 
 
 class Species(C.Structure):
@@ -73,6 +73,14 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                            "(python -m paper_1503_06726_amd.build)")
+    # PyTorch ships its own copy of the HIP runtime under the same soname as the system one the
+    # library links; loading torch first makes the library bind to that copy, so that a process
+    # using both has one runtime (loaded the other way round, torch's device initialisation
+    # fails after the library's)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     vp, dp, ip = C.c_void_p, C.c_void_p, C.c_void_p
     P = C.POINTER(Params)
@@ -97,6 +105,8 @@ def lib():
     L.lbib_get_spread.argtypes = [vp, dp]
     L.lbib_reduce.restype = st
     L.lbib_reduce.argtypes = [vp, dp]
+    L.lbib_reduce_device.restype = st
+    L.lbib_reduce_device.argtypes = [vp, vp]
     L.lbib_sync.restype = st
     L.lbib_sync.argtypes = [vp]
     L.lbib_set_timing.restype = st
@@ -316,6 +326,12 @@ class Simulation:
         out = np.zeros(3 + self.S)
         self._check(self.L.lbib_reduce(self.h, _p(out)), "lbib_reduce")
         return out
+
+    def reduce_device(self, out_ptr: int):
+        """Enqueue the sums of ``reduce`` into device memory at ``out_ptr`` (3 + S doubles,
+        for instance a torch tensor's ``data_ptr()``) without allocating or synchronising
+        (lbib_reduce_device)."""
+        self._check(self.L.lbib_reduce_device(self.h, C.c_void_p(int(out_ptr))), "lbib_reduce_device")
 
     def set_source_cells(self, src=None):
         """Cells whose interior the source/decay law treats as a source (None: every cell)."""
