@@ -74,17 +74,26 @@ enum { LBIB_STORAGE_FP32 = 0, LBIB_STORAGE_FP16 = 1, LBIB_STORAGE_BF16 = 2 };
  * LBIB_SPECIES_NO_FLUX: the cell membranes are no-flux boundaries for the species (Section
  * "Signalling": compounds that exist only inside or only outside the cells; Suppl. "No-flux
  * Boundary Condition for Reaction-Advection-Diffusion Equations": missing populations are
- * replaced by equilibria).  A D2Q5 link crosses a membrane when one of its two nodes lies
- * inside a cell and the other does not (the inside-cell map of the step's positions).  A
- * population arriving across such a link is replaced by the equilibrium w_i phi_b at zero
- * velocity (the wall's), phi_b being the node's own concentration, solved from the
- * populations that did arrive: phi_b = sum_known g_j / (1 - sum_missing w_i).  This is the
- * zeroth-order form of the paper's condition (its first-order interpolation and
- * extrapolation need moments of nodes further inside).  Inside and outside then exchange
- * nothing: a concentration confined to one side stays there exactly.  Cells must keep at
- * least one lattice unit of extracellular space between them (two cells in contact share
- * the inside map).  Not with a source subset (lbib_set_source_cells), a batch, or
- * lbib_ade_steady (LBIB_EINVAL / LBIB_ESTATE). */
+ * replaced by equilibria, the momentum interpolated to first order between the fluid and zero
+ * at the wall, the density extrapolated to first order from the fluid).  By default the
+ * supplement's first-order condition: a D2Q5 link is blocked when a membrane edge cuts it (the
+ * crossing rule of the domain IDs, applied to rows for the horizontal links and to columns for
+ * the vertical ones); the cut nearest to the node puts the wall at a distance q in [0, 1] of
+ * the link.  A population arriving over a blocked link becomes w_i (phi_b + 3 v_i . j_b) with
+ *   j_b = q / (1 + q) phi(x + v_i) u(x + v_i)     (interpolated between the node one step on,
+ *                                                  in the population's direction, and the wall)
+ *   phi_b = 2 phi(x + v_i) - phi(x + 2 v_i)       (extrapolated from the two nodes on),
+ * taken from the previous step's collision (its concentration and fluid velocity); where the
+ * node two steps on lies beyond a wall or behind a cut link, phi_b = phi(x + v_i); where the
+ * node one step on does, phi_b = phi(x) of the previous step and j_b = 0.  Cells in contact are
+ * separated (a link between them is cut twice).  With no_flux_zeroth = 1 in lbib_params the
+ * zeroth-order form applies instead: a link crosses a membrane when one of its nodes lies inside
+ * a cell and the other does not (the inside-cell map of the step's positions), and the
+ * population becomes w_i phi_b at zero velocity, phi_b = sum_known g_j / (1 - sum_missing w_i)
+ * the node's own concentration; cells then need one lattice unit of extracellular space
+ * between them.  In both forms a concentration confined to one side stays there exactly.  Not
+ * with a source subset (lbib_set_source_cells), a batch, or lbib_ade_steady (LBIB_EINVAL /
+ * LBIB_ESTATE). */
 enum { LBIB_SPECIES_NO_FLUX = 1 };
 
 typedef struct {
@@ -128,6 +137,17 @@ typedef struct {
      * sums are those after the rescaling.  This is the mass sink that lets cells grow under
      * mass sources.  Not with a batch (LBIB_EINVAL). */
     int32_t pressure_ring;   /* 0 or 1 */
+    /* The velocity the membrane nodes move with (Eq. conversion2 applied to the fluid of
+     * Eq. bgkequation).  0 (default): u = sum f v / rho, the moments of the populations before
+     * the collision.  1: the half-force-shifted u + f/2, the mean of the momentum before and
+     * after the step's forcing term (f the spread membrane force plus the body acceleration);
+     * with it a membrane in static balance does not drift, and a circle under constant tension
+     * shrinks slowly by leakage, as in the paper's validation Case IV (with 0 it drifts outward
+     * by half the interpolated force density per step).  The fluid's collision, the species'
+     * advection and the reported velocity keep u = sum f v / rho either way.  Not with a batch
+     * (LBIB_EINVAL). */
+    int32_t interp_half_force;   /* 0 or 1 */
+    int32_t no_flux_zeroth;  /* 0: the first-order no-flux condition; 1: its zeroth-order form */
     int32_t reserved;        /* 0 */
 } lbib_params;
 

@@ -38,14 +38,31 @@
  *    R_0 = gamma (a - phi0 + phi0^2 phi1), R_1 = gamma (b - phi0^2 phi1).
  *    With a source subset (orc_set_source_cells), [m != 0] becomes "inside at least one
  *    source cell": the crossing test run over the source cells alone.
+ *  - Half-force velocity (option interp_half_force): the membrane nodes move with the
+ *    interpolated u + f/2, the mean of the momentum before and after the step's forcing,
+ *    instead of u; the fluid's collision and reported velocity keep u = sum f v / rho.
  *  - No-flux membranes (a species flag; Suppl. "No-flux Boundary Condition for
- *    Reaction-Advection-Diffusion Equations"), zeroth-order reading: the clauses of
- *    first-order interpolation and extrapolation are dropped; a population arriving
- *    across a membrane (the inside map [m != 0] of this step differs between the link's
- *    ends) becomes the zero-velocity equilibrium w_i phi_b, with phi_b the node's own
- *    concentration solved from the populations that did arrive.  Applied to the streamed
- *    populations before the moments of the step; the reported fields are the streamed
- *    populations' sums.
+ *    Reaction-Advection-Diffusion Equations").  A D2Q5 link is blocked when a membrane edge
+ *    crosses it; the crossing nearest to the node fixes the wall distance q in [0, 1] (as a
+ *    fraction of the link).  The population that would have arrived across a blocked link is
+ *    missing and becomes the equilibrium w_i (phi_b + 3 v_i . j_b) with
+ *      j_b = q / (1 + q) phi(x + v_i) u(x + v_i)        (momentum interpolated linearly
+ *            between the node one step on, in the direction of the missing population, and
+ *            zero at the wall),
+ *      phi_b = 2 phi(x + v_i) - phi(x + 2 v_i)          (density extrapolated linearly from
+ *            the two nodes on),
+ *    taking the moments of the previous step (the ones that step's collision saw), so that a
+ *    lattice pass needs nothing of its own step's neighbours.  Where x + 2 v_i is not reachable
+ *    (a wall, or a blocked link in between) phi_b = phi(x + v_i); where x + v_i is not,
+ *    phi_b = phi(x) and j_b = 0.  Crossings follow the domain-ID test: an edge (A, B) crosses
+ *    row y when (A.y > y) != (B.y > y) at x_c = A.x + (y - A.y)(B.x - A.x)/(B.y - A.y), which
+ *    cuts the link between columns ceil(x_c) - 1 and ceil(x_c); columns likewise with x and y
+ *    exchanged.  The zeroth-order form (option no_flux_zeroth) drops the interpolation and
+ *    extrapolation: a population arriving across a membrane (the inside map [m != 0] of this
+ *    step differs between the link's ends) becomes the zero-velocity equilibrium w_i phi_b,
+ *    with phi_b the node's own concentration solved from the populations that did arrive.
+ *    Either form is applied to the streamed populations before the moments of the step; the
+ *    reported fields are the sums after the replacement.
  *  - Mass sources and area control (Section "Control of Cell Area"; the supplement's
  *    parameter table makes the lattice source a density per node and step): every node
  *    of cell k in the domain map gains S_k = mass_source + area_alpha (A0_k - A_k) per
@@ -94,6 +111,9 @@ struct orc_ctx {
     int32_t *off;
     double *X, *F, *l0, *A0, *area;
     uint8_t *src;                 /* [n_cells] source cells of the source/decay law, NULL: all */
+    double *phi_prev;             /* [S][ny][nx] concentrations the previous collision saw */
+    double *ux_prev, *uy_prev;    /* velocity the previous collision used */
+    double *q;                    /* [4][ny][nx] wall distances of blocked links (first-order no-flux) */
 };
 
 static int64_t wrapi(int64_t i, int64_t n) { int64_t r = i % n; return r < 0 ? r + n : r; }
@@ -299,6 +319,64 @@ int64_t orc_raster(const orc_params* p, int32_t n_cells, const int32_t* off, con
     return overlaps;
 }
 
+/* Wall distances of the D2Q5 links crossed by membrane edges (Suppl. "No-flux Boundary
+ * Condition ..."; the crossings follow the domain-ID test of Section "Cell Representation").
+ * q[d][y][x], d = 0..3 for directions +x, +y, -x, -y, is the distance from node (x, y) to the
+ * nearest crossing on the link to its upstream neighbour (x, y) - v_{d+1}, as a fraction of the
+ * link, or +inf where no edge crosses that link.  An edge (A, B) crossing row y at x_c cuts the
+ * link between columns ceil(x_c) - 1 and ceil(x_c): the right node (population arriving in +x)
+ * is ceil(x_c) - x_c away, the left one (arriving in -x) x_c - ceil(x_c) + 1; columns likewise.
+ * Links to rows beyond a wall do not exist. */
+static void deposit(double* q, int64_t nn, int d, int64_t k, double v)
+{
+    if (v < q[d * nn + k]) q[d * nn + k] = v;
+}
+
+void orc_link_crossings(const orc_params* p, int32_t n_cells, const int32_t* off, const double* X,
+                        double* q)
+{
+    int64_t nx = p->nx, ny = p->ny, nn = nx * ny;
+    for (int64_t k = 0; k < 4 * nn; ++k) q[k] = INFINITY;
+    for (int32_t c = 0; c < n_cells; ++c) {
+        int64_t a = off[c], n = off[c + 1] - a;
+        for (int64_t k = 0; k < n; ++k) {
+            const double* A = &X[2 * (a + k)];
+            const double* B = &X[2 * (a + (k + 1) % n)];
+            /* rows y with (A.y > y) != (B.y > y): the horizontal links of row y */
+            int64_t lo = (int64_t)floor(fmin(A[1], B[1])), hi = (int64_t)floor(fmax(A[1], B[1]));
+            for (int64_t py = lo; py <= hi; ++py) {
+                double yy = (double)py;
+                if ((A[1] > yy) == (B[1] > yy)) continue;
+                int64_t j;
+                if (p->bc_y == ORC_WALLS) { if (py < 0 || py >= ny) continue; j = py; }
+                else j = wrapi(py, ny);
+                double xc = A[0] + (yy - A[1]) * (B[0] - A[0]) / (B[1] - A[1]);
+                int64_t ir = (int64_t)ceil(xc);
+                deposit(q, nn, 0, j * nx + wrapi(ir, nx), (double)ir - xc);
+                deposit(q, nn, 2, j * nx + wrapi(ir - 1, nx), xc - (double)(ir - 1));
+            }
+            /* columns x with (A.x > x) != (B.x > x): the vertical links of column x */
+            lo = (int64_t)floor(fmin(A[0], B[0]));
+            hi = (int64_t)floor(fmax(A[0], B[0]));
+            for (int64_t px = lo; px <= hi; ++px) {
+                double xx = (double)px;
+                if ((A[0] > xx) == (B[0] > xx)) continue;
+                double yc = A[1] + (xx - A[0]) * (B[1] - A[1]) / (B[0] - A[0]);
+                int64_t jt = (int64_t)ceil(yc), i = wrapi(px, nx);
+                if (p->bc_y == ORC_WALLS) {
+                    if (jt >= 1 && jt < ny) {   /* both rows jt - 1 and jt inside the lattice */
+                        deposit(q, nn, 1, jt * nx + i, (double)jt - yc);
+                        deposit(q, nn, 3, (jt - 1) * nx + i, yc - (double)(jt - 1));
+                    }
+                } else {
+                    deposit(q, nn, 1, wrapi(jt, ny) * nx + i, (double)jt - yc);
+                    deposit(q, nn, 3, wrapi(jt - 1, ny) * nx + i, yc - (double)(jt - 1));
+                }
+            }
+        }
+    }
+}
+
 /* ------------------------------------------------------------------------------------
  * simulation context
  * ---------------------------------------------------------------------------------- */
@@ -319,6 +397,11 @@ orc_ctx* orc_create(const orc_params* p)
     c->ex = (double*)calloc(nn, sizeof(double));
     c->ey = (double*)calloc(nn, sizeof(double));
     c->mask = (int32_t*)calloc(nn, sizeof(int32_t));
+    c->phi_prev = (double*)calloc((size_t)(S > 0 ? S : 1) * nn, sizeof(double));
+    c->ux_prev = (double*)calloc(nn, sizeof(double));
+    c->uy_prev = (double*)calloc(nn, sizeof(double));
+    c->q = (double*)malloc(sizeof(double) * 4 * nn);
+    for (size_t k = 0; k < 4 * nn; ++k) c->q[k] = INFINITY;
     orc_set_fields(c, NULL, NULL, NULL);
     return c;
 }
@@ -330,6 +413,7 @@ void orc_destroy(orc_ctx* c)
     free(c->rho); free(c->ux); free(c->uy); free(c->ex); free(c->ey); free(c->mask);
     free(c->off); free(c->X); free(c->F); free(c->l0); free(c->A0); free(c->area);
     free(c->src);
+    free(c->phi_prev); free(c->ux_prev); free(c->uy_prev); free(c->q);
     free(c);
 }
 
@@ -364,6 +448,27 @@ int32_t orc_set_cells(orc_ctx* c, int32_t n_cells, const int32_t* off, const dou
     return 0;
 }
 
+/* The "previous step" moments of a state set from outside (initial fields, populations): the
+ * sums of its populations. */
+static void prev_from_populations(orc_ctx* c)
+{
+    int64_t nn = c->nn;
+    for (int64_t x = 0; x < nn; ++x) {
+        double r = 0.0, jx = 0.0, jy = 0.0;
+        for (int i = 0; i < 9; ++i) {
+            double fi = c->f[i * nn + x];
+            r += fi; jx += fi * VX[i]; jy += fi * VY[i];
+        }
+        c->ux_prev[x] = jx / r;
+        c->uy_prev[x] = jy / r;
+        for (int s = 0; s < c->p.n_species; ++s) {
+            double sum = 0.0;
+            for (int i = 0; i < 5; ++i) sum += c->g[(s * 5 + i) * nn + x];
+            c->phi_prev[s * nn + x] = sum;
+        }
+    }
+}
+
 /* Equilibrium initial state: f = f^eq(rho, u), g_s = g^eq(phi_s, u).  NULL fields take
  * rho0, zero velocity and zero concentration. */
 void orc_set_fields(orc_ctx* c, const double* rho, const double* u, const double* phi)
@@ -380,6 +485,7 @@ void orc_set_fields(orc_ctx* c, const double* rho, const double* u, const double
             for (int i = 0; i < 5; ++i) c->g[(s * 5 + i) * nn + x] = e5[i];
         }
     }
+    prev_from_populations(c);
 }
 
 void orc_set_source_cells(orc_ctx* c, const uint8_t* src)
@@ -428,8 +534,15 @@ void orc_source_map(orc_ctx* c, int32_t* out)
 static int needs_mask(const orc_params* p)
 {
     for (int s = 0; s < p->n_species; ++s)
-        if (p->reaction[s] == ORC_REACT_SOURCE_DECAY || p->no_flux[s]) return 1;
+        if (p->reaction[s] == ORC_REACT_SOURCE_DECAY || (p->no_flux[s] && p->no_flux_zeroth)) return 1;
     return p->mass_source != 0.0 || p->area_alpha != 0.0;
+}
+
+static int any_no_flux(const orc_params* p)
+{
+    int nf = 0;
+    for (int s = 0; s < p->n_species; ++s) nf |= p->no_flux[s];
+    return nf;
 }
 
 /* No-flux membranes for a species (Section "Signalling"; Suppl. "No-flux Boundary Condition
@@ -463,6 +576,54 @@ static void no_flux_replace(orc_ctx* c, const int32_t* m, double* g)
                 double phib = known / (1.0 - wm);
                 for (int i = 1; i < 5; ++i)
                     if (miss[i]) g[(s * 5 + i) * nn + k] = W5[i] * phib;
+            }
+    }
+}
+
+/* No-flux membranes, the supplement's first-order condition (see the readings above): every
+ * population whose link is blocked (q finite) becomes w_i (phi_b + 3 v_i . j_b), from the wall
+ * distance q and the previous step's moments of the nodes one and two steps on along v_i.
+ * out receives, per species s and direction i, the replacement value (or leaves g alone when
+ * out is NULL and writes into g). */
+static void no_flux_first(orc_ctx* c, const double* q, double* g, int only_s, double* out)
+{
+    const orc_params* p = &c->p;
+    int64_t nx = p->nx, ny = p->ny, nn = c->nn;
+    for (int s = 0; s < p->n_species; ++s) {
+        if (!p->no_flux[s] || (only_s >= 0 && s != only_s)) continue;
+        const double* ph = c->phi_prev + s * nn;
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x) {
+                int64_t k = y * nx + x;
+                for (int i = 1; i < 5; ++i) {
+                    double qq = q[(i - 1) * nn + k];
+                    if (qq == INFINITY) continue;
+                    /* the nodes one and two steps on in the direction of the missing population,
+                     * each reachable when it lies inside the lattice and no membrane blocks the
+                     * link leading to it */
+                    int64_t y1 = y + VY[i], y2 = y + 2 * VY[i];
+                    int ok1 = 1, ok2 = 1;
+                    if (p->bc_y == ORC_WALLS) {
+                        if (y1 < 0 || y1 >= ny) ok1 = 0;
+                        if (y2 < 0 || y2 >= ny) ok2 = 0;
+                    }
+                    int64_t k1 = ok1 ? wrapi(y1, ny) * nx + wrapi(x + VX[i], nx) : k;
+                    int64_t k2 = ok2 ? wrapi(y2, ny) * nx + wrapi(x + 2 * VX[i], nx) : k;
+                    if (ok1 && q[(i - 1) * nn + k1] != INFINITY) ok1 = 0;
+                    if (!ok1 || q[(i - 1) * nn + k2] != INFINITY) ok2 = 0;
+                    double phib, jbx = 0.0, jby = 0.0;
+                    if (!ok1) {
+                        phib = ph[k];
+                    } else {
+                        double w = qq / (1.0 + qq);
+                        jbx = w * ph[k1] * c->ux_prev[k1];
+                        jby = w * ph[k1] * c->uy_prev[k1];
+                        phib = ok2 ? 2.0 * ph[k1] - ph[k2] : ph[k1];
+                    }
+                    double v = W5[i] * (phib + (VX[i] * jbx + VY[i] * jby) / CS2);
+                    if (out) out[(i - 1) * nn + k] = v;
+                    else g[(s * 5 + i) * nn + k] = v;
+                }
             }
     }
 }
@@ -534,7 +695,14 @@ static void step_once(orc_ctx* c)
      * arrived across a no-flux membrane are replaced before the moments */
     if (needs_mask(p)) source_map(c, c->mask);
     else memset(c->mask, 0, sizeof(int32_t) * (size_t)nn);
-    no_flux_replace(c, c->mask, c->g);
+    if (any_no_flux(p) && c->n_cells > 0) {
+        if (p->no_flux_zeroth) {
+            no_flux_replace(c, c->mask, c->g);
+        } else {
+            orc_link_crossings(p, c->n_cells, c->off, c->X, c->q);
+            no_flux_first(c, c->q, c->g, -1, NULL);
+        }
+    }
 
     /* the cell of every node for the mass sources: the domain map, or, when a source subset
      * narrowed that map, the crossing test over all cells */
@@ -571,7 +739,10 @@ static void step_once(orc_ctx* c)
             double sum = 0.0;
             for (int i = 0; i < 5; ++i) sum += c->g[(s * 5 + i) * nn + x];
             phi[s] = sum;
+            c->phi_prev[s * nn + x] = sum;      /* read by the next step's no-flux replacement */
         }
+        c->ux_prev[x] = vx;
+        c->uy_prev[x] = vy;
         for (int s = 0; s < S; ++s) R[s] = orc_reaction(p, s, phi, c->mask[x]);
         for (int s = 0; s < S; ++s) {
             orc_equilibrium5(phi[s], vx, vy, geq);
@@ -628,6 +799,16 @@ static void step_once(orc_ctx* c)
             orc_interp(p, c->n_nodes, c->X, c->ux, c->uy, U);
             c->rho = r2; c->ux = x2; c->uy = y2;
             free(tmp);
+        } else if (p->interp_half_force) {
+            /* the half-force-shifted velocity u + f/2: the mean of the momentum before and
+             * after the forcing term of this step (f the spread and body acceleration) */
+            double* sh = (double*)malloc(sizeof(double) * 2 * (size_t)nn);
+            for (int64_t x = 0; x < nn; ++x) {
+                sh[x] = c->ux[x] + 0.5 * c->ex[x];
+                sh[nn + x] = c->uy[x] + 0.5 * c->ey[x];
+            }
+            orc_interp(p, c->n_nodes, c->X, sh, sh + nn, U);
+            free(sh);
         } else {
             orc_interp(p, c->n_nodes, c->X, c->ux, c->uy, U);
         }
@@ -720,12 +901,19 @@ void orc_get_fields(orc_ctx* c, double* rho, double* u, double* phi, double* X, 
     for (int s = 0; s < c->p.n_species; ++s) nf |= c->p.no_flux[s];
     if (phi && nf && c->n_cells > 0) {
         size_t bytes = sizeof(double) * 5 * (size_t)c->p.n_species * (size_t)nn;
-        int32_t* m = (int32_t*)malloc(sizeof(int32_t) * (size_t)nn);
         g = (double*)malloc(bytes);
         memcpy(g, c->g, bytes);
-        source_map(c, m);
-        no_flux_replace(c, m, g);
-        free(m);
+        if (c->p.no_flux_zeroth) {
+            int32_t* m = (int32_t*)malloc(sizeof(int32_t) * (size_t)nn);
+            source_map(c, m);
+            no_flux_replace(c, m, g);
+            free(m);
+        } else {
+            double* q = (double*)malloc(sizeof(double) * 4 * (size_t)nn);
+            orc_link_crossings(&c->p, c->n_cells, c->off, c->X, q);
+            no_flux_first(c, q, g, -1, NULL);
+            free(q);
+        }
     }
     for (int64_t x = 0; x < nn; ++x) {
         double r = 0.0, jx = 0.0, jy = 0.0;
@@ -763,6 +951,38 @@ void orc_set_populations(orc_ctx* c, const double* f, const double* g)
 {
     if (f) memcpy(c->f, f, sizeof(double) * 9 * (size_t)c->nn);
     if (g && c->p.n_species) memcpy(c->g, g, sizeof(double) * 5 * (size_t)c->p.n_species * (size_t)c->nn);
+    prev_from_populations(c);
+}
+
+void orc_get_prev_moments(const orc_ctx* c, double* phi, double* u)
+{
+    int64_t nn = c->nn;
+    if (phi && c->p.n_species) memcpy(phi, c->phi_prev, sizeof(double) * (size_t)c->p.n_species * (size_t)nn);
+    if (u) {
+        memcpy(u, c->ux_prev, sizeof(double) * (size_t)nn);
+        memcpy(u + nn, c->uy_prev, sizeof(double) * (size_t)nn);
+    }
+}
+
+void orc_set_prev_moments(orc_ctx* c, const double* phi, const double* u)
+{
+    int64_t nn = c->nn;
+    if (phi && c->p.n_species) memcpy(c->phi_prev, phi, sizeof(double) * (size_t)c->p.n_species * (size_t)nn);
+    if (u) {
+        memcpy(c->ux_prev, u, sizeof(double) * (size_t)nn);
+        memcpy(c->uy_prev, u + nn, sizeof(double) * (size_t)nn);
+    }
+}
+
+void orc_no_flux_values(orc_ctx* c, int32_t s, double* out)
+{
+    int64_t nn = c->nn;
+    for (int64_t k = 0; k < 4 * nn; ++k) out[k] = NAN;
+    if (c->n_cells == 0 || s < 0 || s >= c->p.n_species || !c->p.no_flux[s]) return;
+    double* q = (double*)malloc(sizeof(double) * 4 * (size_t)nn);
+    orc_link_crossings(&c->p, c->n_cells, c->off, c->X, q);
+    no_flux_first(c, q, c->g, s, out);
+    free(q);
 }
 
 void orc_get_last_spread(const orc_ctx* c, double* ex, double* ey)

@@ -58,6 +58,8 @@ typedef struct {
     double mass_source;          /* constant mass source per node inside a cell and step */
     double area_alpha;           /* area controller: S_k = mass_source + area_alpha (A0_k - A_k) */
     int32_t pressure_ring;       /* 1: the lattice's outer ring is a pressure boundary at rho0 */
+    int32_t interp_half_force;   /* 1: interpolate u + f/2 (the half-force-shifted velocity) */
+    int32_t no_flux_zeroth;      /* 1: the zeroth-order form of the no-flux condition */
     int32_t reserved;
 } orc_params;
 
@@ -76,6 +78,8 @@ void   orc_interp(const orc_params* p, int64_t n, const double* X, const double*
                   const double* uy, double* U);
 int64_t orc_raster(const orc_params* p, int32_t n_cells, const int32_t* off, const double* X,
                    int32_t* mask);
+void   orc_link_crossings(const orc_params* p, int32_t n_cells, const int32_t* off, const double* X,
+                          double* q);                       /* [4][ny][nx] wall distances, +inf: none */
 
 /* a whole simulation */
 orc_ctx* orc_create(const orc_params* p);
@@ -93,6 +97,12 @@ void     orc_set_populations(orc_ctx* c, const double* f, const double* g);
 void     orc_get_last_spread(const orc_ctx* c, double* ex, double* ey);
 void     orc_get_forces(orc_ctx* c, double* F, double* area);
 void     orc_invariants(const orc_ctx* c, double* out);   /* sum rho, sum rho*ux, sum rho*uy, sum phi_s */
+/* no-flux membranes, first-order form: the moments of the previous step the replacement reads
+ * ([S][ny][nx] concentrations, [2][ny][nx] velocity), and the replacement populations the
+ * current state would receive ([4][ny][nx] for directions 1..4, NaN where none is missing) */
+void     orc_get_prev_moments(const orc_ctx* c, double* phi, double* u);
+void     orc_set_prev_moments(orc_ctx* c, const double* phi, const double* u);
+void     orc_no_flux_values(orc_ctx* c, int32_t s, double* out);
 int32_t  orc_threads(void);                               /* OpenMP threads the lattice loops use */
 
 #ifdef __cplusplus

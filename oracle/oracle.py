@@ -41,7 +41,8 @@ class Params(C.Structure):
                 ("D", C.c_double * 2), ("reaction", C.c_int32 * 2),
                 ("rc", (C.c_double * 4) * 2), ("wall_u_top", C.c_double), ("no_flux", C.c_int32 * 2),
                 ("mass_source", C.c_double), ("area_alpha", C.c_double),
-                ("pressure_ring", C.c_int32), ("reserved", C.c_int32)]
+                ("pressure_ring", C.c_int32), ("interp_half_force", C.c_int32),
+                ("no_flux_zeroth", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -87,6 +88,10 @@ def lib():
     L.orc_get_last_spread.argtypes = [C.c_void_p, dp, dp]
     L.orc_get_forces.argtypes = [C.c_void_p, dp, dp]
     L.orc_invariants.argtypes = [C.c_void_p, dp]
+    L.orc_link_crossings.argtypes = [P, C.c_int32, ip, dp, dp]
+    L.orc_get_prev_moments.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_set_prev_moments.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_no_flux_values.argtypes = [C.c_void_p, C.c_int32, dp]
     L.orc_threads.restype = C.c_int32
     L.orc_threads.argtypes = []
     _lib = L
@@ -121,6 +126,8 @@ def make_params(d: dict, interp_new_u: bool = False, wall_u_top: float = 0.0) ->
     p.mass_source = float(d.get("mass_source", 0.0))
     p.area_alpha = float(d.get("area_alpha", 0.0))
     p.pressure_ring = int(bool(d.get("pressure_ring", False)))
+    p.interp_half_force = int(bool(d.get("interp_half_force", False)))
+    p.no_flux_zeroth = int(bool(d.get("no_flux_zeroth", False)))
     return p
 
 
@@ -179,6 +186,16 @@ def raster(params: dict, offsets, xy):
     ov = lib().orc_raster(C.byref(p), len(offsets) - 1, np.ascontiguousarray(offsets, np.int32),
                           np.ascontiguousarray(xy, np.float64).reshape(-1, 2), m)
     return m, int(ov)
+
+
+def link_crossings(params: dict, offsets, xy):
+    """[4, ny, nx] wall distances of the links crossed by membrane edges, for the populations
+    arriving in +x, +y, -x, -y; +inf where no edge crosses the link."""
+    p = make_params(params)
+    q = np.zeros((4, p.ny, p.nx))
+    lib().orc_link_crossings(C.byref(p), len(offsets) - 1, np.ascontiguousarray(offsets, np.int32),
+                             np.ascontiguousarray(xy, np.float64).reshape(-1, 2), q)
+    return q
 
 
 class Sim:
@@ -265,6 +282,25 @@ class Sim:
         ff = None if f is None else np.ascontiguousarray(f, np.float64)
         gg = None if g is None else np.ascontiguousarray(g, np.float64)
         self.L.orc_set_populations(self.h, _ptr(ff), _ptr(gg))
+
+    def prev_moments(self):
+        """(phi [S, ny, nx], u [2, ny, nx]) of the previous step, read by the no-flux
+        replacement."""
+        phi = np.zeros((max(self.S, 1), self.ny, self.nx)); u = np.zeros((2, self.ny, self.nx))
+        self.L.orc_get_prev_moments(self.h, _ptr(phi), _ptr(u))
+        return phi[:self.S], u
+
+    def set_prev_moments(self, phi=None, u=None):
+        ph = None if phi is None else np.ascontiguousarray(phi, np.float64)
+        uu = None if u is None else np.ascontiguousarray(u, np.float64)
+        self.L.orc_set_prev_moments(self.h, _ptr(ph), _ptr(uu))
+
+    def no_flux_values(self, s: int = 0):
+        """[4, ny, nx] populations the first-order no-flux condition gives the current state in
+        directions +x, +y, -x, -y (NaN where no population is missing)."""
+        out = np.zeros((4, self.ny, self.nx))
+        self.L.orc_no_flux_values(self.h, int(s), out)
+        return out
 
     def last_spread(self):
         ex = np.zeros((self.ny, self.nx)); ey = np.zeros((self.ny, self.nx))

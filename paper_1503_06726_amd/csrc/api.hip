@@ -168,6 +168,14 @@ LatticeArgs lattice_args_at(lbib_ctx* c, int cur)
     a.msrc = p.mass_source;
     a.alpha = p.area_alpha;
     a.pring = p.pressure_ring;
+    if (a.noflux && c->nfq[0]) {
+        a.nfq = c->nfq[cur];
+        a.nfm = c->nfm[cur];
+        a.nfphi = c->nfphi[cur];
+        a.nfu = c->nfu[cur];
+        a.nfphi_out = c->nfphi[1 - cur];
+        a.nfu_out = c->nfu[1 - cur];
+    }
     a.e_out = nullptr;
     return a;
 }
@@ -202,6 +210,12 @@ MembraneArgs membrane_args_at(lbib_ctx* c, int cur, int advect)
     a.kappa = c->p.kappa_area;
     a.advect = advect;
     a.raster = c->mask_needed ? 1 : 0;
+    if (c->nfq[0]) {
+        a.nfq = c->nfq[cur];
+        a.nfm = (unsigned*)c->nfm[cur];
+        a.nfq_old = c->nfq[1 - cur];
+        a.nfm_old = c->nfm[1 - cur];
+    }
     return a;
 }
 
@@ -358,6 +372,12 @@ void free_all(lbib_ctx* c)
     }
     for (int b = 0; b < 2; ++b) state_free(c, c->inside[b], (size_t)c->ny_words());
     state_free(c, c->cmap, (size_t)c->nn);
+    for (int b = 0; b < 2; ++b) {
+        state_free(c, c->nfq[b], 4 * (size_t)c->nn);
+        state_free(c, c->nfm[b], c->nfm_bytes());
+        state_free(c, c->nfphi[b], (size_t)c->S * (size_t)c->nn);
+        state_free(c, c->nfu[b], (size_t)c->nn);
+    }
     state_free(c, c->d_t_count, (size_t)c->tile_cap);
     state_free(c, c->d_t_off, (size_t)c->tile_cap + 1);
     state_free(c, c->d_t_cur, (size_t)c->tile_cap);
@@ -382,7 +402,9 @@ void free_all(lbib_ctx* c)
 // at most N nodes).
 // -------------------------------------------------------------------------------------
 enum Piece {
-    PC_F0, PC_F1, PC_G0, PC_G1, PC_IN0, PC_IN1, PC_CMAP, PC_TCOUNT, PC_TOFF, PC_TCUR, PC_ERR, PC_PARTIAL, PC_STAGE,
+    PC_F0, PC_F1, PC_G0, PC_G1, PC_IN0, PC_IN1, PC_CMAP,
+    PC_NFQ0, PC_NFQ1, PC_NFM0, PC_NFM1, PC_NFPHI0, PC_NFPHI1, PC_NFU0, PC_NFU1,
+    PC_TCOUNT, PC_TOFF, PC_TCUR, PC_ERR, PC_PARTIAL, PC_STAGE,
     PC_OFF, PC_X, PC_L0, PC_A0, PC_AREA, PC_IJ, PC_PART, PC_CNT, PC_REC, PC_RECIJ, PC_LIST, PC_SRC,
     PC_COUNT
 };
@@ -419,6 +441,11 @@ void piece_bytes(const lbib_ctx& c, int64_t n_nodes, int64_t n_cells, size_t sta
     b[PC_G0] = b[PC_G1] = c.S ? c.g_elems() * c.pop_bytes : 0;
     b[PC_IN0] = b[PC_IN1] = (size_t)c.ny_words() * sizeof(unsigned);
     b[PC_CMAP] = mass_sources(c.p) ? (size_t)c.nn * sizeof(unsigned) : 0;
+    const bool nf1 = no_flux_first(c.p);
+    b[PC_NFQ0] = b[PC_NFQ1] = nf1 ? 4 * (size_t)c.nn * sizeof(float) : 0;
+    b[PC_NFM0] = b[PC_NFM1] = nf1 ? c.nfm_bytes() : 0;
+    b[PC_NFPHI0] = b[PC_NFPHI1] = nf1 ? (size_t)c.S * (size_t)c.nn * sizeof(float) : 0;
+    b[PC_NFU0] = b[PC_NFU1] = nf1 ? (size_t)c.nn * sizeof(float2) : 0;
     b[PC_TCOUNT] = b[PC_TCUR] = (size_t)c.tile_cap * sizeof(int);
     b[PC_TOFF] = ((size_t)c.tile_cap + 1) * sizeof(int);
     b[PC_ERR] = sizeof(int);
@@ -446,6 +473,14 @@ void** piece_slot(lbib_ctx* c, int i)
     case PC_IN0: return reinterpret_cast<void**>(&c->inside[0]);
     case PC_IN1: return reinterpret_cast<void**>(&c->inside[1]);
     case PC_CMAP: return reinterpret_cast<void**>(&c->cmap);
+    case PC_NFQ0: return reinterpret_cast<void**>(&c->nfq[0]);
+    case PC_NFQ1: return reinterpret_cast<void**>(&c->nfq[1]);
+    case PC_NFM0: return reinterpret_cast<void**>(&c->nfm[0]);
+    case PC_NFM1: return reinterpret_cast<void**>(&c->nfm[1]);
+    case PC_NFPHI0: return reinterpret_cast<void**>(&c->nfphi[0]);
+    case PC_NFPHI1: return reinterpret_cast<void**>(&c->nfphi[1]);
+    case PC_NFU0: return reinterpret_cast<void**>(&c->nfu[0]);
+    case PC_NFU1: return reinterpret_cast<void**>(&c->nfu[1]);
     case PC_TCOUNT: return reinterpret_cast<void**>(&c->d_t_count);
     case PC_TOFF: return reinterpret_cast<void**>(&c->d_t_off);
     case PC_TCUR: return reinterpret_cast<void**>(&c->d_t_cur);
@@ -603,6 +638,15 @@ bool any_source_decay(const lbib_params& p)
     for (int s = 0; s < p.n_species; ++s)
         if (p.species[s].reaction == LBIB_REACT_SOURCE_DECAY) return true;
     return false;
+}
+
+// no-flux membranes, first-order form: no link of buffer b cut (wall distances +inf)
+lbib_status clear_cuts(lbib_ctx* c, int b)
+{
+    if (!c->nfq[b]) return LBIB_OK;
+    LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->nfq[b], 4 * c->nn, 0x7F800000));
+    LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->nfm[b], (int64_t)(c->nfm_bytes() / 4), 0));
+    return LBIB_OK;
 }
 
 lbib_status init_fields(lbib_ctx* c, const double* rho, const double* u, const double* phi)
@@ -779,6 +823,14 @@ lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out)
         s = dev_alloc(c, &c->cmap, (size_t)c->nn);
         if (s == LBIB_OK && launch_fill_i32(c, (int*)c->cmap, c->nn, -1) != hipSuccess) s = LBIB_EDEVICE;
     }
+    if (s == LBIB_OK && no_flux_first(c->p))
+        for (int b = 0; b < 2 && s == LBIB_OK; ++b) {
+            s = dev_alloc(c, &c->nfq[b], 4 * (size_t)c->nn);
+            if (s == LBIB_OK) s = dev_alloc(c, &c->nfm[b], c->nfm_bytes());
+            if (s == LBIB_OK) s = dev_alloc(c, &c->nfphi[b], (size_t)c->S * (size_t)c->nn);
+            if (s == LBIB_OK) s = dev_alloc(c, &c->nfu[b], (size_t)c->nn);
+            if (s == LBIB_OK) s = clear_cuts(c, b);
+        }
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_count, (size_t)c->tile_cap);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_off, (size_t)c->tile_cap + 1);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_cur, (size_t)c->tile_cap);
@@ -867,7 +919,8 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
     }
     c->max_cell_nodes = max_n;
     // the step keeps the inside map (and, with mass sources, the cell map)
-    c->mask_needed = any_source_decay(c->p) || no_flux_bits(c->p) != 0 || mass_sources(c->p);
+    c->mask_needed = any_source_decay(c->p) || (no_flux_bits(c->p) != 0 && c->p.no_flux_zeroth) ||
+                     mass_sources(c->p);
     LBIB_HIP(c, hipMemcpyAsync(c->d_off, off, (C + 1) * sizeof(int), hipMemcpyHostToDevice, c->stream));
     LBIB_HIP(c, hipMemcpyAsync(c->d_X, xy, N * sizeof(double2), hipMemcpyHostToDevice, c->stream));
     LBIB_HIP(c, hipMemcpyAsync(c->d_l0, l0.data(), N * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -877,6 +930,7 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
     if (c->mask_needed)
         for (int b = 0; b < 2; ++b) LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->inside[b], c->ny_words(), 0));
     if (c->cmap) LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->cmap, c->nn, -1));   // claims of earlier cells
+    for (int b = 0; b < 2; ++b) LBIB_TRY(clear_cuts(c, b));                     // cuts of earlier cells
     LBIB_TRY(build_lists(c));
     LBIB_TRY(membrane(c, 0));
     LBIB_HIP(c, hipStreamSynchronize(c->stream));

@@ -395,6 +395,10 @@ lbib_status lbib_batch_create(lbib_ctx* const* sims, int32_t n, void* hip_stream
             c->err = "the batched pass has no mass sources or pressure boundaries";
             return LBIB_EINVAL;
         }
+        if (c->p.interp_half_force) {
+            c->err = "the batched pass interpolates u, not the half-force-shifted velocity";
+            return LBIB_EINVAL;
+        }
     }
     lbib_batch* b = new (std::nothrow) lbib_batch();
     if (!b) return LBIB_ENOMEM;

@@ -247,7 +247,7 @@ __device__ inline int64_t share_slot(const LatticeArgs& a, int e)
 // The caller stores the shares by node and tile rank; DEFER leaves that to after the tile's
 // population stores, because a workgroup barrier waits for every outstanding global memory
 // operation and the shares are not needed before the end.
-template <bool INTERP, bool DEFER = false>
+template <bool INTERP, bool DEFER = false, bool SPREAD = true>
 __device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0, int y1,
                                     const int ij[SPREAD_UNROLL], const float4 rc[SPREAD_UNROLL],
                                     const int ent[SPREAD_UNROLL], unsigned long long* accx, unsigned long long* accy,
@@ -280,7 +280,11 @@ __device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0
         float wx[4], wy[4];
         delta_weights(a.kernel, r.x, wx);
         delta_weights(a.kernel, r.y, wy);
-        const FixedForce fx = fixed_force(r.z), fy = fixed_force(r.w);
+        FixedForce fx{0, 0u}, fy{0, 0u};
+        if constexpr (SPREAD) {
+            fx = fixed_force(r.z);
+            fy = fixed_force(r.w);
+        }
         float Ux = 0.0f, Uy = 0.0f;
 #pragma unroll
         for (int bb = 0; bb < 4; ++bb) {
@@ -294,9 +298,11 @@ __device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0
                 const int o = ly[bb] * LDS_ROW + (in ? lx[aa] : 0);
                 float2 uv;
                 if constexpr (INTERP) uv = us[o];          // read first: the atomics need not wait for it
-                const unsigned wq = in ? (unsigned)(wx[aa] * wy[bb] * WQ_SCALE) : 0u;
-                atomicAdd(&accx[o], weighted_fixed(fx, wq));
-                atomicAdd(&accy[o], weighted_fixed(fy, wq));
+                if constexpr (SPREAD) {
+                    const unsigned wq = in ? (unsigned)(wx[aa] * wy[bb] * WQ_SCALE) : 0u;
+                    atomicAdd(&accx[o], weighted_fixed(fx, wq));
+                    atomicAdd(&accy[o], weighted_fixed(fy, wq));
+                }
                 if constexpr (INTERP) {
                     sx += in ? wx[aa] * uv.x : 0.0f;
                     sy += in ? wx[aa] * uv.y : 0.0f;
@@ -316,11 +322,58 @@ __device__ inline void couple_chunk(const LatticeArgs& a, int x0, int x1, int y0
     }
 }
 
+// No-flux membranes, the supplement's first-order condition, at node (x, y) for one species:
+// every population whose link a membrane edge cuts (bit d of the node's byte mk; d = 0..3 for
+// +x, +y, -x, -y) is replaced by the equilibrium w (phi_b + 3 v . j_b), in deviations
+// w (dphi_b + 3 v . j_b), with the momentum j_b interpolated between the node one step on in
+// the population's direction and zero at the wall, j_b = q / (1 + q) phi_1 u_1 (q the wall
+// distance as a fraction of the link), and the density extrapolated linearly from the nodes one
+// and two steps on, dphi_b = 2 dphi_1 - dphi_2.  The values are those of the previous step's
+// collision (planes written by the previous pass).  A node two steps on that lies beyond a wall
+// or behind a cut link gives dphi_b = dphi_1; a node one step on that does, dphi_b = the node's
+// own dphi and j_b = 0.
+template <typename Args>
+__device__ inline void nf_first_replace(const Args& a, int s, int x, int y, unsigned mk, float g[5])
+{
+    const int64_t k = (int64_t)y * a.nx + x;
+    const float* __restrict__ ph = a.nfphi + (int64_t)s * a.nn;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        if (!((mk >> d) & 1u)) continue;
+        const int vx = (d == 0) ? 1 : (d == 2) ? -1 : 0;
+        const int vy = (d == 1) ? 1 : (d == 3) ? -1 : 0;
+        int y1 = y + vy, y2 = y + 2 * vy;
+        bool ok1 = true, ok2 = true;
+        if (a.walls) {
+            ok1 = y1 >= 0 && y1 < a.ny;
+            ok2 = y2 >= 0 && y2 < a.ny;
+        } else {
+            y1 = wrap_i(y1, a.ny);
+            y2 = wrap_i(y2, a.ny);
+        }
+        const int64_t k1 = ok1 ? (int64_t)y1 * a.nx + wrap_i(x + vx, a.nx) : k;
+        const int64_t k2 = ok2 ? (int64_t)y2 * a.nx + wrap_i(x + 2 * vx, a.nx) : k;
+        if (ok1 && ((a.nfm[k1] >> d) & 1u)) ok1 = false;
+        if (!ok1 || ((a.nfm[k2] >> d) & 1u)) ok2 = false;
+        float db, jv = 0.0f;
+        if (!ok1) {
+            db = ph[k];
+        } else {
+            const float q = a.nfq[(int64_t)d * a.nn + k];
+            const float d1 = ph[k1];
+            const float2 u1 = a.nfu[k1];
+            jv = q / (1.0f + q) * ((float)a.phi_ref[s] + d1) * ((float)vx * u1.x + (float)vy * u1.y);
+            db = ok2 ? 2.0f * d1 - ph[k2] : d1;
+        }
+        g[1 + d] = Q1 * (db + 3.0f * jv);
+    }
+}
+
 // One lattice tile of TILE_X x LTILE_Y nodes per workgroup; thread (lx, ly) handles rows
 // ly, ly + TILE_Y, ...  Order: listed nodes' records and the population loads issued; moments
 // (rho, u) of every row, u staged in LDS; listed nodes coupled (force spread into LDS, velocity
 // interpolated to the nodes); collision with the spread force and stores.
-template <int S, bool NODES, bool MASK, int ST, int RP, bool NF = false, bool MS = false>
+template <int S, bool NODES, bool MASK, int ST, int RP, int NF = 0, bool MS = false, bool HF = false>
 __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int tile)
 {
     constexpr int LY = TILE_Y * RP;
@@ -358,6 +411,7 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
     float g[RP][S > 0 ? S : 1][5];
     int m[RP];
     unsigned miss[RP];            // no-flux membranes: D2Q5 directions 1..4 that arrived across one
+                                  // (first-order form: bits 0..3, the node's cut links)
     unsigned cell[RP];            // mass sources: the cell the node lies in (~0: none)
     // every lane loads (lanes beyond a ragged edge read the last column / row and discard it):
     // without branches around the loads the compiler waits for exactly the ones each use needs
@@ -381,7 +435,8 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
             m[r] = (((x & 32) ? w1 : w0) >> (x & 31)) & 1u;
         }
         miss[r] = 0u;
-        if constexpr (NF) {
+        if constexpr (NF == 2) miss[r] = a.nfm[(int64_t)yl * a.nx + xl];
+        if constexpr (NF == 1) {
             // direction i arrives from x - v_i: +x from x-1, +y from y-1, -x from x+1, -y from
             // y+1; it crossed a membrane when the inside map differs between the two nodes
             // (a population reflected by a wall did not)
@@ -433,7 +488,45 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
         }
     }
 
-    if constexpr (NODES) {
+    if constexpr (NODES && HF) {
+        // the nodes move with the half-force-shifted velocity u + e/2: every listed node is
+        // spread first, the tile's velocity is restaged with the complete force, then the
+        // nodes interpolate it (the first chunk's records stay in registers for the second pass)
+        __syncthreads();
+        couple_chunk<false>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, us);
+        int cij0[SPREAD_UNROLL], cnd0[SPREAD_UNROLL];
+        float4 crc0[SPREAD_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SPREAD_UNROLL; ++u) {
+            cij0[u] = cij[u];
+            cnd0[u] = cnd[u];
+            crc0[u] = crc[u];
+        }
+        for (int k0 = lbeg + SPREAD_UNROLL * TILE_N; k0 < lend; k0 += SPREAD_UNROLL * TILE_N) {
+            load_candidates(a, k0, lend, cij, crc, cnd);
+            couple_chunk<false>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, us);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+            const int l = lds_slot(t, r);
+            const float ex = a.bodyx + __ll2float_rn((long long)accx[l]) * FIX_INV;
+            const float ey = a.bodyy + __ll2float_rn((long long)accy[l]) * FIX_INV;
+            us[l] = make_float2(ux_r[r] + 0.5f * ex, uy_r[r] + 0.5f * ey);
+        }
+        __syncthreads();
+        couple_chunk<true, true, false>(a, x0, x1, y0, y1, cij0, crc0, cnd0, accx, accy, us, Ud);
+        if (lend - lbeg > SPREAD_UNROLL * TILE_N) {
+            float2 Ux[SPREAD_UNROLL];
+            for (int k0 = lbeg + SPREAD_UNROLL * TILE_N; k0 < lend; k0 += SPREAD_UNROLL * TILE_N) {
+                load_candidates(a, k0, lend, cij, crc, cnd);
+                couple_chunk<true, false, false>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, us, Ux);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SPREAD_UNROLL; ++u) cnd[u] = cnd0[u];
+        // the collision reads the accumulators, final since the barrier above
+    } else if constexpr (NODES) {
         __syncthreads();
         couple_chunk<true, true>(a, x0, x1, y0, y1, cij, crc, cnd, accx, accy, us, Ud);
         if (lend - lbeg > SPREAD_UNROLL * TILE_N) {
@@ -521,7 +614,14 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
         if constexpr (MASK)
             if ((x & 31) == 0) a.inside_clr[(int64_t)(y0 + t / TILE_X + r * TILE_Y) * a.wpr + (x >> 5)] = 0u;
         if constexpr (S > 0) {
-            if constexpr (NF) {
+            if constexpr (NF == 2) {
+                if (miss[r]) {
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        if ((a.noflux >> s) & 1) nf_first_replace(a, s, x, n[r].y, miss[r], g[r][s]);
+                }
+            }
+            if constexpr (NF == 1) {
                 // populations that arrived across a no-flux membrane become the equilibrium at
                 // the wall's zero velocity, w_i phi_b, phi_b the node's own concentration:
                 // in deviations, dphi_b = (sum of the arrived dg_j) / (1 - sum of missing w_i)
@@ -547,6 +647,13 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
             for (int s = 0; s < S; ++s) {
                 dphi[s] = ((g[r][s][0] + g[r][s][1]) + (g[r][s][2] + g[r][s][3])) + g[r][s][4];
                 phi[s] = a.phi_ref[s] + dphi[s];
+            }
+            if constexpr (NF == 2) {
+                // what this collision sees, for the next step's replacement
+                const int64_t k = (int64_t)n[r].y * a.nx + x;
+#pragma unroll
+                for (int s = 0; s < S; ++s) a.nfphi_out[(int64_t)s * a.nn + k] = dphi[s];
+                a.nfu_out[k] = make_float2(ux, uy);
             }
 #pragma unroll
             for (int s = 0; s < S; ++s) {
@@ -596,10 +703,10 @@ constexpr int lattice_waves(int S, int RP, bool)
     return RP == 1 ? 6 : RP == 2 ? (S <= 1 ? 5 : 4) : 3;
 }
 
-template <int S, bool NODES, bool MASK, int ST, bool NF = false, bool MS = false>
+template <int S, bool NODES, bool MASK, int ST, int NF = 0, bool MS = false, bool HF = false>
 __global__ __launch_bounds__(TILE_N) __attribute__((amdgpu_waves_per_eu(lattice_waves(S, RPT, false)))) void k_lattice(LatticeArgs a)
 {
-    lattice_tile<S, NODES, MASK, ST, RPT, NF, MS>(a, tile_of_block((int)blockIdx.x, a.ntx, (a.ny + LTILE_Y - 1) / LTILE_Y));
+    lattice_tile<S, NODES, MASK, ST, RPT, NF, MS, HF>(a, tile_of_block((int)blockIdx.x, a.ntx, (a.ny + LTILE_Y - 1) / LTILE_Y));
 }
 
 // Batched form: every workgroup takes one (simulation, tile) work item; the simulation's
@@ -664,6 +771,8 @@ struct InitArgs {
     int nx, ny, walls, S;
     double rho0;
     double phi_ref[2];
+    float* nfphi;                     // first-order no-flux membranes: the state's concentration
+    float2* nfu;                      // deviations and velocities as the previous step's (or NULL)
 };
 
 template <int ST>
@@ -695,9 +804,11 @@ __global__ void k_init(InitArgs a)
             f[pop_at(a.frow, 9 * TILE_X, i, syy, sx)] = val;
         }
     }
+    if (a.nfu) a.nfu[idx] = make_float2((float)ux, (float)uy);
     for (int s = 0; s < a.S; ++s) {
         const double phi = a.phi ? a.phi[(int64_t)s * a.nn + idx] : 0.0;
         const double dphi = phi - a.phi_ref[s];
+        if (a.nfphi) a.nfphi[(int64_t)s * a.nn + idx] = (float)dphi;
         T* gs = (T*)a.g;
         for (int i = 0; i < 5; ++i) {
             const double vu = vx[i] * ux + vy[i] * uy;
@@ -729,6 +840,12 @@ struct MomentArgs {
     int wpr;
     int noflux;                       // bit s: no-flux membranes for species s
     int pring;                        // the outer ring is held at rho0 (pressure boundary)
+    // no-flux membranes in the first-order form (nfq NULL: the zeroth-order form): the buffers
+    // the next lattice pass reads
+    const float* nfq;
+    const uint8_t* nfm;
+    const float* nfphi;
+    const float2* nfu;
 };
 
 template <int ST>
@@ -750,7 +867,9 @@ __device__ inline void node_moments(const MomentArgs& a, int x, int y, double& d
         drho = 0.0;
     }
     unsigned miss = 0u;
-    if (a.noflux) {
+    if (a.noflux && a.nfq) {
+        miss = a.nfm[(int64_t)y * a.nx + x];
+    } else if (a.noflux) {
         // populations that arrived across a no-flux membrane (as in the lattice pass)
         auto bit = [&](int xx, int yy) { return (a.inside[(int64_t)yy * a.wpr + (xx >> 5)] >> (xx & 31)) & 1u; };
         const unsigned me = bit(n.x, n.y);
@@ -762,6 +881,14 @@ __device__ inline void node_moments(const MomentArgs& a, int x, int y, double& d
     for (int s = 0; s < a.S; ++s) {
         float g[5];
         pull5<ST>((const typename Pop<ST>::T*)a.g + 5 * s * TILE_X, a.grow, a.gchunk, n, g);
+        if (miss && ((a.noflux >> s) & 1) && a.nfq) {
+            // the concentration the next collision sees: the populations over cut links replaced
+            nf_first_replace(a, s, x, y, miss, g);
+            double t = 0.0;
+            for (int i = 0; i < 5; ++i) t += (double)g[i];
+            dphi[s] = t;
+            continue;
+        }
         if (miss && ((a.noflux >> s) & 1)) {
             // the concentration the next collision sees: the missing populations become
             // w_i phi_b, so the sum is (sum of the arrived ones) / (1 - sum of the missing w_i)
@@ -890,33 +1017,44 @@ int reduce_scratch_blocks() { return REDUCE_SCRATCH_BLOCKS; }
 // ---------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------
+// Forms of the lattice pass: NF (no-flux membranes: 0 none, 1 zeroth-order form reading the
+// inside bits, 2 the first-order form), MS (mass sources or the pressure ring), HF (the nodes
+// move with the half-force-shifted velocity); the plain form carries none of their code.
+template <int S, int ST, int NF, bool MS>
+static hipError_t launch_form(lbib_ctx* c, const LatticeArgs& a, bool nodes, bool mask, bool hf)
+{
+    dim3 grid((unsigned)c->nltiles), block(TILE_N);
+    constexpr bool MASK_ONLY = NF == 1 || MS;        // these forms read the inside bits or the cell map
+#define LL(N, M, H) hipLaunchKernelGGL((k_lattice<S, N, M, ST, NF, MS, H>), grid, block, 0, c->stream, a)
+    if (nodes) {
+        if (hf) {
+            if (mask || MASK_ONLY) LL(true, true, true);
+            else LL(true, false, true);
+        } else {
+            if (mask || MASK_ONLY) LL(true, true, false);
+            else LL(true, false, false);
+        }
+    } else if constexpr (NF == 0) {
+        if (mask || MASK_ONLY) LL(false, true, false);
+        else LL(false, false, false);
+    }
+#undef LL
+    return hipGetLastError();
+}
+
 template <int S, int ST>
 static hipError_t launch_lattice_s(lbib_ctx* c, const LatticeArgs& a, bool nodes, bool mask)
 {
-    dim3 grid((unsigned)c->nltiles), block(TILE_N);
-    if ((a.cmap && nodes) || a.pring) {  // mass sources (the cell map; mask is set) or pressure ring
-        if constexpr (S > 0)
-            if (a.noflux) {
-                if (nodes) hipLaunchKernelGGL((k_lattice<S, true, true, ST, true, true>), grid, block, 0, c->stream, a);
-                else hipLaunchKernelGGL((k_lattice<S, false, true, ST, true, true>), grid, block, 0, c->stream, a);
-                return hipGetLastError();
-            }
-        if (nodes) hipLaunchKernelGGL((k_lattice<S, true, true, ST, false, true>), grid, block, 0, c->stream, a);
-        else hipLaunchKernelGGL((k_lattice<S, false, true, ST, false, true>), grid, block, 0, c->stream, a);
-        return hipGetLastError();
-    }
+    const bool hf = c->p.interp_half_force != 0;
+    const bool ms = (a.cmap && nodes) || a.pring;   // mass sources (the cell map) or pressure ring
     if constexpr (S > 0) {
-        if (a.noflux) {                 // no-flux membranes read the inside map (mask is set)
-            if (nodes) hipLaunchKernelGGL((k_lattice<S, true, true, ST, true>), grid, block, 0, c->stream, a);
-            else hipLaunchKernelGGL((k_lattice<S, false, true, ST, true>), grid, block, 0, c->stream, a);
-            return hipGetLastError();
+        if (a.noflux && nodes) {
+            if (a.nfq) return ms ? launch_form<S, ST, 2, true>(c, a, nodes, mask, hf)
+                                 : launch_form<S, ST, 2, false>(c, a, nodes, mask, hf);
+            return ms ? launch_form<S, ST, 1, true>(c, a, nodes, mask, hf) : launch_form<S, ST, 1, false>(c, a, nodes, mask, hf);
         }
     }
-    if (nodes && mask) hipLaunchKernelGGL((k_lattice<S, true, true, ST>), grid, block, 0, c->stream, a);
-    else if (nodes) hipLaunchKernelGGL((k_lattice<S, true, false, ST>), grid, block, 0, c->stream, a);
-    else if (mask) hipLaunchKernelGGL((k_lattice<S, false, true, ST>), grid, block, 0, c->stream, a);
-    else hipLaunchKernelGGL((k_lattice<S, false, false, ST>), grid, block, 0, c->stream, a);
-    return hipGetLastError();
+    return ms ? launch_form<S, ST, 0, true>(c, a, nodes, mask, hf) : launch_form<S, ST, 0, false>(c, a, nodes, mask, hf);
 }
 
 template <int ST>
@@ -1004,6 +1142,8 @@ hipError_t launch_init(lbib_ctx* c, const double* rho, const double* u, const do
     a.rho0 = c->p.rho0;
     a.phi_ref[0] = c->p.species[0].phi_ref;
     a.phi_ref[1] = c->p.species[1].phi_ref;
+    a.nfphi = c->nfphi[c->cur];
+    a.nfu = c->nfu[c->cur];
     const unsigned nb = (unsigned)((c->nn + 255) / 256);
     switch (c->p.storage) {
     case LBIB_STORAGE_FP16: hipLaunchKernelGGL(k_init<1>, dim3(nb), dim3(256), 0, c->stream, a); break;
@@ -1034,6 +1174,11 @@ static MomentArgs moment_args(lbib_ctx* c, double* out)
     a.wpr = c->wpr;
     a.noflux = c->n_cells ? no_flux_bits(c->p) : 0;
     a.pring = c->p.pressure_ring;
+    const bool nf1 = a.noflux && c->nfq[0];
+    a.nfq = nf1 ? c->nfq[c->cur] : nullptr;
+    a.nfm = nf1 ? c->nfm[c->cur] : nullptr;
+    a.nfphi = nf1 ? c->nfphi[c->cur] : nullptr;
+    a.nfu = nf1 ? c->nfu[c->cur] : nullptr;
     return a;
 }
 

@@ -88,7 +88,7 @@ __device__ inline void block_reduce5(double& sum, double m[4], double* red)
 
 // One cell per workgroup: xs holds the cell's positions (dynamic LDS), red the reduction
 // slots, bm the raster bitmap.
-template <int NT, int NB>
+template <int NT, int NB, bool NF1 = false>
 __device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c, double2* xs, double* red,
                                               unsigned* bm)
 {
@@ -98,6 +98,20 @@ __device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c
     const int64_t N = a.n_nodes;
     if (a.raster)
         for (int i = t; i < RASTER_WORDS_FUSED; i += NT) bm[i] = 0u;
+    if constexpr (NF1) {
+        // no-flux membranes, first-order form: the links the cell's edges cut at the previous
+        // positions leave the buffers the lattice pass of this step has read (a cell's nodes
+        // are written by its own workgroup only, at the end, so these are still the old ones)
+        if (a.advect)
+            for (int k = t; k < n; k += NT) {
+                const double2 A = a.X[beg + k], B = a.X[beg + ((k + 1 == n) ? 0 : k + 1)];
+                if (!(finite2(A.x, A.y) && finite2(B.x, B.y))) continue;
+                edge_link_cuts(A, B, a.nx, a.ny, a.walls, [&](int d, int64_t node, float) {
+                    a.nfq_old[(int64_t)d * a.nn + node] = INFINITY;
+                    a.nfm_old[node] = 0;
+                });
+            }
+    }
 
     // 1. move: X^{n+1} = X^n + U, U interpolated by the lattice pass as one share per listed
     //    tile, added in the order of the node's tiles; stage the new positions in LDS and track
@@ -154,6 +168,19 @@ __device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c
         }
     }
     __syncthreads();
+
+    if constexpr (NF1) {
+        // the links the edges cut at the new positions: the wall distance (the smallest over the
+        // cuts of a link: non-negative floats order as their bit patterns) and the blocked bit
+        for (int k = t; k < n; k += NT) {
+            const double2 A = xs[k], B = xs[(k + 1 == n) ? 0 : k + 1];
+            if (!(finite2(A.x, A.y) && finite2(B.x, B.y))) continue;
+            edge_link_cuts(A, B, a.nx, a.ny, a.walls, [&](int d, int64_t node, float q) {
+                atomicMin((unsigned*)&a.nfq[(int64_t)d * a.nn + node], __float_as_uint(q));
+                atomicOr(&a.nfm[node >> 2], (1u << d) << (8 * (int)(node & 3)));
+            });
+        }
+    }
 
     // 2. shoelace area about the first node (translation invariant, less cancellation)
     const double ox = uniform(xs[0].x), oy = uniform(xs[0].y);
@@ -248,12 +275,13 @@ __device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c
 // Three wavefronts per cell with two nodes per lane: a pass covers 384 nodes, and 6 waves per
 // SIMD keep every workgroup of a 2000-cell step resident at once (more nodes per pass cost
 // the registers that residency needs; a cell beyond a pass takes another)
+template <bool NF1>
 __global__ __launch_bounds__(MEMBRANE_THREADS) __attribute__((amdgpu_waves_per_eu(6))) void k_membrane(MembraneArgs a)
 {
     extern __shared__ double2 xs[];
     __shared__ double red[5 * (MEMBRANE_THREADS / 64)];
     __shared__ unsigned bm[RASTER_WORDS_FUSED];
-    membrane_cell<MEMBRANE_THREADS, MEMBRANE_BATCH>(a, blockIdx.x, xs, red, bm);
+    membrane_cell<MEMBRANE_THREADS, MEMBRANE_BATCH, NF1>(a, blockIdx.x, xs, red, bm);
 }
 
 // Batched form: one (simulation, cell) work item per workgroup, the simulation's arguments
@@ -510,7 +538,10 @@ __global__ void k_fill_f32(float* p, int64_t n)
 hipError_t launch_membrane(lbib_ctx* c, const MembraneArgs& a)
 {
     const size_t lds = sizeof(double2) * (size_t)(c->max_cell_nodes > 0 ? c->max_cell_nodes : 1);
-    hipLaunchKernelGGL(k_membrane, dim3((unsigned)c->n_cells), dim3(MEMBRANE_THREADS), lds, c->stream, a);
+    if (a.nfq)
+        hipLaunchKernelGGL(k_membrane<true>, dim3((unsigned)c->n_cells), dim3(MEMBRANE_THREADS), lds, c->stream, a);
+    else
+        hipLaunchKernelGGL(k_membrane<false>, dim3((unsigned)c->n_cells), dim3(MEMBRANE_THREADS), lds, c->stream, a);
     return hipGetLastError();
 }
 

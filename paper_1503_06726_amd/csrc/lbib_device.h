@@ -100,6 +100,15 @@ struct LatticeArgs {
     const double* __restrict__ area;
     double msrc, alpha;
     int pring;                             // the outer ring of nodes is held at density rho0
+    // no-flux membranes in the first-order form (nfq NULL: none): wall distances [4][nn] and
+    // blocked-link bytes [nn] of this step's positions, the concentration deviations [S][nn] and
+    // velocities [nn] the previous step's collision saw (read) and this step's (written)
+    const float* __restrict__ nfq;
+    const uint8_t* __restrict__ nfm;
+    const float* __restrict__ nfphi;
+    const float2* __restrict__ nfu;
+    float* __restrict__ nfphi_out;
+    float2* __restrict__ nfu_out;
     // inspection output (spread field only)
     double* __restrict__ e_out;
 };
@@ -127,6 +136,14 @@ struct MembraneArgs {
     double k_spring, phi_m, kappa;
     int advect;
     int raster;
+    // no-flux membranes in the first-order form (NULL: none): the crossings of the new
+    // positions go into nfq (atomic minimum of the wall distance) and nfm (blocked-link bits,
+    // OR-ed into 32-bit words of four node bytes); those of the previous positions are cleared
+    // from the other pair of buffers, which the lattice pass of this step has read
+    float* __restrict__ nfq;
+    unsigned* __restrict__ nfm;
+    float* __restrict__ nfq_old;
+    uint8_t* __restrict__ nfm_old;
 };
 
 struct ListArgs {
@@ -250,6 +267,56 @@ __device__ inline void stencil_origin(double x, double y, int nx, int ny, int wa
     const int j = (int)floor(y) - 1;
     if (walls) j0 = j < -4 ? -4 : (j > ny ? ny : j);
     else j0 = wrap_i(j, ny);
+}
+
+// The D2Q5 links a membrane edge (A, B) cuts (Suppl. "No-flux Boundary Condition for
+// Reaction-Advection-Diffusion Equations"), by the crossing rule of the domain IDs: the edge
+// crosses row y when (A.y > y) != (B.y > y), at x_c = A.x + (y - A.y)(B.x - A.x)/(B.y - A.y),
+// cutting the link between columns ceil(x_c) - 1 and ceil(x_c); columns likewise with x and y
+// exchanged (links to rows beyond a wall do not exist).  For each cut, emit(d, node, q) names
+// the node whose population arriving in direction d (0..3: +x, +y, -x, -y) crosses the edge
+// and its distance q to the cut, as a fraction of the link.  Contraction is off, so the
+// abscissae round as written (the same values as the rasteriser's).
+template <typename F>
+__device__ inline void edge_link_cuts(double2 A, double2 B, int nx, int ny, int walls, F&& emit)
+{
+#pragma clang fp contract(off)
+    const int ylo = (int)floor(fmin(A.y, B.y)), yhi = (int)floor(fmax(A.y, B.y));
+    for (int py = ylo; py <= yhi && py - ylo <= ny; ++py) {
+        const double yy = (double)py;
+        if ((A.y > yy) == (B.y > yy)) continue;
+        int j;
+        if (walls) {
+            if (py < 0 || py >= ny) continue;
+            j = py;
+        } else {
+            j = wrap_i(py, ny);
+        }
+        const double xc = A.x + (yy - A.y) * (B.x - A.x) / (B.y - A.y);
+        const double ir = ceil(xc);
+        const int i = wrap_i((int)ir, nx), il = (i == 0) ? nx - 1 : i - 1;
+        emit(0, (int64_t)j * nx + i, (float)(ir - xc));
+        emit(2, (int64_t)j * nx + il, (float)(xc - (ir - 1.0)));
+    }
+    const int xlo = (int)floor(fmin(A.x, B.x)), xhi = (int)floor(fmax(A.x, B.x));
+    for (int px = xlo; px <= xhi && px - xlo <= nx; ++px) {
+        const double xx = (double)px;
+        if ((A.x > xx) == (B.x > xx)) continue;
+        const double yc = A.y + (xx - A.x) * (B.y - A.y) / (B.x - A.x);
+        const double jt = ceil(yc);
+        const int i = wrap_i(px, nx), jtop = (int)jt;
+        int j1, j0;
+        if (walls) {
+            if (jtop < 1 || jtop >= ny) continue;             // both rows inside the lattice
+            j1 = jtop;
+            j0 = jtop - 1;
+        } else {
+            j1 = wrap_i(jtop, ny);
+            j0 = (j1 == 0) ? ny - 1 : j1 - 1;
+        }
+        emit(1, (int64_t)j1 * nx + i, (float)(jt - yc));
+        emit(3, (int64_t)j0 * nx + i, (float)(yc - (jt - 1.0)));
+    }
 }
 
 __device__ inline int pack_ij(int i0, int j0)

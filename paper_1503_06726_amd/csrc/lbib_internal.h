@@ -52,6 +52,14 @@ struct lbib_ctx {
     int cur = 0;
     unsigned* inside[2] = {nullptr, nullptr};   // inside-any-cell bits [ny][wpr], by parity cur
     unsigned* cmap = nullptr;   // mass sources: [ny][nx] index of the cell each node lies in (~0: none)
+    // no-flux membranes in the first-order form, by parity cur (NULL otherwise): wall distances
+    // [4][nn] and blocked-link bytes [nn] (4-byte padded) of the positions the pass of parity cur
+    // reads, the concentration deviations [S][nn] and velocities [nn] its collision saw last
+    float* nfq[2] = {nullptr, nullptr};
+    uint8_t* nfm[2] = {nullptr, nullptr};
+    float* nfphi[2] = {nullptr, nullptr};
+    float2* nfu[2] = {nullptr, nullptr};
+    size_t nfm_bytes() const { return ((size_t)nn + 3) / 4 * 4; }
     int wpr = 0;                     // 32-bit words per lattice row
     int64_t ny_words() const { return (int64_t)p.ny * wpr; }
 
@@ -125,6 +133,9 @@ inline int no_flux_bits(const lbib_params& p)
         if (p.species[s].flags & LBIB_SPECIES_NO_FLUX) b |= 1 << s;
     return b;
 }
+
+// does the step keep the first-order no-flux state (a no-flux species, not the zeroth-order form)?
+inline bool no_flux_first(const lbib_params& p) { return no_flux_bits(p) != 0 && !p.no_flux_zeroth; }
 
 // does the step add mass inside the cells (constant source or area controller)?
 inline bool mass_sources(const lbib_params& p) { return p.mass_source != 0.0 || p.area_alpha != 0.0; }

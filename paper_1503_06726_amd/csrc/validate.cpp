@@ -36,6 +36,10 @@ lbib_status check_params(const lbib_params* p, std::string& msg)
     if (p->area_alpha < 0.0) return fail(msg, "area_alpha = %g must not be negative", p->area_alpha);
     if (p->pressure_ring != 0 && p->pressure_ring != 1)
         return fail(msg, "pressure_ring = %g must be 0 or 1", p->pressure_ring);
+    if (p->interp_half_force != 0 && p->interp_half_force != 1)
+        return fail(msg, "interp_half_force = %g must be 0 or 1", p->interp_half_force);
+    if (p->no_flux_zeroth != 0 && p->no_flux_zeroth != 1)
+        return fail(msg, "no_flux_zeroth = %g must be 0 or 1", p->no_flux_zeroth);
     if (p->reserved != 0) return fail(msg, "reserved = %g must be 0", p->reserved);
     if (p->n_species < 0 || p->n_species > 2) return fail(msg, "n_species = %g outside 0..2", p->n_species);
     if (p->storage < LBIB_STORAGE_FP32 || p->storage > LBIB_STORAGE_BF16)

@@ -48,7 +48,8 @@ class Params(C.Structure):
                 ("k_spring", C.c_double), ("phi_m", C.c_double), ("kappa_area", C.c_double),
                 ("n_species", C.c_int32), ("storage", C.c_int32), ("species", Species * 2),
                 ("mass_source", C.c_double), ("area_alpha", C.c_double),
-                ("pressure_ring", C.c_int32), ("reserved", C.c_int32)]
+                ("pressure_ring", C.c_int32), ("interp_half_force", C.c_int32),
+                ("no_flux_zeroth", C.c_int32), ("reserved", C.c_int32)]
 
 
 class LbibError(RuntimeError):
@@ -205,6 +206,8 @@ def make_params(d: dict) -> Params:
     p.mass_source = float(d.get("mass_source", 0.0))
     p.area_alpha = float(d.get("area_alpha", 0.0))
     p.pressure_ring = int(bool(d.get("pressure_ring", False)))
+    p.interp_half_force = int(bool(d.get("interp_half_force", False)))
+    p.no_flux_zeroth = int(bool(d.get("no_flux_zeroth", False)))
     return p
 
 

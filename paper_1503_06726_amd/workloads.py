@@ -66,6 +66,8 @@ class Workload:
     mass_source: float = 0.0        # constant mass source per node inside a cell and step
     area_alpha: float = 0.0         # area controller: S_k = mass_source + area_alpha (A0_k - A_k)
     pressure_ring: bool = False     # the lattice's outer ring holds the density at rho0 (outflow)
+    interp_half_force: bool = False  # membrane nodes move with the interpolated u + f/2
+    no_flux_zeroth: bool = False    # no-flux membranes in the zeroth-order form
     steps: int = 1
     # geometry (may be empty)
     offsets: np.ndarray = None      # int32 [n_cells+1]
@@ -97,7 +99,8 @@ class Workload:
                     species=[dict(D=s.D, phi_ref=s.phi_ref, reaction=s.reaction, c=tuple(s.c),
                                   no_flux=bool(s.no_flux)) for s in self.species],
                     mass_source=self.mass_source, area_alpha=self.area_alpha,
-                    pressure_ring=self.pressure_ring)
+                    pressure_ring=self.pressure_ring, interp_half_force=self.interp_half_force,
+                    no_flux_zeroth=self.no_flux_zeroth)
 
     def mask_needed(self) -> bool:
         return any(s.reaction == REACT_SOURCE_DECAY for s in self.species)

@@ -40,11 +40,12 @@ def test_ctypes_layout_matches_header():
     #include <stddef.h>
     #include "lbib.h"
     int main(void) {
-      printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lbib_params), sizeof(lbib_species),
+      printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lbib_params), sizeof(lbib_species),
              offsetof(lbib_params, tau), offsetof(lbib_params, body_accel), offsetof(lbib_params, kappa_area),
              offsetof(lbib_params, n_species), offsetof(lbib_params, species), offsetof(lbib_species, c),
              offsetof(lbib_species, reaction), offsetof(lbib_params, mass_source), offsetof(lbib_params, area_alpha),
-             offsetof(lbib_params, pressure_ring));
+             offsetof(lbib_params, pressure_ring), offsetof(lbib_params, interp_half_force),
+             offsetof(lbib_params, no_flux_zeroth));
       return 0; }
     """
     with tempfile.TemporaryDirectory() as d:
@@ -56,7 +57,7 @@ def test_ctypes_layout_matches_header():
     P, S = lbib.Params, lbib.Species
     want = [C.sizeof(P), C.sizeof(S), P.tau.offset, P.body_accel.offset, P.kappa_area.offset,
             P.n_species.offset, P.species.offset, S.c.offset, S.reaction.offset, P.mass_source.offset,
-            P.area_alpha.offset, P.pressure_ring.offset]
+            P.area_alpha.offset, P.pressure_ring.offset, P.interp_half_force.offset, P.no_flux_zeroth.offset]
     assert vals == want
 
 
@@ -205,6 +206,7 @@ def test_mass_source_constants_validated():
     assert p.mass_source == d["mass_source"] and p.area_alpha == d["area_alpha"]
     for field, bad, word in (("area_alpha", -1e-6, b"area_alpha"), ("mass_source", float("nan"), b"mass-source"),
                              ("area_alpha", float("inf"), b"mass-source"), ("pressure_ring", 2, b"pressure_ring"),
+                             ("interp_half_force", 2, b"interp_half_force"), ("no_flux_zeroth", -1, b"no_flux_zeroth"),
                              ("reserved", 1, b"reserved")):
         q = lbib.make_params(d)
         setattr(q, field, bad)
@@ -220,3 +222,15 @@ def test_workspace_size_holds_the_cell_map_of_mass_sources():
     extra = _ws(m, 100) - _ws(d, 100)
     assert 200 * 130 * 4 <= extra < 200 * 130 * 4 + 256
     assert _ws(dict(d, area_alpha=1e-6), 100) == _ws(m, 100)
+
+
+def test_workspace_size_holds_the_first_order_no_flux_state():
+    """The first-order no-flux condition keeps, per buffer parity, four wall distances and a
+    blocked-link byte per lattice node, and the previous step's concentration and velocity;
+    the zeroth-order form keeps none of them."""
+    d = dict(W.no_flux_tissue().params_dict())
+    z = dict(d, no_flux_zeroth=True)
+    nn = d["nx"] * d["ny"]
+    extra = _ws(d, 100) - _ws(z, 100)
+    want = 2 * (16 * nn + (nn + 3) // 4 * 4 + 4 * nn + 8 * nn)
+    assert want <= extra < want + 8 * 256

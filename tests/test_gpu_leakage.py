@@ -7,7 +7,11 @@ node spacings (``workloads.leakage_case``).  Bars:
   * node spacings 0.1 and 0.5 give the same area change within 1 % (the paper finds them
     indistinguishable); spacing 2.5 stays within 10 %;
   * the area change converges at first order in the lattice resolution: observed orders
-    log2(e_l / e_{l+1}) between levels 0, 1 and 2 lie in [0.8, 1.2] (the paper fits 0.99).
+    log2(e_l / e_{l+1}) between levels 0, 1 and 2 lie in [0.8, 1.2] (the paper fits 0.99);
+  * with the half-force-shifted velocity u + f/2 the cell shrinks, as the paper's does (with
+    u = sum f v / rho it grows: the nodes drift outward by half the interpolated force
+    density per step): the library follows the oracle at level 0 over the full time, the area
+    decreases at every sample and resolution, and the change converges (orders in [0.7, 1.7]).
 """
 import sys
 
@@ -60,3 +64,24 @@ def test_node_spacing_and_first_order_convergence():
         say(f"  spacing {m}: orders {[(a, b, round(o, 3)) for a, b, o in v]}")
         for a, b, order in v:
             assert 0.8 <= order <= 1.2, (m, a, b, order)
+
+
+def test_half_force_cell_shrinks_as_in_the_paper():
+    r = LK.run_case(0, 0.5, samples=10, half_force=True)
+    w = W.leakage_case(0, 0.5)
+    w.interp_half_force = True
+    o = O.from_workload(w)
+    A0 = polygon_area(o.get_fields()["xy"])
+    for step, e in r["trajectory"][1:]:
+        o.step(w.steps // 10)
+        eo = (polygon_area(o.get_fields()["xy"]) - A0) / A0
+        say(f"  half-force step {step}: library {e:.6e}  oracle {eo:.6e}")
+        assert e < 0.0 and eo < 0.0, (step, e, eo)
+        assert abs(e - eo) <= 2e-3 * abs(eo), (step, e, eo)
+    res = [r] + [LK.run_case(level, 0.5, samples=2, half_force=True) for level in (1, 2)]
+    for q in res:
+        say(f"  half-force level {q['level']}: relative area change {q['rel_area_error']:.5e}")
+        assert q["rel_area_error"] < 0.0
+    for a, b, order in LK.orders(res)[0.5]:
+        say(f"  half-force orders {a}->{b}: {order:.3f}")
+        assert 0.7 <= order <= 1.7, (a, b, order)

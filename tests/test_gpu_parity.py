@@ -150,6 +150,17 @@ def test_coupled_cases(case):
     compare(G, R, w)
 
 
+@pytest.mark.parametrize("case", ["walls", "periodic", "peskin"])
+def test_coupled_half_force_velocity(case):
+    """The nodes move with the half-force-shifted velocity u + f/2 (the option of the
+    forcing's velocity): the coupled step still follows the oracle, over 80 steps (five list
+    rebuilds and graph periods)."""
+    w = CELL_CASES[case]()
+    w.interp_half_force = True
+    G, R = run_pair(w, 80)
+    compare(G, R, w)
+
+
 def test_coupled_tissue_full_size():
     w = W.tissue()
     G, R = run_pair(w, 100)

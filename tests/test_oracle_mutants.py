@@ -73,6 +73,15 @@ MUTANTS = {
     "area controller sign": ("p->mass_source + p->area_alpha * (c->A0[k] - c->area[k]);",
                              "p->mass_source + p->area_alpha * (c->area[k] - c->A0[k]);"),
     "mass source added at rest": ("orc_equilibrium9(1.0, vx, vy, e1);", "orc_equilibrium9(1.0, 0.0, 0.0, e1);"),
+    "no-flux extrapolation dropped": ("phib = ok2 ? 2.0 * ph[k1] - ph[k2] : ph[k1];", "phib = ok2 ? ph[k1] : ph[k1];"),
+    "no-flux interpolation weight": ("double w = qq / (1.0 + qq);", "double w = 1.0 / (1.0 + qq);"),
+    "no-flux wall distance from the far end": ("deposit(q, nn, 0, j * nx + wrapi(ir, nx), (double)ir - xc);",
+                                               "deposit(q, nn, 0, j * nx + wrapi(ir, nx), xc - (double)(ir - 1));"),
+    "no-flux momentum component sign": ("double v = W5[i] * (phib + (VX[i] * jbx + VY[i] * jby) / CS2);",
+                                        "double v = W5[i] * (phib + (VX[i] * jbx - VY[i] * jby) / CS2);"),
+    "no-flux downstream node reversed": ("int64_t k1 = ok1 ? wrapi(y1, ny) * nx + wrapi(x + VX[i], nx) : k;",
+                                         "int64_t k1 = ok1 ? wrapi(y1, ny) * nx + wrapi(x - VX[i], nx) : k;"),
+    "half-force shift sign": ("sh[x] = c->ux[x] + 0.5 * c->ex[x];", "sh[x] = c->ux[x] - 0.5 * c->ex[x];"),
     "pressure ring gamma inverted": ("double gamma = c->p.rho0 / r;\n        for (int i = 0; i < 9; ++i) c->f[i * nn + x] *= gamma;",
                                      "double gamma = r / c->p.rho0;\n        for (int i = 0; i < 9; ++i) c->f[i * nn + x] *= gamma;"),
 }
