@@ -148,8 +148,20 @@ typedef struct {
      * (LBIB_EINVAL). */
     int32_t interp_half_force;   /* 0 or 1 */
     int32_t no_flux_zeroth;  /* 0: the first-order no-flux condition; 1: its zeroth-order form */
+    /* The FP64 monitor: 0 (default) off, or a positive multiple of LBIB_GRAPH_STEPS.  The global
+     * sums of lbib_reduce (sum rho, sum rho u, sum phi_s) are then taken on the device at the
+     * end of every (monitor_every / LBIB_GRAPH_STEPS)-th period of LBIB_GRAPH_STEPS steps
+     * completed by lbib_step since the last lbib_set_cells (or the creation), inside the step
+     * graphs it replays; periods are aligned to the rebuilds of the per-tile node lists, so with
+     * cells set at step 0 the sums follow steps monitor_every, 2 monitor_every, ...  Steps a batch
+     * takes do not count.  lbib_get_monitor returns the latest.  A sum that is not finite sets
+     * the context's error state (see lbib_step). */
+    int32_t monitor_every;
     int32_t reserved;        /* 0 */
 } lbib_params;
+
+/* Steps per captured graph of lbib_step, and the period of the per-tile node lists. */
+#define LBIB_GRAPH_STEPS 16
 
 typedef struct lbib_ctx lbib_ctx;
 
@@ -227,13 +239,25 @@ lbib_status lbib_set_fields(lbib_ctx* ctx, const double* rho, const double* u, c
 /* Enqueue n >= 0 coupled steps on the context's stream (asynchronous).  Each step, from
  * state (f^n, g^n, X^n): spread the membrane forces F(X^n) plus the body acceleration, collide
  * the fluid and every species with u^n = sum f^n v / rho^n and the domain IDs of X^n, stream,
- * then move every node by the interpolated u^n (Fig. "Algorithm Overview"). */
+ * then move every node by the interpolated u^n (Fig. "Algorithm Overview").  Whole periods of
+ * LBIB_GRAPH_STEPS steps, aligned to the per-tile node lists, replay a captured graph.
+ * Watchdog: the device flags a node position or force that became non-finite, a node that
+ * moved more than 2 lattice units between list rebuilds (its spread force would be lost), and,
+ * with the monitor on, a lattice sum that is not finite; every period ends by copying the flags
+ * to pinned host memory.  lbib_step returns LBIB_ENUMERIC, and enqueues no further step, once
+ * flags raised by work that has completed are visible there; every call that reads data
+ * returns LBIB_ENUMERIC for them as well.  lbib_set_cells clears them. */
 lbib_status lbib_step(lbib_ctx* ctx, int32_t n);
 
 /* Copy the current state to host buffers (NULL skips an output); synchronises the stream.
+ * Section "Input and Output": the fluid and the reaction-advection-diffusion solver states
+ * (here their moments) and the geometry points.
  *   rho [ny][nx], u [2][ny][nx], phi [S][ny][nx] doubles (moments of the current populations),
  *   xy [N][2] doubles (current node positions), cell_id_map [ny][nx] int32 (domain IDs).
- * Returns LBIB_ENUMERIC (after copying) if a node position became non-finite. */
+ * Returns LBIB_ENUMERIC (after copying) when the device has flagged a node position or force
+ * that became non-finite, a node that moved more than 2 lattice units between two rebuilds of
+ * the per-tile node lists (its stencil may then reach tiles that do not list it: part of its
+ * spread force and interpolated velocity is lost), or a non-finite monitor sum. */
 lbib_status lbib_get_fields(lbib_ctx* ctx, double* rho, double* u, double* phi, double* xy,
                             int32_t* cell_id_map);
 
@@ -420,6 +444,35 @@ lbib_status lbib_reduce(lbib_ctx* ctx, double* out);
  * device memory of the context's device; LBIB_EDEVICE when the scratch has no device address
  * or a launch fails. */
 lbib_status lbib_reduce_device(lbib_ctx* ctx, double* out_device);
+
+/* Saving and resuming a run (Section "Input and Output": the solver states are saved in a
+ * format the software can load to continue).  The state is everything a step reads that is
+ * not a function of the node positions: the current populations of the fluid and species
+ * lattices as stored (deviations in the storage type), the first-order no-flux condition's
+ * previous-step concentrations and velocities, the cells (offsets, positions, rest lengths and
+ * areas, source flags), the monitor's latest sums and period count, and the error flags.  On
+ * loading, the forces, spreading records, per-tile node lists, inside-cell bits, cell map and
+ * link cuts are rebuilt from the positions as lbib_set_cells builds them, and the lists start
+ * a new period; the run then continues bit for bit as it would have (the list period decides
+ * only which tiles list a node, which does not change any sum).
+ *   lbib_state_size: bytes of the current state (it depends on the parameters and the node
+ *                    count).
+ *   lbib_save_state: copy the state into the host buffer [buf, buf + bytes); synchronises.
+ *                    LBIB_EINVAL when bytes is short.
+ *   lbib_load_state: replace the context's state by a saved one.  The context must have been
+ *                    created with the same parameters (LBIB_EINVAL otherwise, or for a short or
+ *                    foreign buffer); the cells are validated as by lbib_set_cells.  Synchronises;
+ *                    LBIB_ESTATE while a batch has adopted the context.  A failure may leave the
+ *                    cells replaced and the populations unchanged. */
+lbib_status lbib_state_size(lbib_ctx* ctx, size_t* bytes);
+lbib_status lbib_save_state(lbib_ctx* ctx, void* buf, size_t bytes);
+lbib_status lbib_load_state(lbib_ctx* ctx, const void* buf, size_t bytes);
+
+/* The latest sums of the FP64 monitor (lbib_params.monitor_every): out [3 + n_species] doubles
+ * as lbib_reduce's, *taken the number of times the monitor has taken them since the last
+ * lbib_set_cells (0, out untouched, when it has not yet).  Synchronises.  LBIB_ESTATE when the
+ * monitor is off; LBIB_ENUMERIC (after copying) when a sum is not finite. */
+lbib_status lbib_get_monitor(lbib_ctx* ctx, double* out, int64_t* taken);
 
 /* Wait for all queued work on the context's stream. */
 lbib_status lbib_sync(lbib_ctx* ctx);

@@ -318,17 +318,31 @@ lbib_status ensure_stage(lbib_ctx* c, size_t doubles)
 
 }  // namespace
 
+// The error flags that completed device work has copied to pinned host memory (no
+// synchronisation): LBIB_ENUMERIC once any is set.
+static lbib_status host_flags(lbib_ctx* c)
+{
+    const int h = c->h_err ? __atomic_load_n(c->h_err, __ATOMIC_ACQUIRE) : 0;
+    if (!h) return LBIB_OK;
+    c->err = std::string("stepping stopped: ") + lbib::err_text(h);
+    return LBIB_ENUMERIC;
+}
+
+const char* lbib::err_text(int h)
+{
+    if (h & ERR_NONFINITE) return "a membrane node position or force became non-finite";
+    if (h & ERR_MARGIN) return "a membrane node moved more than 2 lattice units between list rebuilds (velocity too large)";
+    if (h & ERR_FIELDS) return "a lattice sum of the monitor is not finite";
+    return "device error flag";
+}
+
 lbib_status lbib::check_err_flag(lbib_ctx* c)
 {
     int h = 0;
     LBIB_HIP(c, hipMemcpyAsync(&h, c->d_err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
-    if (h & ERR_NONFINITE) {
-        c->err = "a membrane node position or force became non-finite";
-        return LBIB_ENUMERIC;
-    }
-    if (h & ERR_MARGIN) {
-        c->err = "a membrane node moved more than 2 lattice units between list rebuilds (velocity too large)";
+    if (h) {
+        c->err = err_text(h);
         return LBIB_ENUMERIC;
     }
     return LBIB_OK;
@@ -382,6 +396,7 @@ void free_all(lbib_ctx* c)
     state_free(c, c->d_t_off, (size_t)c->tile_cap + 1);
     state_free(c, c->d_t_cur, (size_t)c->tile_cap);
     state_free(c, c->d_err, 1);
+    state_free(c, c->d_mon, 8);
     state_free(c, c->d_partial, c->partial_count * 5);
     if (c->d_stage) state_free(c, c->d_stage, c->stage_bytes / sizeof(double));
     c->stage_bytes = 0;
@@ -392,6 +407,8 @@ void free_all(lbib_ctx* c)
     c->pending.clear();
     for (auto e : c->free_events) (void)hipEventDestroy(e);
     c->free_events.clear();
+    if (c->h_err) (void)hipHostFree(c->h_err);
+    c->h_err = c->h_err_dev = nullptr;
 }
 
 // -------------------------------------------------------------------------------------
@@ -404,7 +421,7 @@ void free_all(lbib_ctx* c)
 enum Piece {
     PC_F0, PC_F1, PC_G0, PC_G1, PC_IN0, PC_IN1, PC_CMAP,
     PC_NFQ0, PC_NFQ1, PC_NFM0, PC_NFM1, PC_NFPHI0, PC_NFPHI1, PC_NFU0, PC_NFU1,
-    PC_TCOUNT, PC_TOFF, PC_TCUR, PC_ERR, PC_PARTIAL, PC_STAGE,
+    PC_TCOUNT, PC_TOFF, PC_TCUR, PC_ERR, PC_MON, PC_PARTIAL, PC_STAGE,
     PC_OFF, PC_X, PC_L0, PC_A0, PC_AREA, PC_IJ, PC_PART, PC_CNT, PC_REC, PC_RECIJ, PC_LIST, PC_SRC,
     PC_COUNT
 };
@@ -449,6 +466,7 @@ void piece_bytes(const lbib_ctx& c, int64_t n_nodes, int64_t n_cells, size_t sta
     b[PC_TCOUNT] = b[PC_TCUR] = (size_t)c.tile_cap * sizeof(int);
     b[PC_TOFF] = ((size_t)c.tile_cap + 1) * sizeof(int);
     b[PC_ERR] = sizeof(int);
+    b[PC_MON] = 8 * sizeof(double);
     b[PC_PARTIAL] = c.partial_count * 5 * sizeof(double);
     b[PC_STAGE] = stage_doubles * sizeof(double);
     b[PC_OFF] = N ? (C + 1) * sizeof(int) : 0;
@@ -485,6 +503,7 @@ void** piece_slot(lbib_ctx* c, int i)
     case PC_TOFF: return reinterpret_cast<void**>(&c->d_t_off);
     case PC_TCUR: return reinterpret_cast<void**>(&c->d_t_cur);
     case PC_ERR: return reinterpret_cast<void**>(&c->d_err);
+    case PC_MON: return reinterpret_cast<void**>(&c->d_mon);
     case PC_PARTIAL: return reinterpret_cast<void**>(&c->d_partial);
     case PC_STAGE: return reinterpret_cast<void**>(&c->d_stage);
     case PC_OFF: return reinterpret_cast<void**>(&c->d_off);
@@ -678,6 +697,12 @@ lbib_status init_fields(lbib_ctx* c, const double* rho, const double* u, const d
     return LBIB_OK;
 }
 
+// is the monitor due at the end of the period that brings the count of periods to `period`?
+bool monitor_due(const lbib_ctx* c, int64_t period)
+{
+    return c->p.monitor_every > 0 && period % (c->p.monitor_every / GRAPH_STEPS) == 0;
+}
+
 // one coupled step, launched directly on the context's stream
 lbib_status one_step(lbib_ctx* c)
 {
@@ -687,9 +712,12 @@ lbib_status one_step(lbib_ctx* c)
         LBIB_LAUNCH(c, launch_lattice(c, lattice_args(c), nodes, c->mask_needed));
     }
     c->cur = 1 - c->cur;
-    if (nodes) {
-        LBIB_TRY(membrane(c, 1));
-        if (++c->steps_since_lists >= LIST_PERIOD) LBIB_TRY(build_lists(c));
+    if (nodes) LBIB_TRY(membrane(c, 1));
+    if (++c->steps_since_lists >= LIST_PERIOD) {       // a period ends: lists rebuilt, monitor
+        if (nodes) LBIB_TRY(build_lists(c));
+        c->steps_since_lists = 0;
+        if (monitor_due(c, ++c->period_count))         // FP64 sums of the new state
+            LBIB_LAUNCH(c, launch_reduce(c, c->d_partial, c->d_mon + 1, c->d_mon, c->d_err));
     }
     if (c->timing && c->pending.size() > 4096) LBIB_TRY(harvest(c));
     return LBIB_OK;
@@ -698,10 +726,11 @@ lbib_status one_step(lbib_ctx* c)
 void drop_graphs(lbib_ctx* c)
 {
     for (int i = 0; i < 2; ++i)
-        if (c->graph[i]) {
-            (void)hipGraphExecDestroy(c->graph[i]);
-            c->graph[i] = nullptr;
-        }
+        for (int m = 0; m < 2; ++m)
+            if (c->graph[i][m]) {
+                (void)hipGraphExecDestroy(c->graph[i][m]);
+                c->graph[i][m] = nullptr;
+            }
 }
 
 // Capture GRAPH_STEPS steps (kernels only: no memsets or copies) on a private stream.  The
@@ -711,6 +740,7 @@ lbib_status capture_steps(lbib_ctx* c, hipGraphExec_t* out)
 {
     if (!c->capture_stream) LBIB_HIP(c, hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
     const int cur0 = c->cur, since0 = c->steps_since_lists;
+    const int64_t count0 = c->period_count;
     hipStream_t user = c->stream;
     c->stream = c->capture_stream;
     hipGraph_t graph = nullptr;
@@ -719,12 +749,14 @@ lbib_status capture_steps(lbib_ctx* c, hipGraphExec_t* out)
         st = LBIB_EDEVICE;
     } else {
         for (int k = 0; k < GRAPH_STEPS && st == LBIB_OK; ++k) st = one_step(c);
+        if (st == LBIB_OK && launch_err_mirror(c, c->h_err_dev) != hipSuccess) st = LBIB_EDEVICE;
         hipError_t e = hipStreamEndCapture(c->stream, &graph);
         if (st == LBIB_OK && e != hipSuccess) st = LBIB_EDEVICE;
     }
     c->stream = user;
     c->cur = cur0;
     c->steps_since_lists = since0;
+    c->period_count = count0;
     if (st == LBIB_OK && hipGraphInstantiate(out, graph, nullptr, nullptr, 0) != hipSuccess) st = LBIB_EDEVICE;
     if (graph) (void)hipGraphDestroy(graph);
     if (st != LBIB_OK) {
@@ -835,12 +867,20 @@ lbib_status lbib_create(const lbib_params* p, void* hip_stream, lbib_ctx** out)
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_off, (size_t)c->tile_cap + 1);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_t_cur, (size_t)c->tile_cap);
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_err, 1);
+    if (s == LBIB_OK) s = dev_alloc(c, &c->d_mon, 8);
+    if (s == LBIB_OK && (hipHostMalloc((void**)&c->h_err, sizeof(int), hipHostMallocMapped) != hipSuccess ||
+                         hipHostGetDevicePointer((void**)&c->h_err_dev, c->h_err, 0) != hipSuccess)) {
+        c->h_err_dev = nullptr;
+        s = LBIB_EDEVICE;
+    }
+    if (s == LBIB_OK) *(volatile int*)c->h_err = 0;
     if (s == LBIB_OK) s = dev_alloc(c, &c->d_partial, c->partial_count * 5);
     if (s == LBIB_OK && (launch_fill_i32(c, (int*)c->inside[0], c->ny_words(), 0) != hipSuccess ||
                          launch_fill_i32(c, (int*)c->inside[1], c->ny_words(), 0) != hipSuccess ||
                          launch_fill_i32(c, c->d_t_count, c->tile_cap, 0) != hipSuccess ||
                          launch_fill_i32(c, c->d_t_off, c->tile_cap + 1, 0) != hipSuccess ||
-                         launch_fill_i32(c, c->d_err, 1, 0) != hipSuccess))
+                         launch_fill_i32(c, c->d_err, 1, 0) != hipSuccess ||
+                         launch_fill_i32(c, (int*)c->d_mon, 16, 0) != hipSuccess))
         s = LBIB_EDEVICE;
     if (s == LBIB_OK) s = init_fields(c, nullptr, nullptr, nullptr);
     if (s != LBIB_OK) {
@@ -891,6 +931,8 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
     drop_graphs(c);
     free_nodes(c);
+    c->steps_since_lists = 0;
+    c->period_count = 0;
     if (n_cells == 0) return LBIB_OK;
     const size_t N = (size_t)off[n_cells], C = (size_t)n_cells;
 
@@ -927,12 +969,15 @@ lbib_status lbib_set_cells(lbib_ctx* c, int32_t n_cells, const int32_t* off, con
     LBIB_HIP(c, hipMemcpyAsync(c->d_A0, A0.data(), C * sizeof(double), hipMemcpyHostToDevice, c->stream));
     LBIB_LAUNCH(c, launch_fill_i32(c, c->d_t_count, c->tile_cap, 0));
     LBIB_LAUNCH(c, launch_fill_i32(c, c->d_err, 1, 0));
+    LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->d_mon, 16, 0));
+    c->period_count = 0;
     if (c->mask_needed)
         for (int b = 0; b < 2; ++b) LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->inside[b], c->ny_words(), 0));
     if (c->cmap) LBIB_LAUNCH(c, launch_fill_i32(c, (int*)c->cmap, c->nn, -1));   // claims of earlier cells
     for (int b = 0; b < 2; ++b) LBIB_TRY(clear_cuts(c, b));                     // cuts of earlier cells
     LBIB_TRY(build_lists(c));
     LBIB_TRY(membrane(c, 0));
+    LBIB_LAUNCH(c, launch_err_mirror(c, c->h_err_dev));
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
     return check_err_flag(c);
 }
@@ -968,20 +1013,29 @@ lbib_status lbib_step(lbib_ctx* c, int32_t n)
         c->err = "negative step count";
         return LBIB_EINVAL;
     }
+    LBIB_TRY(host_flags(c));
+    bool direct = false;
     while (n > 0) {
-        // whole periods of GRAPH_STEPS steps replay a captured graph (not while timing kernels)
+        // whole periods of GRAPH_STEPS steps, aligned to the list rebuilds, replay a captured
+        // graph (not while timing kernels); with the monitor due at the period's last step, the
+        // graph that ends with it
         if (c->use_graphs && !c->timing && n >= GRAPH_STEPS && c->steps_since_lists == 0) {
-            hipGraphExec_t& g = c->graph[c->cur];
+            hipGraphExec_t& g = c->graph[c->cur][monitor_due(c, c->period_count + 1) ? 1 : 0];
             if (!g) LBIB_TRY(capture_steps(c, &g));
             if (g) {
+                LBIB_TRY(host_flags(c));
                 LBIB_HIP(c, hipGraphLaunch(g, c->stream));
                 n -= GRAPH_STEPS;        // buffer parities are the same again after the period
+                ++c->period_count;
+                direct = false;
                 continue;
             }
         }
         LBIB_TRY(one_step(c));
+        direct = true;
         --n;
     }
+    if (direct) LBIB_LAUNCH(c, launch_err_mirror(c, c->h_err_dev));   // graphs end with one
     return LBIB_OK;
 }
 
@@ -1102,6 +1156,199 @@ lbib_status lbib_reduce_device(lbib_ctx* c, double* out_device)
     }
     LBIB_TRY(join_batch(c));
     LBIB_LAUNCH(c, launch_reduce(c, scratch, out_device));
+    return LBIB_OK;
+}
+
+lbib_status lbib_get_monitor(lbib_ctx* c, double* out, int64_t* step)
+{
+    if (!c) return LBIB_ESTATE;
+    if (!out || !step) return LBIB_EINVAL;
+    if (c->p.monitor_every <= 0) {
+        c->err = "the monitor is off (monitor_every = 0)";
+        return LBIB_ESTATE;
+    }
+    LBIB_TRY(join_batch(c));
+    double h[8];
+    LBIB_HIP(c, hipMemcpyAsync(h, c->d_mon, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    const int64_t taken = (int64_t)h[0];
+    *step = taken;
+    if (taken <= 0) return LBIB_OK;
+    const int nv = 3 + c->S;
+    for (int v = 0; v < nv; ++v) out[v] = h[1 + v];
+    for (int v = 0; v < nv; ++v)
+        if (!std::isfinite(out[v])) {
+            c->err = "non-finite lattice sum";
+            return LBIB_ENUMERIC;
+        }
+    return LBIB_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Solver state for saving and resuming (Section "Input and Output"): a header, then the
+// current populations of both lattices as stored (chunked deviations in the storage type),
+// the first-order no-flux planes, the cells (offsets, positions, rest lengths and areas,
+// source flags).  Everything else a step reads (forces, spreading records, node lists, the
+// inside-cell bits, the cell map, the link cuts) is a function of the positions and is rebuilt
+// on loading, as lbib_set_cells builds it.
+// ---------------------------------------------------------------------------------------
+namespace {
+
+struct StateHeader {
+    char magic[8];
+    int32_t version, has_src;
+    lbib_params p;
+    int64_t n_cells, n_nodes, period_count;
+    int32_t err, nf1;
+    double mon[8];
+    uint64_t bytes_f, bytes_g, bytes_nfphi, bytes_nfu;
+};
+constexpr char STATE_MAGIC[8] = {'L', 'B', 'I', 'B', 'S', 'T', 'A', 'T'};
+constexpr int32_t STATE_VERSION = 1;
+
+void state_layout(const lbib_ctx* c, StateHeader& h)
+{
+    std::memset(&h, 0, sizeof h);
+    std::memcpy(h.magic, STATE_MAGIC, 8);
+    h.version = STATE_VERSION;
+    h.p = c->p;
+    h.n_cells = c->n_cells;
+    h.n_nodes = c->n_nodes;
+    h.period_count = c->period_count;
+    h.has_src = c->d_src ? 1 : 0;
+    h.nf1 = c->nfq[0] ? 1 : 0;
+    h.bytes_f = c->f_elems() * c->pop_bytes;
+    h.bytes_g = c->S ? c->g_elems() * c->pop_bytes : 0;
+    h.bytes_nfphi = h.nf1 ? (uint64_t)c->S * (uint64_t)c->nn * sizeof(float) : 0;
+    h.bytes_nfu = h.nf1 ? (uint64_t)c->nn * sizeof(float2) : 0;
+}
+
+size_t state_bytes(const StateHeader& h)
+{
+    const size_t N = (size_t)h.n_nodes, C = (size_t)h.n_cells;
+    size_t b = sizeof(StateHeader) + h.bytes_f + h.bytes_g + h.bytes_nfphi + h.bytes_nfu;
+    if (C) b += (C + 1) * sizeof(int32_t) + N * (2 * sizeof(double) + sizeof(double)) + C * sizeof(double);
+    if (h.has_src) b += C;
+    return b;
+}
+
+}  // namespace
+
+lbib_status lbib_state_size(lbib_ctx* c, size_t* bytes)
+{
+    if (!c) return LBIB_ESTATE;
+    if (!bytes) return LBIB_EINVAL;
+    StateHeader h;
+    state_layout(c, h);
+    *bytes = state_bytes(h);
+    return LBIB_OK;
+}
+
+lbib_status lbib_save_state(lbib_ctx* c, void* buf, size_t bytes)
+{
+    if (!c) return LBIB_ESTATE;
+    StateHeader h;
+    state_layout(c, h);
+    if (!buf || bytes < state_bytes(h)) {
+        c->err = "the buffer holds " + std::to_string(bytes) + " bytes; the state needs " +
+                 std::to_string(buf ? state_bytes(h) : 0);
+        return LBIB_EINVAL;
+    }
+    LBIB_TRY(join_batch(c));
+    int hd[2] = {0, 0};
+    LBIB_HIP(c, hipMemcpyAsync(hd, c->d_err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    LBIB_HIP(c, hipMemcpyAsync(h.mon, c->d_mon, sizeof h.mon, hipMemcpyDeviceToHost, c->stream));
+    char* q = (char*)buf + sizeof(StateHeader);
+    auto take = [&](const void* dev, size_t n) -> hipError_t {
+        if (!n) return hipSuccess;
+        const hipError_t e = hipMemcpyAsync(q, dev, n, hipMemcpyDeviceToHost, c->stream);
+        q += n;
+        return e;
+    };
+    LBIB_HIP(c, take(c->f[c->cur], h.bytes_f));
+    LBIB_HIP(c, take(c->g[c->cur], h.bytes_g));
+    LBIB_HIP(c, take(c->nfphi[c->cur], h.bytes_nfphi));
+    LBIB_HIP(c, take(c->nfu[c->cur], h.bytes_nfu));
+    if (c->n_cells) {
+        const size_t N = (size_t)c->n_nodes, C = (size_t)c->n_cells;
+        LBIB_HIP(c, take(c->d_off, (C + 1) * sizeof(int32_t)));
+        LBIB_HIP(c, take(c->d_X, N * sizeof(double2)));
+        LBIB_HIP(c, take(c->d_l0, N * sizeof(double)));
+        LBIB_HIP(c, take(c->d_A0, C * sizeof(double)));
+        if (h.has_src) LBIB_HIP(c, take(c->d_src, C));
+    }
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    h.err = hd[0];
+    std::memcpy(buf, &h, sizeof h);
+    return LBIB_OK;
+}
+
+lbib_status lbib_load_state(lbib_ctx* c, const void* buf, size_t bytes)
+{
+    if (!c) return LBIB_ESTATE;
+    LBIB_TRY(refuse_if_batched(c));
+    StateHeader h;
+    if (!buf || bytes < sizeof h) {
+        c->err = "the buffer is shorter than a state header";
+        return LBIB_EINVAL;
+    }
+    std::memcpy(&h, buf, sizeof h);
+    StateHeader mine;
+    state_layout(c, mine);
+    if (std::memcmp(h.magic, STATE_MAGIC, 8) != 0 || h.version != STATE_VERSION) {
+        c->err = "not a saved lbib state of this version";
+        return LBIB_EINVAL;
+    }
+    // every named field of the parameters (the struct has no padding before its last field)
+    const size_t pfields = offsetof(lbib_params, reserved) + sizeof(int32_t);
+    if (std::memcmp(&h.p, &c->p, pfields) != 0 || h.bytes_f != mine.bytes_f ||
+        h.bytes_g != mine.bytes_g || h.nf1 != mine.nf1 || h.n_cells < 0 || h.n_nodes < 0) {
+        c->err = "the saved state was made with other parameters";
+        return LBIB_EINVAL;
+    }
+    if (bytes < state_bytes(h)) {
+        c->err = "the buffer is shorter than the saved state";
+        return LBIB_EINVAL;
+    }
+    const char* q = (const char*)buf + sizeof(StateHeader) + h.bytes_f + h.bytes_g + h.bytes_nfphi + h.bytes_nfu;
+    if (h.n_cells) {
+        const size_t N = (size_t)h.n_nodes, C = (size_t)h.n_cells;
+        std::vector<int32_t> off(C + 1);
+        std::vector<double> xy(2 * N), l0(N), A0(C);
+        std::memcpy(off.data(), q, (C + 1) * sizeof(int32_t));
+        q += (C + 1) * sizeof(int32_t);
+        std::memcpy(xy.data(), q, 2 * N * sizeof(double));
+        q += 2 * N * sizeof(double);
+        std::memcpy(l0.data(), q, N * sizeof(double));
+        q += N * sizeof(double);
+        std::memcpy(A0.data(), q, C * sizeof(double));
+        q += C * sizeof(double);
+        if ((size_t)off[C] != N) {
+            c->err = "the saved cells are inconsistent";
+            return LBIB_EINVAL;
+        }
+        LBIB_TRY(lbib_set_cells(c, (int32_t)C, off.data(), xy.data(), l0.data(), A0.data()));
+        if (h.has_src) LBIB_TRY(lbib_set_source_cells(c, (const uint8_t*)q));
+    } else {
+        const int32_t none = 0;
+        LBIB_TRY(lbib_set_cells(c, 0, &none, nullptr, nullptr, nullptr));
+    }
+    const char* p = (const char*)buf + sizeof(StateHeader);
+    auto give = [&](void* dev, size_t n) -> hipError_t {
+        if (!n) return hipSuccess;
+        const hipError_t e = hipMemcpyAsync(dev, p, n, hipMemcpyHostToDevice, c->stream);
+        p += n;
+        return e;
+    };
+    LBIB_HIP(c, give(c->f[c->cur], h.bytes_f));
+    LBIB_HIP(c, give(c->g[c->cur], h.bytes_g));
+    LBIB_HIP(c, give(c->nfphi[c->cur], h.bytes_nfphi));
+    LBIB_HIP(c, give(c->nfu[c->cur], h.bytes_nfu));
+    LBIB_HIP(c, hipMemcpyAsync(c->d_mon, h.mon, sizeof h.mon, hipMemcpyHostToDevice, c->stream));
+    LBIB_HIP(c, hipMemcpyAsync(c->d_err, &h.err, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    LBIB_LAUNCH(c, launch_err_mirror(c, c->h_err_dev));
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    c->period_count = h.period_count;
     return LBIB_OK;
 }
 

@@ -956,9 +956,11 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_partial(MomentArgs a, do
 // Final stage, one workgroup: thread t adds the partials of blocks t, t + RED_THREADS, ... in
 // that order, then a fixed LDS tree adds the threads' sums; the order depends on nblocks only,
 // so the result is the same from run to run.
+// With the monitor (count non-NULL) the workgroup also counts the sums taken (count[0] += 1,
+// out = count + 1) and flags a sum that is not finite in err.
 __global__ __launch_bounds__(RED_THREADS) void k_reduce_final(const double* partial, int nblocks, int nv,
                                                               double rho_total, double phi_tot0, double phi_tot1,
-                                                              double* out)
+                                                              double* out, double* count, int* err)
 {
     __shared__ double sh[RED_MAXV][RED_THREADS];
     double acc[RED_MAXV] = {0, 0, 0, 0, 0};
@@ -972,12 +974,31 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_final(const double* part
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        out[0] = rho_total + sh[0][0];
-        out[1] = sh[1][0];
-        out[2] = sh[2][0];
-        if (nv > 3) out[3] = phi_tot0 + sh[3][0];
-        if (nv > 4) out[4] = phi_tot1 + sh[4][0];
+        double v[RED_MAXV] = {rho_total + sh[0][0], sh[1][0], sh[2][0], phi_tot0 + sh[3][0], phi_tot1 + sh[4][0]};
+        bool finite = true;
+        for (int k = 0; k < nv; ++k) {
+            out[k] = v[k];
+            finite = finite && isfinite(v[k]);
+        }
+        if (count) count[0] += 1.0;
+        if (err && !finite) atomicOr(err, ERR_FIELDS);
     }
+}
+
+// The context's error flags copied to host-visible memory (pinned, mapped), which lbib_step
+// reads without synchronising.
+__global__ void k_err_mirror(const int* err, int* host)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int v = __atomic_load_n(err, __ATOMIC_RELAXED);
+        __hip_atomic_store(host, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+hipError_t launch_err_mirror(lbib_ctx* c, int* host_dev)
+{
+    hipLaunchKernelGGL(k_err_mirror, dim3(1), dim3(64), 0, c->stream, (const int*)c->d_err, host_dev);
+    return hipGetLastError();
 }
 
 // Block partials of the sums for the entry point that allocates nothing: a file-scope array
@@ -1203,7 +1224,7 @@ int reduce_blocks(int64_t nn)
     return nb < 1 ? 1 : (int)nb;
 }
 
-hipError_t launch_reduce(lbib_ctx* c, double* partial, double* out_dev)
+hipError_t launch_reduce(lbib_ctx* c, double* partial, double* out_dev, double* count, int* err)
 {
     MomentArgs a = moment_args(c, nullptr);
     const int nblocks = reduce_blocks(c->nn);
@@ -1224,7 +1245,7 @@ hipError_t launch_reduce(lbib_ctx* c, double* partial, double* out_dev)
     const double p0 = c->p.species[0].phi_ref * (double)c->nn;
     const double p1 = c->p.species[1].phi_ref * (double)c->nn;
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, c->stream, (const double*)partial, nblocks,
-                       3 + c->S, rho_total, p0, p1, out_dev);
+                       3 + c->S, rho_total, p0, p1, out_dev, count, err);
     return hipGetLastError();
 }
 

@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lbib.h"
+
 namespace lbib {
 
 // workgroup of the lattice pass: 64 x 4 threads (one 64-wide wavefront per row), each thread
@@ -36,7 +38,7 @@ constexpr int MIN_LTILE_Y = TILE_Y;   // the shortest tile (one row per thread) 
 constexpr int LIST_MARGIN = 2;       // lattice units a node may drift between list rebuilds
 constexpr int LIST_PERIOD = 16;      // steps between list rebuilds (nodes may move 2/16 lu per step)
 constexpr int MAX_NODE_TILES = 9;    // tiles one node can be listed in (3 columns x 3 rows at most)
-constexpr int GRAPH_STEPS = 16;      // steps per captured graph (a multiple of LIST_PERIOD)
+constexpr int GRAPH_STEPS = LBIB_GRAPH_STEPS;   // steps per captured graph (a multiple of LIST_PERIOD)
 
 constexpr int MEMBRANE_THREADS = 192;             // three wavefronts per cell
 constexpr int MEMBRANE_BATCH = 2;               // nodes per lane whose loads are issued together
@@ -59,6 +61,7 @@ constexpr float FIX_CLAMP = 16384.0f;                    // |contribution| bound
 // error flags (device int, OR-ed)
 constexpr int ERR_NONFINITE = 1;     // a node position or force became non-finite
 constexpr int ERR_MARGIN = 2;        // a node drifted beyond its list margin
+constexpr int ERR_FIELDS = 4;        // a monitor sum of the lattice was not finite
 
 // Element (plane p, row y, column x) of a chunked population array whose rows hold `row`
 // elements and whose chunks hold `chunk` = Q * TILE_X elements.

@@ -88,6 +88,10 @@ struct lbib_ctx {
     // staging
     double* d_stage = nullptr;
     size_t stage_bytes = 0;
+    double* d_mon = nullptr;         // FP64 monitor: [0] sums taken, [1 ..] the latest sums
+    int64_t period_count = 0;        // periods of LIST_PERIOD steps completed since the last lbib_set_cells
+    int* h_err = nullptr;            // the error flags mirrored to pinned host memory
+    int* h_err_dev = nullptr;        // its device address
     double* d_partial = nullptr;     // reduction partials
     size_t partial_count = 0;
     bool scratch_ok = false;         // the static reduction scratch has an address on this device
@@ -107,7 +111,7 @@ struct lbib_ctx {
     // captured step sequences: GRAPH_STEPS steps starting right after a list build, one graph
     // per parity (cur) of the population buffers at the start
     bool use_graphs = true;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [parity][monitor at the end]
     hipStream_t capture_stream = nullptr;
 
     // a batch that has adopted this context steps it on the batch's stream; reads wait for
@@ -146,7 +150,9 @@ hipError_t launch_spread_inspect(lbib_ctx* c, const LatticeArgs& a);
 hipError_t launch_init(lbib_ctx* c, const double* stage_rho, const double* stage_u, const double* stage_phi,
                        int has_rho, int has_u, int has_phi);
 hipError_t launch_moments(lbib_ctx* c, double* out);
-hipError_t launch_reduce(lbib_ctx* c, double* partial, double* out_dev);   // partial: reduce_blocks(nn) x 5 doubles
+// partial: reduce_blocks(nn) x 5 doubles; with the monitor, count (out = count + 1) and err
+hipError_t launch_reduce(lbib_ctx* c, double* partial, double* out_dev, double* count = nullptr, int* err = nullptr);
+hipError_t launch_err_mirror(lbib_ctx* c, int* host_dev);
 int reduce_blocks(int64_t nn);
 // the file-scope scratch of the reduction that allocates nothing (k_lattice.hip): its device
 // address on a device, resolved once per device by reduce_scratch_init (with that device current)
@@ -190,6 +196,7 @@ MembraneArgs membrane_args_at(lbib_ctx* c, int cur, int advect);
 ListArgs list_args_h(lbib_ctx* c, int lty);
 lbib_status build_lists(lbib_ctx* c);
 lbib_status check_err_flag(lbib_ctx* c);
+const char* err_text(int flags);
 
 }  // namespace lbib
 

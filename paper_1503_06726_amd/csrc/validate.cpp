@@ -40,6 +40,8 @@ lbib_status check_params(const lbib_params* p, std::string& msg)
         return fail(msg, "interp_half_force = %g must be 0 or 1", p->interp_half_force);
     if (p->no_flux_zeroth != 0 && p->no_flux_zeroth != 1)
         return fail(msg, "no_flux_zeroth = %g must be 0 or 1", p->no_flux_zeroth);
+    if (p->monitor_every < 0 || p->monitor_every % LBIB_GRAPH_STEPS != 0 || p->monitor_every > (1 << 30))
+        return fail(msg, "monitor_every = %g must be 0 or a positive multiple of 16", p->monitor_every);
     if (p->reserved != 0) return fail(msg, "reserved = %g must be 0", p->reserved);
     if (p->n_species < 0 || p->n_species > 2) return fail(msg, "n_species = %g outside 0..2", p->n_species);
     if (p->storage < LBIB_STORAGE_FP32 || p->storage > LBIB_STORAGE_BF16)

@@ -34,7 +34,8 @@ EXPORTS = ["lbib_validate_params", "lbib_validate_cells", "lbib_create", "lbib_s
            "lbib_batch_create", "lbib_batch_step", "lbib_batch_sync", "lbib_batch_get_tile",
            "lbib_batch_set_tile", "lbib_batch_get_groups", "lbib_batch_set_groups", "lbib_batch_autotune",
            "lbib_batch_last_error", "lbib_batch_destroy",
-           "lbib_workspace_size", "lbib_bind_workspace", "lbib_workspace_nodes", "lbib_reduce_device"]
+           "lbib_workspace_size", "lbib_bind_workspace", "lbib_workspace_nodes", "lbib_reduce_device",
+           "lbib_get_monitor", "lbib_state_size", "lbib_save_state", "lbib_load_state"]
 
 
 class Species(C.Structure):
@@ -49,7 +50,7 @@ class Params(C.Structure):
                 ("n_species", C.c_int32), ("storage", C.c_int32), ("species", Species * 2),
                 ("mass_source", C.c_double), ("area_alpha", C.c_double),
                 ("pressure_ring", C.c_int32), ("interp_half_force", C.c_int32),
-                ("no_flux_zeroth", C.c_int32), ("reserved", C.c_int32)]
+                ("no_flux_zeroth", C.c_int32), ("monitor_every", C.c_int32), ("reserved", C.c_int32)]
 
 
 class LbibError(RuntimeError):
@@ -106,6 +107,14 @@ def lib():
     L.lbib_get_spread.argtypes = [vp, dp]
     L.lbib_reduce.restype = st
     L.lbib_reduce.argtypes = [vp, dp]
+    L.lbib_state_size.restype = st
+    L.lbib_state_size.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.lbib_save_state.restype = st
+    L.lbib_save_state.argtypes = [vp, vp, C.c_size_t]
+    L.lbib_load_state.restype = st
+    L.lbib_load_state.argtypes = [vp, vp, C.c_size_t]
+    L.lbib_get_monitor.restype = st
+    L.lbib_get_monitor.argtypes = [vp, dp, C.POINTER(C.c_int64)]
     L.lbib_reduce_device.restype = st
     L.lbib_reduce_device.argtypes = [vp, vp]
     L.lbib_sync.restype = st
@@ -208,6 +217,7 @@ def make_params(d: dict) -> Params:
     p.pressure_ring = int(bool(d.get("pressure_ring", False)))
     p.interp_half_force = int(bool(d.get("interp_half_force", False)))
     p.no_flux_zeroth = int(bool(d.get("no_flux_zeroth", False)))
+    p.monitor_every = int(d.get("monitor_every", 0))
     return p
 
 
@@ -329,6 +339,30 @@ class Simulation:
         out = np.zeros(3 + self.S)
         self._check(self.L.lbib_reduce(self.h, _p(out)), "lbib_reduce")
         return out
+
+    def save_state(self) -> bytes:
+        """The solver state (lbib_save_state) as bytes, loadable with ``load_state``."""
+        n = C.c_size_t()
+        self._check(self.L.lbib_state_size(self.h, C.byref(n)), "lbib_state_size")
+        buf = C.create_string_buffer(int(n.value))
+        self._check(self.L.lbib_save_state(self.h, buf, n), "lbib_save_state")
+        return buf.raw
+
+    def load_state(self, state: bytes):
+        """Continue from a state saved by ``save_state`` (lbib_load_state)."""
+        buf = C.create_string_buffer(state, len(state))
+        self._check(self.L.lbib_load_state(self.h, buf, len(state)), "lbib_load_state")
+        # the header: magic, version and source flag, the parameters, then the cell and node counts
+        n_cells, n_nodes = np.frombuffer(state, np.int64, 2, 16 + C.sizeof(Params))
+        self.n_cells, self.n_nodes = int(n_cells), int(n_nodes)
+
+    def monitor(self):
+        """(sums, times taken) of the FP64 monitor (lbib_get_monitor); sums is None before the
+        monitor has taken any."""
+        out = np.zeros(3 + self.S)
+        n = C.c_int64(0)
+        self._check(self.L.lbib_get_monitor(self.h, _p(out), C.byref(n)), "lbib_get_monitor")
+        return (out if n.value > 0 else None), int(n.value)
 
     def reduce_device(self, out_ptr: int):
         """Enqueue the sums of ``reduce`` into device memory at ``out_ptr`` (3 + S doubles,

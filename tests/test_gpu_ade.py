@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 from oracle import ade_fixed_point as F
+import parity_bars as PB
 from oracle import oracle as O
 from paper_1503_06726_amd import lbib
 from paper_1503_06726_amd import workloads as W
@@ -142,9 +143,9 @@ def test_source_subset_in_the_coupled_step():
     o = O.from_workload(w)
     o.step(60)
     R = o.get_fields()
-    r = {k: rel(G[k], R[k]) for k in ("u", "phi", "xy")}
-    say("  rel-L2:", {k: f"{v:.2e}" for k, v in r.items()})
-    assert max(r.values()) <= 1e-5
+    r = PB.field_errors(G, R, w.rho0, w.xy, 60, w.n_species)
+    say("  errors:", PB.fmt(r))
+    PB.assert_fields(r)
 
 
 def test_ade_and_source_errors():

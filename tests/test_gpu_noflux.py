@@ -18,6 +18,7 @@ import sys
 import numpy as np
 import pytest
 
+import parity_bars as PB
 from oracle import oracle as O
 from paper_1503_06726_amd import lbib
 from paper_1503_06726_amd import workloads as W
@@ -52,10 +53,9 @@ def test_no_flux_matches_oracle(static, steps, zeroth):
     o = O.from_workload(w)
     o.step(steps)
     R = o.get_fields()
-    errs = {k: rel(G[k], R[k]) for k in ("rho", "u", "phi", "xy")}
-    say("  rel-L2:", {k: f"{v:.2e}" for k, v in errs.items()})
-    for k, v in errs.items():
-        assert v <= 1e-5, (k, v)
+    errs = PB.field_errors(G, R, w.rho0, w.xy, steps, w.n_species)
+    say("  errors:", PB.fmt(errs))
+    PB.assert_fields(errs)
     assert np.array_equal(G["mask"], R["mask"])
 
 
