@@ -210,6 +210,7 @@ MembraneArgs membrane_args_at(lbib_ctx* c, int cur, int advect)
     a.kappa = c->p.kappa_area;
     a.advect = advect;
     a.raster = c->mask_needed ? 1 : 0;
+    a.need_area = area_in_step(c->p) ? 1 : 0;
     if (c->nfq[0]) {
         a.nfq = c->nfq[cur];
         a.nfm = (unsigned*)c->nfm[cur];
@@ -1081,6 +1082,13 @@ lbib_status lbib_get_forces(lbib_ctx* c, double* F, double* area)
     if (!c) return LBIB_ESTATE;
     LBIB_TRY(join_batch(c));
     if (!c->n_cells) return LBIB_OK;
+    if (area && !area_in_step(c->p)) {
+        // the step does not keep the areas: the membrane kernel at the current positions
+        // (everything else it writes is the same function of them) computes them
+        MembraneArgs a = membrane_args_at(c, c->cur, 0);
+        a.need_area = 1;
+        LBIB_LAUNCH(c, launch_membrane(c, a));
+    }
     const size_t N = (size_t)c->n_nodes;
     if (F) {
         LBIB_TRY(ensure_stage(c, N));

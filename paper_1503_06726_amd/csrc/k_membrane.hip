@@ -167,6 +167,15 @@ __device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c
             bb[3] = fmin(bb[3], -x.y);
         }
     }
+    if (!a.need_area) {
+        // without the area, the bounding box alone: each wavefront's goes to LDS before the
+        // barrier the positions need anyway (no second barrier for a block reduction)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) bb[q] = wave_min(bb[q]);
+        if ((t & 63) == 0)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) red[(t >> 6) * 5 + 1 + q] = bb[q];
+    }
     __syncthreads();
 
     if constexpr (NF1) {
@@ -182,16 +191,27 @@ __device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c
         }
     }
 
-    // 2. shoelace area about the first node (translation invariant, less cancellation)
-    const double ox = uniform(xs[0].x), oy = uniform(xs[0].y);
-    double A2 = 0.0;
-    for (int k = t; k < n; k += NT) {
-        const int kn = (k + 1 == n) ? 0 : k + 1;
-        A2 += (xs[k].x - ox) * (xs[kn].y - oy) - (xs[kn].x - ox) * (xs[k].y - oy);
+    // 2. shoelace area about the first node (translation invariant, less cancellation), when the
+    //    step reads it (area pressure, area controller) or it is asked for
+    double A = 0.0, s_area = 0.0;
+    if (a.need_area) {
+        const double ox = uniform(xs[0].x), oy = uniform(xs[0].y);
+        double A2 = 0.0;
+        for (int k = t; k < n; k += NT) {
+            const int kn = (k + 1 == n) ? 0 : k + 1;
+            A2 += (xs[k].x - ox) * (xs[kn].y - oy) - (xs[kn].x - ox) * (xs[k].y - oy);
+        }
+        block_reduce5(A2, bb, red);
+        A = 0.5 * A2;
+        s_area = a.kappa * (a.A0[c] - A);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            double m = red[1 + q];
+            for (int w = 1; w < NT / 64; ++w) m = fmin(m, red[w * 5 + 1 + q]);
+            bb[q] = uniform(m);
+        }
     }
-    block_reduce5(A2, bb, red);
-    const double A = 0.5 * A2;
-    const double s_area = a.kappa * (a.A0[c] - A);
 
     // 3. inside-any-cell bits of the new positions (the bitmap was cleared above); with a
     //    source subset only the source cells are rasterised.  No barrier follows the last
@@ -268,7 +288,7 @@ __device__ __forceinline__ void membrane_cell(const MembraneArgs& a, const int c
             }
         }
     }
-    if (t == 0) a.area[c] = A;
+    if (t == 0 && a.need_area) a.area[c] = A;
     if (flags) atomicOr(a.err, flags);
 }
 

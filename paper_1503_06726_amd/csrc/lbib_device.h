@@ -139,6 +139,7 @@ struct MembraneArgs {
     double k_spring, phi_m, kappa;
     int advect;
     int raster;
+    int need_area;                     // compute (and store) the cell areas
     // no-flux membranes in the first-order form (NULL: none): the crossings of the new
     // positions go into nfq (atomic minimum of the wall distance) and nfm (blocked-link bits,
     // OR-ed into 32-bit words of four node bytes); those of the previous positions are cleared

@@ -144,6 +144,9 @@ inline bool no_flux_first(const lbib_params& p) { return no_flux_bits(p) != 0 &&
 // does the step add mass inside the cells (constant source or area controller)?
 inline bool mass_sources(const lbib_params& p) { return p.mass_source != 0.0 || p.area_alpha != 0.0; }
 
+// does a step read the cell areas (area pressure, area controller)?
+inline bool area_in_step(const lbib_params& p) { return p.kappa_area != 0.0 || mass_sources(p); }
+
 // kernel launchers (return the launch error)
 hipError_t launch_lattice(lbib_ctx* c, const LatticeArgs& a, bool nodes, bool mask);
 hipError_t launch_spread_inspect(lbib_ctx* c, const LatticeArgs& a);
