@@ -24,9 +24,22 @@ sys.path.insert(0, ROOT)
 
 METRIC = "coupled LBM+IB MLUPS at 2048²/2000 cells (% HBM peak); ADE iters-to-steady"
 HBM_PEAK_GBS = 8000.0
-# HBM traffic per launch of the lattice kernel measured with rocprofv3 --pmc (FETCH_SIZE,
-# WRITE_SIZE, scaled by a copy kernel of known size); None until taken for the current kernel
-LATTICE_TRAFFIC_BYTES = 525_301_116
+GOLD = os.path.join(ROOT, "tests", "golden")
+# HBM bytes one launch of the lattice pass moves at the large workload in FP32, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, each scaled by what the counter reads for a
+# copy of known size; profiles/k_lattice_large_2048x2048_2000cells_fp32_hbm_bytes.md), with the
+# SHA-256 of the kernel's sources when they were taken: reported only while the sources match.
+LATTICE_TRAFFIC = {"bytes": None, "sources_sha256": None}
+LATTICE_SOURCES = ("paper_1503_06726_amd/csrc/k_lattice.hip", "paper_1503_06726_amd/csrc/lbib_device.h")
+
+
+def lattice_sources_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in LATTICE_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def log(*a):
@@ -69,7 +82,7 @@ def ade_half(samples, lbib, stream):
     from paper_1503_06726_amd import warmstart as WS
     src, _, feat = WS.prepare(samples, stream)
     t0 = time.perf_counter()
-    k0, _ = WS.solve(samples, src, tol=ADE_TOL, max_iters=ADE_CAP, stream=stream)
+    k0, phi_z = WS.solve(samples, src, tol=ADE_TOL, max_iters=ADE_CAP, stream=stream)
     t_zero = time.perf_counter() - t0
     params, meta = WS.load()
     net = lbib.Net(samples[0].ny, samples[0].nx, 16, stream=stream)
@@ -79,7 +92,7 @@ def ade_half(samples, lbib, stream):
     t_pred = time.perf_counter() - t0
     net.close()
     t0 = time.perf_counter()
-    kw, _ = WS.solve(samples, src, phi0=phi_hat, tol=ADE_TOL, max_iters=ADE_CAP, stream=stream)
+    kw, phi_w = WS.solve(samples, src, phi0=phi_hat, tol=ADE_TOL, max_iters=ADE_CAP, stream=stream)
     t_warm = time.perf_counter() - t0
 
     def stats(k):
@@ -87,6 +100,7 @@ def ade_half(samples, lbib, stream):
         return {"median_iters": float(np.median(kk)), "mean_iters": round(float(kk.mean()), 1),
                 "unconverged": int((k == 0).sum())}
     z, wm = stats(k0), stats(kw)
+    true_err = ade_true_error(samples, phi_zero=phi_z, phi_warm=phi_w)
     return {"workload": "static tissue 256x256 walls-y, 50-300 Voronoi cells, seeded source cells, "
                         "D ~ U(0.02, 0.5), decay ~ U(1e-5, 1e-3), source 1e-3; held-out seeds",
             "samples": len(samples), "tol": ADE_TOL, "cap": ADE_CAP, "precision": "f64",
@@ -95,7 +109,33 @@ def ade_half(samples, lbib, stream):
             "speedup_mean": round(z["mean_iters"] / wm["mean_iters"], 3),
             "seconds": {"zero_start_solves": round(t_zero, 2), "prediction": round(t_pred, 3),
                         "warm_start_solves": round(t_warm, 2)},
-            "net": f"BF16 U-Net, {meta['samples']} training samples, {meta['epochs']} epochs"}
+            "net": f"BF16 U-Net, {meta['samples']} training samples, {meta['epochs']} epochs",
+            "true_error": true_err}
+
+
+def ade_true_error(samples, phi_zero, phi_warm):
+    """Relative L2 distance of the iterated steady states from the fixed points a sparse direct
+    solve of the D2Q5 equations gives (stored for the first held-out samples by
+    tests/golden/make_ade_goldens.py), against the asymptotic size tol / lambda of the error
+    the stopping rule leaves (slow modes decay by about 1 - lambda per iteration)."""
+    import numpy as np
+    path = os.path.join(GOLD, "ade_fixed_points.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    n = min(int(g["samples"]), len(samples))
+    rows = []
+    for i in range(n):
+        ref = g[f"phi_{i}"].astype(np.float64)
+        bound = ADE_TOL / float(g[f"decay_{i}"])
+        ez = float(np.linalg.norm(phi_zero[i] - ref) / np.linalg.norm(ref))
+        ew = float(np.linalg.norm(phi_warm[i] - ref) / np.linalg.norm(ref))
+        rows.append((ez, ew, ez / bound, ew / bound))
+    a = np.array(rows)
+    return {"samples": n, "reference": "sparse direct solve of the D2Q5 fixed point (FP64)",
+            "zero_start_rel_l2": {"median": float(np.median(a[:, 0])), "max": float(a[:, 0].max())},
+            "warm_start_rel_l2": {"median": float(np.median(a[:, 1])), "max": float(a[:, 1].max())},
+            "max_error_over_tol_per_decay": {"zero_start": float(a[:, 2].max()), "warm_start": float(a[:, 3].max())}}
 
 
 def sweep_workloads(n: int):
@@ -207,22 +247,86 @@ def storage_half(w, ref, warmup: int, steps: int, kt_steps: int, mlups32: float,
     return out
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, budget_s: float = 12.0, max_steps: int = 30):
+    """The FP64 oracle on the host: a bounded sample of the same workload on all the threads
+    OpenMP gives it and on one thread, and the tiny workload's whole 200-step run on both."""
     from oracle import oracle as O
+    from paper_1503_06726_amd import workloads as W
     log("cpu baseline: oracle on the same workload")
-    o = O.from_workload(w)
-    t0 = time.perf_counter()
-    n = 0
-    while n < max_steps:
-        o.step(1)
-        n += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
+    cores = O.threads()
+
+    def timed(wl, n_max, budget):
+        o = O.from_workload(wl)
+        t0 = time.perf_counter()
+        n = 0
+        while n < n_max:
+            o.step(1)
+            n += 1
+            if time.perf_counter() - t0 > budget:
+                break
+        return n, time.perf_counter() - t0
+
+    n, dt = timed(w, max_steps, budget_s)
+    O.set_threads(1)
+    n1, dt1 = timed(w, 3, 8.0)
+    tiny = W.tiny_cell()
+    nt1, tt1 = timed(tiny, tiny.steps, 60.0)
+    O.set_threads(cores)
+    ntc, ttc = timed(tiny, tiny.steps, 60.0)
     mlups = w.nx * w.ny * n / dt / 1e6
-    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"{n} steps of the same {w.nx}x{w.ny} workload ({w.n_cells} cells) in FP64, "
-                      f"{dt:.1f} s, OpenMP lattice loops"}
+                      f"{dt:.1f} s, OpenMP lattice loops on {cores} threads",
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": round(w.nx * w.ny * n1 / dt1 / 1e6, 3), "unit": "MLUPS", "cores": 1,
+                              "sample": f"{n1} steps of the same workload, {dt1:.1f} s"},
+            "tiny_full_run": {"workload": tiny.name, "steps": nt1,
+                              "seconds_one_thread": round(tt1, 3), "seconds_all_threads": round(ttc, 3),
+                              "mlups_one_thread": round(tiny.nx * tiny.ny * nt1 / tt1 / 1e6, 3),
+                              "mlups_all_threads": round(tiny.nx * tiny.ny * ntc / ttc / 1e6, 3)}}
+
+
+def oracle_field_errors(w, lbib, stream):
+    """Per-field error against the FP64 oracle after 100 and 1,000 steps of the large workload
+    for each population storage, on the seeded samples of tests/golden/horizon_large.npz (the
+    oracle's checkpoints): relative L2 of u, phi and X - X0, and of rho - rho0."""
+    import numpy as np
+    path = os.path.join(GOLD, "horizon_large.npz")
+    if not os.path.exists(path):
+        return None
+    g = np.load(path)
+    lat, nodes = g["lat_idx"], g["node_idx"]
+
+    def rel(a, b):
+        nb = float(np.linalg.norm(b))
+        return float(np.linalg.norm(a - b)) / (nb if nb > 0 else 1.0)
+    out = {"checkpoints": [100, 1000], "samples": {"lattice_nodes": int(lat.size), "membrane_nodes": int(nodes.size)}}
+    for name, st in (("fp32", lbib.STORAGE_FP32), ("fp16", lbib.STORAGE_FP16), ("bf16", lbib.STORAGE_BF16)):
+        sim = lbib.from_workload(w, stream=stream, storage=st)
+        res, done = {}, 0
+        for k in (100, 1000):
+            sim.step(k - done)
+            done = k
+            F = sim.get_fields(mask=False)
+            res[str(k)] = {"u": rel(F["u"].reshape(2, -1)[:, lat], g[f"u_{k}"]),
+                           "phi": rel(F["phi"].reshape(w.n_species, -1)[:, lat], g[f"phi_{k}"]),
+                           "X-X0": rel(F["xy"][nodes] - w.xy[nodes], g[f"dX_{k}"]),
+                           "rho-rho0": rel(F["rho"].reshape(-1)[lat] - w.rho0, g[f"drho_{k}"])}
+        sim.close()
+        out[name] = res
+        log(f"oracle errors {name}: {res}")
+    return out
 
 
 def main():
@@ -300,6 +404,18 @@ def main():
         if n:
             log(f"  {k:12s} {ms / n * 1e3:9.2f} us/launch  ({n} launches)")
 
+    # the FP64 sums of the monitor (lbib_reduce_device: the same two kernels), 50 enqueued back
+    # to back on the library's stream between two synchronisations (launch gaps included)
+    out_sums = torch.zeros(3 + S, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    sim.reduce_device(out_sums.data_ptr())
+    sim.sync()
+    t0 = time.perf_counter()
+    for _ in range(50):
+        sim.reduce_device(out_sums.data_ptr())
+    sim.sync()
+    reduce_us = (time.perf_counter() - t0) / 50 * 1e6
+
     # sanity: the state is finite after the timed run
     red = sim.reduce()
     ref = sim.get_fields(mask=False) if args.storage == "fp32" and not args.no_storage_variants else None
@@ -312,23 +428,35 @@ def main():
     b_lat = lattice_bytes_per_update(S, mask, pb)
     achieved = b_lat * nn / lat_s / 1e9
     b_step = step_bytes_per_update(S, mask, w.n_nodes, nn, pb)
+    traffic = None
+    if (args.storage == "fp32" and args.workload == "large" and LATTICE_TRAFFIC["bytes"]
+            and LATTICE_TRAFFIC["sources_sha256"] == lattice_sources_sha()):
+        traffic = LATTICE_TRAFFIC["bytes"]
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": LATTICE_TRAFFIC_BYTES if args.storage == "fp32" and args.workload == "large" else None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_lattice", "bytes_per_update": b_lat, "us_per_launch": round(lat_s * 1e6, 2),
             "step_bytes_per_update": round(b_step, 2),
             "step_frac": round(b_step * mlups * 1e6 / 1e9 / HBM_PEAK_GBS, 4)}
+    # the whole step against the same roofline (the survey's "% roofline": algorithmic bytes of
+    # the step, lattice pass plus node positions, times the measured update rate)
+    step_roof = {"bytes_per_update": round(b_step, 2), "achieved_GBs": round(b_step * mlups * 1e6 / 1e9, 1),
+                 "peak_GBs": HBM_PEAK_GBS, "frac": round(b_step * mlups * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
+                 "bytes_count": "8 (9 + 5 S) population bytes + 1/8 source bit + 16 N / (nx ny) node-position bytes"}
     out = {"metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic (seeded Voronoi tissue, SeedSequence(1503))",
            "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "n_cells": w.n_cells, "n_nodes": w.n_nodes,
                       "species": S, "tau": w.tau, "storage": f"{args.storage} population deviations, fp64 node positions"},
-           "roofline": roof,
+           "roofline": roof, "step_roofline": step_roof,
            "kernels_us": {k: round(ms / n * 1e3, 2) for k, (ms, n) in timings.items() if n},
+           "monitor_reduction_us": round(reduce_us, 2),
            "mass": red[0]}
     if ref is not None:
         out["storage_variants"] = storage_half(w, ref, args.warmup, args.steps, kt_steps, mlups, lbib, stream)
+        errs = oracle_field_errors(w, lbib, stream) if args.workload == "large" else None
+        if errs is not None:
+            out["storage_variants"]["rel_l2_vs_fp64_oracle"] = errs
     if samples:
         log(f"iterations to steady: {len(samples)} samples")
         out["ade_iters_to_steady"] = ade_half(samples, lbib, stream)

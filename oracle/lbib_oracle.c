@@ -997,6 +997,15 @@ void orc_get_forces(orc_ctx* c, double* F, double* area)
     orc_forces(&c->p, c->n_cells, c->off, c->X, c->l0, c->A0, F, area);
 }
 
+void orc_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads((int)n);
+#else
+    (void)n;
+#endif
+}
+
 int32_t orc_threads(void)
 {
 #ifdef _OPENMP

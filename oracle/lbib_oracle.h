@@ -104,6 +104,7 @@ void     orc_get_prev_moments(const orc_ctx* c, double* phi, double* u);
 void     orc_set_prev_moments(orc_ctx* c, const double* phi, const double* u);
 void     orc_no_flux_values(orc_ctx* c, int32_t s, double* out);
 int32_t  orc_threads(void);                               /* OpenMP threads the lattice loops use */
+void     orc_set_threads(int32_t n);                      /* set them (n > 0) */
 
 #ifdef __cplusplus
 }

@@ -94,6 +94,8 @@ def lib():
     L.orc_no_flux_values.argtypes = [C.c_void_p, C.c_int32, dp]
     L.orc_threads.restype = C.c_int32
     L.orc_threads.argtypes = []
+    L.orc_set_threads.restype = None
+    L.orc_set_threads.argtypes = [C.c_int32]
     _lib = L
     return L
 
@@ -134,6 +136,11 @@ def make_params(d: dict, interp_new_u: bool = False, wall_u_top: float = 0.0) ->
 def threads() -> int:
     """OpenMP threads the oracle's lattice loops run on (1 without OpenMP)."""
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the oracle's lattice loops on n OpenMP threads."""
+    lib().orc_set_threads(int(n))
 
 
 def delta1d(kernel: int, r: float) -> float:

@@ -33,6 +33,7 @@ def test_reduce_device_equals_reduce_on_two_calls():
         nv = 3 + w.n_species
         before = sim.device_bytes()
         out = torch.full((nv,), float("nan"), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()                       # the fill is done before the library writes
         sim.reduce_device(out.data_ptr())
         sim.sync()
         got = out.cpu().numpy()
