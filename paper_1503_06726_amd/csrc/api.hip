@@ -144,13 +144,21 @@ LatticeArgs lattice_args_at(lbib_ctx* c, int cur)
     for (int s = 0; s < 2; ++s) {
         const lbib_species& sp = p.species[s];
         const double tau_s = 3.0 * sp.D + 0.5;    // D = cs2 (tau_D - 1/2), cs2 = 1/3
-        a.omega_s[s] = s < c->S ? (float)(1.0 / tau_s) : 0.0f;
+        a.omega_s_d[s] = s < c->S ? 1.0 / tau_s : 0.0;
+        a.omega_s[s] = (float)a.omega_s_d[s];
+        a.phi_ref_d[s] = sp.phi_ref;
         a.phi_ref[s] = (float)sp.phi_ref;
         a.react[s] = s < c->S ? sp.reaction : 0;
-        for (int k = 0; k < 4; ++k) a.rc[s][k] = (float)sp.c[k];
+        for (int k = 0; k < 4; ++k) {
+            a.rc_d[s][k] = sp.c[k];
+            a.rc[s][k] = (float)sp.c[k];
+        }
     }
     a.bodyx = (float)p.body_accel[0];
     a.bodyy = (float)p.body_accel[1];
+    a.omega_d = 1.0 / p.tau;
+    a.bodyx_d = p.body_accel[0];
+    a.bodyy_d = p.body_accel[1];
     a.kernel = p.delta_kernel;
     a.t_off = c->n_cells ? c->d_t_off : nullptr;
     a.t_list = c->d_list;

@@ -29,6 +29,48 @@ namespace lbib {
 #define Q0 (1.0f / 3.0f)
 #define Q1 (1.0f / 6.0f)
 
+// Arithmetic of the fluid's moments and collision.  With FP32 storage it runs in FP64: in a
+// steadily forced flow every node's populations change by the same small increment each step,
+// so the FP32 rounding of the collision's intermediate products would repeat with the same
+// sign at every node and step and add up to a drift of the velocity (about 1e-5 relative after
+// 1,000 steps of a channel starting up under a body force, growing linearly); in FP64 only the
+// rounding of the stored deviations is left.  The same holds for a species fed by a steady
+// source.  The 16-bit storage forms keep FP32 arithmetic (their storage rounding is far
+// larger).
+template <int ST> struct Arith {
+    using T = float;
+    __device__ static float body(float f, double) { return f; }
+    __device__ static float fix(long long v) { return __ll2float_rn(v) * FIX_INV; }
+    __device__ static float c(float f, double) { return f; }
+};
+template <> struct Arith<0> {
+    using T = double;
+    __device__ static double body(float, double d) { return d; }
+    __device__ static double fix(long long v) { return (double)v * (double)FIX_INV; }   // exact below 2^53
+    __device__ static double c(float, double d) { return d; }
+};
+
+template <typename Rt> struct Moments {
+    Rt drho, rho, ux, uy;
+};
+// density deviation, density and velocity u = sum f v / rho of a node's D2Q9 deviations
+template <typename Rt>
+__device__ inline Moments<Rt> moments(const float f[9], float rho0)
+{
+    Rt fr[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fr[i] = (Rt)f[i];
+    Moments<Rt> m;
+    m.drho = ((fr[0] + fr[1]) + (fr[2] + fr[3])) + ((fr[4] + fr[5]) + (fr[6] + fr[7])) + fr[8];
+    m.rho = (Rt)rho0 + m.drho;
+    const Rt jx = (fr[1] - fr[3]) + (fr[5] - fr[6]) + (fr[8] - fr[7]);
+    const Rt jy = (fr[2] - fr[4]) + (fr[5] + fr[6]) - (fr[7] + fr[8]);
+    const Rt inv = (Rt)1 / m.rho;
+    m.ux = jx * inv;
+    m.uy = jy * inv;
+    return m;
+}
+
 struct Nbr {
     int y, ym, yp;        // rows y, y-1, y+1 (clamped at walls)
     int x, xm, xp;        // columns x, x-1, x+1 (periodic)
@@ -456,8 +498,9 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
     }
     if constexpr (NODES) load_records(a, cnd, cij, crc);
 
-    // moments of every row: rho^n, u^n = sum f v / rho
-    float rho_r[RP], drho_r[RP], ux_r[RP], uy_r[RP];
+    // moments of every row: rho^n, u^n = sum f v / rho (taken again by the collision from the
+    // same populations, so no FP64 value stays live across the coupling)
+    using Rt = typename Arith<ST>::T;
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
         if constexpr (MS) {
@@ -475,16 +518,9 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
                 for (int i = 5; i < 9; ++i) fr[i] = gm * (fr[i] - W5 * d);
             }
         }
-        const float* fr = f[r];
-        drho_r[r] = ((fr[0] + fr[1]) + (fr[2] + fr[3])) + ((fr[4] + fr[5]) + (fr[6] + fr[7])) + fr[8];
-        rho_r[r] = a.rho0 + drho_r[r];
-        const float jx = (fr[1] - fr[3]) + (fr[5] - fr[6]) + (fr[8] - fr[7]);
-        const float jy = (fr[2] - fr[4]) + (fr[5] + fr[6]) - (fr[7] + fr[8]);
-        const float inv = 1.0f / rho_r[r];
-        ux_r[r] = jx * inv;
-        uy_r[r] = jy * inv;
         if constexpr (NODES) {
-            us[lds_slot(t, r)] = make_float2(ux_r[r], uy_r[r]);
+            const Moments<Rt> mo = moments<Rt>(f[r], a.rho0);
+            us[lds_slot(t, r)] = make_float2((float)mo.ux, (float)mo.uy);
         }
     }
 
@@ -512,7 +548,8 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
             const int l = lds_slot(t, r);
             const float ex = a.bodyx + __ll2float_rn((long long)accx[l]) * FIX_INV;
             const float ey = a.bodyy + __ll2float_rn((long long)accy[l]) * FIX_INV;
-            us[l] = make_float2(ux_r[r] + 0.5f * ex, uy_r[r] + 0.5f * ey);
+            const float2 u0 = us[l];
+            us[l] = make_float2(u0.x + 0.5f * ex, u0.y + 0.5f * ey);
         }
         __syncthreads();
         couple_chunk<true, true, false>(a, x0, x1, y0, y1, cij0, crc0, cnd0, accx, accy, us, Ud);
@@ -547,46 +584,49 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
         if (!active[r]) continue;
-        float ex = a.bodyx, ey = a.bodyy;
+        // the spread force: fixed point to the arithmetic type (exact in FP64)
+        Rt ex = Arith<ST>::body(a.bodyx, a.bodyx_d), ey = Arith<ST>::body(a.bodyy, a.bodyy_d);
         if constexpr (NODES) {
             const int l = lds_slot(t, r);
-            ex += __ll2float_rn((long long)accx[l]) * FIX_INV;
-            ey += __ll2float_rn((long long)accy[l]) * FIX_INV;
+            ex += Arith<ST>::fix((long long)accx[l]);
+            ey += Arith<ST>::fix((long long)accy[l]);
         }
-        const float* fr = f[r];
-        const float drho = drho_r[r], rho = rho_r[r], ux = ux_r[r], uy = uy_r[r];
-        const float usq = 1.5f * (ux * ux + uy * uy);
-        const float om = a.omega, om1 = 1.0f - a.omega;
+        const float* fr = f[r];              // converted where used (exact)
+        const Moments<Rt> mo = moments<Rt>(f[r], a.rho0);
+        const Rt drho = mo.drho, rho = mo.rho, ux = mo.ux, uy = mo.uy;
+        const Rt usq = (Rt)1.5 * (ux * ux + uy * uy);
+        const Rt om = Arith<ST>::body(a.omega, a.omega_d), om1 = (Rt)1 - om;
+        const Rt w0 = Arith<ST>::c(W0, 4.0 / 9.0), w1 = Arith<ST>::c(W1, 1.0 / 9.0), w5 = Arith<ST>::c(W5, 1.0 / 36.0);
         // force term 3 w_i rho (v_i . e)
-        const float fx = 3.0f * rho * ex, fy = 3.0f * rho * ey;
+        const Rt fx = (Rt)3 * rho * ex, fy = (Rt)3 * rho * ey;
         if constexpr (MS) {
             // mass source S of the node's cell, added as S f_i^eq(1, u) (the added mass moves
             // with the fluid): the even part gains w_i S (1 + 4.5 vu^2 - 1.5 u^2), the odd part
             // w_i 3 S vu, so rho om becomes rr = rho om + S in both
-            float sig = 0.0f;
+            Rt sig = (Rt)0;
             if (cell[r] != ~0u) {
                 const unsigned k = cell[r];
-                sig = (float)(a.msrc + a.alpha * (a.A0[k] - a.area[k]));
+                sig = (Rt)(a.msrc + a.alpha * (a.A0[k] - a.area[k]));
                 a.cmap[(int64_t)n[r].y * a.nx + x] = ~0u;        // reset for the next step's claims
             }
             using T = typename Pop<ST>::T;
             constexpr int P = TILE_X;
             T* __restrict__ d = row_ptr((T*)a.fdst + (int64_t)n[r].y * a.frow, chunk_col(x, 9 * TILE_X));
-            const float rr = om * rho + sig, od0 = om * drho + sig, rs = 3.0f * rr;
-            store_nt(d, Pop<ST>::st(om1 * fr[0] + W0 * (od0 - rr * usq), SC9[0]));
-            float vu, ev, od;
-            vu = ux;      ev = W1 * (od0 + rr * (4.5f * vu * vu - usq)); od = W1 * (rs * vu + fx);
-            store_nt(d + P,     Pop<ST>::st(om1 * fr[1] + ev + od, SC9[1]));
-            store_nt(d + 3 * P, Pop<ST>::st(om1 * fr[3] + ev - od, SC9[3]));
-            vu = uy;      ev = W1 * (od0 + rr * (4.5f * vu * vu - usq)); od = W1 * (rs * vu + fy);
-            store_nt(d + 2 * P, Pop<ST>::st(om1 * fr[2] + ev + od, SC9[2]));
-            store_nt(d + 4 * P, Pop<ST>::st(om1 * fr[4] + ev - od, SC9[4]));
-            vu = ux + uy; ev = W5 * (od0 + rr * (4.5f * vu * vu - usq)); od = W5 * (rs * vu + fx + fy);
-            store_nt(d + 5 * P, Pop<ST>::st(om1 * fr[5] + ev + od, SC9[5]));
-            store_nt(d + 7 * P, Pop<ST>::st(om1 * fr[7] + ev - od, SC9[7]));
-            vu = uy - ux; ev = W5 * (od0 + rr * (4.5f * vu * vu - usq)); od = W5 * (rs * vu + fy - fx);
-            store_nt(d + 6 * P, Pop<ST>::st(om1 * fr[6] + ev + od, SC9[6]));
-            store_nt(d + 8 * P, Pop<ST>::st(om1 * fr[8] + ev - od, SC9[8]));
+            const Rt rr = om * rho + sig, od0 = om * drho + sig, rs = (Rt)3 * rr, c45 = (Rt)4.5;
+            store_nt(d, Pop<ST>::st((float)(om1 * fr[0] + w0 * (od0 - rr * usq)), SC9[0]));
+            Rt vu, ev, od;
+            vu = ux;      ev = w1 * (od0 + rr * (c45 * vu * vu - usq)); od = w1 * (rs * vu + fx);
+            store_nt(d + P,     Pop<ST>::st((float)(om1 * fr[1] + ev + od), SC9[1]));
+            store_nt(d + 3 * P, Pop<ST>::st((float)(om1 * fr[3] + ev - od), SC9[3]));
+            vu = uy;      ev = w1 * (od0 + rr * (c45 * vu * vu - usq)); od = w1 * (rs * vu + fy);
+            store_nt(d + 2 * P, Pop<ST>::st((float)(om1 * fr[2] + ev + od), SC9[2]));
+            store_nt(d + 4 * P, Pop<ST>::st((float)(om1 * fr[4] + ev - od), SC9[4]));
+            vu = ux + uy; ev = w5 * (od0 + rr * (c45 * vu * vu - usq)); od = w5 * (rs * vu + fx + fy);
+            store_nt(d + 5 * P, Pop<ST>::st((float)(om1 * fr[5] + ev + od), SC9[5]));
+            store_nt(d + 7 * P, Pop<ST>::st((float)(om1 * fr[7] + ev - od), SC9[7]));
+            vu = uy - ux; ev = w5 * (od0 + rr * (c45 * vu * vu - usq)); od = w5 * (rs * vu + fy - fx);
+            store_nt(d + 6 * P, Pop<ST>::st((float)(om1 * fr[6] + ev + od), SC9[6]));
+            store_nt(d + 8 * P, Pop<ST>::st((float)(om1 * fr[8] + ev - od), SC9[8]));
         } else {
             // equilibrium deviation w_i (drho + rho (3 vu + 4.5 vu^2 - 1.5 u^2)), vu = v_i . u,
             // for pairs of opposite directions: the part even in v_i is shared, the odd part
@@ -594,21 +634,21 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
             using T = typename Pop<ST>::T;
             constexpr int P = TILE_X;
             T* __restrict__ d = row_ptr((T*)a.fdst + (int64_t)n[r].y * a.frow, chunk_col(x, 9 * TILE_X));
-            const float rs = 3.0f * om * rho;
-            store_nt(d, Pop<ST>::st(om1 * fr[0] + om * W0 * (drho - rho * usq), SC9[0]));
-            float vu, ev, od;
-            vu = ux;      ev = om * W1 * (drho + rho * (4.5f * vu * vu - usq)); od = W1 * (rs * vu + fx);
-            store_nt(d + P,     Pop<ST>::st(om1 * fr[1] + ev + od, SC9[1]));
-            store_nt(d + 3 * P, Pop<ST>::st(om1 * fr[3] + ev - od, SC9[3]));
-            vu = uy;      ev = om * W1 * (drho + rho * (4.5f * vu * vu - usq)); od = W1 * (rs * vu + fy);
-            store_nt(d + 2 * P, Pop<ST>::st(om1 * fr[2] + ev + od, SC9[2]));
-            store_nt(d + 4 * P, Pop<ST>::st(om1 * fr[4] + ev - od, SC9[4]));
-            vu = ux + uy; ev = om * W5 * (drho + rho * (4.5f * vu * vu - usq)); od = W5 * (rs * vu + fx + fy);
-            store_nt(d + 5 * P, Pop<ST>::st(om1 * fr[5] + ev + od, SC9[5]));
-            store_nt(d + 7 * P, Pop<ST>::st(om1 * fr[7] + ev - od, SC9[7]));
-            vu = uy - ux; ev = om * W5 * (drho + rho * (4.5f * vu * vu - usq)); od = W5 * (rs * vu + fy - fx);
-            store_nt(d + 6 * P, Pop<ST>::st(om1 * fr[6] + ev + od, SC9[6]));
-            store_nt(d + 8 * P, Pop<ST>::st(om1 * fr[8] + ev - od, SC9[8]));
+            const Rt rs = (Rt)3 * om * rho, c45 = (Rt)4.5;
+            store_nt(d, Pop<ST>::st((float)(om1 * fr[0] + om * w0 * (drho - rho * usq)), SC9[0]));
+            Rt vu, ev, od;
+            vu = ux;      ev = om * w1 * (drho + rho * (c45 * vu * vu - usq)); od = w1 * (rs * vu + fx);
+            store_nt(d + P,     Pop<ST>::st((float)(om1 * fr[1] + ev + od), SC9[1]));
+            store_nt(d + 3 * P, Pop<ST>::st((float)(om1 * fr[3] + ev - od), SC9[3]));
+            vu = uy;      ev = om * w1 * (drho + rho * (c45 * vu * vu - usq)); od = w1 * (rs * vu + fy);
+            store_nt(d + 2 * P, Pop<ST>::st((float)(om1 * fr[2] + ev + od), SC9[2]));
+            store_nt(d + 4 * P, Pop<ST>::st((float)(om1 * fr[4] + ev - od), SC9[4]));
+            vu = ux + uy; ev = om * w5 * (drho + rho * (c45 * vu * vu - usq)); od = w5 * (rs * vu + fx + fy);
+            store_nt(d + 5 * P, Pop<ST>::st((float)(om1 * fr[5] + ev + od), SC9[5]));
+            store_nt(d + 7 * P, Pop<ST>::st((float)(om1 * fr[7] + ev - od), SC9[7]));
+            vu = uy - ux; ev = om * w5 * (drho + rho * (c45 * vu * vu - usq)); od = w5 * (rs * vu + fy - fx);
+            store_nt(d + 6 * P, Pop<ST>::st((float)(om1 * fr[6] + ev + od), SC9[6]));
+            store_nt(d + 8 * P, Pop<ST>::st((float)(om1 * fr[8] + ev - od), SC9[8]));
         }
 
         if constexpr (MASK)
@@ -642,47 +682,53 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
                     }
                 }
             }
-            float dphi[S], phi[S], R[S];
+            // the species' moments and collision, in the fluid's arithmetic type
+            Rt dphi[S], phi[S], rct[S];
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                dphi[s] = ((g[r][s][0] + g[r][s][1]) + (g[r][s][2] + g[r][s][3])) + g[r][s][4];
-                phi[s] = a.phi_ref[s] + dphi[s];
+                const float* gs = g[r][s];
+                dphi[s] = (((Rt)gs[0] + (Rt)gs[1]) + ((Rt)gs[2] + (Rt)gs[3])) + (Rt)gs[4];
+                phi[s] = Arith<ST>::body(a.phi_ref[s], a.phi_ref_d[s]) + dphi[s];
             }
             if constexpr (NF == 2) {
                 // what this collision sees, for the next step's replacement
                 const int64_t k = (int64_t)n[r].y * a.nx + x;
 #pragma unroll
-                for (int s = 0; s < S; ++s) a.nfphi_out[(int64_t)s * a.nn + k] = dphi[s];
-                a.nfu_out[k] = make_float2(ux, uy);
+                for (int s = 0; s < S; ++s) a.nfphi_out[(int64_t)s * a.nn + k] = (float)dphi[s];
+                a.nfu_out[k] = make_float2((float)ux, (float)uy);
             }
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 const float* c = a.rc[s];
+                const double* cd = a.rc_d[s];
+                const Rt c0 = Arith<ST>::body(c[0], cd[0]), c1 = Arith<ST>::body(c[1], cd[1]);
                 if (a.react[s] == 1) {
-                    R[s] = (m[r] != 0 ? c[0] : 0.0f) - c[1] * phi[s];
+                    rct[s] = (m[r] != 0 ? c0 : (Rt)0) - c1 * phi[s];
                 } else if (a.react[s] == 2 && S == 2) {
-                    const float u2v = phi[0] * phi[0] * phi[S - 1];
-                    R[s] = (s == 0) ? c[2] * (c[0] - phi[0] + u2v) : c[2] * (c[1] - u2v);
+                    const Rt c2 = Arith<ST>::body(c[2], cd[2]);
+                    const Rt u2v = phi[0] * phi[0] * phi[S - 1];
+                    rct[s] = (s == 0) ? c2 * (c0 - phi[0] + u2v) : c2 * (c1 - u2v);
                 } else {
-                    R[s] = 0.0f;
+                    rct[s] = (Rt)0;
                 }
             }
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                const float os = a.omega_s[s], os1 = 1.0f - a.omega_s[s];
-                const float p3 = 3.0f * phi[s];
+                const Rt os = Arith<ST>::body(a.omega_s[s], a.omega_s_d[s]), os1 = (Rt)1 - os;
+                const Rt p3 = (Rt)3 * phi[s];
+                const Rt q0 = Arith<ST>::c(Q0, 1.0 / 3.0), q1 = Arith<ST>::c(Q1, 1.0 / 6.0);
                 const float* gg = g[r][s];
                 using T = typename Pop<ST>::T;
                 constexpr int P = TILE_X;
                 T* __restrict__ d = row_ptr((T*)a.gdst + (int64_t)n[r].y * a.grow, chunk_col(x, a.gchunk) + 5 * s * P);
                 // equilibrium deviation w_i (dphi + 3 phi v_i . u) and reaction w_i R, by pairs of
                 // opposite directions (shared even part, odd part of changing sign)
-                const float ev = Q1 * (os * dphi[s] + R[s]), ox = Q1 * os * p3 * ux, oy = Q1 * os * p3 * uy;
-                store_nt(d,         Pop<ST>::st(os1 * gg[0] + Q0 * (os * dphi[s] + R[s]), SC5[0]));
-                store_nt(d + P,     Pop<ST>::st(os1 * gg[1] + ev + ox, SC5[1]));
-                store_nt(d + 2 * P, Pop<ST>::st(os1 * gg[2] + ev + oy, SC5[2]));
-                store_nt(d + 3 * P, Pop<ST>::st(os1 * gg[3] + ev - ox, SC5[3]));
-                store_nt(d + 4 * P, Pop<ST>::st(os1 * gg[4] + ev - oy, SC5[4]));
+                const Rt ev = q1 * (os * dphi[s] + rct[s]), ox = q1 * os * p3 * ux, oy = q1 * os * p3 * uy;
+                store_nt(d,         Pop<ST>::st((float)(os1 * gg[0] + q0 * (os * dphi[s] + rct[s])), SC5[0]));
+                store_nt(d + P,     Pop<ST>::st((float)(os1 * gg[1] + ev + ox), SC5[1]));
+                store_nt(d + 2 * P, Pop<ST>::st((float)(os1 * gg[2] + ev + oy), SC5[2]));
+                store_nt(d + 3 * P, Pop<ST>::st((float)(os1 * gg[3] + ev - ox), SC5[3]));
+                store_nt(d + 4 * P, Pop<ST>::st((float)(os1 * gg[4] + ev - oy), SC5[4]));
             }
         }
     }
@@ -696,15 +742,16 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
 }
 
 // Waves per SIMD the lattice pass is compiled for: the register budget that keeps the
-// population loads of RP rows in flight without spilling (96 VGPRs at two rows and one species,
-// for the single and the batched pass; a budget that spills costs far more than a wave).
-constexpr int lattice_waves(int S, int RP, bool)
+// population loads of RP rows in flight without spilling (96 VGPRs at two rows and one species
+// with FP32 arithmetic; the FP64 collision of the FP32 storage form needs 128; a budget that
+// spills costs far more than a wave).
+constexpr int lattice_waves(int S, int RP, int ST)
 {
-    return RP == 1 ? 6 : RP == 2 ? (S <= 1 ? 5 : 4) : 3;
+    return RP == 1 ? (ST == 0 ? 5 : 6) : RP == 2 ? ((S <= 1 && ST != 0) ? 5 : 4) : (ST == 0 ? 2 : 3);
 }
 
 template <int S, bool NODES, bool MASK, int ST, int NF = 0, bool MS = false, bool HF = false>
-__global__ __launch_bounds__(TILE_N) __attribute__((amdgpu_waves_per_eu(lattice_waves(S, RPT, false)))) void k_lattice(LatticeArgs a)
+__global__ __launch_bounds__(TILE_N) __attribute__((amdgpu_waves_per_eu(lattice_waves(S, RPT, ST)))) void k_lattice(LatticeArgs a)
 {
     lattice_tile<S, NODES, MASK, ST, RPT, NF, MS, HF>(a, tile_of_block((int)blockIdx.x, a.ntx, (a.ny + LTILE_Y - 1) / LTILE_Y));
 }
@@ -713,7 +760,7 @@ __global__ __launch_bounds__(TILE_N) __attribute__((amdgpu_waves_per_eu(lattice_
 // arguments come from a device table (independent lattices of any sizes in one launch), and
 // the tile height TILE_Y RP is a parameter of the launch.
 template <int S, bool NODES, bool MASK, int ST, int RP>
-__global__ __launch_bounds__(TILE_N) __attribute__((amdgpu_waves_per_eu(lattice_waves(S, RP, true)))) void k_lattice_batch(const LatticeArgs* __restrict__ tab,
+__global__ __launch_bounds__(TILE_N) __attribute__((amdgpu_waves_per_eu(lattice_waves(S, RP, ST)))) void k_lattice_batch(const LatticeArgs* __restrict__ tab,
                                                           const int2* __restrict__ work)
 {
     const int2 wk = work[blockIdx.x];

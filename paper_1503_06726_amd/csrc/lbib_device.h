@@ -80,9 +80,12 @@ struct LatticeArgs {
     int gchunk;                       // elements per chunk of the species array (5 S TILE_X)
     int nx, ny, walls, ntx;
     float omega, rho0;
+    double omega_d, bodyx_d, bodyy_d;   // the same in FP64 (the FP32-storage collision's arithmetic)
     float omega_s[2], phi_ref[2];
+    double omega_s_d[2], phi_ref_d[2];
     int react[2];
     float rc[2][4];
+    double rc_d[2][4];
     float bodyx, bodyy;
     int kernel;
     // immersed boundary: node lists per lattice tile, spreading records per node

@@ -53,7 +53,7 @@ def test_kernel_weights_match_closed_forms():
         exe = os.path.join(d, "weights")
         with open(src, "w") as f:
             f.write(SRC)
-        subprocess.run([_hipcc(), "-x", "hip", "--cuda-host-only", "-O1", "-std=c++17", "-I", CSRC, src, "-o", exe],
+        subprocess.run([_hipcc(), "-x", "hip", "--cuda-host-only", "-O1", "-std=c++17", "-I", CSRC, "-I", os.path.join(ROOT, "include"), src, "-o", exe],
                        check=True, capture_output=True)
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
     a = np.array([[float(v) for v in line.split()] for line in out.splitlines()])

@@ -53,7 +53,7 @@ def test_tile_order_is_a_permutation():
         exe = os.path.join(d, "tile_order")
         with open(src, "w") as f:
             f.write(SRC)
-        subprocess.run([_hipcc(), "-x", "hip", "--cuda-host-only", "-O1", "-std=c++17", "-I", CSRC, src, "-o", exe],
+        subprocess.run([_hipcc(), "-x", "hip", "--cuda-host-only", "-O1", "-std=c++17", "-I", CSRC, "-I", os.path.join(ROOT, "include"), src, "-o", exe],
                        check=True, capture_output=True)
         out = subprocess.run([exe], capture_output=True, text=True)
     assert out.returncode == 0, out.stdout
