@@ -925,7 +925,9 @@ __device__ inline void node_moments(const MomentArgs& a, int x, int y, double& d
         if (bit(n.xp, n.y) != me) miss |= 8u;
         if (!n.top && bit(n.x, n.yp) != me) miss |= 16u;
     }
-    for (int s = 0; s < a.S; ++s) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {          // constant indices: dphi stays in registers
+        if (s >= a.S) break;
         float g[5];
         pull5<ST>((const typename Pop<ST>::T*)a.g + 5 * s * TILE_X, a.grow, a.gchunk, n, g);
         if (miss && ((a.noflux >> s) & 1) && a.nfq) {
@@ -973,21 +975,37 @@ __global__ void k_moments(MomentArgs a)
 constexpr int RED_THREADS = 256;
 constexpr int RED_MAXV = 5;
 
+// Work items are 64-column segments of one lattice row, one wavefront per item (coalesced
+// rows, no per-node index division); a wavefront takes items w, w + W, w + 2W, ... (W the
+// wavefronts of the grid), four at a time so that their loads are in flight together.
 template <int ST>
 __global__ __launch_bounds__(RED_THREADS) void k_reduce_partial(MomentArgs a, double* partial)
 {
     __shared__ double sh[RED_MAXV][RED_THREADS];
+    constexpr int U = 4;
     const int nv = 3 + a.S;
     double acc[RED_MAXV] = {0, 0, 0, 0, 0};
-    const int64_t stride = (int64_t)gridDim.x * RED_THREADS;
-    for (int64_t idx = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; idx < a.nn; idx += stride) {
-        const int x = (int)(idx % a.nx), y = (int)(idx / a.nx);
-        double drho, jx, jy, dphi[2] = {0.0, 0.0};
-        node_moments<ST>(a, x, y, drho, jx, jy, dphi);
-        acc[0] += drho;
-        acc[1] += jx;
-        acc[2] += jy;
-        for (int s = 0; s < a.S; ++s) acc[3 + s] += dphi[s];
+    const int ncx = (a.nx + 63) / 64;
+    const int items = a.ny * ncx;
+    const int lane = threadIdx.x & 63;
+    const int wstride = (int)gridDim.x * (RED_THREADS / 64);
+    const int w0 = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (RED_THREADS / 64) + (int)(threadIdx.x >> 6));
+    for (int it0 = w0; it0 < items; it0 += U * wstride) {
+        double v[U][RED_MAXV];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int k = 0; k < RED_MAXV; ++k) v[u][k] = 0.0;
+            const int it = it0 + u * wstride;
+            if (it < items) {
+                const int y = it / ncx, x = (it - y * ncx) * 64 + lane;
+                if (x < a.nx) node_moments<ST>(a, x, y, v[u][0], v[u][1], v[u][2], &v[u][3]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < RED_MAXV; ++k) acc[k] += v[u][k];
     }
     for (int v = 0; v < nv; ++v) sh[v][threadIdx.x] = acc[v];
     __syncthreads();
