@@ -8,8 +8,10 @@
 // Tensors are NHWC with the channel count a multiple of 16.  A 3x3 convolution (zero padding,
 // stride 1) is an implicit GEMM: M = output pixels, N = output channels, K = 9 * Cin ordered
 // k = tap * Cin + ci with tap = 3 ky + kx reading the input at (y + ky - 1, x + kx - 1).
-// Weights are stored [Cout][9 Cin] (k contiguous).  MFMA 16x16x16 (bf16): lane l supplies
-// A[l % 16][4 (l / 16) + i] and B[4 (l / 16) + i][l % 16] and holds D[4 (l / 16) + i][l % 16].
+// Weights are stored [Cout][9 Cin] (k contiguous).  Convolutions whose input has a multiple of
+// 32 channels and every weight gradient run on MFMA 16x16x32 (below); the first layer's 16-channel
+// input takes MFMA 16x16x16 (bf16), where lane l supplies A[l % 16][4 (l / 16) + i] and
+// B[4 (l / 16) + i][l % 16] and holds D[4 (l / 16) + i][l % 16].
 #include "lbib_internal.h"
 
 #include <algorithm>
@@ -42,6 +44,15 @@ __device__ __host__ inline bf16 f2bf(float f)
 }
 
 constexpr int THREADS = 256;
+
+// Eight channels (16 bytes) at a time: every channel count is a multiple of 16.
+struct bf8 {
+    uint4 v;
+    __device__ float get(int q) const { return bf2f(((const bf16*)&v)[q]); }
+    __device__ void set(int q, float f) { ((bf16*)&v)[q] = f2bf(f); }
+};
+__device__ inline bf8 ld8(const bf16* p) { return bf8{*(const uint4*)p}; }
+__device__ inline void st8(bf16* p, const bf8& x) { *(uint4*)p = x.v; }
 
 // ---------------------------------------------------------------------------------------
 // 3x3 convolution, forward, LDS-tiled: a workgroup computes CT_BM = 128 output pixels x BN
@@ -166,16 +177,6 @@ __global__ __launch_bounds__(THREADS) void k_conv_tile(const bf16* __restrict__ 
     }
 }
 
-// ---------------------------------------------------------------------------------------
-// weight gradient, LDS-tiled: dW[co][k] += sum_p dZ[p][co] patch[p][k] for a tile of BM output
-// channels x 64 values of k over a chunk of pixels, 64 pixels per step.  Both operands are
-// staged transposed ([co][pixel], [k][pixel]) so that a lane's MFMA fragment is four
-// consecutive pixels; a staging thread moves 4 pixels x 8 channels and writes each channel's
-// four pixels with one 8-byte LDS store.  Each wave owns 16 values of k.  Chunks of pixels are
-// added atomically.  The first k tile also sums the bias gradient db[co] += sum_p dZ[p][co].
-// ---------------------------------------------------------------------------------------
-constexpr int WG_PX = 64;
-
 // four pixels' value of one channel, packed for one LDS store
 __device__ inline uint2 pack4(const uint4 v[4], int q)
 {
@@ -184,85 +185,363 @@ __device__ inline uint2 pack4(const uint4 v[4], int q)
     return make_uint2((uint32_t)e0 | ((uint32_t)e1 << 16), (uint32_t)e2 | ((uint32_t)e3 << 16));
 }
 
-template <int BM>
-__global__ __launch_bounds__(THREADS) void k_conv_wgrad_tile(const bf16* __restrict__ in, const bf16* __restrict__ dZ,
-                                                             float* __restrict__ dW, float* __restrict__ db, int P,
-                                                             int H, int Wd, int Cin, int Cout, int chunk)
+// ---------------------------------------------------------------------------------------
+// The same two products on gfx950's MFMA 16x16x32 (bf16), for channel counts that are multiples
+// of 32.  Lane l supplies A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16], i < 8 (16
+// bytes each, one LDS read), and holds D[4 (l / 16) + i][l % 16], i < 4.
+// ---------------------------------------------------------------------------------------
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ inline v4f mfma32(const bf16* a, const bf16* b, v4f c)
 {
-    constexpr int PR = WG_PX + 8;                                      // padded LDS row (pixels)
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(*(const v8bf*)a, *(const v8bf*)b, c, 0, 0, 0);
+}
+
+// 3x3 convolution, forward (and data gradient with flipped weights), Cin a multiple of 32: a
+// workgroup computes an 8 x 32 pixel tile of one image x BN output channels; wave w takes tile
+// rows 2w and 2w + 1 (four 16-pixel MFMA row tiles).  Per chunk of 32 input channels it stages
+// the tile's 10 x 34 halo of inputs (zero outside the image) and the chunk's weights of all nine
+// taps in LDS once, then runs the nine taps from LDS (each tap's A fragment is the halo shifted
+// by the tap), so every input is fetched once per chunk instead of once per tap.  LDS rows are
+// padded by 8 elements (16 bytes).  The output-channel tiles of one pixel tile run on the same
+// XCD one after another (consecutive workgroups go to the eight XCDs in turn), so the tile's
+// inputs come from that XCD's L2 after the first.
+constexpr int HT_Y = 8, HT_X = 32;
+constexpr int HT_HY = HT_Y + 2, HT_HX = HT_X + 2;
+constexpr int HT_ROW = 32 + 8;
+
+template <int BN, bool RELU, bool OUT_F32>
+__global__ __launch_bounds__(THREADS) void k_conv_halo(const bf16* __restrict__ in, const bf16* __restrict__ W,
+                                                       const float* __restrict__ bias, void* __restrict__ out, int H,
+                                                       int Wd, int Cin, int Cout, int ntiles)
+{
+    const int nct = Cout / BN;
+    const int xcd = (int)blockIdx.x & 7, rr = (int)blockIdx.x >> 3;
+    const int ptile = (rr / nct) * 8 + xcd;
+    if (ptile >= ntiles) return;
+    constexpr int NJ = BN / 16;
+    constexpr int APIECES = HT_HY * HT_HX * 4;                      // 16-byte pieces of the halo
+    constexpr int BPIECES = 9 * BN * 4;
+    __shared__ __attribute__((aligned(16))) bf16 As[HT_HY * HT_HX * HT_ROW];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[9 * BN * HT_ROW];
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    const int m = l & 15, kq = l >> 4;
+    const int tx_n = (Wd + HT_X - 1) / HT_X, ty_n = (H + HT_Y - 1) / HT_Y;
+    const int img = ptile / (tx_n * ty_n);
+    const int tr = ptile - img * tx_n * ty_n;
+    const int y0 = (tr / tx_n) * HT_Y, x0 = (tr % tx_n) * HT_X;
+    const int co0 = (rr % nct) * BN;
+    const int K = 9 * Cin;
+    const bf16* src = in + (int64_t)img * H * Wd * Cin;
+
+    // the chunk's pieces this thread moves: all loads of a chunk are issued before any is
+    // stored, and the next chunk's while the current one multiplies
+    constexpr int AT = (APIECES + THREADS - 1) / THREADS;
+    constexpr int BT = (BPIECES + THREADS - 1) / THREADS;
+    uint4 ra[AT], rb[BT];
+    auto fetch = [&](int c0) {
+#pragma unroll
+        for (int q = 0; q < AT; ++q) {
+            const int pc = t + q * THREADS;
+            const int hp = pc >> 2, c8 = (pc & 3) * 8;
+            const int hy = hp / HT_HX, hx = hp - hy * HT_HX;
+            const int y = y0 + hy - 1, x = x0 + hx - 1;
+            ra[q] = make_uint4(0u, 0u, 0u, 0u);
+            if (pc < APIECES && y >= 0 && y < H && x >= 0 && x < Wd)
+                ra[q] = *(const uint4*)(src + ((int64_t)y * Wd + x) * Cin + c0 + c8);
+        }
+#pragma unroll
+        for (int q = 0; q < BT; ++q) {
+            const int pc = t + q * THREADS;
+            const int r = pc >> 2, c8 = (pc & 3) * 8;                // r = tap * BN + co
+            const int tap = r / BN, co = r - tap * BN;
+            rb[q] = make_uint4(0u, 0u, 0u, 0u);
+            if (pc < BPIECES) rb[q] = *(const uint4*)(W + (int64_t)(co0 + co) * K + tap * Cin + c0 + c8);
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int q = 0; q < AT; ++q) {
+            const int pc = t + q * THREADS;
+            if (pc < APIECES) *(uint4*)(As + (pc >> 2) * HT_ROW + (pc & 3) * 8) = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < BT; ++q) {
+            const int pc = t + q * THREADS;
+            if (pc < BPIECES) *(uint4*)(Bs + (pc >> 2) * HT_ROW + (pc & 3) * 8) = rb[q];
+        }
+    };
+
+    v4f acc[4][NJ];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    fetch(0);
+    for (int c0 = 0; c0 < Cin; c0 += 32) {
+        stash();
+        __syncthreads();
+        if (c0 + 32 < Cin) fetch(c0 + 32);
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap % 3;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int hp = (2 * w + (i >> 1) + dy) * HT_HX + 16 * (i & 1) + m + dx;
+                const bf16* a = As + hp * HT_ROW + 8 * kq;
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+                    acc[i][j] = mfma32(a, Bs + (tap * BN + 16 * j + m) * HT_ROW + 8 * kq, acc[i][j]);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int co = co0 + 16 * j + m;
+        const float bv = bias ? bias[co] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int y = y0 + 2 * w + (i >> 1);
+            if (y >= H) continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int x = x0 + 16 * (i & 1) + 4 * kq + e;
+                if (x >= Wd) continue;
+                float v = acc[i][j][e] + bv;
+                if (RELU) v = fmaxf(v, 0.0f);
+                const int64_t po = ((int64_t)img * H + y) * Wd + x;
+                if (OUT_F32) ((float*)out)[po * Cout + co] = v;
+                else ((bf16*)out)[po * Cout + co] = f2bf(v);
+            }
+        }
+    }
+}
+
+// weight gradient on MFMA 16x16x32: dW[co][k] += sum_p dZ[p][co] patch[p][k] for a tile of BM
+// output channels x BK values of k over a chunk of pixels, PX pixels per step.  Both operands
+// are staged transposed ([co][pixel], [k][pixel]) so that a lane's fragment is eight
+// consecutive pixels; a staging piece is 4 pixels x 8 channels (four 16-byte loads, eight
+// 8-byte LDS stores), the threads take the step's pieces in turn, and the next step's pieces
+// are loaded while the current step multiplies.  Wave w owns k values [w BK / 4, (w + 1) BK / 4).
+// Chunks of pixels are added atomically.  The first k tile also sums the bias gradient
+// db[co] += sum_p dZ[p][co].  Workgroups are dealt so that all (k, co) tiles of one pixel chunk
+// run on the same XCD one after another (the GPU deals consecutive workgroups to its eight
+// XCDs in turn): the chunk's inputs and gradients then come from that XCD's L2 after the
+// first tile, not again from HBM.
+// ROWS: the image width is a multiple of PX and chunks hold whole PX-pixel row segments, so a
+// step's image and row are the same for the whole workgroup and a pixel's address is a row base
+// plus its column (the general form tracks every pixel's image, row and column).
+template <int BM, int BK, int PX, bool ROWS>
+__global__ __launch_bounds__(THREADS) void k_wgrad_m32(const bf16* __restrict__ in, const bf16* __restrict__ dZ,
+                                                       float* __restrict__ dW, float* __restrict__ db, int P, int H,
+                                                       int Wd, int Cin, int Cout, int chunk, int nkt, int tiles,
+                                                       int nchunk)
+{
+    __shared__ float bred[THREADS];
+    const int xcd = (int)blockIdx.x & 7, r = (int)blockIdx.x >> 3;
+    const int tile = r % tiles, ch = (r / tiles) * 8 + xcd;
+    if (ch >= nchunk) return;
+    const int kt = tile % nkt, ct = tile / nkt;
+    constexpr int PR = PX + 8;                                         // padded LDS row (pixels)
     constexpr int NI = BM / 16;
-    constexpr int NA = (WG_PX / 4) * (BM / 8);                         // dZ pieces (<= 128)
-    constexpr int NB = (WG_PX / 4) * 8;                                // patch pieces (128)
+    constexpr int NJ = BK / 64;                                        // 16-wide k tiles per wave
+    constexpr int PA = (PX / 4) * (BM / 8);                            // dZ pieces
+    constexpr int PB = (PX / 4) * (BK / 8);                            // patch pieces
+    constexpr int PT = (PA + PB + THREADS - 1) / THREADS;
     __shared__ __attribute__((aligned(16))) bf16 At[BM * PR];          // dZ^T
-    __shared__ __attribute__((aligned(16))) bf16 Bt[64 * PR];          // patch^T
+    __shared__ __attribute__((aligned(16))) bf16 Bt[BK * PR];          // patch^T
     const int t = threadIdx.x, l = t & 63, w = t >> 6;
     const int m = l & 15, kq = l >> 4;
     const int K = 9 * Cin;
-    const int k0 = blockIdx.x * 64, co0 = blockIdx.y * BM;
-    const int pbeg = blockIdx.z * chunk, pend = min(P, pbeg + chunk);
+    const int k0 = kt * BK, co0 = ct * BM;
+    const int pbeg = ch * chunk, pend = min(P, pbeg + chunk);
     const int hw = H * Wd;
-    v4f acc[NI];
+    v4f acc[NI][NJ];
 #pragma unroll
-    for (int i = 0; i < NI; ++i) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.0f;
-    const bool bias_tile = db && blockIdx.x == 0;
-    // the staging piece of this thread: threads [0, NA) move dZ, [128, 128 + NB) the patches
-    const bool isA = t < NA, isB = t >= 128 && t - 128 < NB;
-    const int pa = isA ? t : t - 128;
-    const int px4 = (pa / (isA ? BM / 8 : 8)) * 4;                     // first of the four pixels
-    const int cp = (pa % (isA ? BM / 8 : 8)) * 8;                      // first channel / k
-    int tap = 0, ci = 0;
-    if (isB && k0 + cp < K) {
-        tap = (k0 + cp) / Cin;
-        ci = k0 + cp - tap * Cin;
-    }
-    for (int pb = pbeg; pb < pend; pb += WG_PX) {
-        uint4 v[4];
+    const bool bias_tile = kt == 0;
+    // this thread's pieces: kind (0 dZ, 1 patch, 2 patch beyond K, -1 none), first pixel of the
+    // four, first channel (dZ) or k (patch), and the patch's tap offsets and input channel
+    // Piece order within each operand: four channel groups (64 contiguous bytes of one pixel)
+    // fastest, then the PX / 4 pixel quads, then the remaining channel groups.  A store
+    // instruction then writes four rows eight apart (two bank halves) x 16 pixel quads (128
+    // bytes): every bank twice, no conflicts; a load instruction reads whole 64-byte segments.
+    auto piece = [](int pc, int groups, int& quad, int& c8) {
+        const int lo = groups < 4 ? groups : 4;
+        const int rest = pc / lo;
+        quad = (rest % (PX / 4)) * 4;
+        c8 = ((rest / (PX / 4)) * lo + pc % lo) * 8;
+    };
+    int kind[PT], px4[PT], cp[PT], dyo[PT], dxo[PT], ci[PT];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            v[j] = make_uint4(0u, 0u, 0u, 0u);
-            const int p = pb + px4 + j;
-            if (p >= pend) continue;
-            if (isA) {
-                v[j] = *(const uint4*)(dZ + (int64_t)p * Cout + co0 + cp);
-            } else if (isB && k0 + cp < K) {
-                const int n = p / hw, rem = p - n * hw, y = rem / Wd, x = rem - y * Wd;
-                const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-                if (yy >= 0 && yy < H && xx >= 0 && xx < Wd)
-                    v[j] = *(const uint4*)(in + ((int64_t)(n * H + yy) * Wd + xx) * Cin + ci);
+    for (int q = 0; q < PT; ++q) {
+        const int pc = t + q * THREADS;
+        kind[q] = -1;
+        px4[q] = cp[q] = dyo[q] = dxo[q] = ci[q] = 0;
+        if (pc < PA) {
+            kind[q] = 0;
+            piece(pc, BM / 8, px4[q], cp[q]);
+        } else if (pc < PA + PB) {
+            const int pb = pc - PA;
+            piece(pb, BK / 8, px4[q], cp[q]);
+            kind[q] = 2;
+            if (k0 + cp[q] < K) {
+                kind[q] = 1;
+                const int tap = (k0 + cp[q]) / Cin;
+                ci[q] = k0 + cp[q] - tap * Cin;
+                dyo[q] = tap / 3 - 1;
+                dxo[q] = tap % 3 - 1;
             }
         }
-        if (isA) {
+    }
+    // image, row and column of each patch piece's first pixel, advanced by PX pixels per step
+    // (no division inside the loop)
+    int pn[PT], py[PT], pxx[PT];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) *(uint2*)(At + (cp + q) * PR + px4) = pack4(v, q);
-        } else if (isB) {
+    for (int q = 0; q < PT; ++q) {
+        const int p = pbeg + px4[q];
+        pn[q] = p / hw;
+        const int rem = p - pn[q] * hw;
+        py[q] = rem / Wd;
+        pxx[q] = rem - py[q] * Wd;
+    }
+    uint4 v[PT][4];
+    // row-segment form: the step's segment starts at pixel pb; (image row, first column) of it
+    int srow = pbeg / Wd, scol = pbeg - srow * Wd;
+    auto fetch_rows = [&](int pb) {
+        const int n = srow / H, y = srow - n * H;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) *(uint2*)(Bt + (cp + q) * PR + px4) = pack4(v, q);
+        for (int q = 0; q < PT; ++q) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[q][j] = make_uint4(0u, 0u, 0u, 0u);
+            if (kind[q] == 0) {
+                const bf16* r = dZ + (int64_t)(pb + px4[q]) * Cout + co0 + cp[q];
+                if (pb < pend)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) v[q][j] = *(const uint4*)(r + (int64_t)j * Cout);
+            } else if (kind[q] == 1) {
+                const int yy = y + dyo[q];
+                if (pb < pend && yy >= 0 && yy < H) {
+                    const bf16* r = in + (int64_t)(n * H + yy) * Wd * Cin + ci[q];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int xx = scol + px4[q] + j + dxo[q];
+                        if (xx >= 0 && xx < Wd) v[q][j] = *(const uint4*)(r + xx * Cin);
+                    }
+                }
+            }
+        }
+        scol += PX;
+        if (scol == Wd) {
+            scol = 0;
+            ++srow;
+        }
+    };
+    auto fetch = [&](int pb) {
+        if constexpr (ROWS) {
+            fetch_rows(pb);
+            return;
+        }
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            int n = pn[q], y = py[q], x = pxx[q];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                v[q][j] = make_uint4(0u, 0u, 0u, 0u);
+                const int p = pb + px4[q] + j;
+                if (p < pend) {
+                    if (kind[q] == 0) {
+                        v[q][j] = *(const uint4*)(dZ + (int64_t)p * Cout + co0 + cp[q]);
+                    } else if (kind[q] == 1) {
+                        const int yy = y + dyo[q], xx = x + dxo[q];
+                        if (yy >= 0 && yy < H && xx >= 0 && xx < Wd)
+                            v[q][j] = *(const uint4*)(in + ((int64_t)(n * H + yy) * Wd + xx) * Cin + ci[q]);
+                    }
+                }
+                if (++x == Wd) {
+                    x = 0;
+                    if (++y == H) {
+                        y = 0;
+                        ++n;
+                    }
+                }
+            }
+            // the next step's first pixel: PX on from this one
+            int xx = pxx[q] + PX;
+            while (xx >= Wd) {
+                xx -= Wd;
+                if (++py[q] == H) {
+                    py[q] = 0;
+                    ++pn[q];
+                }
+            }
+            pxx[q] = xx;
+        }
+    };
+    if constexpr (ROWS) (void)pn, (void)py, (void)pxx;
+    fetch(pbeg);
+    for (int pb = pbeg; pb < pend; pb += PX) {
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+            if (kind[q] < 0) continue;
+            bf16* dst = kind[q] == 0 ? At + cp[q] * PR + px4[q] : Bt + cp[q] * PR + px4[q];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) *(uint2*)(dst + c * PR) = pack4(v[q], c);
         }
         __syncthreads();
-        if (bias_tile && t < BM)
-            for (int px = 0; px < WG_PX; ++px) bsum += bf2f(At[t * PR + px]);
+        if (pb + PX < pend) fetch(pb + PX);
+        if (bias_tile) {
+            // NSEG threads per channel, each adding SEG pixels (a multiple of eight: one LDS read
+            // per eight)
+            constexpr int NSEG = (PX / 8) < (THREADS / BM) ? (PX / 8) : (THREADS / BM);
+            constexpr int SEG = PX / NSEG;
+            if (t / BM < NSEG) {
+                const bf16* r = At + (t % BM) * PR + (t / BM) * SEG;
 #pragma unroll
-        for (int r0 = 0; r0 < WG_PX; r0 += 16) {
-            const v4s b = *(const v4s*)(Bt + (16 * w + m) * PR + r0 + 4 * kq);
+                for (int q = 0; q < SEG; q += 8) {
+                    const bf8 x = ld8(r + q);
 #pragma unroll
-            for (int i = 0; i < NI; ++i) {
-                const v4s a = *(const v4s*)(At + (16 * i + m) * PR + r0 + 4 * kq);
-                acc[i] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[i], 0, 0, 0);
+                    for (int e = 0; e < 8; ++e) bsum += x.get(e);
+                }
+            }
+        }
+#pragma unroll
+        for (int r0 = 0; r0 < PX; r0 += 32) {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const bf16* b = Bt + (w * (BK / 4) + 16 * j + m) * PR + r0 + 8 * kq;
+#pragma unroll
+                for (int i = 0; i < NI; ++i) acc[i][j] = mfma32(At + (16 * i + m) * PR + r0 + 8 * kq, b, acc[i][j]);
             }
         }
         __syncthreads();
     }
-    const int k = k0 + 16 * w + m;
-    if (k < K)
 #pragma unroll
-        for (int i = 0; i < NI; ++i)
+    for (int j = 0; j < NJ; ++j) {
+        const int k = k0 + w * (BK / 4) + 16 * j + m;
+        if (k < K)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int co = co0 + 16 * i + 4 * kq + e;
-                if (acc[i][e] != 0.0f) atomicAdd(&dW[(int64_t)co * K + k], acc[i][e]);
-            }
-    if (bias_tile && t < BM && bsum != 0.0f) atomicAdd(&db[co0 + t], bsum);
+            for (int i = 0; i < NI; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int co = co0 + 16 * i + 4 * kq + e;
+                    if (acc[i][j][e] != 0.0f) atomicAdd(&dW[(int64_t)co * K + k], acc[i][j][e]);
+                }
+    }
+    if (bias_tile) {
+        // the THREADS / BM segments of each channel, added in segment order
+        bred[t] = bsum;
+        __syncthreads();
+        if (t < BM) {
+            float b = 0.0f;
+            for (int sgm = 0; sgm < THREADS / BM; ++sgm) b += bred[sgm * BM + t];
+            if (b != 0.0f) atomicAdd(&db[co0 + t], b);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -278,15 +557,6 @@ __global__ void k_pack_input(const float* __restrict__ src, bf16* __restrict__ d
     dst[i] = c < 8 ? f2bf(src[p * 8 + c]) : (bf16)0;
 }
 
-// The elementwise layers move eight channels (16 bytes) per thread: every channel count is a
-// multiple of 16.
-struct bf8 {
-    uint4 v;
-    __device__ float get(int q) const { return bf2f(((const bf16*)&v)[q]); }
-    __device__ void set(int q, float f) { ((bf16*)&v)[q] = f2bf(f); }
-};
-__device__ inline bf8 ld8(const bf16* p) { return bf8{*(const uint4*)p}; }
-__device__ inline void st8(bf16* p, const bf8& x) { *(uint4*)p = x.v; }
 
 // 2x2 average pool: [B][H][W][C] -> [B][H/2][W/2][C]
 __global__ void k_pool(const bf16* __restrict__ in, bf16* __restrict__ out, int B, int H, int Wd, int C)
@@ -540,7 +810,27 @@ bool conv_tile(hipStream_t s, const bf16* in, void* out, bool relu, bool out_f32
     return true;
 }
 
-// Cin and Cout are multiples of 16 (the activations' channel counts)
+template <int BN>
+bool conv_halo(hipStream_t s, const bf16* in, void* out, bool relu, bool out_f32, const bf16* W, const float* bias,
+               int B, int H, int Wd, int Cin, int Cout)
+{
+    const int ntiles = B * ((H + HT_Y - 1) / HT_Y) * ((Wd + HT_X - 1) / HT_X);
+    const dim3 grid((unsigned)((ntiles + 7) / 8 * 8 * (Cout / BN)));
+    if (out_f32) {
+        NET_K(hipLaunchKernelGGL((k_conv_halo<BN, false, true>), grid, dim3(THREADS), 0, s, in, W, bias, out, H, Wd,
+                                 Cin, Cout, ntiles));
+    } else if (relu) {
+        NET_K(hipLaunchKernelGGL((k_conv_halo<BN, true, false>), grid, dim3(THREADS), 0, s, in, W, bias, out, H, Wd,
+                                 Cin, Cout, ntiles));
+    } else {
+        NET_K(hipLaunchKernelGGL((k_conv_halo<BN, false, false>), grid, dim3(THREADS), 0, s, in, W, bias, out, H, Wd,
+                                 Cin, Cout, ntiles));
+    }
+    return true;
+}
+
+// Cin and Cout are multiples of 16 (the activations' channel counts); Cin a multiple of 32 takes
+// the halo-tiled MFMA 16x16x32 kernel
 bool conv_fwd(lbib_net* n, int l, const bf16* in, void* out, int B, bool relu, bool out_f32, const bf16* W,
               const float* bias, int Cin, int Cout)
 {
@@ -548,6 +838,11 @@ bool conv_fwd(lbib_net* n, int l, const bf16* in, void* out, int B, bool relu, b
     const int H = n->H / div, Wd = n->Wd / div;
     const int P = B * H * Wd;
     hipStream_t s = n->stream;
+    if (Cin % 32 == 0) {
+        if (Cout % 64 == 0) return conv_halo<64>(s, in, out, relu, out_f32, W, bias, B, H, Wd, Cin, Cout);
+        if (Cout % 32 == 0) return conv_halo<32>(s, in, out, relu, out_f32, W, bias, B, H, Wd, Cin, Cout);
+        return conv_halo<16>(s, in, out, relu, out_f32, W, bias, B, H, Wd, Cin, Cout);
+    }
     const bool k32 = Cin % 32 == 0;
     if (Cout % 64 == 0) return k32 ? conv_tile<64, 32>(s, in, out, relu, out_f32, W, bias, P, H, Wd, Cin, Cout)
                                    : conv_tile<64, 16>(s, in, out, relu, out_f32, W, bias, P, H, Wd, Cin, Cout);
@@ -596,6 +891,33 @@ bool forward(lbib_net* n, const float* inputs, int B)
     return ok;
 }
 
+// The weight-gradient tiling of layer l at batch B: output-channel and k tile sizes, pixels per
+// chunk and the number of chunks (about 2048 workgroups in all, at least ~1024 pixels each)
+struct WgradPlan {
+    int BM, BK, nkt, tiles, chunk, nchunk;
+    int px;                   // row-segment step (32, 64 or 128 pixels), 0: the general form
+};
+constexpr int WG_STEP_PX = 128;
+WgradPlan wgrad_plan(const lbib_net* n, int l, int B)
+{
+    const int div = LAYER_DIV[l];
+    const int P = B * (n->H / div) * (n->Wd / div);
+    const int Cout = LAYER_COUT[l], K = 9 * LAYER_CIN[l];
+    WgradPlan w;
+    w.BM = Cout >= 128 ? 128 : Cout;
+    w.BK = K >= 576 ? 128 : 64;
+    w.nkt = (K + w.BK - 1) / w.BK;
+    w.tiles = w.nkt * (Cout / w.BM);
+    const int Wd = n->Wd / div;
+    w.px = Wd % 128 == 0 ? 128 : Wd % 64 == 0 ? 64 : Wd % 32 == 0 ? 32 : 0;
+    const int step = w.px ? w.px : WG_STEP_PX;
+    w.nchunk = std::max(1, std::min(2048 / w.tiles, (P + 1023) / 1024));
+    w.chunk = (P + w.nchunk - 1) / w.nchunk;
+    w.chunk = (w.chunk + step - 1) / step * step;
+    w.nchunk = (P + w.chunk - 1) / w.chunk;
+    return w;
+}
+
 // gradient of convolution l: given dZ (gradient of its pre-activation output) and its input,
 // add to dW/db and, when din is set, write the input gradient
 bool conv_bwd(lbib_net* n, int l, const bf16* in, const bf16* dz, bf16* din, int B)
@@ -606,20 +928,29 @@ bool conv_bwd(lbib_net* n, int l, const bf16* in, const bf16* dz, bf16* din, int
     const int Cin = LAYER_CIN[l], Cout = LAYER_COUT[l], K = 9 * Cin;
     float* dW = n->grad + n->woff[l];
     float* db = n->grad + n->boff[l];
-    // pixel chunks: about 2048 workgroups in all, at least ~1024 pixels each
-    const int BM = Cout >= 64 ? 64 : Cout;
-    const int tiles = ((K + 63) / 64) * (Cout / BM);
-    int nchunk = std::max(1, std::min(2048 / tiles, (P + 1023) / 1024));
-    int chunk = (P + nchunk - 1) / nchunk;
-    chunk = (chunk + WG_PX - 1) / WG_PX * WG_PX;
-    nchunk = (P + chunk - 1) / chunk;
-    const dim3 grid((unsigned)((K + 63) / 64), (unsigned)(Cout / BM), (unsigned)nchunk);
-    if (BM == 64)
-        NET_K(hipLaunchKernelGGL(k_conv_wgrad_tile<64>, grid, dim3(THREADS), 0, s, in, dz, dW, db, P, H, Wd, Cin, Cout, chunk));
-    else if (BM == 32)
-        NET_K(hipLaunchKernelGGL(k_conv_wgrad_tile<32>, grid, dim3(THREADS), 0, s, in, dz, dW, db, P, H, Wd, Cin, Cout, chunk));
-    else
-        NET_K(hipLaunchKernelGGL(k_conv_wgrad_tile<16>, grid, dim3(THREADS), 0, s, in, dz, dW, db, P, H, Wd, Cin, Cout, chunk));
+    const WgradPlan pl = wgrad_plan(n, l, B);
+    const int BM = pl.BM, BK = pl.BK;
+    const dim3 grid((unsigned)(pl.tiles * ((pl.nchunk + 7) / 8) * 8));
+#define NET_WG(bm, bk, px, rows) NET_K(hipLaunchKernelGGL((k_wgrad_m32<bm, bk, px, rows>), grid, dim3(THREADS), 0, s, in, dz, dW, db, P, H, Wd, Cin, Cout, pl.chunk, pl.nkt, pl.tiles, pl.nchunk))
+#define NET_WG_BM(bk, px, rows)                          \
+    do {                                                 \
+        if (BM == 128) NET_WG(128, bk, px, rows);        \
+        else if (BM == 64) NET_WG(64, bk, px, rows);     \
+        else if (BM == 32) NET_WG(32, bk, px, rows);     \
+        else NET_WG(16, bk, px, rows);                   \
+    } while (0)
+#define NET_WG_BK(px, rows)                              \
+    do {                                                 \
+        if (BK == 128) NET_WG_BM(128, px, rows);         \
+        else NET_WG_BM(64, px, rows);                    \
+    } while (0)
+    if (pl.px == 0) NET_WG_BK(WG_STEP_PX, false);
+    else if (pl.px == 128) NET_WG_BK(128, true);
+    else if (pl.px == 64) NET_WG_BK(64, true);
+    else NET_WG_BK(32, true);
+#undef NET_WG_BK
+#undef NET_WG_BM
+#undef NET_WG
     if (din) {
         NET_K(hipLaunchKernelGGL(k_flip, dim3(nblk((int64_t)9 * Cin * Cout)), dim3(THREADS), 0, s, WB(n, l), n->wflip, Cin,
                                  Cout));
