@@ -248,6 +248,56 @@ def storage_half(w, ref, warmup: int, steps: int, kt_steps: int, mlups32: float,
     return out
 
 
+# the surrogate network's convolutions (input, output channels and resolution divisor of the 15
+# layers; the first layer's eight feature channels as the network defines them)
+NET_CIN = (8, 32, 32, 64, 64, 128, 128, 256, 256, 128, 128, 64, 64, 32, 32)
+NET_COUT = (32, 32, 64, 64, 128, 128, 256, 256, 128, 128, 64, 64, 32, 32, 16)
+NET_DIV = (1, 1, 2, 2, 4, 4, 8, 8, 4, 4, 2, 2, 1, 1, 1)
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def net_flops(h: int, w: int, batch: int):
+    """(forward, training step) FLOPs of the 3x3 convolutions: 2 x 9 Cin Cout per output
+    pixel; a training step is the forward pass, the data gradient of every layer but the first
+    and the weight gradient of every layer."""
+    f = [2 * 9 * ci * co * (h // d) * (w // d) for ci, co, d in zip(NET_CIN, NET_COUT, NET_DIV)]
+    return batch * sum(f), batch * (3 * sum(f) - f[0])
+
+
+def net_half(lbib, stream, h: int = 256, w: int = 256, batch: int = 16, steps: int = 20):
+    """Training steps and predictions of the warm-start network at the warm-start workload's
+    size (256 x 256, batch 16), random weights and inputs."""
+    import numpy as np
+    import torch
+    net = lbib.Net(h, w, batch, stream=stream)
+    rng = np.random.default_rng(1503)
+    net.set_params((0.05 * rng.standard_normal(net.n_params)).astype(np.float32))
+    x = torch.tensor(rng.random((batch, h, w, 8)), dtype=torch.float32, device="cuda")
+    y = torch.tensor(rng.random((batch, h, w)), dtype=torch.float32, device="cuda")
+    out = torch.empty((batch, h, w), dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        net.train_step(x.data_ptr(), y.data_ptr(), batch, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.train_step(x.data_ptr(), y.data_ptr(), batch, 1e-4)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        net.predict(x.data_ptr(), batch, out.data_ptr())
+    torch.cuda.synchronize()
+    dp = (time.perf_counter() - t0) / steps
+    net.close()
+    fw, tr = net_flops(h, w, batch)
+    return {"shape": f"{batch} x {h} x {w}", "train_step_ms": round(dt * 1e3, 3),
+            "train_TFLOPs": round(tr / dt / 1e12, 1), "train_frac_bf16_peak": round(tr / dt / 1e12 / BF16_PEAK_TFLOPS, 4),
+            "predict_ms": round(dp * 1e3, 3), "predict_TFLOPs": round(fw / dp / 1e12, 1),
+            "predict_frac_bf16_peak": round(fw / dp / 1e12 / BF16_PEAK_TFLOPS, 4),
+            "flops_count": "2 x 9 Cin Cout per output pixel of the 15 convolutions; training = forward + "
+                           "data gradients (all but the first layer) + weight gradients"}
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -348,14 +398,18 @@ def main():
     ap.add_argument("--sweep-steps", type=int, default=2000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only a plain device copy of 1 GiB (calibrates the HBM byte counters)")
+    ap.add_argument("--net-only", action="store_true",
+                    help="run only the warm-start network's training and prediction timing")
+    ap.add_argument("--no-net", action="store_true", help="skip the warm-start network's timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the lattice would shard into "
               "y-slabs across GPUs, which this build does not implement.", file=sys.stderr)
         sys.exit(2)
 
-    samples = [] if args.copy_probe else ade_samples(args.ade_samples)
-    sweep = [] if args.copy_probe else sweep_workloads(args.sweep_sims)
+    only = args.copy_probe or args.net_only
+    samples = [] if only else ade_samples(args.ade_samples)
+    sweep = [] if only else sweep_workloads(args.sweep_sims)
 
     import torch
     from paper_1503_06726_amd import lbib, workloads as W
@@ -370,6 +424,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log("copy probe: 5 copies of 2^30 bytes")
+        return
+    if args.net_only:
+        r = net_half(lbib, torch.cuda.current_stream().cuda_stream)
+        log(f"warm-start network: {r}")
+        print(json.dumps({"warmstart_net": r}), flush=True)
         return
     w = W.WORKLOADS[args.workload]()
     S = w.n_species
@@ -465,6 +524,9 @@ def main():
     if sweep:
         out["batched_sweep"] = sweep_half(sweep, args.sweep_steps, lbib, stream)
         log(f"  {out['batched_sweep']}")
+    if not args.no_net:
+        out["warmstart_net"] = net_half(lbib, stream)
+        log(f"  warm-start network: {out['warmstart_net']}")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
