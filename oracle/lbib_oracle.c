@@ -66,15 +66,19 @@
  *  - Mass sources and area control (Section "Control of Cell Area"; the supplement's
  *    parameter table makes the lattice source a density per node and step): every node
  *    of cell k in the domain map gains S_k = mass_source + area_alpha (A0_k - A_k) per
- *    step, A_k the shoelace area of the step's positions.  The paper does not say how the
- *    source enters the lattice Boltzmann equation; the added mass is taken to move with
- *    the local fluid, S_k f^eq_i(1, u) added after collision, so rho rises by S_k and u
+ *    step, A_k the shoelace area of the step's positions.  Validation Case III's source,
+ *    proportional to the species' concentration, adds mass_phi_gamma phi_0(x), phi_0 the
+ *    node's concentration of species 0 as its collision sees it (after the no-flux
+ *    replacement).  Case I's point source, and any other per-node source, is a map of
+ *    rates per node and step added wherever set (orc_set_node_sources).  The paper does not
+ *    say how a source enters the lattice Boltzmann equation; the added mass is taken to move
+ *    with the local fluid, S f^eq_i(1, u) added after collision, so rho rises by S and u
  *    is unchanged.
- *  - Pressure boundary (Suppl. "Pressure Boundary Condition for the Fluid Equations"),
- *    used as the iso-pressure outflow of the validation cases: the nodes of the lattice's
- *    outer ring hold the density rho0; at the start of each step their populations are
- *    multiplied by rho0 / rho (the velocity is unchanged).  Reported fields and sums are
- *    those after the rescaling.
+ *  - Pressure boundary (Suppl. "Pressure Boundary Condition for the Fluid Equations"): the
+ *    nodes of the lattice's outer ring (the iso-pressure outflow of the validation cases)
+ *    and any flagged lattice point (orc_set_pressure_nodes) hold the density rho0; at the
+ *    start of each step their populations are multiplied by rho0 / rho (the velocity is
+ *    unchanged).  Reported fields and sums are those after the rescaling.
  *  - ADE-only iteration (the steady-state measurement): the species lattices advance
  *    with u = 0 while the fluid, the membranes and the domain map stay frozen; the
  *    relative change after iteration k is ||phi^k - phi^{k-1}||_2 / ||phi^k||_2, with
@@ -114,6 +118,8 @@ struct orc_ctx {
     double *phi_prev;             /* [S][ny][nx] concentrations the previous collision saw */
     double *ux_prev, *uy_prev;    /* velocity the previous collision used */
     double *q;                    /* [4][ny][nx] wall distances of blocked links (first-order no-flux) */
+    double *nsrc;                 /* [ny][nx] mass source per node and step (point sources), NULL: none */
+    uint8_t *pmap;                /* [ny][nx] pressure points held at rho0, NULL: none */
 };
 
 static int64_t wrapi(int64_t i, int64_t n) { int64_t r = i % n; return r < 0 ? r + n : r; }
@@ -414,6 +420,7 @@ void orc_destroy(orc_ctx* c)
     free(c->off); free(c->X); free(c->F); free(c->l0); free(c->A0); free(c->area);
     free(c->src);
     free(c->phi_prev); free(c->ux_prev); free(c->uy_prev); free(c->q);
+    free(c->nsrc); free(c->pmap);
     free(c);
 }
 
@@ -497,6 +504,28 @@ void orc_set_source_cells(orc_ctx* c, const uint8_t* src)
     memcpy(c->src, src, (size_t)c->n_cells);
 }
 
+/* Point (or any per-node) mass sources: node x gains rate[x] per step, added as
+ * rate[x] f^eq_i(1, u) after the collision like the cells' sources; NULL removes them. */
+void orc_set_node_sources(orc_ctx* c, const double* rate)
+{
+    free(c->nsrc);
+    c->nsrc = NULL;
+    if (!rate) return;
+    c->nsrc = (double*)malloc(sizeof(double) * (size_t)c->nn);
+    memcpy(c->nsrc, rate, sizeof(double) * (size_t)c->nn);
+}
+
+/* Pressure points anywhere in the lattice (Suppl. "Pressure Boundary Condition for the Fluid
+ * Equations"): every flagged node is held at rho0 as the outer ring is; NULL removes them. */
+void orc_set_pressure_nodes(orc_ctx* c, const uint8_t* flags)
+{
+    free(c->pmap);
+    c->pmap = NULL;
+    if (!flags) return;
+    c->pmap = (uint8_t*)malloc((size_t)c->nn);
+    memcpy(c->pmap, flags, (size_t)c->nn);
+}
+
 /* The map the source/decay law reads: domain IDs of all cells, or, with a source subset,
  * nonzero exactly at the nodes inside at least one source cell (the same crossing test
  * over the source cells alone). */
@@ -531,11 +560,16 @@ void orc_source_map(orc_ctx* c, int32_t* out)
     source_map(c, out);
 }
 
+static int cell_sources(const orc_params* p)
+{
+    return p->mass_source != 0.0 || p->area_alpha != 0.0 || p->mass_phi_gamma != 0.0;
+}
+
 static int needs_mask(const orc_params* p)
 {
     for (int s = 0; s < p->n_species; ++s)
         if (p->reaction[s] == ORC_REACT_SOURCE_DECAY || (p->no_flux[s] && p->no_flux_zeroth)) return 1;
-    return p->mass_source != 0.0 || p->area_alpha != 0.0;
+    return cell_sources(p);
 }
 
 static int any_no_flux(const orc_params* p)
@@ -659,13 +693,19 @@ static int on_ring(const orc_params* p, int64_t x)
     return i == 0 || i == p->nx - 1 || j == 0 || j == p->ny - 1;
 }
 
-/* Pressure boundary: the populations of every ring node scaled by gamma = rho0 / rho, so the
- * node's density becomes rho0 and its velocity sum f v / sum f stays as it was. */
+/* is node x a pressure point: on the outer ring (pressure_ring) or flagged in the map? */
+static int pressure_node(const orc_ctx* c, int64_t x)
+{
+    return (c->p.pressure_ring && on_ring(&c->p, x)) || (c->pmap && c->pmap[x]);
+}
+
+/* Pressure boundary: the populations of every pressure point scaled by gamma = rho0 / rho, so
+ * the node's density becomes rho0 and its velocity sum f v / sum f stays as it was. */
 static void pressure_ring(orc_ctx* c)
 {
     int64_t nn = c->nn;
     for (int64_t x = 0; x < nn; ++x) {
-        if (!on_ring(&c->p, x)) continue;
+        if (!pressure_node(c, x)) continue;
         double r = 0.0;
         for (int i = 0; i < 9; ++i) r += c->f[i * nn + x];
         double gamma = c->p.rho0 / r;
@@ -679,8 +719,8 @@ static void step_once(orc_ctx* c)
     int64_t nx = p->nx, ny = p->ny, nn = c->nn;
     int S = p->n_species;
 
-    /* 0: pressure boundary on the outer ring */
-    if (p->pressure_ring) pressure_ring(c);
+    /* 0: pressure boundary on the outer ring and at the pressure points */
+    if (p->pressure_ring || c->pmap) pressure_ring(c);
 
     /* 1-2: forces and spreading */
     memset(c->ex, 0, sizeof(double) * (size_t)nn);
@@ -706,7 +746,7 @@ static void step_once(orc_ctx* c)
 
     /* the cell of every node for the mass sources: the domain map, or, when a source subset
      * narrowed that map, the crossing test over all cells */
-    const int mass = p->mass_source != 0.0 || p->area_alpha != 0.0;
+    const int mass = cell_sources(p);
     int32_t* cell_map = c->mask;
     if (mass && c->src) {
         cell_map = (int32_t*)malloc(sizeof(int32_t) * (size_t)nn);
@@ -727,19 +767,24 @@ static void step_once(orc_ctx* c)
             double force = r * W9[i] * (VX[i] * c->ex[x] + VY[i] * c->ey[x]) / CS2;
             c->f[i * nn + x] = fi - (fi - feq[i]) / p->tau + force;
         }
-        /* mass source of the node's cell (the map holds cell + 1), moving with the fluid */
-        if (mass && cell_map[x] > 0) {
-            int32_t k = cell_map[x] - 1;
-            double S_k = p->mass_source + p->area_alpha * (c->A0[k] - c->area[k]);
-            double e1[9];
-            orc_equilibrium9(1.0, vx, vy, e1);
-            for (int i = 0; i < 9; ++i) c->f[i * nn + x] += S_k * e1[i];
-        }
         for (int s = 0; s < S; ++s) {
             double sum = 0.0;
             for (int i = 0; i < 5; ++i) sum += c->g[(s * 5 + i) * nn + x];
             phi[s] = sum;
             c->phi_prev[s * nn + x] = sum;      /* read by the next step's no-flux replacement */
+        }
+        /* mass sources, moving with the fluid: the node's cell (the map holds cell + 1) gives
+         * S_k + mass_phi_gamma phi_0(x), the node-source map its own rate */
+        double Sx = 0.0;
+        if (mass && cell_map[x] > 0) {
+            int32_t k = cell_map[x] - 1;
+            Sx = p->mass_source + p->area_alpha * (c->A0[k] - c->area[k]) + p->mass_phi_gamma * phi[0];
+        }
+        if (c->nsrc) Sx += c->nsrc[x];
+        if (Sx != 0.0) {
+            double e1[9];
+            orc_equilibrium9(1.0, vx, vy, e1);
+            for (int i = 0; i < 9; ++i) c->f[i * nn + x] += Sx * e1[i];
         }
         c->ux_prev[x] = vx;
         c->uy_prev[x] = vy;
@@ -921,7 +966,7 @@ void orc_get_fields(orc_ctx* c, double* rho, double* u, double* phi, double* X, 
             double fi = c->f[i * nn + x];
             r += fi; jx += fi * VX[i]; jy += fi * VY[i];
         }
-        if (c->p.pressure_ring && on_ring(&c->p, x)) {
+        if (pressure_node(c, x)) {
             /* as the next step's rescaling leaves the node */
             double gamma = c->p.rho0 / r;
             r *= gamma; jx *= gamma; jy *= gamma;
@@ -1022,7 +1067,7 @@ void orc_invariants(const orc_ctx* c, double* out)
     long double m = 0.0L, px = 0.0L, py = 0.0L;
     for (int64_t x = 0; x < nn; ++x) {
         double gamma = 1.0;
-        if (c->p.pressure_ring && on_ring(&c->p, x)) {
+        if (pressure_node(c, x)) {
             double r = 0.0;
             for (int i = 0; i < 9; ++i) r += c->f[i * nn + x];
             gamma = c->p.rho0 / r;

@@ -57,6 +57,7 @@ typedef struct {
     int32_t no_flux[2];          /* 1: the cell membranes are no-flux boundaries for species s */
     double mass_source;          /* constant mass source per node inside a cell and step */
     double area_alpha;           /* area controller: S_k = mass_source + area_alpha (A0_k - A_k) */
+    double mass_phi_gamma;       /* + mass_phi_gamma phi_0(x) at every node inside a cell */
     int32_t pressure_ring;       /* 1: the lattice's outer ring is a pressure boundary at rho0 */
     int32_t interp_half_force;   /* 1: interpolate u + f/2 (the half-force-shifted velocity) */
     int32_t no_flux_zeroth;      /* 1: the zeroth-order form of the no-flux condition */
@@ -89,6 +90,8 @@ int32_t  orc_set_cells(orc_ctx* c, int32_t n_cells, const int32_t* off, const do
 void     orc_set_fields(orc_ctx* c, const double* rho, const double* u, const double* phi);
 void     orc_step(orc_ctx* c, int32_t n);
 void     orc_set_source_cells(orc_ctx* c, const uint8_t* src);     /* [n_cells] flags, NULL: all */
+void     orc_set_node_sources(orc_ctx* c, const double* rate);     /* [ny][nx] mass per node and step, NULL: none */
+void     orc_set_pressure_nodes(orc_ctx* c, const uint8_t* flags); /* [ny][nx] nodes held at rho0, NULL: none */
 void     orc_ade_step(orc_ctx* c, int32_t n, double* change);      /* ADE-only, u = 0; change [n][S] */
 void     orc_source_map(orc_ctx* c, int32_t* out);                  /* [ny][nx], nonzero inside a source cell */
 void     orc_get_fields(orc_ctx* c, double* rho, double* u, double* phi, double* X, int32_t* mask);

@@ -40,7 +40,7 @@ class Params(C.Structure):
                 ("k_spring", C.c_double), ("phi_m", C.c_double), ("kappa_area", C.c_double),
                 ("D", C.c_double * 2), ("reaction", C.c_int32 * 2),
                 ("rc", (C.c_double * 4) * 2), ("wall_u_top", C.c_double), ("no_flux", C.c_int32 * 2),
-                ("mass_source", C.c_double), ("area_alpha", C.c_double),
+                ("mass_source", C.c_double), ("area_alpha", C.c_double), ("mass_phi_gamma", C.c_double),
                 ("pressure_ring", C.c_int32), ("interp_half_force", C.c_int32),
                 ("no_flux_zeroth", C.c_int32), ("reserved", C.c_int32)]
 
@@ -80,6 +80,8 @@ def lib():
     L.orc_set_fields.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
     L.orc_step.argtypes = [C.c_void_p, C.c_int32]
     L.orc_set_source_cells.argtypes = [C.c_void_p, C.c_void_p]
+    L.orc_set_node_sources.argtypes = [C.c_void_p, C.c_void_p]
+    L.orc_set_pressure_nodes.argtypes = [C.c_void_p, C.c_void_p]
     L.orc_ade_step.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
     L.orc_source_map.argtypes = [C.c_void_p, C.c_void_p]
     L.orc_get_fields.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -127,6 +129,7 @@ def make_params(d: dict, interp_new_u: bool = False, wall_u_top: float = 0.0) ->
     p.wall_u_top = float(wall_u_top)
     p.mass_source = float(d.get("mass_source", 0.0))
     p.area_alpha = float(d.get("area_alpha", 0.0))
+    p.mass_phi_gamma = float(d.get("mass_phi_gamma", 0.0))
     p.pressure_ring = int(bool(d.get("pressure_ring", False)))
     p.interp_half_force = int(bool(d.get("interp_half_force", False)))
     p.no_flux_zeroth = int(bool(d.get("no_flux_zeroth", False)))
@@ -244,6 +247,16 @@ class Sim:
         a = None if src is None else np.ascontiguousarray(np.asarray(src) != 0, np.uint8)
         self.L.orc_set_source_cells(self.h, _ptr(a))
 
+    def set_node_sources(self, rate=None):
+        """[ny, nx] mass added per node and step (point sources), None: none."""
+        a = None if rate is None else np.ascontiguousarray(rate, np.float64).reshape(self.ny, self.nx)
+        self.L.orc_set_node_sources(self.h, _ptr(a))
+
+    def set_pressure_nodes(self, flags=None):
+        """[ny, nx] nodes held at rho0 (pressure points), None: none."""
+        a = None if flags is None else np.ascontiguousarray(np.asarray(flags) != 0, np.uint8).reshape(self.ny, self.nx)
+        self.L.orc_set_pressure_nodes(self.h, _ptr(a))
+
     def source_map(self) -> np.ndarray:
         """[ny, nx] int32, nonzero exactly inside a source cell (the source/decay law's map)."""
         m = np.zeros((self.ny, self.nx), np.int32)
@@ -332,6 +345,10 @@ def from_workload(w, **kw) -> Sim:
         s.set_cells(w.offsets, w.xy, w.rest_len, w.rest_area)
         if getattr(w, "source_cells", None) is not None:
             s.set_source_cells(w.source_cells)
+    if getattr(w, "node_sources", None) is not None:
+        s.set_node_sources(w.node_sources)
+    if getattr(w, "pressure_nodes", None) is not None:
+        s.set_pressure_nodes(w.pressure_nodes)
     if w.rho_init is not None or w.u_init is not None or w.phi_init is not None:
         s.set_fields(w.rho_init, w.u_init, w.phi_init)
     return s

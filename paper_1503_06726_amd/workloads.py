@@ -65,6 +65,7 @@ class Workload:
     species: list = field(default_factory=list)
     mass_source: float = 0.0        # constant mass source per node inside a cell and step
     area_alpha: float = 0.0         # area controller: S_k = mass_source + area_alpha (A0_k - A_k)
+    mass_phi_gamma: float = 0.0     # + mass_phi_gamma phi_0(x) inside cells (Case III's source)
     pressure_ring: bool = False     # the lattice's outer ring holds the density at rho0 (outflow)
     interp_half_force: bool = False  # membrane nodes move with the interpolated u + f/2
     no_flux_zeroth: bool = False    # no-flux membranes in the zeroth-order form
@@ -75,6 +76,8 @@ class Workload:
     rest_len: np.ndarray = None     # float64 [N] or None (initial); edge k joins node k and its successor
     rest_area: np.ndarray = None    # float64 [n_cells] or None (initial)
     source_cells: np.ndarray = None  # uint8 [n_cells] source cells of the source/decay law, None: all
+    node_sources: np.ndarray = None  # float64 [ny, nx] mass per node and step (point sources), None: none
+    pressure_nodes: np.ndarray = None  # uint8 [ny, nx] pressure points held at rho0, None: none
     # initial fields (None = rho0, u = 0, phi = phi_ref)
     rho_init: np.ndarray = None     # float64 [ny, nx]
     u_init: np.ndarray = None       # float64 [2, ny, nx]
@@ -99,6 +102,7 @@ class Workload:
                     species=[dict(D=s.D, phi_ref=s.phi_ref, reaction=s.reaction, c=tuple(s.c),
                                   no_flux=bool(s.no_flux)) for s in self.species],
                     mass_source=self.mass_source, area_alpha=self.area_alpha,
+                    mass_phi_gamma=self.mass_phi_gamma,
                     pressure_ring=self.pressure_ring, interp_half_force=self.interp_half_force,
                     no_flux_zeroth=self.no_flux_zeroth)
 

@@ -70,8 +70,8 @@ MUTANTS = {
     "no-flux boundary value without the missing weights": ("double phib = known / (1.0 - wm);", "double phib = known;"),
     "no-flux upstream neighbour reversed": ("int64_t yu = y - VY[i], xu = wrapi(x - VX[i], nx);",
                                             "int64_t yu = y + VY[i], xu = wrapi(x + VX[i], nx);"),
-    "area controller sign": ("p->mass_source + p->area_alpha * (c->A0[k] - c->area[k]);",
-                             "p->mass_source + p->area_alpha * (c->area[k] - c->A0[k]);"),
+    "area controller sign": ("p->mass_source + p->area_alpha * (c->A0[k] - c->area[k]) +",
+                             "p->mass_source + p->area_alpha * (c->area[k] - c->A0[k]) +"),
     "mass source added at rest": ("orc_equilibrium9(1.0, vx, vy, e1);", "orc_equilibrium9(1.0, 0.0, 0.0, e1);"),
     "no-flux extrapolation dropped": ("phib = ok2 ? 2.0 * ph[k1] - ph[k2] : ph[k1];", "phib = ok2 ? ph[k1] : ph[k1];"),
     "no-flux interpolation weight": ("double w = qq / (1.0 + qq);", "double w = 1.0 / (1.0 + qq);"),
@@ -84,6 +84,9 @@ MUTANTS = {
     "half-force shift sign": ("sh[x] = c->ux[x] + 0.5 * c->ex[x];", "sh[x] = c->ux[x] - 0.5 * c->ex[x];"),
     "pressure ring gamma inverted": ("double gamma = c->p.rho0 / r;\n        for (int i = 0; i < 9; ++i) c->f[i * nn + x] *= gamma;",
                                      "double gamma = r / c->p.rho0;\n        for (int i = 0; i < 9; ++i) c->f[i * nn + x] *= gamma;"),
+    "node source dropped": ("if (c->nsrc) Sx += c->nsrc[x];", "if (c->nsrc) Sx += 0.0 * c->nsrc[x];"),
+    "concentration source from the other species": ("+ p->mass_phi_gamma * phi[0];", "+ p->mass_phi_gamma * phi[1];"),
+    "pressure map ignored": ("|| (c->pmap && c->pmap[x]);", "|| (c->pmap && 0);"),
 }
 
 

@@ -924,3 +924,108 @@ def test_uniform_source_grows_a_cell_exponentially():
     closed, rho_closed = run(100, 10.0, 64, False)
     assert abs(rho_c - 1.0) < 3e-3 and rho_closed - 1.0 > 0.02
     assert closed[-1] < coarse[-1]
+
+
+def test_node_sources_add_exactly_their_mass():
+    """Per-node sources (point sources, validation Case I): every step adds the map's total to
+    the lattice's mass, S f^eq(1, u) at each node, and, with the fluid at rest, no momentum."""
+    nx, ny, n = 32, 24, 5
+    rate = np.zeros((ny, nx))
+    rate[5, 7] = 1e-3
+    rate[17, 20] = 2.5e-3
+    rate[0, 31] = 4e-4
+    o = O.Sim(dict(nx=nx, ny=ny, bc_y=0, tau=0.8, rho0=1.0))
+    o.set_node_sources(rate)
+    m0 = o.invariants()[0]
+    o.step(n)
+    inv = o.invariants()
+    assert abs(inv[0] - (m0 + n * rate.sum())) <= 1e-12 * m0
+    assert np.max(np.abs(inv[1:3])) < 1e-12 * m0
+    o.set_node_sources(None)                   # removed: mass stays
+    o.step(3)
+    assert abs(o.invariants()[0] - inv[0]) <= 1e-12 * m0
+
+
+def test_pressure_points_hold_rho0():
+    """Pressure points anywhere in the lattice (Suppl. "Pressure Boundary Condition for the
+    Fluid Equations"): a flagged interior node reports rho0 after every step, as the outer ring
+    does, and takes out part of the mass a point source puts in (a closed box without it keeps
+    all of it)."""
+    nx, ny = 40, 30
+    rate = np.zeros((ny, nx))
+    rate[8, 9] = 2e-3
+    pm = np.zeros((ny, nx), np.uint8)
+    pm[21, 30] = 1
+    o = O.Sim(dict(nx=nx, ny=ny, bc_y=1, tau=0.9, rho0=1.0))
+    o.set_node_sources(rate)
+    o.set_pressure_nodes(pm)
+    m0 = o.invariants()[0]
+    for _ in range(4):
+        o.step(250)
+        assert abs(o.get_fields()["rho"][21, 30] - 1.0) < 1e-14
+    kept = o.invariants()[0] - m0
+    assert 0.0 < kept < 0.8 * 1000 * rate.sum()
+    o.set_pressure_nodes(None)
+    m1 = o.invariants()[0]
+    o.step(100)
+    assert abs(o.invariants()[0] - m1 - 100 * rate.sum()) <= 1e-12 * m1
+
+
+def test_pressure_points_on_the_ring_equal_the_ring_option():
+    """A pressure map that flags exactly the outer ring gives the pressure_ring option's run bit
+    for bit (a source cell drives the flow)."""
+    n = 48
+    ring = np.zeros((n, n), np.uint8)
+    ring[0, :] = ring[-1, :] = ring[:, 0] = ring[:, -1] = 1
+    def run(use_map):
+        o = O.Sim(dict(nx=n, ny=n, bc_y=0, tau=1.0, mass_source=2e-3, pressure_ring=not use_map))
+        o.set_cells(np.array([0, 40], np.int32), _circle(40, n / 2 + 0.3, n / 2 - 0.3, 8.0))
+        if use_map:
+            o.set_pressure_nodes(ring)
+        o.step(60)
+        return o.get_fields(), o.invariants()
+    (Fa, ia), (Fb, ib) = run(False), run(True)
+    for k in ("rho", "u", "xy"):
+        np.testing.assert_array_equal(Fa[k], Fb[k])
+    np.testing.assert_array_equal(ia, ib)
+
+
+def test_concentration_source_adds_gamma_phi():
+    """Validation Case III's source: a node inside a cell gains mass_phi_gamma phi_0(x) per step,
+    phi_0 its concentration of species 0 as the collision sees it (the reported field, after
+    the no-flux replacement).  One step adds gamma times the species inside the cell."""
+    n, gamma = 40, 3e-3
+    cx, cy, R = 20.3, 19.7, 7.0
+    yy, xx = np.mgrid[0:n, 0:n]
+    phi = (1.0 + 0.2 * np.sin(0.3 * xx) * np.cos(0.2 * yy)) * (np.hypot(xx - cx, yy - cy) < R)
+    p = dict(nx=n, ny=n, bc_y=0, tau=1.0, rho0=1.0, mass_phi_gamma=gamma,
+             species=[dict(D=0.1, phi_ref=0.0, reaction=0, c=(0, 0, 0, 0), no_flux=True)])
+    o = O.Sim(p)
+    o.set_cells(np.array([0, 48], np.int32), _circle(48, cx, cy, R))
+    o.set_fields(phi=phi[None])
+    for _ in range(3):
+        F = o.get_fields()
+        inside = F["mask"] > 0
+        want = gamma * F["phi"][0][inside].sum()
+        m0 = o.invariants()[0]
+        o.step(1)
+        got = o.invariants()[0] - m0
+        assert abs(got - want) <= 1e-10 * want, (got, want)
+
+
+def test_point_source_grows_a_cell_linearly():
+    """Validation Case I in lattice units (level 0 of the supplement's table: a cell of diameter
+    10 in a 100 x 100 domain, tau = 1, the point source's 1e-2 per step at the centre node, the
+    boundary held at rho0): the area grows by the source's rate, A = A0 + 1e-2 t, within 2 % of
+    the increase over 300 steps (the membrane is a slightly leaky immersed boundary)."""
+    n, R, nodes = 100, 5.0, 63
+    cx, cy = n / 2 + 0.3, n / 2 - 0.3
+    rate = np.zeros((n, n))
+    rate[int(round(cy)), int(round(cx))] = 1e-2
+    o = O.Sim(dict(nx=n, ny=n, bc_y=0, tau=1.0, rho0=1.0, pressure_ring=True))
+    o.set_cells(np.array([0, nodes], np.int32), _circle(nodes, cx, cy, R))
+    o.set_node_sources(rate)
+    A0 = _shoelace(o.get_fields()["xy"])
+    o.step(300)
+    dA = _shoelace(o.get_fields()["xy"]) - A0
+    assert abs(dA / 3.0 - 1.0) < 0.02, dA
