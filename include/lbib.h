@@ -129,6 +129,12 @@ typedef struct {
      * (LBIB_EINVAL / LBIB_ESTATE). */
     double mass_source;      /* constant mass source per inside node and step (Case II's uniform source) */
     double area_alpha;       /* proportional constant alpha of the area controller, >= 0 */
+    /* Validation Case III (Section "Validation"): a uniform source inside the cell whose
+     * strength is proportional to the species' concentration.  Every node inside a cell gains
+     * mass_phi_gamma phi_0(x) per step as well, phi_0(x) its concentration of species 0 as its
+     * collision sees it (after a no-flux replacement).  Needs n_species >= 1 when nonzero; not
+     * with a source subset or a batch, as above. */
+    double mass_phi_gamma;
     /* Pressure boundary (Suppl. "Pressure Boundary Condition for the Fluid Equations"; the
      * iso-pressure outflow of the validation cases): with pressure_ring = 1 every node of the
      * lattice's outer ring (columns 0 and nx-1, rows 0 and ny-1) is a point of prescribed
@@ -211,7 +217,8 @@ lbib_status lbib_workspace_size(const lbib_params* p, int64_t n_nodes, size_t* b
  * Errors: LBIB_EINVAL for a misaligned pointer, memory that is not device memory of the
  * context's device, a range past the end of its allocation, or a range overlapping the
  * workspace currently bound; LBIB_ENOMEM when bytes is below what the current state needs;
- * LBIB_ESTATE while a batch has adopted the context.  On failure the context is unchanged. */
+ * LBIB_ESTATE while a batch has adopted the context, or while node sources or pressure points
+ * are set (they stay in the library's memory).  On failure the context is unchanged. */
 lbib_status lbib_bind_workspace(lbib_ctx* ctx, void* device_ptr, size_t bytes);
 
 /* Membrane nodes the bound workspace holds, or -1 when no workspace is bound. */
@@ -277,6 +284,23 @@ lbib_status lbib_get_spread(lbib_ctx* ctx, double* e);
  * mass sources are on: they read the same inside map.  Synchronises. */
 lbib_status lbib_set_source_cells(lbib_ctx* ctx, const uint8_t* src);
 
+/* Mass sources at lattice nodes (Section "Validation", Case I: a constant point mass source in
+ * the cell), and any other per-node source.  rate[ny][nx] (host, row-major, copied before
+ * return) is the mass added at each node per step; a node gains it as rate f_i^eq(1, u) after
+ * its collision, like a cell's source (see mass_source), whether or not it lies inside a cell.
+ * The rates are kept in FP32 on the device.  NULL removes them.  LBIB_EINVAL for a rate that
+ * is not finite in FP32; LBIB_ESTATE while a workspace is bound or a batch holds the context. */
+lbib_status lbib_set_node_sources(lbib_ctx* ctx, const double* rate);
+
+/* Pressure points anywhere in the lattice (Suppl. "Pressure Boundary Condition for the Fluid
+ * Equations": lattice points with prescribed pressure, the sinks of growing tissues).
+ * flags[ny][nx] (host, row-major, copied before return): every node with a nonzero flag is
+ * held at density rho0 as the outer ring is with pressure_ring (its streamed populations
+ * rescaled by rho0 / rho before the collision, the velocity unchanged; reported fields and
+ * sums those after the rescaling).  NULL removes them.  LBIB_ESTATE while a workspace is bound
+ * or a batch holds the context. */
+lbib_status lbib_set_pressure_nodes(lbib_ctx* ctx, const uint8_t* flags);
+
 /* ADE-only iterations towards the steady state of the species (the "iterations to steady"
  * measurement).  Every species lattice collides with u = 0 (equilibrium w_i phi) plus its
  * reaction and streams (D2Q5 equations, halfway bounce-back at walls) while the fluid, the
@@ -326,7 +350,8 @@ lbib_status lbib_ade_batch(int32_t nx, int32_t ny, int32_t bc_y, int32_t batch, 
  * the same simulation stepped alone, in either grouping; another tile height changes only the
  * grouping of the interpolation sums (round-off level).
  * While adopted, a context's own lbib_step, lbib_set_cells, lbib_set_fields,
- * lbib_set_source_cells and lbib_ade_steady return LBIB_ESTATE; its reads (lbib_get_fields,
+ * lbib_set_source_cells, lbib_set_node_sources, lbib_set_pressure_nodes and lbib_ade_steady
+ * return LBIB_ESTATE; its reads (lbib_get_fields,
  * lbib_get_forces, lbib_get_spread, lbib_reduce, lbib_sync) wait for the batch's last
  * enqueued work.  Destroying an adopted context leaves the batch unusable (LBIB_ESTATE).
  * --------------------------------------------------------------------------------------- */
@@ -336,8 +361,9 @@ typedef struct lbib_batch lbib_batch;
  * each with cells set, all with the same species count, storage type and source law).  Any
  * context between list rebuilds has its lists rebuilt first.  hip_stream as in lbib_create
  * (the batch's work runs there).  The contexts stay owned by the caller and must outlive the
- * batch.  LBIB_EINVAL for a bad set, and for a context with no-flux species, mass sources or
- * the pressure ring (the batched pass has none of them); *out is NULL on failure. */
+ * batch.  LBIB_EINVAL for a bad set, and for a context with no-flux species, mass sources
+ * (cell or node sources), the pressure ring or pressure points (the batched pass has none of
+ * them); *out is NULL on failure. */
 lbib_status lbib_batch_create(lbib_ctx* const* sims, int32_t n, void* hip_stream, lbib_batch** out);
 
 /* Enqueue n >= 0 steps of every simulation on the batch's stream (asynchronous). */
@@ -450,7 +476,8 @@ lbib_status lbib_reduce_device(lbib_ctx* ctx, double* out_device);
  * not a function of the node positions: the current populations of the fluid and species
  * lattices as stored (deviations in the storage type), the first-order no-flux condition's
  * previous-step concentrations and velocities, the cells (offsets, positions, rest lengths and
- * areas, source flags), the monitor's latest sums and period count, and the error flags.  On
+ * areas, source flags), the node sources and pressure points, the monitor's latest sums and
+ * period count, and the error flags.  On
  * loading, the forces, spreading records, per-tile node lists, inside-cell bits, cell map and
  * link cuts are rebuilt from the positions as lbib_set_cells builds them, and the lists start
  * a new period; the run then continues bit for bit as it would have (the list period decides
@@ -463,7 +490,9 @@ lbib_status lbib_reduce_device(lbib_ctx* ctx, double* out_device);
  *                    created with the same parameters (LBIB_EINVAL otherwise, or for a short or
  *                    foreign buffer); the cells are validated as by lbib_set_cells.  Synchronises;
  *                    LBIB_ESTATE while a batch has adopted the context.  A failure may leave the
- *                    cells replaced and the populations unchanged. */
+ *                    cells replaced and the populations unchanged.  A state with node sources
+ *                    or pressure points is refused with LBIB_ESTATE while a workspace is
+ *                    bound (the workspace does not hold them). */
 lbib_status lbib_state_size(lbib_ctx* ctx, size_t* bytes);
 lbib_status lbib_save_state(lbib_ctx* ctx, void* buf, size_t bytes);
 lbib_status lbib_load_state(lbib_ctx* ctx, const void* buf, size_t bytes);

@@ -176,6 +176,9 @@ LatticeArgs lattice_args_at(lbib_ctx* c, int cur)
     a.msrc = p.mass_source;
     a.alpha = p.area_alpha;
     a.pring = p.pressure_ring;
+    a.gamma = p.mass_phi_gamma;
+    a.nsrc = c->d_nsrc;
+    a.pmap = c->d_pmap;
     if (a.noflux && c->nfq[0]) {
         a.nfq = c->nfq[cur];
         a.nfm = c->nfm[cur];
@@ -401,6 +404,8 @@ void free_all(lbib_ctx* c)
         state_free(c, c->nfphi[b], (size_t)c->S * (size_t)c->nn);
         state_free(c, c->nfu[b], (size_t)c->nn);
     }
+    dev_free(c, c->d_nsrc, (size_t)c->nn);       // never in a workspace
+    dev_free(c, c->d_pmap, (size_t)c->nn);
     state_free(c, c->d_t_count, (size_t)c->tile_cap);
     state_free(c, c->d_t_off, (size_t)c->tile_cap + 1);
     state_free(c, c->d_t_cur, (size_t)c->tile_cap);
@@ -1218,9 +1223,10 @@ struct StateHeader {
     int32_t err, nf1;
     double mon[8];
     uint64_t bytes_f, bytes_g, bytes_nfphi, bytes_nfu;
+    uint64_t bytes_nsrc, bytes_pmap;     // node sources (FP32) and pressure points, 0 when unset
 };
 constexpr char STATE_MAGIC[8] = {'L', 'B', 'I', 'B', 'S', 'T', 'A', 'T'};
-constexpr int32_t STATE_VERSION = 1;
+constexpr int32_t STATE_VERSION = 2;
 
 void state_layout(const lbib_ctx* c, StateHeader& h)
 {
@@ -1237,6 +1243,55 @@ void state_layout(const lbib_ctx* c, StateHeader& h)
     h.bytes_g = c->S ? c->g_elems() * c->pop_bytes : 0;
     h.bytes_nfphi = h.nf1 ? (uint64_t)c->S * (uint64_t)c->nn * sizeof(float) : 0;
     h.bytes_nfu = h.nf1 ? (uint64_t)c->nn * sizeof(float2) : 0;
+    h.bytes_nsrc = c->d_nsrc ? (uint64_t)c->nn * sizeof(float) : 0;
+    h.bytes_pmap = c->d_pmap ? (uint64_t)c->nn : 0;
+}
+
+// Node sources: rate[nn] FP32 mass per node and step, any alignment (NULL removes them).
+lbib_status set_node_sources_f32(lbib_ctx* c, const void* rate)
+{
+    const size_t nn = (size_t)c->nn;
+    std::vector<float> r;
+    if (rate) {
+        r.resize(nn);
+        std::memcpy(r.data(), rate, nn * sizeof(float));
+        for (size_t i = 0; i < nn; ++i)
+            if (!std::isfinite(r[i])) {
+                c->err = "node source rate " + std::to_string(i) + " is not finite";
+                return LBIB_EINVAL;
+            }
+    }
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);                 // the captured launches hold the map (and the kernel form)
+    if (!rate) {
+        dev_free(c, c->d_nsrc, nn);
+        return LBIB_OK;
+    }
+    if (!c->d_nsrc) LBIB_TRY(dev_alloc(c, &c->d_nsrc, nn));
+    LBIB_HIP(c, hipMemcpyAsync(c->d_nsrc, r.data(), nn * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    return LBIB_OK;
+}
+
+// Pressure points: flags[nn], nonzero = held at rho0, stored as 0/1 (NULL removes them).
+lbib_status set_pressure_map(lbib_ctx* c, const uint8_t* flags)
+{
+    const size_t nn = (size_t)c->nn;
+    std::vector<uint8_t> m;
+    if (flags) {
+        m.resize(nn);
+        for (size_t i = 0; i < nn; ++i) m[i] = flags[i] ? 1 : 0;
+    }
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    if (!flags) {
+        dev_free(c, c->d_pmap, nn);
+        return LBIB_OK;
+    }
+    if (!c->d_pmap) LBIB_TRY(dev_alloc(c, &c->d_pmap, nn));
+    LBIB_HIP(c, hipMemcpyAsync(c->d_pmap, m.data(), nn, hipMemcpyHostToDevice, c->stream));
+    LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    return LBIB_OK;
 }
 
 size_t state_bytes(const StateHeader& h)
@@ -1245,7 +1300,7 @@ size_t state_bytes(const StateHeader& h)
     size_t b = sizeof(StateHeader) + h.bytes_f + h.bytes_g + h.bytes_nfphi + h.bytes_nfu;
     if (C) b += (C + 1) * sizeof(int32_t) + N * (2 * sizeof(double) + sizeof(double)) + C * sizeof(double);
     if (h.has_src) b += C;
-    return b;
+    return b + h.bytes_nsrc + h.bytes_pmap;
 }
 
 }  // namespace
@@ -1293,6 +1348,8 @@ lbib_status lbib_save_state(lbib_ctx* c, void* buf, size_t bytes)
         LBIB_HIP(c, take(c->d_A0, C * sizeof(double)));
         if (h.has_src) LBIB_HIP(c, take(c->d_src, C));
     }
+    LBIB_HIP(c, take(c->d_nsrc, h.bytes_nsrc));
+    LBIB_HIP(c, take(c->d_pmap, h.bytes_pmap));
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
     h.err = hd[0];
     std::memcpy(buf, &h, sizeof h);
@@ -1322,11 +1379,27 @@ lbib_status lbib_load_state(lbib_ctx* c, const void* buf, size_t bytes)
         c->err = "the saved state was made with other parameters";
         return LBIB_EINVAL;
     }
+    if ((h.bytes_nsrc && h.bytes_nsrc != (uint64_t)c->nn * sizeof(float)) ||
+        (h.bytes_pmap && h.bytes_pmap != (uint64_t)c->nn)) {
+        c->err = "the saved node maps do not fit the lattice";
+        return LBIB_EINVAL;
+    }
     if (bytes < state_bytes(h)) {
         c->err = "the buffer is shorter than the saved state";
         return LBIB_EINVAL;
     }
+    if ((h.bytes_nsrc || h.bytes_pmap) && c->ws) {
+        c->err = "node sources or pressure points cannot be loaded while a workspace is bound";
+        return LBIB_ESTATE;
+    }
     const char* q = (const char*)buf + sizeof(StateHeader) + h.bytes_f + h.bytes_g + h.bytes_nfphi + h.bytes_nfu;
+    // the node maps follow the cells
+    const char* qmaps = q;
+    if (h.n_cells)
+        qmaps += (h.n_cells + 1) * sizeof(int32_t) + h.n_nodes * 3 * sizeof(double) + h.n_cells * sizeof(double) +
+                 (h.has_src ? h.n_cells : 0);
+    LBIB_TRY(set_node_sources_f32(c, h.bytes_nsrc ? (const float*)qmaps : nullptr));
+    LBIB_TRY(set_pressure_map(c, h.bytes_pmap ? (const uint8_t*)(qmaps + h.bytes_nsrc) : nullptr));
     if (h.n_cells) {
         const size_t N = (size_t)h.n_nodes, C = (size_t)h.n_cells;
         std::vector<int32_t> off(C + 1);
@@ -1366,6 +1439,39 @@ lbib_status lbib_load_state(lbib_ctx* c, const void* buf, size_t bytes)
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
     c->period_count = h.period_count;
     return LBIB_OK;
+}
+
+lbib_status lbib_set_node_sources(lbib_ctx* c, const double* rate)
+{
+    if (!c) return LBIB_ESTATE;
+    LBIB_TRY(refuse_if_batched(c));
+    if (rate && c->ws) {
+        c->err = "node sources cannot be set while a workspace is bound";
+        return LBIB_ESTATE;
+    }
+    std::vector<float> r;
+    if (rate) {
+        r.resize((size_t)c->nn);
+        for (int64_t i = 0; i < c->nn; ++i) {
+            if (!std::isfinite(rate[i])) {
+                c->err = "node source rate " + std::to_string(i) + " is not finite";
+                return LBIB_EINVAL;
+            }
+            r[(size_t)i] = (float)rate[i];
+        }
+    }
+    return set_node_sources_f32(c, rate ? r.data() : nullptr);
+}
+
+lbib_status lbib_set_pressure_nodes(lbib_ctx* c, const uint8_t* flags)
+{
+    if (!c) return LBIB_ESTATE;
+    LBIB_TRY(refuse_if_batched(c));
+    if (flags && c->ws) {
+        c->err = "pressure points cannot be set while a workspace is bound";
+        return LBIB_ESTATE;
+    }
+    return set_pressure_map(c, flags);
 }
 
 lbib_status lbib_set_source_cells(lbib_ctx* c, const uint8_t* src)
@@ -1778,6 +1884,10 @@ lbib_status lbib_bind_workspace(lbib_ctx* c, void* device_ptr, size_t bytes)
             c->err = "the workspace extends past the end of its allocation";
             return LBIB_EINVAL;
         }
+    }
+    if (base && (c->d_nsrc || c->d_pmap)) {
+        c->err = "node sources or pressure points are set; the workspace does not hold them";
+        return LBIB_ESTATE;
     }
     int64_t cap = 0;
     if (base) {

@@ -391,7 +391,7 @@ lbib_status lbib_batch_create(lbib_ctx* const* sims, int32_t n, void* hip_stream
             c->err = "the batched pass has no no-flux membranes";
             return LBIB_EINVAL;
         }
-        if (mass_sources(c->p) || c->p.pressure_ring) {
+        if (mass_sources(c->p) || c->p.pressure_ring || c->d_nsrc || c->d_pmap) {
             c->err = "the batched pass has no mass sources or pressure boundaries";
             return LBIB_EINVAL;
         }

@@ -504,10 +504,12 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
         if constexpr (MS) {
-            // pressure boundary on the outer ring: f_i -> gamma f_i with gamma = rho0 / rho, in
-            // deviations d_i -> gamma (d_i - w_i drho); the velocity is unchanged
+            // pressure boundary on the outer ring and at the pressure points: f_i -> gamma f_i
+            // with gamma = rho0 / rho, in deviations d_i -> gamma (d_i - w_i drho); the
+            // velocity is unchanged
             const int y = y0 + t / TILE_X + r * TILE_Y;
-            if (a.pring && (x == 0 || x == a.nx - 1 || y == 0 || y == a.ny - 1)) {
+            const bool ring = a.pring && (x == 0 || x == a.nx - 1 || y == 0 || y == a.ny - 1);
+            if (ring || (a.pmap && a.pmap[(int64_t)n[r].y * a.nx + n[r].x])) {
                 float* fr = f[r];
                 const float d = ((fr[0] + fr[1]) + (fr[2] + fr[3])) + ((fr[4] + fr[5]) + (fr[6] + fr[7])) + fr[8];
                 const float gm = a.rho0 / (a.rho0 + d);
@@ -584,6 +586,38 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
 #pragma unroll
     for (int r = 0; r < RP; ++r) {
         if (!active[r]) continue;
+        if constexpr (S > 0) {
+            // populations that arrived across a no-flux membrane are replaced first: the
+            // concentration-driven mass source reads the replaced concentration
+            if constexpr (NF == 2) {
+                if (miss[r]) {
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        if ((a.noflux >> s) & 1) nf_first_replace(a, s, x, n[r].y, miss[r], g[r][s]);
+                }
+            }
+            if constexpr (NF == 1) {
+                // populations that arrived across a no-flux membrane become the equilibrium at
+                // the wall's zero velocity, w_i phi_b, phi_b the node's own concentration:
+                // in deviations, dphi_b = (sum of the arrived dg_j) / (1 - sum of missing w_i)
+                if (miss[r]) {
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        if (!((a.noflux >> s) & 1)) continue;
+                        float known = g[r][s][0], wm = 0.0f;
+#pragma unroll
+                        for (int i = 1; i < 5; ++i) {
+                            if ((miss[r] >> i) & 1u) wm += Q1;
+                            else known += g[r][s][i];
+                        }
+                        const float db = known / (1.0f - wm);
+#pragma unroll
+                        for (int i = 1; i < 5; ++i)
+                            if ((miss[r] >> i) & 1u) g[r][s][i] = Q1 * db;
+                    }
+                }
+            }
+        }
         // the spread force: fixed point to the arithmetic type (exact in FP64)
         Rt ex = Arith<ST>::body(a.bodyx, a.bodyx_d), ey = Arith<ST>::body(a.bodyy, a.bodyy_d);
         if constexpr (NODES) {
@@ -607,8 +641,18 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
             if (cell[r] != ~0u) {
                 const unsigned k = cell[r];
                 sig = (Rt)(a.msrc + a.alpha * (a.A0[k] - a.area[k]));
+                if constexpr (S > 0) {
+                    if (a.gamma != 0.0) {
+                        // + gamma phi_0(x), the species' concentration as its collision sees it
+                        // (summed as the species' moments below)
+                        const float* g0 = g[r][0];
+                        const Rt dphi0 = (((Rt)g0[0] + (Rt)g0[1]) + ((Rt)g0[2] + (Rt)g0[3])) + (Rt)g0[4];
+                        sig += (Rt)a.gamma * (Arith<ST>::body(a.phi_ref[0], a.phi_ref_d[0]) + dphi0);
+                    }
+                }
                 a.cmap[(int64_t)n[r].y * a.nx + x] = ~0u;        // reset for the next step's claims
             }
+            if (a.nsrc) sig += (Rt)a.nsrc[(int64_t)n[r].y * a.nx + x];
             using T = typename Pop<ST>::T;
             constexpr int P = TILE_X;
             T* __restrict__ d = row_ptr((T*)a.fdst + (int64_t)n[r].y * a.frow, chunk_col(x, 9 * TILE_X));
@@ -654,34 +698,6 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
         if constexpr (MASK)
             if ((x & 31) == 0) a.inside_clr[(int64_t)(y0 + t / TILE_X + r * TILE_Y) * a.wpr + (x >> 5)] = 0u;
         if constexpr (S > 0) {
-            if constexpr (NF == 2) {
-                if (miss[r]) {
-#pragma unroll
-                    for (int s = 0; s < S; ++s)
-                        if ((a.noflux >> s) & 1) nf_first_replace(a, s, x, n[r].y, miss[r], g[r][s]);
-                }
-            }
-            if constexpr (NF == 1) {
-                // populations that arrived across a no-flux membrane become the equilibrium at
-                // the wall's zero velocity, w_i phi_b, phi_b the node's own concentration:
-                // in deviations, dphi_b = (sum of the arrived dg_j) / (1 - sum of missing w_i)
-                if (miss[r]) {
-#pragma unroll
-                    for (int s = 0; s < S; ++s) {
-                        if (!((a.noflux >> s) & 1)) continue;
-                        float known = g[r][s][0], wm = 0.0f;
-#pragma unroll
-                        for (int i = 1; i < 5; ++i) {
-                            if ((miss[r] >> i) & 1u) wm += Q1;
-                            else known += g[r][s][i];
-                        }
-                        const float db = known / (1.0f - wm);
-#pragma unroll
-                        for (int i = 1; i < 5; ++i)
-                            if ((miss[r] >> i) & 1u) g[r][s][i] = Q1 * db;
-                    }
-                }
-            }
             // the species' moments and collision, in the fluid's arithmetic type
             Rt dphi[S], phi[S], rct[S];
 #pragma unroll
@@ -887,6 +903,7 @@ struct MomentArgs {
     int wpr;
     int noflux;                       // bit s: no-flux membranes for species s
     int pring;                        // the outer ring is held at rho0 (pressure boundary)
+    const uint8_t* pmap;              // pressure points held at rho0 (NULL: none)
     // no-flux membranes in the first-order form (nfq NULL: the zeroth-order form): the buffers
     // the next lattice pass reads
     const float* nfq;
@@ -906,8 +923,8 @@ __device__ inline void node_moments(const MomentArgs& a, int x, int y, double& d
     for (int i = 0; i < 9; ++i) drho += (double)f[i];
     jx = ((double)f[1] - f[3]) + ((double)f[5] - f[6]) + ((double)f[8] - f[7]);
     jy = ((double)f[2] - f[4]) + ((double)f[5] + f[6]) - ((double)f[7] + f[8]);
-    if (a.pring && (x == 0 || x == a.nx - 1 || y == 0 || y == a.ny - 1)) {
-        // the density the next collision sees on the pressure ring: rho0, momentum rescaled
+    if ((a.pring && (x == 0 || x == a.nx - 1 || y == 0 || y == a.ny - 1)) || (a.pmap && a.pmap[(int64_t)y * a.nx + x])) {
+        // the density the next collision sees at a pressure point: rho0, momentum rescaled
         const double gm = a.rho0 / (a.rho0 + drho);
         jx *= gm;
         jy *= gm;
@@ -1132,7 +1149,8 @@ template <int S, int ST>
 static hipError_t launch_lattice_s(lbib_ctx* c, const LatticeArgs& a, bool nodes, bool mask)
 {
     const bool hf = c->p.interp_half_force != 0;
-    const bool ms = (a.cmap && nodes) || a.pring;   // mass sources (the cell map) or pressure ring
+    // mass sources (the cell map), node sources, the pressure ring or pressure points
+    const bool ms = (a.cmap && nodes) || a.pring || a.nsrc || a.pmap;
     if constexpr (S > 0) {
         if (a.noflux && nodes) {
             if (a.nfq) return ms ? launch_form<S, ST, 2, true>(c, a, nodes, mask, hf)
@@ -1260,6 +1278,7 @@ static MomentArgs moment_args(lbib_ctx* c, double* out)
     a.wpr = c->wpr;
     a.noflux = c->n_cells ? no_flux_bits(c->p) : 0;
     a.pring = c->p.pressure_ring;
+    a.pmap = c->d_pmap;
     const bool nf1 = a.noflux && c->nfq[0];
     a.nfq = nf1 ? c->nfq[c->cur] : nullptr;
     a.nfm = nf1 ? c->nfm[c->cur] : nullptr;

@@ -105,7 +105,10 @@ struct LatticeArgs {
     const double* __restrict__ A0;
     const double* __restrict__ area;
     double msrc, alpha;
+    double gamma;                          // + gamma phi_0(x) at nodes inside a cell
     int pring;                             // the outer ring of nodes is held at density rho0
+    const float* __restrict__ nsrc;        // [ny][nx] mass per node and step (NULL: none)
+    const uint8_t* __restrict__ pmap;      // [ny][nx] pressure points held at rho0 (NULL: none)
     // no-flux membranes in the first-order form (nfq NULL: none): wall distances [4][nn] and
     // blocked-link bytes [nn] of this step's positions, the concentration deviations [S][nn] and
     // velocities [nn] the previous step's collision saw (read) and this step's (written)

@@ -78,6 +78,8 @@ struct lbib_ctx {
     float4* d_rec = nullptr;         // [N] spreading records (fractional offset, force)
     int* d_rec_ij = nullptr;         // [N] current stencil origins
     int* d_list = nullptr;           // [N * MAX_NODE_TILES] per-tile node lists
+    float* d_nsrc = nullptr;         // [ny][nx] mass source per node and step (NULL: none)
+    uint8_t* d_pmap = nullptr;       // [ny][nx] pressure points (NULL: none)
     int* d_t_count = nullptr;        // [tile_cap], zero between list builds
     int* d_t_off = nullptr;          // [tile_cap + 1]
     int* d_t_cur = nullptr;          // [tile_cap] fill cursors
@@ -142,7 +144,10 @@ inline int no_flux_bits(const lbib_params& p)
 inline bool no_flux_first(const lbib_params& p) { return no_flux_bits(p) != 0 && !p.no_flux_zeroth; }
 
 // does the step add mass inside the cells (constant source or area controller)?
-inline bool mass_sources(const lbib_params& p) { return p.mass_source != 0.0 || p.area_alpha != 0.0; }
+inline bool mass_sources(const lbib_params& p)
+{
+    return p.mass_source != 0.0 || p.area_alpha != 0.0 || p.mass_phi_gamma != 0.0;
+}
 
 // does a step read the cell areas (area pressure, area controller)?
 inline bool area_in_step(const lbib_params& p) { return p.kappa_area != 0.0 || mass_sources(p); }

@@ -31,7 +31,7 @@ lbib_status check_params(const lbib_params* p, std::string& msg)
         return fail(msg, "body_accel not finite");
     if (!std::isfinite(p->k_spring) || !std::isfinite(p->phi_m) || !std::isfinite(p->kappa_area))
         return fail(msg, "force-law constants not finite");
-    if (!std::isfinite(p->mass_source) || !std::isfinite(p->area_alpha))
+    if (!std::isfinite(p->mass_source) || !std::isfinite(p->area_alpha) || !std::isfinite(p->mass_phi_gamma))
         return fail(msg, "mass-source constants not finite");
     if (p->area_alpha < 0.0) return fail(msg, "area_alpha = %g must not be negative", p->area_alpha);
     if (p->pressure_ring != 0 && p->pressure_ring != 1)
@@ -46,6 +46,8 @@ lbib_status check_params(const lbib_params* p, std::string& msg)
     if (p->n_species < 0 || p->n_species > 2) return fail(msg, "n_species = %g outside 0..2", p->n_species);
     if (p->storage < LBIB_STORAGE_FP32 || p->storage > LBIB_STORAGE_BF16)
         return fail(msg, "storage %g unknown", p->storage);
+    if (p->mass_phi_gamma != 0.0 && p->n_species < 1)
+        return fail(msg, "mass_phi_gamma needs a species (its source reads species 0)");
     int n_sch = 0;
     for (int s = 0; s < p->n_species; ++s) {
         const lbib_species& sp = p->species[s];

@@ -35,7 +35,8 @@ EXPORTS = ["lbib_validate_params", "lbib_validate_cells", "lbib_create", "lbib_s
            "lbib_batch_set_tile", "lbib_batch_get_groups", "lbib_batch_set_groups", "lbib_batch_autotune",
            "lbib_batch_last_error", "lbib_batch_destroy",
            "lbib_workspace_size", "lbib_bind_workspace", "lbib_workspace_nodes", "lbib_reduce_device",
-           "lbib_get_monitor", "lbib_state_size", "lbib_save_state", "lbib_load_state"]
+           "lbib_get_monitor", "lbib_state_size", "lbib_save_state", "lbib_load_state",
+           "lbib_set_node_sources", "lbib_set_pressure_nodes"]
 
 
 class Species(C.Structure):
@@ -48,7 +49,7 @@ class Params(C.Structure):
                 ("tau", C.c_double), ("rho0", C.c_double), ("body_accel", C.c_double * 2),
                 ("k_spring", C.c_double), ("phi_m", C.c_double), ("kappa_area", C.c_double),
                 ("n_species", C.c_int32), ("storage", C.c_int32), ("species", Species * 2),
-                ("mass_source", C.c_double), ("area_alpha", C.c_double),
+                ("mass_source", C.c_double), ("area_alpha", C.c_double), ("mass_phi_gamma", C.c_double),
                 ("pressure_ring", C.c_int32), ("interp_half_force", C.c_int32),
                 ("no_flux_zeroth", C.c_int32), ("monitor_every", C.c_int32), ("reserved", C.c_int32)]
 
@@ -141,6 +142,10 @@ def lib():
     L.lbib_workspace_nodes.argtypes = [vp, C.POINTER(C.c_int64)]
     L.lbib_set_source_cells.restype = st
     L.lbib_set_source_cells.argtypes = [vp, vp]
+    L.lbib_set_node_sources.restype = st
+    L.lbib_set_node_sources.argtypes = [vp, vp]
+    L.lbib_set_pressure_nodes.restype = st
+    L.lbib_set_pressure_nodes.argtypes = [vp, vp]
     L.lbib_net_create.restype = st
     L.lbib_net_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, vp, C.POINTER(C.c_void_p)]
     L.lbib_net_param_count.restype = st
@@ -214,6 +219,7 @@ def make_params(d: dict) -> Params:
             p.species[s].c[k] = float(v)
     p.mass_source = float(d.get("mass_source", 0.0))
     p.area_alpha = float(d.get("area_alpha", 0.0))
+    p.mass_phi_gamma = float(d.get("mass_phi_gamma", 0.0))
     p.pressure_ring = int(bool(d.get("pressure_ring", False)))
     p.interp_half_force = int(bool(d.get("interp_half_force", False)))
     p.no_flux_zeroth = int(bool(d.get("no_flux_zeroth", False)))
@@ -372,8 +378,25 @@ class Simulation:
 
     def set_source_cells(self, src=None):
         """Cells whose interior the source/decay law treats as a source (None: every cell)."""
-        a = None if src is None else np.ascontiguousarray(np.asarray(src) != 0, np.uint8)
+        a = None if src is None else np.ascontiguousarray(np.asarray(src) != 0, np.uint8).ravel()
+        if a is not None and self.n_cells and a.size != self.n_cells:   # (no cells: LBIB_ESTATE)
+            raise ValueError(f"{self.n_cells} source flags are needed, not {a.size}")
         self._check(self.L.lbib_set_source_cells(self.h, _p(a)), "lbib_set_source_cells")
+
+    def set_node_sources(self, rate=None):
+        """Mass per node and step at every lattice node, [ny, nx] (point sources), None: none
+        (lbib_set_node_sources)."""
+        a = None if rate is None else np.ascontiguousarray(rate, np.float64)
+        if a is not None and a.shape != (self.ny, self.nx):
+            raise ValueError(f"node sources must have shape {(self.ny, self.nx)}, not {a.shape}")
+        self._check(self.L.lbib_set_node_sources(self.h, _p(a)), "lbib_set_node_sources")
+
+    def set_pressure_nodes(self, flags=None):
+        """Lattice points held at rho0, [ny, nx] flags, None: none (lbib_set_pressure_nodes)."""
+        a = None if flags is None else np.ascontiguousarray(np.asarray(flags) != 0, np.uint8)
+        if a is not None and a.shape != (self.ny, self.nx):
+            raise ValueError(f"pressure points must have shape {(self.ny, self.nx)}, not {a.shape}")
+        self._check(self.L.lbib_set_pressure_nodes(self.h, _p(a)), "lbib_set_pressure_nodes")
 
     def ade_steady(self, tol: float, max_iters: int, fp64: bool = True):
         """ADE-only iterations (u = 0, frozen fluid and membranes) until the relative change of
@@ -578,4 +601,8 @@ def from_workload(w, stream: int | None = None, storage: int | None = None) -> S
         s.set_cells(w.offsets, w.xy, w.rest_len, w.rest_area)
         if getattr(w, "source_cells", None) is not None:
             s.set_source_cells(w.source_cells)
+    if getattr(w, "node_sources", None) is not None:
+        s.set_node_sources(w.node_sources)
+    if getattr(w, "pressure_nodes", None) is not None:
+        s.set_pressure_nodes(w.pressure_nodes)
     return s

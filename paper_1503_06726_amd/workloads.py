@@ -271,6 +271,59 @@ def leakage_case(level: int, maxlength: float, steps: int | None = None) -> Work
     return _attach_geometry(w, offsets, xy)
 
 
+GROWTH_CASES = (1, 2, 3)        # the growth validations: point source, uniform source, phi-driven source
+
+
+def growth_case(case: int, level: int, maxlength: float = 0.5, steps: int | None = None) -> Workload:
+    """The growth validations (Section "Validation", Cases I-III, and their table of lattice
+    discretisations): a circular cell of diameter 10 * 2^level lattice units centred in a
+    lattice 100 * 2^level squared, tau = 1 for the fluid, one species with tau_D = 1
+    (D = 1/6) that starts at 1 inside the cell and 0 outside and sees the membrane as a no-flux
+    boundary, no membrane forces, the outer ring held at rho0 (iso-pressure outflow), and
+    10^4 * 4^level steps (one unit of non-dimensional time, dt = 1e-4 / 4^level).
+    ceil(pi D / maxlength) equally spaced nodes.  The cell grows by
+      case 1: a point source of 1e-2 lattice areas per step at the centre node (the tabulated
+              S^LB at every level), so A = A0 + 1e-2 t;
+      case 2: a uniform source ln 2 * dt per inside node and step, so A = A0 2^(t dt), doubling
+              in one unit of time;
+      case 3: a uniform source dt * phi per inside node and step (strength 1 times the
+              concentration), so A = A0 (1 + t dt) while the species is conserved."""
+    if case not in GROWTH_CASES:
+        raise ValueError("case must be 1, 2 or 3")
+    if not 0 <= level < LEAKAGE_LEVELS:
+        raise ValueError("level must be 0..3")
+    L = 100 * 2 ** level
+    D = 10.0 * 2 ** level
+    dt = 1e-4 / 4 ** level
+    n = int(math.ceil(math.pi * D / maxlength))
+    c = L / 2.0
+    offsets, xy = circle_cell(c, c, D / 2.0, n, 0.0, None)
+    yy, xx = np.mgrid[0:L, 0:L]
+    phi = (np.hypot(xx - c, yy - c) < D / 2.0).astype(np.float64)[None]
+    w = Workload(name=f"growth case {case} level {level}: {L}x{L}, one {n}-node circle of diameter {D:g}",
+                 nx=L, ny=L, bc_y=PERIODIC, tau=1.0, rho0=1.0, delta_kernel=DELTA_COS4,
+                 species=[Species(D=1.0 / 6.0, phi_ref=0.0, reaction=REACT_NONE, no_flux=True)],
+                 pressure_ring=True, steps=10000 * 4 ** level if steps is None else steps, phi_init=phi)
+    if case == 1:
+        w.node_sources = np.zeros((L, L))
+        w.node_sources[L // 2, L // 2] = 1e-2
+    elif case == 2:
+        w.mass_source = math.log(2.0) * dt
+    else:
+        w.mass_phi_gamma = dt
+    return _attach_geometry(w, offsets, xy)
+
+
+def growth_law(case: int, level: int, area0: float, t: float) -> float:
+    """The analytical area of ``growth_case(case, level)`` after t steps, from its initial area."""
+    dt = 1e-4 / 4 ** level
+    if case == 1:
+        return area0 + 1e-2 * t
+    if case == 2:
+        return area0 * 2.0 ** (t * dt)
+    return area0 * (1.0 + t * dt)
+
+
 def tissue(steps: int = 10000) -> Workload:
     """512x512, no-slip walls in y, periodic in x, tau = 0.8, 100 Voronoi cells at 0.5 lu
     node spacing, springs k = 0.02 at their initial lengths, body acceleration 1e-6 along x,

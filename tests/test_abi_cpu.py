@@ -40,12 +40,12 @@ def test_ctypes_layout_matches_header():
     #include <stddef.h>
     #include "lbib.h"
     int main(void) {
-      printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lbib_params), sizeof(lbib_species),
+      printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lbib_params), sizeof(lbib_species),
              offsetof(lbib_params, tau), offsetof(lbib_params, body_accel), offsetof(lbib_params, kappa_area),
              offsetof(lbib_params, n_species), offsetof(lbib_params, species), offsetof(lbib_species, c),
              offsetof(lbib_species, reaction), offsetof(lbib_params, mass_source), offsetof(lbib_params, area_alpha),
              offsetof(lbib_params, pressure_ring), offsetof(lbib_params, interp_half_force),
-             offsetof(lbib_params, no_flux_zeroth));
+             offsetof(lbib_params, no_flux_zeroth), offsetof(lbib_params, mass_phi_gamma));
       return 0; }
     """
     with tempfile.TemporaryDirectory() as d:
@@ -57,7 +57,8 @@ def test_ctypes_layout_matches_header():
     P, S = lbib.Params, lbib.Species
     want = [C.sizeof(P), C.sizeof(S), P.tau.offset, P.body_accel.offset, P.kappa_area.offset,
             P.n_species.offset, P.species.offset, S.c.offset, S.reaction.offset, P.mass_source.offset,
-            P.area_alpha.offset, P.pressure_ring.offset, P.interp_half_force.offset, P.no_flux_zeroth.offset]
+            P.area_alpha.offset, P.pressure_ring.offset, P.interp_half_force.offset, P.no_flux_zeroth.offset,
+            P.mass_phi_gamma.offset]
     assert vals == want
 
 
@@ -213,6 +214,42 @@ def test_mass_source_constants_validated():
         buf = C.create_string_buffer(256)
         assert lbib.lib().lbib_validate_params(C.byref(q), buf, 256) == lbib.EINVAL
         assert word in buf.value
+
+
+def test_concentration_source_validated():
+    """Case III's source (mass_phi_gamma) must be finite and needs a species to read."""
+    d = dict(W.growth_case(3, 0).params_dict())
+    assert d["mass_phi_gamma"] == 1e-4 and lbib.validate_params(d)[0] == lbib.OK
+    q = lbib.make_params(d)
+    q.mass_phi_gamma = float("nan")
+    buf = C.create_string_buffer(256)
+    assert lbib.lib().lbib_validate_params(C.byref(q), buf, 256) == lbib.EINVAL
+    assert b"mass-source" in buf.value
+    q = lbib.make_params(dict(d, species=[]))
+    assert q.mass_phi_gamma == 1e-4
+    assert lbib.lib().lbib_validate_params(C.byref(q), buf, 256) == lbib.EINVAL
+    assert b"mass_phi_gamma" in buf.value
+
+
+def test_growth_cases_follow_the_table():
+    """The growth validations' discretisation (Section "Validation", table of Cases I-III):
+    lattice 100 * 2^l, diameter 10 * 2^l, tau = tau_D = 1, 10^4 * 4^l steps, the point source's
+    1e-2 per step at every level; the laws double the area at T = 1 (Cases II, III) or add one
+    unit of area (Case I: 10^4 * 4^l * 1e-2 lattice areas = (10 * 2^l)^2 lattice areas)."""
+    for level in range(W.LEAKAGE_LEVELS):
+        for case in W.GROWTH_CASES:
+            w = W.growth_case(case, level)
+            L = 100 * 2 ** level
+            assert (w.nx, w.ny, w.tau, w.steps) == (L, L, 1.0, 10000 * 4 ** level)
+            assert abs(3.0 * w.species[0].D + 0.5 - 1.0) < 1e-15 and w.pressure_ring
+            A0 = math.pi * (5.0 * 2 ** level) ** 2
+            law = W.growth_law(case, level, A0, w.steps)
+            if case == 1:
+                assert w.node_sources.sum() == 1e-2 and w.node_sources[L // 2, L // 2] == 1e-2
+                assert abs(law - A0 - (10.0 * 2 ** level) ** 2) < 1e-9 * A0
+            else:
+                assert abs(law / A0 - 2.0) < 1e-12
+            assert (w.mass_source != 0) == (case == 2) and (w.mass_phi_gamma != 0) == (case == 3)
 
 
 def test_workspace_size_holds_the_cell_map_of_mass_sources():

@@ -5,7 +5,8 @@ Bars:
   * resume is exact: a run of 2n steps and a run of n steps, saved, loaded into a new context
     and stepped n more, agree bit for bit in rho, u, phi, the node positions and the domain-ID
     map (n = 37: the save falls inside a list period and a graph period), for the plain path,
-    both no-flux forms, mass sources with the pressure ring, FP16 storage and the monitor;
+    both no-flux forms, mass sources with the pressure ring, node sources and pressure points
+    (brought by the state into a context without them), FP16 storage and the monitor;
   * the monitor's sums, taken inside the captured step graphs every monitor_every steps, equal
     lbib_reduce's for the same state bit for bit, and the oracle's invariants within the
     reduction test's bars, on the tiny and tissue workloads;
@@ -40,7 +41,19 @@ def resume_cases():
         "no-flux zeroth-order": lambda: _set(W.no_flux_tissue(static=False), no_flux_zeroth=True),
         "mass sources and ring": lambda: _set(W.mass_source_tissue(no_flux=True), pressure_ring=True),
         "half-force": lambda: _set(walls(), interp_half_force=True),
+        "node maps": lambda: _maps(W.growth_case(3, 0)),
     }
+
+
+def _maps(w):
+    """Case III's cell with a point source and interior pressure points as well: the loaded
+    context has no maps of its own, so the state must bring them."""
+    w.node_sources = np.zeros((w.ny, w.nx))
+    w.node_sources[w.ny // 2, w.nx // 2] = 1e-2
+    w.node_sources[20, 70] = -2e-3
+    w.pressure_nodes = np.zeros((w.ny, w.nx), np.uint8)
+    w.pressure_nodes[80, 30] = w.pressure_nodes[15, 15] = 1
+    return w
 
 
 def _set(w, **kw):
@@ -59,6 +72,10 @@ def _sim(w, storage=None, monitor=0):
         s.set_cells(w.offsets, w.xy, w.rest_len, w.rest_area)
         if w.source_cells is not None:
             s.set_source_cells(w.source_cells)
+    if w.node_sources is not None:
+        s.set_node_sources(w.node_sources)
+    if w.pressure_nodes is not None:
+        s.set_pressure_nodes(w.pressure_nodes)
     if w.rho_init is not None or w.u_init is not None or w.phi_init is not None:
         s.set_fields(w.rho_init, w.u_init, w.phi_init)
     return s
