@@ -154,6 +154,16 @@ typedef struct {
      * (LBIB_EINVAL). */
     int32_t interp_half_force;   /* 0 or 1 */
     int32_t no_flux_zeroth;  /* 0: the first-order no-flux condition; 1: its zeroth-order form */
+    /* The bounce-back form of the no-flux condition (0 or 1; with no_flux_zeroth = 0).  Not the
+     * supplement's equilibrium replacement: a population that would arrive across a cut link
+     * becomes the one the node itself sent towards the membrane the step before (its
+     * post-collision population in the opposite direction).  Neither side of a cut link receives
+     * what the other sends, so the species is conserved exactly while membranes move, where the
+     * equilibrium forms lose the species a moving membrane sweeps over (Section "Validation":
+     * the paper finds the integrated concentration of its growing cells converging).  At the
+     * first step after the fields are set (lbib_create, lbib_set_fields) each node is taken to
+     * have sent its own populations; that step is launched outside the step graphs. */
+    int32_t no_flux_bounce;
     /* The FP64 monitor: 0 (default) off, or a positive multiple of LBIB_GRAPH_STEPS.  The global
      * sums of lbib_reduce (sum rho, sum rho u, sum phi_s) are then taken on the device at the
      * end of every (monitor_every / LBIB_GRAPH_STEPS)-th period of LBIB_GRAPH_STEPS steps

@@ -61,7 +61,18 @@
  *    extrapolation: a population arriving across a membrane (the inside map [m != 0] of this
  *    step differs between the link's ends) becomes the zero-velocity equilibrium w_i phi_b,
  *    with phi_b the node's own concentration solved from the populations that did arrive.
- *    Either form is applied to the streamed populations before the moments of the step; the
+ *    The bounce-back form (option no_flux_bounce, with the first-order form's cut links) is
+ *    not the supplement's: the population that would arrive across a cut link becomes the
+ *    one the node itself sent towards the membrane in the previous step (its post-collision
+ *    population in the opposite direction).  What one side of a link sends the other never
+ *    receives, so the species is conserved exactly, also while the membrane moves; the
+ *    supplement's equilibrium forms lose the species a moving membrane sweeps over, where the
+ *    paper's validations find the integrated concentration converging.  An equilibrium state
+ *    set from outside (initial fields) has no previous step: each node is taken to have sent
+ *    its own populations.  For populations restored mid-run, the previous post-collision
+ *    populations are the ones that streamed into them (streaming and the wall reflection form
+ *    a permutation, so they are recovered exactly).
+ *    Each form is applied to the streamed populations before the moments of the step; the
  *    reported fields are the sums after the replacement.
  *  - Mass sources and area control (Section "Control of Cell Area"; the supplement's
  *    parameter table makes the lattice source a density per node and step): every node
@@ -119,6 +130,10 @@ struct orc_ctx {
     double *ux_prev, *uy_prev;    /* velocity the previous collision used */
     double *q;                    /* [4][ny][nx] wall distances of blocked links (first-order no-flux) */
     double *nsrc;                 /* [ny][nx] mass source per node and step (point sources), NULL: none */
+    int sent;                     /* what gnew holds for the bounce-back no-flux form: 1 the previous
+                                     step's post-collision species populations; 0 nothing yet (a
+                                     state restored mid-run: unstream it); 2 nothing yet, the state
+                                     is an equilibrium set from outside (its own populations) */
     uint8_t *pmap;                /* [ny][nx] pressure points held at rho0, NULL: none */
 };
 
@@ -460,6 +475,7 @@ int32_t orc_set_cells(orc_ctx* c, int32_t n_cells, const int32_t* off, const dou
 static void prev_from_populations(orc_ctx* c)
 {
     int64_t nn = c->nn;
+    c->sent = 0;
     for (int64_t x = 0; x < nn; ++x) {
         double r = 0.0, jx = 0.0, jy = 0.0;
         for (int i = 0; i < 9; ++i) {
@@ -493,6 +509,7 @@ void orc_set_fields(orc_ctx* c, const double* rho, const double* u, const double
         }
     }
     prev_from_populations(c);
+    c->sent = 2;
 }
 
 void orc_set_source_cells(orc_ctx* c, const uint8_t* src)
@@ -662,6 +679,53 @@ static void no_flux_first(orc_ctx* c, const double* q, double* g, int only_s, do
     }
 }
 
+/* The populations that streamed into the current state, unstreamed: sent[i][x] is the
+ * population node x sent in direction i (free flight to x + v_i, or back to x itself in the
+ * opposite direction where x + v_i lies beyond a wall). */
+static void unstream_species(orc_ctx* c, double* sent)
+{
+    const orc_params* p = &c->p;
+    int64_t nx = p->nx, ny = p->ny, nn = c->nn;
+    for (int s = 0; s < p->n_species; ++s)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t x = 0; x < nx; ++x)
+                for (int i = 0; i < 5; ++i) {
+                    int64_t yd = y + VY[i], xd = wrapi(x + VX[i], nx);
+                    double v;
+                    if (p->bc_y == ORC_WALLS && (yd < 0 || yd >= ny))
+                        v = c->g[(s * 5 + OPP[i]) * nn + y * nx + x];
+                    else
+                        v = c->g[(s * 5 + i) * nn + wrapi(yd, ny) * nx + xd];
+                    sent[(s * 5 + i) * nn + y * nx + x] = v;
+                }
+}
+
+/* No-flux membranes in the bounce-back form: every population whose link is cut (q finite)
+ * becomes the population the node sent in the opposite direction in the previous step.  An
+ * equilibrium state set from outside has no previous step: each node is taken to have sent
+ * its own populations.  out as in no_flux_first. */
+static void no_flux_bounce(orc_ctx* c, const double* q, double* g, int only_s, double* out)
+{
+    const orc_params* p = &c->p;
+    int64_t nn = c->nn;
+    if (c->sent == 0) {
+        unstream_species(c, c->gnew);
+        c->sent = 1;
+    } else if (c->sent == 2) {
+        memcpy(c->gnew, c->g, sizeof(double) * 5 * (size_t)p->n_species * (size_t)nn);
+    }
+    for (int s = 0; s < p->n_species; ++s) {
+        if (!p->no_flux[s] || (only_s >= 0 && s != only_s)) continue;
+        for (int64_t k = 0; k < nn; ++k)
+            for (int i = 1; i < 5; ++i) {
+                if (q[(i - 1) * nn + k] == INFINITY) continue;
+                double v = c->gnew[(s * 5 + OPP[i]) * nn + k];
+                if (out) out[(i - 1) * nn + k] = v;
+                else g[(s * 5 + i) * nn + k] = v;
+            }
+    }
+}
+
 static void moments(orc_ctx* c)
 {
     int64_t nn = c->nn;
@@ -740,7 +804,8 @@ static void step_once(orc_ctx* c)
             no_flux_replace(c, c->mask, c->g);
         } else {
             orc_link_crossings(p, c->n_cells, c->off, c->X, c->q);
-            no_flux_first(c, c->q, c->g, -1, NULL);
+            if (p->no_flux_bounce) no_flux_bounce(c, c->q, c->g, -1, NULL);
+            else no_flux_first(c, c->q, c->g, -1, NULL);
         }
     }
 
@@ -831,6 +896,7 @@ static void step_once(orc_ctx* c)
     }
     double* t = c->f; c->f = c->fnew; c->fnew = t;
     t = c->g; c->g = c->gnew; c->gnew = t;
+    c->sent = 1;                          /* gnew: this step's post-collision populations */
 
     /* 6: interpolate and move (positions stay unwrapped) */
     if (c->n_nodes > 0) {
@@ -918,6 +984,7 @@ void orc_ade_step(orc_ctx* c, int32_t n, double* change)
                     }
             }
         double* t = c->g; c->g = c->gnew; c->gnew = t;
+        c->sent = 0;                      /* an ADE-only iteration, not a coupled step */
         if (change) {
             for (int s = 0; s < S; ++s) {
                 double d2 = 0.0, p2 = 0.0;
@@ -956,7 +1023,8 @@ void orc_get_fields(orc_ctx* c, double* rho, double* u, double* phi, double* X, 
         } else {
             double* q = (double*)malloc(sizeof(double) * 4 * (size_t)nn);
             orc_link_crossings(&c->p, c->n_cells, c->off, c->X, q);
-            no_flux_first(c, q, g, -1, NULL);
+            if (c->p.no_flux_bounce) no_flux_bounce(c, q, g, -1, NULL);
+            else no_flux_first(c, q, g, -1, NULL);
             free(q);
         }
     }
@@ -1026,7 +1094,8 @@ void orc_no_flux_values(orc_ctx* c, int32_t s, double* out)
     if (c->n_cells == 0 || s < 0 || s >= c->p.n_species || !c->p.no_flux[s]) return;
     double* q = (double*)malloc(sizeof(double) * 4 * (size_t)nn);
     orc_link_crossings(&c->p, c->n_cells, c->off, c->X, q);
-    no_flux_first(c, q, c->g, s, out);
+    if (c->p.no_flux_bounce) no_flux_bounce(c, q, c->g, s, out);
+    else no_flux_first(c, q, c->g, s, out);
     free(q);
 }
 

@@ -61,6 +61,7 @@ typedef struct {
     int32_t pressure_ring;       /* 1: the lattice's outer ring is a pressure boundary at rho0 */
     int32_t interp_half_force;   /* 1: interpolate u + f/2 (the half-force-shifted velocity) */
     int32_t no_flux_zeroth;      /* 1: the zeroth-order form of the no-flux condition */
+    int32_t no_flux_bounce;      /* 1: the bounce-back form (cut links; conserves the species) */
     int32_t reserved;
 } orc_params;
 

@@ -42,7 +42,8 @@ class Params(C.Structure):
                 ("rc", (C.c_double * 4) * 2), ("wall_u_top", C.c_double), ("no_flux", C.c_int32 * 2),
                 ("mass_source", C.c_double), ("area_alpha", C.c_double), ("mass_phi_gamma", C.c_double),
                 ("pressure_ring", C.c_int32), ("interp_half_force", C.c_int32),
-                ("no_flux_zeroth", C.c_int32), ("reserved", C.c_int32)]
+                ("no_flux_zeroth", C.c_int32), ("no_flux_bounce", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -133,6 +134,7 @@ def make_params(d: dict, interp_new_u: bool = False, wall_u_top: float = 0.0) ->
     p.pressure_ring = int(bool(d.get("pressure_ring", False)))
     p.interp_half_force = int(bool(d.get("interp_half_force", False)))
     p.no_flux_zeroth = int(bool(d.get("no_flux_zeroth", False)))
+    p.no_flux_bounce = int(bool(d.get("no_flux_bounce", False)))
     return p
 
 

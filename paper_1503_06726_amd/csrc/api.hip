@@ -186,6 +186,7 @@ LatticeArgs lattice_args_at(lbib_ctx* c, int cur)
         a.nfu = c->nfu[cur];
         a.nfphi_out = c->nfphi[1 - cur];
         a.nfu_out = c->nfu[1 - cur];
+        a.nf_bb = p.no_flux_bounce ? (c->nf_fresh ? 2 : 1) : 0;
     }
     a.e_out = nullptr;
     return a;
@@ -708,6 +709,7 @@ lbib_status init_fields(lbib_ctx* c, const double* rho, const double* u, const d
     }
     LBIB_LAUNCH(c, launch_init(c, d_rho, d_u, d_phi, d_rho != nullptr, d_u != nullptr, d_phi != nullptr));
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
+    c->nf_fresh = true;
     return LBIB_OK;
 }
 
@@ -725,6 +727,7 @@ lbib_status one_step(lbib_ctx* c)
         Timed tm(c, LBIB_K_LATTICE);
         LBIB_LAUNCH(c, launch_lattice(c, lattice_args(c), nodes, c->mask_needed));
     }
+    c->nf_fresh = false;
     c->cur = 1 - c->cur;
     if (nodes) LBIB_TRY(membrane(c, 1));
     if (++c->steps_since_lists >= LIST_PERIOD) {       // a period ends: lists rebuilt, monitor
@@ -1031,9 +1034,11 @@ lbib_status lbib_step(lbib_ctx* c, int32_t n)
     bool direct = false;
     while (n > 0) {
         // whole periods of GRAPH_STEPS steps, aligned to the list rebuilds, replay a captured
-        // graph (not while timing kernels); with the monitor due at the period's last step, the
-        // graph that ends with it
-        if (c->use_graphs && !c->timing && n >= GRAPH_STEPS && c->steps_since_lists == 0) {
+        // graph (not while timing kernels, nor for the first step of a state set from outside
+        // under the bounce-back no-flux form); with the monitor due at the period's last step,
+        // the graph that ends with it
+        const bool fresh_bb = c->nf_fresh && c->p.no_flux_bounce && no_flux_first(c->p);
+        if (c->use_graphs && !c->timing && !fresh_bb && n >= GRAPH_STEPS && c->steps_since_lists == 0) {
             hipGraphExec_t& g = c->graph[c->cur][monitor_due(c, c->period_count + 1) ? 1 : 0];
             if (!g) LBIB_TRY(capture_steps(c, &g));
             if (g) {
@@ -1224,9 +1229,10 @@ struct StateHeader {
     double mon[8];
     uint64_t bytes_f, bytes_g, bytes_nfphi, bytes_nfu;
     uint64_t bytes_nsrc, bytes_pmap;     // node sources (FP32) and pressure points, 0 when unset
+    int32_t fresh, unused;               // not stepped since its fields were set
 };
 constexpr char STATE_MAGIC[8] = {'L', 'B', 'I', 'B', 'S', 'T', 'A', 'T'};
-constexpr int32_t STATE_VERSION = 2;
+constexpr int32_t STATE_VERSION = 3;
 
 void state_layout(const lbib_ctx* c, StateHeader& h)
 {
@@ -1245,6 +1251,7 @@ void state_layout(const lbib_ctx* c, StateHeader& h)
     h.bytes_nfu = h.nf1 ? (uint64_t)c->nn * sizeof(float2) : 0;
     h.bytes_nsrc = c->d_nsrc ? (uint64_t)c->nn * sizeof(float) : 0;
     h.bytes_pmap = c->d_pmap ? (uint64_t)c->nn : 0;
+    h.fresh = c->nf_fresh ? 1 : 0;
 }
 
 // Node sources: rate[nn] FP32 mass per node and step, any alignment (NULL removes them).
@@ -1438,6 +1445,7 @@ lbib_status lbib_load_state(lbib_ctx* c, const void* buf, size_t bytes)
     LBIB_LAUNCH(c, launch_err_mirror(c, c->h_err_dev));
     LBIB_HIP(c, hipStreamSynchronize(c->stream));
     c->period_count = h.period_count;
+    c->nf_fresh = h.fresh != 0;
     return LBIB_OK;
 }
 

@@ -411,6 +411,32 @@ __device__ inline void nf_first_replace(const Args& a, int s, int x, int y, unsi
     }
 }
 
+// No-flux membranes in the bounce-back form (over the first-order form's cut links, bits d of
+// mk for the populations 1 + d): a population that would arrive across a cut link becomes the
+// one the node sent in the opposite direction the step before, its post-collision population
+// stored in its own slot of the source buffer gs (nf_bb = 1).  A state set from outside has
+// not streamed yet: each node is taken to have sent its own populations, which the pull has
+// just brought in as g (nf_bb = 2).  What one side of a cut link sends, the other never
+// receives, so the species is conserved exactly.
+template <int ST, typename Args>
+__device__ inline void nf_bounce(const Args& a, const void* gs, int s, int x, int y, unsigned mk, float g[5])
+{
+    float sent[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) sent[i] = g[i];
+    if (a.nf_bb == 1) {
+        const typename Pop<ST>::T* p = (const typename Pop<ST>::T*)gs;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const int o = 1 + ((d + 2) & 3);           // the direction opposite to 1 + d
+            if ((mk >> d) & 1u) sent[o] = Pop<ST>::ld(p[pop_at(a.grow, a.gchunk, 5 * s + o, y, x)], IS5[o]);
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+        if ((mk >> d) & 1u) g[1 + d] = sent[1 + ((d + 2) & 3)];
+}
+
 // One lattice tile of TILE_X x LTILE_Y nodes per workgroup; thread (lx, ly) handles rows
 // ly, ly + TILE_Y, ...  Order: listed nodes' records and the population loads issued; moments
 // (rho, u) of every row, u staged in LDS; listed nodes coupled (force spread into LDS, velocity
@@ -592,8 +618,11 @@ __device__ __forceinline__ void lattice_tile(const LatticeArgs& a, const int til
             if constexpr (NF == 2) {
                 if (miss[r]) {
 #pragma unroll
-                    for (int s = 0; s < S; ++s)
-                        if ((a.noflux >> s) & 1) nf_first_replace(a, s, x, n[r].y, miss[r], g[r][s]);
+                    for (int s = 0; s < S; ++s) {
+                        if (!((a.noflux >> s) & 1)) continue;
+                        if (a.nf_bb) nf_bounce<ST>(a, a.gsrc, s, x, n[r].y, miss[r], g[r][s]);
+                        else nf_first_replace(a, s, x, n[r].y, miss[r], g[r][s]);
+                    }
                 }
             }
             if constexpr (NF == 1) {
@@ -904,6 +933,7 @@ struct MomentArgs {
     int noflux;                       // bit s: no-flux membranes for species s
     int pring;                        // the outer ring is held at rho0 (pressure boundary)
     const uint8_t* pmap;              // pressure points held at rho0 (NULL: none)
+    int nf_bb;                        // the no-flux form over cut links, as in LatticeArgs
     // no-flux membranes in the first-order form (nfq NULL: the zeroth-order form): the buffers
     // the next lattice pass reads
     const float* nfq;
@@ -949,7 +979,8 @@ __device__ inline void node_moments(const MomentArgs& a, int x, int y, double& d
         pull5<ST>((const typename Pop<ST>::T*)a.g + 5 * s * TILE_X, a.grow, a.gchunk, n, g);
         if (miss && ((a.noflux >> s) & 1) && a.nfq) {
             // the concentration the next collision sees: the populations over cut links replaced
-            nf_first_replace(a, s, x, y, miss, g);
+            if (a.nf_bb) nf_bounce<ST>(a, a.g, s, x, y, miss, g);
+            else nf_first_replace(a, s, x, y, miss, g);
             double t = 0.0;
             for (int i = 0; i < 5; ++i) t += (double)g[i];
             dphi[s] = t;
@@ -1284,6 +1315,7 @@ static MomentArgs moment_args(lbib_ctx* c, double* out)
     a.nfm = nf1 ? c->nfm[c->cur] : nullptr;
     a.nfphi = nf1 ? c->nfphi[c->cur] : nullptr;
     a.nfu = nf1 ? c->nfu[c->cur] : nullptr;
+    a.nf_bb = nf1 && c->p.no_flux_bounce ? (c->nf_fresh ? 2 : 1) : 0;
     return a;
 }
 

@@ -106,6 +106,9 @@ struct LatticeArgs {
     const double* __restrict__ area;
     double msrc, alpha;
     double gamma;                          // + gamma phi_0(x) at nodes inside a cell
+    int nf_bb;                             // no-flux over cut links: 0 first-order replacement,
+                                           // 1 bounce-back from the node's own slots, 2 bounce-back
+                                           // of a state set from outside (its pulled populations)
     int pring;                             // the outer ring of nodes is held at density rho0
     const float* __restrict__ nsrc;        // [ny][nx] mass per node and step (NULL: none)
     const uint8_t* __restrict__ pmap;      // [ny][nx] pressure points held at rho0 (NULL: none)

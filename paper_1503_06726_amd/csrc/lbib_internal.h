@@ -38,6 +38,7 @@ struct lbib_ctx {
     int ntx = 0, nlty = 0, nltiles = 0;   // lattice tiles (TILE_X x LTILE_Y): columns, rows, total
     int tile_cap = 0;                     // tiles of the shortest tile shape (sizes the tile arrays)
     bool mask_needed = false;
+    bool nf_fresh = true;    // the state was set from outside and has not stepped (bounce-back no-flux)
 
     // lattice state: post-collision deviations (FP32, FP16 or BF16), A/B buffers
     void* f[2] = {nullptr, nullptr};

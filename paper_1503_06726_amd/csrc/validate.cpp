@@ -40,6 +40,10 @@ lbib_status check_params(const lbib_params* p, std::string& msg)
         return fail(msg, "interp_half_force = %g must be 0 or 1", p->interp_half_force);
     if (p->no_flux_zeroth != 0 && p->no_flux_zeroth != 1)
         return fail(msg, "no_flux_zeroth = %g must be 0 or 1", p->no_flux_zeroth);
+    if (p->no_flux_bounce != 0 && p->no_flux_bounce != 1)
+        return fail(msg, "no_flux_bounce = %g must be 0 or 1", p->no_flux_bounce);
+    if (p->no_flux_bounce && p->no_flux_zeroth)
+        return fail(msg, "no_flux_bounce works on the first-order form's cut links (no_flux_zeroth = 0)");
     if (p->monitor_every < 0 || p->monitor_every % LBIB_GRAPH_STEPS != 0 || p->monitor_every > (1 << 30))
         return fail(msg, "monitor_every = %g must be 0 or a positive multiple of 16", p->monitor_every);
     if (p->reserved != 0) return fail(msg, "reserved = %g must be 0", p->reserved);

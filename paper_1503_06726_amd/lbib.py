@@ -51,7 +51,8 @@ class Params(C.Structure):
                 ("n_species", C.c_int32), ("storage", C.c_int32), ("species", Species * 2),
                 ("mass_source", C.c_double), ("area_alpha", C.c_double), ("mass_phi_gamma", C.c_double),
                 ("pressure_ring", C.c_int32), ("interp_half_force", C.c_int32),
-                ("no_flux_zeroth", C.c_int32), ("monitor_every", C.c_int32), ("reserved", C.c_int32)]
+                ("no_flux_zeroth", C.c_int32), ("no_flux_bounce", C.c_int32), ("monitor_every", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class LbibError(RuntimeError):
@@ -223,6 +224,7 @@ def make_params(d: dict) -> Params:
     p.pressure_ring = int(bool(d.get("pressure_ring", False)))
     p.interp_half_force = int(bool(d.get("interp_half_force", False)))
     p.no_flux_zeroth = int(bool(d.get("no_flux_zeroth", False)))
+    p.no_flux_bounce = int(bool(d.get("no_flux_bounce", False)))
     p.monitor_every = int(d.get("monitor_every", 0))
     return p
 

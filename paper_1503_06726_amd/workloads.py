@@ -69,6 +69,7 @@ class Workload:
     pressure_ring: bool = False     # the lattice's outer ring holds the density at rho0 (outflow)
     interp_half_force: bool = False  # membrane nodes move with the interpolated u + f/2
     no_flux_zeroth: bool = False    # no-flux membranes in the zeroth-order form
+    no_flux_bounce: bool = False    # no-flux membranes in the bounce-back form (conserves the species)
     steps: int = 1
     # geometry (may be empty)
     offsets: np.ndarray = None      # int32 [n_cells+1]
@@ -104,7 +105,7 @@ class Workload:
                     mass_source=self.mass_source, area_alpha=self.area_alpha,
                     mass_phi_gamma=self.mass_phi_gamma,
                     pressure_ring=self.pressure_ring, interp_half_force=self.interp_half_force,
-                    no_flux_zeroth=self.no_flux_zeroth)
+                    no_flux_zeroth=self.no_flux_zeroth, no_flux_bounce=self.no_flux_bounce)
 
     def mask_needed(self) -> bool:
         return any(s.reaction == REACT_SOURCE_DECAY for s in self.species)
@@ -274,20 +275,23 @@ def leakage_case(level: int, maxlength: float, steps: int | None = None) -> Work
 GROWTH_CASES = (1, 2, 3)        # the growth validations: point source, uniform source, phi-driven source
 
 
-def growth_case(case: int, level: int, maxlength: float = 0.5, steps: int | None = None) -> Workload:
+def growth_case(case: int, level: int, maxlength: float = 0.5, steps: int | None = None,
+                bounce: bool = False) -> Workload:
     """The growth validations (Section "Validation", Cases I-III, and their table of lattice
-    discretisations): a circular cell of diameter 10 * 2^level lattice units centred in a
-    lattice 100 * 2^level squared, tau = 1 for the fluid, one species with tau_D = 1
-    (D = 1/6) that starts at 1 inside the cell and 0 outside and sees the membrane as a no-flux
-    boundary, no membrane forces, the outer ring held at rho0 (iso-pressure outflow), and
+    discretisations): a circular cell of diameter 10 * 2^level lattice units in the middle of a
+    lattice 100 * 2^level squared (its centre 0.3 off the central node in x and y, so that no
+    membrane node starts on a lattice line), tau = 1 for the fluid, one species with tau_D = 1
+    (D = 1/6) that starts at 1 inside the polygon's inscribed circle and 0 elsewhere and sees
+    the membrane as a no-flux boundary, no membrane forces, the outer ring held at rho0 (iso-pressure outflow), and
     10^4 * 4^level steps (one unit of non-dimensional time, dt = 1e-4 / 4^level).
     ceil(pi D / maxlength) equally spaced nodes.  The cell grows by
-      case 1: a point source of 1e-2 lattice areas per step at the centre node (the tabulated
+      case 1: a point source of 1e-2 lattice areas per step at the central node (the tabulated
               S^LB at every level), so A = A0 + 1e-2 t;
       case 2: a uniform source ln 2 * dt per inside node and step, so A = A0 2^(t dt), doubling
               in one unit of time;
       case 3: a uniform source dt * phi per inside node and step (strength 1 times the
-              concentration), so A = A0 (1 + t dt) while the species is conserved."""
+              concentration), so A = A0 (1 + t dt) while the species is conserved.
+    ``bounce``: the no-flux membrane in the bounce-back form, which conserves the species."""
     if case not in GROWTH_CASES:
         raise ValueError("case must be 1, 2 or 3")
     if not 0 <= level < LEAKAGE_LEVELS:
@@ -296,14 +300,15 @@ def growth_case(case: int, level: int, maxlength: float = 0.5, steps: int | None
     D = 10.0 * 2 ** level
     dt = 1e-4 / 4 ** level
     n = int(math.ceil(math.pi * D / maxlength))
-    c = L / 2.0
-    offsets, xy = circle_cell(c, c, D / 2.0, n, 0.0, None)
+    cx, cy = L / 2.0 + 0.3, L / 2.0 - 0.3
+    offsets, xy = circle_cell(cx, cy, D / 2.0, n, 0.0, None)
     yy, xx = np.mgrid[0:L, 0:L]
-    phi = (np.hypot(xx - c, yy - c) < D / 2.0).astype(np.float64)[None]
+    phi = (np.hypot(xx - cx, yy - cy) < D / 2.0 * math.cos(math.pi / n)).astype(np.float64)[None]
     w = Workload(name=f"growth case {case} level {level}: {L}x{L}, one {n}-node circle of diameter {D:g}",
                  nx=L, ny=L, bc_y=PERIODIC, tau=1.0, rho0=1.0, delta_kernel=DELTA_COS4,
                  species=[Species(D=1.0 / 6.0, phi_ref=0.0, reaction=REACT_NONE, no_flux=True)],
-                 pressure_ring=True, steps=10000 * 4 ** level if steps is None else steps, phi_init=phi)
+                 pressure_ring=True, steps=10000 * 4 ** level if steps is None else steps, phi_init=phi,
+                 no_flux_bounce=bounce)
     if case == 1:
         w.node_sources = np.zeros((L, L))
         w.node_sources[L // 2, L // 2] = 1e-2

@@ -40,12 +40,13 @@ def test_ctypes_layout_matches_header():
     #include <stddef.h>
     #include "lbib.h"
     int main(void) {
-      printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lbib_params), sizeof(lbib_species),
+      printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(lbib_params), sizeof(lbib_species),
              offsetof(lbib_params, tau), offsetof(lbib_params, body_accel), offsetof(lbib_params, kappa_area),
              offsetof(lbib_params, n_species), offsetof(lbib_params, species), offsetof(lbib_species, c),
              offsetof(lbib_species, reaction), offsetof(lbib_params, mass_source), offsetof(lbib_params, area_alpha),
              offsetof(lbib_params, pressure_ring), offsetof(lbib_params, interp_half_force),
-             offsetof(lbib_params, no_flux_zeroth), offsetof(lbib_params, mass_phi_gamma));
+             offsetof(lbib_params, no_flux_zeroth), offsetof(lbib_params, mass_phi_gamma),
+             offsetof(lbib_params, no_flux_bounce));
       return 0; }
     """
     with tempfile.TemporaryDirectory() as d:
@@ -58,7 +59,7 @@ def test_ctypes_layout_matches_header():
     want = [C.sizeof(P), C.sizeof(S), P.tau.offset, P.body_accel.offset, P.kappa_area.offset,
             P.n_species.offset, P.species.offset, S.c.offset, S.reaction.offset, P.mass_source.offset,
             P.area_alpha.offset, P.pressure_ring.offset, P.interp_half_force.offset, P.no_flux_zeroth.offset,
-            P.mass_phi_gamma.offset]
+            P.mass_phi_gamma.offset, P.no_flux_bounce.offset]
     assert vals == want
 
 
@@ -229,6 +230,19 @@ def test_concentration_source_validated():
     assert q.mass_phi_gamma == 1e-4
     assert lbib.lib().lbib_validate_params(C.byref(q), buf, 256) == lbib.EINVAL
     assert b"mass_phi_gamma" in buf.value
+
+
+def test_bounce_back_no_flux_validated():
+    """The bounce-back no-flux form is 0 or 1 and works on the first-order form's cut links."""
+    d = dict(W.growth_case(3, 0, bounce=True).params_dict())
+    assert lbib.validate_params(d)[0] == lbib.OK
+    buf = C.create_string_buffer(256)
+    for kw, word in ((dict(no_flux_zeroth=True), b"no_flux_zeroth"), (dict(), b"no_flux_bounce")):
+        q = lbib.make_params(dict(d, **kw))
+        if not kw:
+            q.no_flux_bounce = 2
+        assert lbib.lib().lbib_validate_params(C.byref(q), buf, 256) == lbib.EINVAL
+        assert word in buf.value
 
 
 def test_growth_cases_follow_the_table():

@@ -53,12 +53,13 @@ def compare(g, o, what, X0, steps, S, rho0=1.0):
     return G, R
 
 
-@pytest.mark.parametrize("case,zeroth", [(1, False), (3, False), (3, True)],
-                         ids=["case I", "case III first-order", "case III zeroth-order"])
-def test_growth_cases_match_oracle(case, zeroth):
-    w = W.growth_case(case, 0)
-    w.no_flux_zeroth = zeroth
-    say(f"case {w.name}{' (zeroth-order no-flux)' if zeroth else ''}: 200 steps")
+@pytest.mark.parametrize("case,form", [(1, "first"), (3, "first"), (3, "zeroth"), (1, "bounce"), (3, "bounce")],
+                         ids=["case I", "case III first-order", "case III zeroth-order", "case I bounce-back",
+                              "case III bounce-back"])
+def test_growth_cases_match_oracle(case, form):
+    w = W.growth_case(case, 0, bounce=form == "bounce")
+    w.no_flux_zeroth = form == "zeroth"
+    say(f"case {w.name} ({form} no-flux form): 200 steps")
     g = lbib.from_workload(w)
     o = O.from_workload(w)
     g.step(200)
@@ -67,9 +68,10 @@ def test_growth_cases_match_oracle(case, zeroth):
     g.close()
 
 
-@pytest.mark.parametrize("case", [1, 3], ids=["case I", "case III"])
-def test_growth_trajectory_follows_oracle(case):
-    w = W.growth_case(case, 0)
+@pytest.mark.parametrize("case,bounce", [(1, False), (3, False), (3, True)],
+                         ids=["case I", "case III", "case III bounce-back"])
+def test_growth_trajectory_follows_oracle(case, bounce):
+    w = W.growth_case(case, 0, bounce=bounce)
     say(f"case {w.name}: area every 500 steps to 2000")
     g = lbib.from_workload(w)
     o = O.from_workload(w)
@@ -176,6 +178,36 @@ def test_full_time_laws_and_convergence():
                 assert e[level] < res[3, level]["mean_abs_mass_error"] + abs(res[2, level]["rel_area_error"])
     for level in (0, 1, 2):
         assert abs(res[1, level]["rel_area_error"]) < 1e-3
+
+
+def test_bounce_back_conserves_the_species_on_the_gpu():
+    """With the bounce-back no-flux form Case I at level 1 (4 10^4 steps, the cell grows 2.27
+    times) keeps its species: the extracellular concentration stays exactly zero and the total
+    changes by less than 10^-5 (FP32 storage rounding)."""
+    r = GR.run_case(1, 1, samples=8, bounce=True)
+    say(f"  case I level 1, bounce-back: area ratio {r['area_ratio']:.5f}, mean |mass error| "
+        f"{r['mean_abs_mass_error']:.2e}")
+    assert r["mean_abs_mass_error"] < 1e-5 and r["area_ratio"] > 2.2
+    w = W.growth_case(1, 1, steps=4000, bounce=True)
+    g = lbib.from_workload(w)
+    g.step(4000)
+    F = g.get_fields()
+    assert np.all(F["phi"][0][F["mask"] == 0] == 0.0)
+    g.close()
+
+
+def test_bounce_back_case_iii_converges():
+    """With the species conserved, Case III's area error converges at first order like Case
+    II's (the paper fits 1.01): orders between levels 0, 1 and 2 in [0.7, 1.8]."""
+    e = []
+    for level in (0, 1, 2):
+        r = GR.run_case(3, level, samples=20, bounce=True)
+        e.append(abs(r["rel_area_error"]))
+        say(f"  case III level {level}, bounce-back: area error {r['rel_area_error']:+.4e}, "
+            f"mean |mass error| {r['mean_abs_mass_error']:.2e}")
+    o = [np.log2(e[i] / e[i + 1]) for i in (0, 1)]
+    say(f"  orders {o[0]:.3f}, {o[1]:.3f}")
+    assert all(0.7 <= v <= 1.8 for v in o), o
 
 
 def test_node_map_refusals():

@@ -35,17 +35,23 @@ def rel(a, b):
     return np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0)
 
 
-FORMS = pytest.mark.parametrize("zeroth", [False, True], ids=["first-order", "zeroth-order"])
+FORMS = pytest.mark.parametrize("form", ["first", "zeroth", "bounce"],
+                                ids=["first-order", "zeroth-order", "bounce-back"])
+
+
+def _form(w, form):
+    w.no_flux_zeroth = form == "zeroth"
+    w.no_flux_bounce = form == "bounce"
+    return w
 
 
 @FORMS
 @pytest.mark.parametrize("static,steps", [(False, 60), (True, 60), (False, 160)])
-def test_no_flux_matches_oracle(static, steps, zeroth):
-    if zeroth and steps > 60:
-        pytest.skip("the long run covers the first-order form")
-    w = W.no_flux_tissue(static=static)
-    w.no_flux_zeroth = zeroth
-    say(f"case {w.name}, {'zeroth' if zeroth else 'first'}-order form: {steps} steps")
+def test_no_flux_matches_oracle(static, steps, form):
+    if form == "zeroth" and steps > 60:
+        pytest.skip("the long run covers the first-order and bounce-back forms")
+    w = _form(W.no_flux_tissue(static=static), form)
+    say(f"case {w.name}, {form} form: {steps} steps")
     g = lbib.from_workload(w)
     g.step(steps)
     G = g.get_fields()
@@ -60,9 +66,8 @@ def test_no_flux_matches_oracle(static, steps, zeroth):
 
 
 @FORMS
-def test_no_flux_confines_the_source_on_the_gpu(zeroth):
-    w = W.no_flux_tissue(static=True)
-    w.no_flux_zeroth = zeroth
+def test_no_flux_confines_the_source_on_the_gpu(form):
+    w = _form(W.no_flux_tissue(static=True), form)
     g = lbib.from_workload(w)
     g.step(100)
     F = g.get_fields()

@@ -42,6 +42,7 @@ def resume_cases():
         "mass sources and ring": lambda: _set(W.mass_source_tissue(no_flux=True), pressure_ring=True),
         "half-force": lambda: _set(walls(), interp_half_force=True),
         "node maps": lambda: _maps(W.growth_case(3, 0)),
+        "bounce-back no-flux": lambda: _set(W.no_flux_tissue(static=False), no_flux_bounce=True),
     }
 
 
@@ -108,6 +109,25 @@ def test_resume_is_exact(case, storage, monitor):
         mc, nc = c.monitor()
         say(f"  monitor: {na} sums taken in the whole run, {nc} after resuming")
         assert na >= 1 and nc >= 1
+    for s in (a, b, c):
+        s.close()
+
+
+def test_resume_of_a_state_not_yet_stepped():
+    """A state saved before its first step keeps that mark: under the bounce-back no-flux form
+    the first step takes each node's own populations as the ones it sent, after loading too."""
+    w = _set(W.growth_case(1, 0), no_flux_bounce=True)
+    a = _sim(w)
+    b = _sim(w)
+    state = b.save_state()
+    c = lbib.Simulation(w.params_dict())
+    c.step(5)                                  # a stepped context: the load must reset the mark
+    c.load_state(state)
+    a.step(20)
+    c.step(20)
+    A, Cf = a.get_fields(), c.get_fields()
+    for k in ("rho", "u", "phi", "xy", "mask"):
+        assert np.array_equal(A[k], Cf[k]), k
     for s in (a, b, c):
         s.close()
 

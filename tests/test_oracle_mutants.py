@@ -87,6 +87,12 @@ MUTANTS = {
     "node source dropped": ("if (c->nsrc) Sx += c->nsrc[x];", "if (c->nsrc) Sx += 0.0 * c->nsrc[x];"),
     "concentration source from the other species": ("+ p->mass_phi_gamma * phi[0];", "+ p->mass_phi_gamma * phi[1];"),
     "pressure map ignored": ("|| (c->pmap && c->pmap[x]);", "|| (c->pmap && 0);"),
+    "bounce-back in the same direction": ("double v = c->gnew[(s * 5 + OPP[i]) * nn + k];",
+                                          "double v = c->gnew[(s * 5 + i) * nn + k];"),
+    "bounce-back of a set state unstreamed": ("    } else if (c->sent == 2) {\n        memcpy(c->gnew, c->g,",
+                                              "    } else if (c->sent == 2) {\n        unstream_species(c, c->gnew); if (0) memcpy(c->gnew, c->g,"),
+    "bounce-back restart from the set state's rule": ("        unstream_species(c, c->gnew);\n        c->sent = 1;",
+                                                      "        memcpy(c->gnew, c->g, sizeof(double) * 5 * (size_t)p->n_species * (size_t)nn);\n        c->sent = 1;"),
 }
 
 

@@ -1029,3 +1029,72 @@ def test_point_source_grows_a_cell_linearly():
     o.step(300)
     dA = _shoelace(o.get_fields()["xy"]) - A0
     assert abs(dA / 3.0 - 1.0) < 0.02, dA
+
+
+def _area_and_species(o):
+    F = o.get_fields()
+    return _shoelace(F["xy"]), F["phi"][0], F["mask"] > 0
+
+
+def test_bounce_back_no_flux_conserves_a_growing_cell_species():
+    """The bounce-back form of the no-flux condition: what one side of a cut link sends, the
+    other never receives, so while validation Case I's point source grows the cell (at the
+    coarsest resolution) the species stays inside (the extracellular concentration exactly
+    zero, also after the first step from the set fields) and its total is conserved to
+    round-off.  The supplement's equilibrium forms lose more than 1 % of it meanwhile."""
+    w = W.growth_case(1, 0, steps=1500, bounce=True)
+    o = O.from_workload(w)
+    _, ph, ins = _area_and_species(o)
+    M0 = ph.sum()
+    o.step(1)
+    _, ph, ins = _area_and_species(o)
+    assert np.all(ph[~ins] == 0.0)
+    for _ in range(3):
+        o.step(500)
+        A, ph, ins = _area_and_species(o)
+        assert np.all(ph[~ins] == 0.0)
+        assert abs(ph.sum() - M0) <= 1e-12 * M0
+    assert A > 1.06 * _shoelace(w.xy)                     # the cell did grow
+    w.no_flux_bounce = False
+    e = O.from_workload(w)
+    e.step(1500)
+    assert abs(e.get_fields()["phi"][0].sum() / M0 - 1.0) > 0.01
+
+
+def test_bounce_back_keeps_a_resting_cell_exact():
+    """A cell at rest (no forces, no flow) with the species at 1 inside and 0 outside: every
+    population the bounce-back returns is the equilibrium the node sent, so the field does not
+    change at all (to round-off)."""
+    w = W.growth_case(1, 0, steps=200, bounce=True)
+    w.node_sources = None
+    o = O.from_workload(w)
+    phi0 = o.get_fields()["phi"][0]
+    o.step(200)
+    assert np.max(np.abs(o.get_fields()["phi"][0] - phi0)) < 1e-13
+
+
+def test_bounce_back_restart_from_populations_is_exact():
+    """Populations restored mid-run carry their own history: the populations each node sent the
+    step before are the ones that streamed into them (streaming with the wall reflection is a
+    permutation), so a run restarted from its populations continues bit for bit.  Walls in y
+    and a moving tissue exercise the wall reflection and moving cut links."""
+    w = W.no_flux_tissue(static=False)
+    w.no_flux_bounce = True
+    a = O.from_workload(w)
+    b = O.from_workload(w)
+    a.step(30)
+    b.step(15)
+    f, g = b.populations()
+    phi, u = b.prev_moments()
+    X = b.get_fields()["xy"]
+    c = O.from_workload(w)
+    rest_len = w.rest_len if w.rest_len is not None else W.edge_lengths(w.offsets, w.xy)
+    rest_area = w.rest_area if w.rest_area is not None else np.array(
+        [_shoelace(w.xy[w.offsets[k]:w.offsets[k + 1]]) for k in range(w.n_cells)])
+    c.set_cells(w.offsets, X, rest_len, rest_area)
+    c.set_populations(f, g.reshape(-1, w.ny, w.nx))
+    c.set_prev_moments(phi, u)
+    c.step(15)
+    A, C = a.get_fields(), c.get_fields()
+    for k in ("rho", "u", "phi", "xy"):
+        np.testing.assert_array_equal(A[k], C[k])
