@@ -7,7 +7,8 @@ measured 4e-3).  Gradients travel back through another 15 roundings, and a ReLU 
 pre-activation rounds across zero switches a path on or off, so every layer's weight and bias
 gradient agrees to 1e-1 (rel-L2; measured 3.5e-2 at 32 x 32, 6.6e-2 for the 3 x 5-pixel bottom
 level of the 24 x 40 case, where nothing averages out); a wrong tap, index or transpose gives
-errors of order one."""
+errors of order one.  The 256 x 256 case runs every level at a width the row-segment weight
+gradients take."""
 import sys
 
 import numpy as np
@@ -51,7 +52,7 @@ def random_case(seed, B, H, W):
     return layers, inputs, targets
 
 
-@pytest.mark.parametrize("B,H,W", [(2, 32, 32), (1, 24, 40)])
+@pytest.mark.parametrize("B,H,W", [(2, 32, 32), (1, 24, 40), (1, 256, 256)])
 def test_net_loss_and_gradients_match_reference(B, H, W):
     layers, inputs, targets = random_case(7, B, H, W)
     params = U.pack(layers).astype(np.float32)
