@@ -210,6 +210,33 @@ def test_bounce_back_case_iii_converges():
     assert all(0.7 <= v <= 1.8 for v in o), o
 
 
+@pytest.mark.parametrize("storage,bound", [(lbib.STORAGE_FP16, 1e-2), (lbib.STORAGE_BF16, 1e-1)],
+                         ids=["fp16", "bf16"])
+@pytest.mark.parametrize("case", ["case I bounce-back", "case III bounce-back", "maps in a tissue"])
+def test_reduced_precision_forms(case, storage, bound):
+    """The 16-bit storage forms of the same kernels (node sources, pressure points, the
+    concentration-driven source, the bounce-back no-flux form) against the FP64 oracle after
+    60 steps; the bound (as for the other 16-bit tests) only catches gross mistakes such as a
+    wrong storage scale or a swapped direction."""
+    if case == "maps in a tissue":
+        w = W.random_fields(W.small_tissue(nx=90, ny=70, n_cells=6, bc_y=W.WALLS, seed=1), seed=2)
+        w.node_sources, w.pressure_nodes = _point_maps(w.nx, w.ny)
+    else:
+        w = W.growth_case(1 if case.startswith("case I ") else 3, 0, bounce=True)
+    say(f"case {w.name}, storage {storage}: 60 steps")
+    g = lbib.from_workload(w, storage=storage)
+    g.step(60)
+    G = g.get_fields()
+    g.close()
+    o = O.from_workload(w)
+    o.step(60)
+    errs = PB.field_errors(G, o.get_fields(), w.rho0, w.xy, 60, w.n_species)
+    say("  errors:", PB.fmt(errs))
+    for k in ("u", "X-X0", "phi"):
+        if k in errs:
+            assert errs[k] < bound, (k, errs[k])
+
+
 def test_node_map_refusals():
     w = W.growth_case(1, 0, steps=10)
     g = lbib.from_workload(w)

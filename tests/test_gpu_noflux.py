@@ -92,3 +92,25 @@ def test_no_flux_refusals():
     g.set_source_cells(None)             # all cells: accepted
     g.step(3)
     g.close()
+
+
+@pytest.mark.parametrize("form", ["first", "bounce"], ids=["first-order", "bounce-back"])
+def test_no_flux_at_full_size(form):
+    """The bench workload (2048 x 2048, 2000 cells, 726,782 nodes) with its species behind
+    no-flux membranes: 36 steps cross two list rebuilds and replay one captured period (the
+    bounce-back form's first step runs outside the graphs), and every field stays within the
+    parity bar of the FP64 oracle."""
+    w = _form(W.large(), form)
+    w.species[0].no_flux = True
+    steps = 36
+    say(f"case {w.name}, {form} no-flux form: {steps} steps")
+    g = lbib.from_workload(w)
+    g.step(steps)
+    G = g.get_fields(mask=False)
+    g.close()
+    o = O.from_workload(w)
+    o.step(steps)
+    R = o.get_fields()
+    errs = PB.field_errors(G, R, w.rho0, w.xy, steps, w.n_species)
+    say("  errors:", PB.fmt(errs))
+    PB.assert_fields(errs)
