@@ -500,7 +500,7 @@ lbib_status lbib_reduce_device(lbib_ctx* ctx, double* out_device);
  *                    created with the same parameters (LBIB_EINVAL otherwise, or for a short or
  *                    foreign buffer); the cells are validated as by lbib_set_cells.  Synchronises;
  *                    LBIB_ESTATE while a batch has adopted the context.  A failure may leave the
- *                    cells replaced and the populations unchanged.  A state with node sources
+ *                    node maps and cells replaced and the populations unchanged.  A state with node sources
  *                    or pressure points is refused with LBIB_ESTATE while a workspace is
  *                    bound (the workspace does not hold them). */
 lbib_status lbib_state_size(lbib_ctx* ctx, size_t* bytes);
