@@ -905,7 +905,10 @@ WgradPlan wgrad_plan(const lbib_net* n, int l, int B)
     const int Cout = LAYER_COUT[l], K = 9 * LAYER_CIN[l];
     WgradPlan w;
     w.BM = Cout >= 128 ? 128 : Cout;
-    w.BK = K >= 576 ? 128 : 64;
+    // k tiles of 128 only where they divide K and the output channels fill 128-row tiles of
+    // the dZ operand; elsewhere 64 (a partial last k tile multiplies zeros, and with few output
+    // channels the patch staging dominates either way)
+    w.BK = (K >= 576 && K % 128 == 0 && Cout > 64) ? 128 : 64;
     w.nkt = (K + w.BK - 1) / w.BK;
     w.tiles = w.nkt * (Cout / w.BM);
     const int Wd = n->Wd / div;
