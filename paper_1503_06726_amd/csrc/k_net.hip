@@ -892,7 +892,7 @@ bool forward(lbib_net* n, const float* inputs, int B)
 }
 
 // The weight-gradient tiling of layer l at batch B: output-channel and k tile sizes, pixels per
-// chunk and the number of chunks (about 2048 workgroups in all, at least ~1024 pixels each)
+// chunk and the number of chunks (up to about 4096 workgroups in all, at least ~1024 pixels each)
 struct WgradPlan {
     int BM, BK, nkt, tiles, chunk, nchunk;
     int px;                   // row-segment step (32, 64 or 128 pixels), 0: the general form
@@ -914,7 +914,7 @@ WgradPlan wgrad_plan(const lbib_net* n, int l, int B)
     const int Wd = n->Wd / div;
     w.px = Wd % 128 == 0 ? 128 : Wd % 64 == 0 ? 64 : Wd % 32 == 0 ? 32 : 0;
     const int step = w.px ? w.px : WG_STEP_PX;
-    w.nchunk = std::max(1, std::min(2048 / w.tiles, (P + 1023) / 1024));
+    w.nchunk = std::max(1, std::min(4096 / w.tiles, (P + 1023) / 1024));
     w.chunk = (P + w.nchunk - 1) / w.nchunk;
     w.chunk = (w.chunk + step - 1) / step * step;
     w.nchunk = (P + w.chunk - 1) / w.chunk;
