@@ -674,7 +674,7 @@ def test_first_order_boundary_values_are_exact_for_linear_fields():
     assert left.sum() >= 20 and right.sum() >= 20 and bot.sum() >= 20 and top.sum() >= 20
 
 
-def _neumann_error(level):
+def _neumann_error(level, bounce=False):
     """Diffusion (D = 1/6, fluid at rest) next to a flat no-flux wall at x = 10 s + 0.37 inside
     a long rectangular cell, from the even extension of a Gaussian (width 5 s, 8 s from the
     wall), after 400 s^2 steps; s = 2^level.  The Neumann solution on the half-line is the
@@ -686,7 +686,8 @@ def _neumann_error(level):
     P = _rect(xw, 3.41, 110 * s + 0.37, 20.41)
     D = 1.0 / 6.0
     xc, sg0 = xw + 8 * s, 5.0 * s
-    o = O.Sim(dict(nx=nx, ny=ny, bc_y=0, tau=1.0, species=[dict(D=D, reaction=0, no_flux=True)]))
+    o = O.Sim(dict(nx=nx, ny=ny, bc_y=0, tau=1.0, species=[dict(D=D, reaction=0, no_flux=True)],
+                   no_flux_bounce=bounce))
     o.set_cells(np.array([0, len(P)], np.int32), P)
     x = np.arange(nx, dtype=float)
     ins = (x > xw) & (x < 110 * s + 0.37)
@@ -715,6 +716,17 @@ def test_first_order_no_flux_follows_the_neumann_solution():
     e1, m1 = _neumann_error(1)
     assert e0 < 0.01 and m0 < 0.015
     assert e1 < 0.6 * e0 and m1 < 0.7 * m0
+
+
+def test_bounce_back_no_flux_follows_the_neumann_solution():
+    """The bounce-back form against the same image solution: it keeps the row's mass to
+    round-off, its profile error is below 0.3 % of the peak at the coarse resolution (the wall
+    sits 0.37 of a link from the nodes, not midway) and shrinks at least as fast as first order
+    under refinement."""
+    e0, m0 = _neumann_error(0, bounce=True)
+    e1, m1 = _neumann_error(1, bounce=True)
+    assert e0 < 0.003 and m0 < 1e-12 and m1 < 1e-12
+    assert e1 < 0.6 * e0
 
 
 @NF_FORMS
