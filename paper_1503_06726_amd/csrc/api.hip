@@ -1382,8 +1382,14 @@ lbib_status lbib_load_state(lbib_ctx* c, const void* buf, size_t bytes)
     // every named field of the parameters (the struct has no padding before its last field)
     const size_t pfields = offsetof(lbib_params, reserved) + sizeof(int32_t);
     if (std::memcmp(&h.p, &c->p, pfields) != 0 || h.bytes_f != mine.bytes_f ||
-        h.bytes_g != mine.bytes_g || h.nf1 != mine.nf1 || h.n_cells < 0 || h.n_nodes < 0) {
+        h.bytes_g != mine.bytes_g || h.nf1 != mine.nf1 || h.bytes_nfphi != mine.bytes_nfphi ||
+        h.bytes_nfu != mine.bytes_nfu) {
         c->err = "the saved state was made with other parameters";
+        return LBIB_EINVAL;
+    }
+    // the limits lbib_set_cells enforces, checked before anything is sized from them
+    if (h.n_cells < 0 || h.n_cells > 65535 || h.n_nodes < 0 || h.n_nodes > 200000000) {
+        c->err = "the saved cell counts are out of range";
         return LBIB_EINVAL;
     }
     if ((h.bytes_nsrc && h.bytes_nsrc != (uint64_t)c->nn * sizeof(float)) ||

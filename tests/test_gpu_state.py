@@ -15,6 +15,7 @@ Bars:
     outrun their list margin are caught the same way.  Every kernel still ends normally (the
     values are IEEE infinities and NaNs).
 """
+import ctypes as C
 import sys
 
 import numpy as np
@@ -143,6 +144,13 @@ def test_resume_refuses_other_parameters():
     assert e.value.status == lbib.EINVAL
     with pytest.raises(lbib.LbibError) as e:
         a.load_state(state[:100])
+    assert e.value.status == lbib.EINVAL
+    # a node count beyond lbib_set_cells' limit is refused before anything is sized from it
+    bad = bytearray(state)
+    off = 16 + C.sizeof(lbib.Params) + 8
+    bad[off:off + 8] = (10 ** 12).to_bytes(8, "little", signed=True)
+    with pytest.raises(lbib.LbibError) as e:
+        a.load_state(bytes(bad))
     assert e.value.status == lbib.EINVAL
     for s in (a, other):
         s.close()
